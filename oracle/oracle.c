@@ -1,0 +1,408 @@
+/*
+ * Oracle for the parareal-with-splitting hot path (arXiv 2502.08370).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path. Serial, FP64,
+ * written for reading, not for speed: every substep assembles its tridiagonal
+ * matrix from the operator definition and solves it with the textbook Thomas
+ * algorithm.
+ *
+ * Paper passages followed (section / equation labels of the paper):
+ *  - model problem and operator L u = div(D grad u) - c u: section 2.1,
+ *    eq. cont_problem;
+ *  - dimensional splitting L_j u = (d_jj u_{x_j})_{x_j} - c u / M: section 2.1;
+ *  - domain decomposition splitting L_j u = div(rho_j D grad u) - rho_j c u with
+ *    a partition of unity rho_j: section 2.1 (eq. partition_unity_M2 and the
+ *    sub-operator definition after it);
+ *  - method of lines U' = (A_1 + ... + A_M) U: section 2.2, eq. semidisc_prob;
+ *  - fractional implicit Euler: section 2.2, eq. FIE_method;
+ *  - Douglas-Rachford: section 2.2, eq. DR_method;
+ *  - coarse/fine meshes, propagators, initial guess and the parareal
+ *    iteration: section 3 (the displayed iteration after the initial guess);
+ *  - adjoint: not in the paper; the transpose of the FIE step map, derived in
+ *    the comment above or_adjoint.
+ *
+ * Readings where the paper is silent (all recorded in the design notes):
+ *  - second-order finite differences on the interior nodes of a uniform grid,
+ *    h = 1/(n+1) per direction, coefficient sampled on cell faces;
+ *  - x substep first, then y; domain-decomposition colours in index order;
+ *  - the parareal correction is evaluated as F_n + (G_new - G_old).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static double hx_of(const or_problem* p) { return 1.0 / (p->nx + 1); }
+static double hy_of(const or_problem* p) { return 1.0 / (p->ny + 1); }
+static int npts_of(const or_problem* p) { return p->nx * p->ny; }
+static int n_terms(const or_problem* p) { return p->split == 1 ? p->n_colors : p->dim; }
+
+/* Thomas algorithm (LU without pivoting) for a tridiagonal system with
+ * sub-diagonal lo[i] (row i, column i-1; lo[0] unused), diagonal di[i] and
+ * super-diagonal up[i] (row i, column i+1; up[n-1] unused). The right-hand
+ * side x is overwritten with the solution. cp is scratch of length n. */
+static void thomas(int n, const double* lo, const double* di, const double* up, double* x,
+                   double* cp) {
+  double piv = di[0];
+  cp[0] = (n > 1) ? up[0] / piv : 0.0;
+  x[0] = x[0] / piv;
+  for (int i = 1; i < n; i++) {
+    piv = di[i] - lo[i] * cp[i - 1];
+    cp[i] = (i < n - 1) ? up[i] / piv : 0.0;
+    x[i] = (x[i] - lo[i] * x[i - 1]) / piv;
+  }
+  for (int i = n - 2; i >= 0; i--) x[i] = x[i] - cp[i] * x[i + 1];
+}
+
+/* Scratch for one line of length n: sub, diag, super, pivot ratios, rhs. */
+typedef struct {
+  double *lo, *di, *up, *cp, *rhs;
+} line_ws;
+
+static line_ws ws_alloc(int n) {
+  line_ws w;
+  double* base = (double*)malloc(sizeof(double) * 5 * (size_t)(n > 0 ? n : 1));
+  w.lo = base;
+  w.di = base + n;
+  w.up = base + 2 * n;
+  w.cp = base + 3 * n;
+  w.rhs = base + 4 * n;
+  return w;
+}
+static void ws_free(line_ws* w) { free(w->lo); }
+
+/* Assemble the matrix I - tau*A_line for one line of n nodes with face
+ * coefficients face[0..n] (face f between nodes f-1 and f), spacing h and a
+ * diagonal reaction term react >= 0 (so the row reads
+ * -w_f u_{f-1} + (1 + w_f + w_{f+1} + tau*react) u_f - w_{f+1} u_{f+1},
+ * w = tau*a/h^2). Faces 0 and n couple to Dirichlet boundary nodes (value 0). */
+static void assemble_line(int n, const double* face, long face_stride, double h, double tau,
+                          double react, line_ws* w) {
+  for (int i = 0; i < n; i++) {
+    double aw = face[(long)i * face_stride];
+    double ae = face[(long)(i + 1) * face_stride];
+    double ww = tau * aw / (h * h);
+    double we = tau * ae / (h * h);
+    w->lo[i] = -ww;
+    w->up[i] = -we;
+    w->di[i] = 1.0 + ww + we + tau * react;
+  }
+}
+
+/* One implicit substep (I - tau*A_j) V = U along every line of the split
+ * term j, in place. j = 0: x-lines (dimensional) or colour 0 (domain
+ * decomposition). */
+static void implicit_substep(const or_problem* p, int j, double tau, double* U) {
+  const int nx = p->nx, ny = p->ny;
+  if (p->split == 0) {
+    const int M = p->dim;
+    const double react = p->c / M; /* the reaction is shared equally, section 2.1 */
+    if (j == 0) {
+      line_ws w = ws_alloc(nx);
+      for (int row = 0; row < ny; row++) {
+        assemble_line(nx, p->ax + (long)row * (nx + 1), 1, hx_of(p), tau, react, &w);
+        thomas(nx, w.lo, w.di, w.up, U + (long)row * nx, w.cp);
+      }
+      ws_free(&w);
+    } else {
+      line_ws w = ws_alloc(ny);
+      for (int col = 0; col < nx; col++) {
+        assemble_line(ny, p->ay + col, nx, hy_of(p), tau, react, &w);
+        for (int r = 0; r < ny; r++) w.rhs[r] = U[(long)r * nx + col];
+        thomas(ny, w.lo, w.di, w.up, w.rhs, w.cp);
+        for (int r = 0; r < ny; r++) U[(long)r * nx + col] = w.rhs[r];
+      }
+      ws_free(&w);
+    }
+  } else {
+    /* Domain decomposition (1D): the operator of colour j uses the face
+     * coefficient rho_j * a. Where rho_j vanishes on both faces of a node the
+     * row is the identity, so the whole-line system is block diagonal with one
+     * block per connected component plus identity rows; solving it as one
+     * tridiagonal system is the definition of the substep. */
+    double* wface = (double*)malloc(sizeof(double) * (nx + 1));
+    for (int f = 0; f <= nx; f++) wface[f] = p->rho[(long)j * (nx + 1) + f] * p->ax[f];
+    line_ws w = ws_alloc(nx);
+    assemble_line(nx, wface, 1, hx_of(p), tau, 0.0, &w);
+    thomas(nx, w.lo, w.di, w.up, U, w.cp);
+    ws_free(&w);
+    free(wface);
+  }
+}
+
+/* Stencil application of one split operator along the lines of term j:
+ * (A_j U)_i = [w_{i+1}(U_{i+1}-U_i) - w_i(U_i-U_{i-1})]/h^2 - react*U_i
+ * with U = 0 outside the grid. */
+static void apply_line(int n, const double* face, long face_stride, double h, double react,
+                       const double* u, long us, double* out, long os, int accumulate) {
+  for (int i = 0; i < n; i++) {
+    double ui = u[(long)i * us];
+    double ul = (i > 0) ? u[(long)(i - 1) * us] : 0.0;
+    double ur = (i < n - 1) ? u[(long)(i + 1) * us] : 0.0;
+    double aw = face[(long)i * face_stride];
+    double ae = face[(long)(i + 1) * face_stride];
+    double v = (ae * (ur - ui) - aw * (ui - ul)) / (h * h) - react * ui;
+    if (accumulate)
+      out[(long)i * os] += v;
+    else
+      out[(long)i * os] = v;
+  }
+}
+
+void or_apply_Aj(const or_problem* p, int j, const double* U, double* out) {
+  const int nx = p->nx, ny = p->ny;
+  if (p->split == 0) {
+    const double react = p->c / p->dim;
+    if (j == 0) {
+      for (int row = 0; row < ny; row++)
+        apply_line(nx, p->ax + (long)row * (nx + 1), 1, hx_of(p), react, U + (long)row * nx, 1,
+                   out + (long)row * nx, 1, 0);
+    } else {
+      for (int col = 0; col < nx; col++)
+        apply_line(ny, p->ay + col, nx, hy_of(p), react, U + col, nx, out + col, nx, 0);
+    }
+  } else {
+    double* wface = (double*)malloc(sizeof(double) * (nx + 1));
+    for (int f = 0; f <= nx; f++) wface[f] = p->rho[(long)j * (nx + 1) + f] * p->ax[f];
+    apply_line(nx, wface, 1, hx_of(p), 0.0, U, 1, out, 1, 0);
+    free(wface);
+  }
+}
+
+void or_apply_A(const or_problem* p, const double* U, double* out) {
+  const int npts = npts_of(p);
+  double* tmp = (double*)malloc(sizeof(double) * npts);
+  memset(out, 0, sizeof(double) * npts);
+  for (int j = 0; j < n_terms(p); j++) {
+    or_apply_Aj(p, j, U, tmp);
+    for (int k = 0; k < npts; k++) out[k] += tmp[k];
+  }
+  free(tmp);
+}
+
+void or_faces_from_theta_1d(int nx, const double* theta, double* ax) {
+  for (int f = 0; f <= nx; f++) ax[f] = 0.5 * (exp(theta[f]) + exp(theta[f + 1]));
+}
+
+void or_faces_from_theta(int nx, int ny, const double* theta, double* ax, double* ay) {
+  const int W = nx + 2; /* theta row stride, boundary nodes included */
+  for (int j = 0; j < ny; j++)
+    for (int f = 0; f <= nx; f++) {
+      /* face f of interior row j joins extended nodes (f, j+1) and (f+1, j+1) */
+      double tp = theta[(long)(j + 1) * W + f];
+      double tq = theta[(long)(j + 1) * W + f + 1];
+      ax[(long)j * (nx + 1) + f] = 0.5 * (exp(tp) + exp(tq));
+    }
+  if (ay)
+    for (int g = 0; g <= ny; g++)
+      for (int i = 0; i < nx; i++) {
+        double tp = theta[(long)g * W + i + 1];
+        double tq = theta[(long)(g + 1) * W + i + 1];
+        ay[(long)g * nx + i] = 0.5 * (exp(tp) + exp(tq));
+      }
+}
+
+/* FIE, eq. FIE_method with F = 0: (I - tau A_1) U_1 = U_n,
+ * (I - tau A_j) U_j = U_{j-1}, U_{n+1} = U_M. */
+void or_fie_step(const or_problem* p, double tau, double* U) {
+  for (int j = 0; j < n_terms(p); j++) implicit_substep(p, j, tau, U);
+}
+
+/* Douglas-Rachford, eq. DR_method with F = 0:
+ * U_0 = (I + tau A) U_n, (I - tau A_j) U_j = U_{j-1} - tau A_j U_n. */
+void or_dr_step(const or_problem* p, double tau, double* U) {
+  const int npts = npts_of(p);
+  double* Un = (double*)malloc(sizeof(double) * npts);
+  double* AU = (double*)malloc(sizeof(double) * npts);
+  double* V = (double*)malloc(sizeof(double) * npts);
+  memcpy(Un, U, sizeof(double) * npts);
+  or_apply_A(p, Un, AU);
+  for (int k = 0; k < npts; k++) V[k] = Un[k] + tau * AU[k];
+  for (int j = 0; j < n_terms(p); j++) {
+    or_apply_Aj(p, j, Un, AU);
+    for (int k = 0; k < npts; k++) V[k] = V[k] - tau * AU[k];
+    implicit_substep(p, j, tau, V);
+  }
+  memcpy(U, V, sizeof(double) * npts);
+  free(Un);
+  free(AU);
+  free(V);
+}
+
+/* Fine propagator: s steps of the fine method at dt = DT/s (section 3). */
+void or_fine(const or_problem* p, double* U) {
+  const double DT = p->T / p->n_slices;
+  const double dt = DT / p->fine_steps;
+  for (int t = 0; t < p->fine_steps; t++) {
+    if (p->fine_method == 1)
+      or_dr_step(p, dt, U);
+    else
+      or_fie_step(p, dt, U);
+  }
+}
+
+/* Coarse propagator: FIE (L-stable, section 4) with coarse_steps steps over DT. */
+void or_coarse(const or_problem* p, double* U) {
+  const double DT = p->T / p->n_slices;
+  const double tau = DT / p->coarse_steps;
+  for (int t = 0; t < p->coarse_steps; t++) or_fie_step(p, tau, U);
+}
+
+void or_fine_batch(const or_problem* p, int n, const double* U_in, double* F_out) {
+  const long npts = npts_of(p);
+  for (int k = 0; k < n; k++) {
+    memcpy(F_out + k * npts, U_in + k * npts, sizeof(double) * npts);
+    or_fine(p, F_out + k * npts);
+  }
+}
+
+void or_sequential_fine(const or_problem* p, const double* u0, double* U) {
+  const long npts = npts_of(p);
+  memcpy(U, u0, sizeof(double) * npts);
+  for (int n = 0; n < p->n_slices; n++) {
+    memcpy(U + (n + 1) * npts, U + n * npts, sizeof(double) * npts);
+    or_fine(p, U + (n + 1) * npts);
+  }
+}
+
+double or_coarse_sweep(const or_problem* p, const double* F, double* G_old, double* U) {
+  const long npts = npts_of(p);
+  const int N = p->n_slices;
+  double* g = (double*)malloc(sizeof(double) * npts);
+  double inc = 0.0;
+  for (int n = 0; n < N; n++) {
+    memcpy(g, U + n * npts, sizeof(double) * npts);
+    or_coarse(p, g); /* g = G(U^{k+1}_n) */
+    double* Unext = U + (n + 1) * npts;
+    double* Gn = G_old + n * npts;
+    for (long q = 0; q < npts; q++) {
+      double v;
+      if (F)
+        v = F[n * npts + q] + (g[q] - Gn[q]);
+      else
+        v = g[q];
+      double d = fabs(v - Unext[q]);
+      if (F && d > inc) inc = d;
+      Unext[q] = v;
+      Gn[q] = g[q];
+    }
+  }
+  free(g);
+  return inc;
+}
+
+int or_parareal(const or_problem* p, const double* u0, int k_max, double tol, double* U,
+                double* inc_hist) {
+  const long npts = npts_of(p);
+  const int N = p->n_slices;
+  double* G_old = (double*)malloc(sizeof(double) * N * npts);
+  double* F = (double*)malloc(sizeof(double) * N * npts);
+  memcpy(U, u0, sizeof(double) * npts);
+  or_coarse_sweep(p, NULL, G_old, U); /* U^0_{n+1} = G(U^0_n) */
+  int k = 0;
+  while (k < k_max) {
+    or_fine_batch(p, N, U, F); /* F_n = F^s(U^k_n) for n = 0..N-1 */
+    double inc = or_coarse_sweep(p, F, G_old, U);
+    if (inc_hist) inc_hist[k] = inc;
+    k++;
+    if (inc < tol) break;
+  }
+  free(G_old);
+  free(F);
+  return k;
+}
+
+/* Adjoint of the fine map.
+ * One FIE step is W = Bx^{-1} U, V = By^{-1} W with Bx = I - tau A_x and
+ * By = I - tau A_y, both symmetric. For L = <lambda, V>:
+ *   mu = By^{-1} lambda,   nu = Bx^{-1} mu,   dL/dU = nu;
+ * and since dBy/da_f = -tau dA_y/da_f, dL/da_f = tau mu^T (dA_y/da_f) V, i.e.
+ *   dL/da_f = -(tau/h^2) (mu_q - mu_p)(V_q - V_p) for a y-face f = (p, q),
+ * with mu = V = 0 on boundary nodes (x-faces likewise with nu and W).
+ * Steps are reversed one by one; the forward states of each slice are
+ * recomputed from the slice's starting state. */
+static void face_grad_x(int nx, int ny, double coef, const double* mu, const double* V,
+                        double* gax) {
+  for (int j = 0; j < ny; j++)
+    for (int f = 0; f <= nx; f++) {
+      double mp = (f > 0) ? mu[(long)j * nx + f - 1] : 0.0;
+      double mq = (f < nx) ? mu[(long)j * nx + f] : 0.0;
+      double vp = (f > 0) ? V[(long)j * nx + f - 1] : 0.0;
+      double vq = (f < nx) ? V[(long)j * nx + f] : 0.0;
+      gax[(long)j * (nx + 1) + f] += -coef * (mq - mp) * (vq - vp);
+    }
+}
+
+static void face_grad_y(int nx, int ny, double coef, const double* mu, const double* V,
+                        double* gay) {
+  for (int g = 0; g <= ny; g++)
+    for (int i = 0; i < nx; i++) {
+      double mp = (g > 0) ? mu[(long)(g - 1) * nx + i] : 0.0;
+      double mq = (g < ny) ? mu[(long)g * nx + i] : 0.0;
+      double vp = (g > 0) ? V[(long)(g - 1) * nx + i] : 0.0;
+      double vq = (g < ny) ? V[(long)g * nx + i] : 0.0;
+      gay[(long)g * nx + i] += -coef * (mq - mp) * (vq - vp);
+    }
+}
+
+void or_adjoint(const or_problem* p, const double* u0, const double* lambda_T, double* grad_u0,
+                double* grad_ax, double* grad_ay) {
+  const int nx = p->nx, ny = p->ny, N = p->n_slices, s = p->fine_steps;
+  const long npts = npts_of(p);
+  const double dt = p->T / N / s;
+  double* ckpt = (double*)malloc(sizeof(double) * (N + 1) * npts);
+  double* Wst = (double*)malloc(sizeof(double) * s * npts); /* after x substep */
+  double* Vst = (double*)malloc(sizeof(double) * s * npts); /* after y substep */
+  double* lam = (double*)malloc(sizeof(double) * npts);
+  or_sequential_fine(p, u0, ckpt);
+  memset(grad_ax, 0, sizeof(double) * ny * (nx + 1));
+  if (p->dim == 2) memset(grad_ay, 0, sizeof(double) * (ny + 1) * nx);
+  memcpy(lam, lambda_T, sizeof(double) * npts);
+  for (int n = N - 1; n >= 0; n--) {
+    double* cur = (double*)malloc(sizeof(double) * npts);
+    memcpy(cur, ckpt + (long)n * npts, sizeof(double) * npts);
+    for (int t = 0; t < s; t++) {
+      implicit_substep(p, 0, dt, cur);
+      memcpy(Wst + (long)t * npts, cur, sizeof(double) * npts);
+      if (p->dim == 2) implicit_substep(p, 1, dt, cur);
+      memcpy(Vst + (long)t * npts, cur, sizeof(double) * npts);
+    }
+    free(cur);
+    for (int t = s - 1; t >= 0; t--) {
+      if (p->dim == 2) {
+        implicit_substep(p, 1, dt, lam); /* lam <- mu */
+        face_grad_y(nx, ny, dt / (hy_of(p) * hy_of(p)), lam, Vst + (long)t * npts, grad_ay);
+      }
+      implicit_substep(p, 0, dt, lam); /* lam <- nu */
+      face_grad_x(nx, ny, dt / (hx_of(p) * hx_of(p)), lam, Wst + (long)t * npts, grad_ax);
+    }
+  }
+  memcpy(grad_u0, lam, sizeof(double) * npts);
+  free(ckpt);
+  free(Wst);
+  free(Vst);
+  free(lam);
+}
+
+void or_theta_grad(int nx, int ny, const double* theta, const double* grad_ax,
+                   const double* grad_ay, double* grad_theta) {
+  const int W = nx + 2;
+  memset(grad_theta, 0, sizeof(double) * (long)(nx + 2) * (ny + 2));
+  for (int j = 0; j < ny; j++)
+    for (int f = 0; f <= nx; f++) {
+      double gf = grad_ax[(long)j * (nx + 1) + f];
+      long p0 = (long)(j + 1) * W + f, q0 = p0 + 1;
+      grad_theta[p0] += 0.5 * exp(theta[p0]) * gf;
+      grad_theta[q0] += 0.5 * exp(theta[q0]) * gf;
+    }
+  if (grad_ay)
+    for (int g = 0; g <= ny; g++)
+      for (int i = 0; i < nx; i++) {
+        double gf = grad_ay[(long)g * nx + i];
+        long p0 = (long)g * W + i + 1, q0 = p0 + W;
+        grad_theta[p0] += 0.5 * exp(theta[p0]) * gf;
+        grad_theta[q0] += 0.5 * exp(theta[q0]) * gf;
+      }
+}
