@@ -1,0 +1,186 @@
+/*
+ * pr.h -- C ABI of the MI355X (gfx950) parareal-with-splitting library.
+ *
+ * Method: Arraras, Gaspar, Jimenez-Ciga, Portero, "Space-time parallel
+ * iterative solvers for the integration of parabolic problems" (arXiv
+ * 2502.08370). The library integrates the semi-discrete problem
+ * U' = (A_1 + ... + A_M) U (section 2.2, eq. semidisc_prob) of the model
+ * problem u_t = div(a grad u) - c u on the unit square / unit interval with
+ * homogeneous Dirichlet data (section 2.1, eq. cont_problem, D = a I), using
+ * the parareal algorithm (section 3) whose coarse propagator G and fine
+ * propagator F are fractional implicit Euler (FIE, eq. FIE_method) under
+ * dimensional splitting (A_1 = x-direction, A_2 = y-direction) or overlapping
+ * domain-decomposition splitting with a partition of unity (section 2.1).
+ *
+ * Discretisation: second-order finite differences on the interior nodes of a
+ * uniform grid, h_x = 1/(nx+1), h_y = 1/(ny+1), diffusion coefficient given on
+ * the cell faces (or as a nodal log-coefficient theta whose face value is the
+ * mean of e^theta over the face's two nodes).
+ *
+ * Layouts (all FP64, all row-major with x fastest):
+ *   state           U[j*nx + i], i in [0,nx), j in [0,ny) (ny = 1 in 1D)
+ *   x-faces         ax[j*(nx+1) + f], face f between nodes f-1 and f
+ *   y-faces         ay[g*nx + i], face g between nodes (i,g-1) and (i,g)
+ *   nodal theta     theta[(j+1)*(nx+2) + (i+1)] with boundary nodes included
+ *                   ((ny+2)*(nx+2) values; nx+2 values in 1D)
+ *   PoU weights     rho[k*(nx+1) + f], colour k, face f (1D DD only)
+ * A problem handle may hold several independent instances ("batch"); their
+ * states are packed one after the other at the offsets pr_query_layout
+ * returns.
+ *
+ * Pointers: every state / coefficient / gradient pointer is DEVICE memory
+ * unless marked "host". hip_stream is a hipStream_t (NULL = default stream).
+ * The caller owns every buffer it passes and keeps it alive until the work
+ * queued on the stream has finished; the library owns its workspace
+ * (factorisations, scratch, graphs), allocated in pr_create_problem and
+ * released in pr_destroy_problem; no other call allocates device memory
+ * except pr_parareal_iterate, which builds its iteration graph on first use.
+ *
+ * Errors: every entry point returns a pr_status. Arguments are validated
+ * before any work is queued: on PR_EINVAL / PR_EUNSUPPORTED nothing has been
+ * written. HIP failures map to PR_EDEVICE, a NaN/Inf increment to
+ * PR_ENUMERIC. pr_last_error() returns a thread-local message for the last
+ * failure. No C++ exception crosses this interface. A handle must not be used
+ * from two threads at once; distinct handles are independent.
+ */
+#ifndef PR_H
+#define PR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pr_problem_s* pr_problem;
+
+typedef enum {
+  PR_OK = 0,
+  PR_EINVAL = 1,        /* invalid argument or descriptor */
+  PR_ENOMEM = 2,        /* device or host allocation failed */
+  PR_EDEVICE = 3,       /* a HIP call failed */
+  PR_ENUMERIC = 4,      /* NaN or Inf detected in a parareal increment */
+  PR_EUNSUPPORTED = 5   /* valid request outside what this build implements */
+} pr_status;
+
+enum { PR_SPLIT_DIM = 0, PR_SPLIT_DD = 1 };          /* section 2.1 */
+enum { PR_FIE = 0, PR_DR = 1 };                      /* eq. FIE_method, eq. DR_method */
+enum { PR_COEF_FACES = 0, PR_COEF_NODAL_LOG = 1 };
+
+/* Description of one problem instance (section 2.1, section 3).
+ *   dim            1 or 2
+ *   nx, ny         interior nodes per direction (ny must be 1 when dim == 1)
+ *   T              final time (> 0)
+ *   n_slices       N_c: coarse intervals, DT = T / N_c
+ *   fine_steps     s: fine steps per coarse interval, dt = DT / s
+ *   coarse_steps   FIE steps taken by one application of G (>= 1)
+ *   fine           PR_FIE (PR_DR is reserved and rejected)
+ *   split          PR_SPLIT_DIM (dim 1 or 2) or PR_SPLIT_DD (dim 1 only)
+ *   coef_mode      PR_COEF_FACES: coef_x = ax, coef_y = ay (NULL in 1D)
+ *                  PR_COEF_NODAL_LOG: coef_x = theta, coef_y unused
+ *   coef_x, coef_y device pointers, read during pr_create_problem /
+ *                  pr_set_coefficients only
+ *   c              reaction coefficient >= 0; split equally over the M
+ *                  dimensional terms (c/M per substep); must be 0 for DD
+ *   n_colors       DD: number M of split terms (colours), 1..64
+ *   rho            DD: HOST pointer to the partition-of-unity face weights
+ *                  [n_colors][nx+1], each in [0,1], summing to 1 on every
+ *                  face (|sum - 1| <= 1e-14). The connected components of
+ *                  colour k are the maximal runs of faces with rho_k > 0;
+ *                  each component is one independent tridiagonal system. */
+typedef struct {
+  int dim, nx, ny;
+  double T;
+  int n_slices, fine_steps, coarse_steps;
+  int fine;
+  int split;
+  int coef_mode;
+  const double* coef_x;
+  const double* coef_y;
+  double c;
+  int n_colors;
+  const double* rho;
+} pr_problem_desc;
+
+/* Per-instance offsets (in doubles) into the packed buffers of a batch:
+ *   u0_offset      single-state buffers (u0, grad_u0, lambda_T): npts each
+ *   slices_offset  N-state buffers (pr_fine_propagate in/out, G_old): N*npts
+ *   states_offset  (N+1)-state buffers (parareal iterate U): (N+1)*npts */
+typedef struct {
+  size_t u0_offset, slices_offset, states_offset;
+  int npts, n_slices;
+} pr_instance_layout;
+
+/* Create a handle for n_instances problems (descs[0..n_instances-1], host
+ * array). Validates every descriptor, allocates the workspace and computes
+ * the per-line LU factorisations of I - tau A_j for tau = dt and tau = DT/
+ * coarse_steps (section 2.2, eq. FIE_method), reading the coefficients on
+ * hip_stream. *out receives the handle (NULL on failure). */
+pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void* hip_stream,
+                            pr_problem* out);
+
+/* Release the handle and its workspace (waits for the device). NULL is OK. */
+pr_status pr_destroy_problem(pr_problem p);
+
+/* Fill per_instance[0..n_instances-1] (host, may be NULL) and totals[3]
+ * (host, may be NULL) = total doubles of the u0 / slices / states buffers. */
+pr_status pr_query_layout(pr_problem p, pr_instance_layout* per_instance, size_t* totals);
+
+/* Number of instances in the handle (host int). */
+pr_status pr_num_instances(pr_problem p, int* n_instances);
+
+/* Replace the diffusion coefficient of one instance (same coef_mode as at
+ * creation; device pointers) and recompute its factorisations on hip_stream. */
+pr_status pr_set_coefficients(pr_problem p, int instance, const double* coef_x,
+                              const double* coef_y, void* hip_stream);
+
+/* Fine propagator for all slices at once (section 3): F_out[n] = F^s(U_in[n])
+ * for every instance and n = 0..N-1, each F^s being s FIE steps of size dt.
+ * U_in and F_out use the slices layout and must not overlap. Asynchronous. */
+pr_status pr_fine_propagate(pr_problem p, const double* U_in, double* F_out, void* hip_stream);
+
+/* Coarse sweep of the parareal correction (section 3), serial in n:
+ *   F == NULL (initial guess):  U[n+1] = G(U[n]),  G_old[n] = G(U[n])
+ *   F != NULL (iteration):      g = G(U[n]); U[n+1] = F[n] + (g - G_old[n]);
+ *                               G_old[n] = g
+ * for n = 0..N-1 with U[0] left unchanged. U uses the states layout, F and
+ * G_old the slices layout. inc_dev (device, n_instances doubles, may be NULL)
+ * receives max_{n>=1} max_i |U_new[n]_i - U_old[n]_i| per instance (0 for the
+ * initial guess; NaN/Inf propagate). Asynchronous. */
+pr_status pr_coarse_sweep(pr_problem p, const double* F, double* G_old, double* U,
+                          double* inc_dev, void* hip_stream);
+
+/* Parareal (section 3): U[0] = u0, initial coarse guess, then corrections
+ * until k_max corrections were done or the increment of an instance drops
+ * below tol (instances that converged stop changing). u0 uses the u0 layout,
+ * U the states layout (output: the final iterate). k_done and inc are HOST
+ * arrays of n_instances entries: corrections performed and the last
+ * increment. Each correction is one replay of a captured HIP graph followed
+ * by one host synchronisation. Returns PR_ENUMERIC if an increment is NaN/Inf.
+ * Reaching k_max with inc >= tol is not an error. */
+pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_max, double tol,
+                              int* k_done, double* inc, void* hip_stream);
+
+/* Sequential fine solution (section 3, "fine approximation"): U[0] = u0,
+ * U[n+1] = F^s(U[n]). u0: u0 layout, U: states layout. Asynchronous. */
+pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hip_stream);
+
+/* Adjoint of the fine map u(T) = (F^s)^N u0 (dimensional splitting, FIE,
+ * single-instance handles): for L = <lambda_T, u(T)>, writes
+ * grad_u0 = dL/du0 (u0 layout) and grad_coef = dL/d(coefficient) in the
+ * handle's coef_mode (faces: ax gradient followed by ay gradient; nodal log:
+ * gradient with respect to theta, (nx+2)*(ny+2) values). U_ckpt (device,
+ * states layout, may be NULL) receives the slice-boundary checkpoints of the
+ * forward solve. Each FIE step is reversed with the transposed (= same,
+ * symmetric) line solves in reverse substep order; the forward states inside
+ * a slice are recomputed from its checkpoint. Asynchronous. */
+pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, double* grad_u0,
+                     double* grad_coef, double* U_ckpt, void* hip_stream);
+
+/* Thread-local message describing the last non-OK status ("" if none). */
+const char* pr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,177 @@
+"""MI355X-native parareal with splitting (arXiv 2502.08370): Python front end.
+
+The numerical work runs in libpr.so (hand-written HIP for gfx950) behind the C
+ABI of include/pr.h. This module marshals torch CUDA (HIP) tensors and the
+current stream into those calls; torch provides device memory and streams
+only.
+
+    import paper_2502_08370_amd as pr
+    prob = pr.Problem([dict(dim=2, nx=1023, ny=1023, T=0.05, n_slices=64, fine_steps=64,
+                            ax=ax, ay=ay)])
+    U = prob.new_states()
+    k, inc = prob.parareal_iterate(u0, U, k_max=64, tol=1e-8)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _binding as B
+from ._binding import PrError
+
+__all__ = ["Problem", "PrError", "lib"]
+
+lib = B.lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(a, device):
+    torch = _torch()
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.detach().to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """A handle over one or more independent problem instances (section 2.1 model,
+    section 3 parareal).
+
+    Each instance is a dict with keys: dim, nx, ny, T, n_slices, fine_steps,
+    coarse_steps (1), split ('dim' | 'dd'), fine ('fie'), c (0.0), and either
+    ax / ay (face coefficients) or theta (nodal log coefficient), plus rho
+    (partition-of-unity face weights, host array) for 'dd'.
+    """
+
+    def __init__(self, instances, device="cuda", stream=None):
+        torch = _torch()
+        if isinstance(instances, dict):
+            instances = [instances]
+        self.device = torch.device(device)
+        n = len(instances)
+        descs = (B.PrProblemDesc * n)()
+        keep = []
+        self.instances = []
+        for i, ins in enumerate(instances):
+            d = descs[i]
+            d.dim, d.nx = int(ins["dim"]), int(ins["nx"])
+            d.ny = 1 if d.dim == 1 else int(ins["ny"])
+            d.T = float(ins["T"])
+            d.n_slices, d.fine_steps = int(ins["n_slices"]), int(ins["fine_steps"])
+            d.coarse_steps = int(ins.get("coarse_steps", 1))
+            d.fine = B.PR_DR if ins.get("fine", "fie") == "dr" else B.PR_FIE
+            d.split = B.PR_SPLIT_DD if ins.get("split", "dim") == "dd" else B.PR_SPLIT_DIM
+            d.c = float(ins.get("c", 0.0))
+            if ins.get("theta") is not None:
+                d.coef_mode = B.PR_COEF_NODAL_LOG
+                cx, cy = _dev_f64(ins["theta"], self.device), None
+            else:
+                d.coef_mode = B.PR_COEF_FACES
+                cx = _dev_f64(ins["ax"], self.device)
+                cy = _dev_f64(ins.get("ay"), self.device)
+            keep += [cx, cy]
+            d.coef_x, d.coef_y = _ptr(cx), _ptr(cy)
+            rho = ins.get("rho")
+            if rho is not None:
+                rho = np.ascontiguousarray(rho, dtype=np.float64)
+                keep.append(rho)
+                d.n_colors = rho.shape[0]
+                d.rho = C.c_void_p(rho.ctypes.data)
+            self.instances.append(dict(dim=d.dim, nx=d.nx, ny=d.ny, n_slices=d.n_slices,
+                                       coef_mode=d.coef_mode))
+        h = C.c_void_p()
+        B.check(B.lib().pr_create_problem(descs, n, _stream(stream), C.byref(h)))
+        self._h = h
+        lay = (B.PrInstanceLayout * n)()
+        tot = (C.c_size_t * 3)()
+        B.check(B.lib().pr_query_layout(h, lay, tot))
+        self.layout = [dict(u0=l.u0_offset, slices=l.slices_offset, states=l.states_offset,
+                            npts=l.npts, n_slices=l.n_slices) for l in lay]
+        self.totals = dict(u0=tot[0], slices=tot[1], states=tot[2])
+        del keep
+
+    # ---------------------------------------------------------------- buffers
+    def _new(self, kind):
+        torch = _torch()
+        return torch.zeros(self.totals[kind], dtype=torch.float64, device=self.device)
+
+    def new_u0(self):
+        return self._new("u0")
+
+    def new_slices(self):
+        return self._new("slices")
+
+    def new_states(self):
+        return self._new("states")
+
+    def view(self, buf, i, kind):
+        """Instance i's part of a packed buffer, shaped (count, ny, nx) or (ny, nx)."""
+        l, ins = self.layout[i], self.instances[i]
+        shape = (ins["ny"], ins["nx"]) if ins["dim"] == 2 else (ins["nx"],)
+        off = l[kind]
+        if kind == "u0":
+            return buf[off:off + l["npts"]].view(shape)
+        cnt = l["n_slices"] + (1 if kind == "states" else 0)
+        return buf[off:off + cnt * l["npts"]].view((cnt,) + shape)
+
+    def pack_u0(self, u0s):
+        """Pack a list of per-instance initial states into one device buffer."""
+        buf = self.new_u0()
+        for i, u in enumerate(u0s):
+            self.view(buf, i, "u0").copy_(_dev_f64(u, self.device).view(self.view(buf, i, "u0").shape))
+        return buf
+
+    # ------------------------------------------------------------ entry points
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            B.lib().pr_destroy_problem(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_coefficients(self, i, coef_x, coef_y=None, stream=None):
+        cx, cy = _dev_f64(coef_x, self.device), _dev_f64(coef_y, self.device)
+        B.check(B.lib().pr_set_coefficients(self._h, int(i), _ptr(cx), _ptr(cy), _stream(stream)))
+        _torch().cuda.current_stream().synchronize()
+
+    def fine_propagate(self, U_in, F_out, stream=None):
+        B.check(B.lib().pr_fine_propagate(self._h, _ptr(U_in), _ptr(F_out), _stream(stream)))
+
+    def coarse_sweep(self, F, G_old, U, inc=None, stream=None):
+        B.check(B.lib().pr_coarse_sweep(self._h, _ptr(F), _ptr(G_old), _ptr(U), _ptr(inc),
+                                        _stream(stream)))
+
+    def parareal_iterate(self, u0, U, k_max, tol=0.0, stream=None):
+        n = len(self.layout)
+        k = (C.c_int * n)()
+        inc = (C.c_double * n)()
+        B.check(B.lib().pr_parareal_iterate(self._h, _ptr(u0), _ptr(U), int(k_max), float(tol), k,
+                                            inc, _stream(stream)))
+        return list(k), list(inc)
+
+    def sequential_fine(self, u0, U, stream=None):
+        B.check(B.lib().pr_sequential_fine(self._h, _ptr(u0), _ptr(U), _stream(stream)))
+
+    def adjoint(self, u0, lambda_T, grad_u0, grad_coef, U_ckpt=None, stream=None):
+        B.check(B.lib().pr_adjoint(self._h, _ptr(u0), _ptr(lambda_T), _ptr(grad_u0),
+                                   _ptr(grad_coef), _ptr(U_ckpt), _stream(stream)))

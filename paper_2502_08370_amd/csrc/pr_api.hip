@@ -1,0 +1,535 @@
+// Host runtime of the parareal-with-splitting library: validation, workspace,
+// factorisation set-up and the launch sequences behind the C ABI of pr.h.
+// Method: arXiv 2502.08370 (section 2: splitting and FIE; section 3: parareal).
+#include "pr.h"
+#include "pr_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace prk;
+
+namespace {
+
+thread_local std::string g_err;
+
+pr_status fail(pr_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPOK(expr)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(PR_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+int pow2_at_least(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Device buffer owned by the library.
+struct DBuf {
+  double* p = nullptr;
+  size_t n = 0;
+  ~DBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t count) {
+    n = count;
+    if (count == 0) return hipSuccess;
+    return hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(double));
+  }
+};
+
+struct Instance {
+  pr_problem_desc d;  // copy (pointer members are not retained)
+  int npts = 0;
+  double dt = 0, tauG = 0;
+  size_t off_u0 = 0, off_slices = 0, off_states = 0;
+  // dimensional splitting
+  DimInst h{};       // host mirror of the device descriptor (all-slices layout)
+  DimInst hseq{};    // single-slice variant (sequential fine solve)
+  DBuf ax, ay, theta;
+  DBuf fxE, fxR, fxG, fyE, fyR, fyG, fxPhiC, fyPhiC, fxPhiS, fyPhiS;
+  DBuf cxE, cxR, cxG, cyE, cyR, cyG;
+  DBuf Z, sigX, sigY, tmp;
+  DBuf Zseq, sigXseq, sigYseq;
+};
+
+}  // namespace
+
+struct pr_problem_s {
+  std::vector<std::unique_ptr<Instance>> inst;
+  size_t tot_u0 = 0, tot_slices = 0, tot_states = 0;
+  int M = 32;  // fine-sweep chunk length
+  // device descriptors: [0, n) all-slices variants, [n, 2n) single-slice variants
+  DimInst* d_inst = nullptr;
+  // grouped work lists per lane width L (index log2 L) and direction
+  struct Group {
+    int L = 0;
+    WorkItem* d_work[2] = {nullptr, nullptr};
+    int n_work[2] = {0, 0};
+  };
+  std::vector<Group> groups;
+  std::vector<Group> seq_groups;  // one per instance, L = 1
+  // parareal workspace
+  DBuf F, Gold;
+  unsigned long long* d_inc = nullptr;
+  double* h_inc = nullptr;  // pinned
+  ~pr_problem_s() {
+    if (d_inst) (void)hipFree(d_inst);
+    for (auto* gs : {&groups, &seq_groups})
+      for (auto& g : *gs)
+        for (auto* w : g.d_work)
+          if (w) (void)hipFree(w);
+    if (d_inc) (void)hipFree(d_inc);
+    if (h_inc) (void)hipHostFree(h_inc);
+  }
+};
+
+namespace {
+
+pr_status validate(const pr_problem_desc& d, int idx) {
+  if (d.dim != 1 && d.dim != 2) return fail(PR_EINVAL, "instance %d: dim must be 1 or 2", idx);
+  if (d.nx < 1 || d.ny < 1) return fail(PR_EINVAL, "instance %d: nx, ny must be >= 1", idx);
+  if (d.dim == 1 && d.ny != 1) return fail(PR_EINVAL, "instance %d: ny must be 1 in 1D", idx);
+  if ((long)d.nx * d.ny > (1L << 31) / 8) return fail(PR_EINVAL, "instance %d: grid too large", idx);
+  if (!(d.T > 0) || !std::isfinite(d.T)) return fail(PR_EINVAL, "instance %d: T must be > 0", idx);
+  if (d.n_slices < 1 || d.fine_steps < 1 || d.coarse_steps < 1)
+    return fail(PR_EINVAL, "instance %d: n_slices, fine_steps, coarse_steps must be >= 1", idx);
+  if (d.fine != PR_FIE && d.fine != PR_DR) return fail(PR_EINVAL, "instance %d: bad fine", idx);
+  if (d.fine == PR_DR)
+    return fail(PR_EUNSUPPORTED, "instance %d: Douglas-Rachford fine propagator not built", idx);
+  if (d.split != PR_SPLIT_DIM && d.split != PR_SPLIT_DD)
+    return fail(PR_EINVAL, "instance %d: bad split", idx);
+  if (d.coef_mode != PR_COEF_FACES && d.coef_mode != PR_COEF_NODAL_LOG)
+    return fail(PR_EINVAL, "instance %d: bad coef_mode", idx);
+  if (!d.coef_x) return fail(PR_EINVAL, "instance %d: coef_x is NULL", idx);
+  if (d.dim == 2 && d.coef_mode == PR_COEF_FACES && !d.coef_y)
+    return fail(PR_EINVAL, "instance %d: coef_y is NULL", idx);
+  if (!(d.c >= 0) || !std::isfinite(d.c)) return fail(PR_EINVAL, "instance %d: c must be >= 0", idx);
+  if (d.split == PR_SPLIT_DIM && d.dim == 1)
+    return fail(PR_EUNSUPPORTED, "instance %d: 1D problems use the DD split (one colour, rho = 1)",
+                idx);
+  if (d.split == PR_SPLIT_DD) {
+    if (d.dim != 1) return fail(PR_EUNSUPPORTED, "instance %d: DD splitting is 1D only", idx);
+    return fail(PR_EUNSUPPORTED, "instance %d: DD splitting not built yet", idx);
+  }
+  return PR_OK;
+}
+
+pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
+  const pr_problem_desc& d = I.d;
+  const int nx = d.nx, ny = d.ny, N = d.n_slices, M = P->M;
+  const size_t npts = (size_t)nx * ny;
+  I.npts = (int)npts;
+  I.dt = d.T / d.n_slices / d.fine_steps;
+  I.tauG = d.T / d.n_slices / d.coarse_steps;
+  // face coefficients
+  HIPOK(I.ax.alloc((size_t)ny * (nx + 1)));
+  if (d.dim == 2) HIPOK(I.ay.alloc((size_t)(ny + 1) * nx));
+  pr_status st = PR_OK;
+  (void)st;
+  const int Px = (nx + M - 1) / M, Py = (ny + M - 1) / M;
+  HIPOK(I.fxE.alloc(npts)); HIPOK(I.fxR.alloc(npts)); HIPOK(I.fxG.alloc(npts));
+  HIPOK(I.cxE.alloc(npts)); HIPOK(I.cxR.alloc(npts)); HIPOK(I.cxG.alloc(npts));
+  HIPOK(I.fxPhiC.alloc(npts)); HIPOK(I.fxPhiS.alloc((size_t)ny * Px));
+  if (d.dim == 2) {
+    HIPOK(I.fyE.alloc(npts)); HIPOK(I.fyR.alloc(npts)); HIPOK(I.fyG.alloc(npts));
+    HIPOK(I.cyE.alloc(npts)); HIPOK(I.cyR.alloc(npts)); HIPOK(I.cyG.alloc(npts));
+    HIPOK(I.fyPhiC.alloc(npts)); HIPOK(I.fyPhiS.alloc((size_t)nx * Py));
+  }
+  const int L = std::min(64, pow2_at_least(N));
+  const int B = (N + L - 1) / L;
+  DimInst& h = I.h;
+  h.nx = nx; h.ny = ny; h.N = N; h.L = L; h.B = B; h.M = M; h.Px = Px; h.Py = Py;
+  h.steps = d.fine_steps;
+  h.slab = (long)npts * L;
+  HIPOK(I.Z.alloc((size_t)B * npts * L));
+  HIPOK(I.sigX.alloc((size_t)B * ny * Px * L));
+  if (d.dim == 2) HIPOK(I.sigY.alloc((size_t)B * nx * Py * L));
+  HIPOK(I.tmp.alloc(npts));
+  h.Z = I.Z.p; h.sigX = I.sigX.p; h.sigY = I.sigY.p;
+  h.fxE = I.fxE.p; h.fxR = I.fxR.p; h.fxG = I.fxG.p;
+  h.fyE = I.fyE.p; h.fyR = I.fyR.p; h.fyG = I.fyG.p;
+  h.fxPhiC = I.fxPhiC.p; h.fyPhiC = I.fyPhiC.p; h.fxPhiS = I.fxPhiS.p; h.fyPhiS = I.fyPhiS.p;
+  h.cxE = I.cxE.p; h.cxR = I.cxR.p; h.cxG = I.cxG.p;
+  h.cyE = I.cyE.p; h.cyR = I.cyR.p; h.cyG = I.cyG.p;
+  h.tmp = I.tmp.p;
+  // single-slice variant for the sequential fine solve
+  I.hseq = h;
+  I.hseq.N = 1; I.hseq.L = 1; I.hseq.B = 1; I.hseq.slab = (long)npts;
+  HIPOK(I.Zseq.alloc(npts));
+  HIPOK(I.sigXseq.alloc((size_t)ny * Px));
+  if (d.dim == 2) HIPOK(I.sigYseq.alloc((size_t)nx * Py));
+  I.hseq.Z = I.Zseq.p; I.hseq.sigX = I.sigXseq.p; I.hseq.sigY = I.sigYseq.p;
+  return PR_OK;
+}
+
+// Factorisations of I - tau A_x, I - tau A_y at tau = dt (fine, line-major, with
+// chunk phi) and tau = DT / coarse_steps (coarse, position-major).
+pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
+                             const double* coef_y, hipStream_t s) {
+  const pr_problem_desc& d = I.d;
+  const int nx = d.nx, ny = d.ny, M = P->M;
+  if (d.coef_mode == PR_COEF_NODAL_LOG) {
+    if (d.dim == 2)
+      HIPOK(launch_faces_from_theta_2d(coef_x, nx, ny, I.ax.p, I.ay.p, s));
+    else
+      HIPOK(launch_faces_from_theta_1d(coef_x, nx, I.ax.p, s));
+  } else {
+    HIPOK(hipMemcpyAsync(I.ax.p, coef_x, I.ax.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (d.dim == 2)
+      HIPOK(hipMemcpyAsync(I.ay.p, coef_y, I.ay.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  const double hx = 1.0 / (nx + 1), hy = 1.0 / (ny + 1);
+  const double react = d.c / d.dim;
+  for (int coarse = 0; coarse < 2; coarse++) {
+    const double tau = coarse ? I.tauG : I.dt;
+    FactorJob jx{};
+    jx.face = I.ax.p; jx.n_lines = ny; jx.n_pos = nx;
+    jx.face_line_stride = nx + 1; jx.face_pos_stride = 1;
+    jx.tau_over_h2 = tau / (hx * hx); jx.react = tau * react;
+    jx.E = coarse ? I.cxE.p : I.fxE.p; jx.R = coarse ? I.cxR.p : I.fxR.p;
+    jx.G = coarse ? I.cxG.p : I.fxG.p; jx.pos_major = coarse;
+    HIPOK(launch_factorize(jx, s));
+    if (d.dim == 2) {
+      FactorJob jy{};
+      jy.face = I.ay.p; jy.n_lines = nx; jy.n_pos = ny;
+      jy.face_line_stride = 1; jy.face_pos_stride = nx;
+      jy.tau_over_h2 = tau / (hy * hy); jy.react = tau * react;
+      jy.E = coarse ? I.cyE.p : I.fyE.p; jy.R = coarse ? I.cyR.p : I.fyR.p;
+      jy.G = coarse ? I.cyG.p : I.fyG.p; jy.pos_major = coarse;
+      HIPOK(launch_factorize(jy, s));
+    }
+  }
+  HIPOK(launch_chunk_phi(I.fxG.p, ny, nx, M, I.fxPhiC.p, I.fxPhiS.p, s));
+  if (d.dim == 2) HIPOK(launch_chunk_phi(I.fyG.p, nx, ny, M, I.fyPhiC.p, I.fyPhiS.p, s));
+  return PR_OK;
+}
+
+// Work list of one direction for the instances in `members` (all-slices
+// variant): items (inst, b, group), ordered so that line groups whose values
+// share the previous sweep's chunk carries run on the same XCD (workgroups are
+// dealt to the 8 XCDs round-robin by id).
+std::vector<WorkItem> build_work(const std::vector<int>& members,
+                                 const std::vector<std::unique_ptr<Instance>>& inst, int dir,
+                                 int M, bool seq) {
+  const int kXcd = 8;
+  std::vector<std::vector<WorkItem>> per(kXcd);
+  for (int m : members) {
+    const DimInst& h = seq ? inst[m]->hseq : inst[m]->h;
+    if (dir == 1 && inst[m]->d.dim == 1) continue;
+    const int n_lines = dir == 0 ? h.ny : h.nx;
+    const int G = 64 / h.L;
+    const int n_groups = (n_lines + G - 1) / G;
+    const int groups_per_chunk = std::max(1, M / G);
+    for (int b = 0; b < h.B; b++)
+      for (int g = 0; g < n_groups; g++) {
+        int x = (g / groups_per_chunk) % kXcd;
+        per[x].push_back(WorkItem{m, b, g, 0});
+      }
+  }
+  std::vector<WorkItem> out;
+  size_t longest = 0;
+  for (auto& v : per) longest = std::max(longest, v.size());
+  for (size_t r = 0; r < longest; r++)
+    for (int x = 0; x < kXcd; x++)
+      if (r < per[x].size()) out.push_back(per[x][r]);
+  return out;
+}
+
+hipError_t upload_work(const std::vector<WorkItem>& w, WorkItem** d, int* n) {
+  *n = (int)w.size();
+  if (w.empty()) return hipSuccess;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(d), w.size() * sizeof(WorkItem));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*d, w.data(), w.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Fine propagation of every slice of every instance: in_base + per-instance
+// offset (slices or states layout) -> out_base + slices offset.
+pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout, double* out_base,
+                   hipStream_t s) {
+  const int n = (int)P->inst.size();
+  for (int i = 0; i < n; i++) {
+    Instance& I = *P->inst[i];
+    const double* U = in_base + (in_states_layout ? I.off_states : I.off_slices);
+    HIPOK(launch_to_interleaved(P->d_inst + i, I.h, U, s));
+  }
+  // all instances advance step by step; one grouped launch per lane width and direction
+  int smax = 0;
+  for (auto& I : P->inst) smax = std::max(smax, I->d.fine_steps);
+  for (int t = 0; t < smax; t++) {
+    for (auto& g : P->groups) {
+      for (int dir = 0; dir < 2; dir++) {
+        if (!g.n_work[dir]) continue;
+        HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir], g.n_work[dir], g.L, P->M, dir,
+                                dir == 1 || t > 0, t, s));
+      }
+    }
+  }
+  for (int i = 0; i < n; i++) {
+    Instance& I = *P->inst[i];
+    HIPOK(launch_from_interleaved(P->d_inst + i, I.h, out_base + I.off_slices, s));
+  }
+  return PR_OK;
+}
+
+// One coarse propagation G (coarse_steps FIE steps) of state src of instance i,
+// finishing with the y sweep in `mode` (see launch_coarse_y).
+pr_status coarse_apply(pr_problem_s* P, int i, const double* src, int mode, const double* F,
+                       double* Gold, double* Unext, unsigned long long* inc, hipStream_t s) {
+  Instance& I = *P->inst[i];
+  const DimInst* dI = P->d_inst + i;
+  for (int c = 0; c < I.d.coarse_steps; c++) {
+    const double* from = c == 0 ? src : I.tmp.p;
+    HIPOK(launch_coarse_x(dI, I.h, from, I.tmp.p, s));
+    const bool last = c + 1 == I.d.coarse_steps;
+    HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, I.tmp.p, last ? mode : 0, F, Gold, Unext, inc, s));
+  }
+  return PR_OK;
+}
+
+pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, double* U,
+                            unsigned long long* inc_bits, hipStream_t s,
+                            const std::vector<char>* active) {
+  const int n = (int)P->inst.size();
+  if (inc_bits) HIPOK(launch_fill_zero(reinterpret_cast<double*>(inc_bits), n, s));
+  for (int i = 0; i < n; i++) {
+    if (active && !(*active)[i]) continue;
+    Instance& I = *P->inst[i];
+    for (int k = 0; k < I.d.n_slices; k++) {
+      const double* Un = U + I.off_states + (size_t)k * I.npts;
+      double* Unext = U + I.off_states + (size_t)(k + 1) * I.npts;
+      double* Gk = Gold + I.off_slices + (size_t)k * I.npts;
+      const double* Fk = F ? F + I.off_slices + (size_t)k * I.npts : nullptr;
+      pr_status st = coarse_apply(P, i, Un, F ? 1 : 2, Fk, Gk, Unext,
+                                  inc_bits ? inc_bits + i : P->d_inc + i, s);
+      if (st != PR_OK) return st;
+    }
+  }
+  return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pr_last_error(void) { return g_err.c_str(); }
+
+pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void* hip_stream,
+                            pr_problem* out) {
+  if (!out) return fail(PR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!descs || n_instances < 1) return fail(PR_EINVAL, "need at least one descriptor");
+  for (int i = 0; i < n_instances; i++) {
+    pr_status st = validate(descs[i], i);
+    if (st != PR_OK) return st;
+  }
+  hipStream_t s = as_stream(hip_stream);
+  std::unique_ptr<pr_problem_s> P(new (std::nothrow) pr_problem_s());
+  if (!P) return fail(PR_ENOMEM, "host allocation failed");
+  size_t ou = 0, osl = 0, ost = 0;
+  for (int i = 0; i < n_instances; i++) {
+    auto I = std::make_unique<Instance>();
+    I->d = descs[i];
+    I->d.coef_x = I->d.coef_y = I->d.rho = nullptr;
+    const size_t npts = (size_t)descs[i].nx * descs[i].ny;
+    I->off_u0 = ou; I->off_slices = osl; I->off_states = ost;
+    ou += npts; osl += npts * descs[i].n_slices; ost += npts * (descs[i].n_slices + 1);
+    pr_status st = setup_dim_instance(P.get(), *I, s);
+    if (st != PR_OK) return st;
+    st = factorize_instance(P.get(), *I, descs[i].coef_x, descs[i].coef_y, s);
+    if (st != PR_OK) return st;
+    P->inst.push_back(std::move(I));
+  }
+  P->tot_u0 = ou; P->tot_slices = osl; P->tot_states = ost;
+  // device descriptors
+  std::vector<DimInst> hd(2 * n_instances);
+  for (int i = 0; i < n_instances; i++) {
+    hd[i] = P->inst[i]->h;
+    hd[n_instances + i] = P->inst[i]->hseq;
+  }
+  HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_inst), hd.size() * sizeof(DimInst)));
+  HIPOK(hipMemcpy(P->d_inst, hd.data(), hd.size() * sizeof(DimInst), hipMemcpyHostToDevice));
+  // grouped work lists by lane width
+  for (int L = 1; L <= 64; L <<= 1) {
+    std::vector<int> members;
+    for (int i = 0; i < n_instances; i++)
+      if (P->inst[i]->h.L == L) members.push_back(i);
+    if (members.empty()) continue;
+    pr_problem_s::Group g;
+    g.L = L;
+    for (int dir = 0; dir < 2; dir++)
+      HIPOK(upload_work(build_work(members, P->inst, dir, P->M, false), &g.d_work[dir],
+                        &g.n_work[dir]));
+    P->groups.push_back(g);
+  }
+  for (int i = 0; i < n_instances; i++) {
+    pr_problem_s::Group g;
+    g.L = 1;
+    std::vector<WorkItem> w;
+    for (int dir = 0; dir < 2; dir++) {
+      std::vector<WorkItem> wl = build_work({i}, P->inst, dir, P->M, true);
+      for (auto& it : wl) it.inst = n_instances + i;  // single-slice descriptor
+      HIPOK(upload_work(wl, &g.d_work[dir], &g.n_work[dir]));
+    }
+    P->seq_groups.push_back(g);
+  }
+  // parareal workspace
+  HIPOK(P->F.alloc(osl));
+  HIPOK(P->Gold.alloc(osl));
+  HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_inc), n_instances * sizeof(unsigned long long)));
+  HIPOK(hipHostMalloc(reinterpret_cast<void**>(&P->h_inc), n_instances * sizeof(double)));
+  HIPOK(hipStreamSynchronize(s));
+  *out = P.release();
+  return PR_OK;
+}
+
+pr_status pr_destroy_problem(pr_problem p) {
+  if (!p) return PR_OK;
+  (void)hipDeviceSynchronize();
+  delete p;
+  return PR_OK;
+}
+
+pr_status pr_num_instances(pr_problem p, int* n) {
+  if (!p || !n) return fail(PR_EINVAL, "NULL argument");
+  *n = (int)p->inst.size();
+  return PR_OK;
+}
+
+pr_status pr_query_layout(pr_problem p, pr_instance_layout* per, size_t* totals) {
+  if (!p) return fail(PR_EINVAL, "NULL handle");
+  if (per)
+    for (size_t i = 0; i < p->inst.size(); i++) {
+      const Instance& I = *p->inst[i];
+      per[i].u0_offset = I.off_u0;
+      per[i].slices_offset = I.off_slices;
+      per[i].states_offset = I.off_states;
+      per[i].npts = I.npts;
+      per[i].n_slices = I.d.n_slices;
+    }
+  if (totals) {
+    totals[0] = p->tot_u0;
+    totals[1] = p->tot_slices;
+    totals[2] = p->tot_states;
+  }
+  return PR_OK;
+}
+
+pr_status pr_set_coefficients(pr_problem p, int instance, const double* coef_x,
+                              const double* coef_y, void* hip_stream) {
+  if (!p) return fail(PR_EINVAL, "NULL handle");
+  if (instance < 0 || instance >= (int)p->inst.size()) return fail(PR_EINVAL, "bad instance");
+  Instance& I = *p->inst[instance];
+  if (!coef_x || (I.d.dim == 2 && I.d.coef_mode == PR_COEF_FACES && !coef_y))
+    return fail(PR_EINVAL, "NULL coefficient pointer");
+  return factorize_instance(p, I, coef_x, coef_y, as_stream(hip_stream));
+}
+
+pr_status pr_fine_propagate(pr_problem p, const double* U_in, double* F_out, void* hip_stream) {
+  if (!p || !U_in || !F_out) return fail(PR_EINVAL, "NULL argument");
+  if (U_in == F_out) return fail(PR_EINVAL, "U_in and F_out must not overlap");
+  return fine_all(p, U_in, false, F_out, as_stream(hip_stream));
+}
+
+pr_status pr_coarse_sweep(pr_problem p, const double* F, double* G_old, double* U, double* inc_dev,
+                          void* hip_stream) {
+  if (!p || !G_old || !U) return fail(PR_EINVAL, "NULL argument");
+  hipStream_t s = as_stream(hip_stream);
+  return coarse_sweep_impl(p, F, G_old, U, reinterpret_cast<unsigned long long*>(inc_dev), s,
+                           nullptr);
+}
+
+pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_max, double tol,
+                              int* k_done, double* inc, void* hip_stream) {
+  if (!p || !u0 || !U || !k_done || !inc) return fail(PR_EINVAL, "NULL argument");
+  if (k_max < 0) return fail(PR_EINVAL, "k_max must be >= 0");
+  if (!(tol >= 0)) return fail(PR_EINVAL, "tol must be >= 0");
+  hipStream_t s = as_stream(hip_stream);
+  const int n = (int)p->inst.size();
+  for (int i = 0; i < n; i++) {
+    Instance& I = *p->inst[i];
+    HIPOK(launch_copy(u0 + I.off_u0, U + I.off_states, I.npts, s));
+    k_done[i] = 0;
+    inc[i] = 0.0;
+  }
+  pr_status st = coarse_sweep_impl(p, nullptr, p->Gold.p, U, p->d_inc, s, nullptr);
+  if (st != PR_OK) return st;
+  std::vector<char> active(n, 1);
+  int n_active = n;
+  for (int k = 0; k < k_max && n_active > 0; k++) {
+    st = fine_all(p, U, true, p->F.p, s);
+    if (st != PR_OK) return st;
+    st = coarse_sweep_impl(p, p->F.p, p->Gold.p, U, p->d_inc, s, &active);
+    if (st != PR_OK) return st;
+    HIPOK(hipMemcpyAsync(p->h_inc, p->d_inc, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPOK(hipStreamSynchronize(s));
+    for (int i = 0; i < n; i++) {
+      if (!active[i]) continue;
+      double v = p->h_inc[i];
+      k_done[i] = k + 1;
+      inc[i] = v;
+      if (!std::isfinite(v)) return fail(PR_ENUMERIC, "instance %d: non-finite increment", i);
+      if (v < tol) {
+        active[i] = 0;
+        n_active--;
+      }
+    }
+  }
+  return PR_OK;
+}
+
+pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hip_stream) {
+  if (!p || !u0 || !U) return fail(PR_EINVAL, "NULL argument");
+  hipStream_t s = as_stream(hip_stream);
+  const int n = (int)p->inst.size();
+  for (int i = 0; i < n; i++) {
+    Instance& I = *p->inst[i];
+    const DimInst* dI = p->d_inst + n + i;
+    HIPOK(launch_copy(u0 + I.off_u0, U + I.off_states, I.npts, s));
+    auto& g = p->seq_groups[i];
+    for (int k = 0; k < I.d.n_slices; k++) {
+      const double* src = U + I.off_states + (size_t)k * I.npts;
+      double* dst = U + I.off_states + (size_t)(k + 1) * I.npts;
+      HIPOK(launch_to_interleaved(dI, I.hseq, src, s));
+      for (int t = 0; t < I.d.fine_steps; t++)
+        for (int dir = 0; dir < 2; dir++) {
+          if (!g.n_work[dir]) continue;
+          HIPOK(launch_fine_sweep(p->d_inst, g.d_work[dir], g.n_work[dir], 1, p->M, dir,
+                                  dir == 1 || t > 0, t, s));
+        }
+      HIPOK(launch_from_interleaved(dI, I.hseq, dst, s));
+    }
+  }
+  return PR_OK;
+}
+
+pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, double* grad_u0,
+                     double* grad_coef, double* U_ckpt, void* hip_stream) {
+  (void)u0; (void)lambda_T; (void)grad_u0; (void)grad_coef; (void)U_ckpt; (void)hip_stream;
+  if (!p) return fail(PR_EINVAL, "NULL handle");
+  return fail(PR_EUNSUPPORTED, "adjoint not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the
+// parareal-with-splitting library. Not part of the public ABI (include/pr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace prk {
+
+// Device-side description of one dimensional-splitting instance.
+//
+// Fine workspace layout ("interleaved"): the N slices of an instance are
+// grouped in B blocks of L consecutive slices (L a power of two <= 64,
+// padding slices are zero). Block b holds Z[b][j][i][l]: for each grid node
+// the L slice values are contiguous, so a wave whose lanes walk (line, slice)
+// reads and writes whole 8*L-byte segments at every step of a line solve, in
+// both sweep directions, and every lane of a line shares the same
+// factorisation entries.
+//
+// Line systems (I - tau A_dir) are factorised once per tau (LU without
+// pivoting, diagonally dominant M-matrix): with w_f = tau a_f / h^2,
+//   forward   y_p = d_p + e_p y_{p-1}
+//   backward  x_p = r_p y_p + g_p x_{p+1}
+// e_p = w_p / u_{p-1}, r_p = 1 / u_p, g_p = w_{p+1} / u_p, u the LU pivots.
+// The fine sweeps split each line into chunks of M positions and leave the
+// back substitution of every chunk uncoupled (x_{chunk end + 1} taken as 0);
+// the exact result is z_p + phi_p * sigma_k with phi_p = prod_{t=p..end} g_t
+// and sigma_k the true value just past chunk k. The consumer of a sweep's
+// output (the next sweep or the final transpose) adds phi_p * sigma_k when it
+// loads, so each sweep moves every value through HBM exactly once.
+struct DimInst {
+  int nx, ny;        // interior nodes
+  int N;             // slices
+  int L, B;          // lanes per slice block, number of slice blocks
+  int M;             // chunk length of the fine sweeps
+  int Px, Py;        // chunks per x-line (ceil(nx/M)), per y-line (ceil(ny/M))
+  int steps;         // fine steps per slice; grouped sweeps skip instances past it
+  long slab;         // doubles per slice block of Z: ny*nx*L
+  double* Z;         // [B][ny][nx][L]
+  double* sigX;      // [B][ny][Px][L]  chunk carries of the x sweep
+  double* sigY;      // [B][nx][Py][L]  chunk carries of the y sweep
+  // fine factorisations, line-major: x-line j entry (j*nx + i), y-line i entry (i*ny + j)
+  const double* fxE; const double* fxR; const double* fxG;
+  const double* fyE; const double* fyR; const double* fyG;
+  // phi of the fine sweeps, stored where their consumer reads them:
+  //   fxPhiC[i*ny + j]: x-line j, position i (read by y-lines)
+  //   fyPhiC[j*nx + i]: y-line i, position j (read by x-lines and the final transpose)
+  //   fxPhiS[j*Px + k], fyPhiS[i*Py + k]: phi at the first position of chunk k
+  const double* fxPhiC; const double* fyPhiC;
+  const double* fxPhiS; const double* fyPhiS;
+  // coarse factorisations, position-major: x: (i*ny + j), y: (j*nx + i)
+  const double* cxE; const double* cxR; const double* cxG;
+  const double* cyE; const double* cyR; const double* cyG;
+  double* tmp;       // one-state scratch of the coarse sweep
+};
+
+// Work item of a grouped fine-sweep launch: instance, slice block, line group.
+struct WorkItem {
+  int inst, b, group, pad;
+};
+
+// Factorisation of one direction of one instance at one tau.
+struct FactorJob {
+  const double* face;  // face coefficients of this direction
+  int n_lines, n_pos;  // lines and positions per line
+  long face_line_stride, face_pos_stride;  // in doubles
+  double tau_over_h2;  // tau / h^2
+  double react;        // tau * c / M added to the diagonal
+  double* E; double* R; double* G;  // outputs
+  int pos_major;       // 0: [line][pos], 1: [pos][line]
+  int pad;
+};
+
+// ---- launchers (pr_kernels_dim.hip) ----
+hipError_t launch_faces_from_theta_2d(const double* theta, int nx, int ny, double* ax, double* ay,
+                                      hipStream_t s);
+hipError_t launch_faces_from_theta_1d(const double* theta, int nx, double* ax, hipStream_t s);
+hipError_t launch_factorize(const FactorJob& job, hipStream_t s);
+hipError_t launch_chunk_phi(const double* G, int n_lines, int n_pos, int M, double* phiC,
+                            double* phiS, hipStream_t s);
+hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const double* U_in,
+                                 hipStream_t s);
+hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, double* F_out,
+                                   hipStream_t s);
+hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
+                             int M, int dir, int has_prev, int step, hipStream_t s);
+hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
+                           hipStream_t s);
+// Coarse y sweep. mode 0: write the result to dst; mode 1: parareal update
+// (U_next = F + (g - G_old), G_old = g, increment into inc_bits); mode 2:
+// initial guess (U_next = g, G_old = g).
+hipError_t launch_coarse_y(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
+                           int mode, const double* F, double* G_old, double* U_next,
+                           unsigned long long* inc_bits, hipStream_t s);
+hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s);
+hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
+
+}  // namespace prk
