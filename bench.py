@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the parareal-with-splitting hot path on one MI355X.
+
+Workload (default): 2D u_t = div(a grad u), a = 1 + 0.5 sin(2 pi x) cos(2 pi y),
+1023 x 1023 interior nodes, FP64, N = 64 slices, s = 64 fine FIE steps per
+slice, one coarse FIE step, synthetic seeded u0 (16 sine modes).
+
+One timed step = one parareal iteration = the fine propagator on all 64 slices
+(pr_fine_propagate: 64 x 64 FIE steps = 4.29e9 point-updates) plus the serial
+coarse sweep fused with the correction and the increment (pr_coarse_sweep).
+value = fine point-updates per second over the whole step, in Gpts/s.
+
+Also reported: the fine sweep kernel's roofline (algorithmic bytes per launch
+over its mean launch time from hipEvents on the work stream), the oracle timed
+on a bounded sample on the host, and the parareal wall time to tolerance
+against the sequential fine solve on the same GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fine-propagator Gpts/s + % HBM roofline; parareal wall time vs plain loop"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, budget_s):
+    """Oracle (serial FP64 C, one thread) on a bounded sample of the same workload:
+    the fine propagator on one slice for as many fine steps as fit the budget."""
+    import numpy as np
+    import oracle
+    P = oracle.Problem(dim=2, nx=w.nx, ny=w.ny, T=w.T, n_slices=w.n_slices,
+                       fine_steps=w.fine_steps, ax=w.ax, ay=w.ay)
+    dt = w.T / w.n_slices / w.fine_steps
+    u = np.ascontiguousarray(w.u0)
+    t0 = time.perf_counter()
+    u = P.fie_step(u, dt)
+    one = time.perf_counter() - t0
+    steps = max(1, int(budget_s / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u = P.fie_step(u, dt)
+    el = time.perf_counter() - t0
+    pts = w.nx * w.ny * steps
+    return {"value": pts / el / 1e9, "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle FIE steps on one {w.nx}x{w.ny} slice: {steps} fine steps "
+                      f"({pts:.3g} point-updates) in {el:.2f} s",
+            "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1023)
+    ap.add_argument("--slices", type=int, default=64)
+    ap.add_argument("--fine-steps", type=int, default=64)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-parareal", action="store_true",
+                    help="skip the parareal-to-tolerance vs sequential comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        log(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+            "(slices would shard across GPUs with one state handed forward per coarse sweep; "
+            "not built).")
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_2502_08370_amd as pr
+
+    w = W.config2(n=args.n, n_slices=args.slices, fine_steps=args.fine_steps)
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(w, args.cpu_seconds)
+        log(f"  {cpu['sample']}: {cpu['value']:.4f} Gpts/s")
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    N, s, npts = w.n_slices, w.fine_steps, w.nx * w.ny
+    prob = pr.Problem([dict(dim=2, nx=w.nx, ny=w.ny, T=w.T, n_slices=N, fine_steps=s,
+                            ax=w.ax, ay=w.ay)])
+    u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
+    U = prob.new_states()
+    G = prob.new_slices()
+    F = prob.new_slices()
+    inc = torch.zeros(1, dtype=torch.float64, device=dev)
+    U[:npts].copy_(u0)
+    prob.coarse_sweep(None, G, U, inc)  # initial guess
+
+    def step():
+        prob.fine_propagate(U[:N * npts], F)
+        prob.coarse_sweep(F, G, U, inc)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    prob.profile(2)
+    prob.profile(1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_host = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host
+    prob.profile(0)
+    ms_step = e0.elapsed_time(e1) / args.steps
+    phases = prob.profile_read()
+    log(f"step {ms_step:.3f} ms (host {1e3 * t_host / args.steps:.3f} ms); phases: "
+        + ", ".join(f"{k} {v[0] / args.steps:.3f} ms/{v[1] // args.steps}" for k, v in phases.items()))
+
+    fine_pts = npts * N * s
+    value = fine_pts / (ms_step * 1e-3) / 1e9
+    sweep_ms, sweep_n = phases["fine_sweep"]
+    sweep_avg_ms = sweep_ms / sweep_n
+    bytes_per_sweep = 16.0 * npts * N  # one substep: read + write one FP64 per point per slice
+    achieved = bytes_per_sweep / (sweep_avg_ms * 1e-3) / 1e9
+    fine_ms = (phases["fine_sweep"][0] + phases.get("fine_transpose", (0, 0))[0]) / args.steps
+    coarse_ms = (phases.get("coarse_x", (0, 0))[0] + phases.get("coarse_y", (0, 0))[0]) / args.steps
+
+    result = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "slices": N, "fine_steps": s,
+                   "coarse_steps": 1, "split": "dimensional", "integrators": "FIE/FIE",
+                   "step": "one parareal iteration: F^s on all slices + serial coarse sweep "
+                           "with correction and increment"},
+        "roofline": {"bound": "hbm", "kernel": "k_fine_sweep", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": bytes_per_sweep,
+                     "mean_launch_ms": round(sweep_avg_ms, 5), "launches": int(sweep_n)},
+        "fine_propagator": {"gpts": round(fine_pts / (fine_ms * 1e-3) / 1e9, 3),
+                            "ms": round(fine_ms, 4)},
+        "coarse_sweep_ms": round(coarse_ms, 4),
+        "cpu_baseline": cpu,
+    }
+
+    if not args.no_parareal:
+        # parareal to tolerance vs the sequential fine solve (the plain loop of fine steps)
+        Ub = prob.new_states()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k, incv = prob.parareal_iterate(u0, Ub, k_max=N, tol=w.tol)
+        torch.cuda.synchronize()
+        t_par = time.perf_counter() - t0
+        Us = prob.new_states()
+        t0 = time.perf_counter()
+        prob.sequential_fine(u0, Us)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        Ub3, Us3 = Ub.view(N + 1, -1), Us.view(N + 1, -1)
+        err = ((Ub3 - Us3).abs().max() / Us3.abs().max()).item()
+        result["parareal"] = {"iterations": k[0], "tol": w.tol, "last_increment": incv[0],
+                              "wall_s": round(t_par, 4), "sequential_fine_wall_s": round(t_seq, 4),
+                              "speedup_vs_sequential": round(t_seq / t_par, 3),
+                              "rel_err_vs_sequential": err}
+        log(f"parareal: {k[0]} iterations, {t_par:.3f} s; sequential fine {t_seq:.3f} s; "
+            f"rel err vs sequential {err:.2e}")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

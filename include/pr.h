@@ -177,6 +177,23 @@ pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hi
 pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, double* grad_u0,
                      double* grad_coef, double* U_ckpt, void* hip_stream);
 
+/* Phase timers. When enabled, the library records a pair of hipEvents on the
+ * work stream around every launch and accumulates their elapsed times per
+ * phase (no extra synchronisation is added while recording). Phases:
+ *   0 fine sweeps (one FIE substep of every line of every slice)
+ *   1 fine layout transposes (slice-interleaved workspace in/out)
+ *   2 coarse x sweeps      3 coarse y sweeps (fused with the parareal update)
+ *   4 other (copies, fills)
+ * pr_profile_control(p, 1) enables, 0 disables, 2 clears the totals.
+ * pr_profile_read waits for the recorded events and returns the totals. */
+#define PR_PROFILE_PHASES 8
+typedef struct {
+  double ms[PR_PROFILE_PHASES];
+  long long count[PR_PROFILE_PHASES];
+} pr_profile;
+pr_status pr_profile_control(pr_problem p, int mode);
+pr_status pr_profile_read(pr_problem p, pr_profile* out);
+
 /* Thread-local message describing the last non-OK status ("" if none). */
 const char* pr_last_error(void);
 

@@ -172,6 +172,17 @@ class Problem:
     def sequential_fine(self, u0, U, stream=None):
         B.check(B.lib().pr_sequential_fine(self._h, _ptr(u0), _ptr(U), _stream(stream)))
 
+    def profile(self, mode):
+        """1: start recording phase timers, 0: stop, 2: clear."""
+        B.check(B.lib().pr_profile_control(self._h, int(mode)))
+
+    def profile_read(self):
+        """{phase: (total ms, launches)} of the recorded phase timers."""
+        out = B.PrProfile()
+        B.check(B.lib().pr_profile_read(self._h, C.byref(out)))
+        return {B.PHASE_NAMES[i]: (out.ms[i], out.count[i]) for i in range(B.PROFILE_PHASES)
+                if out.count[i]}
+
     def adjoint(self, u0, lambda_T, grad_u0, grad_coef, U_ckpt=None, stream=None):
         B.check(B.lib().pr_adjoint(self._h, _ptr(u0), _ptr(lambda_T), _ptr(grad_u0),
                                    _ptr(grad_coef), _ptr(U_ckpt), _stream(stream)))

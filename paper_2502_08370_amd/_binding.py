@@ -41,6 +41,14 @@ class PrInstanceLayout(C.Structure):
                 ("states_offset", C.c_size_t), ("npts", C.c_int), ("n_slices", C.c_int)]
 
 
+PROFILE_PHASES = 8
+PHASE_NAMES = ["fine_sweep", "fine_transpose", "coarse_x", "coarse_y", "other", "p5", "p6", "p7"]
+
+
+class PrProfile(C.Structure):
+    _fields_ = [("ms", C.c_double * PROFILE_PHASES), ("count", C.c_longlong * PROFILE_PHASES)]
+
+
 class PrError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -70,6 +78,8 @@ def lib():
             "pr_parareal_iterate": [vp, vp, vp, i, d, C.POINTER(i), _dp, vp],
             "pr_sequential_fine": [vp, vp, vp, vp],
             "pr_adjoint": [vp, vp, vp, vp, vp, vp, vp],
+            "pr_profile_control": [vp, i],
+            "pr_profile_read": [vp, C.POINTER(PrProfile)],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -91,4 +101,5 @@ def exported_symbols():
     """Names of the pr_* entry points this binding knows (all declared in pr.h)."""
     return ["pr_create_problem", "pr_destroy_problem", "pr_query_layout", "pr_num_instances",
             "pr_set_coefficients", "pr_fine_propagate", "pr_coarse_sweep", "pr_parareal_iterate",
-            "pr_sequential_fine", "pr_adjoint", "pr_last_error"]
+            "pr_sequential_fine", "pr_adjoint", "pr_profile_control", "pr_profile_read",
+            "pr_last_error"]

@@ -63,23 +63,29 @@ struct Instance {
   double dt = 0, tauG = 0;
   size_t off_u0 = 0, off_slices = 0, off_states = 0;
   // dimensional splitting
-  DimInst h{};       // host mirror of the device descriptor (all-slices layout)
-  DimInst hseq{};    // single-slice variant (sequential fine solve)
+  DimInst h{};       // host mirror of the device descriptor
   DBuf ax, ay, theta;
   DBuf fxE, fxR, fxG, fyE, fyR, fyG, fxPhiC, fyPhiC, fxPhiS, fyPhiS;
   DBuf cxE, cxR, cxG, cyE, cyR, cyG;
   DBuf Z, sigX, sigY, tmp;
-  DBuf Zseq, sigXseq, sigYseq;
 };
 
 }  // namespace
 
 struct pr_problem_s {
   std::vector<std::unique_ptr<Instance>> inst;
+  // phase timers (pr_profile_control / pr_profile_read)
+  bool prof = false;
+  struct Rec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> ev_free;
+  std::vector<Rec> recs;
+  pr_profile acc{};
   size_t tot_u0 = 0, tot_slices = 0, tot_states = 0;
-  int M = 32;  // fine-sweep chunk length
-  // device descriptors: [0, n) all-slices variants, [n, 2n) single-slice variants
-  DimInst* d_inst = nullptr;
+  int M = 16;  // fine-sweep chunk length
+  DimInst* d_inst = nullptr;  // device descriptors, one per instance
   // grouped work lists per lane width L (index log2 L) and direction
   struct Group {
     int L = 0;
@@ -87,19 +93,22 @@ struct pr_problem_s {
     int n_work[2] = {0, 0};
   };
   std::vector<Group> groups;
-  std::vector<Group> seq_groups;  // one per instance, L = 1
   // parareal workspace
   DBuf F, Gold;
   unsigned long long* d_inc = nullptr;
   double* h_inc = nullptr;  // pinned
   ~pr_problem_s() {
     if (d_inst) (void)hipFree(d_inst);
-    for (auto* gs : {&groups, &seq_groups})
-      for (auto& g : *gs)
-        for (auto* w : g.d_work)
-          if (w) (void)hipFree(w);
+    for (auto& g : groups)
+      for (auto* w : g.d_work)
+        if (w) (void)hipFree(w);
     if (d_inc) (void)hipFree(d_inc);
     if (h_inc) (void)hipHostFree(h_inc);
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ev_free) (void)hipEventDestroy(e);
   }
 };
 
@@ -127,6 +136,9 @@ pr_status validate(const pr_problem_desc& d, int idx) {
   if (d.split == PR_SPLIT_DIM && d.dim == 1)
     return fail(PR_EUNSUPPORTED, "instance %d: 1D problems use the DD split (one colour, rho = 1)",
                 idx);
+  if (d.split == PR_SPLIT_DIM && (d.nx > kMaxCoarseLine || d.ny > kMaxCoarseLine))
+    return fail(PR_EUNSUPPORTED, "instance %d: dimensional splitting supports nx, ny <= %d", idx,
+                kMaxCoarseLine);
   if (d.split == PR_SPLIT_DD) {
     if (d.dim != 1) return fail(PR_EUNSUPPORTED, "instance %d: DD splitting is 1D only", idx);
     return fail(PR_EUNSUPPORTED, "instance %d: DD splitting not built yet", idx);
@@ -155,7 +167,8 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
     HIPOK(I.cyE.alloc(npts)); HIPOK(I.cyR.alloc(npts)); HIPOK(I.cyG.alloc(npts));
     HIPOK(I.fyPhiC.alloc(npts)); HIPOK(I.fyPhiS.alloc((size_t)nx * Py));
   }
-  const int L = std::min(64, pow2_at_least(N));
+  // lanes per slice block: a power of two in [8, 64] (fewer slices are padded)
+  const int L = std::min(64, std::max(8, pow2_at_least(N)));
   const int B = (N + L - 1) / L;
   DimInst& h = I.h;
   h.nx = nx; h.ny = ny; h.N = N; h.L = L; h.B = B; h.M = M; h.Px = Px; h.Py = Py;
@@ -172,13 +185,6 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   h.cxE = I.cxE.p; h.cxR = I.cxR.p; h.cxG = I.cxG.p;
   h.cyE = I.cyE.p; h.cyR = I.cyR.p; h.cyG = I.cyG.p;
   h.tmp = I.tmp.p;
-  // single-slice variant for the sequential fine solve
-  I.hseq = h;
-  I.hseq.N = 1; I.hseq.L = 1; I.hseq.B = 1; I.hseq.slab = (long)npts;
-  HIPOK(I.Zseq.alloc(npts));
-  HIPOK(I.sigXseq.alloc((size_t)ny * Px));
-  if (d.dim == 2) HIPOK(I.sigYseq.alloc((size_t)nx * Py));
-  I.hseq.Z = I.Zseq.p; I.hseq.sigX = I.sigXseq.p; I.hseq.sigY = I.sigYseq.p;
   return PR_OK;
 }
 
@@ -207,7 +213,7 @@ pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
     jx.face_line_stride = nx + 1; jx.face_pos_stride = 1;
     jx.tau_over_h2 = tau / (hx * hx); jx.react = tau * react;
     jx.E = coarse ? I.cxE.p : I.fxE.p; jx.R = coarse ? I.cxR.p : I.fxR.p;
-    jx.G = coarse ? I.cxG.p : I.fxG.p; jx.pos_major = coarse;
+    jx.G = coarse ? I.cxG.p : I.fxG.p; jx.pos_major = 0;
     HIPOK(launch_factorize(jx, s));
     if (d.dim == 2) {
       FactorJob jy{};
@@ -215,7 +221,7 @@ pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
       jy.face_line_stride = 1; jy.face_pos_stride = nx;
       jy.tau_over_h2 = tau / (hy * hy); jy.react = tau * react;
       jy.E = coarse ? I.cyE.p : I.fyE.p; jy.R = coarse ? I.cyR.p : I.fyR.p;
-      jy.G = coarse ? I.cyG.p : I.fyG.p; jy.pos_major = coarse;
+      jy.G = coarse ? I.cyG.p : I.fyG.p; jy.pos_major = 0;
       HIPOK(launch_factorize(jy, s));
     }
   }
@@ -230,11 +236,11 @@ pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
 // dealt to the 8 XCDs round-robin by id).
 std::vector<WorkItem> build_work(const std::vector<int>& members,
                                  const std::vector<std::unique_ptr<Instance>>& inst, int dir,
-                                 int M, bool seq) {
+                                 int M) {
   const int kXcd = 8;
   std::vector<std::vector<WorkItem>> per(kXcd);
   for (int m : members) {
-    const DimInst& h = seq ? inst[m]->hseq : inst[m]->h;
+    const DimInst& h = inst[m]->h;
     if (dir == 1 && inst[m]->d.dim == 1) continue;
     const int n_lines = dir == 0 ? h.ny : h.nx;
     const int G = 64 / h.L;
@@ -265,6 +271,43 @@ hipError_t upload_work(const std::vector<WorkItem>& w, WorkItem** d, int* n) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+enum { PH_FINE = 0, PH_TRANSPOSE = 1, PH_COARSE_X = 2, PH_COARSE_Y = 3, PH_OTHER = 4 };
+
+hipEvent_t take_event(pr_problem_s* P) {
+  if (!P->ev_free.empty()) {
+    hipEvent_t e = P->ev_free.back();
+    P->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records a start event on construction and a stop event on destruction when
+// profiling is on.
+struct PhaseTimer {
+  pr_problem_s* P;
+  int phase;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  PhaseTimer(pr_problem_s* P_, int ph, hipStream_t s_) : P(P_), phase(ph), s(s_) {
+    if (!P->prof) return;
+    a = take_event(P);
+    if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+  }
+  ~PhaseTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(P);
+    if (!b || hipEventRecord(b, s) != hipSuccess) {
+      P->ev_free.push_back(a);
+      if (b) P->ev_free.push_back(b);
+      return;
+    }
+    P->recs.push_back({phase, a, b});
+  }
+};
+
 // Fine propagation of every slice of every instance: in_base + per-instance
 // offset (slices or states layout) -> out_base + slices offset.
 pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout, double* out_base,
@@ -273,6 +316,7 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
     const double* U = in_base + (in_states_layout ? I.off_states : I.off_slices);
+    PhaseTimer pt(P, PH_TRANSPOSE, s);
     HIPOK(launch_to_interleaved(P->d_inst + i, I.h, U, s));
   }
   // all instances advance step by step; one grouped launch per lane width and direction
@@ -282,6 +326,7 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
     for (auto& g : P->groups) {
       for (int dir = 0; dir < 2; dir++) {
         if (!g.n_work[dir]) continue;
+        PhaseTimer pt(P, PH_FINE, s);
         HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir], g.n_work[dir], g.L, P->M, dir,
                                 dir == 1 || t > 0, t, s));
       }
@@ -289,6 +334,7 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   }
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
+    PhaseTimer pt(P, PH_TRANSPOSE, s);
     HIPOK(launch_from_interleaved(P->d_inst + i, I.h, out_base + I.off_slices, s));
   }
   return PR_OK;
@@ -302,9 +348,14 @@ pr_status coarse_apply(pr_problem_s* P, int i, const double* src, int mode, cons
   const DimInst* dI = P->d_inst + i;
   for (int c = 0; c < I.d.coarse_steps; c++) {
     const double* from = c == 0 ? src : I.tmp.p;
-    HIPOK(launch_coarse_x(dI, I.h, from, I.tmp.p, s));
+    {
+      PhaseTimer pt(P, PH_COARSE_X, s);
+      HIPOK(launch_coarse_x(dI, I.h, from, I.tmp.p, false, s));
+    }
     const bool last = c + 1 == I.d.coarse_steps;
-    HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, I.tmp.p, last ? mode : 0, F, Gold, Unext, inc, s));
+    PhaseTimer pt(P, PH_COARSE_Y, s);
+    HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, I.tmp.p, last ? mode : 0, F, Gold, Unext, inc, false,
+                          s));
   }
   return PR_OK;
 }
@@ -336,6 +387,41 @@ extern "C" {
 
 const char* pr_last_error(void) { return g_err.c_str(); }
 
+pr_status pr_profile_control(pr_problem p, int mode) {
+  if (!p) return fail(PR_EINVAL, "NULL handle");
+  if (mode == 0 || mode == 1) {
+    p->prof = mode == 1;
+  } else if (mode == 2) {
+    pr_profile z{};
+    p->acc = z;
+    HIPOK(hipDeviceSynchronize());
+    for (auto& r : p->recs) {
+      p->ev_free.push_back(r.a);
+      p->ev_free.push_back(r.b);
+    }
+    p->recs.clear();
+  } else {
+    return fail(PR_EINVAL, "mode must be 0, 1 or 2");
+  }
+  return PR_OK;
+}
+
+pr_status pr_profile_read(pr_problem p, pr_profile* out) {
+  if (!p || !out) return fail(PR_EINVAL, "NULL argument");
+  for (auto& r : p->recs) {
+    HIPOK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIPOK(hipEventElapsedTime(&ms, r.a, r.b));
+    p->acc.ms[r.phase] += ms;
+    p->acc.count[r.phase] += 1;
+    p->ev_free.push_back(r.a);
+    p->ev_free.push_back(r.b);
+  }
+  p->recs.clear();
+  *out = p->acc;
+  return PR_OK;
+}
+
 pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void* hip_stream,
                             pr_problem* out) {
   if (!out) return fail(PR_EINVAL, "out is NULL");
@@ -364,11 +450,8 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
   }
   P->tot_u0 = ou; P->tot_slices = osl; P->tot_states = ost;
   // device descriptors
-  std::vector<DimInst> hd(2 * n_instances);
-  for (int i = 0; i < n_instances; i++) {
-    hd[i] = P->inst[i]->h;
-    hd[n_instances + i] = P->inst[i]->hseq;
-  }
+  std::vector<DimInst> hd(n_instances);
+  for (int i = 0; i < n_instances; i++) hd[i] = P->inst[i]->h;
   HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_inst), hd.size() * sizeof(DimInst)));
   HIPOK(hipMemcpy(P->d_inst, hd.data(), hd.size() * sizeof(DimInst), hipMemcpyHostToDevice));
   // grouped work lists by lane width
@@ -380,20 +463,9 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
     pr_problem_s::Group g;
     g.L = L;
     for (int dir = 0; dir < 2; dir++)
-      HIPOK(upload_work(build_work(members, P->inst, dir, P->M, false), &g.d_work[dir],
+      HIPOK(upload_work(build_work(members, P->inst, dir, P->M), &g.d_work[dir],
                         &g.n_work[dir]));
     P->groups.push_back(g);
-  }
-  for (int i = 0; i < n_instances; i++) {
-    pr_problem_s::Group g;
-    g.L = 1;
-    std::vector<WorkItem> w;
-    for (int dir = 0; dir < 2; dir++) {
-      std::vector<WorkItem> wl = build_work({i}, P->inst, dir, P->M, true);
-      for (auto& it : wl) it.inst = n_instances + i;  // single-slice descriptor
-      HIPOK(upload_work(wl, &g.d_work[dir], &g.n_work[dir]));
-    }
-    P->seq_groups.push_back(g);
   }
   // parareal workspace
   HIPOK(P->F.alloc(osl));
@@ -506,20 +578,22 @@ pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hi
   const int n = (int)p->inst.size();
   for (int i = 0; i < n; i++) {
     Instance& I = *p->inst[i];
-    const DimInst* dI = p->d_inst + n + i;
+    const DimInst* dI = p->d_inst + i;
     HIPOK(launch_copy(u0 + I.off_u0, U + I.off_states, I.npts, s));
-    auto& g = p->seq_groups[i];
+    // one state at a time: every fine step is an exact x then y line solve
     for (int k = 0; k < I.d.n_slices; k++) {
       const double* src = U + I.off_states + (size_t)k * I.npts;
       double* dst = U + I.off_states + (size_t)(k + 1) * I.npts;
-      HIPOK(launch_to_interleaved(dI, I.hseq, src, s));
-      for (int t = 0; t < I.d.fine_steps; t++)
-        for (int dir = 0; dir < 2; dir++) {
-          if (!g.n_work[dir]) continue;
-          HIPOK(launch_fine_sweep(p->d_inst, g.d_work[dir], g.n_work[dir], 1, p->M, dir,
-                                  dir == 1 || t > 0, t, s));
+      for (int t = 0; t < I.d.fine_steps; t++) {
+        {
+          PhaseTimer pt(p, PH_COARSE_X, s);
+          HIPOK(launch_coarse_x(dI, I.h, t == 0 ? src : I.tmp.p, I.tmp.p, true, s));
         }
-      HIPOK(launch_from_interleaved(dI, I.hseq, dst, s));
+        PhaseTimer pt(p, PH_COARSE_Y, s);
+        const bool last = t + 1 == I.d.fine_steps;
+        HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, last ? dst : I.tmp.p, 0, nullptr, nullptr, nullptr,
+                              nullptr, true, s));
+      }
     }
   }
   return PR_OK;

@@ -39,8 +39,8 @@ struct DimInst {
   int steps;         // fine steps per slice; grouped sweeps skip instances past it
   long slab;         // doubles per slice block of Z: ny*nx*L
   double* Z;         // [B][ny][nx][L]
-  double* sigX;      // [B][ny][Px][L]  chunk carries of the x sweep
-  double* sigY;      // [B][nx][Py][L]  chunk carries of the y sweep
+  double* sigX;      // [B][Px][ny][L]  chunk carries of the x sweep
+  double* sigY;      // [B][Py][nx][L]  chunk carries of the y sweep
   // fine factorisations, line-major: x-line j entry (j*nx + i), y-line i entry (i*ny + j)
   const double* fxE; const double* fxR; const double* fxG;
   const double* fyE; const double* fyR; const double* fyG;
@@ -50,7 +50,7 @@ struct DimInst {
   //   fxPhiS[j*Px + k], fyPhiS[i*Py + k]: phi at the first position of chunk k
   const double* fxPhiC; const double* fyPhiC;
   const double* fxPhiS; const double* fyPhiS;
-  // coarse factorisations, position-major: x: (i*ny + j), y: (j*nx + i)
+  // coarse factorisations, line-major like the fine ones
   const double* cxE; const double* cxR; const double* cxG;
   const double* cyE; const double* cyR; const double* cyG;
   double* tmp;       // one-state scratch of the coarse sweep
@@ -86,14 +86,18 @@ hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, doub
                                    hipStream_t s);
 hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
                              int M, int dir, int has_prev, int step, hipStream_t s);
+// Exact line solves of one state, one wave per line (lines <= kMaxCoarseLine).
+// fine = false uses the coarse factorisation, fine = true the fine one.
 hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
-                           hipStream_t s);
+                           bool fine, hipStream_t s);
+// Largest grid extent the coarse sweeps handle (whole line per wave, 64-point chunks).
+constexpr int kMaxCoarseLine = 1024;
 // Coarse y sweep. mode 0: write the result to dst; mode 1: parareal update
 // (U_next = F + (g - G_old), G_old = g, increment into inc_bits); mode 2:
 // initial guess (U_next = g, G_old = g).
 hipError_t launch_coarse_y(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
                            int mode, const double* F, double* G_old, double* U_next,
-                           unsigned long long* inc_bits, hipStream_t s);
+                           unsigned long long* inc_bits, bool fine, hipStream_t s);
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
 

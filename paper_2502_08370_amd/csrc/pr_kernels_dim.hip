@@ -8,13 +8,19 @@
 // by every slice and every step.
 #include "pr_internal.h"
 
-#include <cfloat>
-
 namespace prk {
 
 namespace {
 
 constexpr int kWave = 64;
+
+#define GLOBAL __attribute__((address_space(1)))
+typedef GLOBAL double gdouble;
+
+// Pointers read from descriptor tables are generic; these casts let the
+// compiler emit global (not flat) memory instructions for them.
+__device__ __forceinline__ gdouble* gp(double* p) { return (gdouble*)p; }
+__device__ __forceinline__ const gdouble* gp(const double* p) { return (const gdouble*)p; }
 
 __device__ __forceinline__ unsigned long long abs_bits(double v) {
   return static_cast<unsigned long long>(__double_as_longlong(fabs(v)));
@@ -26,6 +32,40 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     v = o > v ? o : v;
   }
   return v;
+}
+
+// Value of v held by lane `src` (wave-uniform result).
+__device__ __forceinline__ double lane_value(double v, int src) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Inclusive scan over the 64 lanes, in lane order, of the affine maps
+// y -> a*y + b: lane i ends with the composition f_i o ... o f_0.
+__device__ __forceinline__ void affine_scan_up(double& a, double& b, int lane) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    double ap = __shfl_up(a, off, kWave);
+    double bp = __shfl_up(b, off, kWave);
+    if (lane >= off) {
+      b = fma(a, bp, b);
+      a = a * ap;
+    }
+  }
+}
+
+// Same in reverse lane order: lane i ends with f_i o f_{i+1} o ... o f_63.
+__device__ __forceinline__ void affine_scan_down(double& a, double& b, int lane) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    double an = __shfl_down(a, off, kWave);
+    double bn = __shfl_down(b, off, kWave);
+    if (lane + off < kWave) {
+      b = fma(a, bn, b);
+      a = a * an;
+    }
+  }
 }
 
 // ---------------------------------------------------------------- setup ---
@@ -114,7 +154,7 @@ __global__ __launch_bounds__(kWave) void k_to_interleaved(const DimInst* __restr
     tile[s][lane] = (slice < I.N && i < nx) ? U[slice * npts + (long)j * nx + i] : 0.0;
   }
   __syncthreads();
-  double* Zb = I.Z + b * I.slab + ((long)j * nx + i0) * L;
+  gdouble* Zb = gp(I.Z) + b * I.slab + ((long)j * nx + i0) * L;
   const int cnt = min(64, nx - i0);
   for (int q = lane; q < cnt * L; q += kWave) {
     int t = q / L, s = q - t * L;
@@ -131,16 +171,15 @@ __global__ __launch_bounds__(kWave) void k_from_interleaved(const DimInst* __res
   const int i0 = blockIdx.x * 64, j = blockIdx.y, b = blockIdx.z;
   const int L = I.L, nx = I.nx, M = I.M, Py = I.Py;
   const long npts = (long)nx * I.ny;
-  const double* Zb = I.Z + b * I.slab + ((long)j * nx + i0) * L;
-  const double* sig = I.sigY + (long)b * nx * Py * L;
-  const int cnt = min(64, nx - i0);
+  const gdouble* Zb = gp(I.Z) + b * I.slab + ((long)j * nx + i0) * L;
   const int kj = j / M;
+  const gdouble* sig = gp(I.sigY) + ((long)b * Py + kj) * nx * L;
+  const gdouble* phiC = gp(I.fyPhiC) + (long)j * nx;
+  const int cnt = min(64, nx - i0);
   for (int q = lane; q < cnt * L; q += kWave) {
     int t = q / L, s = q - t * L;
     int i = i0 + t;
-    double phi = I.fyPhiC[(long)j * nx + i];
-    double sg = sig[((long)i * Py + kj) * L + s];
-    tile[s][t] = fma(phi, sg, Zb[q]);
+    tile[s][t] = fma(phiC[i], sig[(long)i * L + s], Zb[q]);
   }
   __syncthreads();
   for (int s = 0; s < L; s++) {
@@ -151,18 +190,24 @@ __global__ __launch_bounds__(kWave) void k_from_interleaved(const DimInst* __res
 
 // -------------------------------------------------------- fine sweeps ---
 
-// One substep of the fine FIE step for every line of direction `dir` of every
+// One substep of the fine FIE step for every line of direction DIR of every
 // slice of the work items' instances. Lanes = (line in group, slice); each
-// wave walks its lines position by position in chunks of M, keeping the
-// chunk in registers. If has_prev, the pending chunk correction of the
-// previous (other-direction) sweep is added to every value on load.
-template <int L, int M>
+// wave walks its lines in chunks of M positions, holding one chunk in
+// registers while the next one is being loaded. With HP, the pending chunk
+// correction of the previous (other-direction) sweep is added on load.
+// A partial last chunk is computed in full on clamped loads: the line's last
+// back-substitution factor is 0, so the padded positions cannot leak into the
+// real ones, and only real positions are stored.
+template <int L, int M, int DIR, bool HP>
 __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict__ insts,
-                                                      const WorkItem* __restrict__ work, int dir,
-                                                      int has_prev, int step) {
-  constexpr int G = kWave / L;            // lines per wave
-  constexpr int NQ = (G * M + kWave - 1) / kWave;
-  __shared__ double sE[G][M + 1], sR[G][M + 1], sG[G][M + 1], sP[G][M + 1];
+                                                      const WorkItem* __restrict__ work,
+                                                      int step) {
+  constexpr int G = kWave / L;  // lines per wave
+  constexpr bool kUni = (L == kWave);
+  constexpr int NQ = kUni ? 1 : (G * M + kWave - 1) / kWave;
+  static_assert(M <= kWave, "chunk longer than a wave");
+  // factor staging when a wave holds several lines: [4][G][M+1]
+  __shared__ double sF[kUni ? 1 : 4][kUni ? 1 : G][M + 1];
 
   const WorkItem w = work[blockIdx.x];
   const DimInst& I = insts[w.inst];
@@ -171,287 +216,293 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   const int gsub = lane / L;
   const int sl = lane - gsub * L;
 
-  int n_lines, n_pos, P, Pprev;
-  long lstr, pstr;
-  const double *E, *R, *Gf, *phiPrev, *phiS, *sigPrev;
-  double* sigOut;
-  if (dir == 0) {
-    n_lines = I.ny; n_pos = I.nx; P = I.Px; Pprev = I.Py;
-    lstr = (long)I.nx * L; pstr = L;
-    E = I.fxE; R = I.fxR; Gf = I.fxG; phiS = I.fxPhiS;
-    phiPrev = I.fyPhiC;
-    sigPrev = I.sigY + (long)w.b * I.nx * I.Py * L;
-    sigOut = I.sigX + (long)w.b * I.ny * I.Px * L;
-  } else {
-    n_lines = I.nx; n_pos = I.ny; P = I.Py; Pprev = I.Px;
-    lstr = L; pstr = (long)I.nx * L;
-    E = I.fyE; R = I.fyR; Gf = I.fyG; phiS = I.fyPhiS;
-    phiPrev = I.fxPhiC;
-    sigPrev = I.sigX + (long)w.b * I.ny * I.Px * L;
-    sigOut = I.sigY + (long)w.b * I.nx * I.Py * L;
-  }
+  const int n_lines = DIR == 0 ? I.ny : I.nx;
+  const int n_pos = DIR == 0 ? I.nx : I.ny;
+  const int P = DIR == 0 ? I.Px : I.Py;
+  const int nl_prev = n_pos;  // lines of the previous sweep = our positions
+  const long pstr = DIR == 0 ? (long)L : (long)I.nx * L;
+  const long lstr = DIR == 0 ? (long)I.nx * L : (long)L;
+  const gdouble* E = gp(DIR == 0 ? I.fxE : I.fyE);
+  const gdouble* R = gp(DIR == 0 ? I.fxR : I.fyR);
+  const gdouble* Gf = gp(DIR == 0 ? I.fxG : I.fyG);
+  const gdouble* phiS = gp(DIR == 0 ? I.fxPhiS : I.fyPhiS);
+  const gdouble* phiPrev = gp(DIR == 0 ? I.fyPhiC : I.fxPhiC);
+  const gdouble* sigPrev = DIR == 0 ? gp(I.sigY) + (long)w.b * I.Py * I.nx * L
+                                    : gp(I.sigX) + (long)w.b * I.Px * I.ny * L;
+  gdouble* sigOut = DIR == 0 ? gp(I.sigX) + (long)w.b * I.Px * I.ny * L
+                             : gp(I.sigY) + (long)w.b * I.Py * I.nx * L;
+
   const int line0 = w.group * G;
   const int line = line0 + gsub;
   const bool active = line < n_lines;
-  const int lc = active ? line : n_lines - 1;   // clamped for in-bounds loads
-  const int kprev = lc / M;
-  double* zbase = I.Z + w.b * I.slab + (long)lc * lstr + sl;
+  const int lc = active ? line : n_lines - 1;  // clamped for in-bounds loads
+  // row of the previous sweep's carries for the chunk that holds this line
+  const gdouble* sgRow = sigPrev + ((long)(lc / M) * nl_prev) * L + sl;
+  gdouble* zbase = gp(I.Z) + w.b * I.slab + (long)lc * lstr + sl;
+  const long frow = (long)line0 * n_pos;  // line-uniform factor row when kUni
 
-  double ycarry = 0.0;
-  for (int k = 0; k < P; k++) {
+  auto issue = [&](double (&v)[M], double (&sg)[M], double (&f)[4][NQ], int k) {
     const int p0 = k * M;
     const int cnt = min(M, n_pos - p0);
-    // stage this chunk's factors (shared by the L lanes of each line) in LDS
+    const gdouble* zc = zbase + (long)p0 * pstr;
+    const gdouble* sc = sgRow + (long)p0 * L;
+    if (cnt == M) {
 #pragma unroll
-    for (int qq = 0; qq < NQ; qq++) {
-      int q = lane + qq * kWave;
-      if (q < G * M) {
-        int g = q / M, t = q - g * M;
-        int ln = line0 + g, p = p0 + t;
-        bool ok = ln < n_lines && p < n_pos;
-        long idx = (long)(ok ? ln : 0) * n_pos + (ok ? p : 0);
-        sE[g][t] = ok ? E[idx] : 0.0;
-        sR[g][t] = ok ? R[idx] : 0.0;
-        sG[g][t] = ok ? Gf[idx] : 0.0;
-        sP[g][t] = (ok && has_prev) ? phiPrev[idx] : 0.0;
+      for (int t = 0; t < M; t++) v[t] = zc[t * pstr];
+      if constexpr (HP) {
+#pragma unroll
+        for (int t = 0; t < M; t++) sg[t] = sc[t * L];
       }
-    }
-    double v[M];
-#pragma unroll
-    for (int t = 0; t < M; t++) {
-      int p = p0 + (t < cnt ? t : 0);
-      v[t] = zbase[(long)p * pstr];
-    }
-    double sg[M];
-    if (has_prev) {
+    } else {
 #pragma unroll
       for (int t = 0; t < M; t++) {
-        int p = p0 + (t < cnt ? t : 0);
-        sg[t] = sigPrev[((long)p * Pprev + kprev) * L + sl];
+        const int tt = t < cnt ? t : 0;
+        v[t] = zc[tt * pstr];
+        if constexpr (HP) sg[t] = sc[tt * L];
       }
     }
-    __syncthreads();
-    // forward elimination (carried across chunks)
+    if constexpr (kUni) {
+      const long idx = frow + p0 + (lane < cnt ? lane : 0);
+      f[0][0] = E[idx];
+      f[1][0] = R[idx];
+      f[2][0] = Gf[idx];
+      if constexpr (HP) f[3][0] = phiPrev[idx];
+    } else {
+#pragma unroll
+      for (int qq = 0; qq < NQ; qq++) {
+        const int q = lane + qq * kWave;
+        const int g = q / M, t = q - g * M;
+        const int ln = line0 + g, p = p0 + t;
+        const bool ok = q < G * M && ln < n_lines && p < n_pos;
+        const long idx = ok ? (long)ln * n_pos + p : 0;
+        f[0][qq] = E[idx];
+        f[1][qq] = R[idx];
+        f[2][qq] = Gf[idx];
+        if constexpr (HP) f[3][qq] = phiPrev[idx];
+      }
+    }
+  };
+
+  double ycarry = 0.0;
+  auto process = [&](double (&v)[M], double (&sg)[M], double (&f)[4][NQ], int k) {
+    const int p0 = k * M;
+    const int cnt = min(M, n_pos - p0);
+    if constexpr (!kUni) {
+#pragma unroll
+      for (int qq = 0; qq < NQ; qq++) {
+        const int q = lane + qq * kWave;
+        if (q < G * M) {
+          const int g = q / M, t = q - g * M;
+#pragma unroll
+          for (int c = 0; c < (HP ? 4 : 3); c++) sF[c][g][t] = f[c][qq];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    auto fac = [&](int c, int t) -> double {
+      if constexpr (kUni)
+        return lane_value(f[c][0], t);
+      else
+        return sF[c][gsub][t];
+    };
     double y = ycarry;
 #pragma unroll
     for (int t = 0; t < M; t++) {
-      if (t < cnt) {
-        double d = has_prev ? fma(sP[gsub][t], sg[t], v[t]) : v[t];
-        y = fma(sE[gsub][t], y, d);
-        v[t] = y;
-      }
+      double d = v[t];
+      if constexpr (HP) d = fma(fac(3, t), sg[t], d);
+      y = fma(fac(0, t), y, d);
+      v[t] = y;
     }
     ycarry = y;
-    // back substitution inside the chunk with a zero carry past its end
     double z = 0.0;
 #pragma unroll
     for (int t = M - 1; t >= 0; t--) {
-      if (t < cnt) {
-        z = fma(sG[gsub][t], z, sR[gsub][t] * v[t]);
-        v[t] = z;
-      }
+      z = fma(fac(2, t), z, fac(1, t) * v[t]);
+      v[t] = z;
     }
     if (active) {
+      gdouble* zc = zbase + (long)p0 * pstr;
+      if (cnt == M) {
 #pragma unroll
-      for (int t = 0; t < M; t++)
-        if (t < cnt) zbase[(long)(p0 + t) * pstr] = v[t];
-      sigOut[((long)line * P + k) * L + sl] = v[0];  // first value, resolved below
+        for (int t = 0; t < M; t++) zc[t * pstr] = v[t];
+      } else {
+#pragma unroll
+        for (int t = 0; t < M; t++)
+          if (t < cnt) zc[t * pstr] = v[t];
+      }
+      // first value of the chunk: resolved into the chunk's carry below
+      sigOut[((long)k * n_lines + line) * L + sl] = v[0];
     }
-    __syncthreads();
+    if constexpr (!kUni) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  };
+
+  double vA[M], sA[M], vB[M], sB[M];
+  double fA[4][NQ], fB[4][NQ];
+  issue(vA, sA, fA, 0);
+  for (int k = 0; k < P; k += 2) {
+    if (k + 1 < P) issue(vB, sB, fB, k + 1);
+    process(vA, sA, fA, k);
+    if (k + 1 < P) {
+      if (k + 2 < P) issue(vA, sA, fA, k + 2);
+      process(vB, sB, fB, k + 1);
+    }
   }
-  // carries: sigma_{P-1} = 0, sigma_k = zfirst_{k+1} + phi_{k+1 start} sigma_{k+1}
+  // chunk carries: sigma_{P-1} = 0, sigma_k = zfirst_{k+1} + phi_{(k+1) start} sigma_{k+1}
   if (active) {
-    double* so = sigOut + (long)line * P * L + sl;
+    gdouble* so = sigOut + (long)line * L + sl;
+    const long kstr = (long)n_lines * L;
+    const gdouble* ps = phiS + (long)line * P;
     double sigma = 0.0;
-    double zf_next = so[(long)(P - 1) * L];
-    so[(long)(P - 1) * L] = 0.0;
-    for (int k = P - 2; k >= 0; k--) {
-      sigma = fma(phiS[(long)line * P + k + 1], sigma, zf_next);
-      zf_next = so[(long)k * L];
-      so[(long)k * L] = sigma;
+    double zf_next = so[(long)(P - 1) * kstr];
+    so[(long)(P - 1) * kstr] = 0.0;
+    constexpr int kB = 8;
+    for (int k0 = P - 2; k0 >= 0; k0 -= kB) {
+      double zf[kB], ph[kB];
+#pragma unroll
+      for (int u = 0; u < kB; u++) {
+        const int k = k0 - u;
+        zf[u] = k >= 0 ? so[(long)k * kstr] : 0.0;
+        ph[u] = k >= 0 ? ps[k + 1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kB; u++) {
+        const int k = k0 - u;
+        if (k >= 0) {
+          sigma = fma(ph[u], sigma, zf_next);
+          zf_next = zf[u];
+          so[(long)k * kstr] = sigma;
+        }
+      }
     }
   }
 }
 
 // -------------------------------------------------------- coarse sweeps ---
-// One state (natural layout), lane = line. These solve each line exactly
-// (no deferred correction): the coarse chain is serial in the slices, so the
-// result must be final when the next slice starts.
+// One state (natural layout). Each line is solved exactly by one wave: lane l
+// owns positions 64c + l of the line (c = 0..NC-1), the forward elimination
+// and the back substitution run as affine scans across the lanes (64
+// positions per step) and the line stays in registers between the two.
 
-constexpr int kCT = 32;  // columns per LDS tile of the coarse x sweep
-
-// x-lines (rows): lane = row, the strided direction goes through an LDS
-// transpose so that global loads and stores stay coalesced.
-__global__ __launch_bounds__(kWave) void k_coarse_x(const DimInst* __restrict__ insts,
-                                                    const double* __restrict__ src,
-                                                    double* __restrict__ dst) {
-  __shared__ double T[kWave][kCT + 1];
-  const DimInst& I = insts[0];
-  const int nx = I.nx, ny = I.ny;
-  const int lane = threadIdx.x;
-  const int j0 = blockIdx.x * kWave;
-  const int row = j0 + lane;
-  const bool active = row < ny;
-  const int rc = active ? row : ny - 1;
-  const int ntile = (nx + kCT - 1) / kCT;
-  // forward elimination, tile by tile
-  double y = 0.0;
-  for (int tI = 0; tI < ntile; tI++) {
-    const int i0 = tI * kCT, cnt = min(kCT, nx - i0);
-    for (int q = lane; q < kWave * kCT; q += kWave) {
-      int r = q / kCT, c = q - r * kCT;
-      int rr = j0 + r;
-      if (rr < ny && c < cnt) T[r][c] = src[(long)rr * nx + i0 + c];
-    }
-    double e[kCT];
+template <int NC>
+__device__ __forceinline__ void line_solve_scan(double (&v)[NC], const gdouble* E,
+                                                const gdouble* R, const gdouble* Gf, int n,
+                                                int lane) {
+  double carry = 0.0;
 #pragma unroll
-    for (int t = 0; t < kCT; t++) e[t] = (t < cnt) ? I.cxE[(long)(i0 + t) * ny + rc] : 0.0;
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < kCT; t++) {
-      if (t < cnt) {
-        y = fma(e[t], y, T[lane][t]);
-        T[lane][t] = y;
-      }
-    }
-    __syncthreads();
-    for (int q = lane; q < kWave * kCT; q += kWave) {
-      int r = q / kCT, c = q - r * kCT;
-      int rr = j0 + r;
-      if (rr < ny && c < cnt) dst[(long)rr * nx + i0 + c] = T[r][c];
-    }
-    __syncthreads();
+  for (int c = 0; c < NC; c++) {
+    const int p = c * kWave + lane;
+    const bool ok = p < n;
+    double a = ok ? E[p] : 1.0, b = ok ? v[c] : 0.0;
+    affine_scan_up(a, b, lane);
+    v[c] = fma(a, carry, b);
+    carry = lane_value(v[c], kWave - 1);
   }
-  // back substitution, tiles in reverse
-  double x = 0.0;
-  for (int tI = ntile - 1; tI >= 0; tI--) {
-    const int i0 = tI * kCT, cnt = min(kCT, nx - i0);
-    for (int q = lane; q < kWave * kCT; q += kWave) {
-      int r = q / kCT, c = q - r * kCT;
-      int rr = j0 + r;
-      if (rr < ny && c < cnt) T[r][c] = dst[(long)rr * nx + i0 + c];
-    }
-    double rv[kCT], gv[kCT];
+  carry = 0.0;
 #pragma unroll
-    for (int t = 0; t < kCT; t++) {
-      rv[t] = (t < cnt) ? I.cxR[(long)(i0 + t) * ny + rc] : 0.0;
-      gv[t] = (t < cnt) ? I.cxG[(long)(i0 + t) * ny + rc] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = kCT - 1; t >= 0; t--) {
-      if (t < cnt) {
-        x = fma(gv[t], x, rv[t] * T[lane][t]);
-        T[lane][t] = x;
-      }
-    }
-    __syncthreads();
-    for (int q = lane; q < kWave * kCT; q += kWave) {
-      int r = q / kCT, c = q - r * kCT;
-      int rr = j0 + r;
-      if (rr < ny && c < cnt) dst[(long)rr * nx + i0 + c] = T[r][c];
-    }
-    __syncthreads();
+  for (int c = NC - 1; c >= 0; c--) {
+    const int p = c * kWave + lane;
+    const bool ok = p < n;
+    double a = ok ? Gf[p] : 0.0, b = ok ? R[p] * v[c] : 0.0;
+    affine_scan_down(a, b, lane);
+    v[c] = fma(a, carry, b);
+    carry = lane_value(v[c], 0);
   }
 }
 
-constexpr int kRY = 16;  // rows per register batch of the coarse y sweep
+constexpr int kRowsPerBlock = 4;
 
-// y-lines (columns): lane = column, naturally coalesced.
-__global__ __launch_bounds__(kWave) void k_coarse_y(const DimInst* __restrict__ insts,
-                                                    const double* __restrict__ src,
-                                                    double* __restrict__ dst, int mode,
-                                                    const double* __restrict__ F,
-                                                    double* __restrict__ Gold,
-                                                    double* __restrict__ Unext,
-                                                    unsigned long long* __restrict__ inc_bits) {
+// x-lines (rows), one wave per row: coalesced along the row.
+template <int NC>
+__global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_x(
+    const DimInst* __restrict__ insts, const double* __restrict__ src, double* __restrict__ dst,
+    const double* __restrict__ FE, const double* __restrict__ FR, const double* __restrict__ FG) {
   const DimInst& I = insts[0];
   const int nx = I.nx, ny = I.ny;
-  const int col = blockIdx.x * kWave + threadIdx.x;
-  const bool active = col < nx;
-  const int cc = active ? col : nx - 1;
-  const int nb = (ny + kRY - 1) / kRY;
-  double y = 0.0;
-  for (int bI = 0; bI < nb; bI++) {
-    const int jb = bI * kRY, cnt = min(kRY, ny - jb);
-    double d[kRY], e[kRY];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int row = blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
+  if (row >= ny) return;  // whole wave
+  const long base = (long)row * nx;
+  double v[NC];
 #pragma unroll
-    for (int t = 0; t < kRY; t++) {
-      int j = jb + (t < cnt ? t : 0);
-      d[t] = src[(long)j * nx + cc];
-      e[t] = I.cyE[(long)j * nx + cc];
+  for (int c = 0; c < NC; c++) {
+    int p = c * kWave + lane;
+    v[c] = p < nx ? src[base + p] : 0.0;
+  }
+  line_solve_scan<NC>(v, gp(FE) + base, gp(FR) + base, gp(FG) + base, nx, lane);
+#pragma unroll
+  for (int c = 0; c < NC; c++) {
+    int p = c * kWave + lane;
+    if (p < nx) dst[base + p] = v[c];
+  }
+}
+
+constexpr int kColsPerBlock = 16;
+constexpr int kTS = kColsPerBlock + 1;  // padded LDS row stride
+
+// y-lines (columns): a block of 16 columns is staged in LDS through
+// 128-byte row segments, each wave solves one column, and the result is
+// written back (mode 0), or combined with the parareal correction (mode 1:
+// U_next = F + (g - G_old), G_old = g, increment) or the initial guess
+// (mode 2: U_next = G_old = g).
+template <int NC>
+__global__ __launch_bounds__(kWave* kColsPerBlock) void k_coarse_y(
+    const DimInst* __restrict__ insts, const double* __restrict__ src, double* __restrict__ dst,
+    int mode, const double* __restrict__ F, double* __restrict__ Gold,
+    double* __restrict__ Unext, unsigned long long* __restrict__ inc_bits,
+    const double* __restrict__ FE, const double* __restrict__ FR, const double* __restrict__ FG) {
+  extern __shared__ double T[];  // [ny][kTS]
+  const DimInst& I = insts[0];
+  const int nx = I.nx, ny = I.ny;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wv = tid >> 6;
+  const int i0 = blockIdx.x * kColsPerBlock;
+  const int total = ny * kColsPerBlock;
+  for (int q = tid; q < total; q += kWave * kColsPerBlock) {
+    int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+    int i = i0 + c;
+    T[j * kTS + c] = i < nx ? src[(long)j * nx + i] : 0.0;
+  }
+  __syncthreads();
+  const int col = i0 + wv;
+  if (col < nx) {
+    double v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      int p = c * kWave + lane;
+      v[c] = p < ny ? T[p * kTS + wv] : 0.0;
     }
+    const long lb = (long)col * ny;
+    line_solve_scan<NC>(v, gp(FE) + lb, gp(FR) + lb, gp(FG) + lb, ny, lane);
 #pragma unroll
-    for (int t = 0; t < kRY; t++) {
-      if (t < cnt) {
-        y = fma(e[t], y, d[t]);
-        d[t] = y;
-      }
-    }
-    if (active) {
-#pragma unroll
-      for (int t = 0; t < kRY; t++)
-        if (t < cnt) dst[(long)(jb + t) * nx + cc] = d[t];
+    for (int c = 0; c < NC; c++) {
+      int p = c * kWave + lane;
+      if (p < ny) T[p * kTS + wv] = v[c];
     }
   }
-  double x = 0.0;
+  __syncthreads();
   unsigned long long mx = 0;
-  for (int bI = nb - 1; bI >= 0; bI--) {
-    const int jb = bI * kRY, cnt = min(kRY, ny - jb);
-    double v[kRY], rv[kRY], gv[kRY];
-#pragma unroll
-    for (int t = 0; t < kRY; t++) {
-      int j = jb + (t < cnt ? t : 0);
-      long idx = (long)j * nx + cc;
-      v[t] = dst[idx];
-      rv[t] = I.cyR[idx];
-      gv[t] = I.cyG[idx];
-    }
-#pragma unroll
-    for (int t = kRY - 1; t >= 0; t--) {
-      if (t < cnt) {
-        x = fma(gv[t], x, rv[t] * v[t]);
-        v[t] = x;
-      }
-    }
-    if (!active) continue;
+  for (int q = tid; q < total; q += kWave * kColsPerBlock) {
+    int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+    int i = i0 + c;
+    if (i >= nx) continue;
+    long idx = (long)j * nx + i;
+    double g = T[j * kTS + c];
     if (mode == 0) {
-#pragma unroll
-      for (int t = 0; t < kRY; t++)
-        if (t < cnt) dst[(long)(jb + t) * nx + cc] = v[t];
+      dst[idx] = g;
     } else if (mode == 2) {
-#pragma unroll
-      for (int t = 0; t < kRY; t++)
-        if (t < cnt) {
-          long idx = (long)(jb + t) * nx + cc;
-          Unext[idx] = v[t];
-          Gold[idx] = v[t];
-        }
+      Unext[idx] = g;
+      Gold[idx] = g;
     } else {
-      double f[kRY], go[kRY], uo[kRY];
-#pragma unroll
-      for (int t = 0; t < kRY; t++) {
-        int j = jb + (t < cnt ? t : 0);
-        long idx = (long)j * nx + cc;
-        f[t] = F[idx];
-        go[t] = Gold[idx];
-        uo[t] = Unext[idx];
-      }
-#pragma unroll
-      for (int t = 0; t < kRY; t++)
-        if (t < cnt) {
-          long idx = (long)(jb + t) * nx + cc;
-          double un = f[t] + (v[t] - go[t]);
-          unsigned long long bits = abs_bits(un - uo[t]);
-          mx = bits > mx ? bits : mx;
-          Unext[idx] = un;
-          Gold[idx] = v[t];
-        }
+      double un = F[idx] + (g - Gold[idx]);
+      unsigned long long bits = abs_bits(un - Unext[idx]);
+      mx = bits > mx ? bits : mx;
+      Unext[idx] = un;
+      Gold[idx] = g;
     }
   }
   if (mode == 1) {
     mx = wave_max_u64(mx);
-    if (threadIdx.x == 0 && mx != 0) atomicMax(inc_bits, mx);
+    if (lane == 0 && mx != 0) atomicMax(inc_bits, mx);
   }
 }
 
@@ -465,6 +516,12 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, siz
   size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) b[i] = a[i];
+}
+
+int chunks_pow2(int n) {
+  int c = (n + kWave - 1) / kWave, p = 1;
+  while (p < c) p <<= 1;
+  return p;
 }
 
 }  // namespace
@@ -512,25 +569,32 @@ hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, doub
   return hipGetLastError();
 }
 
-template <int L, int M>
+template <int L, int M, int DIR, bool HP>
 static hipError_t launch_sweep_t(const DimInst* d_insts, const WorkItem* d_work, int n_work,
-                                 int dir, int has_prev, int step, hipStream_t s) {
-  hipLaunchKernelGGL((k_fine_sweep<L, M>), dim3(n_work), dim3(kWave), 0, s, d_insts, d_work, dir,
-                     has_prev, step);
+                                 int step, hipStream_t s) {
+  hipLaunchKernelGGL((k_fine_sweep<L, M, DIR, HP>), dim3(n_work), dim3(kWave), 0, s, d_insts,
+                     d_work, step);
   return hipGetLastError();
+}
+
+template <int L, int M>
+static hipError_t launch_sweep_lm(const DimInst* d_insts, const WorkItem* d_work, int n_work,
+                                  int dir, int has_prev, int step, hipStream_t s) {
+  if (dir == 0)
+    return has_prev ? launch_sweep_t<L, M, 0, true>(d_insts, d_work, n_work, step, s)
+                    : launch_sweep_t<L, M, 0, false>(d_insts, d_work, n_work, step, s);
+  return has_prev ? launch_sweep_t<L, M, 1, true>(d_insts, d_work, n_work, step, s)
+                  : launch_sweep_t<L, M, 1, false>(d_insts, d_work, n_work, step, s);
 }
 
 template <int M>
 static hipError_t launch_sweep_m(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
                                  int dir, int has_prev, int step, hipStream_t s) {
   switch (L) {
-    case 1: return launch_sweep_t<1, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
-    case 2: return launch_sweep_t<2, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
-    case 4: return launch_sweep_t<4, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
-    case 8: return launch_sweep_t<8, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
-    case 16: return launch_sweep_t<16, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
-    case 32: return launch_sweep_t<32, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
-    case 64: return launch_sweep_t<64, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
+    case 8: return launch_sweep_lm<8, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
+    case 16: return launch_sweep_lm<16, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
+    case 32: return launch_sweep_lm<32, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
+    case 64: return launch_sweep_lm<64, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -544,19 +608,58 @@ hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int
   }
 }
 
+template <int NC>
+static hipError_t launch_cx(const DimInst* d_inst, const DimInst& h, const double* src,
+                            double* dst, bool fine, hipStream_t s) {
+  hipLaunchKernelGGL((k_coarse_x<NC>), dim3((h.ny + kRowsPerBlock - 1) / kRowsPerBlock),
+                     dim3(kWave * kRowsPerBlock), 0, s, d_inst, src, dst, fine ? h.fxE : h.cxE,
+                     fine ? h.fxR : h.cxR, fine ? h.fxG : h.cxG);
+  return hipGetLastError();
+}
+
 hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_x, dim3((h.ny + kWave - 1) / kWave), dim3(kWave), 0, s, d_inst, src,
-                     dst);
+                           bool fine, hipStream_t s) {
+  switch (chunks_pow2(h.nx)) {
+    case 1: return launch_cx<1>(d_inst, h, src, dst, fine, s);
+    case 2: return launch_cx<2>(d_inst, h, src, dst, fine, s);
+    case 4: return launch_cx<4>(d_inst, h, src, dst, fine, s);
+    case 8: return launch_cx<8>(d_inst, h, src, dst, fine, s);
+    case 16: return launch_cx<16>(d_inst, h, src, dst, fine, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NC>
+static hipError_t launch_cy(const DimInst* d_inst, const DimInst& h, const double* src,
+                            double* dst, int mode, const double* F, double* G_old,
+                            double* U_next, unsigned long long* inc_bits, bool fine,
+                            hipStream_t s) {
+  size_t lds = (size_t)h.ny * kTS * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_y<NC>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       kMaxCoarseLine * kTS * (int)sizeof(double));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_coarse_y<NC>), dim3((h.nx + kColsPerBlock - 1) / kColsPerBlock),
+                     dim3(kWave * kColsPerBlock), lds, s, d_inst, src, dst, mode, F, G_old, U_next,
+                     inc_bits, fine ? h.fyE : h.cyE, fine ? h.fyR : h.cyR, fine ? h.fyG : h.cyG);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_y(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
                            int mode, const double* F, double* G_old, double* U_next,
-                           unsigned long long* inc_bits, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_y, dim3((h.nx + kWave - 1) / kWave), dim3(kWave), 0, s, d_inst, src,
-                     dst, mode, F, G_old, U_next, inc_bits);
-  return hipGetLastError();
+                           unsigned long long* inc_bits, bool fine, hipStream_t s) {
+  switch (chunks_pow2(h.ny)) {
+    case 1: return launch_cy<1>(d_inst, h, src, dst, mode, F, G_old, U_next, inc_bits, fine, s);
+    case 2: return launch_cy<2>(d_inst, h, src, dst, mode, F, G_old, U_next, inc_bits, fine, s);
+    case 4: return launch_cy<4>(d_inst, h, src, dst, mode, F, G_old, U_next, inc_bits, fine, s);
+    case 8: return launch_cy<8>(d_inst, h, src, dst, mode, F, G_old, U_next, inc_bits, fine, s);
+    case 16: return launch_cy<16>(d_inst, h, src, dst, mode, F, G_old, U_next, inc_bits, fine, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s) {
