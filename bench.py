@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -32,13 +34,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def oracle_problem(w):
+    import oracle
+    if w.theta is not None:
+        ax, ay = oracle.faces_from_theta(w.nx, w.ny, w.theta, dim=w.dim)
+    else:
+        ax, ay = w.ax, w.ay
+    return oracle.Problem(dim=w.dim, nx=w.nx, ny=w.ny, T=w.T, n_slices=w.n_slices,
+                          fine_steps=w.fine_steps, split=w.split, ax=ax, ay=ay, rho=w.rho)
+
+
+def covered_nodes(w):
+    """Nodes each colour's substep solves for (its components: runs of faces with rho > 0,
+    node range [first face - 1, last face]); the other nodes are untouched."""
+    tot = []
+    for r in w.rho:
+        pos = r > 0
+        cover = np.zeros(w.nx, bool)
+        cover |= pos[1:]      # face f+1 > 0 touches node f
+        cover |= pos[:-1]     # face f > 0 touches node f (f < n)
+        tot.append(int(cover.sum()))
+    return tot
+
+
 def cpu_baseline(w, budget_s):
     """Oracle (serial FP64 C, one thread) on a bounded sample of the same workload:
     the fine propagator on one slice for as many fine steps as fit the budget."""
-    import numpy as np
-    import oracle
-    P = oracle.Problem(dim=2, nx=w.nx, ny=w.ny, T=w.T, n_slices=w.n_slices,
-                       fine_steps=w.fine_steps, ax=w.ax, ay=w.ay)
+    P = oracle_problem(w)
     dt = w.T / w.n_slices / w.fine_steps
     u = np.ascontiguousarray(w.u0)
     t0 = time.perf_counter()
@@ -50,8 +72,9 @@ def cpu_baseline(w, budget_s):
         u = P.fie_step(u, dt)
     el = time.perf_counter() - t0
     pts = w.nx * w.ny * steps
+    shape = f"{w.nx}x{w.ny}" if w.dim == 2 else f"{w.nx}-node"
     return {"value": pts / el / 1e9, "unit": "Gpts/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle FIE steps on one {w.nx}x{w.ny} slice: {steps} fine steps "
+            "sample": f"oracle FIE steps on one {shape} slice: {steps} fine steps "
                       f"({pts:.3g} point-updates) in {el:.2f} s",
             "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
 
@@ -69,6 +92,9 @@ def _cpu_model():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["varcoef2d", "dd1d"], default="varcoef2d",
+                    help="varcoef2d: 2D variable coefficient 1023^2, N=64, s=64 (default); "
+                         "dd1d: 1D domain decomposition 2^20 nodes, 8 components, N=32, s=128")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1023)
@@ -89,7 +115,10 @@ def main():
     import workloads as W
     import paper_2502_08370_amd as pr
 
-    w = W.config2(n=args.n, n_slices=args.slices, fine_steps=args.fine_steps)
+    if args.workload == "dd1d":
+        w = W.config3()
+    else:
+        w = W.config2(n=args.n, n_slices=args.slices, fine_steps=args.fine_steps)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -99,8 +128,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     N, s, npts = w.n_slices, w.fine_steps, w.nx * w.ny
-    prob = pr.Problem([dict(dim=2, nx=w.nx, ny=w.ny, T=w.T, n_slices=N, fine_steps=s,
-                            ax=w.ax, ay=w.ay)])
+    inst = dict(dim=w.dim, nx=w.nx, ny=w.ny, T=w.T, n_slices=N, fine_steps=s, split=w.split)
+    if w.theta is not None:
+        inst["theta"] = w.theta
+    else:
+        inst["ax"], inst["ay"] = w.ax, w.ay
+    if w.rho is not None:
+        inst["rho"] = w.rho
+    prob = pr.Problem([inst])
     u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
     U = prob.new_states()
     G = prob.new_slices()
@@ -136,7 +171,11 @@ def main():
     value = fine_pts / (ms_step * 1e-3) / 1e9
     sweep_ms, sweep_n = phases["fine_sweep"]
     sweep_avg_ms = sweep_ms / sweep_n
-    bytes_per_sweep = 16.0 * npts * N  # one substep: read + write one FP64 per point per slice
+    if w.split == "dd":
+        # one colour substep reads and writes each node of that colour's components once
+        bytes_per_sweep = 16.0 * float(np.mean(covered_nodes(w))) * N
+    else:
+        bytes_per_sweep = 16.0 * npts * N  # one substep: read + write one FP64 per point per slice
     achieved = bytes_per_sweep / (sweep_avg_ms * 1e-3) / 1e9
     fine_ms = (phases["fine_sweep"][0] + phases.get("fine_transpose", (0, 0))[0]) / args.steps
     coarse_ms = (phases.get("coarse_x", (0, 0))[0] + phases.get("coarse_y", (0, 0))[0]) / args.steps
@@ -146,11 +185,16 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}", "slices": N, "fine_steps": s,
-                   "coarse_steps": 1, "split": "dimensional", "integrators": "FIE/FIE",
+        "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}" if w.dim == 2 else f"{w.nx}",
+                   "slices": N, "fine_steps": s, "coarse_steps": 1,
+                   "split": "domain decomposition" if w.split == "dd" else "dimensional",
+                   "integrators": "FIE/FIE",
                    "step": "one parareal iteration: F^s on all slices + serial coarse sweep "
                            "with correction and increment"},
-        "roofline": {"bound": "hbm", "kernel": "k_fine_sweep", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm",
+                     "kernel": ("dd substep (k_dd_local + k_dd_carries + k_dd_correct)"
+                                if w.split == "dd" else "k_fine_sweep"),
+                     "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_launch": bytes_per_sweep,
                      "mean_launch_ms": round(sweep_avg_ms, 5), "launches": int(sweep_n)},

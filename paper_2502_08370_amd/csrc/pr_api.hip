@@ -57,17 +57,58 @@ struct DBuf {
   }
 };
 
+// Device array of a trivially copyable type, owned by the library.
+template <class T>
+struct DArr {
+  T* p = nullptr;
+  size_t n = 0;
+  ~DArr() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t upload(const std::vector<T>& v) {
+    n = v.size();
+    if (n == 0) return hipSuccess;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice);
+  }
+};
+
+// Factors of the domain-decomposition substeps at one tau.
+struct DDFactorSet {
+  DBuf E, R, G, CHI, PHI, PSIE, CHIA, PHIA;
+  DDFactors view() const {
+    return DDFactors{E.p, R.p, G.p, CHI.p, PHI.p, PSIE.p, CHIA.p, PHIA.p};
+  }
+};
+
 struct Instance {
   pr_problem_desc d;  // copy (pointer members are not retained)
   int npts = 0;
   double dt = 0, tauG = 0;
   size_t off_u0 = 0, off_slices = 0, off_states = 0;
-  // dimensional splitting
+  bool dd = false;
+  // dimensional splitting (and, for DD, the transpose fields nx, ny, N, L, B, slab, Z)
   DimInst h{};       // host mirror of the device descriptor
   DBuf ax, ay, theta;
   DBuf fxE, fxR, fxG, fyE, fyR, fyG, fxPhiC, fyPhiC, fxPhiS, fyPhiS;
   DBuf cxE, cxR, cxG, cyE, cyR, cyG;
   DBuf Z, sigX, sigY, tmp;
+  // domain decomposition (1D)
+  int n_colors = 0;
+  std::vector<int> seg_off;   // colour k's segments: [seg_off[k], seg_off[k+1])
+  std::vector<int> comp_off;  // colour k's components: [comp_off[k], comp_off[k+1])
+  DBuf rho, W;
+  DArr<DDSeg> segs;
+  DArr<int> seg_colour, comp_lo, comp_hi, comp_colour, comp_first, comp_count;
+  DDFactorSet ffine, fcoarse;
+  DBuf Yb, Za, Yin, Xin;      // fine (interleaved) carries
+  DBuf Yb1, Za1, Yin1, Xin1;  // single-state carries
+  DDInst hdd{}, hdd1{};       // interleaved fine workspace / single state (tmp)
+  DDInst* d_dd = nullptr;     // device copies [hdd, hdd1]
+  ~Instance() {
+    if (d_dd) (void)hipFree(d_dd);
+  }
 };
 
 }  // namespace
@@ -141,7 +182,22 @@ pr_status validate(const pr_problem_desc& d, int idx) {
                 kMaxCoarseLine);
   if (d.split == PR_SPLIT_DD) {
     if (d.dim != 1) return fail(PR_EUNSUPPORTED, "instance %d: DD splitting is 1D only", idx);
-    return fail(PR_EUNSUPPORTED, "instance %d: DD splitting not built yet", idx);
+    if (d.c != 0.0) return fail(PR_EUNSUPPORTED, "instance %d: DD splitting needs c = 0", idx);
+    if (d.n_colors < 1 || d.n_colors > 64)
+      return fail(PR_EINVAL, "instance %d: n_colors must be in 1..64", idx);
+    if (!d.rho) return fail(PR_EINVAL, "instance %d: rho is NULL", idx);
+    for (int f = 0; f <= d.nx; f++) {
+      double sum = 0.0;
+      for (int k = 0; k < d.n_colors; k++) {
+        double r = d.rho[(size_t)k * (d.nx + 1) + f];
+        if (!(r >= 0.0 && r <= 1.0))
+          return fail(PR_EINVAL, "instance %d: rho[%d][%d] = %g outside [0, 1]", idx, k, f, r);
+        sum += r;
+      }
+      if (std::fabs(sum - 1.0) > 1e-14)
+        return fail(PR_EINVAL, "instance %d: partition of unity sums to %.17g on face %d", idx,
+                    sum, f);
+    }
   }
   return PR_OK;
 }
@@ -230,6 +286,163 @@ pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
   return PR_OK;
 }
 
+enum { PH_FINE = 0, PH_TRANSPOSE = 1, PH_COARSE_X = 2, PH_COARSE_Y = 3, PH_OTHER = 4 };
+
+hipEvent_t take_event(pr_problem_s* P) {
+  if (!P->ev_free.empty()) {
+    hipEvent_t e = P->ev_free.back();
+    P->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records a start event on construction and a stop event on destruction when
+// profiling is on.
+struct PhaseTimer {
+  pr_problem_s* P;
+  int phase;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  PhaseTimer(pr_problem_s* P_, int ph, hipStream_t s_) : P(P_), phase(ph), s(s_) {
+    if (!P->prof) return;
+    a = take_event(P);
+    if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+  }
+  ~PhaseTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(P);
+    if (!b || hipEventRecord(b, s) != hipSuccess) {
+      P->ev_free.push_back(a);
+      if (b) P->ev_free.push_back(b);
+      return;
+    }
+    P->recs.push_back({phase, a, b});
+  }
+};
+
+// Domain-decomposition instance: components are the maximal runs of faces with
+// rho_k > 0 (node range [first face - 1, last face] clipped to the grid),
+// cut into segments of kDDSeg nodes.
+pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host, hipStream_t s) {
+  (void)P;
+  const pr_problem_desc& d = I.d;
+  const int n = d.nx, N = d.n_slices, K = d.n_colors;
+  I.dd = true;
+  I.n_colors = K;
+  I.npts = n;
+  I.dt = d.T / d.n_slices / d.fine_steps;
+  I.tauG = d.T / d.n_slices / d.coarse_steps;
+  std::vector<int> clo, chi, ccol, cfirst, ccount, scol;
+  std::vector<DDSeg> segs;
+  I.seg_off.assign(1, 0);
+  I.comp_off.assign(1, 0);
+  for (int k = 0; k < K; k++) {
+    const double* rk = rho_host + (size_t)k * (n + 1);
+    int f = 0;
+    while (f <= n) {
+      if (!(rk[f] > 0.0)) {
+        f++;
+        continue;
+      }
+      const int fa = f;
+      while (f <= n && rk[f] > 0.0) f++;
+      const int fb = f - 1;
+      const int lo = std::max(fa - 1, 0), hi = std::min(fb, n - 1);
+      if (lo > hi) continue;
+      const int ci = (int)clo.size();
+      clo.push_back(lo); chi.push_back(hi); ccol.push_back(k);
+      cfirst.push_back((int)segs.size());
+      for (int s0 = lo; s0 <= hi; s0 += kDDSeg) {
+        segs.push_back(DDSeg{s0, std::min(kDDSeg, hi - s0 + 1), ci, s0 == lo ? 1 : 0});
+        scol.push_back(k);
+      }
+      ccount.push_back((int)segs.size() - cfirst.back());
+    }
+    I.seg_off.push_back((int)segs.size());
+    I.comp_off.push_back((int)clo.size());
+  }
+  const int n_segs = (int)segs.size();
+  HIPOK(I.segs.upload(segs));
+  HIPOK(I.seg_colour.upload(scol));
+  HIPOK(I.comp_lo.upload(clo)); HIPOK(I.comp_hi.upload(chi)); HIPOK(I.comp_colour.upload(ccol));
+  HIPOK(I.comp_first.upload(cfirst)); HIPOK(I.comp_count.upload(ccount));
+  HIPOK(I.rho.alloc((size_t)K * (n + 1)));
+  HIPOK(hipMemcpyAsync(I.rho.p, rho_host, I.rho.n * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPOK(I.ax.alloc((size_t)n + 1));
+  HIPOK(I.W.alloc((size_t)K * (n + 1)));
+  for (DDFactorSet* fs : {&I.ffine, &I.fcoarse}) {
+    for (DBuf* b : {&fs->E, &fs->R, &fs->G, &fs->CHI, &fs->PHI}) {
+      HIPOK(b->alloc((size_t)K * n));
+      HIPOK(launch_fill_zero(b->p, b->n, s));
+    }
+    for (DBuf* b : {&fs->PSIE, &fs->CHIA, &fs->PHIA}) HIPOK(b->alloc(std::max(n_segs, 1)));
+  }
+  const int L = std::min(64, std::max(8, pow2_at_least(N)));
+  const int B = (N + L - 1) / L;
+  HIPOK(I.Z.alloc((size_t)B * n * L));
+  HIPOK(I.tmp.alloc(n));
+  for (DBuf* b : {&I.Yb, &I.Za, &I.Yin, &I.Xin}) HIPOK(b->alloc((size_t)B * std::max(n_segs, 1) * L));
+  for (DBuf* b : {&I.Yb1, &I.Za1, &I.Yin1, &I.Xin1}) HIPOK(b->alloc(std::max(n_segs, 1)));
+  DDInst& h = I.hdd;
+  h.n = n; h.N = N; h.L = L; h.B = B; h.n_colors = K; h.n_segs = n_segs;
+  h.slab = (long)n * L; h.Z = I.Z.p; h.segs = I.segs.p;
+  h.Yb = I.Yb.p; h.Za = I.Za.p; h.Yin = I.Yin.p; h.Xin = I.Xin.p;
+  DDInst& h1 = I.hdd1;
+  h1 = h;
+  h1.N = 1; h1.L = 1; h1.B = 1; h1.slab = n; h1.Z = I.tmp.p;
+  h1.Yb = I.Yb1.p; h1.Za = I.Za1.p; h1.Yin = I.Yin1.p; h1.Xin = I.Xin1.p;
+  HIPOK(hipMalloc(reinterpret_cast<void**>(&I.d_dd), 2 * sizeof(DDInst)));
+  DDInst both[2] = {h, h1};
+  HIPOK(hipMemcpy(I.d_dd, both, sizeof(both), hipMemcpyHostToDevice));
+  // transpose view (natural [slice][node] <-> interleaved [b][node][l])
+  DimInst& t = I.h;
+  t.nx = n; t.ny = 1; t.N = N; t.L = L; t.B = B; t.M = 1; t.Px = 1; t.Py = 1;
+  t.steps = d.fine_steps; t.slab = (long)n * L; t.Z = I.Z.p; t.tmp = I.tmp.p;
+  return PR_OK;
+}
+
+pr_status factorize_dd_instance(Instance& I, const double* coef_x, hipStream_t s) {
+  const pr_problem_desc& d = I.d;
+  const int n = d.nx, K = I.n_colors;
+  if (d.coef_mode == PR_COEF_NODAL_LOG)
+    HIPOK(launch_faces_from_theta_1d(coef_x, n, I.ax.p, s));
+  else
+    HIPOK(hipMemcpyAsync(I.ax.p, coef_x, I.ax.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPOK(launch_dd_faces(I.rho.p, I.ax.p, n, K, I.W.p, s));
+  const double h = 1.0 / (n + 1);
+  const int n_comps = I.comp_off.back(), n_segs = I.seg_off.back();
+  for (int coarse = 0; coarse < 2; coarse++) {
+    DDFactorSet& fs = coarse ? I.fcoarse : I.ffine;
+    const double tau = coarse ? I.tauG : I.dt;
+    HIPOK(launch_dd_factorize(I.W.p, n, I.comp_lo.p, I.comp_hi.p, I.comp_colour.p, n_comps,
+                              tau / (h * h), fs.E.p, fs.R.p, fs.G.p, s));
+    HIPOK(launch_dd_segfactors(I.segs.p, I.seg_colour.p, n_segs, n, fs.E.p, fs.R.p, fs.G.p,
+                               fs.CHI.p, fs.PHI.p, fs.PSIE.p, fs.CHIA.p, fs.PHIA.p, s));
+  }
+  return PR_OK;
+}
+
+// One FIE step (eq. FIE_method) of the DD splitting: colours in order, each
+// colour's components solved by segment solves, carry scans and corrections.
+// which = 0: interleaved fine workspace, 1: the single state in tmp.
+pr_status dd_fie_step(pr_problem_s* P, Instance& I, bool coarse, int which, hipStream_t s) {
+  const DDInst* dI = I.d_dd + which;
+  const DDInst& h = which ? I.hdd1 : I.hdd;
+  const DDFactors f = (coarse ? I.fcoarse : I.ffine).view();
+  for (int k = 0; k < I.n_colors; k++) {
+    const int sb = I.seg_off[k], sc = I.seg_off[k + 1] - sb;
+    const int cb = I.comp_off[k], cc = I.comp_off[k + 1] - cb;
+    PhaseTimer pt(P, which ? PH_COARSE_X : PH_FINE, s);
+    HIPOK(launch_dd_local(dI, h, f, k, sb, sc, s));
+    HIPOK(launch_dd_carries(dI, h, f, I.comp_first.p + cb, I.comp_count.p + cb, cc, s));
+    HIPOK(launch_dd_correct(dI, h, f, k, sb, sc, s));
+  }
+  return PR_OK;
+}
+
 // Work list of one direction for the instances in `members` (all-slices
 // variant): items (inst, b, group), ordered so that line groups whose values
 // share the previous sweep's chunk carries run on the same XCD (workgroups are
@@ -271,43 +484,6 @@ hipError_t upload_work(const std::vector<WorkItem>& w, WorkItem** d, int* n) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-enum { PH_FINE = 0, PH_TRANSPOSE = 1, PH_COARSE_X = 2, PH_COARSE_Y = 3, PH_OTHER = 4 };
-
-hipEvent_t take_event(pr_problem_s* P) {
-  if (!P->ev_free.empty()) {
-    hipEvent_t e = P->ev_free.back();
-    P->ev_free.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// Records a start event on construction and a stop event on destruction when
-// profiling is on.
-struct PhaseTimer {
-  pr_problem_s* P;
-  int phase;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  PhaseTimer(pr_problem_s* P_, int ph, hipStream_t s_) : P(P_), phase(ph), s(s_) {
-    if (!P->prof) return;
-    a = take_event(P);
-    if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
-  }
-  ~PhaseTimer() {
-    if (!a) return;
-    hipEvent_t b = take_event(P);
-    if (!b || hipEventRecord(b, s) != hipSuccess) {
-      P->ev_free.push_back(a);
-      if (b) P->ev_free.push_back(b);
-      return;
-    }
-    P->recs.push_back({phase, a, b});
-  }
-};
-
 // Fine propagation of every slice of every instance: in_base + per-instance
 // offset (slices or states layout) -> out_base + slices offset.
 pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout, double* out_base,
@@ -334,8 +510,16 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   }
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
+    if (!I.dd) continue;
+    for (int t = 0; t < I.d.fine_steps; t++) {
+      pr_status st = dd_fie_step(P, I, false, 0, s);
+      if (st != PR_OK) return st;
+    }
+  }
+  for (int i = 0; i < n; i++) {
+    Instance& I = *P->inst[i];
     PhaseTimer pt(P, PH_TRANSPOSE, s);
-    HIPOK(launch_from_interleaved(P->d_inst + i, I.h, out_base + I.off_slices, s));
+    HIPOK(launch_from_interleaved(P->d_inst + i, I.h, out_base + I.off_slices, !I.dd, s));
   }
   return PR_OK;
 }
@@ -346,6 +530,16 @@ pr_status coarse_apply(pr_problem_s* P, int i, const double* src, int mode, cons
                        double* Gold, double* Unext, unsigned long long* inc, hipStream_t s) {
   Instance& I = *P->inst[i];
   const DimInst* dI = P->d_inst + i;
+  if (I.dd) {
+    HIPOK(launch_copy(src, I.tmp.p, I.npts, s));
+    for (int c = 0; c < I.d.coarse_steps; c++) {
+      pr_status st = dd_fie_step(P, I, true, 1, s);
+      if (st != PR_OK) return st;
+    }
+    PhaseTimer pt(P, PH_COARSE_Y, s);
+    HIPOK(launch_update(I.tmp.p, F, Gold, Unext, I.npts, mode, inc, s));
+    return PR_OK;
+  }
   for (int c = 0; c < I.d.coarse_steps; c++) {
     const double* from = c == 0 ? src : I.tmp.p;
     {
@@ -442,9 +636,16 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
     const size_t npts = (size_t)descs[i].nx * descs[i].ny;
     I->off_u0 = ou; I->off_slices = osl; I->off_states = ost;
     ou += npts; osl += npts * descs[i].n_slices; ost += npts * (descs[i].n_slices + 1);
-    pr_status st = setup_dim_instance(P.get(), *I, s);
-    if (st != PR_OK) return st;
-    st = factorize_instance(P.get(), *I, descs[i].coef_x, descs[i].coef_y, s);
+    pr_status st;
+    if (descs[i].split == PR_SPLIT_DD) {
+      st = setup_dd_instance(P.get(), *I, descs[i].rho, s);
+      if (st != PR_OK) return st;
+      st = factorize_dd_instance(*I, descs[i].coef_x, s);
+    } else {
+      st = setup_dim_instance(P.get(), *I, s);
+      if (st != PR_OK) return st;
+      st = factorize_instance(P.get(), *I, descs[i].coef_x, descs[i].coef_y, s);
+    }
     if (st != PR_OK) return st;
     P->inst.push_back(std::move(I));
   }
@@ -458,7 +659,7 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
   for (int L = 1; L <= 64; L <<= 1) {
     std::vector<int> members;
     for (int i = 0; i < n_instances; i++)
-      if (P->inst[i]->h.L == L) members.push_back(i);
+      if (!P->inst[i]->dd && P->inst[i]->h.L == L) members.push_back(i);
     if (members.empty()) continue;
     pr_problem_s::Group g;
     g.L = L;
@@ -516,6 +717,7 @@ pr_status pr_set_coefficients(pr_problem p, int instance, const double* coef_x,
   Instance& I = *p->inst[instance];
   if (!coef_x || (I.d.dim == 2 && I.d.coef_mode == PR_COEF_FACES && !coef_y))
     return fail(PR_EINVAL, "NULL coefficient pointer");
+  if (I.dd) return factorize_dd_instance(I, coef_x, as_stream(hip_stream));
   return factorize_instance(p, I, coef_x, coef_y, as_stream(hip_stream));
 }
 
@@ -580,6 +782,17 @@ pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hi
     Instance& I = *p->inst[i];
     const DimInst* dI = p->d_inst + i;
     HIPOK(launch_copy(u0 + I.off_u0, U + I.off_states, I.npts, s));
+    if (I.dd) {
+      for (int k = 0; k < I.d.n_slices; k++) {
+        HIPOK(launch_copy(U + I.off_states + (size_t)k * I.npts, I.tmp.p, I.npts, s));
+        for (int t = 0; t < I.d.fine_steps; t++) {
+          pr_status st = dd_fie_step(p, I, false, 1, s);
+          if (st != PR_OK) return st;
+        }
+        HIPOK(launch_copy(I.tmp.p, U + I.off_states + (size_t)(k + 1) * I.npts, I.npts, s));
+      }
+      continue;
+    }
     // one state at a time: every fine step is an exact x then y line solve
     for (int k = 0; k < I.d.n_slices; k++) {
       const double* src = U + I.off_states + (size_t)k * I.npts;

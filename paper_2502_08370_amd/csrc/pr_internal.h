@@ -73,6 +73,67 @@ struct FactorJob {
   int pad;
 };
 
+// ---------------------------------------------------------------------------
+// Domain-decomposition splitting in 1D (section 2.1: L_k u = (rho_k a u_x)_x,
+// partition of unity rho_k). The substep of colour k solves (I - tau A_k) on
+// each connected component of colour k (a run of faces with rho_k > 0) and
+// leaves every other node unchanged. Components are long, so each is cut into
+// segments of kDDSeg nodes: phase 1 solves every segment with zero carries in
+// both directions using the component's LU factors, phase 2 resolves the
+// carries across the segments of each component, phase 3 adds them:
+//   x_i = z_i + chi_i Yin + phi_i Xin
+// with Yin the forward-elimination value just before the segment and Xin the
+// solution just after it; chi_i is the back-substituted product of forward
+// multipliers and phi_i the product of back-substitution multipliers.
+constexpr int kDDSeg = 64;
+
+struct DDSeg {
+  int lo, len;    // first node, node count (<= kDDSeg)
+  int comp;       // component index (within the colour's list)
+  int first;      // 1 for the first segment of its component
+};
+
+// One set of factors (one tau) for all colours, indexed [colour][node].
+struct DDFactors {
+  const double* E; const double* R; const double* G;
+  const double* CHI; const double* PHI;
+  const double* PSIE;  // per segment: product of e over the segment
+  const double* CHIA;  // per segment: chi at its first node
+  const double* PHIA;  // per segment: phi at its first node
+};
+
+struct DDInst {
+  int n, N, L, B;       // nodes, slices, lanes per slice block, slice blocks
+  int n_colors, n_segs;  // colours, segments of all colours
+  long slab;            // doubles per slice block of Z: n*L
+  double* Z;            // [B][n][L] (fine) or the state itself (L = 1)
+  const DDSeg* segs;    // [n_segs], colour-major
+  // per (segment, slice): [B][n_segs][L]
+  double* Yb; double* Za; double* Yin; double* Xin;
+};
+
+hipError_t launch_dd_local(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
+                           int seg_begin, int seg_count, hipStream_t s);
+hipError_t launch_dd_carries(const DDInst* d, const DDInst& h, const DDFactors& f,
+                             const int* comp_first, const int* comp_count, int n_comps,
+                             hipStream_t s);
+hipError_t launch_dd_correct(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
+                             int seg_begin, int seg_count, hipStream_t s);
+// Set-up: component LU (one thread per component) and segment factors.
+hipError_t launch_dd_faces(const double* rho, const double* a, int n, int n_colors, double* w,
+                           hipStream_t s);
+hipError_t launch_dd_factorize(const double* w, int n, const int* comp_lo, const int* comp_hi,
+                               const int* comp_colour, int n_comps, double tau_over_h2, double* E,
+                               double* R, double* G, hipStream_t s);
+hipError_t launch_dd_segfactors(const DDSeg* segs, const int* seg_colour, int n_segs, int n,
+                                const double* E, const double* R, const double* G, double* CHI,
+                                double* PHI, double* PSIE, double* CHIA, double* PHIA,
+                                hipStream_t s);
+// Parareal correction over whole states: U_next = F + (g - G_old), G_old = g,
+// increment (mode 1), or U_next = G_old = g (mode 2).
+hipError_t launch_update(const double* g, const double* F, double* G_old, double* U_next,
+                         size_t n, int mode, unsigned long long* inc_bits, hipStream_t s);
+
 // ---- launchers (pr_kernels_dim.hip) ----
 hipError_t launch_faces_from_theta_2d(const double* theta, int nx, int ny, double* ax, double* ay,
                                       hipStream_t s);
@@ -82,8 +143,9 @@ hipError_t launch_chunk_phi(const double* G, int n_lines, int n_pos, int M, doub
                             double* phiS, hipStream_t s);
 hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const double* U_in,
                                  hipStream_t s);
+// with_corr = false: plain transpose (no pending chunk correction).
 hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, double* F_out,
-                                   hipStream_t s);
+                                   bool with_corr, hipStream_t s);
 hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
                              int M, int dir, int has_prev, int step, hipStream_t s);
 // Exact line solves of one state, one wave per line (lines <= kMaxCoarseLine).

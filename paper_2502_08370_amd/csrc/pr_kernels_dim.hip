@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kWave) void k_to_interleaved(const DimInst* __restr
 
 // Z (+ the pending chunk correction of the last y sweep) -> natural F[slice][j][i].
 __global__ __launch_bounds__(kWave) void k_from_interleaved(const DimInst* __restrict__ insts,
-                                                            double* __restrict__ F) {
+                                                            double* __restrict__ F, int with_corr) {
   __shared__ double tile[64][65];
   const DimInst& I = insts[0];
   const int lane = threadIdx.x;
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kWave) void k_from_interleaved(const DimInst* __res
   for (int q = lane; q < cnt * L; q += kWave) {
     int t = q / L, s = q - t * L;
     int i = i0 + t;
-    tile[s][t] = fma(phiC[i], sig[(long)i * L + s], Zb[q]);
+    tile[s][t] = with_corr ? fma(phiC[i], sig[(long)i * L + s], Zb[q]) : Zb[q];
   }
   __syncthreads();
   for (int s = 0; s < L; s++) {
@@ -563,9 +563,9 @@ hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const 
 }
 
 hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, double* F_out,
-                                   hipStream_t s) {
+                                   bool with_corr, hipStream_t s) {
   dim3 grid((h.nx + 63) / 64, h.ny, h.B);
-  hipLaunchKernelGGL(k_from_interleaved, grid, dim3(kWave), 0, s, d_inst, F_out);
+  hipLaunchKernelGGL(k_from_interleaved, grid, dim3(kWave), 0, s, d_inst, F_out, (int)with_corr);
   return hipGetLastError();
 }
 
