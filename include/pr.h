@@ -34,7 +34,9 @@
  * queued on the stream has finished; the library owns its workspace
  * (factorisations, scratch, graphs), allocated in pr_create_problem and
  * released in pr_destroy_problem; no other call allocates device memory
- * except pr_parareal_iterate, which builds its iteration graph on first use.
+ * except pr_parareal_iterate (its iteration graph, on first use) and
+ * pr_adjoint (its recompute workspace of 2s+2 states plus N+1 checkpoints when
+ * U_ckpt is NULL, on first use).
  *
  * Errors: every entry point returns a pr_status. Arguments are validated
  * before any work is queued: on PR_EINVAL / PR_EUNSUPPORTED nothing has been

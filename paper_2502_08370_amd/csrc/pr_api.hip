@@ -106,6 +106,8 @@ struct Instance {
   DBuf Yb1, Za1, Yin1, Xin1;  // single-state carries
   DDInst hdd{}, hdd1{};       // interleaved fine workspace / single state (tmp)
   DDInst* d_dd = nullptr;     // device copies [hdd, hdd1]
+  // adjoint workspace (allocated on the first pr_adjoint call)
+  DBuf adjWV, adjCkpt, adjLam, adjMu, adjGax, adjGay;
   ~Instance() {
     if (d_dd) (void)hipFree(d_dd);
   }
@@ -251,6 +253,9 @@ pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
   const pr_problem_desc& d = I.d;
   const int nx = d.nx, ny = d.ny, M = P->M;
   if (d.coef_mode == PR_COEF_NODAL_LOG) {
+    const size_t nth = (size_t)(nx + 2) * (ny + 2);
+    if (I.theta.n != nth) HIPOK(I.theta.alloc(nth));
+    HIPOK(hipMemcpyAsync(I.theta.p, coef_x, nth * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (d.dim == 2)
       HIPOK(launch_faces_from_theta_2d(coef_x, nx, ny, I.ax.p, I.ay.p, s));
     else
@@ -322,6 +327,10 @@ struct PhaseTimer {
     P->recs.push_back({phase, a, b});
   }
 };
+
+// Sequential fine solve of one dimensional-splitting instance: U[0] = u0,
+// U[n+1] = F^s(U[n]), every fine step an exact x then y line solve.
+pr_status seq_fine_dim(pr_problem_s* P, int i, const double* u0, double* U, hipStream_t s);
 
 // Domain-decomposition instance: components are the maximal runs of faces with
 // rho_k > 0 (node range [first face - 1, last face] clipped to the grid),
@@ -575,6 +584,29 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
   return PR_OK;
 }
 
+pr_status seq_fine_dim(pr_problem_s* p, int i, const double* u0, double* U, hipStream_t s) {
+  {
+    Instance& I = *p->inst[i];
+    const DimInst* dI = p->d_inst + i;
+    if (U != u0) HIPOK(launch_copy(u0, U, I.npts, s));
+    for (int k = 0; k < I.d.n_slices; k++) {
+      const double* src = U + (size_t)k * I.npts;
+      double* dst = U + (size_t)(k + 1) * I.npts;
+      for (int t = 0; t < I.d.fine_steps; t++) {
+        {
+          PhaseTimer pt(p, PH_COARSE_X, s);
+          HIPOK(launch_coarse_x(dI, I.h, t == 0 ? src : I.tmp.p, I.tmp.p, true, s));
+        }
+        PhaseTimer pt(p, PH_COARSE_Y, s);
+        const bool last = t + 1 == I.d.fine_steps;
+        HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, last ? dst : I.tmp.p, 0, nullptr, nullptr, nullptr,
+                              nullptr, true, s));
+      }
+    }
+  }
+  return PR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -793,30 +825,76 @@ pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hi
       }
       continue;
     }
-    // one state at a time: every fine step is an exact x then y line solve
-    for (int k = 0; k < I.d.n_slices; k++) {
-      const double* src = U + I.off_states + (size_t)k * I.npts;
-      double* dst = U + I.off_states + (size_t)(k + 1) * I.npts;
-      for (int t = 0; t < I.d.fine_steps; t++) {
-        {
-          PhaseTimer pt(p, PH_COARSE_X, s);
-          HIPOK(launch_coarse_x(dI, I.h, t == 0 ? src : I.tmp.p, I.tmp.p, true, s));
-        }
-        PhaseTimer pt(p, PH_COARSE_Y, s);
-        const bool last = t + 1 == I.d.fine_steps;
-        HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, last ? dst : I.tmp.p, 0, nullptr, nullptr, nullptr,
-                              nullptr, true, s));
-      }
-    }
+    pr_status st = seq_fine_dim(p, i, u0 + I.off_u0, U + I.off_states, s);
+    if (st != PR_OK) return st;
   }
   return PR_OK;
 }
 
 pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, double* grad_u0,
                      double* grad_coef, double* U_ckpt, void* hip_stream) {
-  (void)u0; (void)lambda_T; (void)grad_u0; (void)grad_coef; (void)U_ckpt; (void)hip_stream;
-  if (!p) return fail(PR_EINVAL, "NULL handle");
-  return fail(PR_EUNSUPPORTED, "adjoint not built yet");
+  if (!p || !u0 || !lambda_T || !grad_u0 || !grad_coef) return fail(PR_EINVAL, "NULL argument");
+  if (p->inst.size() != 1) return fail(PR_EUNSUPPORTED, "pr_adjoint needs a single-instance handle");
+  Instance& I = *p->inst[0];
+  if (I.dd || I.d.dim != 2)
+    return fail(PR_EUNSUPPORTED, "pr_adjoint supports 2D dimensional splitting");
+  hipStream_t s = as_stream(hip_stream);
+  const int nx = I.d.nx, ny = I.d.ny, N = I.d.n_slices, S = I.d.fine_steps;
+  const size_t npts = I.npts;
+  // workspace: post-x and post-y states of one slice's fine steps, checkpoints, lambda, mu
+  if (I.adjWV.n != 2 * (size_t)S * npts) HIPOK(I.adjWV.alloc(2 * (size_t)S * npts));
+  if (!U_ckpt && I.adjCkpt.n != (size_t)(N + 1) * npts) HIPOK(I.adjCkpt.alloc((size_t)(N + 1) * npts));
+  if (I.adjLam.n != npts) HIPOK(I.adjLam.alloc(npts));
+  if (I.adjMu.n != npts) HIPOK(I.adjMu.alloc(npts));
+  if (I.adjGax.n != (size_t)ny * (nx + 1)) HIPOK(I.adjGax.alloc((size_t)ny * (nx + 1)));
+  if (I.adjGay.n != (size_t)(ny + 1) * nx) HIPOK(I.adjGay.alloc((size_t)(ny + 1) * nx));
+  double* ckpt = U_ckpt ? U_ckpt : I.adjCkpt.p;
+  const DimInst* dI = p->d_inst;
+  // forward: checkpoints at the slice boundaries
+  pr_status st = seq_fine_dim(p, 0, u0, ckpt, s);
+  if (st != PR_OK) return st;
+  HIPOK(launch_fill_zero(I.adjGax.p, I.adjGax.n, s));
+  HIPOK(launch_fill_zero(I.adjGay.p, I.adjGay.n, s));
+  HIPOK(launch_copy(lambda_T, I.adjLam.p, npts, s));
+  const double hx = 1.0 / (nx + 1), hy = 1.0 / (ny + 1);
+  const double cx = I.dt / (hx * hx), cy = I.dt / (hy * hy);
+  double* Wst = I.adjWV.p;                       // W_t = state after the x substep of step t
+  double* Vst = I.adjWV.p + (size_t)S * npts;    // V_t = state after the y substep
+  for (int n = N - 1; n >= 0; n--) {
+    // recompute the slice's fine steps from its checkpoint
+    for (int t = 0; t < S; t++) {
+      const double* prev = t == 0 ? ckpt + (size_t)n * npts : Vst + (size_t)(t - 1) * npts;
+      {
+        PhaseTimer pt(p, PH_COARSE_X, s);
+        HIPOK(launch_coarse_x(dI, I.h, prev, Wst + (size_t)t * npts, true, s));
+      }
+      PhaseTimer pt(p, PH_COARSE_Y, s);
+      HIPOK(launch_coarse_y(dI, I.h, Wst + (size_t)t * npts, Vst + (size_t)t * npts, 0, nullptr,
+                            nullptr, nullptr, nullptr, true, s));
+    }
+    // reverse the steps: transposed (= same, symmetric) solves in reverse substep order
+    for (int t = S - 1; t >= 0; t--) {
+      {
+        PhaseTimer pt(p, PH_COARSE_Y, s);
+        HIPOK(launch_coarse_y(dI, I.h, I.adjLam.p, I.adjMu.p, 0, nullptr, nullptr, nullptr,
+                              nullptr, true, s));
+      }
+      HIPOK(launch_face_grad_y(I.adjMu.p, Vst + (size_t)t * npts, nx, ny, cy, I.adjGay.p, s));
+      {
+        PhaseTimer pt(p, PH_COARSE_X, s);
+        HIPOK(launch_coarse_x(dI, I.h, I.adjMu.p, I.adjLam.p, true, s));
+      }
+      HIPOK(launch_face_grad_x(I.adjLam.p, Wst + (size_t)t * npts, nx, ny, cx, I.adjGax.p, s));
+    }
+  }
+  HIPOK(launch_copy(I.adjLam.p, grad_u0, npts, s));
+  if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
+    HIPOK(launch_theta_chain(I.theta.p, I.adjGax.p, I.adjGay.p, nx, ny, grad_coef, s));
+  } else {
+    HIPOK(launch_copy(I.adjGax.p, grad_coef, I.adjGax.n, s));
+    HIPOK(launch_copy(I.adjGay.p, grad_coef + I.adjGax.n, I.adjGay.n, s));
+  }
+  return PR_OK;
 }
 
 }  // extern "C"

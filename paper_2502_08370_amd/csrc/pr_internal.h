@@ -134,6 +134,14 @@ hipError_t launch_dd_segfactors(const DDSeg* segs, const int* seg_colour, int n_
 hipError_t launch_update(const double* g, const double* F, double* G_old, double* U_next,
                          size_t n, int mode, unsigned long long* inc_bits, hipStream_t s);
 
+// ---- adjoint (pr_kernels_adj.hip) ----
+hipError_t launch_face_grad_x(const double* nu, const double* W, int nx, int ny, double coef,
+                              double* gax, hipStream_t s);
+hipError_t launch_face_grad_y(const double* mu, const double* V, int nx, int ny, double coef,
+                              double* gay, hipStream_t s);
+hipError_t launch_theta_chain(const double* theta, const double* gax, const double* gay, int nx,
+                              int ny, double* gth, hipStream_t s);
+
 // ---- launchers (pr_kernels_dim.hip) ----
 hipError_t launch_faces_from_theta_2d(const double* theta, int nx, int ny, double* ax, double* ay,
                                       hipStream_t s);
