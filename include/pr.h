@@ -163,6 +163,24 @@ pr_status pr_coarse_sweep(pr_problem p, const double* F, double* G_old, double* 
 pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_max, double tol,
                               int* k_done, double* inc, void* hip_stream);
 
+/* Tuning options (pr_set_option / pr_get_option):
+ *   PR_OPT_GRAPH       1 (default): pr_parareal_iterate captures one correction
+ *                      as a HIP graph and replays it; 0: direct launches
+ *   PR_OPT_FINE_CHUNK  chunk length of the fine line sweeps: 16 (default), 32
+ *   PR_OPT_LANES       slice lanes per line in the fine sweeps (lines per wave =
+ *                      64 / lanes): 0 = per-instance default (the smallest power
+ *                      of two >= N, in [8, 64]), or a cap of 8, 16, 32, 64
+ * Results do not depend on the options beyond rounding. */
+enum { PR_OPT_GRAPH = 1, PR_OPT_FINE_CHUNK = 2, PR_OPT_LANES = 3 };
+pr_status pr_set_option(pr_problem p, int option, int value);
+pr_status pr_get_option(pr_problem p, int option, int* value);
+
+/* Autotuner: times pr_fine_propagate on the handle's own shapes for every
+ * (lanes, chunk) choice, keeps the fastest and reports it (host pointers,
+ * each may be NULL; best_ms = its time). Overwrites the library's internal
+ * parareal buffers (not the caller's). Synchronous. */
+pr_status pr_autotune(pr_problem p, void* hip_stream, int* lanes, int* chunk, float* best_ms);
+
 /* Sequential fine solution (section 3, "fine approximation"): U[0] = u0,
  * U[n+1] = F^s(U[n]). u0: u0 layout, U: states layout. Asynchronous. */
 pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hip_stream);

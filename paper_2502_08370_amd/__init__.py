@@ -172,6 +172,45 @@ class Problem:
     def sequential_fine(self, u0, U, stream=None):
         B.check(B.lib().pr_sequential_fine(self._h, _ptr(u0), _ptr(U), _stream(stream)))
 
+    def set_option(self, name, value):
+        """name: 'graph' (0/1), 'fine_chunk' (16/32), 'lanes' (0/8/16/32/64)."""
+        opt = {"graph": B.PR_OPT_GRAPH, "fine_chunk": B.PR_OPT_FINE_CHUNK, "lanes": B.PR_OPT_LANES}[name]
+        B.check(B.lib().pr_set_option(self._h, opt, int(value)))
+
+    def get_option(self, name):
+        opt = {"graph": B.PR_OPT_GRAPH, "fine_chunk": B.PR_OPT_FINE_CHUNK, "lanes": B.PR_OPT_LANES}[name]
+        v = C.c_int()
+        B.check(B.lib().pr_get_option(self._h, opt, C.byref(v)))
+        return v.value
+
+    def autotune(self, cache=None, stream=None):
+        """Pick the fastest (lanes, fine_chunk) for this handle's shapes. With a cache
+        path (JSON), reuse a previous choice for the same shapes."""
+        import json
+        import os
+        key = json.dumps(sorted((ins["nx"], ins["ny"], ins["n_slices"]) for ins in self.instances))
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                lanes, chunk = table[key]["lanes"], table[key]["fine_chunk"]
+                self.set_option("lanes", lanes)
+                self.set_option("fine_chunk", chunk)
+                return dict(table[key], cached=True)
+        lanes, chunk, ms = C.c_int(), C.c_int(), C.c_float()
+        B.check(B.lib().pr_autotune(self._h, _stream(stream), C.byref(lanes), C.byref(chunk),
+                                    C.byref(ms)))
+        res = dict(lanes=lanes.value, fine_chunk=chunk.value, fine_ms=ms.value)
+        if cache:
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    table = json.load(f)
+            table[key] = res
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        return dict(res, cached=False)
+
     def profile(self, mode):
         """1: start recording phase timers, 0: stop, 2: clear."""
         B.check(B.lib().pr_profile_control(self._h, int(mode)))

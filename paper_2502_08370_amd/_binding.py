@@ -16,6 +16,7 @@ PR_OK, PR_EINVAL, PR_ENOMEM, PR_EDEVICE, PR_ENUMERIC, PR_EUNSUPPORTED = range(6)
 PR_SPLIT_DIM, PR_SPLIT_DD = 0, 1
 PR_FIE, PR_DR = 0, 1
 PR_COEF_FACES, PR_COEF_NODAL_LOG = 0, 1
+PR_OPT_GRAPH, PR_OPT_FINE_CHUNK, PR_OPT_LANES = 1, 2, 3
 
 STATUS_NAMES = {0: "PR_OK", 1: "PR_EINVAL", 2: "PR_ENOMEM", 3: "PR_EDEVICE", 4: "PR_ENUMERIC",
                 5: "PR_EUNSUPPORTED"}
@@ -80,6 +81,9 @@ def lib():
             "pr_adjoint": [vp, vp, vp, vp, vp, vp, vp],
             "pr_profile_control": [vp, i],
             "pr_profile_read": [vp, C.POINTER(PrProfile)],
+            "pr_set_option": [vp, i, i],
+            "pr_get_option": [vp, i, C.POINTER(i)],
+            "pr_autotune": [vp, vp, C.POINTER(i), C.POINTER(i), C.POINTER(C.c_float)],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -102,4 +106,4 @@ def exported_symbols():
     return ["pr_create_problem", "pr_destroy_problem", "pr_query_layout", "pr_num_instances",
             "pr_set_coefficients", "pr_fine_propagate", "pr_coarse_sweep", "pr_parareal_iterate",
             "pr_sequential_fine", "pr_adjoint", "pr_profile_control", "pr_profile_read",
-            "pr_last_error"]
+            "pr_set_option", "pr_get_option", "pr_autotune", "pr_last_error"]

@@ -66,6 +66,10 @@ struct DArr {
     if (p) (void)hipFree(p);
   }
   hipError_t upload(const std::vector<T>& v) {
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+    }
     n = v.size();
     if (n == 0) return hipSuccess;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T));
@@ -88,6 +92,7 @@ struct Instance {
   double dt = 0, tauG = 0;
   size_t off_u0 = 0, off_slices = 0, off_states = 0;
   bool dd = false;
+  int Ldef = 0;  // default lane width (sizes the interleaved workspace)
   // dimensional splitting (and, for DD, the transpose fields nx, ny, N, L, B, slab, Z)
   DimInst h{};       // host mirror of the device descriptor
   DBuf ax, ay, theta;
@@ -140,7 +145,25 @@ struct pr_problem_s {
   DBuf F, Gold;
   unsigned long long* d_inc = nullptr;
   double* h_inc = nullptr;  // pinned
+  int* d_active = nullptr;  // per-instance flags read by every kernel
+  // batched coarse sweeps: items of slice index n are [xoff[n], xoff[n+1])
+  DArr<LineItem> xitems, yitems;
+  std::vector<int> xoff, yoff;
+  int Nmax = 0, csmax = 0, max_ny = 1;
+  bool any_dd = false;
+  // captured parareal correction
+  bool use_graph = true;
+  hipStream_t gstream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double graph_tol = -1.0;
+  const double* graph_U = nullptr;
+  int lanes_cap = 0;  // 0: each instance uses its default lane width
   ~pr_problem_s() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (gstream) (void)hipStreamDestroy(gstream);
+    if (d_active) (void)hipFree(d_active);
     if (d_inst) (void)hipFree(d_inst);
     for (auto& g : groups)
       for (auto* w : g.d_work)
@@ -228,6 +251,7 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   // lanes per slice block: a power of two in [8, 64] (fewer slices are padded)
   const int L = std::min(64, std::max(8, pow2_at_least(N)));
   const int B = (N + L - 1) / L;
+  I.Ldef = L;
   DimInst& h = I.h;
   h.nx = nx; h.ny = ny; h.N = N; h.L = L; h.B = B; h.M = M; h.Px = Px; h.Py = Py;
   h.steps = d.fine_steps;
@@ -327,6 +351,9 @@ struct PhaseTimer {
     P->recs.push_back({phase, a, b});
   }
 };
+
+pr_status set_all_active(pr_problem_s* P, hipStream_t s);
+pr_status build_schedules(pr_problem_s* P);
 
 // Sequential fine solve of one dimensional-splitting instance: U[0] = u0,
 // U[n+1] = F^s(U[n]), every fine step an exact x then y line solve.
@@ -563,22 +590,40 @@ pr_status coarse_apply(pr_problem_s* P, int i, const double* src, int mode, cons
   return PR_OK;
 }
 
+// Coarse sweep of every instance. Dimensional instances: one batched x and
+// one batched y launch per (slice index, coarse step) over all instances that
+// have that slice and are active on the device. DD instances: per instance,
+// skipped when host_active says so.
 pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, double* U,
                             unsigned long long* inc_bits, hipStream_t s,
-                            const std::vector<char>* active) {
+                            const std::vector<char>* host_active) {
   const int n = (int)P->inst.size();
-  if (inc_bits) HIPOK(launch_fill_zero(reinterpret_cast<double*>(inc_bits), n, s));
+  unsigned long long* inc = inc_bits ? inc_bits : P->d_inc;
+  HIPOK(launch_fill_zero(reinterpret_cast<double*>(inc), n, s));
   for (int i = 0; i < n; i++) {
-    if (active && !(*active)[i]) continue;
     Instance& I = *P->inst[i];
+    if (!I.dd || (host_active && !(*host_active)[i])) continue;
     for (int k = 0; k < I.d.n_slices; k++) {
       const double* Un = U + I.off_states + (size_t)k * I.npts;
       double* Unext = U + I.off_states + (size_t)(k + 1) * I.npts;
       double* Gk = Gold + I.off_slices + (size_t)k * I.npts;
       const double* Fk = F ? F + I.off_slices + (size_t)k * I.npts : nullptr;
-      pr_status st = coarse_apply(P, i, Un, F ? 1 : 2, Fk, Gk, Unext,
-                                  inc_bits ? inc_bits + i : P->d_inc + i, s);
+      pr_status st = coarse_apply(P, i, Un, F ? 1 : 2, Fk, Gk, Unext, inc + i, s);
       if (st != PR_OK) return st;
+    }
+  }
+  for (int k = 0; k < P->Nmax; k++) {
+    const int xb = P->xoff[k], xn = P->xoff[k + 1] - xb;
+    const int yb = P->yoff[k], yn = P->yoff[k + 1] - yb;
+    if (xn == 0 && yn == 0) continue;
+    for (int c = 0; c < P->csmax; c++) {
+      {
+        PhaseTimer pt(P, PH_COARSE_X, s);
+        HIPOK(launch_coarse_xb(P->d_inst, P->xitems.p + xb, xn, k, c, U, s));
+      }
+      PhaseTimer pt(P, PH_COARSE_Y, s);
+      HIPOK(launch_coarse_yb(P->d_inst, P->yitems.p + yb, yn, k, c, F ? 1 : 2, F, Gold, U, inc,
+                             P->max_ny, s));
     }
   }
   return PR_OK;
@@ -605,6 +650,108 @@ pr_status seq_fine_dim(pr_problem_s* p, int i, const double* u0, double* U, hipS
     }
   }
   return PR_OK;
+}
+
+pr_status set_all_active(pr_problem_s* P, hipStream_t s) {
+  std::vector<int> ones(P->inst.size(), 1);
+  HIPOK(hipMemcpyAsync(P->d_active, ones.data(), ones.size() * sizeof(int), hipMemcpyHostToDevice,
+                       s));
+  HIPOK(hipStreamSynchronize(s));
+  return PR_OK;
+}
+
+// Device descriptors, grouped fine-sweep work lists (by lane width) and the
+// per-slice-index item lists of the batched coarse sweeps.
+pr_status build_schedules(pr_problem_s* P) {
+  const int n = (int)P->inst.size();
+  std::vector<DimInst> hd(n);
+  for (int i = 0; i < n; i++) hd[i] = P->inst[i]->h;
+  HIPOK(hipMemcpy(P->d_inst, hd.data(), hd.size() * sizeof(DimInst), hipMemcpyHostToDevice));
+  for (auto& g : P->groups)
+    for (auto*& w : g.d_work)
+      if (w) {
+        (void)hipFree(w);
+        w = nullptr;
+      }
+  P->groups.clear();
+  for (int L = 1; L <= 64; L <<= 1) {
+    std::vector<int> members;
+    for (int i = 0; i < n; i++)
+      if (!P->inst[i]->dd && P->inst[i]->h.L == L) members.push_back(i);
+    if (members.empty()) continue;
+    pr_problem_s::Group g;
+    g.L = L;
+    for (int dir = 0; dir < 2; dir++)
+      HIPOK(upload_work(build_work(members, P->inst, dir, P->M), &g.d_work[dir], &g.n_work[dir]));
+    P->groups.push_back(g);
+  }
+  P->Nmax = 0;
+  P->csmax = 0;
+  P->max_ny = 1;
+  P->any_dd = false;
+  for (auto& I : P->inst) {
+    if (I->dd) {
+      P->any_dd = true;
+      continue;
+    }
+    P->Nmax = std::max(P->Nmax, I->d.n_slices);
+    P->csmax = std::max(P->csmax, I->d.coarse_steps);
+    P->max_ny = std::max(P->max_ny, I->d.ny);
+  }
+  std::vector<LineItem> xi, yi;
+  P->xoff.assign(1, 0);
+  P->yoff.assign(1, 0);
+  for (int k = 0; k < P->Nmax; k++) {
+    for (int i = 0; i < n; i++) {
+      const Instance& I = *P->inst[i];
+      if (I.dd || I.d.n_slices <= k) continue;
+      for (int rb = 0; rb < (I.d.ny + kCoarseRowsPerBlock - 1) / kCoarseRowsPerBlock; rb++)
+        xi.push_back(LineItem{i, rb});
+      for (int cb = 0; cb < (I.d.nx + kCoarseColsPerBlock - 1) / kCoarseColsPerBlock; cb++)
+        yi.push_back(LineItem{i, cb});
+    }
+    P->xoff.push_back((int)xi.size());
+    P->yoff.push_back((int)yi.size());
+  }
+  HIPOK(P->xitems.upload(xi));
+  HIPOK(P->yitems.upload(yi));
+  return PR_OK;
+}
+
+// Lane width (lines per wave = 64 / L) and chunk length of the fine sweeps.
+// lanes_cap = 0 keeps every instance's default L; otherwise L = min(cap, default).
+// Workspaces were sized for the default L and M = 16, which bound every choice.
+pr_status apply_layout(pr_problem_s* P, int lanes_cap, int M) {
+  HIPOK(hipDeviceSynchronize());
+  for (auto& Ip : P->inst) {
+    Instance& I = *Ip;
+    if (I.dd) continue;
+    DimInst& h = I.h;
+    const int nx = I.d.nx, ny = I.d.ny, N = I.d.n_slices;
+    const int L = lanes_cap ? std::min(lanes_cap, I.Ldef) : I.Ldef;
+    h.L = L;
+    h.B = (N + L - 1) / L;
+    h.slab = (long)nx * ny * L;
+    if (M != h.M) {
+      h.M = M;
+      h.Px = (nx + M - 1) / M;
+      h.Py = (ny + M - 1) / M;
+      HIPOK(launch_chunk_phi(I.fxG.p, ny, nx, M, I.fxPhiC.p, I.fxPhiS.p, nullptr));
+      if (I.d.dim == 2) HIPOK(launch_chunk_phi(I.fyG.p, nx, ny, M, I.fyPhiC.p, I.fyPhiS.p, nullptr));
+    }
+  }
+  P->M = M;
+  P->lanes_cap = lanes_cap;
+  HIPOK(hipDeviceSynchronize());
+  if (P->gexec) {
+    (void)hipGraphExecDestroy(P->gexec);
+    P->gexec = nullptr;
+  }
+  if (P->graph) {
+    (void)hipGraphDestroy(P->graph);
+    P->graph = nullptr;
+  }
+  return build_schedules(P);
 }
 
 }  // namespace
@@ -682,24 +829,24 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
     P->inst.push_back(std::move(I));
   }
   P->tot_u0 = ou; P->tot_slices = osl; P->tot_states = ost;
-  // device descriptors
-  std::vector<DimInst> hd(n_instances);
-  for (int i = 0; i < n_instances; i++) hd[i] = P->inst[i]->h;
-  HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_inst), hd.size() * sizeof(DimInst)));
-  HIPOK(hipMemcpy(P->d_inst, hd.data(), hd.size() * sizeof(DimInst), hipMemcpyHostToDevice));
-  // grouped work lists by lane width
-  for (int L = 1; L <= 64; L <<= 1) {
-    std::vector<int> members;
-    for (int i = 0; i < n_instances; i++)
-      if (!P->inst[i]->dd && P->inst[i]->h.L == L) members.push_back(i);
-    if (members.empty()) continue;
-    pr_problem_s::Group g;
-    g.L = L;
-    for (int dir = 0; dir < 2; dir++)
-      HIPOK(upload_work(build_work(members, P->inst, dir, P->M), &g.d_work[dir],
-                        &g.n_work[dir]));
-    P->groups.push_back(g);
+  HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_active), n_instances * sizeof(int)));
+  HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_inst), n_instances * sizeof(DimInst)));
+  for (int i = 0; i < n_instances; i++) {
+    DimInst& h = P->inst[i]->h;
+    h.idx = i;
+    h.cs = P->inst[i]->d.coarse_steps;
+    h.npts = P->inst[i]->npts;
+    h.off_slices = (long)P->inst[i]->off_slices;
+    h.off_states = (long)P->inst[i]->off_states;
+    h.active = P->d_active;
   }
+  {
+    pr_status st = set_all_active(P.get(), s);
+    if (st != PR_OK) return st;
+    st = build_schedules(P.get());
+    if (st != PR_OK) return st;
+  }
+  HIPOK(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
   // parareal workspace
   HIPOK(P->F.alloc(osl));
   HIPOK(P->Gold.alloc(osl));
@@ -772,37 +919,159 @@ pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_m
   if (!p || !u0 || !U || !k_done || !inc) return fail(PR_EINVAL, "NULL argument");
   if (k_max < 0) return fail(PR_EINVAL, "k_max must be >= 0");
   if (!(tol >= 0)) return fail(PR_EINVAL, "tol must be >= 0");
-  hipStream_t s = as_stream(hip_stream);
+  // the work runs on the library's stream once the caller's stream has drained
+  HIPOK(hipStreamSynchronize(as_stream(hip_stream)));
+  hipStream_t s = p->gstream;
   const int n = (int)p->inst.size();
+  pr_status st = set_all_active(p, s);
+  if (st != PR_OK) return st;
   for (int i = 0; i < n; i++) {
     Instance& I = *p->inst[i];
     HIPOK(launch_copy(u0 + I.off_u0, U + I.off_states, I.npts, s));
     k_done[i] = 0;
     inc[i] = 0.0;
   }
-  pr_status st = coarse_sweep_impl(p, nullptr, p->Gold.p, U, p->d_inc, s, nullptr);
+  st = coarse_sweep_impl(p, nullptr, p->Gold.p, U, p->d_inc, s, nullptr);  // initial guess
   if (st != PR_OK) return st;
   std::vector<char> active(n, 1);
   int n_active = n;
-  for (int k = 0; k < k_max && n_active > 0; k++) {
-    st = fine_all(p, U, true, p->F.p, s);
-    if (st != PR_OK) return st;
-    st = coarse_sweep_impl(p, p->F.p, p->Gold.p, U, p->d_inc, s, &active);
-    if (st != PR_OK) return st;
+  // one parareal correction: F on all active slices, coarse sweep with the
+  // correction and increment, device mask update, increment to the host
+  auto correction = [&]() -> pr_status {
+    pr_status r = fine_all(p, U, true, p->F.p, s);
+    if (r != PR_OK) return r;
+    r = coarse_sweep_impl(p, p->F.p, p->Gold.p, U, p->d_inc, s, &active);
+    if (r != PR_OK) return r;
+    HIPOK(launch_mask_update(reinterpret_cast<const double*>(p->d_inc), p->d_active, n, tol, s));
     HIPOK(hipMemcpyAsync(p->h_inc, p->d_inc, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    return PR_OK;
+  };
+  const bool graph = p->use_graph && !p->any_dd && !p->prof && k_max > 0;
+  if (graph && (!p->gexec || p->graph_tol != tol || p->graph_U != U)) {
+    if (p->gexec) {
+      (void)hipGraphExecDestroy(p->gexec);
+      p->gexec = nullptr;
+    }
+    if (p->graph) {
+      (void)hipGraphDestroy(p->graph);
+      p->graph = nullptr;
+    }
+    HIPOK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    pr_status r = correction();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (r != PR_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    HIPOK(e);
+    p->graph = g;
+    HIPOK(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+    p->graph_tol = tol;
+    p->graph_U = U;
+  }
+  pr_status result = PR_OK;
+  for (int k = 0; k < k_max && n_active > 0; k++) {
+    if (graph) {
+      HIPOK(hipGraphLaunch(p->gexec, s));
+    } else {
+      st = correction();
+      if (st != PR_OK) return st;
+    }
     HIPOK(hipStreamSynchronize(s));
     for (int i = 0; i < n; i++) {
       if (!active[i]) continue;
-      double v = p->h_inc[i];
+      const double v = p->h_inc[i];
       k_done[i] = k + 1;
       inc[i] = v;
-      if (!std::isfinite(v)) return fail(PR_ENUMERIC, "instance %d: non-finite increment", i);
+      if (!std::isfinite(v)) result = fail(PR_ENUMERIC, "instance %d: non-finite increment", i);
       if (v < tol) {
         active[i] = 0;
         n_active--;
       }
     }
+    if (result != PR_OK) break;
   }
+  st = set_all_active(p, s);
+  if (st != PR_OK) return st;
+  return result;
+}
+
+pr_status pr_set_option(pr_problem p, int option, int value) {
+  if (!p) return fail(PR_EINVAL, "NULL handle");
+  switch (option) {
+    case PR_OPT_GRAPH:
+      if (value != 0 && value != 1) return fail(PR_EINVAL, "graph option must be 0 or 1");
+      p->use_graph = value == 1;
+      return PR_OK;
+    case PR_OPT_FINE_CHUNK:
+      if (value != 16 && value != 32) return fail(PR_EINVAL, "fine chunk must be 16 or 32");
+      return apply_layout(p, p->lanes_cap, value);
+    case PR_OPT_LANES:
+      if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
+        return fail(PR_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
+      return apply_layout(p, value, p->M);
+    default:
+      return fail(PR_EINVAL, "unknown option %d", option);
+  }
+}
+
+pr_status pr_get_option(pr_problem p, int option, int* value) {
+  if (!p || !value) return fail(PR_EINVAL, "NULL argument");
+  switch (option) {
+    case PR_OPT_GRAPH: *value = p->use_graph ? 1 : 0; return PR_OK;
+    case PR_OPT_FINE_CHUNK: *value = p->M; return PR_OK;
+    case PR_OPT_LANES: *value = p->lanes_cap; return PR_OK;
+    default: return fail(PR_EINVAL, "unknown option %d", option);
+  }
+}
+
+pr_status pr_autotune(pr_problem p, void* hip_stream, int* lanes, int* chunk, float* best_ms) {
+  if (!p) return fail(PR_EINVAL, "NULL handle");
+  hipStream_t s = as_stream(hip_stream);
+  int Lmax = 8;
+  for (auto& I : p->inst)
+    if (!I->dd) Lmax = std::max(Lmax, I->Ldef);
+  hipEvent_t e0, e1;
+  HIPOK(hipEventCreate(&e0));
+  HIPOK(hipEventCreate(&e1));
+  float best = -1.f;
+  int bl = p->lanes_cap, bm = p->M;
+  const bool prof = p->prof;
+  p->prof = false;
+  pr_status st = PR_OK;
+  for (int L = 8; L <= Lmax && st == PR_OK; L <<= 1)
+    for (int M : {16, 32}) {
+      st = apply_layout(p, L == Lmax ? 0 : L, M);
+      if (st != PR_OK) break;
+      float ms_min = -1.f;
+      for (int rep = 0; rep < 3 && st == PR_OK; rep++) {
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(PR_EDEVICE, "event record"); break; }
+        st = fine_all(p, p->Gold.p, false, p->F.p, s);
+        if (st != PR_OK) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          st = fail(PR_EDEVICE, "event sync");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && (ms_min < 0 || ms < ms_min)) ms_min = ms;  // first run warms up
+      }
+      if (st == PR_OK && (best < 0 || ms_min < best)) {
+        best = ms_min;
+        bl = L == Lmax ? 0 : L;
+        bm = M;
+      }
+    }
+  p->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != PR_OK) return st;
+  st = apply_layout(p, bl, bm);
+  if (st != PR_OK) return st;
+  if (lanes) *lanes = bl;
+  if (chunk) *chunk = bm;
+  if (best_ms) *best_ms = best;
   return PR_OK;
 }
 

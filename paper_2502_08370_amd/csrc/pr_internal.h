@@ -54,6 +54,17 @@ struct DimInst {
   const double* cxE; const double* cxR; const double* cxG;
   const double* cyE; const double* cyR; const double* cyG;
   double* tmp;       // one-state scratch of the coarse sweep
+  // batch bookkeeping
+  int idx;           // instance index in the handle
+  int cs;            // coarse steps per coarse propagation
+  long npts;         // nx*ny
+  long off_slices, off_states;  // offsets of the instance in packed buffers
+  const int* active; // per-instance flags (0: converged, skipped by every kernel)
+};
+
+// Work item of a batched coarse launch: instance and line block.
+struct LineItem {
+  int inst, block;
 };
 
 // Work item of a grouped fine-sweep launch: instance, slice block, line group.
@@ -162,6 +173,21 @@ hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double
                            bool fine, hipStream_t s);
 // Largest grid extent the coarse sweeps handle (whole line per wave, 64-point chunks).
 constexpr int kMaxCoarseLine = 1024;
+constexpr int kCoarseRowsPerBlock = 4;    // x lines per block of the coarse x kernels
+constexpr int kCoarseColsPerBlock = 16;   // y lines per block of the coarse y kernels
+// Batched coarse sweep: one launch covers every instance's slice n (items of
+// instances with n < N and still active). step c of the instance's coarse
+// propagation: c == 0 reads U[n] from U_base, later steps the instance's tmp;
+// the last step (c == cs-1) applies mode (1: correction + increment, 2:
+// initial guess) to U[n+1] / G_old[n] / F[n], the others write tmp.
+hipError_t launch_coarse_xb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
+                            int c, const double* U_base, hipStream_t s);
+hipError_t launch_coarse_yb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
+                            int c, int mode, const double* F_base, double* G_base, double* U_base,
+                            unsigned long long* inc_bits, int max_ny, hipStream_t s);
+// Parareal bookkeeping on the device: inc = 0 for active instances (start of
+// a correction) and active &= !(inc < tol) (end of a correction).
+hipError_t launch_mask_update(const double* inc, int* active, int n, double tol, hipStream_t s);
 // Coarse y sweep. mode 0: write the result to dst; mode 1: parareal update
 // (U_next = F + (g - G_old), G_old = g, increment into inc_bits); mode 2:
 // initial guess (U_next = g, G_old = g).

@@ -144,6 +144,7 @@ __global__ __launch_bounds__(kWave) void k_to_interleaved(const DimInst* __restr
                                                           const double* __restrict__ U) {
   __shared__ double tile[64][65];
   const DimInst& I = insts[0];
+  if (I.active && !I.active[I.idx]) return;
   const int lane = threadIdx.x;
   const int i0 = blockIdx.x * 64, j = blockIdx.y, b = blockIdx.z;
   const int L = I.L, nx = I.nx;
@@ -167,6 +168,7 @@ __global__ __launch_bounds__(kWave) void k_from_interleaved(const DimInst* __res
                                                             double* __restrict__ F, int with_corr) {
   __shared__ double tile[64][65];
   const DimInst& I = insts[0];
+  if (I.active && !I.active[I.idx]) return;
   const int lane = threadIdx.x;
   const int i0 = blockIdx.x * 64, j = blockIdx.y, b = blockIdx.z;
   const int L = I.L, nx = I.nx, M = I.M, Py = I.Py;
@@ -212,6 +214,7 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   const WorkItem w = work[blockIdx.x];
   const DimInst& I = insts[w.inst];
   if (step >= I.steps) return;  // this instance has finished its fine steps
+  if (I.active && !I.active[I.idx]) return;  // converged instance
   const int lane = threadIdx.x;
   const int gsub = lane / L;
   const int sl = lane - gsub * L;
@@ -409,7 +412,7 @@ __device__ __forceinline__ void line_solve_scan(double (&v)[NC], const gdouble* 
   }
 }
 
-constexpr int kRowsPerBlock = 4;
+constexpr int kRowsPerBlock = kCoarseRowsPerBlock;
 
 // x-lines (rows), one wave per row: coalesced along the row.
 template <int NC>
@@ -436,7 +439,7 @@ __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_x(
   }
 }
 
-constexpr int kColsPerBlock = 16;
+constexpr int kColsPerBlock = kCoarseColsPerBlock;
 constexpr int kTS = kColsPerBlock + 1;  // padded LDS row stride
 
 // y-lines (columns): a block of 16 columns is staged in LDS through
@@ -504,6 +507,148 @@ __global__ __launch_bounds__(kWave* kColsPerBlock) void k_coarse_y(
     mx = wave_max_u64(mx);
     if (lane == 0 && mx != 0) atomicMax(inc_bits, mx);
   }
+}
+
+// ----------------------------------------------- batched coarse sweeps ---
+// Same line solves as k_coarse_x / k_coarse_y, one launch per slice index n
+// over the work items of every instance; lines of different instances have
+// different lengths, so the chunk count is a per-block runtime value (<= NCMAX).
+
+template <int NCMAX>
+__device__ __forceinline__ void line_solve_scan_n(double (&v)[NCMAX], int nc, const gdouble* E,
+                                                  const gdouble* R, const gdouble* Gf, int n,
+                                                  int lane) {
+  double carry = 0.0;
+#pragma unroll
+  for (int c = 0; c < NCMAX; c++) {
+    if (c < nc) {
+      const int p = c * kWave + lane;
+      const bool ok = p < n;
+      double a = ok ? E[p] : 1.0, b = ok ? v[c] : 0.0;
+      affine_scan_up(a, b, lane);
+      v[c] = fma(a, carry, b);
+      carry = lane_value(v[c], kWave - 1);
+    }
+  }
+  carry = 0.0;
+#pragma unroll
+  for (int c = NCMAX - 1; c >= 0; c--) {
+    if (c < nc) {
+      const int p = c * kWave + lane;
+      const bool ok = p < n;
+      double a = ok ? Gf[p] : 0.0, b = ok ? R[p] * v[c] : 0.0;
+      affine_scan_down(a, b, lane);
+      v[c] = fma(a, carry, b);
+      carry = lane_value(v[c], 0);
+    }
+  }
+}
+
+template <int NCMAX>
+__global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_xb(
+    const DimInst* __restrict__ insts, const LineItem* __restrict__ items, int n, int c,
+    const double* __restrict__ U_base) {
+  const LineItem it = items[blockIdx.x];
+  const DimInst& I = insts[it.inst];
+  if (I.active && !I.active[I.idx]) return;
+  if (n >= I.N || c >= I.cs) return;
+  const int nx = I.nx, ny = I.ny;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int row = it.block * kRowsPerBlock + (threadIdx.x >> 6);
+  if (row >= ny) return;  // whole wave
+  const gdouble* src = c == 0 ? gp(U_base) + I.off_states + (long)n * I.npts : gp(I.tmp);
+  gdouble* dst = gp(I.tmp);
+  const long base = (long)row * nx;
+  const int nc = (nx + kWave - 1) / kWave;
+  double v[NCMAX];
+#pragma unroll
+  for (int cc = 0; cc < NCMAX; cc++) {
+    const int p = cc * kWave + lane;
+    v[cc] = (cc < nc && p < nx) ? src[base + p] : 0.0;
+  }
+  line_solve_scan_n<NCMAX>(v, nc, gp(I.cxE) + base, gp(I.cxR) + base, gp(I.cxG) + base, nx, lane);
+#pragma unroll
+  for (int cc = 0; cc < NCMAX; cc++) {
+    const int p = cc * kWave + lane;
+    if (cc < nc && p < nx) dst[base + p] = v[cc];
+  }
+}
+
+template <int NCMAX>
+__global__ __launch_bounds__(kWave* kColsPerBlock) void k_coarse_yb(
+    const DimInst* __restrict__ insts, const LineItem* __restrict__ items, int n, int c, int mode,
+    const double* __restrict__ F_base, double* __restrict__ G_base, double* __restrict__ U_base,
+    unsigned long long* __restrict__ inc_bits) {
+  extern __shared__ double T[];  // [ny][kTS]
+  const LineItem it = items[blockIdx.x];
+  const DimInst& I = insts[it.inst];
+  if (I.active && !I.active[I.idx]) return;  // uniform over the block
+  if (n >= I.N || c >= I.cs) return;
+  const int nx = I.nx, ny = I.ny;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wv = tid >> 6;
+  const int i0 = it.block * kColsPerBlock;
+  const int total = ny * kColsPerBlock;
+  const gdouble* src = gp(I.tmp);
+  for (int q = tid; q < total; q += kWave * kColsPerBlock) {
+    int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
+    int i = i0 + cc;
+    T[j * kTS + cc] = i < nx ? src[(long)j * nx + i] : 0.0;
+  }
+  __syncthreads();
+  const int col = i0 + wv;
+  if (col < nx) {
+    const int nc = (ny + kWave - 1) / kWave;
+    double v[NCMAX];
+#pragma unroll
+    for (int cc = 0; cc < NCMAX; cc++) {
+      int p = cc * kWave + lane;
+      v[cc] = (cc < nc && p < ny) ? T[p * kTS + wv] : 0.0;
+    }
+    const long lb = (long)col * ny;
+    line_solve_scan_n<NCMAX>(v, nc, gp(I.cyE) + lb, gp(I.cyR) + lb, gp(I.cyG) + lb, ny, lane);
+#pragma unroll
+    for (int cc = 0; cc < NCMAX; cc++) {
+      int p = cc * kWave + lane;
+      if (cc < nc && p < ny) T[p * kTS + wv] = v[cc];
+    }
+  }
+  __syncthreads();
+  const int md = (c + 1 == I.cs) ? mode : 0;
+  gdouble* tmpw = gp(I.tmp);
+  const gdouble* Fn = gp(F_base) + I.off_slices + (long)n * I.npts;
+  gdouble* Gn = gp(G_base) + I.off_slices + (long)n * I.npts;
+  gdouble* Un = gp(U_base) + I.off_states + (long)(n + 1) * I.npts;
+  unsigned long long mx = 0;
+  for (int q = tid; q < total; q += kWave * kColsPerBlock) {
+    int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
+    int i = i0 + cc;
+    if (i >= nx) continue;
+    long idx = (long)j * nx + i;
+    double g = T[j * kTS + cc];
+    if (md == 0) {
+      tmpw[idx] = g;
+    } else if (md == 2) {
+      Un[idx] = g;
+      Gn[idx] = g;
+    } else {
+      double un = Fn[idx] + (g - Gn[idx]);
+      unsigned long long bits = abs_bits(un - Un[idx]);
+      mx = bits > mx ? bits : mx;
+      Un[idx] = un;
+      Gn[idx] = g;
+    }
+  }
+  if (md == 1) {
+    mx = wave_max_u64(mx);
+    if (lane == 0 && mx != 0) atomicMax(inc_bits + I.idx, mx);
+  }
+}
+
+__global__ void k_mask_update(const double* __restrict__ inc, int* __restrict__ active, int n,
+                              double tol) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && active[i] && inc[i] < tol) active[i] = 0;
 }
 
 __global__ void k_fill_zero(double* __restrict__ p, size_t n) {
@@ -673,6 +818,37 @@ hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s) 
   if (n == 0) return hipSuccess;
   int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_xb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
+                            int c, const double* U_base, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_coarse_xb<16>), dim3(n_items), dim3(kWave * kRowsPerBlock), 0, s, d_insts,
+                     items, n, c, U_base);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_yb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
+                            int c, int mode, const double* F_base, double* G_base, double* U_base,
+                            unsigned long long* inc_bits, int max_ny, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_yb<16>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       kMaxCoarseLine * kTS * (int)sizeof(double));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  size_t lds = (size_t)max_ny * kTS * sizeof(double);
+  hipLaunchKernelGGL((k_coarse_yb<16>), dim3(n_items), dim3(kWave * kColsPerBlock), lds, s,
+                     d_insts, items, n, c, mode, F_base, G_base, U_base, inc_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_update(const double* inc, int* active, int n, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_update, dim3((n + 255) / 256), dim3(256), 0, s, inc, active, n, tol);
   return hipGetLastError();
 }
 
