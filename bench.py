@@ -57,6 +57,18 @@ def covered_nodes(w):
     return tot
 
 
+def measured_traffic(kernel_src, summary):
+    """HBM bytes per launch from the committed byte-counter summary, or None when the
+    kernel source has changed since the counters were taken (or no summary exists)."""
+    import hashlib
+    try:
+        fig = json.load(open(summary))
+        h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    return fig["traffic_bytes_per_launch"] if fig.get("source_sha256_16") == h else None
+
+
 def cpu_baseline(w, budget_s):
     """Oracle (serial FP64 C, one thread) on a bounded sample of the same workload:
     the fine propagator on one slice for as many fine steps as fit the budget."""
@@ -168,6 +180,8 @@ def main():
                          "batch: 256 uneven 2D instances, batched parareal vs a loop of "
                          "single-instance launches")
     ap.add_argument("--instances", type=int, default=256)
+    ap.add_argument("--copy-probe-mib", type=int, default=512,
+                    help="size of a plain device-to-device copy timed in the same run (0: skip)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
@@ -253,6 +267,13 @@ def main():
     else:
         bytes_per_sweep = 16.0 * npts * N  # one substep: read + write one FP64 per point per slice
     achieved = bytes_per_sweep / (sweep_avg_ms * 1e-3) / 1e9
+    traffic = None
+    if w.split != "dd" and (w.nx, w.n_slices, w.fine_steps) == (1023, 64, 64):
+        tb = measured_traffic(os.path.join(ROOT, "paper_2502_08370_amd", "csrc", "pr_kernels_dim.hip"),
+                              os.path.join(ROOT, "profiles", "pmc_fine_sweep_varcoef2d_1023_N64_s64.json"))
+        if tb is not None:
+            traffic = {"gbs": round(tb / (sweep_avg_ms * 1e-3) / 1e9, 1), "bytes_per_launch": tb,
+                       "over_algorithmic": round(tb / bytes_per_sweep, 4)}
     fine_ms = (phases["fine_sweep"][0] + phases.get("fine_transpose", (0, 0))[0]) / args.steps
     coarse_ms = (phases.get("coarse_x", (0, 0))[0] + phases.get("coarse_y", (0, 0))[0]) / args.steps
 
@@ -272,13 +293,34 @@ def main():
                                 if w.split == "dd" else "k_fine_sweep"),
                      "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": bytes_per_sweep,
+                     "traffic": traffic["gbs"] if traffic else None,
+                     "traffic_detail": traffic, "bytes_per_launch": bytes_per_sweep,
                      "mean_launch_ms": round(sweep_avg_ms, 5), "launches": int(sweep_n)},
         "fine_propagator": {"gpts": round(fine_pts / (fine_ms * 1e-3) / 1e9, 3),
                             "ms": round(fine_ms, 4)},
         "coarse_sweep_ms": round(coarse_ms, 4),
         "cpu_baseline": cpu,
     }
+
+    if args.copy_probe_mib > 0:
+        # plain copy of known size: achievable bandwidth in this session, and the reference
+        # for scaling hardware byte counters
+        nbytes = args.copy_probe_mib << 20
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(5):
+            b.copy_(a)
+        c1.record()
+        torch.cuda.synchronize()
+        gbs = 2 * nbytes * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+        result["copy_probe"] = {"bytes_copied": nbytes, "read_plus_write_gbs": round(gbs, 1)}
+        result["roofline"]["frac_of_copy_probe"] = round(achieved / gbs, 4)
+        log(f"copy probe {args.copy_probe_mib} MiB: {gbs:.1f} GB/s read+write")
+        del a, b
 
     if not args.no_parareal:
         # parareal to tolerance vs the sequential fine solve (the plain loop of fine steps)

@@ -166,12 +166,16 @@ pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_m
 /* Tuning options (pr_set_option / pr_get_option):
  *   PR_OPT_GRAPH       1 (default): pr_parareal_iterate captures one correction
  *                      as a HIP graph and replays it; 0: direct launches
- *   PR_OPT_FINE_CHUNK  chunk length of the fine line sweeps: 16 (default), 32
+ *   PR_OPT_FINE_CHUNK  chunk length of the fine line sweeps: 16, 32 (default)
  *   PR_OPT_LANES       slice lanes per line in the fine sweeps (lines per wave =
  *                      64 / lanes): 0 = per-instance default (the smallest power
  *                      of two >= N, in [8, 64]), or a cap of 8, 16, 32, 64
+ *   PR_OPT_BLOCKS_PER_PASS  0 (default): every fine step covers all slice
+ *                      blocks; k > 0: blocks are processed k at a time, each
+ *                      group running all s fine steps before the next (a
+ *                      smaller working set between consecutive sweeps)
  * Results do not depend on the options beyond rounding. */
-enum { PR_OPT_GRAPH = 1, PR_OPT_FINE_CHUNK = 2, PR_OPT_LANES = 3 };
+enum { PR_OPT_GRAPH = 1, PR_OPT_FINE_CHUNK = 2, PR_OPT_LANES = 3, PR_OPT_BLOCKS_PER_PASS = 4 };
 pr_status pr_set_option(pr_problem p, int option, int value);
 pr_status pr_get_option(pr_problem p, int option, int* value);
 

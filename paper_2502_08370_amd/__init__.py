@@ -45,6 +45,10 @@ def _dev_f64(a, device):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
 
 
+_OPTS = {"graph": B.PR_OPT_GRAPH, "fine_chunk": B.PR_OPT_FINE_CHUNK, "lanes": B.PR_OPT_LANES,
+         "blocks_per_pass": B.PR_OPT_BLOCKS_PER_PASS}
+
+
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -173,14 +177,13 @@ class Problem:
         B.check(B.lib().pr_sequential_fine(self._h, _ptr(u0), _ptr(U), _stream(stream)))
 
     def set_option(self, name, value):
-        """name: 'graph' (0/1), 'fine_chunk' (16/32), 'lanes' (0/8/16/32/64)."""
-        opt = {"graph": B.PR_OPT_GRAPH, "fine_chunk": B.PR_OPT_FINE_CHUNK, "lanes": B.PR_OPT_LANES}[name]
-        B.check(B.lib().pr_set_option(self._h, opt, int(value)))
+        """name: 'graph' (0/1), 'fine_chunk' (16/32), 'lanes' (0/8/16/32/64),
+        'blocks_per_pass' (0 = all slice blocks per launch, k > 0 = k at a time)."""
+        B.check(B.lib().pr_set_option(self._h, _OPTS[name], int(value)))
 
     def get_option(self, name):
-        opt = {"graph": B.PR_OPT_GRAPH, "fine_chunk": B.PR_OPT_FINE_CHUNK, "lanes": B.PR_OPT_LANES}[name]
         v = C.c_int()
-        B.check(B.lib().pr_get_option(self._h, opt, C.byref(v)))
+        B.check(B.lib().pr_get_option(self._h, _OPTS[name], C.byref(v)))
         return v.value
 
     def autotune(self, cache=None, stream=None):

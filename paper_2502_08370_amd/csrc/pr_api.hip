@@ -132,14 +132,17 @@ struct pr_problem_s {
   std::vector<Rec> recs;
   pr_profile acc{};
   size_t tot_u0 = 0, tot_slices = 0, tot_states = 0;
-  int M = 16;  // fine-sweep chunk length
+  int M = 32;  // fine-sweep chunk length (PR_OPT_FINE_CHUNK)
   DimInst* d_inst = nullptr;  // device descriptors, one per instance
   // grouped work lists per lane width L (index log2 L) and direction
   struct Group {
     int L = 0;
     WorkItem* d_work[2] = {nullptr, nullptr};
     int n_work[2] = {0, 0};
+    std::vector<int> pass_off[2];  // items of pass q: [pass_off[q], pass_off[q+1])
   };
+  int blocks_per_pass = 0;  // 0: every slice block in every launch
+  int n_passes = 1;
   std::vector<Group> groups;
   // parareal workspace
   DBuf F, Gold;
@@ -229,7 +232,8 @@ pr_status validate(const pr_problem_desc& d, int idx) {
 
 pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   const pr_problem_desc& d = I.d;
-  const int nx = d.nx, ny = d.ny, N = d.n_slices, M = P->M;
+  const int nx = d.nx, ny = d.ny, N = d.n_slices;
+  const int M = 16;  // chunk-sized arrays are allocated for the shortest chunk
   const size_t npts = (size_t)nx * ny;
   I.npts = (int)npts;
   I.dt = d.T / d.n_slices / d.fine_steps;
@@ -253,7 +257,9 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   const int B = (N + L - 1) / L;
   I.Ldef = L;
   DimInst& h = I.h;
-  h.nx = nx; h.ny = ny; h.N = N; h.L = L; h.B = B; h.M = M; h.Px = Px; h.Py = Py;
+  const int Mc = P->M;
+  h.nx = nx; h.ny = ny; h.N = N; h.L = L; h.B = B; h.M = Mc;
+  h.Px = (nx + Mc - 1) / Mc; h.Py = (ny + Mc - 1) / Mc;
   h.steps = d.fine_steps;
   h.slab = (long)npts * L;
   HIPOK(I.Z.alloc((size_t)B * npts * L));
@@ -485,7 +491,7 @@ pr_status dd_fie_step(pr_problem_s* P, Instance& I, bool coarse, int which, hipS
 // dealt to the 8 XCDs round-robin by id).
 std::vector<WorkItem> build_work(const std::vector<int>& members,
                                  const std::vector<std::unique_ptr<Instance>>& inst, int dir,
-                                 int M) {
+                                 int M, int b_lo = 0, int b_hi = 1 << 30) {
   const int kXcd = 8;
   std::vector<std::vector<WorkItem>> per(kXcd);
   for (int m : members) {
@@ -495,7 +501,7 @@ std::vector<WorkItem> build_work(const std::vector<int>& members,
     const int G = 64 / h.L;
     const int n_groups = (n_lines + G - 1) / G;
     const int groups_per_chunk = std::max(1, M / G);
-    for (int b = 0; b < h.B; b++)
+    for (int b = std::max(0, b_lo); b < std::min(h.B, b_hi); b++)
       for (int g = 0; g < n_groups; g++) {
         int x = (g / groups_per_chunk) % kXcd;
         per[x].push_back(WorkItem{m, b, g, 0});
@@ -531,16 +537,21 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
     PhaseTimer pt(P, PH_TRANSPOSE, s);
     HIPOK(launch_to_interleaved(P->d_inst + i, I.h, U, s));
   }
-  // all instances advance step by step; one grouped launch per lane width and direction
+  // all instances advance step by step; one grouped launch per lane width and
+  // direction (per pass of slice blocks when passes are enabled: a pass runs all
+  // its steps before the next one starts, keeping its working set cached)
   int smax = 0;
   for (auto& I : P->inst) smax = std::max(smax, I->d.fine_steps);
-  for (int t = 0; t < smax; t++) {
-    for (auto& g : P->groups) {
-      for (int dir = 0; dir < 2; dir++) {
-        if (!g.n_work[dir]) continue;
-        PhaseTimer pt(P, PH_FINE, s);
-        HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir], g.n_work[dir], g.L, P->M, dir,
-                                dir == 1 || t > 0, t, s));
+  for (int q = 0; q < P->n_passes; q++) {
+    for (int t = 0; t < smax; t++) {
+      for (auto& g : P->groups) {
+        for (int dir = 0; dir < 2; dir++) {
+          const int off = g.pass_off[dir][q], cnt = g.pass_off[dir][q + 1] - off;
+          if (!cnt) continue;
+          PhaseTimer pt(P, PH_FINE, s);
+          HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir] + off, cnt, g.L, P->M, dir,
+                                  dir == 1 || t > 0, t, s));
+        }
       }
     }
   }
@@ -674,6 +685,11 @@ pr_status build_schedules(pr_problem_s* P) {
         w = nullptr;
       }
   P->groups.clear();
+  int Bmax = 1;
+  for (auto& I : P->inst)
+    if (!I->dd) Bmax = std::max(Bmax, I->h.B);
+  const int bpp = P->blocks_per_pass > 0 ? P->blocks_per_pass : Bmax;
+  P->n_passes = (Bmax + bpp - 1) / bpp;
   for (int L = 1; L <= 64; L <<= 1) {
     std::vector<int> members;
     for (int i = 0; i < n; i++)
@@ -681,8 +697,16 @@ pr_status build_schedules(pr_problem_s* P) {
     if (members.empty()) continue;
     pr_problem_s::Group g;
     g.L = L;
-    for (int dir = 0; dir < 2; dir++)
-      HIPOK(upload_work(build_work(members, P->inst, dir, P->M), &g.d_work[dir], &g.n_work[dir]));
+    for (int dir = 0; dir < 2; dir++) {
+      std::vector<WorkItem> all;
+      g.pass_off[dir].assign(1, 0);
+      for (int q = 0; q < P->n_passes; q++) {
+        std::vector<WorkItem> part = build_work(members, P->inst, dir, P->M, q * bpp, (q + 1) * bpp);
+        all.insert(all.end(), part.begin(), part.end());
+        g.pass_off[dir].push_back((int)all.size());
+      }
+      HIPOK(upload_work(all, &g.d_work[dir], &g.n_work[dir]));
+    }
     P->groups.push_back(g);
   }
   P->Nmax = 0;
@@ -1011,6 +1035,10 @@ pr_status pr_set_option(pr_problem p, int option, int value) {
       if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
         return fail(PR_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
       return apply_layout(p, value, p->M);
+    case PR_OPT_BLOCKS_PER_PASS:
+      if (value < 0) return fail(PR_EINVAL, "blocks per pass must be >= 0");
+      p->blocks_per_pass = value;
+      return apply_layout(p, p->lanes_cap, p->M);
     default:
       return fail(PR_EINVAL, "unknown option %d", option);
   }
@@ -1022,6 +1050,7 @@ pr_status pr_get_option(pr_problem p, int option, int* value) {
     case PR_OPT_GRAPH: *value = p->use_graph ? 1 : 0; return PR_OK;
     case PR_OPT_FINE_CHUNK: *value = p->M; return PR_OK;
     case PR_OPT_LANES: *value = p->lanes_cap; return PR_OK;
+    case PR_OPT_BLOCKS_PER_PASS: *value = p->blocks_per_pass; return PR_OK;
     default: return fail(PR_EINVAL, "unknown option %d", option);
   }
 }

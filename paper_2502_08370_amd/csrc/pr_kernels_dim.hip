@@ -101,12 +101,15 @@ __global__ void k_factorize(FactorJob job) {
   int line = blockIdx.x * blockDim.x + threadIdx.x;
   if (line >= job.n_lines) return;
   const double* face = job.face + line * job.face_line_stride;
-  double u_prev = 1.0;
+  // the matrix is symmetric, so the forward multiplier e_p = w_p / u_{p-1}
+  // equals the previous back-substitution factor g_{p-1} = w_p r_{p-1}; both
+  // are formed as that product so that E[p] == G[p-1] exactly
+  double r_prev = 0.0;
   double wl = job.tau_over_h2 * face[0];
   for (int p = 0; p < job.n_pos; p++) {
     double wr = job.tau_over_h2 * face[(long)(p + 1) * job.face_pos_stride];
     double diag = 1.0 + wl + wr + job.react;
-    double e = (p == 0) ? 0.0 : wl / u_prev;
+    double e = (p == 0) ? 0.0 : wl * r_prev;
     double u = diag - wl * e;
     double r = 1.0 / u;
     double g = (p + 1 < job.n_pos) ? wr * r : 0.0;
@@ -114,7 +117,7 @@ __global__ void k_factorize(FactorJob job) {
     job.E[idx] = e;
     job.R[idx] = r;
     job.G[idx] = g;
-    u_prev = u;
+    r_prev = r;
     wl = wr;
   }
 }
@@ -210,6 +213,9 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   static_assert(M <= kWave, "chunk longer than a wave");
   // factor staging when a wave holds several lines: [4][G][M+1]
   __shared__ double sF[kUni ? 1 : 4][kUni ? 1 : G][M + 1];
+  // first value of every chunk of the wave's lines, resolved into carries at the end
+  constexpr int kMaxChunks = (kMaxCoarseLine + M - 1) / M;
+  __shared__ double zfirst[kMaxChunks][kWave];
 
   const WorkItem w = work[blockIdx.x];
   const DimInst& I = insts[w.inst];
@@ -225,7 +231,6 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   const int nl_prev = n_pos;  // lines of the previous sweep = our positions
   const long pstr = DIR == 0 ? (long)L : (long)I.nx * L;
   const long lstr = DIR == 0 ? (long)I.nx * L : (long)L;
-  const gdouble* E = gp(DIR == 0 ? I.fxE : I.fyE);
   const gdouble* R = gp(DIR == 0 ? I.fxR : I.fyR);
   const gdouble* Gf = gp(DIR == 0 ? I.fxG : I.fyG);
   const gdouble* phiS = gp(DIR == 0 ? I.fxPhiS : I.fyPhiS);
@@ -266,7 +271,6 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
     }
     if constexpr (kUni) {
       const long idx = frow + p0 + (lane < cnt ? lane : 0);
-      f[0][0] = E[idx];
       f[1][0] = R[idx];
       f[2][0] = Gf[idx];
       if constexpr (HP) f[3][0] = phiPrev[idx];
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
         const int ln = line0 + g, p = p0 + t;
         const bool ok = q < G * M && ln < n_lines && p < n_pos;
         const long idx = ok ? (long)ln * n_pos + p : 0;
-        f[0][qq] = E[idx];
+        f[0][qq] = (ok && p > 0) ? Gf[idx - 1] : 0.0;  // e_p = g_{p-1}
         f[1][qq] = R[idx];
         f[2][qq] = Gf[idx];
         if constexpr (HP) f[3][qq] = phiPrev[idx];
@@ -287,6 +291,7 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   };
 
   double ycarry = 0.0;
+  double gcarry = 0.0;  // g at the last position of the previous chunk (kUni path)
   auto process = [&](double (&v)[M], double (&sg)[M], double (&f)[4][NQ], int k) {
     const int p0 = k * M;
     const int cnt = min(M, n_pos - p0);
@@ -303,10 +308,13 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
     auto fac = [&](int c, int t) -> double {
-      if constexpr (kUni)
+      if constexpr (kUni) {
+        if (c == 0)  // e_p = g_{p-1}: the previous lane's g, or the last g of the previous chunk
+          return t == 0 ? gcarry : lane_value(f[2][0], t - 1);
         return lane_value(f[c][0], t);
-      else
+      } else {
         return sF[c][gsub][t];
+      }
     };
     double y = ycarry;
 #pragma unroll
@@ -317,6 +325,7 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       v[t] = y;
     }
     ycarry = y;
+    if constexpr (kUni) gcarry = lane_value(f[2][0], M - 1);
     double z = 0.0;
 #pragma unroll
     for (int t = M - 1; t >= 0; t--) {
@@ -333,9 +342,8 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
         for (int t = 0; t < M; t++)
           if (t < cnt) zc[t * pstr] = v[t];
       }
-      // first value of the chunk: resolved into the chunk's carry below
-      sigOut[((long)k * n_lines + line) * L + sl] = v[0];
     }
+    zfirst[k][lane] = v[0];  // resolved into the chunk's carry below
     if constexpr (!kUni) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   };
 
@@ -351,28 +359,26 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
     }
   }
   // chunk carries: sigma_{P-1} = 0, sigma_k = zfirst_{k+1} + phi_{(k+1) start} sigma_{k+1}
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (active) {
     gdouble* so = sigOut + (long)line * L + sl;
     const long kstr = (long)n_lines * L;
     const gdouble* ps = phiS + (long)line * P;
     double sigma = 0.0;
-    double zf_next = so[(long)(P - 1) * kstr];
     so[(long)(P - 1) * kstr] = 0.0;
     constexpr int kB = 8;
     for (int k0 = P - 2; k0 >= 0; k0 -= kB) {
-      double zf[kB], ph[kB];
+      double ph[kB];
 #pragma unroll
       for (int u = 0; u < kB; u++) {
         const int k = k0 - u;
-        zf[u] = k >= 0 ? so[(long)k * kstr] : 0.0;
         ph[u] = k >= 0 ? ps[k + 1] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < kB; u++) {
         const int k = k0 - u;
         if (k >= 0) {
-          sigma = fma(ph[u], sigma, zf_next);
-          zf_next = zf[u];
+          sigma = fma(ph[u], sigma, zfirst[k + 1][lane]);
           so[(long)k * kstr] = sigma;
         }
       }
@@ -395,7 +401,7 @@ __device__ __forceinline__ void line_solve_scan(double (&v)[NC], const gdouble* 
   for (int c = 0; c < NC; c++) {
     const int p = c * kWave + lane;
     const bool ok = p < n;
-    double a = ok ? E[p] : 1.0, b = ok ? v[c] : 0.0;
+    double a = ok ? (p > 0 ? Gf[p - 1] : 0.0) : 1.0, b = ok ? v[c] : 0.0;  // e_p = g_{p-1}
     affine_scan_up(a, b, lane);
     v[c] = fma(a, carry, b);
     carry = lane_value(v[c], kWave - 1);
@@ -524,7 +530,7 @@ __device__ __forceinline__ void line_solve_scan_n(double (&v)[NCMAX], int nc, co
     if (c < nc) {
       const int p = c * kWave + lane;
       const bool ok = p < n;
-      double a = ok ? E[p] : 1.0, b = ok ? v[c] : 0.0;
+      double a = ok ? (p > 0 ? Gf[p - 1] : 0.0) : 1.0, b = ok ? v[c] : 0.0;  // e_p = g_{p-1}
       affine_scan_up(a, b, lane);
       v[c] = fma(a, carry, b);
       carry = lane_value(v[c], kWave - 1);
