@@ -76,7 +76,8 @@ enum { PR_COEF_FACES = 0, PR_COEF_NODAL_LOG = 1 };
  *   n_slices       N_c: coarse intervals, DT = T / N_c
  *   fine_steps     s: fine steps per coarse interval, dt = DT / s
  *   coarse_steps   FIE steps taken by one application of G (>= 1)
- *   fine           PR_FIE (PR_DR is reserved and rejected)
+ *   fine           PR_FIE or PR_DR (the Douglas-Rachford fine propagator needs
+ *                  PR_SPLIT_DIM; the coarse propagator is always FIE)
  *   split          PR_SPLIT_DIM (dim 1 or 2) or PR_SPLIT_DD (dim 1 only)
  *   coef_mode      PR_COEF_FACES: coef_x = ax, coef_y = ay (NULL in 1D)
  *                  PR_COEF_NODAL_LOG: coef_x = theta, coef_y unused
@@ -197,7 +198,8 @@ pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hi
  * states layout, may be NULL) receives the slice-boundary checkpoints of the
  * forward solve. Each FIE step is reversed with the transposed (= same,
  * symmetric) line solves in reverse substep order; the forward states inside
- * a slice are recomputed from its checkpoint. Asynchronous. */
+ * a slice are recomputed from its checkpoint. PR_EUNSUPPORTED for DD, 1D,
+ * Douglas-Rachford or multi-instance handles. Asynchronous. */
 pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, double* grad_u0,
                      double* grad_coef, double* U_ckpt, void* hip_stream);
 

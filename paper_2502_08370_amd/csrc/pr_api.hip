@@ -99,6 +99,7 @@ struct Instance {
   DBuf fxE, fxR, fxG, fyE, fyR, fyG, fxPhiC, fyPhiC, fxPhiS, fyPhiS;
   DBuf cxE, cxR, cxG, cyE, cyR, cyG;
   DBuf Z, sigX, sigY, tmp;
+  DBuf drS;  // Douglas-Rachford stencil values, shaped like Z
   // domain decomposition (1D)
   int n_colors = 0;
   std::vector<int> seg_off;   // colour k's segments: [seg_off[k], seg_off[k+1])
@@ -137,12 +138,15 @@ struct pr_problem_s {
   // grouped work lists per lane width L (index log2 L) and direction
   struct Group {
     int L = 0;
+    int dr = 0;                // Douglas-Rachford instances (the sweeps add / subtract S)
+    std::vector<int> members;  // instances of the group
     WorkItem* d_work[2] = {nullptr, nullptr};
     int n_work[2] = {0, 0};
     std::vector<int> pass_off[2];  // items of pass q: [pass_off[q], pass_off[q+1])
   };
   int blocks_per_pass = 0;  // 0: every slice block in every launch
   int n_passes = 1;
+  int pass_blocks = 1 << 30;  // slice blocks per pass in effect
   std::vector<Group> groups;
   // parareal workspace
   DBuf F, Gold;
@@ -192,8 +196,9 @@ pr_status validate(const pr_problem_desc& d, int idx) {
   if (d.n_slices < 1 || d.fine_steps < 1 || d.coarse_steps < 1)
     return fail(PR_EINVAL, "instance %d: n_slices, fine_steps, coarse_steps must be >= 1", idx);
   if (d.fine != PR_FIE && d.fine != PR_DR) return fail(PR_EINVAL, "instance %d: bad fine", idx);
-  if (d.fine == PR_DR)
-    return fail(PR_EUNSUPPORTED, "instance %d: Douglas-Rachford fine propagator not built", idx);
+  if (d.fine == PR_DR && d.split != PR_SPLIT_DIM)
+    return fail(PR_EUNSUPPORTED,
+                "instance %d: the Douglas-Rachford fine propagator needs the dimensional split", idx);
   if (d.split != PR_SPLIT_DIM && d.split != PR_SPLIT_DD)
     return fail(PR_EINVAL, "instance %d: bad split", idx);
   if (d.coef_mode != PR_COEF_FACES && d.coef_mode != PR_COEF_NODAL_LOG)
@@ -267,6 +272,17 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   if (d.dim == 2) HIPOK(I.sigY.alloc((size_t)B * nx * Py * L));
   HIPOK(I.tmp.alloc(npts));
   h.Z = I.Z.p; h.sigX = I.sigX.p; h.sigY = I.sigY.p;
+  h.dr = d.fine == PR_DR;
+  h.drS = nullptr;
+  h.ay = I.ay.p;
+  if (h.dr) {
+    // S = dt A_y U with A_y = D_y a D_y - c/2 (the reaction shared by the two terms)
+    HIPOK(I.drS.alloc((size_t)B * npts * L));
+    h.drS = I.drS.p;
+    const double hy = 1.0 / (ny + 1);
+    h.dr_coef = I.dt / (hy * hy);
+    h.dr_react = I.dt * (d.c / 2.0);
+  }
   h.fxE = I.fxE.p; h.fxR = I.fxR.p; h.fxG = I.fxG.p;
   h.fyE = I.fyE.p; h.fyR = I.fyR.p; h.fyG = I.fyG.p;
   h.fxPhiC = I.fxPhiC.p; h.fyPhiC = I.fyPhiC.p; h.fxPhiS = I.fxPhiS.p; h.fyPhiS = I.fyPhiS.p;
@@ -545,12 +561,18 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   for (int q = 0; q < P->n_passes; q++) {
     for (int t = 0; t < smax; t++) {
       for (auto& g : P->groups) {
+        if (g.dr) {  // S = dt A_y U of this step's input
+          PhaseTimer pt(P, PH_FINE, s);
+          for (int i : g.members)
+            HIPOK(launch_dr_stencil(P->d_inst + i, P->inst[i]->h, t > 0, t, q * P->pass_blocks,
+                                    (q + 1) * P->pass_blocks, s));
+        }
         for (int dir = 0; dir < 2; dir++) {
           const int off = g.pass_off[dir][q], cnt = g.pass_off[dir][q + 1] - off;
           if (!cnt) continue;
           PhaseTimer pt(P, PH_FINE, s);
           HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir] + off, cnt, g.L, P->M, dir,
-                                  dir == 1 || t > 0, t, s));
+                                  dir == 1 || t > 0, t, s, g.dr ? (dir == 0 ? 1 : -1) : 0));
         }
       }
     }
@@ -649,12 +671,28 @@ pr_status seq_fine_dim(pr_problem_s* p, int i, const double* u0, double* U, hipS
       const double* src = U + (size_t)k * I.npts;
       double* dst = U + (size_t)(k + 1) * I.npts;
       for (int t = 0; t < I.d.fine_steps; t++) {
+        const double* in = t == 0 ? src : I.tmp.p;
+        const bool last = t + 1 == I.d.fine_steps;
+        if (I.h.dr) {
+          // S = dt A_y U into drS[0, npts), U + S into drS[npts, 2 npts); x solve;
+          // subtract S; y solve
+          double* UpS = I.drS.p + I.npts;
+          {
+            PhaseTimer pt(p, PH_COARSE_X, s);
+            HIPOK(launch_dr_stencil_nat(dI, I.h, in, UpS, 0, s));
+            HIPOK(launch_coarse_x(dI, I.h, UpS, I.tmp.p, true, s));
+            HIPOK(launch_dr_stencil_nat(dI, I.h, nullptr, I.tmp.p, 1, s));
+          }
+          PhaseTimer pt(p, PH_COARSE_Y, s);
+          HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, last ? dst : I.tmp.p, 0, nullptr, nullptr,
+                                nullptr, nullptr, true, s));
+          continue;
+        }
         {
           PhaseTimer pt(p, PH_COARSE_X, s);
-          HIPOK(launch_coarse_x(dI, I.h, t == 0 ? src : I.tmp.p, I.tmp.p, true, s));
+          HIPOK(launch_coarse_x(dI, I.h, in, I.tmp.p, true, s));
         }
         PhaseTimer pt(p, PH_COARSE_Y, s);
-        const bool last = t + 1 == I.d.fine_steps;
         HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, last ? dst : I.tmp.p, 0, nullptr, nullptr, nullptr,
                               nullptr, true, s));
       }
@@ -690,25 +728,29 @@ pr_status build_schedules(pr_problem_s* P) {
     if (!I->dd) Bmax = std::max(Bmax, I->h.B);
   const int bpp = P->blocks_per_pass > 0 ? P->blocks_per_pass : Bmax;
   P->n_passes = (Bmax + bpp - 1) / bpp;
-  for (int L = 1; L <= 64; L <<= 1) {
-    std::vector<int> members;
-    for (int i = 0; i < n; i++)
-      if (!P->inst[i]->dd && P->inst[i]->h.L == L) members.push_back(i);
-    if (members.empty()) continue;
-    pr_problem_s::Group g;
-    g.L = L;
-    for (int dir = 0; dir < 2; dir++) {
-      std::vector<WorkItem> all;
-      g.pass_off[dir].assign(1, 0);
-      for (int q = 0; q < P->n_passes; q++) {
-        std::vector<WorkItem> part = build_work(members, P->inst, dir, P->M, q * bpp, (q + 1) * bpp);
-        all.insert(all.end(), part.begin(), part.end());
-        g.pass_off[dir].push_back((int)all.size());
+  P->pass_blocks = bpp;
+  for (int L = 1; L <= 64; L <<= 1)
+    for (int dr = 0; dr < 2; dr++) {
+      std::vector<int> members;
+      for (int i = 0; i < n; i++)
+        if (!P->inst[i]->dd && P->inst[i]->h.L == L && P->inst[i]->h.dr == dr) members.push_back(i);
+      if (members.empty()) continue;
+      pr_problem_s::Group g;
+      g.L = L;
+      g.dr = dr;
+      g.members = members;
+      for (int dir = 0; dir < 2; dir++) {
+        std::vector<WorkItem> all;
+        g.pass_off[dir].assign(1, 0);
+        for (int q = 0; q < P->n_passes; q++) {
+          std::vector<WorkItem> part = build_work(members, P->inst, dir, P->M, q * bpp, (q + 1) * bpp);
+          all.insert(all.end(), part.begin(), part.end());
+          g.pass_off[dir].push_back((int)all.size());
+        }
+        HIPOK(upload_work(all, &g.d_work[dir], &g.n_work[dir]));
       }
-      HIPOK(upload_work(all, &g.d_work[dir], &g.n_work[dir]));
+      P->groups.push_back(g);
     }
-    P->groups.push_back(g);
-  }
   P->Nmax = 0;
   P->csmax = 0;
   P->max_ny = 1;
@@ -1136,6 +1178,8 @@ pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, dou
   Instance& I = *p->inst[0];
   if (I.dd || I.d.dim != 2)
     return fail(PR_EUNSUPPORTED, "pr_adjoint supports 2D dimensional splitting");
+  if (I.d.fine != PR_FIE)
+    return fail(PR_EUNSUPPORTED, "pr_adjoint supports the FIE fine propagator only");
   hipStream_t s = as_stream(hip_stream);
   const int nx = I.d.nx, ny = I.d.ny, N = I.d.n_slices, S = I.d.fine_steps;
   const size_t npts = I.npts;

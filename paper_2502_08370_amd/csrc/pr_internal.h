@@ -60,6 +60,13 @@ struct DimInst {
   long npts;         // nx*ny
   long off_slices, off_states;  // offsets of the instance in packed buffers
   const int* active; // per-instance flags (0: converged, skipped by every kernel)
+  // Douglas-Rachford fine propagator (eq. DR_method): S = dt A_y U of the step's
+  // input, stored like Z; the x sweep adds it on load, the y sweep subtracts it
+  int dr;
+  double* drS;       // [B][ny][nx][L]
+  const double* ay;  // y-face coefficients [(ny+1)][nx]
+  double dr_coef;    // dt / h_y^2
+  double dr_react;   // dt * c / 2
 };
 
 // Work item of a batched coarse launch: instance and line block.
@@ -165,8 +172,18 @@ hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const 
 // with_corr = false: plain transpose (no pending chunk correction).
 hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, double* F_out,
                                    bool with_corr, hipStream_t s);
+// sgn = +1 / -1: add / subtract the instance's DR array on load (0: FIE).
 hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
-                             int M, int dir, int has_prev, int step, hipStream_t s);
+                             int M, int dir, int has_prev, int step, hipStream_t s, int sgn = 0);
+// S = dt A_y U on the slice-interleaved workspace (U with the pending y-sweep
+// correction when has_prev) of one instance, slice blocks [b_lo, b_hi), before
+// fine step `step` (nothing once the instance has finished its steps).
+hipError_t launch_dr_stencil(const DimInst* d_inst, const DimInst& h, int has_prev, int step,
+                             int b_lo, int b_hi, hipStream_t s);
+// Natural-layout DR helpers for one state: S = dt A_y U and out = U + S (mode 0);
+// out = out - S (mode 1).
+hipError_t launch_dr_stencil_nat(const DimInst* d_inst, const DimInst& h, const double* U,
+                                 double* out, int mode, hipStream_t s);
 // Exact line solves of one state, one wave per line (lines <= kMaxCoarseLine).
 // fine = false uses the coarse factorisation, fine = true the fine one.
 hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
@@ -174,7 +191,7 @@ hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double
 // Largest grid extent the coarse sweeps handle (whole line per wave, 64-point chunks).
 constexpr int kMaxCoarseLine = 1024;
 constexpr int kCoarseRowsPerBlock = 4;    // x lines per block of the coarse x kernels
-constexpr int kCoarseColsPerBlock = 16;   // y lines per block of the coarse y kernels
+constexpr int kCoarseColsPerBlock = 8;    // y lines per block of the coarse y kernels
 // Batched coarse sweep: one launch covers every instance's slice n (items of
 // instances with n < N and still active). step c of the instance's coarse
 // propagation: c == 0 reads U[n] from U_base, later steps the instance's tmp;

@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kWave) void k_from_interleaved(const DimInst* __res
 // A partial last chunk is computed in full on clamped loads: the line's last
 // back-substitution factor is 0, so the padded positions cannot leak into the
 // real ones, and only real positions are stored.
-template <int L, int M, int DIR, bool HP>
+template <int L, int M, int DIR, bool HP, int SGN = 0>
 __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict__ insts,
                                                       const WorkItem* __restrict__ work,
                                                       int step) {
@@ -249,24 +249,47 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   gdouble* zbase = gp(I.Z) + w.b * I.slab + (long)lc * lstr + sl;
   const long frow = (long)line0 * n_pos;  // line-uniform factor row when kUni
 
+  // With one line per wave the row pointers are wave-uniform: keep them apart
+  // from the per-lane slice offset so addresses are scalar base + lane offset.
+  const gdouble* zrow_u = gp(I.Z) + w.b * I.slab + (long)line0 * lstr;
+  const gdouble* sgrow_u = sigPrev + ((long)(line0 / M) * nl_prev) * L;
+  const unsigned usl = (unsigned)sl;  // lane offset (unsigned: scalar-base addressing)
+  // DR: the stencil array lives at the same offsets as Z
+  const long drOff = SGN != 0 ? (long)(I.drS - I.Z) : 0;
   auto issue = [&](double (&v)[M], double (&sg)[M], double (&f)[4][NQ], int k) {
     const int p0 = k * M;
     const int cnt = min(M, n_pos - p0);
-    const gdouble* zc = zbase + (long)p0 * pstr;
-    const gdouble* sc = sgRow + (long)p0 * L;
-    if (cnt == M) {
-#pragma unroll
-      for (int t = 0; t < M; t++) v[t] = zc[t * pstr];
-      if constexpr (HP) {
-#pragma unroll
-        for (int t = 0; t < M; t++) sg[t] = sc[t * L];
-      }
-    } else {
+    if constexpr (kUni) {
+      const gdouble* zc = zrow_u + (long)p0 * pstr;
+      const gdouble* sc = sgrow_u + (long)p0 * L;
 #pragma unroll
       for (int t = 0; t < M; t++) {
-        const int tt = t < cnt ? t : 0;
-        v[t] = zc[tt * pstr];
-        if constexpr (HP) sg[t] = sc[tt * L];
+        const int tt = (cnt == M || t < cnt) ? t : 0;
+        v[t] = (zc + (long)tt * pstr)[usl];
+        if constexpr (SGN != 0) v[t] = fma((double)SGN, (zc + drOff + (long)tt * pstr)[usl], v[t]);
+        if constexpr (HP) sg[t] = (sc + (long)tt * L)[usl];
+      }
+    } else {
+      const gdouble* zc = zbase + (long)p0 * pstr;
+      const gdouble* sc = sgRow + (long)p0 * L;
+      if (cnt == M) {
+#pragma unroll
+        for (int t = 0; t < M; t++) {
+          v[t] = zc[t * pstr];
+          if constexpr (SGN != 0) v[t] = fma((double)SGN, zc[drOff + t * pstr], v[t]);
+        }
+        if constexpr (HP) {
+#pragma unroll
+          for (int t = 0; t < M; t++) sg[t] = sc[t * L];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < M; t++) {
+          const int tt = t < cnt ? t : 0;
+          v[t] = zc[tt * pstr];
+          if constexpr (SGN != 0) v[t] = fma((double)SGN, zc[drOff + tt * pstr], v[t]);
+          if constexpr (HP) sg[t] = sc[tt * L];
+        }
       }
     }
     if constexpr (kUni) {
@@ -332,7 +355,17 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       z = fma(fac(2, t), z, fac(1, t) * v[t]);
       v[t] = z;
     }
-    if (active) {
+    if constexpr (kUni) {
+      gdouble* zc = (gdouble*)zrow_u + (long)p0 * pstr;
+      if (cnt == M) {
+#pragma unroll
+        for (int t = 0; t < M; t++) (zc + (long)t * pstr)[usl] = v[t];
+      } else {
+#pragma unroll
+        for (int t = 0; t < M; t++)
+          if (t < cnt) (zc + (long)t * pstr)[usl] = v[t];
+      }
+    } else if (active) {
       gdouble* zc = zbase + (long)p0 * pstr;
       if (cnt == M) {
 #pragma unroll
@@ -388,34 +421,72 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
 
 // -------------------------------------------------------- coarse sweeps ---
 // One state (natural layout). Each line is solved exactly by one wave: lane l
-// owns positions 64c + l of the line (c = 0..NC-1), the forward elimination
-// and the back substitution run as affine scans across the lanes (64
-// positions per step) and the line stays in registers between the two.
+// owns the K consecutive positions lK .. lK+K-1 (K*64 >= line length). The
+// forward elimination y_p = e_p y_{p-1} + d_p and the back substitution
+// x_p = g_p x_{p+1} + r_p y_p are affine recurrences: each lane composes its K
+// maps, one inclusive scan of the 64 lane maps across the wave gives every lane
+// its incoming value, and each lane re-runs its K steps from it. The line stays
+// in registers between the two passes.
 
-template <int NC>
-__device__ __forceinline__ void line_solve_scan(double (&v)[NC], const gdouble* E,
-                                                const gdouble* R, const gdouble* Gf, int n,
-                                                int lane) {
-  double carry = 0.0;
+// positions per lane: the smallest power of two with 64 K >= n
+__device__ __forceinline__ int chunks_pow2_dev(int n) {
+  const int c = (n + kWave - 1) / kWave;
+  int p = 1;
+  while (p < c) p <<= 1;
+  return p;
+}
+
+template <int KMAX>
+__device__ __forceinline__ void line_solve_blocked(double (&v)[KMAX], int K, const gdouble* R,
+                                                   const gdouble* Gf, int n, int lane) {
+  const int p0 = lane * K;
+  double gq[KMAX], rq[KMAX], eq[KMAX];
 #pragma unroll
-  for (int c = 0; c < NC; c++) {
-    const int p = c * kWave + lane;
-    const bool ok = p < n;
-    double a = ok ? (p > 0 ? Gf[p - 1] : 0.0) : 1.0, b = ok ? v[c] : 0.0;  // e_p = g_{p-1}
-    affine_scan_up(a, b, lane);
-    v[c] = fma(a, carry, b);
-    carry = lane_value(v[c], kWave - 1);
+  for (int t = 0; t < KMAX; t++) {
+    if (t < K) {
+      const int p = p0 + t;
+      const bool ok = p < n;
+      gq[t] = ok ? Gf[p] : 0.0;
+      rq[t] = ok ? R[p] : 0.0;
+      eq[t] = ok ? (p > 0 ? Gf[p - 1] : 0.0) : 1.0;  // e_p = g_{p-1}; identity past the end
+      if (!ok) v[t] = 0.0;
+    }
   }
-  carry = 0.0;
+  // forward elimination
+  double A = 1.0, B = 0.0;
 #pragma unroll
-  for (int c = NC - 1; c >= 0; c--) {
-    const int p = c * kWave + lane;
-    const bool ok = p < n;
-    double a = ok ? Gf[p] : 0.0, b = ok ? R[p] * v[c] : 0.0;
-    affine_scan_down(a, b, lane);
-    v[c] = fma(a, carry, b);
-    carry = lane_value(v[c], 0);
-  }
+  for (int t = 0; t < KMAX; t++)
+    if (t < K) {
+      B = fma(eq[t], B, v[t]);
+      A = eq[t] * A;
+    }
+  affine_scan_up(A, B, lane);
+  double y = __shfl_up(B, 1, kWave);  // value just before the lane's first position
+  if (lane == 0) y = 0.0;
+#pragma unroll
+  for (int t = 0; t < KMAX; t++)
+    if (t < K) {
+      y = fma(eq[t], y, v[t]);
+      v[t] = y;
+    }
+  // back substitution
+  A = 1.0;
+  B = 0.0;
+#pragma unroll
+  for (int t = KMAX - 1; t >= 0; t--)
+    if (t < K) {
+      B = fma(gq[t], B, rq[t] * v[t]);
+      A = gq[t] * A;
+    }
+  affine_scan_down(A, B, lane);
+  double x = __shfl_down(B, 1, kWave);  // value just after the lane's last position
+  if (lane == kWave - 1) x = 0.0;
+#pragma unroll
+  for (int t = KMAX - 1; t >= 0; t--)
+    if (t < K) {
+      x = fma(gq[t], x, rq[t] * v[t]);
+      v[t] = x;
+    }
 }
 
 constexpr int kRowsPerBlock = kCoarseRowsPerBlock;
@@ -434,19 +505,22 @@ __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_x(
   double v[NC];
 #pragma unroll
   for (int c = 0; c < NC; c++) {
-    int p = c * kWave + lane;
+    int p = lane * NC + c;
     v[c] = p < nx ? src[base + p] : 0.0;
   }
-  line_solve_scan<NC>(v, gp(FE) + base, gp(FR) + base, gp(FG) + base, nx, lane);
+  line_solve_blocked<NC>(v, NC, gp(FR) + base, gp(FG) + base, nx, lane);
 #pragma unroll
   for (int c = 0; c < NC; c++) {
-    int p = c * kWave + lane;
+    int p = lane * NC + c;
     if (p < nx) dst[base + p] = v[c];
   }
 }
 
 constexpr int kColsPerBlock = kCoarseColsPerBlock;
 constexpr int kTS = kColsPerBlock + 1;  // padded LDS row stride
+// staged elements per thread: a column block of the longest line
+constexpr int kStageIt = (kMaxCoarseLine * kColsPerBlock + kWave * kColsPerBlock - 1) /
+                         (kWave * kColsPerBlock);
 
 // y-lines (columns): a block of 16 columns is staged in LDS through
 // 128-byte row segments, each wave solves one column, and the result is
@@ -466,10 +540,21 @@ __global__ __launch_bounds__(kWave* kColsPerBlock) void k_coarse_y(
   const int lane = tid & (kWave - 1), wv = tid >> 6;
   const int i0 = blockIdx.x * kColsPerBlock;
   const int total = ny * kColsPerBlock;
-  for (int q = tid; q < total; q += kWave * kColsPerBlock) {
-    int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
-    int i = i0 + c;
-    T[j * kTS + c] = i < nx ? src[(long)j * nx + i] : 0.0;
+  {
+    double st[kStageIt];
+#pragma unroll
+    for (int u = 0; u < kStageIt; u++) {
+      const int q = tid + u * kWave * kColsPerBlock;
+      const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+      const int i = i0 + c;
+      st[u] = (q < total && i < nx) ? src[(long)j * nx + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageIt; u++) {
+      const int q = tid + u * kWave * kColsPerBlock;
+      const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+      if (q < total) T[j * kTS + c] = st[u];
+    }
   }
   __syncthreads();
   const int col = i0 + wv;
@@ -477,14 +562,14 @@ __global__ __launch_bounds__(kWave* kColsPerBlock) void k_coarse_y(
     double v[NC];
 #pragma unroll
     for (int c = 0; c < NC; c++) {
-      int p = c * kWave + lane;
+      int p = lane * NC + c;
       v[c] = p < ny ? T[p * kTS + wv] : 0.0;
     }
     const long lb = (long)col * ny;
-    line_solve_scan<NC>(v, gp(FE) + lb, gp(FR) + lb, gp(FG) + lb, ny, lane);
+    line_solve_blocked<NC>(v, NC, gp(FR) + lb, gp(FG) + lb, ny, lane);
 #pragma unroll
     for (int c = 0; c < NC; c++) {
-      int p = c * kWave + lane;
+      int p = lane * NC + c;
       if (p < ny) T[p * kTS + wv] = v[c];
     }
   }
@@ -521,36 +606,6 @@ __global__ __launch_bounds__(kWave* kColsPerBlock) void k_coarse_y(
 // different lengths, so the chunk count is a per-block runtime value (<= NCMAX).
 
 template <int NCMAX>
-__device__ __forceinline__ void line_solve_scan_n(double (&v)[NCMAX], int nc, const gdouble* E,
-                                                  const gdouble* R, const gdouble* Gf, int n,
-                                                  int lane) {
-  double carry = 0.0;
-#pragma unroll
-  for (int c = 0; c < NCMAX; c++) {
-    if (c < nc) {
-      const int p = c * kWave + lane;
-      const bool ok = p < n;
-      double a = ok ? (p > 0 ? Gf[p - 1] : 0.0) : 1.0, b = ok ? v[c] : 0.0;  // e_p = g_{p-1}
-      affine_scan_up(a, b, lane);
-      v[c] = fma(a, carry, b);
-      carry = lane_value(v[c], kWave - 1);
-    }
-  }
-  carry = 0.0;
-#pragma unroll
-  for (int c = NCMAX - 1; c >= 0; c--) {
-    if (c < nc) {
-      const int p = c * kWave + lane;
-      const bool ok = p < n;
-      double a = ok ? Gf[p] : 0.0, b = ok ? R[p] * v[c] : 0.0;
-      affine_scan_down(a, b, lane);
-      v[c] = fma(a, carry, b);
-      carry = lane_value(v[c], 0);
-    }
-  }
-}
-
-template <int NCMAX>
 __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_xb(
     const DimInst* __restrict__ insts, const LineItem* __restrict__ items, int n, int c,
     const double* __restrict__ U_base) {
@@ -565,18 +620,18 @@ __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_xb(
   const gdouble* src = c == 0 ? gp(U_base) + I.off_states + (long)n * I.npts : gp(I.tmp);
   gdouble* dst = gp(I.tmp);
   const long base = (long)row * nx;
-  const int nc = (nx + kWave - 1) / kWave;
+  const int K = chunks_pow2_dev(nx);
   double v[NCMAX];
 #pragma unroll
   for (int cc = 0; cc < NCMAX; cc++) {
-    const int p = cc * kWave + lane;
-    v[cc] = (cc < nc && p < nx) ? src[base + p] : 0.0;
+    const int p = lane * K + cc;
+    v[cc] = (cc < K && p < nx) ? src[base + p] : 0.0;
   }
-  line_solve_scan_n<NCMAX>(v, nc, gp(I.cxE) + base, gp(I.cxR) + base, gp(I.cxG) + base, nx, lane);
+  line_solve_blocked<NCMAX>(v, K, gp(I.cxR) + base, gp(I.cxG) + base, nx, lane);
 #pragma unroll
   for (int cc = 0; cc < NCMAX; cc++) {
-    const int p = cc * kWave + lane;
-    if (cc < nc && p < nx) dst[base + p] = v[cc];
+    const int p = lane * K + cc;
+    if (cc < K && p < nx) dst[base + p] = v[cc];
   }
 }
 
@@ -596,27 +651,39 @@ __global__ __launch_bounds__(kWave* kColsPerBlock) void k_coarse_yb(
   const int i0 = it.block * kColsPerBlock;
   const int total = ny * kColsPerBlock;
   const gdouble* src = gp(I.tmp);
-  for (int q = tid; q < total; q += kWave * kColsPerBlock) {
-    int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
-    int i = i0 + cc;
-    T[j * kTS + cc] = i < nx ? src[(long)j * nx + i] : 0.0;
+  {
+    // all loads in flight before the first LDS store
+    double st[kStageIt];
+#pragma unroll
+    for (int u = 0; u < kStageIt; u++) {
+      const int q = tid + u * kWave * kColsPerBlock;
+      const int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
+      const int i = i0 + cc;
+      st[u] = (q < total && i < nx) ? src[(long)j * nx + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageIt; u++) {
+      const int q = tid + u * kWave * kColsPerBlock;
+      const int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
+      if (q < total) T[j * kTS + cc] = st[u];
+    }
   }
   __syncthreads();
   const int col = i0 + wv;
   if (col < nx) {
-    const int nc = (ny + kWave - 1) / kWave;
+    const int K = chunks_pow2_dev(ny);
     double v[NCMAX];
 #pragma unroll
     for (int cc = 0; cc < NCMAX; cc++) {
-      int p = cc * kWave + lane;
-      v[cc] = (cc < nc && p < ny) ? T[p * kTS + wv] : 0.0;
+      int p = lane * K + cc;
+      v[cc] = (cc < K && p < ny) ? T[p * kTS + wv] : 0.0;
     }
     const long lb = (long)col * ny;
-    line_solve_scan_n<NCMAX>(v, nc, gp(I.cyE) + lb, gp(I.cyR) + lb, gp(I.cyG) + lb, ny, lane);
+    line_solve_blocked<NCMAX>(v, K, gp(I.cyR) + lb, gp(I.cyG) + lb, ny, lane);
 #pragma unroll
     for (int cc = 0; cc < NCMAX; cc++) {
-      int p = cc * kWave + lane;
-      if (cc < nc && p < ny) T[p * kTS + wv] = v[cc];
+      int p = lane * K + cc;
+      if (cc < K && p < ny) T[p * kTS + wv] = v[cc];
     }
   }
   __syncthreads();
@@ -626,23 +693,51 @@ __global__ __launch_bounds__(kWave* kColsPerBlock) void k_coarse_yb(
   gdouble* Gn = gp(G_base) + I.off_slices + (long)n * I.npts;
   gdouble* Un = gp(U_base) + I.off_states + (long)(n + 1) * I.npts;
   unsigned long long mx = 0;
-  for (int q = tid; q < total; q += kWave * kColsPerBlock) {
-    int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
-    int i = i0 + cc;
-    if (i >= nx) continue;
-    long idx = (long)j * nx + i;
-    double g = T[j * kTS + cc];
-    if (md == 0) {
-      tmpw[idx] = g;
-    } else if (md == 2) {
-      Un[idx] = g;
-      Gn[idx] = g;
-    } else {
-      double un = Fn[idx] + (g - Gn[idx]);
-      unsigned long long bits = abs_bits(un - Un[idx]);
-      mx = bits > mx ? bits : mx;
-      Un[idx] = un;
-      Gn[idx] = g;
+  if (md == 1) {
+    // correction: all loads of F, G_old and the old U in flight before use
+    double fv[kStageIt], gv[kStageIt], uv[kStageIt];
+#pragma unroll
+    for (int u = 0; u < kStageIt; u++) {
+      const int q = tid + u * kWave * kColsPerBlock;
+      const int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
+      const int i = i0 + cc;
+      const bool ok = q < total && i < nx;
+      const long idx = ok ? (long)j * nx + i : 0;
+      fv[u] = ok ? Fn[idx] : 0.0;
+      gv[u] = ok ? Gn[idx] : 0.0;
+      uv[u] = ok ? Un[idx] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageIt; u++) {
+      const int q = tid + u * kWave * kColsPerBlock;
+      const int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
+      const int i = i0 + cc;
+      if (q < total && i < nx) {
+        const long idx = (long)j * nx + i;
+        const double g = T[j * kTS + cc];
+        const double un = fv[u] + (g - gv[u]);
+        const unsigned long long bits = abs_bits(un - uv[u]);
+        mx = bits > mx ? bits : mx;
+        Un[idx] = un;
+        Gn[idx] = g;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < kStageIt; u++) {
+      const int q = tid + u * kWave * kColsPerBlock;
+      const int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
+      const int i = i0 + cc;
+      if (q < total && i < nx) {
+        const long idx = (long)j * nx + i;
+        const double g = T[j * kTS + cc];
+        if (md == 0) {
+          tmpw[idx] = g;
+        } else {
+          Un[idx] = g;
+          Gn[idx] = g;
+        }
+      }
     }
   }
   if (md == 1) {
@@ -655,6 +750,61 @@ __global__ void k_mask_update(const double* __restrict__ inc, int* __restrict__ 
                               double tol) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n && active[i] && inc[i] < tol) active[i] = 0;
+}
+
+// ------------------------------------------------------ Douglas-Rachford ---
+// S = dt A_y U (eq. DR_method needs the split operators applied to the step's
+// input): (A_y U)_j = [a_{j+1}(U_{j+1} - U_j) - a_j(U_j - U_{j-1})]/h^2 - (c/2) U_j,
+// U = 0 outside the grid. On the interleaved workspace the input values carry the
+// pending correction of the previous y sweep, added here for all three rows.
+__global__ void k_dr_stencil(const DimInst* __restrict__ insts, int has_prev, int step, int b_lo,
+                             int b_hi) {
+  const DimInst& I = insts[0];
+  if (step >= I.steps) return;  // this instance has finished its fine steps
+  if (I.active && !I.active[I.idx]) return;
+  const int nx = I.nx, ny = I.ny, L = I.L, M = I.M, Py = I.Py;
+  const long total = (long)(b_hi - b_lo) * I.slab;
+  const long t0 = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t0 >= total) return;
+  const long t = t0 + (long)b_lo * I.slab;
+  const int l = (int)(t % L);
+  const long node = t / L;
+  const int b = (int)(node / ((long)nx * ny));
+  const long rem = node - (long)b * nx * ny;
+  const int j = (int)(rem / nx), i = (int)(rem - (long)j * nx);
+  const gdouble* Zb = gp(I.Z) + b * I.slab;
+  const gdouble* sig = gp(I.sigY) + (long)b * Py * nx * L;
+  auto val = [&](int jj) -> double {
+    if (jj < 0 || jj >= ny) return 0.0;
+    double z = Zb[((long)jj * nx + i) * L + l];
+    if (has_prev)
+      z = fma(gp(I.fyPhiC)[(long)jj * nx + i], sig[((long)(jj / M) * nx + i) * L + l], z);
+    return z;
+  };
+  const double um = val(j - 1), u0 = val(j), up = val(j + 1);
+  const double aw = gp(I.ay)[(long)j * nx + i], ae = gp(I.ay)[(long)(j + 1) * nx + i];
+  gp(I.drS)[t] = I.dr_coef * (ae * (up - u0) - aw * (u0 - um)) - I.dr_react * u0;
+}
+
+// Natural layout, one state: mode 0: S = dt A_y U, out = U + S; mode 1: out -= S.
+__global__ void k_dr_stencil_nat(const DimInst* __restrict__ insts, const double* __restrict__ U,
+                                 double* __restrict__ out, int mode) {
+  const DimInst& I = insts[0];
+  const int nx = I.nx, ny = I.ny;
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= (long)nx * ny) return;
+  gdouble* S = gp(I.drS);  // the first state's worth of the DR buffer
+  if (mode == 1) {
+    out[t] = out[t] - S[t];
+    return;
+  }
+  const int j = (int)(t / nx), i = (int)(t - (long)j * nx);
+  const double u0 = U[t];
+  const double um = j > 0 ? U[t - nx] : 0.0, up = j + 1 < ny ? U[t + nx] : 0.0;
+  const double aw = gp(I.ay)[(long)j * nx + i], ae = gp(I.ay)[(long)(j + 1) * nx + i];
+  const double sv = I.dr_coef * (ae * (up - u0) - aw * (u0 - um)) - I.dr_react * u0;
+  S[t] = sv;
+  out[t] = u0 + sv;
 }
 
 __global__ void k_fill_zero(double* __restrict__ p, size_t n) {
@@ -720,17 +870,23 @@ hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, doub
   return hipGetLastError();
 }
 
-template <int L, int M, int DIR, bool HP>
+template <int L, int M, int DIR, bool HP, int SGN = 0>
 static hipError_t launch_sweep_t(const DimInst* d_insts, const WorkItem* d_work, int n_work,
                                  int step, hipStream_t s) {
-  hipLaunchKernelGGL((k_fine_sweep<L, M, DIR, HP>), dim3(n_work), dim3(kWave), 0, s, d_insts,
+  hipLaunchKernelGGL((k_fine_sweep<L, M, DIR, HP, SGN>), dim3(n_work), dim3(kWave), 0, s, d_insts,
                      d_work, step);
   return hipGetLastError();
 }
 
 template <int L, int M>
 static hipError_t launch_sweep_lm(const DimInst* d_insts, const WorkItem* d_work, int n_work,
-                                  int dir, int has_prev, int step, hipStream_t s) {
+                                  int dir, int has_prev, int step, hipStream_t s, int sgn) {
+  if (sgn != 0) {  // Douglas-Rachford: x adds S, y subtracts it
+    if (dir == 0)
+      return has_prev ? launch_sweep_t<L, M, 0, true, 1>(d_insts, d_work, n_work, step, s)
+                      : launch_sweep_t<L, M, 0, false, 1>(d_insts, d_work, n_work, step, s);
+    return launch_sweep_t<L, M, 1, true, -1>(d_insts, d_work, n_work, step, s);
+  }
   if (dir == 0)
     return has_prev ? launch_sweep_t<L, M, 0, true>(d_insts, d_work, n_work, step, s)
                     : launch_sweep_t<L, M, 0, false>(d_insts, d_work, n_work, step, s);
@@ -740,21 +896,21 @@ static hipError_t launch_sweep_lm(const DimInst* d_insts, const WorkItem* d_work
 
 template <int M>
 static hipError_t launch_sweep_m(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
-                                 int dir, int has_prev, int step, hipStream_t s) {
+                                 int dir, int has_prev, int step, hipStream_t s, int sgn) {
   switch (L) {
-    case 8: return launch_sweep_lm<8, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
-    case 16: return launch_sweep_lm<16, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
-    case 32: return launch_sweep_lm<32, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
-    case 64: return launch_sweep_lm<64, M>(d_insts, d_work, n_work, dir, has_prev, step, s);
+    case 8: return launch_sweep_lm<8, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn);
+    case 16: return launch_sweep_lm<16, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn);
+    case 32: return launch_sweep_lm<32, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn);
+    case 64: return launch_sweep_lm<64, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
-                             int M, int dir, int has_prev, int step, hipStream_t s) {
+                             int M, int dir, int has_prev, int step, hipStream_t s, int sgn) {
   switch (M) {
-    case 16: return launch_sweep_m<16>(d_insts, d_work, n_work, L, dir, has_prev, step, s);
-    case 32: return launch_sweep_m<32>(d_insts, d_work, n_work, L, dir, has_prev, step, s);
+    case 16: return launch_sweep_m<16>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn);
+    case 32: return launch_sweep_m<32>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn);
     default: return hipErrorInvalidValue;
   }
 }
@@ -850,6 +1006,25 @@ hipError_t launch_coarse_yb(const DimInst* d_insts, const LineItem* items, int n
   size_t lds = (size_t)max_ny * kTS * sizeof(double);
   hipLaunchKernelGGL((k_coarse_yb<16>), dim3(n_items), dim3(kWave * kColsPerBlock), lds, s,
                      d_insts, items, n, c, mode, F_base, G_base, U_base, inc_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_dr_stencil(const DimInst* d_inst, const DimInst& h, int has_prev, int step,
+                             int b_lo, int b_hi, hipStream_t s) {
+  b_lo = std::max(0, b_lo);
+  b_hi = std::min(h.B, b_hi);
+  if (b_hi <= b_lo) return hipSuccess;
+  const long total = (long)(b_hi - b_lo) * h.slab;
+  hipLaunchKernelGGL(k_dr_stencil, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d_inst,
+                     has_prev, step, b_lo, b_hi);
+  return hipGetLastError();
+}
+
+hipError_t launch_dr_stencil_nat(const DimInst* d_inst, const DimInst& h, const double* U,
+                                 double* out, int mode, hipStream_t s) {
+  const long total = (long)h.nx * h.ny;
+  hipLaunchKernelGGL(k_dr_stencil_nat, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     d_inst, U, out, mode);
   return hipGetLastError();
 }
 
