@@ -96,8 +96,9 @@ struct Instance {
   // dimensional splitting (and, for DD, the transpose fields nx, ny, N, L, B, slab, Z)
   DimInst h{};       // host mirror of the device descriptor
   DBuf ax, ay, theta;
-  DBuf fxE, fxR, fxG, fyE, fyR, fyG, fxPhiC, fyPhiC, fxPhiS, fyPhiS;
-  DBuf cxE, cxR, cxG, cyE, cyR, cyG;
+  DBuf fxR, fxG, fyR, fyG, fxPhiC, fyPhiC, fxPhiS, fyPhiS;
+  DBuf cxR, cxG, cyR, cyG;
+  DBuf cxRb, cxGb, cyRb, cyGb, fxRb, fxGb, fyRb, fyGb;  // lane-blocked copies
   DBuf Z, sigX, sigY, tmp;
   DBuf drS;  // Douglas-Rachford stencil values, shaped like Z
   // domain decomposition (1D)
@@ -151,12 +152,14 @@ struct pr_problem_s {
   // parareal workspace
   DBuf F, Gold;
   unsigned long long* d_inc = nullptr;
+  unsigned long long* d_incp = nullptr;  // per-column-block increment maxima, all instances
+  size_t n_incp = 0;
   double* h_inc = nullptr;  // pinned
   int* d_active = nullptr;  // per-instance flags read by every kernel
   // batched coarse sweeps: items of slice index n are [xoff[n], xoff[n+1])
   DArr<LineItem> xitems, yitems;
   std::vector<int> xoff, yoff;
-  int Nmax = 0, csmax = 0, max_ny = 1;
+  int Nmax = 0, csmax = 0, max_nx = 1, max_ny = 1;
   bool any_dd = false;
   // captured parareal correction
   bool use_graph = true;
@@ -176,6 +179,7 @@ struct pr_problem_s {
       for (auto* w : g.d_work)
         if (w) (void)hipFree(w);
     if (d_inc) (void)hipFree(d_inc);
+    if (d_incp) (void)hipFree(d_incp);
     if (h_inc) (void)hipHostFree(h_inc);
     for (auto& r : recs) {
       (void)hipEventDestroy(r.a);
@@ -249,13 +253,19 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   pr_status st = PR_OK;
   (void)st;
   const int Px = (nx + M - 1) / M, Py = (ny + M - 1) / M;
-  HIPOK(I.fxE.alloc(npts)); HIPOK(I.fxR.alloc(npts)); HIPOK(I.fxG.alloc(npts));
-  HIPOK(I.cxE.alloc(npts)); HIPOK(I.cxR.alloc(npts)); HIPOK(I.cxG.alloc(npts));
+  HIPOK(I.fxR.alloc(npts)); HIPOK(I.fxG.alloc(npts));
+  HIPOK(I.cxR.alloc(npts)); HIPOK(I.cxG.alloc(npts));
   HIPOK(I.fxPhiC.alloc(npts)); HIPOK(I.fxPhiS.alloc((size_t)ny * Px));
+  const int Kx = positions_per_lane(nx), Ky = positions_per_lane(ny);
+  const size_t nbx = (size_t)ny * 64 * Kx, nby = (size_t)nx * 64 * Ky;
+  HIPOK(I.cxRb.alloc(nbx)); HIPOK(I.cxGb.alloc(nbx));
+  HIPOK(I.fxRb.alloc(nbx)); HIPOK(I.fxGb.alloc(nbx));
   if (d.dim == 2) {
-    HIPOK(I.fyE.alloc(npts)); HIPOK(I.fyR.alloc(npts)); HIPOK(I.fyG.alloc(npts));
-    HIPOK(I.cyE.alloc(npts)); HIPOK(I.cyR.alloc(npts)); HIPOK(I.cyG.alloc(npts));
+    HIPOK(I.fyR.alloc(npts)); HIPOK(I.fyG.alloc(npts));
+    HIPOK(I.cyR.alloc(npts)); HIPOK(I.cyG.alloc(npts));
     HIPOK(I.fyPhiC.alloc(npts)); HIPOK(I.fyPhiS.alloc((size_t)nx * Py));
+    HIPOK(I.cyRb.alloc(nby)); HIPOK(I.cyGb.alloc(nby));
+    HIPOK(I.fyRb.alloc(nby)); HIPOK(I.fyGb.alloc(nby));
   }
   // lanes per slice block: a power of two in [8, 64] (fewer slices are padded)
   const int L = std::min(64, std::max(8, pow2_at_least(N)));
@@ -283,11 +293,12 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
     h.dr_coef = I.dt / (hy * hy);
     h.dr_react = I.dt * (d.c / 2.0);
   }
-  h.fxE = I.fxE.p; h.fxR = I.fxR.p; h.fxG = I.fxG.p;
-  h.fyE = I.fyE.p; h.fyR = I.fyR.p; h.fyG = I.fyG.p;
+  h.fxR = I.fxR.p; h.fxG = I.fxG.p;
+  h.fyR = I.fyR.p; h.fyG = I.fyG.p;
   h.fxPhiC = I.fxPhiC.p; h.fyPhiC = I.fyPhiC.p; h.fxPhiS = I.fxPhiS.p; h.fyPhiS = I.fyPhiS.p;
-  h.cxE = I.cxE.p; h.cxR = I.cxR.p; h.cxG = I.cxG.p;
-  h.cyE = I.cyE.p; h.cyR = I.cyR.p; h.cyG = I.cyG.p;
+  h.Kx = Kx; h.Ky = Ky;
+  h.cxRb = I.cxRb.p; h.cxGb = I.cxGb.p; h.cyRb = I.cyRb.p; h.cyGb = I.cyGb.p;
+  h.fxRb = I.fxRb.p; h.fxGb = I.fxGb.p; h.fyRb = I.fyRb.p; h.fyGb = I.fyGb.p;
   h.tmp = I.tmp.p;
   return PR_OK;
 }
@@ -319,17 +330,21 @@ pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
     jx.face = I.ax.p; jx.n_lines = ny; jx.n_pos = nx;
     jx.face_line_stride = nx + 1; jx.face_pos_stride = 1;
     jx.tau_over_h2 = tau / (hx * hx); jx.react = tau * react;
-    jx.E = coarse ? I.cxE.p : I.fxE.p; jx.R = coarse ? I.cxR.p : I.fxR.p;
+    jx.E = nullptr; jx.R = coarse ? I.cxR.p : I.fxR.p;
     jx.G = coarse ? I.cxG.p : I.fxG.p; jx.pos_major = 0;
     HIPOK(launch_factorize(jx, s));
+    HIPOK(launch_block_factors(jx.R, ny, nx, coarse ? I.cxRb.p : I.fxRb.p, s));
+    HIPOK(launch_block_factors(jx.G, ny, nx, coarse ? I.cxGb.p : I.fxGb.p, s));
     if (d.dim == 2) {
       FactorJob jy{};
       jy.face = I.ay.p; jy.n_lines = nx; jy.n_pos = ny;
       jy.face_line_stride = 1; jy.face_pos_stride = nx;
       jy.tau_over_h2 = tau / (hy * hy); jy.react = tau * react;
-      jy.E = coarse ? I.cyE.p : I.fyE.p; jy.R = coarse ? I.cyR.p : I.fyR.p;
+      jy.E = nullptr; jy.R = coarse ? I.cyR.p : I.fyR.p;
       jy.G = coarse ? I.cyG.p : I.fyG.p; jy.pos_major = 0;
       HIPOK(launch_factorize(jy, s));
+      HIPOK(launch_block_factors(jy.R, nx, ny, coarse ? I.cyRb.p : I.fyRb.p, s));
+      HIPOK(launch_block_factors(jy.G, nx, ny, coarse ? I.cyGb.p : I.fyGb.p, s));
     }
   }
   HIPOK(launch_chunk_phi(I.fxG.p, ny, nx, M, I.fxPhiC.p, I.fxPhiS.p, s));
@@ -532,6 +547,17 @@ std::vector<WorkItem> build_work(const std::vector<int>& members,
   return out;
 }
 
+// Appends `items` to `out` in launch order such that, with workgroups dealt to
+// the 8 XCDs round-robin, each XCD receives a contiguous range of the list
+// (neighbouring line blocks share cache lines).
+void append_xcd_ordered(const std::vector<LineItem>& items, std::vector<LineItem>& out) {
+  const int nb = (int)items.size(), per = nb / 8, rem = nb % 8;
+  for (int bid = 0; bid < nb; bid++) {
+    const int x = bid % 8, r = bid / 8;
+    out.push_back(items[x * per + std::min(x, rem) + r]);
+  }
+}
+
 hipError_t upload_work(const std::vector<WorkItem>& w, WorkItem** d, int* n) {
   *n = (int)w.size();
   if (w.empty()) return hipSuccess;
@@ -593,33 +619,18 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   return PR_OK;
 }
 
-// One coarse propagation G (coarse_steps FIE steps) of state src of instance i,
-// finishing with the y sweep in `mode` (see launch_coarse_y).
-pr_status coarse_apply(pr_problem_s* P, int i, const double* src, int mode, const double* F,
-                       double* Gold, double* Unext, unsigned long long* inc, hipStream_t s) {
+// One coarse propagation G (coarse_steps FIE steps) of state src of DD
+// instance i, followed by the parareal update in `mode` (see launch_update).
+pr_status coarse_apply_dd(pr_problem_s* P, int i, const double* src, int mode, const double* F,
+                          double* Gold, double* Unext, unsigned long long* inc, hipStream_t s) {
   Instance& I = *P->inst[i];
-  const DimInst* dI = P->d_inst + i;
-  if (I.dd) {
-    HIPOK(launch_copy(src, I.tmp.p, I.npts, s));
-    for (int c = 0; c < I.d.coarse_steps; c++) {
-      pr_status st = dd_fie_step(P, I, true, 1, s);
-      if (st != PR_OK) return st;
-    }
-    PhaseTimer pt(P, PH_COARSE_Y, s);
-    HIPOK(launch_update(I.tmp.p, F, Gold, Unext, I.npts, mode, inc, s));
-    return PR_OK;
-  }
+  HIPOK(launch_copy(src, I.tmp.p, I.npts, s));
   for (int c = 0; c < I.d.coarse_steps; c++) {
-    const double* from = c == 0 ? src : I.tmp.p;
-    {
-      PhaseTimer pt(P, PH_COARSE_X, s);
-      HIPOK(launch_coarse_x(dI, I.h, from, I.tmp.p, false, s));
-    }
-    const bool last = c + 1 == I.d.coarse_steps;
-    PhaseTimer pt(P, PH_COARSE_Y, s);
-    HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, I.tmp.p, last ? mode : 0, F, Gold, Unext, inc, false,
-                          s));
+    pr_status st = dd_fie_step(P, I, true, 1, s);
+    if (st != PR_OK) return st;
   }
+  PhaseTimer pt(P, PH_COARSE_Y, s);
+  HIPOK(launch_update(I.tmp.p, F, Gold, Unext, I.npts, mode, inc, s));
   return PR_OK;
 }
 
@@ -641,10 +652,11 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
       double* Unext = U + I.off_states + (size_t)(k + 1) * I.npts;
       double* Gk = Gold + I.off_slices + (size_t)k * I.npts;
       const double* Fk = F ? F + I.off_slices + (size_t)k * I.npts : nullptr;
-      pr_status st = coarse_apply(P, i, Un, F ? 1 : 2, Fk, Gk, Unext, inc + i, s);
+      pr_status st = coarse_apply_dd(P, i, Un, F ? 1 : 2, Fk, Gk, Unext, inc + i, s);
       if (st != PR_OK) return st;
     }
   }
+  if (P->n_incp) HIPOK(launch_fill_zero(reinterpret_cast<double*>(P->d_incp), P->n_incp, s));
   for (int k = 0; k < P->Nmax; k++) {
     const int xb = P->xoff[k], xn = P->xoff[k + 1] - xb;
     const int yb = P->yoff[k], yn = P->yoff[k + 1] - yb;
@@ -655,10 +667,10 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
         HIPOK(launch_coarse_xb(P->d_inst, P->xitems.p + xb, xn, k, c, U, s));
       }
       PhaseTimer pt(P, PH_COARSE_Y, s);
-      HIPOK(launch_coarse_yb(P->d_inst, P->yitems.p + yb, yn, k, c, F ? 1 : 2, F, Gold, U, inc,
-                             P->max_ny, s));
+      HIPOK(launch_coarse_yb(P->d_inst, P->yitems.p + yb, yn, k, c, F ? 1 : 2, F, Gold, U, s));
     }
   }
+  if (P->n_incp) HIPOK(launch_inc_reduce(P->d_inst, n, inc, s));
   return PR_OK;
 }
 
@@ -684,8 +696,7 @@ pr_status seq_fine_dim(pr_problem_s* p, int i, const double* u0, double* U, hipS
             HIPOK(launch_dr_stencil_nat(dI, I.h, nullptr, I.tmp.p, 1, s));
           }
           PhaseTimer pt(p, PH_COARSE_Y, s);
-          HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, last ? dst : I.tmp.p, 0, nullptr, nullptr,
-                                nullptr, nullptr, true, s));
+          HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, last ? dst : I.tmp.p, true, s));
           continue;
         }
         {
@@ -693,8 +704,7 @@ pr_status seq_fine_dim(pr_problem_s* p, int i, const double* u0, double* U, hipS
           HIPOK(launch_coarse_x(dI, I.h, in, I.tmp.p, true, s));
         }
         PhaseTimer pt(p, PH_COARSE_Y, s);
-        HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, last ? dst : I.tmp.p, 0, nullptr, nullptr, nullptr,
-                              nullptr, true, s));
+        HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, last ? dst : I.tmp.p, true, s));
       }
     }
   }
@@ -753,6 +763,7 @@ pr_status build_schedules(pr_problem_s* P) {
     }
   P->Nmax = 0;
   P->csmax = 0;
+  P->max_nx = 1;
   P->max_ny = 1;
   P->any_dd = false;
   for (auto& I : P->inst) {
@@ -762,20 +773,24 @@ pr_status build_schedules(pr_problem_s* P) {
     }
     P->Nmax = std::max(P->Nmax, I->d.n_slices);
     P->csmax = std::max(P->csmax, I->d.coarse_steps);
+    P->max_nx = std::max(P->max_nx, I->d.nx);
     P->max_ny = std::max(P->max_ny, I->d.ny);
   }
   std::vector<LineItem> xi, yi;
   P->xoff.assign(1, 0);
   P->yoff.assign(1, 0);
   for (int k = 0; k < P->Nmax; k++) {
+    std::vector<LineItem> xk, yk;
     for (int i = 0; i < n; i++) {
       const Instance& I = *P->inst[i];
       if (I.dd || I.d.n_slices <= k) continue;
       for (int rb = 0; rb < (I.d.ny + kCoarseRowsPerBlock - 1) / kCoarseRowsPerBlock; rb++)
-        xi.push_back(LineItem{i, rb});
+        xk.push_back(LineItem{i, rb});
       for (int cb = 0; cb < (I.d.nx + kCoarseColsPerBlock - 1) / kCoarseColsPerBlock; cb++)
-        yi.push_back(LineItem{i, cb});
+        yk.push_back(LineItem{i, cb});
     }
+    append_xcd_ordered(xk, xi);
+    append_xcd_ordered(yk, yi);
     P->xoff.push_back((int)xi.size());
     P->yoff.push_back((int)yi.size());
   }
@@ -905,6 +920,21 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
     h.off_slices = (long)P->inst[i]->off_slices;
     h.off_states = (long)P->inst[i]->off_states;
     h.active = P->d_active;
+  }
+  // per-column-block increment maxima of the coarse sweeps
+  for (auto& I : P->inst)
+    if (!I->dd) P->n_incp += (I->d.nx + kCoarseColsPerBlock - 1) / kCoarseColsPerBlock;
+  if (P->n_incp)
+    HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_incp),
+                    P->n_incp * sizeof(unsigned long long)));
+  {
+    size_t o = 0;
+    for (auto& I : P->inst) {
+      I->h.incp = nullptr;
+      if (I->dd) continue;
+      I->h.incp = P->d_incp + o;
+      o += (I->d.nx + kCoarseColsPerBlock - 1) / kCoarseColsPerBlock;
+    }
   }
   {
     pr_status st = set_all_active(P.get(), s);
@@ -1211,15 +1241,13 @@ pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, dou
         HIPOK(launch_coarse_x(dI, I.h, prev, Wst + (size_t)t * npts, true, s));
       }
       PhaseTimer pt(p, PH_COARSE_Y, s);
-      HIPOK(launch_coarse_y(dI, I.h, Wst + (size_t)t * npts, Vst + (size_t)t * npts, 0, nullptr,
-                            nullptr, nullptr, nullptr, true, s));
+      HIPOK(launch_coarse_y(dI, I.h, Wst + (size_t)t * npts, Vst + (size_t)t * npts, true, s));
     }
     // reverse the steps: transposed (= same, symmetric) solves in reverse substep order
     for (int t = S - 1; t >= 0; t--) {
       {
         PhaseTimer pt(p, PH_COARSE_Y, s);
-        HIPOK(launch_coarse_y(dI, I.h, I.adjLam.p, I.adjMu.p, 0, nullptr, nullptr, nullptr,
-                              nullptr, true, s));
+        HIPOK(launch_coarse_y(dI, I.h, I.adjLam.p, I.adjMu.p, true, s));
       }
       HIPOK(launch_face_grad_y(I.adjMu.p, Vst + (size_t)t * npts, nx, ny, cy, I.adjGay.p, s));
       {

@@ -42,18 +42,22 @@ struct DimInst {
   double* sigX;      // [B][Px][ny][L]  chunk carries of the x sweep
   double* sigY;      // [B][Py][nx][L]  chunk carries of the y sweep
   // fine factorisations, line-major: x-line j entry (j*nx + i), y-line i entry (i*ny + j)
-  const double* fxE; const double* fxR; const double* fxG;
-  const double* fyE; const double* fyR; const double* fyG;
+  const double* fxR; const double* fxG;
+  const double* fyR; const double* fyG;
   // phi of the fine sweeps, stored where their consumer reads them:
   //   fxPhiC[i*ny + j]: x-line j, position i (read by y-lines)
   //   fyPhiC[j*nx + i]: y-line i, position j (read by x-lines and the final transpose)
   //   fxPhiS[j*Px + k], fyPhiS[i*Py + k]: phi at the first position of chunk k
   const double* fxPhiC; const double* fyPhiC;
   const double* fxPhiS; const double* fyPhiS;
-  // coarse factorisations, line-major like the fine ones
-  const double* cxE; const double* cxR; const double* cxG;
-  const double* cyE; const double* cyR; const double* cyG;
+  // Lane-blocked factor copies for the one-wave-per-line solvers (coarse
+  // propagator, sequential fine solve, adjoint): line l, position p = lane*K + c
+  // at [l][c][lane], zero past the line end; K = Kx for x-lines, Ky for y-lines.
+  int Kx, Ky;
+  const double* cxRb; const double* cxGb; const double* cyRb; const double* cyGb;
+  const double* fxRb; const double* fxGb; const double* fyRb; const double* fyGb;
   double* tmp;       // one-state scratch of the coarse sweep
+  unsigned long long* incp;  // per-column-block increment maxima of a coarse sweep
   // batch bookkeeping
   int idx;           // instance index in the handle
   int cs;            // coarse steps per coarse propagation
@@ -86,7 +90,7 @@ struct FactorJob {
   long face_line_stride, face_pos_stride;  // in doubles
   double tau_over_h2;  // tau / h^2
   double react;        // tau * c / M added to the diagonal
-  double* E; double* R; double* G;  // outputs
+  double* E; double* R; double* G;  // outputs (E may be NULL)
   int pos_major;       // 0: [line][pos], 1: [pos][line]
   int pad;
 };
@@ -165,6 +169,11 @@ hipError_t launch_faces_from_theta_2d(const double* theta, int nx, int ny, doubl
                                       hipStream_t s);
 hipError_t launch_faces_from_theta_1d(const double* theta, int nx, double* ax, hipStream_t s);
 hipError_t launch_factorize(const FactorJob& job, hipStream_t s);
+// positions per lane K of a line of n points (smallest power of two, 64 K >= n)
+int positions_per_lane(int n);
+// lane-blocked copy [line][c][lane] of line-major factors [line][pos]
+hipError_t launch_block_factors(const double* src, int n_lines, int n_pos, double* dst,
+                                hipStream_t s);
 hipError_t launch_chunk_phi(const double* G, int n_lines, int n_pos, int M, double* phiC,
                             double* phiS, hipStream_t s);
 hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const double* U_in,
@@ -191,26 +200,27 @@ hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double
 // Largest grid extent the coarse sweeps handle (whole line per wave, 64-point chunks).
 constexpr int kMaxCoarseLine = 1024;
 constexpr int kCoarseRowsPerBlock = 4;    // x lines per block of the coarse x kernels
-constexpr int kCoarseColsPerBlock = 8;    // y lines per block of the coarse y kernels
+constexpr int kCoarseColsPerBlock = 4;    // y lines per block of the coarse y kernels
 // Batched coarse sweep: one launch covers every instance's slice n (items of
 // instances with n < N and still active). step c of the instance's coarse
 // propagation: c == 0 reads U[n] from U_base, later steps the instance's tmp;
 // the last step (c == cs-1) applies mode (1: correction + increment, 2:
 // initial guess) to U[n+1] / G_old[n] / F[n], the others write tmp.
+// The mode-1 increment of each instance goes to its partial maxima (incp,
+// zeroed by the caller before the sweep); launch_inc_reduce folds them into
+// inc_bits[instance] after the sweep's last launch.
 hipError_t launch_coarse_xb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
                             int c, const double* U_base, hipStream_t s);
 hipError_t launch_coarse_yb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
                             int c, int mode, const double* F_base, double* G_base, double* U_base,
-                            unsigned long long* inc_bits, int max_ny, hipStream_t s);
+                            hipStream_t s);
+hipError_t launch_inc_reduce(const DimInst* d_insts, int n_inst, unsigned long long* inc_bits,
+                             hipStream_t s);
 // Parareal bookkeeping on the device: inc = 0 for active instances (start of
 // a correction) and active &= !(inc < tol) (end of a correction).
 hipError_t launch_mask_update(const double* inc, int* active, int n, double tol, hipStream_t s);
-// Coarse y sweep. mode 0: write the result to dst; mode 1: parareal update
-// (U_next = F + (g - G_old), G_old = g, increment into inc_bits); mode 2:
-// initial guess (U_next = g, G_old = g).
 hipError_t launch_coarse_y(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
-                           int mode, const double* F, double* G_old, double* U_next,
-                           unsigned long long* inc_bits, bool fine, hipStream_t s);
+                           bool fine, hipStream_t s);
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
 

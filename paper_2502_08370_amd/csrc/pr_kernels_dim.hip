@@ -114,7 +114,7 @@ __global__ void k_factorize(FactorJob job) {
     double r = 1.0 / u;
     double g = (p + 1 < job.n_pos) ? wr * r : 0.0;
     long idx = job.pos_major ? (long)p * job.n_lines + line : (long)line * job.n_pos + p;
-    job.E[idx] = e;
+    if (job.E) job.E[idx] = e;
     job.R[idx] = r;
     job.G[idx] = g;
     r_prev = r;
@@ -142,54 +142,80 @@ __global__ void k_chunk_phi(const double* __restrict__ G, int n_lines, int n_pos
 
 // ------------------------------------------------- interleave transposes ---
 
-// Natural U[slice][j][i] -> Z[b][j][i][l]; one block per (64-column tile, row, block).
-__global__ __launch_bounds__(kWave) void k_to_interleaved(const DimInst* __restrict__ insts,
-                                                          const double* __restrict__ U) {
+// Natural U[slice][j][i] <-> Z[b][j][i][l] through a 64 x 64 LDS tile; one
+// block of kTrWaves waves per (64-column tile, row, slice block). Every load of
+// a thread is issued before its first LDS store.
+constexpr int kTrWaves = 4;
+constexpr int kTrThreads = kTrWaves * kWave;
+constexpr int kTrIt = kWave * kWave / kTrThreads;  // tile entries per thread
+
+__global__ __launch_bounds__(kTrThreads) void k_to_interleaved(const DimInst* __restrict__ insts,
+                                                               const double* __restrict__ U) {
   __shared__ double tile[64][65];
   const DimInst& I = insts[0];
   if (I.active && !I.active[I.idx]) return;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int i0 = blockIdx.x * 64, j = blockIdx.y, b = blockIdx.z;
-  const int L = I.L, nx = I.nx;
+  const int L = I.L, nx = I.nx, lg = 31 - __clz(L);
   const long npts = (long)nx * I.ny;
-  for (int s = 0; s < L; s++) {
-    int slice = b * L + s;
-    int i = i0 + lane;
-    tile[s][lane] = (slice < I.N && i < nx) ? U[slice * npts + (long)j * nx + i] : 0.0;
+  const int i = i0 + lane;
+  double v[kTrIt];
+#pragma unroll
+  for (int u = 0; u < kTrIt; u++) {
+    const int sl = w + kTrWaves * u, slice = b * L + sl;
+    v[u] = (sl < L && slice < I.N && i < nx) ? U[slice * npts + (long)j * nx + i] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kTrIt; u++) {
+    const int sl = w + kTrWaves * u;
+    if (sl < L) tile[sl][lane] = v[u];
   }
   __syncthreads();
   gdouble* Zb = gp(I.Z) + b * I.slab + ((long)j * nx + i0) * L;
-  const int cnt = min(64, nx - i0);
-  for (int q = lane; q < cnt * L; q += kWave) {
-    int t = q / L, s = q - t * L;
-    Zb[q] = tile[s][t];
+  const int n = min(64, nx - i0) * L;
+#pragma unroll
+  for (int u = 0; u < kTrIt; u++) {
+    const int q = tid + kTrThreads * u;
+    if (q < n) Zb[q] = tile[q & (L - 1)][q >> lg];
   }
 }
 
 // Z (+ the pending chunk correction of the last y sweep) -> natural F[slice][j][i].
-__global__ __launch_bounds__(kWave) void k_from_interleaved(const DimInst* __restrict__ insts,
-                                                            double* __restrict__ F, int with_corr) {
+__global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
+    const DimInst* __restrict__ insts, double* __restrict__ F, int with_corr) {
   __shared__ double tile[64][65];
   const DimInst& I = insts[0];
   if (I.active && !I.active[I.idx]) return;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int i0 = blockIdx.x * 64, j = blockIdx.y, b = blockIdx.z;
-  const int L = I.L, nx = I.nx, M = I.M, Py = I.Py;
+  const int L = I.L, nx = I.nx, M = I.M, Py = I.Py, lg = 31 - __clz(L);
   const long npts = (long)nx * I.ny;
   const gdouble* Zb = gp(I.Z) + b * I.slab + ((long)j * nx + i0) * L;
-  const int kj = j / M;
-  const gdouble* sig = gp(I.sigY) + ((long)b * Py + kj) * nx * L;
-  const gdouble* phiC = gp(I.fyPhiC) + (long)j * nx;
-  const int cnt = min(64, nx - i0);
-  for (int q = lane; q < cnt * L; q += kWave) {
-    int t = q / L, s = q - t * L;
-    int i = i0 + t;
-    tile[s][t] = with_corr ? fma(phiC[i], sig[(long)i * L + s], Zb[q]) : Zb[q];
+  const gdouble* sig = with_corr ? gp(I.sigY) + ((long)b * Py + j / M) * nx * L : nullptr;
+  const gdouble* phiC = with_corr ? gp(I.fyPhiC) + (long)j * nx : nullptr;
+  const int n = min(64, nx - i0) * L;
+  double z[kTrIt], ph[kTrIt], sg[kTrIt];
+#pragma unroll
+  for (int u = 0; u < kTrIt; u++) {
+    const int q = tid + kTrThreads * u;
+    const bool ok = q < n;
+    const int t = q >> lg, sl = q & (L - 1);
+    z[u] = ok ? Zb[q] : 0.0;
+    ph[u] = (ok && with_corr) ? phiC[i0 + t] : 0.0;
+    sg[u] = (ok && with_corr) ? sig[(long)(i0 + t) * L + sl] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kTrIt; u++) {
+    const int q = tid + kTrThreads * u;
+    if (q < n) tile[q & (L - 1)][q >> lg] = fma(ph[u], sg[u], z[u]);
   }
   __syncthreads();
-  for (int s = 0; s < L; s++) {
-    int slice = b * L + s;
-    if (slice < I.N && lane < cnt) F[slice * npts + (long)j * nx + i0 + lane] = tile[s][lane];
+  const int cnt = min(64, nx - i0);
+#pragma unroll
+  for (int u = 0; u < kTrIt; u++) {
+    const int sl = w + kTrWaves * u, slice = b * L + sl;
+    if (sl < L && slice < I.N && lane < cnt)
+      F[slice * npts + (long)j * nx + i0 + lane] = tile[sl][lane];
   }
 }
 
@@ -421,12 +447,19 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
 
 // -------------------------------------------------------- coarse sweeps ---
 // One state (natural layout). Each line is solved exactly by one wave: lane l
-// owns the K consecutive positions lK .. lK+K-1 (K*64 >= line length). The
+// owns the K consecutive positions lK .. lK+K-1 (64 K >= line length). The
 // forward elimination y_p = e_p y_{p-1} + d_p and the back substitution
 // x_p = g_p x_{p+1} + r_p y_p are affine recurrences: each lane composes its K
 // maps, one inclusive scan of the 64 lane maps across the wave gives every lane
 // its incoming value, and each lane re-runs its K steps from it. The line stays
 // in registers between the two passes.
+//
+// The factors are read in the lane-blocked layout [line][c][lane] (position
+// lane*K + c; one contiguous 512-byte segment per load). The state moves between
+// its natural layout and the lanes through an LDS line buffer with one pad slot
+// per 16 entries, which keeps both the position-ordered accesses of the global
+// loads and stores and the lane-blocked accesses of the solve free of bank
+// conflicts.
 
 // positions per lane: the smallest power of two with 64 K >= n
 __device__ __forceinline__ int chunks_pow2_dev(int n) {
@@ -436,314 +469,344 @@ __device__ __forceinline__ int chunks_pow2_dev(int n) {
   return p;
 }
 
-template <int KMAX>
-__device__ __forceinline__ void line_solve_blocked(double (&v)[KMAX], int K, const gdouble* R,
-                                                   const gdouble* Gf, int n, int lane) {
-  const int p0 = lane * K;
-  double gq[KMAX], rq[KMAX], eq[KMAX];
+__device__ __forceinline__ int lds_pad(int q) { return q + (q >> 4); }
+
+// doubles of one LDS line buffer for K positions per lane (odd: consecutive
+// buffers start on different banks)
+__host__ __device__ constexpr int line_buf_len(int K) { return 68 * K + 1; }
+
+constexpr int kKMax = kMaxCoarseLine / kWave;  // positions per lane of the longest line
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Every loop below runs all kKMax entries whatever K is: entries t >= K load
+// from a clamped in-range address and are padded with identity maps (e = g = 1,
+// r = 0, value 0), so there is no branch on K between a load and its use and the
+// loads stay in flight together.
+
+// Loads the line's blocked factors (Rb, Gb at the line) into registers.
+__device__ __forceinline__ void load_line_factors(double (&gq)[kKMax], double (&rq)[kKMax], int K,
+                                                  const gdouble* Rb, const gdouble* Gb,
+                                                  int lane) {
 #pragma unroll
-  for (int t = 0; t < KMAX; t++) {
-    if (t < K) {
-      const int p = p0 + t;
-      const bool ok = p < n;
-      gq[t] = ok ? Gf[p] : 0.0;
-      rq[t] = ok ? R[p] : 0.0;
-      eq[t] = ok ? (p > 0 ? Gf[p - 1] : 0.0) : 1.0;  // e_p = g_{p-1}; identity past the end
-      if (!ok) v[t] = 0.0;
-    }
+  for (int t = 0; t < kKMax; t++) {
+    const int tc = t < K ? t : 0;
+    gq[t] = Gb[tc * kWave + lane];
+    rq[t] = Rb[tc * kWave + lane];
   }
-  // forward elimination
+}
+
+// Solves the line whose right-hand side is v (lane-blocked, zero past the line
+// end and for t >= K) in place, with the line's factors from load_line_factors.
+__device__ __forceinline__ void line_solve_lanes(double (&v)[kKMax], int K,
+                                                 const double (&gq)[kKMax],
+                                                 const double (&rq)[kKMax], int lane) {
+  // e_p = g_{p-1}: the lane's previous entry, or the last entry of the lane below
+  double glast = 0.0;
+#pragma unroll
+  for (int t = 0; t < kKMax; t++) glast = t == K - 1 ? gq[t] : glast;
+  double e0 = __shfl_up(glast, 1, kWave);
+  if (lane == 0) e0 = 0.0;
+  double eq[kKMax], gg[kKMax], rr[kKMax];
+#pragma unroll
+  for (int t = 0; t < kKMax; t++) {
+    const bool in = t < K;
+    eq[t] = in ? (t == 0 ? e0 : gq[t - 1]) : 1.0;
+    gg[t] = in ? gq[t] : 1.0;
+    rr[t] = in ? rq[t] : 0.0;
+  }
+  // forward elimination (past the line end g = 0, so those positions stay 0)
   double A = 1.0, B = 0.0;
 #pragma unroll
-  for (int t = 0; t < KMAX; t++)
-    if (t < K) {
-      B = fma(eq[t], B, v[t]);
-      A = eq[t] * A;
-    }
+  for (int t = 0; t < kKMax; t++) {
+    B = fma(eq[t], B, v[t]);
+    A = eq[t] * A;
+  }
   affine_scan_up(A, B, lane);
   double y = __shfl_up(B, 1, kWave);  // value just before the lane's first position
   if (lane == 0) y = 0.0;
 #pragma unroll
-  for (int t = 0; t < KMAX; t++)
-    if (t < K) {
-      y = fma(eq[t], y, v[t]);
-      v[t] = y;
-    }
+  for (int t = 0; t < kKMax; t++) {
+    y = fma(eq[t], y, v[t]);
+    v[t] = y;
+  }
   // back substitution
   A = 1.0;
   B = 0.0;
 #pragma unroll
-  for (int t = KMAX - 1; t >= 0; t--)
-    if (t < K) {
-      B = fma(gq[t], B, rq[t] * v[t]);
-      A = gq[t] * A;
-    }
+  for (int t = kKMax - 1; t >= 0; t--) {
+    B = fma(gg[t], B, rr[t] * v[t]);
+    A = gg[t] * A;
+  }
   affine_scan_down(A, B, lane);
   double x = __shfl_down(B, 1, kWave);  // value just after the lane's last position
   if (lane == kWave - 1) x = 0.0;
 #pragma unroll
-  for (int t = KMAX - 1; t >= 0; t--)
-    if (t < K) {
-      x = fma(gq[t], x, rq[t] * v[t]);
-      v[t] = x;
-    }
+  for (int t = kKMax - 1; t >= 0; t--) {
+    x = fma(gg[t], x, rr[t] * v[t]);
+    v[t] = x;
+  }
+}
+
+// LDS line buffers are sized for the longest line, so every buffer access
+// below stays inside its own buffer for any K.
+constexpr int kLineBuf = line_buf_len(kKMax);
+
+// One row (contiguous, n values): src -> dst (may alias); buf is the wave's
+// LDS line buffer.
+__device__ __forceinline__ void solve_row(const gdouble* src, gdouble* dst, const gdouble* Rb,
+                                          const gdouble* Gb, int n, int K, double* buf,
+                                          int lane) {
+  double v[kKMax], gq[kKMax], rq[kKMax];
+#pragma unroll
+  for (int t = 0; t < kKMax; t++) {
+    const int p = t * kWave + lane;
+    const double x = src[p < n ? p : 0];
+    v[t] = p < n ? x : 0.0;  // p >= n for every t >= K
+  }
+  load_line_factors(gq, rq, K, Rb, Gb, lane);
+#pragma unroll
+  for (int t = 0; t < kKMax; t++) buf[lds_pad(t * kWave + lane)] = v[t];
+  wave_lds_fence();
+#pragma unroll
+  for (int t = 0; t < kKMax; t++) {
+    const double x = buf[lds_pad(lane * K + (t < K ? t : 0))];
+    v[t] = t < K ? x : 0.0;
+  }
+  line_solve_lanes(v, K, gq, rq, lane);
+  wave_lds_fence();
+#pragma unroll
+  for (int t = 0; t < kKMax; t++)
+    if (t < K) buf[lds_pad(lane * K + t)] = v[t];
+  wave_lds_fence();
+#pragma unroll
+  for (int t = 0; t < kKMax; t++) {
+    const int p = t * kWave + lane;
+    if (p < n) dst[p] = buf[lds_pad(p)];
+  }
 }
 
 constexpr int kRowsPerBlock = kCoarseRowsPerBlock;
-
-// x-lines (rows), one wave per row: coalesced along the row.
-template <int NC>
-__global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_x(
-    const DimInst* __restrict__ insts, const double* __restrict__ src, double* __restrict__ dst,
-    const double* __restrict__ FE, const double* __restrict__ FR, const double* __restrict__ FG) {
-  const DimInst& I = insts[0];
-  const int nx = I.nx, ny = I.ny;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int row = blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
-  if (row >= ny) return;  // whole wave
-  const long base = (long)row * nx;
-  double v[NC];
-#pragma unroll
-  for (int c = 0; c < NC; c++) {
-    int p = lane * NC + c;
-    v[c] = p < nx ? src[base + p] : 0.0;
-  }
-  line_solve_blocked<NC>(v, NC, gp(FR) + base, gp(FG) + base, nx, lane);
-#pragma unroll
-  for (int c = 0; c < NC; c++) {
-    int p = lane * NC + c;
-    if (p < nx) dst[base + p] = v[c];
-  }
-}
-
 constexpr int kColsPerBlock = kCoarseColsPerBlock;
-constexpr int kTS = kColsPerBlock + 1;  // padded LDS row stride
+constexpr int kColThreads = kWave * kColsPerBlock;
 // staged elements per thread: a column block of the longest line
-constexpr int kStageIt = (kMaxCoarseLine * kColsPerBlock + kWave * kColsPerBlock - 1) /
-                         (kWave * kColsPerBlock);
+constexpr int kStageIt = (kMaxCoarseLine * kColsPerBlock + kColThreads - 1) / kColThreads;
 
-// y-lines (columns): a block of 16 columns is staged in LDS through
-// 128-byte row segments, each wave solves one column, and the result is
-// written back (mode 0), or combined with the parareal correction (mode 1:
-// U_next = F + (g - G_old), G_old = g, increment) or the initial guess
-// (mode 2: U_next = G_old = g).
-template <int NC>
-__global__ __launch_bounds__(kWave* kColsPerBlock) void k_coarse_y(
-    const DimInst* __restrict__ insts, const double* __restrict__ src, double* __restrict__ dst,
-    int mode, const double* __restrict__ F, double* __restrict__ Gold,
-    double* __restrict__ Unext, unsigned long long* __restrict__ inc_bits,
-    const double* __restrict__ FE, const double* __restrict__ FR, const double* __restrict__ FG) {
-  extern __shared__ double T[];  // [ny][kTS]
-  const DimInst& I = insts[0];
-  const int nx = I.nx, ny = I.ny;
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1), wv = tid >> 6;
-  const int i0 = blockIdx.x * kColsPerBlock;
+// Columns i0 .. i0 + kColsPerBlock - 1 of a state, one column per wave, result
+// into dst (mode 0), or combined with the parareal correction (mode 1:
+// U_next = F + (g - G_old), G_old = g, increment) or the initial guess (mode 2:
+// U_next = G_old = g). The columns are staged into one LDS line buffer each
+// through row segments. Every global load of the block (state, factors and the
+// correction operands) is issued before the first LDS store. Returns the
+// thread's largest |change| bit pattern (mode 1).
+__device__ __forceinline__ unsigned long long solve_cols(
+    const gdouble* src, int nx, int ny, int i0, int K, const gdouble* Rb, const gdouble* Gb,
+    int mode, gdouble* dst, const gdouble* F, gdouble* Gold, gdouble* Unext, double* T,
+    int tid) {
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
   const int total = ny * kColsPerBlock;
-  {
-    double st[kStageIt];
+  const int col = i0 + wv;
+  const int colc = col < nx ? col : nx - 1;  // clamped for the factor loads
+  double st[kStageIt], gq[kKMax], rq[kKMax];
+  double fv[kStageIt], gv[kStageIt], uv[kStageIt];
+#pragma unroll
+  for (int u = 0; u < kStageIt; u++) {
+    const int q = tid + u * kColThreads;
+    const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+    const int i = i0 + c;
+    const bool ok = q < total && i < nx;
+    const double x = src[ok ? (long)j * nx + i : 0];
+    st[u] = ok ? x : 0.0;
+  }
+  load_line_factors(gq, rq, K, Rb + (long)colc * kWave * K, Gb + (long)colc * kWave * K, lane);
+  if (mode == 1) {
 #pragma unroll
     for (int u = 0; u < kStageIt; u++) {
-      const int q = tid + u * kWave * kColsPerBlock;
+      const int q = tid + u * kColThreads;
       const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
       const int i = i0 + c;
-      st[u] = (q < total && i < nx) ? src[(long)j * nx + i] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kStageIt; u++) {
-      const int q = tid + u * kWave * kColsPerBlock;
-      const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
-      if (q < total) T[j * kTS + c] = st[u];
+      const bool ok = q < total && i < nx;
+      const long idx = ok ? (long)j * nx + i : 0;
+      fv[u] = F[idx];
+      gv[u] = Gold[idx];
+      uv[u] = Unext[idx];
     }
   }
+#pragma unroll
+  for (int u = 0; u < kStageIt; u++) {
+    const int q = tid + u * kColThreads;
+    const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+    if (q < total) T[c * kLineBuf + lds_pad(j)] = st[u];
+  }
   __syncthreads();
-  const int col = i0 + wv;
-  if (col < nx) {
-    double v[NC];
+  if (col < nx) {  // wave-uniform
+    double* buf = T + wv * kLineBuf;
+    double v[kKMax];
 #pragma unroll
-    for (int c = 0; c < NC; c++) {
-      int p = lane * NC + c;
-      v[c] = p < ny ? T[p * kTS + wv] : 0.0;
+    for (int t = 0; t < kKMax; t++) {
+      const int p = lane * K + (t < K ? t : 0);
+      const double x = buf[lds_pad(p)];
+      v[t] = (t < K && p < ny) ? x : 0.0;
     }
-    const long lb = (long)col * ny;
-    line_solve_blocked<NC>(v, NC, gp(FR) + lb, gp(FG) + lb, ny, lane);
+    line_solve_lanes(v, K, gq, rq, lane);
 #pragma unroll
-    for (int c = 0; c < NC; c++) {
-      int p = lane * NC + c;
-      if (p < ny) T[p * kTS + wv] = v[c];
-    }
+    for (int t = 0; t < kKMax; t++)
+      if (t < K) buf[lds_pad(lane * K + t)] = v[t];
   }
   __syncthreads();
   unsigned long long mx = 0;
-  for (int q = tid; q < total; q += kWave * kColsPerBlock) {
-    int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
-    int i = i0 + c;
-    if (i >= nx) continue;
-    long idx = (long)j * nx + i;
-    double g = T[j * kTS + c];
-    if (mode == 0) {
-      dst[idx] = g;
-    } else if (mode == 2) {
-      Unext[idx] = g;
-      Gold[idx] = g;
-    } else {
-      double un = F[idx] + (g - Gold[idx]);
-      unsigned long long bits = abs_bits(un - Unext[idx]);
-      mx = bits > mx ? bits : mx;
-      Unext[idx] = un;
-      Gold[idx] = g;
+#pragma unroll
+  for (int u = 0; u < kStageIt; u++) {
+    const int q = tid + u * kColThreads;
+    const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+    const int i = i0 + c;
+    if (q < total && i < nx) {
+      const long idx = (long)j * nx + i;
+      const double g = T[c * kLineBuf + lds_pad(j)];
+      if (mode == 0) {
+        dst[idx] = g;
+      } else if (mode == 2) {
+        Unext[idx] = g;
+        Gold[idx] = g;
+      } else {
+        const double un = fv[u] + (g - gv[u]);
+        const unsigned long long bits = abs_bits(un - uv[u]);
+        mx = bits > mx ? bits : mx;
+        Unext[idx] = un;
+        Gold[idx] = g;
+      }
     }
   }
-  if (mode == 1) {
-    mx = wave_max_u64(mx);
-    if (lane == 0 && mx != 0) atomicMax(inc_bits, mx);
-  }
+  return mx;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin by id; this maps launch slot
+// `bid` of `nb` to a logical block so that each XCD holds a contiguous range
+// (neighbouring column blocks share cache lines of the same rows).
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+  const int x = bid & 7, r = bid >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return x * per + min(x, rem) + r;
+}
+
+// x-lines (rows) of one state, one wave per row.
+__global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_x(
+    const DimInst* __restrict__ insts, const double* __restrict__ src, double* __restrict__ dst,
+    const double* __restrict__ Rb, const double* __restrict__ Gb) {
+  __shared__ double T[kRowsPerBlock * kLineBuf];
+  const DimInst& I = insts[0];
+  const int nx = I.nx, ny = I.ny, K = I.Kx;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * kRowsPerBlock + wv;
+  if (row >= ny) return;  // whole wave; no block-level barrier follows
+  const long base = (long)row * nx;
+  solve_row(gp(src) + base, gp(dst) + base, gp(Rb) + (long)row * kWave * K,
+            gp(Gb) + (long)row * kWave * K, nx, K, T + wv * kLineBuf, lane);
+}
+
+// y-lines (columns) of one state, kColsPerBlock columns per block: dst = result.
+__global__ __launch_bounds__(kColThreads) void k_coarse_y(const DimInst* __restrict__ insts,
+                                                          const double* __restrict__ src,
+                                                          double* __restrict__ dst,
+                                                          const double* __restrict__ Rb,
+                                                          const double* __restrict__ Gb) {
+  __shared__ double T[kColsPerBlock * kLineBuf];
+  const DimInst& I = insts[0];
+  const int i0 = xcd_block(blockIdx.x, gridDim.x) * kColsPerBlock;
+  solve_cols(gp(src), I.nx, I.ny, i0, I.Ky, gp(Rb), gp(Gb), 0, gp(dst), nullptr, nullptr, nullptr,
+             T, threadIdx.x);
 }
 
 // ----------------------------------------------- batched coarse sweeps ---
-// Same line solves as k_coarse_x / k_coarse_y, one launch per slice index n
-// over the work items of every instance; lines of different instances have
-// different lengths, so the chunk count is a per-block runtime value (<= NCMAX).
+// Same line solves, one launch per slice index n over the line blocks of every
+// instance that has that slice (items ordered on the host per XCD).
 
-template <int NCMAX>
 __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_xb(
     const DimInst* __restrict__ insts, const LineItem* __restrict__ items, int n, int c,
     const double* __restrict__ U_base) {
+  __shared__ double T[kRowsPerBlock * kLineBuf];
   const LineItem it = items[blockIdx.x];
   const DimInst& I = insts[it.inst];
   if (I.active && !I.active[I.idx]) return;
   if (n >= I.N || c >= I.cs) return;
-  const int nx = I.nx, ny = I.ny;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int row = it.block * kRowsPerBlock + (threadIdx.x >> 6);
+  const int nx = I.nx, ny = I.ny, K = I.Kx;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int row = it.block * kRowsPerBlock + wv;
   if (row >= ny) return;  // whole wave
   const gdouble* src = c == 0 ? gp(U_base) + I.off_states + (long)n * I.npts : gp(I.tmp);
-  gdouble* dst = gp(I.tmp);
   const long base = (long)row * nx;
-  const int K = chunks_pow2_dev(nx);
-  double v[NCMAX];
-#pragma unroll
-  for (int cc = 0; cc < NCMAX; cc++) {
-    const int p = lane * K + cc;
-    v[cc] = (cc < K && p < nx) ? src[base + p] : 0.0;
-  }
-  line_solve_blocked<NCMAX>(v, K, gp(I.cxR) + base, gp(I.cxG) + base, nx, lane);
-#pragma unroll
-  for (int cc = 0; cc < NCMAX; cc++) {
-    const int p = lane * K + cc;
-    if (cc < K && p < nx) dst[base + p] = v[cc];
-  }
+  solve_row(src + base, gp(I.tmp) + base, gp(I.cxRb) + (long)row * kWave * K,
+            gp(I.cxGb) + (long)row * kWave * K, nx, K, T + wv * kLineBuf, lane);
 }
 
-template <int NCMAX>
-__global__ __launch_bounds__(kWave* kColsPerBlock) void k_coarse_yb(
+// The increment of the correction (mode 1) goes to the instance's per-column-
+// block partial maxima (plain read-modify-write: one block per entry per
+// launch, launches in stream order); k_inc_reduce folds them afterwards.
+__global__ __launch_bounds__(kColThreads) void k_coarse_yb(
     const DimInst* __restrict__ insts, const LineItem* __restrict__ items, int n, int c, int mode,
-    const double* __restrict__ F_base, double* __restrict__ G_base, double* __restrict__ U_base,
-    unsigned long long* __restrict__ inc_bits) {
-  extern __shared__ double T[];  // [ny][kTS]
+    const double* __restrict__ F_base, double* __restrict__ G_base, double* __restrict__ U_base) {
+  __shared__ double T[kColsPerBlock * kLineBuf];
+  __shared__ unsigned long long wmax[kColsPerBlock];
   const LineItem it = items[blockIdx.x];
   const DimInst& I = insts[it.inst];
   if (I.active && !I.active[I.idx]) return;  // uniform over the block
   if (n >= I.N || c >= I.cs) return;
-  const int nx = I.nx, ny = I.ny;
   const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1), wv = tid >> 6;
-  const int i0 = it.block * kColsPerBlock;
-  const int total = ny * kColsPerBlock;
-  const gdouble* src = gp(I.tmp);
-  {
-    // all loads in flight before the first LDS store
-    double st[kStageIt];
-#pragma unroll
-    for (int u = 0; u < kStageIt; u++) {
-      const int q = tid + u * kWave * kColsPerBlock;
-      const int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
-      const int i = i0 + cc;
-      st[u] = (q < total && i < nx) ? src[(long)j * nx + i] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kStageIt; u++) {
-      const int q = tid + u * kWave * kColsPerBlock;
-      const int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
-      if (q < total) T[j * kTS + cc] = st[u];
-    }
-  }
-  __syncthreads();
-  const int col = i0 + wv;
-  if (col < nx) {
-    const int K = chunks_pow2_dev(ny);
-    double v[NCMAX];
-#pragma unroll
-    for (int cc = 0; cc < NCMAX; cc++) {
-      int p = lane * K + cc;
-      v[cc] = (cc < K && p < ny) ? T[p * kTS + wv] : 0.0;
-    }
-    const long lb = (long)col * ny;
-    line_solve_blocked<NCMAX>(v, K, gp(I.cyR) + lb, gp(I.cyG) + lb, ny, lane);
-#pragma unroll
-    for (int cc = 0; cc < NCMAX; cc++) {
-      int p = lane * K + cc;
-      if (cc < K && p < ny) T[p * kTS + wv] = v[cc];
-    }
-  }
-  __syncthreads();
   const int md = (c + 1 == I.cs) ? mode : 0;
-  gdouble* tmpw = gp(I.tmp);
-  const gdouble* Fn = gp(F_base) + I.off_slices + (long)n * I.npts;
-  gdouble* Gn = gp(G_base) + I.off_slices + (long)n * I.npts;
-  gdouble* Un = gp(U_base) + I.off_states + (long)(n + 1) * I.npts;
-  unsigned long long mx = 0;
-  if (md == 1) {
-    // correction: all loads of F, G_old and the old U in flight before use
-    double fv[kStageIt], gv[kStageIt], uv[kStageIt];
-#pragma unroll
-    for (int u = 0; u < kStageIt; u++) {
-      const int q = tid + u * kWave * kColsPerBlock;
-      const int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
-      const int i = i0 + cc;
-      const bool ok = q < total && i < nx;
-      const long idx = ok ? (long)j * nx + i : 0;
-      fv[u] = ok ? Fn[idx] : 0.0;
-      gv[u] = ok ? Gn[idx] : 0.0;
-      uv[u] = ok ? Un[idx] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kStageIt; u++) {
-      const int q = tid + u * kWave * kColsPerBlock;
-      const int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
-      const int i = i0 + cc;
-      if (q < total && i < nx) {
-        const long idx = (long)j * nx + i;
-        const double g = T[j * kTS + cc];
-        const double un = fv[u] + (g - gv[u]);
-        const unsigned long long bits = abs_bits(un - uv[u]);
-        mx = bits > mx ? bits : mx;
-        Un[idx] = un;
-        Gn[idx] = g;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int u = 0; u < kStageIt; u++) {
-      const int q = tid + u * kWave * kColsPerBlock;
-      const int j = q / kColsPerBlock, cc = q - j * kColsPerBlock;
-      const int i = i0 + cc;
-      if (q < total && i < nx) {
-        const long idx = (long)j * nx + i;
-        const double g = T[j * kTS + cc];
-        if (md == 0) {
-          tmpw[idx] = g;
-        } else {
-          Un[idx] = g;
-          Gn[idx] = g;
-        }
-      }
-    }
-  }
+  unsigned long long mx = solve_cols(
+      gp(I.tmp), I.nx, I.ny, it.block * kColsPerBlock, I.Ky, gp(I.cyRb), gp(I.cyGb), md,
+      gp(I.tmp), gp(F_base) + I.off_slices + (long)n * I.npts,
+      gp(G_base) + I.off_slices + (long)n * I.npts,
+      gp(U_base) + I.off_states + (long)(n + 1) * I.npts, T, tid);
   if (md == 1) {
     mx = wave_max_u64(mx);
-    if (lane == 0 && mx != 0) atomicMax(inc_bits + I.idx, mx);
+    if ((tid & (kWave - 1)) == 0) wmax[tid / kWave] = mx;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long m = wmax[0];
+#pragma unroll
+      for (int w = 1; w < kColsPerBlock; w++) m = wmax[w] > m ? wmax[w] : m;
+      unsigned long long* slot = I.incp + it.block;
+      if (m > *slot) *slot = m;
+    }
   }
+}
+
+// inc[idx] = max(inc[idx], largest partial) for each instance with partials;
+// one block per instance.
+__global__ __launch_bounds__(256) void k_inc_reduce(const DimInst* __restrict__ insts,
+                                                    unsigned long long* __restrict__ inc) {
+  __shared__ unsigned long long wm[4];
+  const DimInst& I = insts[blockIdx.x];
+  if (!I.incp) return;  // block-uniform
+  const int tid = threadIdx.x;
+  const int nb = (I.nx + kColsPerBlock - 1) / kColsPerBlock;
+  unsigned long long m = 0;
+  for (int b = tid; b < nb; b += 256) m = I.incp[b] > m ? I.incp[b] : m;
+  m = wave_max_u64(m);
+  if ((tid & (kWave - 1)) == 0) wm[tid / kWave] = m;
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; w++) m = wm[w] > m ? wm[w] : m;
+    m = wm[0] > m ? wm[0] : m;
+    if (m > inc[I.idx]) inc[I.idx] = m;
+  }
+}
+
+// Lane-blocked copy of line-major factors: dst[l][c][lane] = src[l][lane*K + c]
+// (0 past the line end). One thread per destination entry.
+__global__ void k_block_factors(const double* __restrict__ src, int n_lines, int n_pos, int K,
+                                double* __restrict__ dst) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long per = (long)kWave * K;
+  if (t >= (long)n_lines * per) return;
+  const long l = t / per;
+  const int r = (int)(t - l * per);
+  const int c = r / kWave, lane = r - c * kWave;
+  const int p = lane * K + c;
+  dst[t] = p < n_pos ? src[l * n_pos + p] : 0.0;
 }
 
 __global__ void k_mask_update(const double* __restrict__ inc, int* __restrict__ active, int n,
@@ -819,12 +882,6 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, siz
   for (; i < n; i += stride) b[i] = a[i];
 }
 
-int chunks_pow2(int n) {
-  int c = (n + kWave - 1) / kWave, p = 1;
-  while (p < c) p <<= 1;
-  return p;
-}
-
 }  // namespace
 
 // ------------------------------------------------------------- launchers ---
@@ -859,14 +916,15 @@ hipError_t launch_chunk_phi(const double* G, int n_lines, int n_pos, int M, doub
 hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const double* U_in,
                                  hipStream_t s) {
   dim3 grid((h.nx + 63) / 64, h.ny, h.B);
-  hipLaunchKernelGGL(k_to_interleaved, grid, dim3(kWave), 0, s, d_inst, U_in);
+  hipLaunchKernelGGL(k_to_interleaved, grid, dim3(kTrThreads), 0, s, d_inst, U_in);
   return hipGetLastError();
 }
 
 hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, double* F_out,
                                    bool with_corr, hipStream_t s) {
   dim3 grid((h.nx + 63) / 64, h.ny, h.B);
-  hipLaunchKernelGGL(k_from_interleaved, grid, dim3(kWave), 0, s, d_inst, F_out, (int)with_corr);
+  hipLaunchKernelGGL(k_from_interleaved, grid, dim3(kTrThreads), 0, s, d_inst, F_out,
+                     (int)with_corr);
   return hipGetLastError();
 }
 
@@ -915,58 +973,34 @@ hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int
   }
 }
 
-template <int NC>
-static hipError_t launch_cx(const DimInst* d_inst, const DimInst& h, const double* src,
-                            double* dst, bool fine, hipStream_t s) {
-  hipLaunchKernelGGL((k_coarse_x<NC>), dim3((h.ny + kRowsPerBlock - 1) / kRowsPerBlock),
-                     dim3(kWave * kRowsPerBlock), 0, s, d_inst, src, dst, fine ? h.fxE : h.cxE,
-                     fine ? h.fxR : h.cxR, fine ? h.fxG : h.cxG);
+int positions_per_lane(int n) {
+  int p = 1;
+  while (p * kWave < n) p <<= 1;
+  return p;
+}
+
+hipError_t launch_block_factors(const double* src, int n_lines, int n_pos, double* dst,
+                                hipStream_t s) {
+  const long total = (long)n_lines * kWave * positions_per_lane(n_pos);
+  hipLaunchKernelGGL(k_block_factors, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src,
+                     n_lines, n_pos, positions_per_lane(n_pos), dst);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
                            bool fine, hipStream_t s) {
-  switch (chunks_pow2(h.nx)) {
-    case 1: return launch_cx<1>(d_inst, h, src, dst, fine, s);
-    case 2: return launch_cx<2>(d_inst, h, src, dst, fine, s);
-    case 4: return launch_cx<4>(d_inst, h, src, dst, fine, s);
-    case 8: return launch_cx<8>(d_inst, h, src, dst, fine, s);
-    case 16: return launch_cx<16>(d_inst, h, src, dst, fine, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int NC>
-static hipError_t launch_cy(const DimInst* d_inst, const DimInst& h, const double* src,
-                            double* dst, int mode, const double* F, double* G_old,
-                            double* U_next, unsigned long long* inc_bits, bool fine,
-                            hipStream_t s) {
-  size_t lds = (size_t)h.ny * kTS * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_y<NC>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kMaxCoarseLine * kTS * (int)sizeof(double));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL((k_coarse_y<NC>), dim3((h.nx + kColsPerBlock - 1) / kColsPerBlock),
-                     dim3(kWave * kColsPerBlock), lds, s, d_inst, src, dst, mode, F, G_old, U_next,
-                     inc_bits, fine ? h.fyE : h.cyE, fine ? h.fyR : h.cyR, fine ? h.fyG : h.cyG);
+  hipLaunchKernelGGL(k_coarse_x, dim3((h.ny + kRowsPerBlock - 1) / kRowsPerBlock),
+                     dim3(kWave * kRowsPerBlock), 0, s, d_inst, src, dst, fine ? h.fxRb : h.cxRb,
+                     fine ? h.fxGb : h.cxGb);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_y(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
-                           int mode, const double* F, double* G_old, double* U_next,
-                           unsigned long long* inc_bits, bool fine, hipStream_t s) {
-  switch (chunks_pow2(h.ny)) {
-    case 1: return launch_cy<1>(d_inst, h, src, dst, mode, F, G_old, U_next, inc_bits, fine, s);
-    case 2: return launch_cy<2>(d_inst, h, src, dst, mode, F, G_old, U_next, inc_bits, fine, s);
-    case 4: return launch_cy<4>(d_inst, h, src, dst, mode, F, G_old, U_next, inc_bits, fine, s);
-    case 8: return launch_cy<8>(d_inst, h, src, dst, mode, F, G_old, U_next, inc_bits, fine, s);
-    case 16: return launch_cy<16>(d_inst, h, src, dst, mode, F, G_old, U_next, inc_bits, fine, s);
-    default: return hipErrorInvalidValue;
-  }
+                           bool fine, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_y, dim3((h.nx + kColsPerBlock - 1) / kColsPerBlock),
+                     dim3(kColThreads), 0, s, d_inst, src, dst, fine ? h.fyRb : h.cyRb,
+                     fine ? h.fyGb : h.cyGb);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s) {
@@ -986,26 +1020,24 @@ hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s) 
 hipError_t launch_coarse_xb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
                             int c, const double* U_base, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_coarse_xb<16>), dim3(n_items), dim3(kWave * kRowsPerBlock), 0, s, d_insts,
+  hipLaunchKernelGGL(k_coarse_xb, dim3(n_items), dim3(kWave * kRowsPerBlock), 0, s, d_insts,
                      items, n, c, U_base);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_yb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
                             int c, int mode, const double* F_base, double* G_base, double* U_base,
-                            unsigned long long* inc_bits, int max_ny, hipStream_t s) {
+                            hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_yb<16>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kMaxCoarseLine * kTS * (int)sizeof(double));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  size_t lds = (size_t)max_ny * kTS * sizeof(double);
-  hipLaunchKernelGGL((k_coarse_yb<16>), dim3(n_items), dim3(kWave * kColsPerBlock), lds, s,
-                     d_insts, items, n, c, mode, F_base, G_base, U_base, inc_bits);
+  hipLaunchKernelGGL(k_coarse_yb, dim3(n_items), dim3(kColThreads), 0, s, d_insts, items, n, c,
+                     mode, F_base, G_base, U_base);
+  return hipGetLastError();
+}
+
+hipError_t launch_inc_reduce(const DimInst* d_insts, int n_inst, unsigned long long* inc,
+                             hipStream_t s) {
+  if (n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_inc_reduce, dim3(n_inst), dim3(256), 0, s, d_insts, inc);
   return hipGetLastError();
 }
 
