@@ -80,9 +80,11 @@ struct DArr {
 
 // Factors of the domain-decomposition substeps at one tau.
 struct DDFactorSet {
-  DBuf E, R, G, CHI, PHI, PSIE, CHIA, PHIA;
+  DBuf R, G, CHI, PHI, PSIE, CHIA, PHIA;
+  DBuf PC0, PP0, PC1, PP1, FC, FP;  // deferred corrections (fine set only)
   DDFactors view() const {
-    return DDFactors{E.p, R.p, G.p, CHI.p, PHI.p, PSIE.p, CHIA.p, PHIA.p};
+    return DDFactors{R.p, G.p, CHI.p, PHI.p, PSIE.p, CHIA.p, PHIA.p,
+                     PC0.p, PP0.p, PC1.p, PP1.p, FC.p, FP.p};
   }
 };
 
@@ -105,6 +107,12 @@ struct Instance {
   int n_colors = 0;
   std::vector<int> seg_off;   // colour k's segments: [seg_off[k], seg_off[k+1])
   std::vector<int> comp_off;  // colour k's components: [comp_off[k], comp_off[k+1])
+  std::vector<int> run_off;   // colour k's carry runs: [run_off[k], run_off[k+1])
+  DArr<DDRun> runs;
+  DArr<int> comp_run_first, comp_run_count;
+  DArr<int> seg_src0, seg_src1, fin_seg;  // pending-correction sources (deferred substeps)
+  DBuf RP, RQ, RU, RV, RW, RY, RX;        // fine (interleaved) run maps and carries
+  DBuf RP1, RQ1, RU1, RV1, RW1, RY1, RX1;  // single-state run maps and carries
   DBuf rho, W;
   DArr<DDSeg> segs;
   DArr<int> seg_colour, comp_lo, comp_hi, comp_colour, comp_first, comp_count;
@@ -412,6 +420,7 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
   std::vector<DDSeg> segs;
   I.seg_off.assign(1, 0);
   I.comp_off.assign(1, 0);
+  // components of every colour
   for (int k = 0; k < K; k++) {
     const double* rk = rho_host + (size_t)k * (n + 1);
     int f = 0;
@@ -425,19 +434,84 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
       const int fb = f - 1;
       const int lo = std::max(fa - 1, 0), hi = std::min(fb, n - 1);
       if (lo > hi) continue;
-      const int ci = (int)clo.size();
       clo.push_back(lo); chi.push_back(hi); ccol.push_back(k);
+    }
+    I.comp_off.push_back((int)clo.size());
+  }
+  // Segments: every component cut at a common set of points (multiples of
+  // kDDSeg and every component end of every colour), so that segments of
+  // different colours covering a node span the same node range.
+  std::vector<int> cuts;
+  for (int x = 0; x < n; x += kDDSeg) cuts.push_back(x);
+  for (size_t c = 0; c < clo.size(); c++) {
+    cuts.push_back(clo[c]);
+    cuts.push_back(chi[c] + 1);
+  }
+  std::sort(cuts.begin(), cuts.end());
+  cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
+  std::vector<std::vector<int>> starts(K);  // segment starts per colour (sorted)
+  for (int k = 0; k < K; k++) {
+    for (int c = I.comp_off[k]; c < I.comp_off[k + 1]; c++) {
       cfirst.push_back((int)segs.size());
-      for (int s0 = lo; s0 <= hi; s0 += kDDSeg) {
-        segs.push_back(DDSeg{s0, std::min(kDDSeg, hi - s0 + 1), ci, s0 == lo ? 1 : 0});
+      auto it = std::upper_bound(cuts.begin(), cuts.end(), clo[c]);
+      int a = clo[c];
+      while (a <= chi[c]) {
+        const int b = (it != cuts.end() && *it <= chi[c]) ? *it : chi[c] + 1;
+        segs.push_back(DDSeg{a, b - a, c, k});
         scol.push_back(k);
+        starts[k].push_back(a);
+        a = b;
+        if (it != cuts.end()) ++it;
       }
       ccount.push_back((int)segs.size() - cfirst.back());
     }
     I.seg_off.push_back((int)segs.size());
-    I.comp_off.push_back((int)clo.size());
   }
   const int n_segs = (int)segs.size();
+  // Pending-correction sources of the deferred fine substeps. When colour k
+  // loads a node, the node still carries the correction of the last substep
+  // that solved it: the largest colour k' < k covering it in the same step
+  // ("fresh"), else the largest colour covering it in the previous step
+  // ("stale", colour k itself at the latest). Segments are aligned, so the
+  // source is one segment per segment. After the last step every node
+  // carries the correction of the largest colour covering it.
+  auto seg_at = [&](int k, int a) -> int {  // colour k's segment starting at a, or -1
+    auto it = std::lower_bound(starts[k].begin(), starts[k].end(), a);
+    if (it == starts[k].end() || *it != a) return -1;
+    return I.seg_off[k] + (int)(it - starts[k].begin());
+  };
+  std::vector<int> sfresh(n_segs, -1), sstale(n_segs, -1), fin(n, -1);
+  for (int k = 0; k < K; k++)
+    for (int si = I.seg_off[k]; si < I.seg_off[k + 1]; si++) {
+      for (int k2 = k - 1; k2 >= 0 && sfresh[si] < 0; k2--) sfresh[si] = seg_at(k2, segs[si].lo);
+      for (int k2 = K - 1; k2 >= k && sstale[si] < 0; k2--) sstale[si] = seg_at(k2, segs[si].lo);
+    }
+  for (int k = K - 1; k >= 0; k--)
+    for (int si = I.seg_off[k]; si < I.seg_off[k + 1]; si++)
+      for (int x = segs[si].lo; x < segs[si].lo + segs[si].len; x++)
+        if (fin[x] < 0) fin[x] = si;
+  std::vector<int> src1(n_segs);
+  for (int si = 0; si < n_segs; si++) src1[si] = sfresh[si] >= 0 ? sfresh[si] : sstale[si];
+  HIPOK(I.seg_src0.upload(sfresh));
+  HIPOK(I.seg_src1.upload(src1));
+  HIPOK(I.fin_seg.upload(fin));
+  // carry runs: kDDRun consecutive segments of one component
+  std::vector<DDRun> runs;
+  std::vector<int> crfirst, crcount;
+  I.run_off.assign(1, 0);
+  for (int k = 0; k < K; k++) {
+    for (int c = I.comp_off[k]; c < I.comp_off[k + 1]; c++) {
+      crfirst.push_back((int)runs.size());
+      for (int q = 0; q < ccount[c]; q += kDDRun)
+        runs.push_back(DDRun{cfirst[c] + q, std::min(kDDRun, ccount[c] - q)});
+      crcount.push_back((int)runs.size() - crfirst.back());
+    }
+    I.run_off.push_back((int)runs.size());
+  }
+  const int n_runs = (int)runs.size();
+  HIPOK(I.runs.upload(runs));
+  HIPOK(I.comp_run_first.upload(crfirst));
+  HIPOK(I.comp_run_count.upload(crcount));
   HIPOK(I.segs.upload(segs));
   HIPOK(I.seg_colour.upload(scol));
   HIPOK(I.comp_lo.upload(clo)); HIPOK(I.comp_hi.upload(chi)); HIPOK(I.comp_colour.upload(ccol));
@@ -447,26 +521,41 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
   HIPOK(I.ax.alloc((size_t)n + 1));
   HIPOK(I.W.alloc((size_t)K * (n + 1)));
   for (DDFactorSet* fs : {&I.ffine, &I.fcoarse}) {
-    for (DBuf* b : {&fs->E, &fs->R, &fs->G, &fs->CHI, &fs->PHI}) {
+    for (DBuf* b : {&fs->R, &fs->G, &fs->CHI, &fs->PHI}) {
       HIPOK(b->alloc((size_t)K * n));
       HIPOK(launch_fill_zero(b->p, b->n, s));
     }
     for (DBuf* b : {&fs->PSIE, &fs->CHIA, &fs->PHIA}) HIPOK(b->alloc(std::max(n_segs, 1)));
   }
+  for (DBuf* b : {&I.ffine.PC0, &I.ffine.PP0, &I.ffine.PC1, &I.ffine.PP1}) {
+    HIPOK(b->alloc((size_t)K * n));
+    HIPOK(launch_fill_zero(b->p, b->n, s));
+  }
+  for (DBuf* b : {&I.ffine.FC, &I.ffine.FP}) HIPOK(b->alloc((size_t)n));
   const int L = std::min(64, std::max(8, pow2_at_least(N)));
   const int B = (N + L - 1) / L;
   HIPOK(I.Z.alloc((size_t)B * n * L));
   HIPOK(I.tmp.alloc(n));
   for (DBuf* b : {&I.Yb, &I.Za, &I.Yin, &I.Xin}) HIPOK(b->alloc((size_t)B * std::max(n_segs, 1) * L));
   for (DBuf* b : {&I.Yb1, &I.Za1, &I.Yin1, &I.Xin1}) HIPOK(b->alloc(std::max(n_segs, 1)));
+  for (DBuf* b : {&I.RP, &I.RQ, &I.RU, &I.RV, &I.RW, &I.RY, &I.RX})
+    HIPOK(b->alloc((size_t)B * std::max(n_runs, 1) * L));
+  for (DBuf* b : {&I.RP1, &I.RQ1, &I.RU1, &I.RV1, &I.RW1, &I.RY1, &I.RX1})
+    HIPOK(b->alloc(std::max(n_runs, 1)));
   DDInst& h = I.hdd;
   h.n = n; h.N = N; h.L = L; h.B = B; h.n_colors = K; h.n_segs = n_segs;
   h.slab = (long)n * L; h.Z = I.Z.p; h.segs = I.segs.p;
   h.Yb = I.Yb.p; h.Za = I.Za.p; h.Yin = I.Yin.p; h.Xin = I.Xin.p;
+  h.n_runs = n_runs; h.runs = I.runs.p;
+  h.seg_src0 = I.seg_src0.p; h.seg_src1 = I.seg_src1.p; h.fin_seg = I.fin_seg.p;
+  h.RP = I.RP.p; h.RQ = I.RQ.p; h.RU = I.RU.p; h.RV = I.RV.p; h.RW = I.RW.p;
+  h.RY = I.RY.p; h.RX = I.RX.p;
   DDInst& h1 = I.hdd1;
   h1 = h;
   h1.N = 1; h1.L = 1; h1.B = 1; h1.slab = n; h1.Z = I.tmp.p;
   h1.Yb = I.Yb1.p; h1.Za = I.Za1.p; h1.Yin = I.Yin1.p; h1.Xin = I.Xin1.p;
+  h1.RP = I.RP1.p; h1.RQ = I.RQ1.p; h1.RU = I.RU1.p; h1.RV = I.RV1.p; h1.RW = I.RW1.p;
+  h1.RY = I.RY1.p; h1.RX = I.RX1.p;
   HIPOK(hipMalloc(reinterpret_cast<void**>(&I.d_dd), 2 * sizeof(DDInst)));
   DDInst both[2] = {h, h1};
   HIPOK(hipMemcpy(I.d_dd, both, sizeof(both), hipMemcpyHostToDevice));
@@ -491,27 +580,37 @@ pr_status factorize_dd_instance(Instance& I, const double* coef_x, hipStream_t s
     DDFactorSet& fs = coarse ? I.fcoarse : I.ffine;
     const double tau = coarse ? I.tauG : I.dt;
     HIPOK(launch_dd_factorize(I.W.p, n, I.comp_lo.p, I.comp_hi.p, I.comp_colour.p, n_comps,
-                              tau / (h * h), fs.E.p, fs.R.p, fs.G.p, s));
-    HIPOK(launch_dd_segfactors(I.segs.p, I.seg_colour.p, n_segs, n, fs.E.p, fs.R.p, fs.G.p,
+                              tau / (h * h), fs.R.p, fs.G.p, s));
+    HIPOK(launch_dd_segfactors(I.segs.p, I.seg_colour.p, n_segs, n, fs.R.p, fs.G.p,
                                fs.CHI.p, fs.PHI.p, fs.PSIE.p, fs.CHIA.p, fs.PHIA.p, s));
   }
+  DDFactorSet& ff = I.ffine;
+  HIPOK(launch_dd_pending(I.d_dd, I.hdd, ff.view(), ff.PC0.p, ff.PP0.p, ff.PC1.p, ff.PP1.p,
+                          ff.FC.p, ff.FP.p, s));
   return PR_OK;
 }
 
 // One FIE step (eq. FIE_method) of the DD splitting: colours in order, each
 // colour's components solved by segment solves, carry scans and corrections.
-// which = 0: interleaved fine workspace, 1: the single state in tmp.
-pr_status dd_fie_step(pr_problem_s* P, Instance& I, bool coarse, int which, hipStream_t s) {
+// which = 0: interleaved fine workspace, whose corrections are deferred to the
+// next load (step = the step's index; the last step's are applied by
+// launch_dd_from_interleaved); which = 1: the single state in tmp, corrected
+// in place.
+pr_status dd_fie_step(pr_problem_s* P, Instance& I, bool coarse, int which, int step,
+                      hipStream_t s) {
   const DDInst* dI = I.d_dd + which;
   const DDInst& h = which ? I.hdd1 : I.hdd;
   const DDFactors f = (coarse ? I.fcoarse : I.ffine).view();
+  const bool defer = which == 0;
   for (int k = 0; k < I.n_colors; k++) {
     const int sb = I.seg_off[k], sc = I.seg_off[k + 1] - sb;
     const int cb = I.comp_off[k], cc = I.comp_off[k + 1] - cb;
+    const int rb = I.run_off[k], rc = I.run_off[k + 1] - rb;
     PhaseTimer pt(P, which ? PH_COARSE_X : PH_FINE, s);
-    HIPOK(launch_dd_local(dI, h, f, k, sb, sc, s));
-    HIPOK(launch_dd_carries(dI, h, f, I.comp_first.p + cb, I.comp_count.p + cb, cc, s));
-    HIPOK(launch_dd_correct(dI, h, f, k, sb, sc, s));
+    HIPOK(launch_dd_local(dI, h, f, k, sb, sc, defer, step > 0, s));
+    HIPOK(launch_dd_carries(dI, h, f, rb, rc, I.comp_run_first.p + cb, I.comp_run_count.p + cb, cc,
+                            s));
+    if (!defer) HIPOK(launch_dd_correct(dI, h, f, k, sb, sc, s));
   }
   return PR_OK;
 }
@@ -607,14 +706,17 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
     Instance& I = *P->inst[i];
     if (!I.dd) continue;
     for (int t = 0; t < I.d.fine_steps; t++) {
-      pr_status st = dd_fie_step(P, I, false, 0, s);
+      pr_status st = dd_fie_step(P, I, false, 0, t, s);
       if (st != PR_OK) return st;
     }
   }
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
     PhaseTimer pt(P, PH_TRANSPOSE, s);
-    HIPOK(launch_from_interleaved(P->d_inst + i, I.h, out_base + I.off_slices, !I.dd, s));
+    if (I.dd)
+      HIPOK(launch_dd_from_interleaved(I.d_dd, I.hdd, I.ffine.view(), out_base + I.off_slices, s));
+    else
+      HIPOK(launch_from_interleaved(P->d_inst + i, I.h, out_base + I.off_slices, true, s));
   }
   return PR_OK;
 }
@@ -622,15 +724,15 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
 // One coarse propagation G (coarse_steps FIE steps) of state src of DD
 // instance i, followed by the parareal update in `mode` (see launch_update).
 pr_status coarse_apply_dd(pr_problem_s* P, int i, const double* src, int mode, const double* F,
-                          double* Gold, double* Unext, unsigned long long* inc, hipStream_t s) {
+                          double* Gold, double* Unext, hipStream_t s) {
   Instance& I = *P->inst[i];
   HIPOK(launch_copy(src, I.tmp.p, I.npts, s));
   for (int c = 0; c < I.d.coarse_steps; c++) {
-    pr_status st = dd_fie_step(P, I, true, 1, s);
+    pr_status st = dd_fie_step(P, I, true, 1, 0, s);
     if (st != PR_OK) return st;
   }
   PhaseTimer pt(P, PH_COARSE_Y, s);
-  HIPOK(launch_update(I.tmp.p, F, Gold, Unext, I.npts, mode, inc, s));
+  HIPOK(launch_update(I.tmp.p, F, Gold, Unext, I.npts, mode, I.h.incp, s));
   return PR_OK;
 }
 
@@ -644,6 +746,7 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
   const int n = (int)P->inst.size();
   unsigned long long* inc = inc_bits ? inc_bits : P->d_inc;
   HIPOK(launch_fill_zero(reinterpret_cast<double*>(inc), n, s));
+  HIPOK(launch_fill_zero(reinterpret_cast<double*>(P->d_incp), P->n_incp, s));
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
     if (!I.dd || (host_active && !(*host_active)[i])) continue;
@@ -652,11 +755,10 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
       double* Unext = U + I.off_states + (size_t)(k + 1) * I.npts;
       double* Gk = Gold + I.off_slices + (size_t)k * I.npts;
       const double* Fk = F ? F + I.off_slices + (size_t)k * I.npts : nullptr;
-      pr_status st = coarse_apply_dd(P, i, Un, F ? 1 : 2, Fk, Gk, Unext, inc + i, s);
+      pr_status st = coarse_apply_dd(P, i, Un, F ? 1 : 2, Fk, Gk, Unext, s);
       if (st != PR_OK) return st;
     }
   }
-  if (P->n_incp) HIPOK(launch_fill_zero(reinterpret_cast<double*>(P->d_incp), P->n_incp, s));
   for (int k = 0; k < P->Nmax; k++) {
     const int xb = P->xoff[k], xn = P->xoff[k + 1] - xb;
     const int yb = P->yoff[k], yn = P->yoff[k + 1] - yb;
@@ -670,7 +772,7 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
       HIPOK(launch_coarse_yb(P->d_inst, P->yitems.p + yb, yn, k, c, F ? 1 : 2, F, Gold, U, s));
     }
   }
-  if (P->n_incp) HIPOK(launch_inc_reduce(P->d_inst, n, inc, s));
+  HIPOK(launch_inc_reduce(P->d_inst, n, inc, s));
   return PR_OK;
 }
 
@@ -921,19 +1023,19 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
     h.off_states = (long)P->inst[i]->off_states;
     h.active = P->d_active;
   }
-  // per-column-block increment maxima of the coarse sweeps
-  for (auto& I : P->inst)
-    if (!I->dd) P->n_incp += (I->d.nx + kCoarseColsPerBlock - 1) / kCoarseColsPerBlock;
-  if (P->n_incp)
-    HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_incp),
-                    P->n_incp * sizeof(unsigned long long)));
+  // per-block increment maxima of the coarse sweeps: one per column block of
+  // the batched y launches, one per block of the DD update kernel
+  for (auto& I : P->inst) {
+    I->h.n_incp = I->dd ? update_blocks(I->npts)
+                        : (I->d.nx + kCoarseColsPerBlock - 1) / kCoarseColsPerBlock;
+    P->n_incp += I->h.n_incp;
+  }
+  HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_incp), P->n_incp * sizeof(unsigned long long)));
   {
     size_t o = 0;
     for (auto& I : P->inst) {
-      I->h.incp = nullptr;
-      if (I->dd) continue;
       I->h.incp = P->d_incp + o;
-      o += (I->d.nx + kCoarseColsPerBlock - 1) / kCoarseColsPerBlock;
+      o += I->h.n_incp;
     }
   }
   {
@@ -1188,7 +1290,7 @@ pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hi
       for (int k = 0; k < I.d.n_slices; k++) {
         HIPOK(launch_copy(U + I.off_states + (size_t)k * I.npts, I.tmp.p, I.npts, s));
         for (int t = 0; t < I.d.fine_steps; t++) {
-          pr_status st = dd_fie_step(p, I, false, 1, s);
+          pr_status st = dd_fie_step(p, I, false, 1, 0, s);
           if (st != PR_OK) return st;
         }
         HIPOK(launch_copy(I.tmp.p, U + I.off_states + (size_t)(k + 1) * I.npts, I.npts, s));

@@ -57,7 +57,8 @@ struct DimInst {
   const double* cxRb; const double* cxGb; const double* cyRb; const double* cyGb;
   const double* fxRb; const double* fxGb; const double* fyRb; const double* fyGb;
   double* tmp;       // one-state scratch of the coarse sweep
-  unsigned long long* incp;  // per-column-block increment maxima of a coarse sweep
+  unsigned long long* incp;  // per-block increment maxima of a coarse sweep
+  int n_incp;                // their count
   // batch bookkeeping
   int idx;           // instance index in the handle
   int cs;            // coarse steps per coarse propagation
@@ -111,17 +112,34 @@ constexpr int kDDSeg = 64;
 
 struct DDSeg {
   int lo, len;    // first node, node count (<= kDDSeg)
-  int comp;       // component index (within the colour's list)
-  int first;      // 1 for the first segment of its component
+  int comp;       // component index
+  int colour;
 };
 
 // One set of factors (one tau) for all colours, indexed [colour][node].
 struct DDFactors {
-  const double* E; const double* R; const double* G;
+  const double* R; const double* G;  // e_i = G[i-1] (see k_dd_factorize)
   const double* CHI; const double* PHI;
   const double* PSIE;  // per segment: product of e over the segment
   const double* CHIA;  // per segment: chi at its first node
   const double* PHIA;  // per segment: phi at its first node
+  // Deferred corrections (fine set only, else NULL): chi and phi of the
+  // correction a node carries when colour k loads it, [colour][node], at the
+  // first step (PC0, PP0: same-step sources only) and later (PC1, PP1); and of
+  // the correction it carries after the last substep (FC, FP: [node]).
+  const double* PC0; const double* PP0; const double* PC1; const double* PP1;
+  const double* FC; const double* FP;
+};
+
+// The carries are resolved over runs of kDDRun consecutive segments of one
+// component: each run is summarised by the affine maps that give its last Y and
+// its first X from the Y before it and the X after it (2a), one wave scan per
+// component and slice chains the runs (2b), and each run then re-derives the
+// carries of its segments (2c).
+constexpr int kDDRun = 16;
+
+struct DDRun {
+  int seg0, len;  // first segment (index into segs), segment count (<= kDDRun)
 };
 
 struct DDInst {
@@ -132,29 +150,58 @@ struct DDInst {
   const DDSeg* segs;    // [n_segs], colour-major
   // per (segment, slice): [B][n_segs][L]
   double* Yb; double* Za; double* Yin; double* Xin;
+  int n_runs;           // runs of all colours
+  const DDRun* runs;    // [n_runs], colour-major, runs of a component contiguous
+  // per (run, slice): [B][n_runs][L]. Run maps: Y_last = P Y_before + Q,
+  // X_first = U X_after + V Y_before + W; run carries RY = Y_before, RX = X_after.
+  double* RP; double* RQ; double* RU; double* RV; double* RW; double* RY; double* RX;
+  // Deferred corrections (fine substeps): a segment's phase-1 output is left as
+  // z; the exact value z + chi Yin + phi Xin is formed by the next load of the
+  // node. Per segment: the segment whose correction its nodes carry when it is
+  // loaded at the first step (seg_src0: an earlier colour of the same step, or
+  // -1) and at later steps (seg_src1: the same, else the previous step's last
+  // colour covering it); per node: the segment whose correction it carries
+  // after the last substep (fin_seg).
+  const int* seg_src0; const int* seg_src1; const int* fin_seg;
 };
 
+// Phase 1. defer: apply the pending correction of the previous substeps on
+// load (stale_ok: the previous step's corrections exist) and leave this one
+// pending; otherwise the input carries no correction.
 hipError_t launch_dd_local(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
-                           int seg_begin, int seg_count, hipStream_t s);
-hipError_t launch_dd_carries(const DDInst* d, const DDInst& h, const DDFactors& f,
-                             const int* comp_first, const int* comp_count, int n_comps,
-                             hipStream_t s);
+                           int seg_begin, int seg_count, bool defer, bool stale_ok, hipStream_t s);
+// Interleaved Z with the pending corrections of the last substeps -> natural
+// F[slice][node].
+hipError_t launch_dd_from_interleaved(const DDInst* d, const DDInst& h, const DDFactors& f,
+                                      double* F, hipStream_t s);
+// Runs [run_begin, run_begin + run_count) of one colour; comp_run_first /
+// comp_run_count (device, n_comps entries) list each component's runs.
+hipError_t launch_dd_carries(const DDInst* d, const DDInst& h, const DDFactors& f, int run_begin,
+                             int run_count, const int* comp_run_first, const int* comp_run_count,
+                             int n_comps, hipStream_t s);
 hipError_t launch_dd_correct(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
                              int seg_begin, int seg_count, hipStream_t s);
 // Set-up: component LU (one thread per component) and segment factors.
 hipError_t launch_dd_faces(const double* rho, const double* a, int n, int n_colors, double* w,
                            hipStream_t s);
 hipError_t launch_dd_factorize(const double* w, int n, const int* comp_lo, const int* comp_hi,
-                               const int* comp_colour, int n_comps, double tau_over_h2, double* E,
-                               double* R, double* G, hipStream_t s);
+                               const int* comp_colour, int n_comps, double tau_over_h2, double* R,
+                               double* G, hipStream_t s);
 hipError_t launch_dd_segfactors(const DDSeg* segs, const int* seg_colour, int n_segs, int n,
-                                const double* E, const double* R, const double* G, double* CHI,
+                                const double* R, const double* G, double* CHI,
                                 double* PHI, double* PSIE, double* CHIA, double* PHIA,
                                 hipStream_t s);
+// Pending-correction factors of the deferred fine substeps (PC0, PP0, PC1,
+// PP1, FC, FP of f, written through the given non-const pointers).
+hipError_t launch_dd_pending(const DDInst* d, const DDInst& h, const DDFactors& f, double* PC0,
+                             double* PP0, double* PC1, double* PP1, double* FC, double* FP,
+                             hipStream_t s);
 // Parareal correction over whole states: U_next = F + (g - G_old), G_old = g,
-// increment (mode 1), or U_next = G_old = g (mode 2).
+// increment (mode 1), or U_next = G_old = g (mode 2). The increment goes to
+// partial[0 .. update_blocks(n)) as per-block maxima (see launch_inc_reduce).
+int update_blocks(size_t n);
 hipError_t launch_update(const double* g, const double* F, double* G_old, double* U_next,
-                         size_t n, int mode, unsigned long long* inc_bits, hipStream_t s);
+                         size_t n, int mode, unsigned long long* partial, hipStream_t s);
 
 // ---- adjoint (pr_kernels_adj.hip) ----
 hipError_t launch_face_grad_x(const double* nu, const double* W, int nx, int ny, double coef,

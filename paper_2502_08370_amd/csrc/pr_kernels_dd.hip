@@ -67,29 +67,32 @@ __global__ void k_dd_faces(const double* __restrict__ rho, const double* __restr
 
 // LU of I - tau A_k restricted to one component (nodes lo..hi), one thread
 // per component. Faces just outside a component carry rho_k = 0, so the
-// restricted matrix is the exact block of the substep.
+// restricted matrix is the exact block of the substep. The matrix is
+// symmetric, so the forward multiplier e_i = w_i / u_{i-1} equals
+// g_{i-1} = w_i r_{i-1}; it is formed as that product, and the kernels read it
+// as G[i-1] (0 at a component's first node, where the previous entry is the
+// end of another component or untouched zero).
 __global__ void k_dd_factorize(const double* __restrict__ w, int n,
                                const int* __restrict__ comp_lo, const int* __restrict__ comp_hi,
                                const int* __restrict__ comp_colour, int n_comps,
-                               double tau_over_h2, double* __restrict__ E,
-                               double* __restrict__ R, double* __restrict__ G) {
+                               double tau_over_h2, double* __restrict__ R,
+                               double* __restrict__ G) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_comps) return;
   const int lo = comp_lo[c], hi = comp_hi[c], k = comp_colour[c];
   const double* wk = w + (long)k * (n + 1);
   const long base = (long)k * n;
-  double u_prev = 1.0;
+  double r_prev = 0.0;
   double wl = tau_over_h2 * wk[lo];
   for (int i = lo; i <= hi; i++) {
     double wr = tau_over_h2 * wk[i + 1];
     double diag = 1.0 + wl + wr;
-    double e = (i == lo) ? 0.0 : wl / u_prev;
+    double e = (i == lo) ? 0.0 : wl * r_prev;
     double u = diag - wl * e;
     double r = 1.0 / u;
-    E[base + i] = e;
     R[base + i] = r;
     G[base + i] = (i < hi) ? wr * r : 0.0;
-    u_prev = u;
+    r_prev = r;
     wl = wr;
   }
 }
@@ -98,8 +101,8 @@ __global__ void k_dd_factorize(const double* __restrict__ w, int n,
 // g_i chi_{i+1} (chi past the end 0) and phi_i = g_i phi_{i+1} (phi past the
 // end 1), with psi_i the product of e from the segment start to i.
 __global__ void k_dd_segfactors(const DDSeg* __restrict__ segs, const int* __restrict__ seg_colour,
-                                int n_segs, int n, const double* __restrict__ E,
-                                const double* __restrict__ R, const double* __restrict__ G,
+                                int n_segs, int n, const double* __restrict__ R,
+                                const double* __restrict__ G,
                                 double* __restrict__ CHI, double* __restrict__ PHI,
                                 double* __restrict__ PSIE, double* __restrict__ CHIA,
                                 double* __restrict__ PHIA) {
@@ -109,7 +112,7 @@ __global__ void k_dd_segfactors(const DDSeg* __restrict__ segs, const int* __res
   const long base = (long)seg_colour[s] * n + sg.lo;
   double p = 1.0;
   for (int t = 0; t < sg.len; t++) {  // psi kept in CHI until the backward pass
-    p = p * E[base + t];
+    p = p * (sg.lo + t > 0 ? G[base + t - 1] : 0.0);  // e = g of the previous node
     CHI[base + t] = p;
   }
   PSIE[s] = p;
@@ -127,38 +130,26 @@ __global__ void k_dd_segfactors(const DDSeg* __restrict__ segs, const int* __res
 // ------------------------------------------------------------- phase 1 ---
 // Segment solves with zero carries: forward elimination (tilde y) and back
 // substitution (tilde z) of each segment, in place; records tilde y at the
-// segment's last node (Yb) and tilde z at its first node (Za).
-template <int L>
+// segment's last node (Yb) and tilde z at its first node (Za). With DEFER the
+// loaded values first receive the pending correction chi Yin + phi Xin of the
+// segment's source (see DDInst), and the segment's own correction is left
+// pending in turn.
+template <int L, bool DEFER>
 __global__ __launch_bounds__(kWave) void k_dd_local(const DDInst* __restrict__ insts, DDFactors f,
-                                                    int colour, int seg_begin, int seg_count) {
+                                                    int colour, int seg_begin, int seg_count,
+                                                    int stale_ok) {
   constexpr int G = kWave / L;
   constexpr int M = kDDSeg;
   constexpr int NQ = (G * M + kWave - 1) / kWave;
+  constexpr int NS = DEFER ? G : 1;
   __shared__ double sE[G][M + 1], sR[G][M + 1], sG[G][M + 1];
+  __shared__ double sC[NS][M + 1], sP[NS][M + 1];
   const DDInst& I = insts[0];
   const int lane = threadIdx.x, gsub = lane / L, sl = lane - gsub * L;
   const int b = blockIdx.y;
   const int s0 = blockIdx.x * G;
   const long cb = (long)colour * I.n;
-  const gdouble* E = gp(f.E) + cb;
-  const gdouble* R = gp(f.R) + cb;
-  const gdouble* Gf = gp(f.G) + cb;
-  // factors of the wave's segments; padded positions act as identity
-#pragma unroll
-  for (int qq = 0; qq < NQ; qq++) {
-    const int q = lane + qq * kWave;
-    if (q < G * M) {
-      const int g = q / M, t = q - g * M;
-      const int sidx = s0 + g;
-      const DDSeg sg = I.segs[seg_begin + min(sidx, seg_count - 1)];
-      const bool ok = sidx < seg_count && t < sg.len;
-      const long node = sg.lo + (ok ? t : 0);
-      sE[g][t] = ok ? E[node] : 1.0;
-      sR[g][t] = ok ? R[node] : 0.0;
-      sG[g][t] = ok ? Gf[node] : 0.0;
-    }
-  }
-  __syncthreads();
+  // the lane's segment values first (the longest-latency loads)
   const int sidx = s0 + gsub;
   const bool active = sidx < seg_count;
   const int sg_i = seg_begin + (active ? sidx : seg_count - 1);
@@ -166,7 +157,50 @@ __global__ __launch_bounds__(kWave) void k_dd_local(const DDInst* __restrict__ i
   gdouble* zb = gp(I.Z) + b * I.slab + (long)sg.lo * L + sl;
   double v[M];
 #pragma unroll
-  for (int t = 0; t < M; t++) v[t] = t < sg.len ? zb[(long)t * L] : 0.0;
+  for (int t = 0; t < M; t++) {
+    const double x = zb[(long)(t < sg.len ? t : 0) * L];
+    v[t] = t < sg.len ? x : 0.0;
+  }
+  // factors of the wave's segments; padded positions act as identity and
+  // carry no pending correction
+  const gdouble* R = gp(f.R) + cb;
+  const gdouble* Gf = gp(f.G) + cb;
+  const gdouble* PC = DEFER ? gp(stale_ok ? f.PC1 : f.PC0) + cb : nullptr;
+  const gdouble* PP = DEFER ? gp(stale_ok ? f.PP1 : f.PP0) + cb : nullptr;
+#pragma unroll
+  for (int qq = 0; qq < NQ; qq++) {
+    const int q = lane + qq * kWave;
+    if (q < G * M) {
+      const int g = q / M, t = q - g * M;
+      const int gidx = s0 + g;
+      const DDSeg gs = I.segs[seg_begin + min(gidx, seg_count - 1)];
+      const bool ok = gidx < seg_count && t < gs.len;
+      const long node = gs.lo + (ok ? t : 0);
+      // e = g of the previous node (same cache lines as g)
+      const double e = Gf[node > 0 ? node - 1 : 0], r = R[node], gg = Gf[node];
+      sE[g][t] = ok ? (node > 0 ? e : 0.0) : 1.0;
+      sR[g][t] = ok ? r : 0.0;
+      sG[g][t] = ok ? gg : 0.0;
+      if constexpr (DEFER) {
+        const double c = PC[node], p = PP[node];
+        sC[g][t] = ok ? c : 0.0;
+        sP[g][t] = ok ? p : 0.0;
+      }
+    }
+  }
+  double ys = 0.0, xs = 0.0;
+  if constexpr (DEFER) {
+    const int src = (stale_ok ? I.seg_src1 : I.seg_src0)[sg_i];
+    const long si = ((long)b * I.n_segs + (src >= 0 ? src : 0)) * L + sl;
+    const double yv = gp(I.Yin)[si], xv = gp(I.Xin)[si];
+    ys = src >= 0 ? yv : 0.0;
+    xs = src >= 0 ? xv : 0.0;
+  }
+  __syncthreads();
+  if constexpr (DEFER) {
+#pragma unroll
+    for (int t = 0; t < M; t++) v[t] = fma(sP[gsub][t], xs, fma(sC[gsub][t], ys, v[t]));
+  }
   double y = 0.0;
 #pragma unroll
   for (int t = 0; t < M; t++) {
@@ -189,82 +223,387 @@ __global__ __launch_bounds__(kWave) void k_dd_local(const DDInst* __restrict__ i
   }
 }
 
+// Pending-correction factors: for each node of each segment, chi and phi of
+// the colour whose correction the node carries when the segment's colour loads
+// it (first step / later steps); for each node, those of its final correction.
+__global__ void k_dd_pending(const DDInst* __restrict__ insts, DDFactors f,
+                             double* __restrict__ PC0, double* __restrict__ PP0,
+                             double* __restrict__ PC1, double* __restrict__ PP1,
+                             double* __restrict__ FC, double* __restrict__ FP) {
+  const DDInst& I = insts[0];
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nseg_nodes = (long)I.n_segs * kDDSeg;
+  if (t < nseg_nodes) {
+    const int si = (int)(t / kDDSeg), j = (int)(t - (long)si * kDDSeg);
+    const DDSeg sg = I.segs[si];
+    if (j >= sg.len) return;
+    const long node = sg.lo + j, at = (long)sg.colour * I.n + node;
+    const int s0 = I.seg_src0[si], s1 = I.seg_src1[si];
+    PC0[at] = s0 >= 0 ? f.CHI[(long)I.segs[s0].colour * I.n + node] : 0.0;
+    PP0[at] = s0 >= 0 ? f.PHI[(long)I.segs[s0].colour * I.n + node] : 0.0;
+    PC1[at] = s1 >= 0 ? f.CHI[(long)I.segs[s1].colour * I.n + node] : 0.0;
+    PP1[at] = s1 >= 0 ? f.PHI[(long)I.segs[s1].colour * I.n + node] : 0.0;
+  } else if (t < nseg_nodes + I.n) {
+    const long node = t - nseg_nodes;
+    const int fs = I.fin_seg[node];
+    FC[node] = fs >= 0 ? f.CHI[(long)I.segs[fs].colour * I.n + node] : 0.0;
+    FP[node] = fs >= 0 ? f.PHI[(long)I.segs[fs].colour * I.n + node] : 0.0;
+  }
+}
+
+// Final transpose of the deferred fine substeps: F[slice][node] = Z[b][node][l]
+// + chi Yin + phi Xin of the node's last segment; one block of 4 waves per
+// (64-node tile, slice block).
+__global__ __launch_bounds__(4 * kWave) void k_dd_from_interleaved(
+    const DDInst* __restrict__ insts, DDFactors f, double* __restrict__ F) {
+  __shared__ double tile[64][65];
+  const DDInst& I = insts[0];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int i0 = blockIdx.x * 64, b = blockIdx.y;
+  const int L = I.L, lg = 31 - __clz(L);
+  const int cnt = min(64, I.n - i0), n = cnt * L;
+  const gdouble* Zb = gp(I.Z) + b * I.slab + (long)i0 * L;
+  constexpr int kIt = 64 * 64 / (4 * kWave);
+  double z[kIt], c[kIt], p[kIt], yi[kIt], xi[kIt];
+#pragma unroll
+  for (int u = 0; u < kIt; u++) {
+    const int q = tid + 4 * kWave * u;
+    const bool ok = q < n;
+    const int t = ok ? q >> lg : 0, sl = q & (L - 1);
+    const int node = i0 + t;
+    const int fs0 = I.fin_seg[node];
+    const int fs = fs0 >= 0 ? fs0 : 0;  // FC = FP = 0 when there is none
+    const long bi = ((long)b * I.n_segs + fs) * L + sl;
+    z[u] = Zb[ok ? q : 0];
+    c[u] = gp(f.FC)[node];
+    p[u] = gp(f.FP)[node];
+    yi[u] = gp(I.Yin)[bi];
+    xi[u] = gp(I.Xin)[bi];
+  }
+#pragma unroll
+  for (int u = 0; u < kIt; u++) {
+    const int q = tid + 4 * kWave * u;
+    if (q < n) tile[q & (L - 1)][q >> lg] = fma(p[u], xi[u], fma(c[u], yi[u], z[u]));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kIt; u++) {
+    const int sl = w + 4 * u, slice = b * L + sl;
+    if (sl < L && slice < I.N && lane < cnt)
+      F[(long)slice * I.n + i0 + lane] = tile[sl][lane];
+  }
+}
+
 // ------------------------------------------------------------- phase 2 ---
 // Carry resolution per (component, slice): Y_s = Yb_s + psi_s Y_{s-1} over the
-// component's segments (wave scans, 64 segments per step), then
-// X_s = Za_s + chi_s Y_{s-1} + phi_s X_{s+1} backwards; stores
-// Yin_s = Y_{s-1} and Xin_s = X_{s+1}.
-__global__ __launch_bounds__(kWave) void k_dd_carries(const DDInst* __restrict__ insts,
-                                                      DDFactors f,
-                                                      const int* __restrict__ comp_first,
-                                                      const int* __restrict__ comp_count) {
+// component's segments, then X_s = Za_s + chi_s Y_{s-1} + phi_s X_{s+1}
+// backwards; stores Yin_s = Y_{s-1} and Xin_s = X_{s+1}. Three launches over
+// runs of kDDRun segments (see pr_internal.h); lanes are (run, slice).
+
+// Loads the carry inputs of a run's segments (identity maps past its end).
+template <int L>
+__device__ __forceinline__ void load_run(const DDInst& I, const DDFactors& f, const DDRun& rn,
+                                         int b, int sl, double (&yb)[kDDRun],
+                                         double (&za)[kDDRun], double (&ps)[kDDRun],
+                                         double (&ca)[kDDRun], double (&pa)[kDDRun]) {
+#pragma unroll
+  for (int t = 0; t < kDDRun; t++) {
+    const bool ok = t < rn.len;
+    const int sidx = rn.seg0 + (ok ? t : 0);
+    const long bi = ((long)b * I.n_segs + sidx) * L + sl;
+    const double y = gp(I.Yb)[bi], z = gp(I.Za)[bi];
+    const double p = gp(f.PSIE)[sidx], c = gp(f.CHIA)[sidx], h = gp(f.PHIA)[sidx];
+    yb[t] = ok ? y : 0.0;
+    za[t] = ok ? z : 0.0;
+    ps[t] = ok ? p : 1.0;
+    ca[t] = ok ? c : 0.0;
+    pa[t] = ok ? h : 1.0;
+  }
+}
+
+// 2a: run maps.
+template <int L>
+__global__ __launch_bounds__(kWave) void k_dd_runmaps(const DDInst* __restrict__ insts,
+                                                      DDFactors f, int run_begin, int run_count) {
+  constexpr int G = kWave / L;
+  const DDInst& I = insts[0];
+  const int lane = threadIdx.x, g = lane / L, sl = lane - g * L;
+  const int b = blockIdx.y;
+  const int rix = blockIdx.x * G + g;
+  const bool active = rix < run_count;
+  const int ri = run_begin + (active ? rix : run_count - 1);
+  const DDRun rn = I.runs[ri];
+  double yb[kDDRun], za[kDDRun], ps[kDDRun], ca[kDDRun], pa[kDDRun];
+  load_run<L>(I, f, rn, b, sl, yb, za, ps, ca, pa);
+  // forward: Y before segment t = pp[t] Y_before + qq[t]
+  double p = 1.0, q = 0.0, pp[kDDRun], qq[kDDRun];
+#pragma unroll
+  for (int t = 0; t < kDDRun; t++) {
+    pp[t] = p;
+    qq[t] = q;
+    q = fma(ps[t], q, yb[t]);
+    p = ps[t] * p;
+  }
+  // backward: X at segment t = u X_after + v Y_before + w
+  double u = 1.0, v = 0.0, w = 0.0;
+#pragma unroll
+  for (int t = kDDRun - 1; t >= 0; t--) {
+    w = fma(pa[t], w, fma(ca[t], qq[t], za[t]));
+    v = fma(pa[t], v, ca[t] * pp[t]);
+    u = pa[t] * u;
+  }
+  if (active) {
+    const long ridx = ((long)b * I.n_runs + ri) * L + sl;
+    gp(I.RP)[ridx] = p;
+    gp(I.RQ)[ridx] = q;
+    gp(I.RU)[ridx] = u;
+    gp(I.RV)[ridx] = v;
+    gp(I.RW)[ridx] = w;
+  }
+}
+
+// 2b: chains the runs of one component for one slice, 64 runs per wave step.
+// Components of up to kScanChunks * 64 runs take a path that issues every load
+// up front and keeps the forward results in registers.
+constexpr int kScanChunks = 4;
+
+__global__ __launch_bounds__(kWave) void k_dd_runscan(const DDInst* __restrict__ insts,
+                                                      const int* __restrict__ comp_run_first,
+                                                      const int* __restrict__ comp_run_count) {
   const DDInst& I = insts[0];
   const int lane = threadIdx.x;
   const int comp = blockIdx.x;
   const int slice = blockIdx.y;  // b * L + l
   const int b = slice / I.L, sl = slice - b * I.L;
-  const int first = comp_first[comp], count = comp_count[comp];
-  const long sb = (long)b * I.n_segs;
+  const int first = comp_run_first[comp], count = comp_run_count[comp];
+  const long rb = (long)b * I.n_runs;
   const int nch = (count + kWave - 1) / kWave;
+  if (nch <= kScanChunks) {
+    double rp[kScanChunks], rq[kScanChunks], ru[kScanChunks], rv[kScanChunks], rw[kScanChunks];
+    double ry[kScanChunks];
+#pragma unroll
+    for (int ch = 0; ch < kScanChunks; ch++) {
+      const int r = first + ch * kWave + lane;
+      const bool ok = r < first + count;
+      const long ri = (rb + (ok ? r : first)) * I.L + sl;
+      const double p = gp(I.RP)[ri], q = gp(I.RQ)[ri];
+      const double u = gp(I.RU)[ri], v = gp(I.RV)[ri], w = gp(I.RW)[ri];
+      rp[ch] = ok ? p : 1.0;  // identity past the end (forward)
+      rq[ch] = ok ? q : 0.0;
+      ru[ch] = ok ? u : 0.0;  // X = 0 after the component (backward)
+      rv[ch] = ok ? v : 0.0;
+      rw[ch] = ok ? w : 0.0;
+    }
+    double carry = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < kScanChunks; ch++) {
+      double a = rp[ch], bb = rq[ch];
+      affine_scan_up(a, bb, lane);
+      const double Y = fma(a, carry, bb);
+      double prev = __shfl_up(Y, 1, kWave);
+      if (lane == 0) prev = carry;
+      ry[ch] = prev;
+      carry = lane_value(Y, kWave - 1);
+    }
+    carry = 0.0;
+#pragma unroll
+    for (int ch = kScanChunks - 1; ch >= 0; ch--) {
+      double a = ru[ch], bb = fma(rv[ch], ry[ch], rw[ch]);
+      affine_scan_down(a, bb, lane);
+      const double X = fma(a, carry, bb);
+      double next = __shfl_down(X, 1, kWave);
+      if (lane == kWave - 1) next = carry;
+      const int r = first + ch * kWave + lane;
+      if (r < first + count) {
+        const long ri = (rb + r) * I.L + sl;
+        gp(I.RY)[ri] = ry[ch];
+        gp(I.RX)[ri] = next;
+      }
+      carry = lane_value(X, 0);
+    }
+    return;
+  }
   double carry = 0.0;
   for (int ch = 0; ch < nch; ch++) {
-    const int s = first + ch * kWave + lane;
-    const bool ok = s < first + count;
-    const long bi = (sb + (ok ? s : first)) * I.L + sl;
-    double a = ok ? f.PSIE[s] : 1.0;
-    double bb = ok ? I.Yb[bi] : 0.0;
+    const int r = first + ch * kWave + lane;
+    const bool ok = r < first + count;
+    const long ri = (rb + (ok ? r : first)) * I.L + sl;
+    const double rp = gp(I.RP)[ri], rq = gp(I.RQ)[ri];
+    double a = ok ? rp : 1.0;
+    double bb = ok ? rq : 0.0;
     affine_scan_up(a, bb, lane);
     const double Y = fma(a, carry, bb);
     double prev = __shfl_up(Y, 1, kWave);
     if (lane == 0) prev = carry;
-    if (ok) I.Yin[bi] = prev;
+    if (ok) gp(I.RY)[ri] = prev;
     carry = lane_value(Y, kWave - 1);
   }
   carry = 0.0;
   for (int ch = nch - 1; ch >= 0; ch--) {
-    const int s = first + ch * kWave + lane;
-    const bool ok = s < first + count;
-    const long bi = (sb + (ok ? s : first)) * I.L + sl;
-    double a = ok ? f.PHIA[s] : 0.0;
-    double bb = ok ? fma(f.CHIA[s], I.Yin[bi], I.Za[bi]) : 0.0;
+    const int r = first + ch * kWave + lane;
+    const bool ok = r < first + count;
+    const long ri = (rb + (ok ? r : first)) * I.L + sl;
+    const double ru = gp(I.RU)[ri], rv = gp(I.RV)[ri], rw = gp(I.RW)[ri], ry = gp(I.RY)[ri];
+    double a = ok ? ru : 0.0;
+    double bb = ok ? fma(rv, ry, rw) : 0.0;
     affine_scan_down(a, bb, lane);
     const double X = fma(a, carry, bb);
     double next = __shfl_down(X, 1, kWave);
     if (lane == kWave - 1) next = carry;
-    if (ok) I.Xin[bi] = next;
+    if (ok) gp(I.RX)[ri] = next;
     carry = lane_value(X, 0);
   }
 }
 
+// 2c: carries of every segment from its run's carries.
+template <int L>
+__global__ __launch_bounds__(kWave) void k_dd_segcarries(const DDInst* __restrict__ insts,
+                                                         DDFactors f, int run_begin,
+                                                         int run_count) {
+  constexpr int G = kWave / L;
+  const DDInst& I = insts[0];
+  const int lane = threadIdx.x, g = lane / L, sl = lane - g * L;
+  const int b = blockIdx.y;
+  const int rix = blockIdx.x * G + g;
+  const bool active = rix < run_count;
+  const int ri = run_begin + (active ? rix : run_count - 1);
+  const DDRun rn = I.runs[ri];
+  double yb[kDDRun], za[kDDRun], ps[kDDRun], ca[kDDRun], pa[kDDRun];
+  load_run<L>(I, f, rn, b, sl, yb, za, ps, ca, pa);
+  const long ridx = ((long)b * I.n_runs + ri) * L + sl;
+  double Y = gp(I.RY)[ridx];
+  double X = gp(I.RX)[ridx];
+  double yin[kDDRun], xin[kDDRun];
+#pragma unroll
+  for (int t = 0; t < kDDRun; t++) {
+    yin[t] = Y;
+    Y = fma(ps[t], Y, yb[t]);
+  }
+#pragma unroll
+  for (int t = kDDRun - 1; t >= 0; t--) {
+    xin[t] = X;
+    X = fma(pa[t], X, fma(ca[t], yin[t], za[t]));
+  }
+  if (active) {
+#pragma unroll
+    for (int t = 0; t < kDDRun; t++)
+      if (t < rn.len) {
+        const long bi = ((long)b * I.n_segs + rn.seg0 + t) * L + sl;
+        gp(I.Yin)[bi] = yin[t];
+        gp(I.Xin)[bi] = xin[t];
+      }
+  }
+}
+
 // ------------------------------------------------------------- phase 3 ---
+// x = z + chi Yin + phi Xin over each segment; chi and phi of the wave's
+// segments are staged in LDS, and every value load is issued before the first
+// store.
 template <int L>
 __global__ __launch_bounds__(kWave) void k_dd_correct(const DDInst* __restrict__ insts,
                                                       DDFactors f, int colour, int seg_begin,
                                                       int seg_count) {
   constexpr int G = kWave / L;
   constexpr int M = kDDSeg;
+  constexpr int NQ = (G * M + kWave - 1) / kWave;
+  __shared__ double sC[G][M + 1], sP[G][M + 1];
   const DDInst& I = insts[0];
   const int lane = threadIdx.x, gsub = lane / L, sl = lane - gsub * L;
   const int b = blockIdx.y;
-  const int sidx = blockIdx.x * G + gsub;
-  if (sidx >= seg_count) return;
-  const int sg_i = seg_begin + sidx;
+  const int s0 = blockIdx.x * G;
+  const long cb = (long)colour * I.n;
+#pragma unroll
+  for (int qq = 0; qq < NQ; qq++) {
+    const int q = lane + qq * kWave;
+    if (q < G * M) {
+      const int g = q / M, t = q - g * M;
+      const int sidx = s0 + g;
+      const DDSeg sg = I.segs[seg_begin + min(sidx, seg_count - 1)];
+      const long node = cb + sg.lo + (t < sg.len ? t : 0);
+      sC[g][t] = gp(f.CHI)[node];
+      sP[g][t] = gp(f.PHI)[node];
+    }
+  }
+  const int sidx = s0 + gsub;
+  const bool active = sidx < seg_count;
+  const int sg_i = seg_begin + (active ? sidx : seg_count - 1);
   const DDSeg sg = I.segs[sg_i];
   const long bi = ((long)b * I.n_segs + sg_i) * L + sl;
   const double yin = gp(I.Yin)[bi], xin = gp(I.Xin)[bi];
-  const long cb = (long)colour * I.n + sg.lo;
-  const gdouble* chi = gp(f.CHI) + cb;
-  const gdouble* phi = gp(f.PHI) + cb;
   gdouble* zb = gp(I.Z) + b * I.slab + (long)sg.lo * L + sl;
-#pragma unroll 8
-  for (int t = 0; t < M; t++)
-    if (t < sg.len) zb[(long)t * L] = fma(phi[t], xin, fma(chi[t], yin, zb[(long)t * L]));
+  double v[M];
+#pragma unroll
+  for (int t = 0; t < M; t++) v[t] = zb[(long)(t < sg.len ? t : 0) * L];
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int t = 0; t < M; t++)
+      if (t < sg.len) zb[(long)t * L] = fma(sP[gsub][t], xin, fma(sC[gsub][t], yin, v[t]));
+  }
+}
+
+// Single state (L = 1): one wave per segment, lane = node. The zero-carry
+// segment solve is one forward and one backward affine scan across the lanes.
+__global__ __launch_bounds__(4 * kWave) void k_dd_local1(const DDInst* __restrict__ insts,
+                                                         DDFactors f, int colour, int seg_begin,
+                                                         int seg_count) {
+  const DDInst& I = insts[0];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = blockIdx.x * 4 + threadIdx.x / kWave;
+  if (w >= seg_count) return;  // whole wave; no block-level barrier follows
+  const int si = seg_begin + w;
+  const DDSeg sg = I.segs[si];
+  const bool ok = lane < sg.len;
+  const long node = sg.lo + (ok ? lane : 0);
+  const long cb = (long)colour * I.n;
+  const double em = gp(f.G)[cb + (node > 0 ? node - 1 : 0)];
+  const double e = node > 0 ? em : 0.0;  // e = g of the previous node
+  const double r = gp(f.R)[cb + node], g = gp(f.G)[cb + node];
+  const double z0 = gp(I.Z)[node];
+  // forward: y_t = e_t y_{t-1} + d_t from y = 0 before the segment (e = 1,
+  // d = 0 past its end)
+  double a = ok ? e : 1.0, bb = ok ? z0 : 0.0;
+  affine_scan_up(a, bb, lane);
+  const double y = bb;
+  // backward: z_t = g_t z_{t+1} + r_t y_t from z = 0 after the segment
+  a = ok ? g : 0.0;
+  bb = ok ? r * y : 0.0;
+  affine_scan_down(a, bb, lane);
+  const double z = bb;
+  if (ok) gp(I.Z)[node] = z;
+  const double ylast = lane_value(y, sg.len - 1), zfirst = lane_value(z, 0);
+  if (lane == 0) {
+    gp(I.Yb)[si] = ylast;
+    gp(I.Za)[si] = zfirst;
+  }
+}
+
+__global__ __launch_bounds__(4 * kWave) void k_dd_correct1(const DDInst* __restrict__ insts,
+                                                           DDFactors f, int colour,
+                                                           int seg_begin, int seg_count) {
+  const DDInst& I = insts[0];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = blockIdx.x * 4 + threadIdx.x / kWave;
+  if (w >= seg_count) return;
+  const int si = seg_begin + w;
+  const DDSeg sg = I.segs[si];
+  if (lane >= sg.len) return;
+  const long node = sg.lo + lane;
+  const long cb = (long)colour * I.n;
+  const double yin = gp(I.Yin)[si], xin = gp(I.Xin)[si];
+  gp(I.Z)[node] =
+      fma(gp(f.PHI)[cb + node], xin, fma(gp(f.CHI)[cb + node], yin, gp(I.Z)[node]));
 }
 
 // ------------------------------------------------------ parareal update ---
-__global__ void k_update(const double* __restrict__ g, const double* __restrict__ F,
-                         double* __restrict__ Gold, double* __restrict__ Unext, size_t n, int mode,
-                         unsigned long long* __restrict__ inc_bits) {
+// Whole-state update; the block's largest |change| (mode 1) goes to
+// partial[block] (plain read-modify-write: launches run in stream order).
+__global__ __launch_bounds__(256) void k_update(const double* __restrict__ g,
+                                                const double* __restrict__ F,
+                                                double* __restrict__ Gold,
+                                                double* __restrict__ Unext, size_t n, int mode,
+                                                unsigned long long* __restrict__ partial) {
+  __shared__ unsigned long long wm[4];
   size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   unsigned long long mx = 0;
@@ -285,7 +624,12 @@ __global__ void k_update(const double* __restrict__ g, const double* __restrict_
       unsigned long long o = __shfl_xor(mx, off, kWave);
       mx = o > mx ? o : mx;
     }
-    if ((threadIdx.x & (kWave - 1)) == 0 && mx != 0) atomicMax(inc_bits, mx);
+    if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < 4; w++) mx = wm[w] > mx ? wm[w] : mx;
+      if (mx > partial[blockIdx.x]) partial[blockIdx.x] = mx;
+    }
   }
 }
 
@@ -300,51 +644,104 @@ hipError_t launch_dd_faces(const double* rho, const double* a, int n, int n_colo
 }
 
 hipError_t launch_dd_factorize(const double* w, int n, const int* comp_lo, const int* comp_hi,
-                               const int* comp_colour, int n_comps, double tau_over_h2, double* E,
-                               double* R, double* G, hipStream_t s) {
+                               const int* comp_colour, int n_comps, double tau_over_h2, double* R,
+                               double* G, hipStream_t s) {
   hipLaunchKernelGGL(k_dd_factorize, dim3((n_comps + 63) / 64), dim3(64), 0, s, w, n, comp_lo,
-                     comp_hi, comp_colour, n_comps, tau_over_h2, E, R, G);
+                     comp_hi, comp_colour, n_comps, tau_over_h2, R, G);
   return hipGetLastError();
 }
 
 hipError_t launch_dd_segfactors(const DDSeg* segs, const int* seg_colour, int n_segs, int n,
-                                const double* E, const double* R, const double* G, double* CHI,
+                                const double* R, const double* G, double* CHI,
                                 double* PHI, double* PSIE, double* CHIA, double* PHIA,
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_dd_segfactors, dim3((n_segs + 63) / 64), dim3(64), 0, s, segs, seg_colour,
-                     n_segs, n, E, R, G, CHI, PHI, PSIE, CHIA, PHIA);
+                     n_segs, n, R, G, CHI, PHI, PSIE, CHIA, PHIA);
+  return hipGetLastError();
+}
+
+template <int L, bool DEFER>
+static hipError_t dd_local_t(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
+                             int seg_begin, int seg_count, bool stale_ok, hipStream_t s) {
+  constexpr int G = kWave / L;
+  dim3 grid((seg_count + G - 1) / G, h.B);
+  hipLaunchKernelGGL((k_dd_local<L, DEFER>), grid, dim3(kWave), 0, s, d, f, colour, seg_begin,
+                     seg_count, (int)stale_ok);
   return hipGetLastError();
 }
 
 template <int L>
-static hipError_t dd_local_t(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
-                             int seg_begin, int seg_count, hipStream_t s) {
-  constexpr int G = kWave / L;
-  dim3 grid((seg_count + G - 1) / G, h.B);
-  hipLaunchKernelGGL((k_dd_local<L>), grid, dim3(kWave), 0, s, d, f, colour, seg_begin, seg_count);
-  return hipGetLastError();
+static hipError_t dd_local_l(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
+                             int seg_begin, int seg_count, bool defer, bool stale_ok,
+                             hipStream_t s) {
+  return defer ? dd_local_t<L, true>(d, h, f, colour, seg_begin, seg_count, stale_ok, s)
+               : dd_local_t<L, false>(d, h, f, colour, seg_begin, seg_count, stale_ok, s);
 }
 
 hipError_t launch_dd_local(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
-                           int seg_begin, int seg_count, hipStream_t s) {
+                           int seg_begin, int seg_count, bool defer, bool stale_ok,
+                           hipStream_t s) {
   if (seg_count <= 0) return hipSuccess;
   switch (h.L) {
-    case 1: return dd_local_t<1>(d, h, f, colour, seg_begin, seg_count, s);
-    case 8: return dd_local_t<8>(d, h, f, colour, seg_begin, seg_count, s);
-    case 16: return dd_local_t<16>(d, h, f, colour, seg_begin, seg_count, s);
-    case 32: return dd_local_t<32>(d, h, f, colour, seg_begin, seg_count, s);
-    case 64: return dd_local_t<64>(d, h, f, colour, seg_begin, seg_count, s);
+    case 1:
+      if (defer) return hipErrorInvalidValue;  // single states are corrected in place
+      hipLaunchKernelGGL(k_dd_local1, dim3((seg_count + 3) / 4), dim3(4 * kWave), 0, s, d, f,
+                         colour, seg_begin, seg_count);
+      return hipGetLastError();
+    case 8: return dd_local_l<8>(d, h, f, colour, seg_begin, seg_count, defer, stale_ok, s);
+    case 16: return dd_local_l<16>(d, h, f, colour, seg_begin, seg_count, defer, stale_ok, s);
+    case 32: return dd_local_l<32>(d, h, f, colour, seg_begin, seg_count, defer, stale_ok, s);
+    case 64: return dd_local_l<64>(d, h, f, colour, seg_begin, seg_count, defer, stale_ok, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_dd_carries(const DDInst* d, const DDInst& h, const DDFactors& f,
-                             const int* comp_first, const int* comp_count, int n_comps,
+hipError_t launch_dd_pending(const DDInst* d, const DDInst& h, const DDFactors& f, double* PC0,
+                             double* PP0, double* PC1, double* PP1, double* FC, double* FP,
                              hipStream_t s) {
-  if (n_comps <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dd_carries, dim3(n_comps, h.B * h.L), dim3(kWave), 0, s, d, f, comp_first,
-                     comp_count);
+  const long total = (long)h.n_segs * kDDSeg + h.n;
+  hipLaunchKernelGGL(k_dd_pending, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d, f,
+                     PC0, PP0, PC1, PP1, FC, FP);
   return hipGetLastError();
+}
+
+hipError_t launch_dd_from_interleaved(const DDInst* d, const DDInst& h, const DDFactors& f,
+                                      double* F, hipStream_t s) {
+  hipLaunchKernelGGL(k_dd_from_interleaved, dim3((h.n + 63) / 64, h.B), dim3(4 * kWave), 0, s, d,
+                     f, F);
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t dd_carries_t(const DDInst* d, const DDInst& h, const DDFactors& f,
+                               int run_begin, int run_count, const int* comp_run_first,
+                               const int* comp_run_count, int n_comps, hipStream_t s) {
+  constexpr int G = kWave / L;
+  const dim3 grid((run_count + G - 1) / G, h.B);
+  hipLaunchKernelGGL((k_dd_runmaps<L>), grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
+  hipLaunchKernelGGL(k_dd_runscan, dim3(n_comps, h.B * h.L), dim3(kWave), 0, s, d, comp_run_first,
+                     comp_run_count);
+  hipLaunchKernelGGL((k_dd_segcarries<L>), grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd_carries(const DDInst* d, const DDInst& h, const DDFactors& f, int run_begin,
+                             int run_count, const int* comp_run_first, const int* comp_run_count,
+                             int n_comps, hipStream_t s) {
+  if (n_comps <= 0 || run_count <= 0) return hipSuccess;
+  switch (h.L) {
+    case 1: return dd_carries_t<1>(d, h, f, run_begin, run_count, comp_run_first, comp_run_count,
+                                   n_comps, s);
+    case 8: return dd_carries_t<8>(d, h, f, run_begin, run_count, comp_run_first, comp_run_count,
+                                   n_comps, s);
+    case 16: return dd_carries_t<16>(d, h, f, run_begin, run_count, comp_run_first,
+                                     comp_run_count, n_comps, s);
+    case 32: return dd_carries_t<32>(d, h, f, run_begin, run_count, comp_run_first,
+                                     comp_run_count, n_comps, s);
+    case 64: return dd_carries_t<64>(d, h, f, run_begin, run_count, comp_run_first,
+                                     comp_run_count, n_comps, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int L>
@@ -361,7 +758,10 @@ hipError_t launch_dd_correct(const DDInst* d, const DDInst& h, const DDFactors& 
                              int seg_begin, int seg_count, hipStream_t s) {
   if (seg_count <= 0) return hipSuccess;
   switch (h.L) {
-    case 1: return dd_correct_t<1>(d, h, f, colour, seg_begin, seg_count, s);
+    case 1:
+      hipLaunchKernelGGL(k_dd_correct1, dim3((seg_count + 3) / 4), dim3(4 * kWave), 0, s, d, f,
+                         colour, seg_begin, seg_count);
+      return hipGetLastError();
     case 8: return dd_correct_t<8>(d, h, f, colour, seg_begin, seg_count, s);
     case 16: return dd_correct_t<16>(d, h, f, colour, seg_begin, seg_count, s);
     case 32: return dd_correct_t<32>(d, h, f, colour, seg_begin, seg_count, s);
@@ -370,12 +770,13 @@ hipError_t launch_dd_correct(const DDInst* d, const DDInst& h, const DDFactors& 
   }
 }
 
+int update_blocks(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 2048); }
+
 hipError_t launch_update(const double* g, const double* F, double* G_old, double* U_next,
-                         size_t n, int mode, unsigned long long* inc_bits, hipStream_t s) {
+                         size_t n, int mode, unsigned long long* partial, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_update, dim3(blocks), dim3(256), 0, s, g, F, G_old, U_next, n, mode,
-                     inc_bits);
+  hipLaunchKernelGGL(k_update, dim3(update_blocks(n)), dim3(256), 0, s, g, F, G_old, U_next, n,
+                     mode, partial);
   return hipGetLastError();
 }
 

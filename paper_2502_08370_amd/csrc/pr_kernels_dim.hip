@@ -782,7 +782,7 @@ __global__ __launch_bounds__(256) void k_inc_reduce(const DimInst* __restrict__ 
   const DimInst& I = insts[blockIdx.x];
   if (!I.incp) return;  // block-uniform
   const int tid = threadIdx.x;
-  const int nb = (I.nx + kColsPerBlock - 1) / kColsPerBlock;
+  const int nb = I.n_incp;
   unsigned long long m = 0;
   for (int b = tid; b < nb; b += 256) m = I.incp[b] > m ? I.incp[b] : m;
   m = wave_max_u64(m);
