@@ -268,12 +268,17 @@ def main():
         bytes_per_sweep = 16.0 * npts * N  # one substep: read + write one FP64 per point per slice
     achieved = bytes_per_sweep / (sweep_avg_ms * 1e-3) / 1e9
     traffic = None
+    tb = None
+    csrc = os.path.join(ROOT, "paper_2502_08370_amd", "csrc")
     if w.split != "dd" and (w.nx, w.n_slices, w.fine_steps) == (1023, 64, 64):
-        tb = measured_traffic(os.path.join(ROOT, "paper_2502_08370_amd", "csrc", "pr_kernels_dim.hip"),
+        tb = measured_traffic(os.path.join(csrc, "pr_kernels_dim.hip"),
                               os.path.join(ROOT, "profiles", "pmc_fine_sweep_varcoef2d_1023_N64_s64.json"))
-        if tb is not None:
-            traffic = {"gbs": round(tb / (sweep_avg_ms * 1e-3) / 1e9, 1), "bytes_per_launch": tb,
-                       "over_algorithmic": round(tb / bytes_per_sweep, 4)}
+    elif w.split == "dd" and (w.nx, w.n_slices, w.fine_steps) == (1 << 20, 32, 128):
+        tb = measured_traffic(os.path.join(csrc, "pr_kernels_dd.hip"),
+                              os.path.join(ROOT, "profiles", "pmc_dd_substep_dd1d_1048576_M2_N32_s128.json"))
+    if tb is not None:
+        traffic = {"gbs": round(tb / (sweep_avg_ms * 1e-3) / 1e9, 1), "bytes_per_launch": tb,
+                   "over_algorithmic": round(tb / bytes_per_sweep, 4)}
     fine_ms = (phases["fine_sweep"][0] + phases.get("fine_transpose", (0, 0))[0]) / args.steps
     coarse_ms = (phases.get("coarse_x", (0, 0))[0] + phases.get("coarse_y", (0, 0))[0]) / args.steps
 
@@ -289,8 +294,8 @@ def main():
                    "step": "one parareal iteration: F^s on all slices + serial coarse sweep "
                            "with correction and increment"},
         "roofline": {"bound": "hbm",
-                     "kernel": ("dd substep (k_dd_local + k_dd_carries + k_dd_correct)"
-                                if w.split == "dd" else "k_fine_sweep"),
+                     "kernel": ("dd substep (k_dd_local + k_dd_runmaps + k_dd_runscan + "
+                                "k_dd_segcarries)" if w.split == "dd" else "k_fine_sweep"),
                      "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic["gbs"] if traffic else None,

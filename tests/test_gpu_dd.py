@@ -102,3 +102,38 @@ def test_dd_full_size_sampled():
     torch.cuda.synchronize()
     g1 = U.cpu().numpy()[w.nx: 2 * w.nx]
     assert relerr(g1, O.coarse(w.u0)) <= TOL
+
+
+def random_pou(n, n_colors, seed, max_cover=3):
+    """Random partition of unity: every face gets a random set of 1..max_cover
+    colours with positive weights summing to 1. Components are short and
+    fragmented, nodes are covered by up to max_cover + 1 colours, and colours
+    meet in every order: the hard cases for the deferred-correction sources."""
+    rng = np.random.default_rng(seed)
+    rho = np.zeros((n_colors, n + 1))
+    for f in range(n + 1):
+        k = rng.integers(1, min(max_cover, n_colors) + 1)
+        cols = rng.choice(n_colors, size=k, replace=False)
+        wts = rng.random(k) + 0.05
+        rho[cols, f] = wts / wts.sum()
+    rho /= rho.sum(axis=0, keepdims=True)
+    return rho
+
+
+@pytest.mark.parametrize("n,colors,N,s,seed", [(300, 3, 3, 3, 1), (517, 4, 40, 2, 2),
+                                               (129, 2, 9, 4, 3), (700, 5, 5, 2, 4)])
+def test_dd_random_partition(n, colors, N, s, seed):
+    w = W.small_dd1(n, 1, 1, 0, n_slices=N, fine_steps=s, seed=seed, T=1e-3)
+    w.rho = random_pou(n, colors, seed)
+    P, O = gpu_problem(w), oracle_problem(w)
+    Uin = slice_inputs(w, seed=5)
+    F = P.new_slices()
+    P.fine_propagate(dev(Uin), F)
+    torch.cuda.synchronize()
+    ref = O.fine_batch(Uin)
+    assert relerr(F.cpu().numpy().reshape(ref.shape), ref) <= TOL
+    U = P.new_states()
+    k, inc = P.parareal_iterate(dev(w.u0), U, k_max=2, tol=0.0)
+    torch.cuda.synchronize()
+    Uo, ko, _ = O.parareal(w.u0, 2)
+    assert relerr(U.cpu().numpy().reshape(Uo.shape), Uo) <= TOL
