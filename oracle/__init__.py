@@ -31,6 +31,7 @@ class OrProblem(C.Structure):
         ("c", C.c_double),
         ("ax", _dp), ("ay", _dp),
         ("n_colors", C.c_int), ("rho", _dp),
+        ("n_forcing", C.c_int), ("fS", _dp), ("fg_fine", _dp), ("fg_coarse", _dp),
     ]
 
 
@@ -59,10 +60,10 @@ def lib():
         L.or_faces_from_theta_1d.argtypes = [C.c_int, _dp, _dp]
         L.or_apply_A.argtypes = [P, _dp, _dp]
         L.or_apply_Aj.argtypes = [P, C.c_int, _dp, _dp]
-        L.or_fie_step.argtypes = [P, C.c_double, _dp]
-        L.or_dr_step.argtypes = [P, C.c_double, _dp]
-        L.or_fine.argtypes = [P, _dp]
-        L.or_coarse.argtypes = [P, _dp]
+        L.or_fie_step.argtypes = [P, C.c_double, _dp, _dp]
+        L.or_dr_step.argtypes = [P, C.c_double, _dp, _dp]
+        L.or_fine.argtypes = [P, C.c_int, _dp]
+        L.or_coarse.argtypes = [P, C.c_int, _dp]
         L.or_fine_batch.argtypes = [P, C.c_int, _dp, _dp]
         L.or_sequential_fine.argtypes = [P, _dp, _dp]
         L.or_coarse_sweep.argtypes = [P, _dp, _dp, _dp]
@@ -92,11 +93,14 @@ class Problem:
     dim: 1 or 2; nx, ny: interior nodes; T, n_slices (N_c), fine_steps (s),
     coarse_steps; split: 'dim' or 'dd'; fine: 'fie' or 'dr'; c: reaction;
     ax (ny, nx+1) / ay (ny+1, nx): face coefficients; rho (M, nx+1): partition
-    of unity face weights for the domain-decomposition split (1D).
+    of unity face weights for the domain-decomposition split (1D); forcing:
+    None or (S, g_fine, g_coarse) with S (m, ny, nx) the spatial factors of the
+    source F(t) = sum_m g_m(t) S_m and g_fine (m, N*s), g_coarse (m, N*cs) its
+    time factors at the fine / coarse step end times (see oracle.h).
     """
 
     def __init__(self, *, dim, nx, ny, T, n_slices, fine_steps, coarse_steps=1, split="dim",
-                 fine="fie", c=0.0, ax, ay=None, rho=None):
+                 fine="fie", c=0.0, ax, ay=None, rho=None, forcing=None):
         self.dim, self.nx, self.ny = int(dim), int(nx), int(ny)
         if self.dim == 1:
             self.ny = 1
@@ -106,11 +110,20 @@ class Problem:
         self.ax = _f64(ax).reshape(self.ny, self.nx + 1)
         self.ay = None if ay is None else _f64(ay).reshape(self.ny + 1, self.nx)
         self.rho = None if rho is None else _f64(rho).reshape(-1, self.nx + 1)
+        self.fS = self.fgf = self.fgc = None
+        nf = 0
+        if forcing is not None:
+            S, gf, gc = forcing
+            nf = int(np.asarray(S).shape[0])
+            self.fS = _f64(S).reshape(nf, self.nx * self.ny)
+            self.fgf = _f64(gf).reshape(nf, self.n_slices * self.fine_steps)
+            self.fgc = _f64(gc).reshape(nf, self.n_slices * self.coarse_steps)
         self._s = OrProblem(
             self.dim, self.nx, self.ny, self.T, self.n_slices, self.fine_steps, self.coarse_steps,
             1 if split == "dd" else 0, 1 if fine == "dr" else 0, self.c,
             _ptr(self.ax), _ptr(self.ay),
-            0 if self.rho is None else self.rho.shape[0], _ptr(self.rho))
+            0 if self.rho is None else self.rho.shape[0], _ptr(self.rho),
+            nf, _ptr(self.fS), _ptr(self.fgf), _ptr(self.fgc))
 
     @property
     def npts(self):
@@ -138,24 +151,26 @@ class Problem:
         lib().or_apply_Aj(self._p(), int(j), _ptr(u), _ptr(out))
         return out
 
-    def fie_step(self, u, tau):
+    def fie_step(self, u, tau, F=None):
         u = self.state(u)
-        lib().or_fie_step(self._p(), float(tau), _ptr(u))
+        lib().or_fie_step(self._p(), float(tau), _ptr(None if F is None else self.state(F)), _ptr(u))
         return u
 
-    def dr_step(self, u, tau):
+    def dr_step(self, u, tau, F=None):
         u = self.state(u)
-        lib().or_dr_step(self._p(), float(tau), _ptr(u))
+        lib().or_dr_step(self._p(), float(tau), _ptr(None if F is None else self.state(F)), _ptr(u))
         return u
 
-    def fine(self, u):
+    def fine(self, u, n=0):
+        """Fine propagator over coarse interval n."""
         u = self.state(u)
-        lib().or_fine(self._p(), _ptr(u))
+        lib().or_fine(self._p(), int(n), _ptr(u))
         return u
 
-    def coarse(self, u):
+    def coarse(self, u, n=0):
+        """Coarse propagator over coarse interval n."""
         u = self.state(u)
-        lib().or_coarse(self._p(), _ptr(u))
+        lib().or_coarse(self._p(), int(n), _ptr(u))
         return u
 
     def fine_batch(self, U):

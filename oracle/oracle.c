@@ -204,15 +204,17 @@ void or_faces_from_theta(int nx, int ny, const double* theta, double* ax, double
       }
 }
 
-/* FIE, eq. FIE_method with F = 0: (I - tau A_1) U_1 = U_n,
+/* FIE, eq. FIE_method: (I - tau A_1) U_1 = U_n + tau F_{n+1},
  * (I - tau A_j) U_j = U_{j-1}, U_{n+1} = U_M. */
-void or_fie_step(const or_problem* p, double tau, double* U) {
+void or_fie_step(const or_problem* p, double tau, const double* F, double* U) {
+  if (F)
+    for (int k = 0; k < npts_of(p); k++) U[k] = U[k] + tau * F[k];
   for (int j = 0; j < n_terms(p); j++) implicit_substep(p, j, tau, U);
 }
 
-/* Douglas-Rachford, eq. DR_method with F = 0:
- * U_0 = (I + tau A) U_n, (I - tau A_j) U_j = U_{j-1} - tau A_j U_n. */
-void or_dr_step(const or_problem* p, double tau, double* U) {
+/* Douglas-Rachford, eq. DR_method:
+ * U_0 = (I + tau A) U_n + tau F_{n+1}, (I - tau A_j) U_j = U_{j-1} - tau A_j U_n. */
+void or_dr_step(const or_problem* p, double tau, const double* F, double* U) {
   const int npts = npts_of(p);
   double* Un = (double*)malloc(sizeof(double) * npts);
   double* AU = (double*)malloc(sizeof(double) * npts);
@@ -220,6 +222,8 @@ void or_dr_step(const or_problem* p, double tau, double* U) {
   memcpy(Un, U, sizeof(double) * npts);
   or_apply_A(p, Un, AU);
   for (int k = 0; k < npts; k++) V[k] = Un[k] + tau * AU[k];
+  if (F)
+    for (int k = 0; k < npts; k++) V[k] = V[k] + tau * F[k];
   for (int j = 0; j < n_terms(p); j++) {
     or_apply_Aj(p, j, Un, AU);
     for (int k = 0; k < npts; k++) V[k] = V[k] - tau * AU[k];
@@ -231,30 +235,53 @@ void or_dr_step(const or_problem* p, double tau, double* U) {
   free(V);
 }
 
-/* Fine propagator: s steps of the fine method at dt = DT/s (section 3). */
-void or_fine(const or_problem* p, double* U) {
+/* Source F at one time level: F = sum_m table[m*stride + idx] S_m. Returns
+ * NULL (F = 0) when the problem has no source terms. */
+static double* source_at(const or_problem* p, const double* table, long stride, long idx) {
+  if (p->n_forcing <= 0) return NULL;
+  const long npts = npts_of(p);
+  double* F = (double*)calloc(npts, sizeof(double));
+  for (int m = 0; m < p->n_forcing; m++) {
+    const double g = table[m * stride + idx];
+    for (long q = 0; q < npts; q++) F[q] = F[q] + g * p->fS[m * npts + q];
+  }
+  return F;
+}
+
+/* Fine propagator: s steps of the fine method at dt = DT/s over coarse
+ * interval n (section 3). */
+void or_fine(const or_problem* p, int n, double* U) {
   const double DT = p->T / p->n_slices;
   const double dt = DT / p->fine_steps;
+  const long stride = (long)p->n_slices * p->fine_steps;
   for (int t = 0; t < p->fine_steps; t++) {
+    double* F = source_at(p, p->fg_fine, stride, (long)n * p->fine_steps + t);
     if (p->fine_method == 1)
-      or_dr_step(p, dt, U);
+      or_dr_step(p, dt, F, U);
     else
-      or_fie_step(p, dt, U);
+      or_fie_step(p, dt, F, U);
+    free(F);
   }
 }
 
-/* Coarse propagator: FIE (L-stable, section 4) with coarse_steps steps over DT. */
-void or_coarse(const or_problem* p, double* U) {
+/* Coarse propagator: FIE (L-stable, section 4) with coarse_steps steps over
+ * coarse interval n. */
+void or_coarse(const or_problem* p, int n, double* U) {
   const double DT = p->T / p->n_slices;
   const double tau = DT / p->coarse_steps;
-  for (int t = 0; t < p->coarse_steps; t++) or_fie_step(p, tau, U);
+  const long stride = (long)p->n_slices * p->coarse_steps;
+  for (int t = 0; t < p->coarse_steps; t++) {
+    double* F = source_at(p, p->fg_coarse, stride, (long)n * p->coarse_steps + t);
+    or_fie_step(p, tau, F, U);
+    free(F);
+  }
 }
 
 void or_fine_batch(const or_problem* p, int n, const double* U_in, double* F_out) {
   const long npts = npts_of(p);
   for (int k = 0; k < n; k++) {
     memcpy(F_out + k * npts, U_in + k * npts, sizeof(double) * npts);
-    or_fine(p, F_out + k * npts);
+    or_fine(p, k, F_out + k * npts);
   }
 }
 
@@ -263,7 +290,7 @@ void or_sequential_fine(const or_problem* p, const double* u0, double* U) {
   memcpy(U, u0, sizeof(double) * npts);
   for (int n = 0; n < p->n_slices; n++) {
     memcpy(U + (n + 1) * npts, U + n * npts, sizeof(double) * npts);
-    or_fine(p, U + (n + 1) * npts);
+    or_fine(p, n, U + (n + 1) * npts);
   }
 }
 
@@ -274,7 +301,7 @@ double or_coarse_sweep(const or_problem* p, const double* F, double* G_old, doub
   double inc = 0.0;
   for (int n = 0; n < N; n++) {
     memcpy(g, U + n * npts, sizeof(double) * npts);
-    or_coarse(p, g); /* g = G(U^{k+1}_n) */
+    or_coarse(p, n, g); /* g = G(U^{k+1}_n) */
     double* Unext = U + (n + 1) * npts;
     double* Gn = G_old + n * npts;
     for (long q = 0; q < npts; q++) {
@@ -364,6 +391,12 @@ void or_adjoint(const or_problem* p, const double* u0, const double* lambda_T, d
     double* cur = (double*)malloc(sizeof(double) * npts);
     memcpy(cur, ckpt + (long)n * npts, sizeof(double) * npts);
     for (int t = 0; t < s; t++) {
+      /* the source enters the x substep's right-hand side; the face gradients
+       * below only need the post-substep states */
+      double* F = source_at(p, p->fg_fine, (long)N * s, (long)n * s + t);
+      if (F)
+        for (long q = 0; q < npts; q++) cur[q] = cur[q] + dt * F[q];
+      free(F);
       implicit_substep(p, 0, dt, cur);
       memcpy(Wst + (long)t * npts, cur, sizeof(double) * npts);
       if (p->dim == 2) implicit_substep(p, 1, dt, cur);

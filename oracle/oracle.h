@@ -20,6 +20,11 @@
  *    (i,g-1) and (i,g).
  *  - Domain decomposition (1D only): rho[k*(nx+1) + f] is the partition of
  *    unity weight of colour k on face f.
+ *  - Source term (F of eq. FIE_method and eq. DR_method, homogeneous boundary
+ *    data): F(t) = sum_m g_m(t) S_m with n_forcing spatial factors S_m (grid
+ *    functions) and g_m given at the time levels the steps use: fine step j of
+ *    slice n ends at t = n*DT + (j+1)*dt (table entry n*fine_steps + j), coarse
+ *    step c at t = n*DT + (c+1)*DT/coarse_steps (entry n*coarse_steps + c).
  *
  * All floating-point work is IEEE double, round to nearest, compiled with
  * contraction disabled so results are reproducible.
@@ -45,6 +50,10 @@ typedef struct {
   const double* ay;   /* (ny+1)*nx y-face coefficients, NULL when dim == 1 */
   int n_colors;       /* domain decomposition: number of split terms M */
   const double* rho;  /* domain decomposition: n_colors*(nx+1) face weights */
+  int n_forcing;            /* separable source terms; 0: F = 0 */
+  const double* fS;         /* n_forcing*nx*ny spatial factors S_m */
+  const double* fg_fine;    /* n_forcing*(n_slices*fine_steps) values g_m */
+  const double* fg_coarse;  /* n_forcing*(n_slices*coarse_steps) values g_m */
 } or_problem;
 
 /* Face coefficients a_f = (e^theta_p + e^theta_q)/2 from a nodal log
@@ -60,19 +69,20 @@ void or_apply_A(const or_problem* p, const double* U, double* out);
 /* Apply one split operator A_j (j = 0 x-direction / colour 0, ...). */
 void or_apply_Aj(const or_problem* p, int j, const double* U, double* out);
 
-/* One FIE step (eq. FIE_method) with step tau, in place. */
-void or_fie_step(const or_problem* p, double tau, double* U);
+/* One FIE step (eq. FIE_method) with step tau and source F (NULL: F = 0), in place. */
+void or_fie_step(const or_problem* p, double tau, const double* F, double* U);
 
-/* One Douglas-Rachford step (eq. DR_method) with step tau, in place. */
-void or_dr_step(const or_problem* p, double tau, double* U);
+/* One Douglas-Rachford step (eq. DR_method) with step tau and source F (NULL: F = 0), in place. */
+void or_dr_step(const or_problem* p, double tau, const double* F, double* U);
 
-/* Fine propagator F^s over one coarse interval, in place. */
-void or_fine(const or_problem* p, double* U);
+/* Fine propagator F^s over coarse interval n (its source levels), in place. */
+void or_fine(const or_problem* p, int n, double* U);
 
-/* Coarse propagator G over one coarse interval, in place. */
-void or_coarse(const or_problem* p, double* U);
+/* Coarse propagator G over coarse interval n, in place. */
+void or_coarse(const or_problem* p, int n, double* U);
 
-/* F^s applied independently to n states U_in[n*npts] -> F_out. */
+/* F^s applied independently to n states U_in[n*npts] -> F_out (state k is
+ * propagated over coarse interval k). */
 void or_fine_batch(const or_problem* p, int n, const double* U_in, double* F_out);
 
 /* Sequential fine solution at the coarse nodes: U[0] = u0,

@@ -22,7 +22,7 @@ def oracle_problem(w):
         ax, ay = w.ax, w.ay
     return oracle.Problem(dim=w.dim, nx=w.nx, ny=w.ny, T=w.T, n_slices=w.n_slices,
                           fine_steps=w.fine_steps, coarse_steps=w.coarse_steps, split=w.split,
-                          fine=w.fine, c=w.c, ax=ax, ay=ay, rho=w.rho)
+                          fine=w.fine, c=w.c, ax=ax, ay=ay, rho=w.rho, forcing=w.forcing)
 
 
 def instance_dict(w):
@@ -34,6 +34,8 @@ def instance_dict(w):
         d["ax"], d["ay"] = w.ax, w.ay
     if w.rho is not None:
         d["rho"] = w.rho
+    if w.forcing is not None:
+        d["forcing"] = w.forcing
     return d
 
 

@@ -491,3 +491,91 @@ def test_increment_covers_first_slice():
     d = np.abs(U1 - U0).reshape(P.n_slices + 1, -1).max(1)
     assert np.argmax(d) == 1 and d[0] == 0
     assert hist[0] == d.max()
+
+
+# ---------------------------------------------------------- source terms ---
+def _forced_problem(nx, ny, T, N, s, fine, forcing, theta_seed=2, c=0.0):
+    w = W.small_dim2(nx, ny, n_slices=N, fine_steps=s, seed=theta_seed, T=T, c=c)
+    w.fine = fine
+    return problem(w, forcing=forcing)
+
+
+def test_forcing_dr_preserves_forced_steady_state():
+    """eq. DR_method with F = -A S (time independent): S solves U' = AU + F with
+    U' = 0, and the DR step maps it to itself exactly (its first stage adds
+    tau A S + tau F = 0 and every later stage returns S). FIE, with its first-
+    order splitting error, moves it: a sign or scale error on tau F breaks the
+    first property, a source added to the wrong stage the second."""
+    nx, ny, N, s = 13, 11, 2, 3
+    S = W.sine_modes_2d(nx, ny, seed=9)
+    A = _forced_problem(nx, ny, 0.05, N, s, "fie", None, theta_seed=4, c=0.7)
+    F = -A.apply_A(S)
+    forcing = (F[None], np.ones((1, N * s)), np.ones((1, N)))
+    dr = _forced_problem(nx, ny, 0.05, N, s, "dr", forcing, theta_seed=4, c=0.7)
+    fie = _forced_problem(nx, ny, 0.05, N, s, "fie", forcing, theta_seed=4, c=0.7)
+    assert np.abs(dr.fine(S, 1) - S).max() <= 1e-13 * np.abs(S).max()
+    assert np.abs(fie.fine(S, 1) - S).max() > 1e-3 * np.abs(S).max()
+
+
+@pytest.mark.parametrize("fine,steps", [("fie", (32, 64, 128)), ("dr", (16, 32, 64))])
+def test_forcing_manufactured_first_order_in_time(fine, steps):
+    """Manufactured semi-discrete solution U(t) = sin(2 pi t) S with the source
+    F(t) = 2 pi cos(2 pi t) S - sin(2 pi t) A S (A the discrete operator, so
+    the space error is zero): both splitting methods are first-order
+    convergent (section 2.2), so halving dt halves the error at the slice
+    ends, and the error is far below the solution's size."""
+    nx, ny, T, N = 15, 13, 0.5, 2
+    S = W.sine_modes_2d(nx, ny, seed=3)
+    AS = _forced_problem(nx, ny, T, N, 1, fine, None).apply_A(S)
+    g = lambda t: np.stack([2 * np.pi * np.cos(2 * np.pi * t), np.sin(2 * np.pi * t)])
+    DT = T / N
+    errs = []
+    for s in steps:
+        dt = DT / s
+        tf = np.array([n * DT + (j + 1) * dt for n in range(N) for j in range(s)])
+        tc = np.array([(n + 1) * DT for n in range(N)])
+        P = _forced_problem(nx, ny, T, N, s, fine, (np.stack([S, -AS]), g(tf), g(tc)))
+        U = P.sequential_fine(np.zeros_like(S))
+        exact = np.stack([np.sin(2 * np.pi * n * DT) * S for n in range(N + 1)])
+        errs.append(np.abs(U - exact).max())
+    assert errs[-1] < 0.05 * np.abs(S).max()
+    assert 1.75 < errs[-2] / errs[-1] < 2.25
+    assert errs[0] > errs[1] > errs[2]
+
+
+def test_forcing_superposition():
+    """The forced propagators are affine: F(u) = F_unforced(u) + F(0)."""
+    nx, ny, N, s = 9, 7, 3, 2
+    rng = np.random.default_rng(11)
+    forcing = (rng.standard_normal((2, ny, nx)), rng.standard_normal((2, N * s)),
+               rng.standard_normal((2, N)))
+    u = rng.standard_normal((ny, nx))
+    for fine in ("fie", "dr"):
+        Pf = _forced_problem(nx, ny, 0.1, N, s, fine, forcing)
+        P0 = _forced_problem(nx, ny, 0.1, N, s, fine, None)
+        for n in range(N):
+            lhs = Pf.fine(u, n)
+            rhs = P0.fine(u, n) + Pf.fine(np.zeros_like(u), n)
+            assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(lhs).max()
+        lhs = Pf.coarse(u, 1)
+        assert np.abs(lhs - (P0.coarse(u, 1) + Pf.coarse(np.zeros_like(u), 1))).max() <= 1e-13
+
+
+def test_manufactured_problem_converges():
+    """The paper's test problem (section 5, u = sin 2pi t sin 2pi x sin 2pi y with
+    its source): with dt proportional to h^2 the FIE fine solution's error
+    (maximum over time of the discrete 2-norm, the paper's error measure)
+    falls like h^2, i.e. by about 4 per halving of h (second-order finite
+    differences, first-order FIE)."""
+    errs = []
+    for n, s in [(15, 4), (31, 16), (63, 64)]:
+        w = W.manufactured2d(n, 8, s)
+        P = problem(w, forcing=w.forcing)
+        U = P.sequential_fine(w.u0)
+        DT = w.T / w.n_slices
+        exact = np.stack([np.sin(2 * np.pi * k * DT) * w.extra["exact_space"]
+                          for k in range(w.n_slices + 1)])
+        errs.append(np.sqrt(((U - exact) ** 2).sum(axis=(1, 2)) / (n + 1) ** 2).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert 3.0 < errs[1] / errs[2] < 4.6
+    assert errs[2] < 0.05

@@ -133,6 +133,9 @@ class Workload:
     u0: Optional[np.ndarray] = None
     k_max: int = 0
     tol: float = 0.0
+    # source F(t) = sum_m g_m(t) S_m: (S (m, ny, nx), g at the fine step ends
+    # (m, N*s), g at the coarse step ends (m, N*cs)), or None
+    forcing: Optional[tuple] = None
     extra: dict = field(default_factory=dict)
 
     @property
@@ -244,3 +247,32 @@ def small_dd1(n: int, n_cores: int, n_colors: int, overlap: int, n_slices: int, 
     return Workload(f"smalldd_{n}_M{n_colors}_q{n_cores // n_colors}", 1, n, 1, T, n_slices,
                     fine_steps, split="dd", theta=theta, rho=rho,
                     u0=sine_series_1d(n, seed=seed + 1, kmax=min(n, 64)), k_max=n_slices, tol=0.0)
+
+
+def step_end_times(T: float, n_slices: int, steps: int) -> np.ndarray:
+    """End times of the steps of every slice: t = n*DT + (j+1)*DT/steps, ordered
+    slice-major (the layout of the source time tables)."""
+    DT = T / n_slices
+    n = np.repeat(np.arange(n_slices), steps)
+    j = np.tile(np.arange(steps), n_slices)
+    return n * DT + (j + 1) * (DT / steps)
+
+
+def manufactured2d(n: int, n_slices: int, fine_steps: int, coarse_steps: int = 1,
+                   T: float = 1.0) -> Workload:
+    """The paper's test problem (section 5): heat equation on the unit square with
+    D = I, homogeneous Dirichlet data, u0 = 0 and the source f for which
+    u = sin(2 pi t) sin(2 pi x) sin(2 pi y) is the exact solution:
+    f = u_t - Lap u = (2 pi cos 2 pi t + 8 pi^2 sin 2 pi t) sin(2 pi x) sin(2 pi y),
+    sampled at the interior nodes (one separable source term). The paper's run:
+    h = 1e-3 (n = 999), DT = 0.05 (N = 20), dt = 2.5e-3 (s = 20), T = 1."""
+    x = np.arange(1, n + 1) / (n + 1)
+    S = np.outer(np.sin(2 * np.pi * x), np.sin(2 * np.pi * x))[None]
+    g = lambda t: (2 * np.pi * np.cos(2 * np.pi * t) + 8 * np.pi ** 2 * np.sin(2 * np.pi * t))[None]
+    w = Workload(f"manufactured2d_{n}_N{n_slices}_s{fine_steps}", 2, n, n, T, n_slices, fine_steps,
+                 coarse_steps=coarse_steps, theta=np.zeros((n + 2, n + 2)), u0=np.zeros((n, n)),
+                 forcing=(S, g(step_end_times(T, n_slices, fine_steps)),
+                          g(step_end_times(T, n_slices, coarse_steps))),
+                 k_max=n_slices, tol=1e-6)
+    w.extra["exact_space"] = S[0]
+    return w
