@@ -90,7 +90,21 @@ enum { PR_COEF_FACES = 0, PR_COEF_NODAL_LOG = 1 };
  *                  [n_colors][nx+1], each in [0,1], summing to 1 on every
  *                  face (|sum - 1| <= 1e-14). The connected components of
  *                  colour k are the maximal runs of faces with rho_k > 0;
- *                  each component is one independent tridiagonal system. */
+ *                  each component is one independent tridiagonal system.
+ *   n_forcing      number of separable source terms, 0..PR_MAX_FORCING: the
+ *                  source of eq. FIE_method / eq. DR_method (homogeneous
+ *                  boundary data) is F(t) = sum_m g_m(t) S_m, and tau F at the
+ *                  step's end time enters the step's first stage
+ *   forcing_space  device pointer, [n_forcing][ny][nx]: the grid functions S_m;
+ *                  read during pr_create_problem only (the library keeps a copy)
+ *   forcing_time_fine    HOST pointer, [n_forcing][n_slices * fine_steps]:
+ *                  g_m at the end of fine step j of slice n, entry n*fine_steps + j
+ *                  (t = n*DT + (j+1)*dt)
+ *   forcing_time_coarse  HOST pointer, [n_forcing][n_slices * coarse_steps]:
+ *                  g_m at the end of coarse step c of slice n (t = n*DT +
+ *                  (c+1)*DT/coarse_steps)
+ * Unused pointers may be NULL. */
+#define PR_MAX_FORCING 2
 typedef struct {
   int dim, nx, ny;
   double T;
@@ -103,6 +117,10 @@ typedef struct {
   double c;
   int n_colors;
   const double* rho;
+  int n_forcing;
+  const double* forcing_space;
+  const double* forcing_time_fine;
+  const double* forcing_time_coarse;
 } pr_problem_desc;
 
 /* Per-instance offsets (in doubles) into the packed buffers of a batch:

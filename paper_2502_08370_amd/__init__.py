@@ -58,9 +58,12 @@ class Problem:
     section 3 parareal).
 
     Each instance is a dict with keys: dim, nx, ny, T, n_slices, fine_steps,
-    coarse_steps (1), split ('dim' | 'dd'), fine ('fie'), c (0.0), and either
-    ax / ay (face coefficients) or theta (nodal log coefficient), plus rho
-    (partition-of-unity face weights, host array) for 'dd'.
+    coarse_steps (1), split ('dim' | 'dd'), fine ('fie' | 'dr'), c (0.0), and
+    either ax / ay (face coefficients) or theta (nodal log coefficient), plus rho
+    (partition-of-unity face weights, host array) for 'dd', and optionally
+    forcing = (S, g_fine, g_coarse): the source F(t) = sum_m g_m(t) S_m with S
+    of shape (m, ny, nx), g_fine (m, n_slices*fine_steps) and g_coarse
+    (m, n_slices*coarse_steps) at the step end times (m <= 2).
     """
 
     def __init__(self, instances, device="cuda", stream=None):
@@ -97,6 +100,18 @@ class Problem:
                 keep.append(rho)
                 d.n_colors = rho.shape[0]
                 d.rho = C.c_void_p(rho.ctypes.data)
+            forcing = ins.get("forcing")
+            if forcing is not None:
+                S, gf, gc = forcing
+                m = int(np.asarray(S).shape[0])
+                Sd = _dev_f64(np.asarray(S).reshape(m, -1), self.device)
+                gf = np.ascontiguousarray(np.asarray(gf, dtype=np.float64).reshape(m, -1))
+                gc = np.ascontiguousarray(np.asarray(gc, dtype=np.float64).reshape(m, -1))
+                keep += [Sd, gf, gc]
+                d.n_forcing = m
+                d.forcing_space = _ptr(Sd)
+                d.forcing_time_fine = C.c_void_p(gf.ctypes.data)
+                d.forcing_time_coarse = C.c_void_p(gc.ctypes.data)
             self.instances.append(dict(dim=d.dim, nx=d.nx, ny=d.ny, n_slices=d.n_slices,
                                        coef_mode=d.coef_mode))
         h = C.c_void_p()

@@ -34,6 +34,10 @@ class PrProblemDesc(C.Structure):
         ("c", C.c_double),
         ("n_colors", C.c_int),
         ("rho", C.c_void_p),
+        ("n_forcing", C.c_int),
+        ("forcing_space", C.c_void_p),
+        ("forcing_time_fine", C.c_void_p),
+        ("forcing_time_coarse", C.c_void_p),
     ]
 
 

@@ -103,6 +103,7 @@ struct Instance {
   DBuf cxRb, cxGb, cyRb, cyGb, fxRb, fxGb, fyRb, fyGb;  // lane-blocked copies
   DBuf Z, sigX, sigY, tmp;
   DBuf drS;  // Douglas-Rachford stencil values, shaped like Z
+  DBuf fS, fgf, fgc;  // source: spatial factors, step-premultiplied time tables
   // domain decomposition (1D)
   int n_colors = 0;
   std::vector<int> seg_off;   // colour k's segments: [seg_off[k], seg_off[k+1])
@@ -148,6 +149,7 @@ struct pr_problem_s {
   struct Group {
     int L = 0;
     int dr = 0;                // Douglas-Rachford instances (the sweeps add / subtract S)
+    int ft = 0;                // instances with a source term (the x sweep adds it)
     std::vector<int> members;  // instances of the group
     WorkItem* d_work[2] = {nullptr, nullptr};
     int n_work[2] = {0, 0};
@@ -213,6 +215,10 @@ pr_status validate(const pr_problem_desc& d, int idx) {
                 "instance %d: the Douglas-Rachford fine propagator needs the dimensional split", idx);
   if (d.split != PR_SPLIT_DIM && d.split != PR_SPLIT_DD)
     return fail(PR_EINVAL, "instance %d: bad split", idx);
+  if (d.n_forcing < 0 || d.n_forcing > PR_MAX_FORCING)
+    return fail(PR_EINVAL, "instance %d: n_forcing must be in 0..%d", idx, PR_MAX_FORCING);
+  if (d.n_forcing > 0 && (!d.forcing_space || !d.forcing_time_fine || !d.forcing_time_coarse))
+    return fail(PR_EINVAL, "instance %d: source term arrays are NULL", idx);
   if (d.coef_mode != PR_COEF_FACES && d.coef_mode != PR_COEF_NODAL_LOG)
     return fail(PR_EINVAL, "instance %d: bad coef_mode", idx);
   if (!d.coef_x) return fail(PR_EINVAL, "instance %d: coef_x is NULL", idx);
@@ -244,6 +250,35 @@ pr_status validate(const pr_problem_desc& d, int idx) {
                     sum, f);
     }
   }
+  return PR_OK;
+}
+
+// Source term tables of eq. FIE_method / eq. DR_method: S_m copied, unused
+// terms zero; g_m premultiplied by the step (dt fine, DT / coarse_steps coarse).
+pr_status setup_forcing(Instance& I, const pr_problem_desc& d, hipStream_t s) {
+  DimInst& h = I.h;
+  h.nforce = d.n_forcing;
+  h.fS = h.fgf = h.fgc = nullptr;
+  if (d.n_forcing == 0) return PR_OK;
+  const size_t npts = (size_t)d.nx * d.ny;
+  const size_t nf = (size_t)d.n_slices * d.fine_steps, nc = (size_t)d.n_slices * d.coarse_steps;
+  HIPOK(I.fS.alloc(kMaxForcing * npts));
+  HIPOK(launch_fill_zero(I.fS.p, I.fS.n, s));
+  HIPOK(hipMemcpyAsync(I.fS.p, d.forcing_space, d.n_forcing * npts * sizeof(double),
+                       hipMemcpyDeviceToDevice, s));
+  std::vector<double> tf(kMaxForcing * nf, 0.0), tc(kMaxForcing * nc, 0.0);
+  for (int m = 0; m < d.n_forcing; m++) {
+    for (size_t i = 0; i < nf; i++) tf[m * nf + i] = I.dt * d.forcing_time_fine[m * nf + i];
+    for (size_t i = 0; i < nc; i++) tc[m * nc + i] = I.tauG * d.forcing_time_coarse[m * nc + i];
+  }
+  HIPOK(I.fgf.alloc(tf.size()));
+  HIPOK(I.fgc.alloc(tc.size()));
+  HIPOK(hipMemcpyAsync(I.fgf.p, tf.data(), tf.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPOK(hipMemcpyAsync(I.fgc.p, tc.data(), tc.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPOK(hipStreamSynchronize(s));  // the host tables are released on return
+  h.fS = I.fS.p;
+  h.fgf = I.fgf.p;
+  h.fgc = I.fgc.p;
   return PR_OK;
 }
 
@@ -308,7 +343,7 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   h.cxRb = I.cxRb.p; h.cxGb = I.cxGb.p; h.cyRb = I.cyRb.p; h.cyGb = I.cyGb.p;
   h.fxRb = I.fxRb.p; h.fxGb = I.fxGb.p; h.fyRb = I.fyRb.p; h.fyGb = I.fyGb.p;
   h.tmp = I.tmp.p;
-  return PR_OK;
+  return setup_forcing(I, d, s);
 }
 
 // Factorisations of I - tau A_x, I - tau A_y at tau = dt (fine, line-major, with
@@ -563,7 +598,8 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
   DimInst& t = I.h;
   t.nx = n; t.ny = 1; t.N = N; t.L = L; t.B = B; t.M = 1; t.Px = 1; t.Py = 1;
   t.steps = d.fine_steps; t.slab = (long)n * L; t.Z = I.Z.p; t.tmp = I.tmp.p;
-  return PR_OK;
+  t.npts = n;
+  return setup_forcing(I, d, s);
 }
 
 pr_status factorize_dd_instance(Instance& I, const double* coef_x, hipStream_t s) {
@@ -697,7 +733,8 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
           if (!cnt) continue;
           PhaseTimer pt(P, PH_FINE, s);
           HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir] + off, cnt, g.L, P->M, dir,
-                                  dir == 1 || t > 0, t, s, g.dr ? (dir == 0 ? 1 : -1) : 0));
+                                  dir == 1 || t > 0, t, s, g.dr ? (dir == 0 ? 1 : -1) : 0,
+                                  dir == 0 && g.ft));
         }
       }
     }
@@ -706,6 +743,10 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
     Instance& I = *P->inst[i];
     if (!I.dd) continue;
     for (int t = 0; t < I.d.fine_steps; t++) {
+      if (I.h.nforce) {
+        PhaseTimer pt(P, PH_FINE, s);
+        HIPOK(launch_force_interleaved(P->d_inst + i, I.h, t, s));
+      }
       pr_status st = dd_fie_step(P, I, false, 0, t, s);
       if (st != PR_OK) return st;
     }
@@ -723,11 +764,15 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
 
 // One coarse propagation G (coarse_steps FIE steps) of state src of DD
 // instance i, followed by the parareal update in `mode` (see launch_update).
-pr_status coarse_apply_dd(pr_problem_s* P, int i, const double* src, int mode, const double* F,
-                          double* Gold, double* Unext, hipStream_t s) {
+pr_status coarse_apply_dd(pr_problem_s* P, int i, int n, const double* src, int mode,
+                          const double* F, double* Gold, double* Unext, hipStream_t s) {
   Instance& I = *P->inst[i];
   HIPOK(launch_copy(src, I.tmp.p, I.npts, s));
-  for (int c = 0; c < I.d.coarse_steps; c++) {
+  const int cs = I.d.coarse_steps;
+  for (int c = 0; c < cs; c++) {
+    if (I.h.nforce)
+      HIPOK(launch_force_state(P->d_inst + i, I.h, I.tmp.p, I.fgc.p, (long)n * cs + c,
+                               (long)I.d.n_slices * cs, s));
     pr_status st = dd_fie_step(P, I, true, 1, 0, s);
     if (st != PR_OK) return st;
   }
@@ -755,7 +800,7 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
       double* Unext = U + I.off_states + (size_t)(k + 1) * I.npts;
       double* Gk = Gold + I.off_slices + (size_t)k * I.npts;
       const double* Fk = F ? F + I.off_slices + (size_t)k * I.npts : nullptr;
-      pr_status st = coarse_apply_dd(P, i, Un, F ? 1 : 2, Fk, Gk, Unext, s);
+      pr_status st = coarse_apply_dd(P, i, k, Un, F ? 1 : 2, Fk, Gk, Unext, s);
       if (st != PR_OK) return st;
     }
   }
@@ -787,6 +832,10 @@ pr_status seq_fine_dim(pr_problem_s* p, int i, const double* u0, double* U, hipS
       for (int t = 0; t < I.d.fine_steps; t++) {
         const double* in = t == 0 ? src : I.tmp.p;
         const bool last = t + 1 == I.d.fine_steps;
+        // source at the end of fine step t of slice k
+        const double* gtab = I.h.nforce ? I.fgf.p : nullptr;
+        const long gidx = (long)k * I.d.fine_steps + t;
+        const long gstride = (long)I.d.n_slices * I.d.fine_steps;
         if (I.h.dr) {
           // S = dt A_y U into drS[0, npts), U + S into drS[npts, 2 npts); x solve;
           // subtract S; y solve
@@ -794,7 +843,7 @@ pr_status seq_fine_dim(pr_problem_s* p, int i, const double* u0, double* U, hipS
           {
             PhaseTimer pt(p, PH_COARSE_X, s);
             HIPOK(launch_dr_stencil_nat(dI, I.h, in, UpS, 0, s));
-            HIPOK(launch_coarse_x(dI, I.h, UpS, I.tmp.p, true, s));
+            HIPOK(launch_coarse_x(dI, I.h, UpS, I.tmp.p, true, s, gtab, gidx, gstride));
             HIPOK(launch_dr_stencil_nat(dI, I.h, nullptr, I.tmp.p, 1, s));
           }
           PhaseTimer pt(p, PH_COARSE_Y, s);
@@ -803,7 +852,7 @@ pr_status seq_fine_dim(pr_problem_s* p, int i, const double* u0, double* U, hipS
         }
         {
           PhaseTimer pt(p, PH_COARSE_X, s);
-          HIPOK(launch_coarse_x(dI, I.h, in, I.tmp.p, true, s));
+          HIPOK(launch_coarse_x(dI, I.h, in, I.tmp.p, true, s, gtab, gidx, gstride));
         }
         PhaseTimer pt(p, PH_COARSE_Y, s);
         HIPOK(launch_coarse_y(dI, I.h, I.tmp.p, last ? dst : I.tmp.p, true, s));
@@ -842,14 +891,19 @@ pr_status build_schedules(pr_problem_s* P) {
   P->n_passes = (Bmax + bpp - 1) / bpp;
   P->pass_blocks = bpp;
   for (int L = 1; L <= 64; L <<= 1)
-    for (int dr = 0; dr < 2; dr++) {
+    for (int key = 0; key < 4; key++) {
+      const int dr = key & 1, ft = key >> 1;
       std::vector<int> members;
-      for (int i = 0; i < n; i++)
-        if (!P->inst[i]->dd && P->inst[i]->h.L == L && P->inst[i]->h.dr == dr) members.push_back(i);
+      for (int i = 0; i < n; i++) {
+        const DimInst& hi = P->inst[i]->h;
+        if (!P->inst[i]->dd && hi.L == L && hi.dr == dr && (hi.nforce > 0) == (ft == 1))
+          members.push_back(i);
+      }
       if (members.empty()) continue;
       pr_problem_s::Group g;
       g.L = L;
       g.dr = dr;
+      g.ft = ft;
       g.members = members;
       for (int dir = 0; dir < 2; dir++) {
         std::vector<WorkItem> all;
@@ -1290,6 +1344,9 @@ pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hi
       for (int k = 0; k < I.d.n_slices; k++) {
         HIPOK(launch_copy(U + I.off_states + (size_t)k * I.npts, I.tmp.p, I.npts, s));
         for (int t = 0; t < I.d.fine_steps; t++) {
+          if (I.h.nforce)
+            HIPOK(launch_force_state(dI, I.h, I.tmp.p, I.fgf.p, (long)k * I.d.fine_steps + t,
+                                     (long)I.d.n_slices * I.d.fine_steps, s));
           pr_status st = dd_fie_step(p, I, false, 1, 0, s);
           if (st != PR_OK) return st;
         }
@@ -1340,7 +1397,8 @@ pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, dou
       const double* prev = t == 0 ? ckpt + (size_t)n * npts : Vst + (size_t)(t - 1) * npts;
       {
         PhaseTimer pt(p, PH_COARSE_X, s);
-        HIPOK(launch_coarse_x(dI, I.h, prev, Wst + (size_t)t * npts, true, s));
+        HIPOK(launch_coarse_x(dI, I.h, prev, Wst + (size_t)t * npts, true, s,
+                              I.h.nforce ? I.fgf.p : nullptr, (long)n * S + t, (long)N * S));
       }
       PhaseTimer pt(p, PH_COARSE_Y, s);
       HIPOK(launch_coarse_y(dI, I.h, Wst + (size_t)t * npts, Vst + (size_t)t * npts, true, s));

@@ -72,7 +72,15 @@ struct DimInst {
   const double* ay;  // y-face coefficients [(ny+1)][nx]
   double dr_coef;    // dt / h_y^2
   double dr_react;   // dt * c / 2
+  // source F(t) = sum_m g_m(t) S_m of eq. FIE_method / eq. DR_method; tau F at
+  // the step's end time enters its first stage (the x substep, the x sweep's load)
+  int nforce;        // 0: no source
+  const double* fS;  // [kMaxForcing][npts] (unused terms zero)
+  const double* fgf; // [kMaxForcing][N * steps]: dt * g_m at the fine step ends
+  const double* fgc; // [kMaxForcing][N * cs]: (DT / cs) * g_m at the coarse step ends
 };
+
+constexpr int kMaxForcing = 2;
 
 // Work item of a batched coarse launch: instance and line block.
 struct LineItem {
@@ -228,9 +236,11 @@ hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const 
 // with_corr = false: plain transpose (no pending chunk correction).
 hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, double* F_out,
                                    bool with_corr, hipStream_t s);
-// sgn = +1 / -1: add / subtract the instance's DR array on load (0: FIE).
+// sgn = +1 / -1: add / subtract the instance's DR array on load (0: FIE);
+// forced: the x sweep adds the step's source term (dir 0 only).
 hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
-                             int M, int dir, int has_prev, int step, hipStream_t s, int sgn = 0);
+                             int M, int dir, int has_prev, int step, hipStream_t s, int sgn = 0,
+                             bool forced = false);
 // S = dt A_y U on the slice-interleaved workspace (U with the pending y-sweep
 // correction when has_prev) of one instance, slice blocks [b_lo, b_hi), before
 // fine step `step` (nothing once the instance has finished its steps).
@@ -241,9 +251,12 @@ hipError_t launch_dr_stencil(const DimInst* d_inst, const DimInst& h, int has_pr
 hipError_t launch_dr_stencil_nat(const DimInst* d_inst, const DimInst& h, const double* U,
                                  double* out, int mode, hipStream_t s);
 // Exact line solves of one state, one wave per line (lines <= kMaxCoarseLine).
-// fine = false uses the coarse factorisation, fine = true the fine one.
+// fine = false uses the coarse factorisation, fine = true the fine one. With
+// gtab != NULL the x solve's right-hand side also receives sum_m
+// gtab[m * gstride + gidx] S_m (a source table premultiplied by the step).
 hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
-                           bool fine, hipStream_t s);
+                           bool fine, hipStream_t s, const double* gtab = nullptr, long gidx = 0,
+                           long gstride = 0);
 // Largest grid extent the coarse sweeps handle (whole line per wave, 64-point chunks).
 constexpr int kMaxCoarseLine = 1024;
 constexpr int kCoarseRowsPerBlock = 4;    // x lines per block of the coarse x kernels
@@ -269,6 +282,13 @@ hipError_t launch_mask_update(const double* inc, int* active, int n, double tol,
 hipError_t launch_coarse_y(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
                            bool fine, hipStream_t s);
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s);
+// Source of the DD substeps (every node, since the first stage of a step
+// touches all of them): interleaved Z[b][node][l] += sum_m gtab[m][slice*steps
+// + step] S_m[node] (forced_z), or one state u += sum_m gtab[m*gstride + gidx] S_m.
+hipError_t launch_force_interleaved(const DimInst* d_inst, const DimInst& h, int step,
+                                    hipStream_t s);
+hipError_t launch_force_state(const DimInst* d_inst, const DimInst& h, double* u,
+                              const double* gtab, long gidx, long gstride, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s);
 
 }  // namespace prk

@@ -229,16 +229,20 @@ __global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
 // A partial last chunk is computed in full on clamped loads: the line's last
 // back-substitution factor is 0, so the padded positions cannot leak into the
 // real ones, and only real positions are stored.
-template <int L, int M, int DIR, bool HP, int SGN = 0>
+template <int L, int M, int DIR, bool HP, int SGN = 0, bool FT = false>
 __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict__ insts,
                                                       const WorkItem* __restrict__ work,
                                                       int step) {
   constexpr int G = kWave / L;  // lines per wave
   constexpr bool kUni = (L == kWave);
   constexpr int NQ = kUni ? 1 : (G * M + kWave - 1) / kWave;
+  // per-position rows: e, r, g, phi of the pending correction, and with a
+  // source the spatial factors S_0, S_1
+  constexpr int NF = FT ? 4 + kMaxForcing : 4;
   static_assert(M <= kWave, "chunk longer than a wave");
-  // factor staging when a wave holds several lines: [4][G][M+1]
-  __shared__ double sF[kUni ? 1 : 4][kUni ? 1 : G][M + 1];
+  static_assert(!FT || DIR == 0, "the source enters the first (x) stage");
+  // factor staging when a wave holds several lines: [NF][G][M+1]
+  __shared__ double sF[kUni ? 1 : NF][kUni ? 1 : G][M + 1];
   // first value of every chunk of the wave's lines, resolved into carries at the end
   constexpr int kMaxChunks = (kMaxCoarseLine + M - 1) / M;
   __shared__ double zfirst[kMaxChunks][kWave];
@@ -282,7 +286,20 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   const unsigned usl = (unsigned)sl;  // lane offset (unsigned: scalar-base addressing)
   // DR: the stencil array lives at the same offsets as Z
   const long drOff = SGN != 0 ? (long)(I.drS - I.Z) : 0;
-  auto issue = [&](double (&v)[M], double (&sg)[M], double (&f)[4][NQ], int k) {
+  // source: dt * g_m of this lane's slice at this step (0 on padding slices)
+  double gl[kMaxForcing] = {};
+  const gdouble* fS = FT ? gp(I.fS) : nullptr;
+  if constexpr (FT) {
+    const int slice = w.b * L + sl;
+    const long nst = (long)I.N * I.steps;
+    const long gi = (long)(slice < I.N ? slice : 0) * I.steps + step;
+#pragma unroll
+    for (int m = 0; m < kMaxForcing; m++) {
+      const double g = gp(I.fgf)[m * nst + gi];
+      gl[m] = slice < I.N ? g : 0.0;
+    }
+  }
+  auto issue = [&](double (&v)[M], double (&sg)[M], double (&f)[NF][NQ], int k) {
     const int p0 = k * M;
     const int cnt = min(M, n_pos - p0);
     if constexpr (kUni) {
@@ -323,6 +340,10 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       f[1][0] = R[idx];
       f[2][0] = Gf[idx];
       if constexpr (HP) f[3][0] = phiPrev[idx];
+      if constexpr (FT) {
+#pragma unroll
+        for (int m = 0; m < kMaxForcing; m++) f[4 + m][0] = fS[m * I.npts + idx];
+      }
     } else {
 #pragma unroll
       for (int qq = 0; qq < NQ; qq++) {
@@ -335,13 +356,17 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
         f[1][qq] = R[idx];
         f[2][qq] = Gf[idx];
         if constexpr (HP) f[3][qq] = phiPrev[idx];
+        if constexpr (FT) {
+#pragma unroll
+          for (int m = 0; m < kMaxForcing; m++) f[4 + m][qq] = fS[m * I.npts + idx];
+        }
       }
     }
   };
 
   double ycarry = 0.0;
   double gcarry = 0.0;  // g at the last position of the previous chunk (kUni path)
-  auto process = [&](double (&v)[M], double (&sg)[M], double (&f)[4][NQ], int k) {
+  auto process = [&](double (&v)[M], double (&sg)[M], double (&f)[NF][NQ], int k) {
     const int p0 = k * M;
     const int cnt = min(M, n_pos - p0);
     if constexpr (!kUni) {
@@ -351,7 +376,8 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
         if (q < G * M) {
           const int g = q / M, t = q - g * M;
 #pragma unroll
-          for (int c = 0; c < (HP ? 4 : 3); c++) sF[c][g][t] = f[c][qq];
+          for (int c = 0; c < NF; c++)
+            if (HP || c != 3) sF[c][g][t] = f[c][qq];
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -370,6 +396,10 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
     for (int t = 0; t < M; t++) {
       double d = v[t];
       if constexpr (HP) d = fma(fac(3, t), sg[t], d);
+      if constexpr (FT) {
+#pragma unroll
+        for (int m = 0; m < kMaxForcing; m++) d = fma(gl[m], fac(4 + m, t), d);
+      }
       y = fma(fac(0, t), y, d);
       v[t] = y;
     }
@@ -407,7 +437,7 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   };
 
   double vA[M], sA[M], vB[M], sB[M];
-  double fA[4][NQ], fB[4][NQ];
+  double fA[NF][NQ], fB[NF][NQ];
   issue(vA, sA, fA, 0);
   for (int k = 0; k < P; k += 2) {
     if (k + 1 < P) issue(vB, sB, fB, k + 1);
@@ -555,16 +585,27 @@ __device__ __forceinline__ void line_solve_lanes(double (&v)[kKMax], int K,
 constexpr int kLineBuf = line_buf_len(kKMax);
 
 // One row (contiguous, n values): src -> dst (may alias); buf is the wave's
-// LDS line buffer.
+// LDS line buffer. With S != NULL the right-hand side also receives
+// g0 S_0 + g1 S_1 (S_m at the row, S_1 = S_0 + spts).
 __device__ __forceinline__ void solve_row(const gdouble* src, gdouble* dst, const gdouble* Rb,
-                                          const gdouble* Gb, int n, int K, double* buf,
-                                          int lane) {
+                                          const gdouble* Gb, int n, int K, double* buf, int lane,
+                                          const gdouble* S = nullptr, long spts = 0,
+                                          double g0 = 0.0, double g1 = 0.0) {
   double v[kKMax], gq[kKMax], rq[kKMax];
 #pragma unroll
   for (int t = 0; t < kKMax; t++) {
     const int p = t * kWave + lane;
     const double x = src[p < n ? p : 0];
     v[t] = p < n ? x : 0.0;  // p >= n for every t >= K
+  }
+  if (S) {  // wave-uniform
+#pragma unroll
+    for (int t = 0; t < kKMax; t++) {
+      const int p = t * kWave + lane;
+      const int pc = p < n ? p : 0;
+      const double s0 = S[pc], s1 = S[spts + pc];
+      v[t] = p < n ? fma(g1, s1, fma(g0, s0, v[t])) : 0.0;
+    }
   }
   load_line_factors(gq, rq, K, Rb, Gb, lane);
 #pragma unroll
@@ -691,10 +732,12 @@ __device__ __forceinline__ int xcd_block(int bid, int nb) {
   return x * per + min(x, rem) + r;
 }
 
-// x-lines (rows) of one state, one wave per row.
+// x-lines (rows) of one state, one wave per row; with gtab the source
+// sum_m gtab[m * gstride + gidx] S_m joins the right-hand side.
 __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_x(
     const DimInst* __restrict__ insts, const double* __restrict__ src, double* __restrict__ dst,
-    const double* __restrict__ Rb, const double* __restrict__ Gb) {
+    const double* __restrict__ Rb, const double* __restrict__ Gb, const double* __restrict__ gtab,
+    long gidx, long gstride) {
   __shared__ double T[kRowsPerBlock * kLineBuf];
   const DimInst& I = insts[0];
   const int nx = I.nx, ny = I.ny, K = I.Kx;
@@ -702,8 +745,10 @@ __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_x(
   const int row = xcd_block(blockIdx.x, gridDim.x) * kRowsPerBlock + wv;
   if (row >= ny) return;  // whole wave; no block-level barrier follows
   const long base = (long)row * nx;
+  const gdouble* S = gtab ? gp(I.fS) + base : nullptr;
+  const double g0 = gtab ? gtab[gidx] : 0.0, g1 = gtab ? gtab[gstride + gidx] : 0.0;
   solve_row(gp(src) + base, gp(dst) + base, gp(Rb) + (long)row * kWave * K,
-            gp(Gb) + (long)row * kWave * K, nx, K, T + wv * kLineBuf, lane);
+            gp(Gb) + (long)row * kWave * K, nx, K, T + wv * kLineBuf, lane, S, I.npts, g0, g1);
 }
 
 // y-lines (columns) of one state, kColsPerBlock columns per block: dst = result.
@@ -737,8 +782,12 @@ __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_xb(
   if (row >= ny) return;  // whole wave
   const gdouble* src = c == 0 ? gp(U_base) + I.off_states + (long)n * I.npts : gp(I.tmp);
   const long base = (long)row * nx;
+  // source at the end of coarse step c of slice n
+  const gdouble* S = I.nforce ? gp(I.fS) + base : nullptr;
+  const long nc = (long)I.N * I.cs, gi = (long)n * I.cs + c;
+  const double g0 = I.nforce ? I.fgc[gi] : 0.0, g1 = I.nforce ? I.fgc[nc + gi] : 0.0;
   solve_row(src + base, gp(I.tmp) + base, gp(I.cxRb) + (long)row * kWave * K,
-            gp(I.cxGb) + (long)row * kWave * K, nx, K, T + wv * kLineBuf, lane);
+            gp(I.cxGb) + (long)row * kWave * K, nx, K, T + wv * kLineBuf, lane, S, I.npts, g0, g1);
 }
 
 // The increment of the correction (mode 1) goes to the instance's per-column-
@@ -870,6 +919,40 @@ __global__ void k_dr_stencil_nat(const DimInst* __restrict__ insts, const double
   out[t] = u0 + sv;
 }
 
+// ---------------------------------------------------------------- source ---
+// Z[b][node][l] += sum_m (dt g_m)(slice, step) S_m[node] for every node (DD
+// fine workspace, where the first stage of a step touches every node).
+__global__ void k_force_interleaved(const DimInst* __restrict__ insts, int step) {
+  const DimInst& I = insts[0];
+  const long total = (long)I.B * I.slab;
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int L = I.L;
+  const int l = (int)(t % L);
+  const long node_all = t / L;
+  const int b = (int)(node_all / I.npts);
+  const long node = node_all - (long)b * I.npts;
+  const int slice = b * L + l;
+  if (slice >= I.N) return;
+  const long nst = (long)I.N * I.steps, gi = (long)slice * I.steps + step;
+  double v = gp(I.Z)[t];
+#pragma unroll
+  for (int m = 0; m < kMaxForcing; m++) v = fma(gp(I.fgf)[m * nst + gi], gp(I.fS)[m * I.npts + node], v);
+  gp(I.Z)[t] = v;
+}
+
+// u += sum_m gtab[m * gstride + gidx] S_m (one state).
+__global__ void k_force_state(const DimInst* __restrict__ insts, double* __restrict__ u,
+                              const double* __restrict__ gtab, long gidx, long gstride) {
+  const DimInst& I = insts[0];
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= I.npts) return;
+  double v = u[t];
+#pragma unroll
+  for (int m = 0; m < kMaxForcing; m++) v = fma(gtab[m * gstride + gidx], I.fS[m * I.npts + t], v);
+  u[t] = v;
+}
+
 __global__ void k_fill_zero(double* __restrict__ p, size_t n) {
   size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -928,47 +1011,60 @@ hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, doub
   return hipGetLastError();
 }
 
-template <int L, int M, int DIR, bool HP, int SGN = 0>
+template <int L, int M, int DIR, bool HP, int SGN = 0, bool FT = false>
 static hipError_t launch_sweep_t(const DimInst* d_insts, const WorkItem* d_work, int n_work,
                                  int step, hipStream_t s) {
-  hipLaunchKernelGGL((k_fine_sweep<L, M, DIR, HP, SGN>), dim3(n_work), dim3(kWave), 0, s, d_insts,
-                     d_work, step);
+  hipLaunchKernelGGL((k_fine_sweep<L, M, DIR, HP, SGN, FT>), dim3(n_work), dim3(kWave), 0, s,
+                     d_insts, d_work, step);
   return hipGetLastError();
+}
+
+// x sweep: pending correction (hp), DR array added (SGN), source (FT)
+template <int L, int M, int SGN>
+static hipError_t launch_sweep_x(const DimInst* d_insts, const WorkItem* d_work, int n_work,
+                                 int has_prev, int step, hipStream_t s, bool forced) {
+  if (forced)
+    return has_prev ? launch_sweep_t<L, M, 0, true, SGN, true>(d_insts, d_work, n_work, step, s)
+                    : launch_sweep_t<L, M, 0, false, SGN, true>(d_insts, d_work, n_work, step, s);
+  return has_prev ? launch_sweep_t<L, M, 0, true, SGN>(d_insts, d_work, n_work, step, s)
+                  : launch_sweep_t<L, M, 0, false, SGN>(d_insts, d_work, n_work, step, s);
 }
 
 template <int L, int M>
 static hipError_t launch_sweep_lm(const DimInst* d_insts, const WorkItem* d_work, int n_work,
-                                  int dir, int has_prev, int step, hipStream_t s, int sgn) {
+                                  int dir, int has_prev, int step, hipStream_t s, int sgn,
+                                  bool forced) {
   if (sgn != 0) {  // Douglas-Rachford: x adds S, y subtracts it
-    if (dir == 0)
-      return has_prev ? launch_sweep_t<L, M, 0, true, 1>(d_insts, d_work, n_work, step, s)
-                      : launch_sweep_t<L, M, 0, false, 1>(d_insts, d_work, n_work, step, s);
+    if (dir == 0) return launch_sweep_x<L, M, 1>(d_insts, d_work, n_work, has_prev, step, s, forced);
     return launch_sweep_t<L, M, 1, true, -1>(d_insts, d_work, n_work, step, s);
   }
-  if (dir == 0)
-    return has_prev ? launch_sweep_t<L, M, 0, true>(d_insts, d_work, n_work, step, s)
-                    : launch_sweep_t<L, M, 0, false>(d_insts, d_work, n_work, step, s);
+  if (dir == 0) return launch_sweep_x<L, M, 0>(d_insts, d_work, n_work, has_prev, step, s, forced);
   return has_prev ? launch_sweep_t<L, M, 1, true>(d_insts, d_work, n_work, step, s)
                   : launch_sweep_t<L, M, 1, false>(d_insts, d_work, n_work, step, s);
 }
 
 template <int M>
 static hipError_t launch_sweep_m(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
-                                 int dir, int has_prev, int step, hipStream_t s, int sgn) {
+                                 int dir, int has_prev, int step, hipStream_t s, int sgn,
+                                 bool f) {
   switch (L) {
-    case 8: return launch_sweep_lm<8, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn);
-    case 16: return launch_sweep_lm<16, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn);
-    case 32: return launch_sweep_lm<32, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn);
-    case 64: return launch_sweep_lm<64, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn);
+    case 8: return launch_sweep_lm<8, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
+    case 16: return launch_sweep_lm<16, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
+    case 32: return launch_sweep_lm<32, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
+    case 64: return launch_sweep_lm<64, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
-                             int M, int dir, int has_prev, int step, hipStream_t s, int sgn) {
+                             int M, int dir, int has_prev, int step, hipStream_t s, int sgn,
+                             bool forced) {
+  if (forced && dir != 0) return hipErrorInvalidValue;
   switch (M) {
-    case 16: return launch_sweep_m<16>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn);
-    case 32: return launch_sweep_m<32>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn);
+    case 16:
+      return launch_sweep_m<16>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn, forced);
+    case 32:
+      return launch_sweep_m<32>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn, forced);
     default: return hipErrorInvalidValue;
   }
 }
@@ -988,10 +1084,10 @@ hipError_t launch_block_factors(const double* src, int n_lines, int n_pos, doubl
 }
 
 hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
-                           bool fine, hipStream_t s) {
+                           bool fine, hipStream_t s, const double* gtab, long gidx, long gstride) {
   hipLaunchKernelGGL(k_coarse_x, dim3((h.ny + kRowsPerBlock - 1) / kRowsPerBlock),
                      dim3(kWave * kRowsPerBlock), 0, s, d_inst, src, dst, fine ? h.fxRb : h.cxRb,
-                     fine ? h.fxGb : h.cxGb);
+                     fine ? h.fxGb : h.cxGb, gtab, gidx, gstride);
   return hipGetLastError();
 }
 
@@ -1000,6 +1096,21 @@ hipError_t launch_coarse_y(const DimInst* d_inst, const DimInst& h, const double
   hipLaunchKernelGGL(k_coarse_y, dim3((h.nx + kColsPerBlock - 1) / kColsPerBlock),
                      dim3(kColThreads), 0, s, d_inst, src, dst, fine ? h.fyRb : h.cyRb,
                      fine ? h.fyGb : h.cyGb);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_interleaved(const DimInst* d_inst, const DimInst& h, int step,
+                                    hipStream_t s) {
+  const long total = (long)h.B * h.slab;
+  hipLaunchKernelGGL(k_force_interleaved, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     d_inst, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_state(const DimInst* d_inst, const DimInst& h, double* u,
+                              const double* gtab, long gidx, long gstride, hipStream_t s) {
+  hipLaunchKernelGGL(k_force_state, dim3((unsigned)((h.npts + 255) / 256)), dim3(256), 0, s,
+                     d_inst, u, gtab, gidx, gstride);
   return hipGetLastError();
 }
 
