@@ -174,11 +174,16 @@ def bench_batch(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["varcoef2d", "dd1d", "batch"], default="varcoef2d",
+    ap.add_argument("--workload", choices=["varcoef2d", "dd1d", "batch", "manufactured"],
+                    default="varcoef2d",
                     help="varcoef2d: 2D variable coefficient 1023^2, N=64, s=64 (default); "
                          "dd1d: 1D domain decomposition 2^20 nodes, 8 components, N=32, s=128; "
                          "batch: 256 uneven 2D instances, batched parareal vs a loop of "
-                         "single-instance launches")
+                         "single-instance launches; manufactured: the paper's test problem "
+                         "(h = 1e-3, DT = 0.05, dt = 2.5e-3, T = 1, source term), errors "
+                         "against the exact solution")
+    ap.add_argument("--fine", choices=["fie", "dr"], default="fie",
+                    help="fine propagator (eq. FIE_method or eq. DR_method)")
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--copy-probe-mib", type=int, default=512,
                     help="size of a plain device-to-device copy timed in the same run (0: skip)")
@@ -207,8 +212,11 @@ def main():
         return bench_batch(args)
     if args.workload == "dd1d":
         w = W.config3()
+    elif args.workload == "manufactured":
+        w = W.manufactured2d(999, 20, 20)
     else:
         w = W.config2(n=args.n, n_slices=args.slices, fine_steps=args.fine_steps)
+    w.fine = args.fine
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -218,13 +226,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     N, s, npts = w.n_slices, w.fine_steps, w.nx * w.ny
-    inst = dict(dim=w.dim, nx=w.nx, ny=w.ny, T=w.T, n_slices=N, fine_steps=s, split=w.split)
+    inst = dict(dim=w.dim, nx=w.nx, ny=w.ny, T=w.T, n_slices=N, fine_steps=s, split=w.split,
+                fine=w.fine)
     if w.theta is not None:
         inst["theta"] = w.theta
     else:
         inst["ax"], inst["ay"] = w.ax, w.ay
     if w.rho is not None:
         inst["rho"] = w.rho
+    if w.forcing is not None:
+        inst["forcing"] = w.forcing
     prob = pr.Problem([inst])
     u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
     U = prob.new_states()
@@ -290,7 +301,7 @@ def main():
         "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}" if w.dim == 2 else f"{w.nx}",
                    "slices": N, "fine_steps": s, "coarse_steps": 1,
                    "split": "domain decomposition" if w.split == "dd" else "dimensional",
-                   "integrators": "FIE/FIE",
+                   "integrators": "FIE/" + w.fine.upper(),
                    "step": "one parareal iteration: F^s on all slices + serial coarse sweep "
                            "with correction and increment"},
         "roofline": {"bound": "hbm",
@@ -348,6 +359,17 @@ def main():
                               "rel_err_vs_sequential": err}
         log(f"parareal: {k[0]} iterations, {t_par:.3f} s; sequential fine {t_seq:.3f} s; "
             f"rel err vs sequential {err:.2e}")
+        if "exact_space" in w.extra:
+            # the paper's error measure: max over the coarse time levels of the discrete
+            # 2-norm of the difference to the exact solution
+            Sx = torch.as_tensor(w.extra["exact_space"], device=dev).reshape(-1)
+            tn = torch.arange(N + 1, device=dev, dtype=torch.float64) * (w.T / N)
+            ex = torch.sin(2 * torch.pi * tn)[:, None] * Sx[None, :]
+            h = 1.0 / (w.nx + 1)
+            e2 = lambda V: (((V - ex) ** 2).sum(dim=1).sqrt() * h).max().item()
+            result["manufactured"] = {"error_parareal": e2(Ub3), "error_sequential_fine": e2(Us3),
+                                      "h": h, "DT": w.T / N, "dt": w.T / N / s}
+            log(f"error vs exact solution: parareal {e2(Ub3):.3e}, sequential fine {e2(Us3):.3e}")
     print(json.dumps(result), flush=True)
 
 

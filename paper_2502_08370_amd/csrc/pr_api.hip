@@ -150,6 +150,7 @@ struct pr_problem_s {
     int L = 0;
     int dr = 0;                // Douglas-Rachford instances (the sweeps add / subtract S)
     int ft = 0;                // instances with a source term (the x sweep adds it)
+    int M = 32;                // chunk length of the group's sweeps
     std::vector<int> members;  // instances of the group
     WorkItem* d_work[2] = {nullptr, nullptr};
     int n_work[2] = {0, 0};
@@ -315,7 +316,9 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   const int B = (N + L - 1) / L;
   I.Ldef = L;
   DimInst& h = I.h;
-  const int Mc = P->M;
+  // Douglas-Rachford sweeps hold three arrays per chunk (values, S, carries):
+  // they use the short chunk
+  const int Mc = d.fine == PR_DR ? kDRChunk : P->M;
   h.nx = nx; h.ny = ny; h.N = N; h.L = L; h.B = B; h.M = Mc;
   h.Px = (nx + Mc - 1) / Mc; h.Py = (ny + Mc - 1) / Mc;
   h.steps = d.fine_steps;
@@ -351,7 +354,7 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
 pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
                              const double* coef_y, hipStream_t s) {
   const pr_problem_desc& d = I.d;
-  const int nx = d.nx, ny = d.ny, M = P->M;
+  const int nx = d.nx, ny = d.ny, M = I.h.M;
   if (d.coef_mode == PR_COEF_NODAL_LOG) {
     const size_t nth = (size_t)(nx + 2) * (ny + 2);
     if (I.theta.n != nth) HIPOK(I.theta.alloc(nth));
@@ -722,17 +725,17 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   for (int q = 0; q < P->n_passes; q++) {
     for (int t = 0; t < smax; t++) {
       for (auto& g : P->groups) {
-        if (g.dr) {  // S = dt A_y U of this step's input
+        if (g.dr && t == 0) {  // S = dt A_y U of the input; later steps' S come from the y sweep
           PhaseTimer pt(P, PH_FINE, s);
           for (int i : g.members)
-            HIPOK(launch_dr_stencil(P->d_inst + i, P->inst[i]->h, t > 0, t, q * P->pass_blocks,
+            HIPOK(launch_dr_stencil(P->d_inst + i, P->inst[i]->h, 0, t, q * P->pass_blocks,
                                     (q + 1) * P->pass_blocks, s));
         }
         for (int dir = 0; dir < 2; dir++) {
           const int off = g.pass_off[dir][q], cnt = g.pass_off[dir][q + 1] - off;
           if (!cnt) continue;
           PhaseTimer pt(P, PH_FINE, s);
-          HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir] + off, cnt, g.L, P->M, dir,
+          HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir] + off, cnt, g.L, g.M, dir,
                                   dir == 1 || t > 0, t, s, g.dr ? (dir == 0 ? 1 : -1) : 0,
                                   dir == 0 && g.ft));
         }
@@ -904,12 +907,13 @@ pr_status build_schedules(pr_problem_s* P) {
       g.L = L;
       g.dr = dr;
       g.ft = ft;
+      g.M = dr ? kDRChunk : P->M;
       g.members = members;
       for (int dir = 0; dir < 2; dir++) {
         std::vector<WorkItem> all;
         g.pass_off[dir].assign(1, 0);
         for (int q = 0; q < P->n_passes; q++) {
-          std::vector<WorkItem> part = build_work(members, P->inst, dir, P->M, q * bpp, (q + 1) * bpp);
+          std::vector<WorkItem> part = build_work(members, P->inst, dir, g.M, q * bpp, (q + 1) * bpp);
           all.insert(all.end(), part.begin(), part.end());
           g.pass_off[dir].push_back((int)all.size());
         }
@@ -969,12 +973,14 @@ pr_status apply_layout(pr_problem_s* P, int lanes_cap, int M) {
     h.L = L;
     h.B = (N + L - 1) / L;
     h.slab = (long)nx * ny * L;
-    if (M != h.M) {
-      h.M = M;
-      h.Px = (nx + M - 1) / M;
-      h.Py = (ny + M - 1) / M;
-      HIPOK(launch_chunk_phi(I.fxG.p, ny, nx, M, I.fxPhiC.p, I.fxPhiS.p, nullptr));
-      if (I.d.dim == 2) HIPOK(launch_chunk_phi(I.fyG.p, nx, ny, M, I.fyPhiC.p, I.fyPhiS.p, nullptr));
+    const int Mi = I.d.fine == PR_DR ? kDRChunk : M;
+    if (Mi != h.M) {
+      h.M = Mi;
+      h.Px = (nx + Mi - 1) / Mi;
+      h.Py = (ny + Mi - 1) / Mi;
+      HIPOK(launch_chunk_phi(I.fxG.p, ny, nx, Mi, I.fxPhiC.p, I.fxPhiS.p, nullptr));
+      if (I.d.dim == 2)
+        HIPOK(launch_chunk_phi(I.fyG.p, nx, ny, Mi, I.fyPhiC.p, I.fyPhiS.p, nullptr));
     }
   }
   P->M = M;

@@ -66,7 +66,10 @@ struct DimInst {
   long off_slices, off_states;  // offsets of the instance in packed buffers
   const int* active; // per-instance flags (0: converged, skipped by every kernel)
   // Douglas-Rachford fine propagator (eq. DR_method): S = dt A_y U of the step's
-  // input, stored like Z; the x sweep adds it on load, the y sweep subtracts it
+  // input, stored like Z. The x sweep adds it on load (and writes back S with
+  // its pending correction applied), the y sweep subtracts it; since the y
+  // stage solves (I - dt A_y) U' = Y, the next step's S = dt A_y U' = U' - Y is
+  // formed by the y sweep itself (stored with U''s pending chunk correction)
   int dr;
   double* drS;       // [B][ny][nx][L]
   const double* ay;  // y-face coefficients [(ny+1)][nx]
@@ -81,6 +84,7 @@ struct DimInst {
 };
 
 constexpr int kMaxForcing = 2;
+constexpr int kDRChunk = 16;  // chunk length of the Douglas-Rachford sweeps
 
 // Work item of a batched coarse launch: instance and line block.
 struct LineItem {

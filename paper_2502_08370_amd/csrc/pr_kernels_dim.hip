@@ -284,8 +284,10 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   const gdouble* zrow_u = gp(I.Z) + w.b * I.slab + (long)line0 * lstr;
   const gdouble* sgrow_u = sigPrev + ((long)(line0 / M) * nl_prev) * L;
   const unsigned usl = (unsigned)sl;  // lane offset (unsigned: scalar-base addressing)
-  // DR: the stencil array lives at the same offsets as Z
+  // DR: the stencil array lives at the same offsets as Z; its values are held
+  // in their own registers (sv) and combined when the chunk is processed
   const long drOff = SGN != 0 ? (long)(I.drS - I.Z) : 0;
+  constexpr int MS = SGN != 0 ? M : 1;
   // source: dt * g_m of this lane's slice at this step (0 on padding slices)
   double gl[kMaxForcing] = {};
   const gdouble* fS = FT ? gp(I.fS) : nullptr;
@@ -299,7 +301,8 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       gl[m] = slice < I.N ? g : 0.0;
     }
   }
-  auto issue = [&](double (&v)[M], double (&sg)[M], double (&f)[NF][NQ], int k) {
+  auto issue = [&](double (&v)[M], double (&sv)[MS], double (&sg)[M], double (&f)[NF][NQ],
+                   int k) {
     const int p0 = k * M;
     const int cnt = min(M, n_pos - p0);
     if constexpr (kUni) {
@@ -309,7 +312,7 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       for (int t = 0; t < M; t++) {
         const int tt = (cnt == M || t < cnt) ? t : 0;
         v[t] = (zc + (long)tt * pstr)[usl];
-        if constexpr (SGN != 0) v[t] = fma((double)SGN, (zc + drOff + (long)tt * pstr)[usl], v[t]);
+        if constexpr (SGN != 0) sv[t] = (zc + drOff + (long)tt * pstr)[usl];
         if constexpr (HP) sg[t] = (sc + (long)tt * L)[usl];
       }
     } else {
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
 #pragma unroll
         for (int t = 0; t < M; t++) {
           v[t] = zc[t * pstr];
-          if constexpr (SGN != 0) v[t] = fma((double)SGN, zc[drOff + t * pstr], v[t]);
+          if constexpr (SGN != 0) sv[t] = zc[drOff + t * pstr];
         }
         if constexpr (HP) {
 #pragma unroll
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
         for (int t = 0; t < M; t++) {
           const int tt = t < cnt ? t : 0;
           v[t] = zc[tt * pstr];
-          if constexpr (SGN != 0) v[t] = fma((double)SGN, zc[drOff + tt * pstr], v[t]);
+          if constexpr (SGN != 0) sv[t] = zc[drOff + tt * pstr];
           if constexpr (HP) sg[t] = sc[tt * L];
         }
       }
@@ -366,7 +369,8 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
 
   double ycarry = 0.0;
   double gcarry = 0.0;  // g at the last position of the previous chunk (kUni path)
-  auto process = [&](double (&v)[M], double (&sg)[M], double (&f)[NF][NQ], int k) {
+  auto process = [&](double (&v)[M], double (&sv)[MS], double (&sg)[M], double (&f)[NF][NQ],
+                     int k) {
     const int p0 = k * M;
     const int cnt = min(M, n_pos - p0);
     if constexpr (!kUni) {
@@ -396,6 +400,14 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
     for (int t = 0; t < M; t++) {
       double d = v[t];
       if constexpr (HP) d = fma(fac(3, t), sg[t], d);
+      if constexpr (SGN > 0) {
+        // x stage of DR: U + S; S carries the same pending correction as U
+        if constexpr (HP) sv[t] = fma(fac(3, t), sg[t], sv[t]);
+        d = d + sv[t];
+      } else if constexpr (SGN < 0) {
+        d = d - sv[t];  // y stage: W - S
+        sv[t] = d;      // kept: the next step's S is U' - (W - S)
+      }
       if constexpr (FT) {
 #pragma unroll
         for (int m = 0; m < kMaxForcing; m++) d = fma(gl[m], fac(4 + m, t), d);
@@ -411,25 +423,41 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       z = fma(fac(2, t), z, fac(1, t) * v[t]);
       v[t] = z;
     }
+    if constexpr (SGN < 0) {
+#pragma unroll
+      for (int t = 0; t < M; t++) sv[t] = v[t] - sv[t];  // S' = U' - Y (same pending correction)
+    }
     if constexpr (kUni) {
       gdouble* zc = (gdouble*)zrow_u + (long)p0 * pstr;
       if (cnt == M) {
 #pragma unroll
-        for (int t = 0; t < M; t++) (zc + (long)t * pstr)[usl] = v[t];
+        for (int t = 0; t < M; t++) {
+          (zc + (long)t * pstr)[usl] = v[t];
+          if constexpr (SGN != 0) (zc + drOff + (long)t * pstr)[usl] = sv[t];
+        }
       } else {
 #pragma unroll
         for (int t = 0; t < M; t++)
-          if (t < cnt) (zc + (long)t * pstr)[usl] = v[t];
+          if (t < cnt) {
+            (zc + (long)t * pstr)[usl] = v[t];
+            if constexpr (SGN != 0) (zc + drOff + (long)t * pstr)[usl] = sv[t];
+          }
       }
     } else if (active) {
       gdouble* zc = zbase + (long)p0 * pstr;
       if (cnt == M) {
 #pragma unroll
-        for (int t = 0; t < M; t++) zc[t * pstr] = v[t];
+        for (int t = 0; t < M; t++) {
+          zc[t * pstr] = v[t];
+          if constexpr (SGN != 0) zc[drOff + t * pstr] = sv[t];
+        }
       } else {
 #pragma unroll
         for (int t = 0; t < M; t++)
-          if (t < cnt) zc[t * pstr] = v[t];
+          if (t < cnt) {
+            zc[t * pstr] = v[t];
+            if constexpr (SGN != 0) zc[drOff + t * pstr] = sv[t];
+          }
       }
     }
     zfirst[k][lane] = v[0];  // resolved into the chunk's carry below
@@ -437,14 +465,15 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   };
 
   double vA[M], sA[M], vB[M], sB[M];
+  double svA[MS], svB[MS];
   double fA[NF][NQ], fB[NF][NQ];
-  issue(vA, sA, fA, 0);
+  issue(vA, svA, sA, fA, 0);
   for (int k = 0; k < P; k += 2) {
-    if (k + 1 < P) issue(vB, sB, fB, k + 1);
-    process(vA, sA, fA, k);
+    if (k + 1 < P) issue(vB, svB, sB, fB, k + 1);
+    process(vA, svA, sA, fA, k);
     if (k + 1 < P) {
-      if (k + 2 < P) issue(vA, sA, fA, k + 2);
-      process(vB, sB, fB, k + 1);
+      if (k + 2 < P) issue(vA, svA, sA, fA, k + 2);
+      process(vB, svB, sB, fB, k + 1);
     }
   }
   // chunk carries: sigma_{P-1} = 0, sigma_k = zfirst_{k+1} + phi_{(k+1) start} sigma_{k+1}
@@ -1034,9 +1063,14 @@ template <int L, int M>
 static hipError_t launch_sweep_lm(const DimInst* d_insts, const WorkItem* d_work, int n_work,
                                   int dir, int has_prev, int step, hipStream_t s, int sgn,
                                   bool forced) {
-  if (sgn != 0) {  // Douglas-Rachford: x adds S, y subtracts it
-    if (dir == 0) return launch_sweep_x<L, M, 1>(d_insts, d_work, n_work, has_prev, step, s, forced);
-    return launch_sweep_t<L, M, 1, true, -1>(d_insts, d_work, n_work, step, s);
+  if (sgn != 0) {  // Douglas-Rachford (short chunks only): x adds S, y subtracts it
+    if constexpr (M == kDRChunk) {
+      if (dir == 0)
+        return launch_sweep_x<L, M, 1>(d_insts, d_work, n_work, has_prev, step, s, forced);
+      return launch_sweep_t<L, M, 1, true, -1>(d_insts, d_work, n_work, step, s);
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
   if (dir == 0) return launch_sweep_x<L, M, 0>(d_insts, d_work, n_work, has_prev, step, s, forced);
   return has_prev ? launch_sweep_t<L, M, 1, true>(d_insts, d_work, n_work, step, s)
