@@ -213,10 +213,10 @@ __global__ __launch_bounds__(kWave) void k_dd_local(const DDInst* __restrict__ i
     z = fma(sG[gsub][t], z, sR[gsub][t] * v[t]);
     v[t] = z;
   }
-  if (active) {
+  if (active) {  // streaming stores: each value is read once, by a later substep
 #pragma unroll
     for (int t = 0; t < M; t++)
-      if (t < sg.len) zb[(long)t * L] = v[t];
+      if (t < sg.len) __builtin_nontemporal_store(v[t], &zb[(long)t * L]);
     const long bi = ((long)b * I.n_segs + sg_i) * L + sl;
     gp(I.Yb)[bi] = y;
     gp(I.Za)[bi] = v[0];
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(4 * kWave) void k_dd_from_interleaved(
   for (int u = 0; u < kIt; u++) {
     const int sl = w + 4 * u, slice = b * L + sl;
     if (sl < L && slice < I.N && lane < cnt)
-      F[(long)slice * I.n + i0 + lane] = tile[sl][lane];
+      __builtin_nontemporal_store(tile[sl][lane], &F[(long)slice * I.n + i0 + lane]);
   }
 }
 

@@ -228,7 +228,9 @@ __global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
 // correction of the previous (other-direction) sweep is added on load.
 // A partial last chunk is computed in full on clamped loads: the line's last
 // back-substitution factor is 0, so the padded positions cannot leak into the
-// real ones, and only real positions are stored.
+// real ones, and only real positions are stored. The workspace values are
+// written with nontemporal stores (each is read once, by the next sweep), which
+// keeps the reused carries and factors in the caches.
 template <int L, int M, int DIR, bool HP, int SGN = 0, bool FT = false>
 __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict__ insts,
                                                       const WorkItem* __restrict__ work,
@@ -432,15 +434,15 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       if (cnt == M) {
 #pragma unroll
         for (int t = 0; t < M; t++) {
-          (zc + (long)t * pstr)[usl] = v[t];
-          if constexpr (SGN != 0) (zc + drOff + (long)t * pstr)[usl] = sv[t];
+          __builtin_nontemporal_store(v[t], &(zc + (long)t * pstr)[usl]);
+          if constexpr (SGN != 0) __builtin_nontemporal_store(sv[t], &(zc + drOff + (long)t * pstr)[usl]);
         }
       } else {
 #pragma unroll
         for (int t = 0; t < M; t++)
           if (t < cnt) {
-            (zc + (long)t * pstr)[usl] = v[t];
-            if constexpr (SGN != 0) (zc + drOff + (long)t * pstr)[usl] = sv[t];
+            __builtin_nontemporal_store(v[t], &(zc + (long)t * pstr)[usl]);
+            if constexpr (SGN != 0) __builtin_nontemporal_store(sv[t], &(zc + drOff + (long)t * pstr)[usl]);
           }
       }
     } else if (active) {
@@ -448,15 +450,15 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       if (cnt == M) {
 #pragma unroll
         for (int t = 0; t < M; t++) {
-          zc[t * pstr] = v[t];
-          if constexpr (SGN != 0) zc[drOff + t * pstr] = sv[t];
+          __builtin_nontemporal_store(v[t], &zc[t * pstr]);
+          if constexpr (SGN != 0) __builtin_nontemporal_store(sv[t], &zc[drOff + t * pstr]);
         }
       } else {
 #pragma unroll
         for (int t = 0; t < M; t++)
           if (t < cnt) {
-            zc[t * pstr] = v[t];
-            if constexpr (SGN != 0) zc[drOff + t * pstr] = sv[t];
+            __builtin_nontemporal_store(v[t], &zc[t * pstr]);
+            if constexpr (SGN != 0) __builtin_nontemporal_store(sv[t], &zc[drOff + t * pstr]);
           }
       }
     }
