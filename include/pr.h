@@ -221,6 +221,23 @@ pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hi
 pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, double* grad_u0,
                      double* grad_coef, double* U_ckpt, void* hip_stream);
 
+/* Parallel-in-time adjoint (not in the paper; derived from the transpose of
+ * eq. FIE_method): same outputs as pr_adjoint. The adjoint of one slice's fine
+ * map is the fine map of the transposed grid (each step: y solve, then x
+ * solve), so the boundary adjoints lambda_n (lambda_N = lambda_T) are computed
+ * as the states of the transposed problem, either exactly by its sequential
+ * fine solve (k_max = 0) or by parareal on that backward problem (k_max > 0
+ * corrections at most, stopping below tol; *k_done receives the count, host
+ * pointer, may be NULL). Then every slice recomputes its forward steps and
+ * runs its reverse steps at once, with the face gradients accumulated over
+ * slices. Device workspace: two states per fine step per slice (2*s*N*nx*ny
+ * doubles) plus small carries; PR_ENOMEM when it does not fit. Single
+ * instance, 2D dimensional splitting, FIE fine propagator (else
+ * PR_EUNSUPPORTED). Synchronous when k_max > 0, else asynchronous. */
+pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lambda_T,
+                              double* grad_u0, double* grad_coef, double* U_ckpt, int k_max,
+                              double tol, int* k_done, void* hip_stream);
+
 /* Phase timers. When enabled, the library records a pair of hipEvents on the
  * work stream around every launch and accumulates their elapsed times per
  * phase (no extra synchronisation is added while recording). Phases:

@@ -243,3 +243,14 @@ class Problem:
     def adjoint(self, u0, lambda_T, grad_u0, grad_coef, U_ckpt=None, stream=None):
         B.check(B.lib().pr_adjoint(self._h, _ptr(u0), _ptr(lambda_T), _ptr(grad_u0),
                                    _ptr(grad_coef), _ptr(U_ckpt), _stream(stream)))
+
+    def adjoint_parallel(self, u0, lambda_T, grad_u0, grad_coef, U_ckpt=None, k_max=0, tol=0.0,
+                         stream=None):
+        """Parallel-in-time adjoint (pr_adjoint_parallel): k_max = 0 computes the
+        boundary adjoints exactly, k_max > 0 by parareal on the backward problem.
+        Returns the number of backward parareal corrections done."""
+        k = C.c_int(0)
+        B.check(B.lib().pr_adjoint_parallel(self._h, _ptr(u0), _ptr(lambda_T), _ptr(grad_u0),
+                                            _ptr(grad_coef), _ptr(U_ckpt), int(k_max), float(tol),
+                                            C.byref(k), _stream(stream)))
+        return k.value

@@ -51,6 +51,8 @@ struct DBuf {
     if (p) (void)hipFree(p);
   }
   hipError_t alloc(size_t count) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
     n = count;
     if (count == 0) return hipSuccess;
     return hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(double));
@@ -124,6 +126,10 @@ struct Instance {
   DDInst* d_dd = nullptr;     // device copies [hdd, hdd1]
   // adjoint workspace (allocated on the first pr_adjoint call)
   DBuf adjWV, adjCkpt, adjLam, adjMu, adjGax, adjGay;
+  // parallel-in-time adjoint: forward snapshots of every step of every slice,
+  // their chunk carries, the adjoint workspace, the boundary adjoints
+  DBuf pSnap, pSigX, pSigY, pInit, pLam, pSigXa, pSigYa, pBnd, pBndT, pLamIn, pCoefT0, pCoefT1;
+  DArr<DimInst> pDesc;
   ~Instance() {
     if (d_dd) (void)hipFree(d_dd);
   }
@@ -180,7 +186,9 @@ struct pr_problem_s {
   double graph_tol = -1.0;
   const double* graph_U = nullptr;
   int lanes_cap = 0;  // 0: each instance uses its default lane width
+  pr_problem_s* adjT = nullptr;  // transposed problem of the parallel-in-time adjoint
   ~pr_problem_s() {
+    delete adjT;
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (gstream) (void)hipStreamDestroy(gstream);
@@ -1154,6 +1162,11 @@ pr_status pr_set_coefficients(pr_problem p, int instance, const double* coef_x,
   Instance& I = *p->inst[instance];
   if (!coef_x || (I.d.dim == 2 && I.d.coef_mode == PR_COEF_FACES && !coef_y))
     return fail(PR_EINVAL, "NULL coefficient pointer");
+  if (p->adjT) {  // the transposed problem of the parallel adjoint is rebuilt on demand
+    (void)hipDeviceSynchronize();
+    delete p->adjT;
+    p->adjT = nullptr;
+  }
   if (I.dd) return factorize_dd_instance(I, coef_x, as_stream(hip_stream));
   return factorize_instance(p, I, coef_x, coef_y, as_stream(hip_stream));
 }
@@ -1424,6 +1437,174 @@ pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, dou
     }
   }
   HIPOK(launch_copy(I.adjLam.p, grad_u0, npts, s));
+  if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
+    HIPOK(launch_theta_chain(I.theta.p, I.adjGax.p, I.adjGay.p, nx, ny, grad_coef, s));
+  } else {
+    HIPOK(launch_copy(I.adjGax.p, grad_coef, I.adjGax.n, s));
+    HIPOK(launch_copy(I.adjGay.p, grad_coef + I.adjGax.n, I.adjGay.n, s));
+  }
+  return PR_OK;
+}
+
+// Parallel-in-time adjoint (not in the paper; derived from the transpose of
+// eq. FIE_method). One FIE step is V = By^{-1} Bx^{-1} (U + dt F) with
+// symmetric Bx, By, so the adjoint of the fine map of one slice is s steps of
+// "y solve, then x solve" — the forward map of the transposed grid. The
+// boundary adjoints lambda_n = F_n^T lambda_{n+1} are therefore the states of
+// the transposed problem started from lambda_T^T: its sequential fine solve
+// (k_max = 0, exact) or parareal (k_max > 0, tolerance tol), run through an
+// internal handle. With lambda_{n+1} known for every slice, all slices
+// recompute their forward steps at once (batched sweeps, every step's state
+// kept) and run their reverse steps at once, accumulating the face gradients
+// over slices.
+pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lambda_T,
+                              double* grad_u0, double* grad_coef, double* U_ckpt, int k_max,
+                              double tol, int* k_done, void* hip_stream) {
+  if (!p || !u0 || !lambda_T || !grad_u0 || !grad_coef) return fail(PR_EINVAL, "NULL argument");
+  if (p->inst.size() != 1)
+    return fail(PR_EUNSUPPORTED, "pr_adjoint_parallel needs a single-instance handle");
+  if (k_max < 0 || !(tol >= 0)) return fail(PR_EINVAL, "k_max must be >= 0 and tol >= 0");
+  Instance& I = *p->inst[0];
+  if (I.dd || I.d.dim != 2)
+    return fail(PR_EUNSUPPORTED, "pr_adjoint_parallel supports 2D dimensional splitting");
+  if (I.d.fine != PR_FIE)
+    return fail(PR_EUNSUPPORTED, "pr_adjoint_parallel supports the FIE fine propagator only");
+  hipStream_t s = as_stream(hip_stream);
+  const int nx = I.d.nx, ny = I.d.ny, N = I.d.n_slices, S = I.d.fine_steps;
+  const size_t npts = I.npts;
+  const DimInst& h = I.h;
+  const pr_problem_s::Group& g = p->groups.at(0);
+  // 1. transposed problem (once per handle): nx <-> ny, coefficients transposed
+  if (!p->adjT) {
+    pr_problem_desc dT = I.d;
+    dT.nx = ny;
+    dT.ny = nx;
+    dT.n_forcing = 0;
+    dT.forcing_space = dT.forcing_time_fine = dT.forcing_time_coarse = nullptr;
+    dT.rho = nullptr;
+    if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
+      HIPOK(I.pCoefT0.alloc((size_t)(nx + 2) * (ny + 2)));
+      HIPOK(launch_transpose_states(I.theta.p, I.pCoefT0.p, nx + 2, ny + 2, 1, s));
+      dT.coef_x = I.pCoefT0.p;
+      dT.coef_y = nullptr;
+    } else {  // x-faces of the transposed grid are the y-faces, and back
+      HIPOK(I.pCoefT0.alloc((size_t)nx * (ny + 1)));
+      HIPOK(I.pCoefT1.alloc((size_t)(nx + 1) * ny));
+      HIPOK(launch_transpose_states(I.ay.p, I.pCoefT0.p, nx, ny + 1, 1, s));
+      HIPOK(launch_transpose_states(I.ax.p, I.pCoefT1.p, nx + 1, ny, 1, s));
+      dT.coef_x = I.pCoefT0.p;
+      dT.coef_y = I.pCoefT1.p;
+    }
+    HIPOK(hipStreamSynchronize(s));
+    pr_problem hT = nullptr;
+    pr_status st = pr_create_problem(&dT, 1, hip_stream, &hT);
+    if (st != PR_OK) return st;
+    p->adjT = hT;
+  }
+  // 2. forward checkpoints at the slice boundaries (exact sequential fine solve)
+  if (!U_ckpt && I.adjCkpt.n != (size_t)(N + 1) * npts) HIPOK(I.adjCkpt.alloc((size_t)(N + 1) * npts));
+  double* ckpt = U_ckpt ? U_ckpt : I.adjCkpt.p;
+  pr_status st = seq_fine_dim(p, 0, u0, ckpt, s);
+  if (st != PR_OK) return st;
+  // 3. boundary adjoints: states of the transposed problem from lambda_T^T
+  if (I.pBnd.n != (size_t)(N + 1) * npts) {
+    HIPOK(I.pBnd.alloc((size_t)(N + 1) * npts));
+    HIPOK(I.pBndT.alloc((size_t)(N + 1) * npts));
+    HIPOK(I.pLamIn.alloc((size_t)N * npts));
+  }
+  HIPOK(launch_transpose_states(lambda_T, I.pBndT.p, nx, ny, 1, s));  // u0 of the transposed problem
+  int kd = 0;
+  if (k_max == 0) {
+    st = pr_sequential_fine(p->adjT, I.pBndT.p, I.pBndT.p, hip_stream);
+  } else {
+    double incT = 0.0;
+    HIPOK(launch_copy(I.pBndT.p, I.pBnd.p, npts, s));  // pr_parareal_iterate reads u0 separately
+    st = pr_parareal_iterate(p->adjT, I.pBnd.p, I.pBndT.p, k_max, tol, &kd, &incT, hip_stream);
+  }
+  if (st != PR_OK) return st;
+  if (k_done) *k_done = kd;
+  // transposed state m is lambda_{N-m}^T
+  HIPOK(launch_transpose_states(I.pBndT.p, I.pBnd.p, ny, nx, N + 1, s));
+  for (int n = 0; n < N; n++)  // slice n ends with lambda_{n+1} = state N-1-n
+    HIPOK(launch_copy(I.pBnd.p + (size_t)(N - 1 - n) * npts, I.pLamIn.p + (size_t)n * npts, npts, s));
+  // 4. workspaces and per-step descriptors
+  const size_t slabs = (size_t)h.B * h.slab;
+  const size_t nsx = (size_t)h.B * ny * h.Px * h.L, nsy = (size_t)h.B * nx * h.Py * h.L;
+  if (I.pSnap.n != 2 * (size_t)S * slabs || I.pSigX.n != (size_t)S * nsx) {
+    HIPOK(I.pSnap.alloc(2 * (size_t)S * slabs));
+    HIPOK(I.pSigX.alloc((size_t)S * nsx));
+    HIPOK(I.pSigY.alloc((size_t)S * nsy));
+    HIPOK(I.pInit.alloc(slabs));
+    HIPOK(I.pLam.alloc(slabs));
+    HIPOK(I.pSigXa.alloc(nsx));
+    HIPOK(I.pSigYa.alloc(nsy));
+  }
+  auto snap = [&](int k) { return I.pSnap.p + (size_t)k * slabs; };
+  // descriptors: [0] checkpoints, [1 + 2t] x step t, [2 + 2t] y step t,
+  // [2S + 1 + 2t] W_t, [2S + 2 + 2t] V_t, [4S + 1] adjoint workspace
+  std::vector<DimInst> D(4 * (size_t)S + 2, h);
+  for (auto& d : D) {
+    d.active = nullptr;
+    d.zout = 0;
+  }
+  D[0].Z = I.pInit.p;
+  for (int t = 0; t < S; t++) {
+    DimInst& dx = D[1 + 2 * t];
+    dx.Z = t == 0 ? I.pInit.p : snap(2 * t - 1);
+    dx.zout = (long)(snap(2 * t) - dx.Z);
+    dx.sigY = t == 0 ? I.pSigY.p : I.pSigY.p + (size_t)(t - 1) * nsy;
+    dx.sigX = I.pSigX.p + (size_t)t * nsx;
+    DimInst& dy = D[2 + 2 * t];
+    dy.Z = snap(2 * t);
+    dy.zout = (long)(snap(2 * t + 1) - dy.Z);
+    dy.sigX = I.pSigX.p + (size_t)t * nsx;
+    dy.sigY = I.pSigY.p + (size_t)t * nsy;
+    DimInst& gw = D[2 * S + 1 + 2 * t];
+    gw.Z = snap(2 * t);
+    gw.sigX = I.pSigX.p + (size_t)t * nsx;
+    DimInst& gv = D[2 * S + 2 + 2 * t];
+    gv.Z = snap(2 * t + 1);
+    gv.sigY = I.pSigY.p + (size_t)t * nsy;
+  }
+  DimInst& da = D[4 * S + 1];
+  da.Z = I.pLam.p;
+  da.sigX = I.pSigXa.p;
+  da.sigY = I.pSigYa.p;
+  da.nforce = 0;
+  HIPOK(I.pDesc.upload(D));
+  const DimInst* Dd = I.pDesc.p;
+  // 5. recompute every forward step of every slice (sources included)
+  HIPOK(launch_to_interleaved(Dd, h, ckpt, s));
+  for (int t = 0; t < S; t++) {
+    PhaseTimer pt(p, PH_FINE, s);
+    HIPOK(launch_fine_sweep(Dd + 1 + 2 * t, g.d_work[0], g.n_work[0], g.L, g.M, 0, t > 0, t, s, 0,
+                            g.ft != 0));
+    HIPOK(launch_fine_sweep(Dd + 2 + 2 * t, g.d_work[1], g.n_work[1], g.L, g.M, 1, 1, t, s, 0,
+                            false));
+  }
+  // 6. reverse steps of every slice from lambda_{n+1}: y solve, face gradients
+  //    with V_t, x solve, face gradients with W_t
+  if (I.adjGax.n != (size_t)ny * (nx + 1)) HIPOK(I.adjGax.alloc((size_t)ny * (nx + 1)));
+  if (I.adjGay.n != (size_t)(ny + 1) * nx) HIPOK(I.adjGay.alloc((size_t)(ny + 1) * nx));
+  HIPOK(launch_fill_zero(I.adjGax.p, I.adjGax.n, s));
+  HIPOK(launch_fill_zero(I.adjGay.p, I.adjGay.n, s));
+  const double hx = 1.0 / (nx + 1), hy = 1.0 / (ny + 1);
+  const double cx = I.dt / (hx * hx), cy = I.dt / (hy * hy);
+  const DimInst* Da = Dd + 4 * S + 1;
+  HIPOK(launch_to_interleaved(Da, h, I.pLamIn.p, s));
+  for (int t = S - 1; t >= 0; t--) {
+    {
+      PhaseTimer pt(p, PH_FINE, s);
+      HIPOK(launch_fine_sweep(Da, g.d_work[1], g.n_work[1], g.L, g.M, 1, t < S - 1, t, s, 0, false));
+    }
+    HIPOK(launch_grad_faces(1, Da, Dd + 2 * S + 2 + 2 * t, h, cy, I.adjGay.p, s));
+    {
+      PhaseTimer pt(p, PH_FINE, s);
+      HIPOK(launch_fine_sweep(Da, g.d_work[0], g.n_work[0], g.L, g.M, 0, 1, t, s, 0, false));
+    }
+    HIPOK(launch_grad_faces(0, Da, Dd + 2 * S + 1 + 2 * t, h, cx, I.adjGax.p, s));
+  }
+  HIPOK(launch_slice_xcorr(Da, h, 0, grad_u0, s));  // lambda_0
   if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
     HIPOK(launch_theta_chain(I.theta.p, I.adjGax.p, I.adjGay.p, nx, ny, grad_coef, s));
   } else {

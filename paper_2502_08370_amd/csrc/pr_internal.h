@@ -39,6 +39,7 @@ struct DimInst {
   int steps;         // fine steps per slice; grouped sweeps skip instances past it
   long slab;         // doubles per slice block of Z: ny*nx*L
   double* Z;         // [B][ny][nx][L]
+  long zout;         // fine sweeps store at Z + zout (0: in place)
   double* sigX;      // [B][Px][ny][L]  chunk carries of the x sweep
   double* sigY;      // [B][Py][nx][L]  chunk carries of the y sweep
   // fine factorisations, line-major: x-line j entry (j*nx + i), y-line i entry (i*ny + j)
@@ -222,6 +223,18 @@ hipError_t launch_face_grad_y(const double* mu, const double* V, int nx, int ny,
                               double* gay, hipStream_t s);
 hipError_t launch_theta_chain(const double* theta, const double* gax, const double* gay, int nx,
                               int ny, double* gth, hipStream_t s);
+// Batched face gradients of the parallel-in-time adjoint: g[face] += -coef *
+// sum over slices (a_q - a_p)(w_q - w_p), a and w the true values (pending
+// chunk correction of a sweep of direction dir applied) of the workspaces
+// described by A and Bst (device descriptors; h is A's host copy).
+hipError_t launch_grad_faces(int dir, const DimInst* A, const DimInst* Bst, const DimInst& h,
+                             double coef, double* g, hipStream_t s);
+// Batched 2D transposes of count states: out[s][i][j] = in[s][j][i].
+hipError_t launch_transpose_states(const double* in, double* out, int nx, int ny, int count,
+                                   hipStream_t s);
+// One slice of an interleaved workspace after an x sweep, corrected, natural layout.
+hipError_t launch_slice_xcorr(const DimInst* A, const DimInst& h, int slice, double* out,
+                              hipStream_t s);
 
 // ---- launchers (pr_kernels_dim.hip) ----
 hipError_t launch_faces_from_theta_2d(const double* theta, int nx, int ny, double* ax, double* ay,

@@ -290,6 +290,7 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   // in their own registers (sv) and combined when the chunk is processed
   const long drOff = SGN != 0 ? (long)(I.drS - I.Z) : 0;
   constexpr int MS = SGN != 0 ? M : 1;
+  const long zo = I.zout;  // stores go to Z + zout (out-of-place recompute of the adjoint)
   // source: dt * g_m of this lane's slice at this step (0 on padding slices)
   double gl[kMaxForcing] = {};
   const gdouble* fS = FT ? gp(I.fS) : nullptr;
@@ -434,14 +435,14 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       if (cnt == M) {
 #pragma unroll
         for (int t = 0; t < M; t++) {
-          __builtin_nontemporal_store(v[t], &(zc + (long)t * pstr)[usl]);
+          __builtin_nontemporal_store(v[t], &(zc + zo + (long)t * pstr)[usl]);
           if constexpr (SGN != 0) __builtin_nontemporal_store(sv[t], &(zc + drOff + (long)t * pstr)[usl]);
         }
       } else {
 #pragma unroll
         for (int t = 0; t < M; t++)
           if (t < cnt) {
-            __builtin_nontemporal_store(v[t], &(zc + (long)t * pstr)[usl]);
+            __builtin_nontemporal_store(v[t], &(zc + zo + (long)t * pstr)[usl]);
             if constexpr (SGN != 0) __builtin_nontemporal_store(sv[t], &(zc + drOff + (long)t * pstr)[usl]);
           }
       }
@@ -450,14 +451,14 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       if (cnt == M) {
 #pragma unroll
         for (int t = 0; t < M; t++) {
-          __builtin_nontemporal_store(v[t], &zc[t * pstr]);
+          __builtin_nontemporal_store(v[t], &zc[zo + t * pstr]);
           if constexpr (SGN != 0) __builtin_nontemporal_store(sv[t], &zc[drOff + t * pstr]);
         }
       } else {
 #pragma unroll
         for (int t = 0; t < M; t++)
           if (t < cnt) {
-            __builtin_nontemporal_store(v[t], &zc[t * pstr]);
+            __builtin_nontemporal_store(v[t], &zc[zo + t * pstr]);
             if constexpr (SGN != 0) __builtin_nontemporal_store(sv[t], &zc[drOff + t * pstr]);
           }
       }

@@ -110,3 +110,94 @@ def test_adjoint_full_size():
     assert relerr(g0.cpu().numpy().reshape(ny, nx), rg0) <= TOL
     assert relerr(gth.cpu().numpy().reshape(ny + 2, nx + 2), rth) <= TOL
     _fd_check(w, theta_star, w.extra["dirs"])
+
+
+# ------------------------------------------------- parallel in time (N4) ---
+def _adjoint_pair(w, mode, k_max=0, tol=0.0, lam_seed=2):
+    nx, ny = w.nx, w.ny
+    P = gpu_problem(w)
+    lam = np.random.default_rng(lam_seed).standard_normal((ny, nx))
+    ncoef = (nx + 2) * (ny + 2) if mode == "theta" else ny * (nx + 1) + (ny + 1) * nx
+    out = {}
+    for name in ("serial", "parallel"):
+        g0 = torch.empty(nx * ny, dtype=torch.float64, device="cuda")
+        gc = torch.empty(ncoef, dtype=torch.float64, device="cuda")
+        ck = P.new_states()
+        if name == "serial":
+            P.adjoint(dev(w.u0), dev(lam), g0, gc, ck)
+            k = None
+        else:
+            k = P.adjoint_parallel(dev(w.u0), dev(lam), g0, gc, ck, k_max=k_max, tol=tol)
+        torch.cuda.synchronize()
+        out[name] = (g0.cpu().numpy(), gc.cpu().numpy(), ck.cpu().numpy(), k)
+    return out, lam
+
+
+@pytest.mark.parametrize("nx,ny,N,s,mode,c,lanes", [
+    (13, 9, 3, 4, "theta", 0.0, 0), (40, 33, 4, 3, "faces", 0.0, 0), (65, 70, 2, 5, "theta", 1.5, 0),
+    (47, 31, 40, 2, "theta", 0.0, 0), (50, 44, 70, 2, "faces", 0.3, 16), (33, 65, 9, 3, "theta", 0.0, 8)])
+def test_parallel_adjoint_matches_oracle(nx, ny, N, s, mode, c, lanes):
+    w = W.small_dim2(nx, ny, n_slices=N, fine_steps=s, seed=nx + N, c=c)
+    theta = w.theta
+    if mode == "faces":
+        w.ax, w.ay = oracle.faces_from_theta(nx, ny, w.theta)
+        w.theta = None
+    P, O = gpu_problem(w), oracle_problem(w)
+    if lanes:
+        P.set_option("lanes", lanes)
+    lam = np.random.default_rng(4).standard_normal((ny, nx))
+    ncoef = (nx + 2) * (ny + 2) if mode == "theta" else ny * (nx + 1) + (ny + 1) * nx
+    g0 = torch.empty(nx * ny, dtype=torch.float64, device="cuda")
+    gc = torch.empty(ncoef, dtype=torch.float64, device="cuda")
+    ck = P.new_states()
+    P.adjoint_parallel(dev(w.u0), dev(lam), g0, gc, ck)
+    torch.cuda.synchronize()
+    rg0, rgax, rgay = O.adjoint(w.u0, lam)
+    assert relerr(g0.cpu().numpy().reshape(ny, nx), rg0) <= TOL
+    if mode == "theta":
+        rth = oracle.theta_grad(nx, ny, theta, rgax, rgay)
+        assert relerr(gc.cpu().numpy().reshape(ny + 2, nx + 2), rth) <= TOL
+    else:
+        assert relerr(gc.cpu().numpy(), np.concatenate([rgax.ravel(), rgay.ravel()])) <= TOL
+    seq = O.sequential_fine(w.u0)
+    assert relerr(ck.cpu().numpy().reshape(seq.shape), seq) <= TOL
+
+
+def test_parallel_adjoint_with_source_matches_serial():
+    w = W.small_dim2(37, 29, n_slices=5, fine_steps=3, seed=12)
+    rng = np.random.default_rng(3)
+    w.forcing = (rng.standard_normal((2, 29, 37)), rng.standard_normal((2, 15)),
+                 rng.standard_normal((2, 5)))
+    out, _ = _adjoint_pair(w, "theta")
+    for a, b in zip(out["serial"][:3], out["parallel"][:3]):
+        assert relerr(b, a) <= TOL
+
+
+def test_parallel_adjoint_backward_parareal():
+    """Boundary adjoints by parareal on the backward problem: K = N corrections
+    reproduce the exact gradients (finite termination, section 3), and fewer
+    corrections give gradients whose error shrinks as K grows."""
+    w = W.small_dim2(45, 38, n_slices=8, fine_steps=4, seed=5)
+    exact, lam = _adjoint_pair(w, "theta")
+    g_ser, c_ser = exact["serial"][0], exact["serial"][1]
+    full, _ = _adjoint_pair(w, "theta", k_max=8, tol=0.0)
+    assert full["parallel"][3] == 8
+    assert relerr(full["parallel"][0], g_ser) <= TOL
+    assert relerr(full["parallel"][1], c_ser) <= TOL
+    errs = []
+    for K in (1, 3, 5):
+        r, _ = _adjoint_pair(w, "theta", k_max=K, tol=0.0)
+        assert r["parallel"][3] == K
+        errs.append(relerr(r["parallel"][1], c_ser))
+    assert errs[0] > errs[1] > errs[2]
+
+
+def test_parallel_adjoint_rejects_unsupported():
+    import paper_2502_08370_amd as pr
+    w = W.small_dim2(16, 16, 2, 2, seed=0)
+    w.fine = "dr"
+    P = gpu_problem(w)
+    z = torch.zeros(256, dtype=torch.float64, device="cuda")
+    gc = torch.zeros(18 * 18, dtype=torch.float64, device="cuda")
+    with pytest.raises(pr.PrError):
+        P.adjoint_parallel(dev(w.u0), z, z.clone(), gc)
