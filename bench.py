@@ -171,17 +171,81 @@ def bench_batch(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_adjoint(args):
+    """Gradient of 0.5 ||u(T) - u_obs||^2 with respect to u0 and theta on the
+    differentiation workload (511^2, N = 32, s = 32): the serial adjoint (one
+    reverse chain of N*s steps, per-slice recompute) against the parallel-in-time
+    adjoint (boundary adjoints by the transposed problem, exact or by backward
+    parareal to a tolerance, then every slice's recompute and reverse steps at
+    once). value = differentiated fine point-updates per second of the parallel
+    adjoint with exact boundary adjoints."""
+    import torch
+    import paper_2502_08370_amd as pr
+    import workloads as W
+    w = W.config5()
+    dev = torch.device("cuda:0")
+    n, N, s = w.nx, w.n_slices, w.fine_steps
+    P = pr.Problem([dict(dim=2, nx=n, ny=n, T=w.T, n_slices=N, fine_steps=s, theta=w.theta)])
+    Pstar = pr.Problem([dict(dim=2, nx=n, ny=n, T=w.T, n_slices=N, fine_steps=s,
+                             theta=w.extra["theta_star"])])
+    u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
+    Us = Pstar.new_states()
+    Pstar.sequential_fine(u0, Us)
+    Uf = P.new_states()
+    P.sequential_fine(u0, Uf)
+    npts = n * n
+    lam = (Uf[N * npts:] - Us[N * npts:]).contiguous()  # dL/du(T)
+    out = {}
+    for name, kw in (("serial", None), ("parallel_exact", dict(k_max=0)),
+                     ("parallel_parareal", dict(k_max=N, tol=1e-8 * lam.abs().max().item()))):
+        g0 = torch.empty(npts, dtype=torch.float64, device=dev)
+        gc = torch.empty((n + 2) ** 2, dtype=torch.float64, device=dev)
+        times = []
+        for rep in range(1 + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = None
+            if kw is None:
+                P.adjoint(u0, lam, g0, gc)
+            else:
+                k = P.adjoint_parallel(u0, lam, g0, gc, **kw)
+            torch.cuda.synchronize()
+            if rep:
+                times.append(time.perf_counter() - t0)
+        out[name] = (min(times), g0.clone(), gc.clone(), k)
+        log(f"{name}: {1e3 * min(times):.1f} ms" + (f", backward corrections {k}" if k else ""))
+    ref = out["serial"][2]
+    agree = {k: (v[2] - ref).abs().max().item() / ref.abs().max().item() for k, v in out.items()}
+    t_par = out["parallel_exact"][0]
+    pts = npts * N * s
+    result = {
+        "metric": METRIC, "value": round(pts / t_par / 1e9, 3), "unit": "Gpts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(1e3 * t_par, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": f"{n}x{n}", "slices": N, "fine_steps": s,
+                   "step": "gradient of a terminal misfit wrt u0 and theta (forward checkpoints, "
+                           "boundary adjoints, per-slice recompute and reverse steps)"},
+        "adjoint_ms": {k: round(1e3 * v[0], 3) for k, v in out.items()},
+        "backward_parareal_corrections": out["parallel_parareal"][3],
+        "theta_gradient_rel_diff_vs_serial": agree,
+        "speedup_parallel_exact_vs_serial": round(out["serial"][0] / t_par, 3),
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["varcoef2d", "dd1d", "batch", "manufactured"],
+    ap.add_argument("--workload", choices=["varcoef2d", "dd1d", "batch", "manufactured", "adjoint"],
                     default="varcoef2d",
                     help="varcoef2d: 2D variable coefficient 1023^2, N=64, s=64 (default); "
                          "dd1d: 1D domain decomposition 2^20 nodes, 8 components, N=32, s=128; "
                          "batch: 256 uneven 2D instances, batched parareal vs a loop of "
                          "single-instance launches; manufactured: the paper's test problem "
                          "(h = 1e-3, DT = 0.05, dt = 2.5e-3, T = 1, source term), errors "
-                         "against the exact solution")
+                         "against the exact solution; adjoint: serial vs parallel-in-time "
+                         "adjoint on 511^2, N=32, s=32")
     ap.add_argument("--fine", choices=["fie", "dr"], default="fie",
                     help="fine propagator (eq. FIE_method or eq. DR_method)")
     ap.add_argument("--instances", type=int, default=256)
@@ -210,6 +274,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
     if args.workload == "dd1d":
         w = W.config3()
     elif args.workload == "manufactured":

@@ -233,7 +233,8 @@ pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, dou
  * slices. Device workspace: two states per fine step per slice (2*s*N*nx*ny
  * doubles) plus small carries; PR_ENOMEM when it does not fit. Single
  * instance, 2D dimensional splitting, FIE fine propagator (else
- * PR_EUNSUPPORTED). Synchronous when k_max > 0, else asynchronous. */
+ * PR_EUNSUPPORTED). Synchronizes hip_stream on entry; with k_max > 0 the call
+ * is synchronous, otherwise the rest of the work is queued asynchronously. */
 pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lambda_T,
                               double* grad_u0, double* grad_coef, double* U_ckpt, int k_max,
                               double tol, int* k_done, void* hip_stream);

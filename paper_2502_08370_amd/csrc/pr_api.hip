@@ -130,6 +130,7 @@ struct Instance {
   // their chunk carries, the adjoint workspace, the boundary adjoints
   DBuf pSnap, pSigX, pSigY, pInit, pLam, pSigXa, pSigYa, pBnd, pBndT, pLamIn, pCoefT0, pCoefT1;
   DArr<DimInst> pDesc;
+  std::vector<DimInst> pDescHost;  // source of pDesc's stream-ordered upload
   ~Instance() {
     if (d_dd) (void)hipFree(d_dd);
   }
@@ -186,9 +187,14 @@ struct pr_problem_s {
   double graph_tol = -1.0;
   const double* graph_U = nullptr;
   int lanes_cap = 0;  // 0: each instance uses its default lane width
-  pr_problem_s* adjT = nullptr;  // transposed problem of the parallel-in-time adjoint
+  pr_problem_s* adjT = nullptr;  // transposed problem of the parallel adjoint
+  hipStream_t astream = nullptr;  // its stream (runs beside the forward checkpoints)
+  hipEvent_t aev[2] = {nullptr, nullptr};
   ~pr_problem_s() {
     delete adjT;
+    for (auto e : aev)
+      if (e) (void)hipEventDestroy(e);
+    if (astream) (void)hipStreamDestroy(astream);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (gstream) (void)hipStreamDestroy(gstream);
@@ -1474,60 +1480,9 @@ pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lamb
   const size_t npts = I.npts;
   const DimInst& h = I.h;
   const pr_problem_s::Group& g = p->groups.at(0);
-  // 1. transposed problem (once per handle): nx <-> ny, coefficients transposed
-  if (!p->adjT) {
-    pr_problem_desc dT = I.d;
-    dT.nx = ny;
-    dT.ny = nx;
-    dT.n_forcing = 0;
-    dT.forcing_space = dT.forcing_time_fine = dT.forcing_time_coarse = nullptr;
-    dT.rho = nullptr;
-    if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
-      HIPOK(I.pCoefT0.alloc((size_t)(nx + 2) * (ny + 2)));
-      HIPOK(launch_transpose_states(I.theta.p, I.pCoefT0.p, nx + 2, ny + 2, 1, s));
-      dT.coef_x = I.pCoefT0.p;
-      dT.coef_y = nullptr;
-    } else {  // x-faces of the transposed grid are the y-faces, and back
-      HIPOK(I.pCoefT0.alloc((size_t)nx * (ny + 1)));
-      HIPOK(I.pCoefT1.alloc((size_t)(nx + 1) * ny));
-      HIPOK(launch_transpose_states(I.ay.p, I.pCoefT0.p, nx, ny + 1, 1, s));
-      HIPOK(launch_transpose_states(I.ax.p, I.pCoefT1.p, nx + 1, ny, 1, s));
-      dT.coef_x = I.pCoefT0.p;
-      dT.coef_y = I.pCoefT1.p;
-    }
-    HIPOK(hipStreamSynchronize(s));
-    pr_problem hT = nullptr;
-    pr_status st = pr_create_problem(&dT, 1, hip_stream, &hT);
-    if (st != PR_OK) return st;
-    p->adjT = hT;
-  }
-  // 2. forward checkpoints at the slice boundaries (exact sequential fine solve)
-  if (!U_ckpt && I.adjCkpt.n != (size_t)(N + 1) * npts) HIPOK(I.adjCkpt.alloc((size_t)(N + 1) * npts));
-  double* ckpt = U_ckpt ? U_ckpt : I.adjCkpt.p;
-  pr_status st = seq_fine_dim(p, 0, u0, ckpt, s);
-  if (st != PR_OK) return st;
-  // 3. boundary adjoints: states of the transposed problem from lambda_T^T
-  if (I.pBnd.n != (size_t)(N + 1) * npts) {
-    HIPOK(I.pBnd.alloc((size_t)(N + 1) * npts));
-    HIPOK(I.pBndT.alloc((size_t)(N + 1) * npts));
-    HIPOK(I.pLamIn.alloc((size_t)N * npts));
-  }
-  HIPOK(launch_transpose_states(lambda_T, I.pBndT.p, nx, ny, 1, s));  // u0 of the transposed problem
-  int kd = 0;
-  if (k_max == 0) {
-    st = pr_sequential_fine(p->adjT, I.pBndT.p, I.pBndT.p, hip_stream);
-  } else {
-    double incT = 0.0;
-    HIPOK(launch_copy(I.pBndT.p, I.pBnd.p, npts, s));  // pr_parareal_iterate reads u0 separately
-    st = pr_parareal_iterate(p->adjT, I.pBnd.p, I.pBndT.p, k_max, tol, &kd, &incT, hip_stream);
-  }
-  if (st != PR_OK) return st;
-  if (k_done) *k_done = kd;
-  // transposed state m is lambda_{N-m}^T
-  HIPOK(launch_transpose_states(I.pBndT.p, I.pBnd.p, ny, nx, N + 1, s));
-  for (int n = 0; n < N; n++)  // slice n ends with lambda_{n+1} = state N-1-n
-    HIPOK(launch_copy(I.pBnd.p + (size_t)(N - 1 - n) * npts, I.pLamIn.p + (size_t)n * npts, npts, s));
-  // 4. workspaces and per-step descriptors
+  HIPOK(hipStreamSynchronize(s));
+  // 1. workspaces and per-step descriptors (the library's work of earlier calls
+  //    has drained: nothing reads them while they change)
   const size_t slabs = (size_t)h.B * h.slab;
   const size_t nsx = (size_t)h.B * ny * h.Px * h.L, nsy = (size_t)h.B * nx * h.Py * h.L;
   if (I.pSnap.n != 2 * (size_t)S * slabs || I.pSigX.n != (size_t)S * nsx) {
@@ -1542,7 +1497,8 @@ pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lamb
   auto snap = [&](int k) { return I.pSnap.p + (size_t)k * slabs; };
   // descriptors: [0] checkpoints, [1 + 2t] x step t, [2 + 2t] y step t,
   // [2S + 1 + 2t] W_t, [2S + 2 + 2t] V_t, [4S + 1] adjoint workspace
-  std::vector<DimInst> D(4 * (size_t)S + 2, h);
+  std::vector<DimInst>& D = I.pDescHost;
+  D.assign(4 * (size_t)S + 2, h);
   for (auto& d : D) {
     d.active = nullptr;
     d.zout = 0;
@@ -1572,6 +1528,74 @@ pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lamb
   da.sigY = I.pSigYa.p;
   da.nforce = 0;
   HIPOK(I.pDesc.upload(D));
+  // 2. transposed problem (once per handle): nx <-> ny, coefficients transposed
+  if (!p->adjT) {
+    pr_problem_desc dT = I.d;
+    dT.nx = ny;
+    dT.ny = nx;
+    dT.n_forcing = 0;
+    dT.forcing_space = dT.forcing_time_fine = dT.forcing_time_coarse = nullptr;
+    dT.rho = nullptr;
+    if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
+      HIPOK(I.pCoefT0.alloc((size_t)(nx + 2) * (ny + 2)));
+      HIPOK(launch_transpose_states(I.theta.p, I.pCoefT0.p, nx + 2, ny + 2, 1, s));
+      dT.coef_x = I.pCoefT0.p;
+      dT.coef_y = nullptr;
+    } else {  // x-faces of the transposed grid are the y-faces, and back
+      HIPOK(I.pCoefT0.alloc((size_t)nx * (ny + 1)));
+      HIPOK(I.pCoefT1.alloc((size_t)(nx + 1) * ny));
+      HIPOK(launch_transpose_states(I.ay.p, I.pCoefT0.p, nx, ny + 1, 1, s));
+      HIPOK(launch_transpose_states(I.ax.p, I.pCoefT1.p, nx + 1, ny, 1, s));
+      dT.coef_x = I.pCoefT0.p;
+      dT.coef_y = I.pCoefT1.p;
+    }
+    HIPOK(hipStreamSynchronize(s));
+    pr_problem hT = nullptr;
+    pr_status st = pr_create_problem(&dT, 1, hip_stream, &hT);
+    if (st != PR_OK) return st;
+    p->adjT = hT;
+  }
+  // 3. boundary adjoints: states of the transposed problem from lambda_T^T.
+  //    The exact chain runs on a second stream, beside the forward checkpoints
+  //    of step 4 (the two serial chains are independent).
+  if (!p->astream) {
+    HIPOK(hipStreamCreateWithFlags(&p->astream, hipStreamNonBlocking));
+    HIPOK(hipEventCreateWithFlags(&p->aev[0], hipEventDisableTiming));
+    HIPOK(hipEventCreateWithFlags(&p->aev[1], hipEventDisableTiming));
+  }
+  if (I.pBnd.n != (size_t)(N + 1) * npts) {
+    HIPOK(I.pBnd.alloc((size_t)(N + 1) * npts));
+    HIPOK(I.pBndT.alloc((size_t)(N + 1) * npts));
+    HIPOK(I.pLamIn.alloc((size_t)N * npts));
+  }
+  HIPOK(launch_transpose_states(lambda_T, I.pBndT.p, nx, ny, 1, s));  // u0 of the transposed problem
+  pr_status st = PR_OK;
+  int kd = 0;
+  hipStream_t bs = s;  // stream of the boundary-adjoint chain
+  if (k_max == 0) {
+    bs = p->astream;
+    HIPOK(hipEventRecord(p->aev[0], s));
+    HIPOK(hipStreamWaitEvent(bs, p->aev[0], 0));
+    st = pr_sequential_fine(p->adjT, I.pBndT.p, I.pBndT.p, bs);
+  } else {
+    double incT = 0.0;
+    HIPOK(launch_copy(I.pBndT.p, I.pBnd.p, npts, s));  // pr_parareal_iterate reads u0 separately
+    st = pr_parareal_iterate(p->adjT, I.pBnd.p, I.pBndT.p, k_max, tol, &kd, &incT, hip_stream);
+  }
+  if (st != PR_OK) return st;
+  if (k_done) *k_done = kd;
+  // transposed state m is lambda_{N-m}^T
+  HIPOK(launch_transpose_states(I.pBndT.p, I.pBnd.p, ny, nx, N + 1, bs));
+  for (int n = 0; n < N; n++)  // slice n ends with lambda_{n+1} = state N-1-n
+    HIPOK(launch_copy(I.pBnd.p + (size_t)(N - 1 - n) * npts, I.pLamIn.p + (size_t)n * npts, npts,
+                      bs));
+  if (bs != s) HIPOK(hipEventRecord(p->aev[1], bs));
+  // 4. forward checkpoints at the slice boundaries (exact sequential fine solve)
+  if (!U_ckpt && I.adjCkpt.n != (size_t)(N + 1) * npts) HIPOK(I.adjCkpt.alloc((size_t)(N + 1) * npts));
+  double* ckpt = U_ckpt ? U_ckpt : I.adjCkpt.p;
+  st = seq_fine_dim(p, 0, u0, ckpt, s);
+  if (st != PR_OK) return st;
+  if (bs != s) HIPOK(hipStreamWaitEvent(s, p->aev[1], 0));
   const DimInst* Dd = I.pDesc.p;
   // 5. recompute every forward step of every slice (sources included)
   HIPOK(launch_to_interleaved(Dd, h, ckpt, s));
