@@ -92,8 +92,9 @@ class Problem:
 
     dim: 1 or 2; nx, ny: interior nodes; T, n_slices (N_c), fine_steps (s),
     coarse_steps; split: 'dim' or 'dd'; fine: 'fie' or 'dr'; c: reaction;
-    ax (ny, nx+1) / ay (ny+1, nx): face coefficients; rho (M, nx+1): partition
-    of unity face weights for the domain-decomposition split (1D); forcing:
+    ax (ny, nx+1) / ay (ny+1, nx): face coefficients; rho: partition of unity
+    of the domain-decomposition split, (M, nx+1) face weights in 1D, (M, 2nx+1)
+    half-grid samples in x in 2D (vertical strips, see oracle.h); forcing:
     None or (S, g_fine, g_coarse) with S (m, ny, nx) the spatial factors of the
     source F(t) = sum_m g_m(t) S_m and g_fine (m, N*s), g_coarse (m, N*cs) its
     time factors at the fine / coarse step end times (see oracle.h).
@@ -109,7 +110,8 @@ class Problem:
         self.split, self.fine_method, self.c = split, fine, float(c)
         self.ax = _f64(ax).reshape(self.ny, self.nx + 1)
         self.ay = None if ay is None else _f64(ay).reshape(self.ny + 1, self.nx)
-        self.rho = None if rho is None else _f64(rho).reshape(-1, self.nx + 1)
+        rw = 2 * self.nx + 1 if self.dim == 2 else self.nx + 1
+        self.rho = None if rho is None else _f64(rho).reshape(-1, rw)
         self.fS = self.fgf = self.fgc = None
         nf = 0
         if forcing is not None:

@@ -26,6 +26,9 @@
  *  - second-order finite differences on the interior nodes of a uniform grid,
  *    h = 1/(n+1) per direction, coefficient sampled on cell faces;
  *  - x substep first, then y; domain-decomposition colours in index order;
+ *  - 2D domain decomposition: rho_j depends on x only (vertical strips) and is
+ *    applied where each flux lives (x-faces for x-fluxes, node columns for
+ *    y-fluxes and the reaction);
  *  - the parareal correction is evaluated as F_n + (G_new - G_old).
  */
 #include "oracle.h"
@@ -91,6 +94,111 @@ static void assemble_line(int n, const double* face, long face_stride, double h,
   }
 }
 
+/* Domain decomposition in 2D (section 2.1, Fig. fig:domaindecomposition:
+ * subdomains made of vertical strips). The partition of unity of colour j is
+ * sampled on the half grid of x: r[2f] on x-face f (between nodes f-1 and f),
+ * r[2i+1] at node column i. A_j discretises div(rho_j D grad u) - rho_j c u
+ * with rho_j taken where each flux lives: x-fluxes at the x-faces, y-fluxes
+ * (which sit at the node's x) at the node column, the reaction at the node.
+ * Entry of row (i,k) of I - tau A_j; returns the diagonal, and the couplings
+ * to the west, east, south and north neighbours through the out-pointers. */
+static double dd2_row(const or_problem* p, const double* r, double tau, int i, int k, double* w,
+                      double* e, double* so, double* no) {
+  const int nx = p->nx;
+  const double hx = hx_of(p), hy = hy_of(p);
+  const double fw = r[2 * i] * p->ax[(long)k * (nx + 1) + i] / (hx * hx);
+  const double fe = r[2 * i + 2] * p->ax[(long)k * (nx + 1) + i + 1] / (hx * hx);
+  const double fs = r[2 * i + 1] * p->ay[(long)k * nx + i] / (hy * hy);
+  const double fn = r[2 * i + 1] * p->ay[(long)(k + 1) * nx + i] / (hy * hy);
+  *w = -tau * fw;
+  *e = -tau * fe;
+  *so = -tau * fs;
+  *no = -tau * fn;
+  return 1.0 + tau * (fw + fe + fs + fn + r[2 * i + 1] * p->c);
+}
+
+/* A column takes part in colour j's operator when rho_j is nonzero on its
+ * node or on one of its two x-faces; otherwise its rows are identity rows. */
+static int dd2_active(const double* r, int i) {
+  return r[2 * i] > 0.0 || r[2 * i + 1] > 0.0 || r[2 * i + 2] > 0.0;
+}
+
+/* (I - tau A_j) V = U in place. Columns outside colour j's support are
+ * identity rows and no x-face couples a supported column to an unsupported
+ * one, so the system splits into one 2D system per maximal run of supported
+ * columns (a strip, a connected component of the subdomain). Each strip system
+ * is assembled in natural order (x fastest inside the strip, unknown
+ * k*w + (i - i0)), which makes it banded with half-bandwidth w, and solved by
+ * Gaussian elimination without pivoting (the matrix is a strictly diagonally
+ * dominant M-matrix) followed by back substitution. */
+static void dd2_substep(const or_problem* p, int j, double tau, double* U) {
+  const int nx = p->nx, ny = p->ny;
+  const double* r = p->rho + (long)j * (2 * nx + 1);
+  int i0 = 0;
+  while (i0 < nx) {
+    if (!dd2_active(r, i0)) {
+      i0++;
+      continue;
+    }
+    int i1 = i0;
+    while (i1 < nx && dd2_active(r, i1)) i1++;
+    const int w = i1 - i0;
+    const long n = (long)w * ny, bw = w, width = 2 * bw + 1;
+    double* A = (double*)calloc((size_t)(n * width), sizeof(double)); /* A[q][bw + (col - q)] */
+    double* b = (double*)malloc(sizeof(double) * n);
+    for (int k = 0; k < ny; k++)
+      for (int i = i0; i < i1; i++) {
+        const long q = (long)k * w + (i - i0);
+        double cw, ce, cs, cn;
+        A[q * width + bw] = dd2_row(p, r, tau, i, k, &cw, &ce, &cs, &cn);
+        if (i > i0) A[q * width + bw - 1] = cw;
+        if (i + 1 < i1) A[q * width + bw + 1] = ce;
+        if (k > 0) A[q * width + bw - w] = cs;
+        if (k + 1 < ny) A[q * width + bw + w] = cn;
+        b[q] = U[(long)k * nx + i];
+      }
+    for (long q = 0; q < n; q++) { /* eliminate column q below the diagonal */
+      const double piv = A[q * width + bw];
+      const long last = (q + bw < n - 1) ? q + bw : n - 1;
+      for (long t = q + 1; t <= last; t++) {
+        const double f = A[t * width + bw + (q - t)] / piv;
+        if (f == 0.0) continue;
+        for (long c = q; c <= q + bw && c < n; c++)
+          A[t * width + bw + (c - t)] = A[t * width + bw + (c - t)] - f * A[q * width + bw + (c - q)];
+        b[t] = b[t] - f * b[q];
+      }
+    }
+    for (long q = n - 1; q >= 0; q--) { /* back substitution */
+      double v = b[q];
+      for (long c = q + 1; c <= q + bw && c < n; c++) v = v - A[q * width + bw + (c - q)] * b[c];
+      b[q] = v / A[q * width + bw];
+    }
+    for (int k = 0; k < ny; k++)
+      for (int i = i0; i < i1; i++) U[(long)k * nx + i] = b[(long)k * w + (i - i0)];
+    free(A);
+    free(b);
+    i0 = i1;
+  }
+}
+
+/* A_j U for the 2D domain-decomposition split (the operator of dd2_row). */
+static void dd2_apply(const or_problem* p, int j, const double* U, double* out) {
+  const int nx = p->nx, ny = p->ny;
+  const double* r = p->rho + (long)j * (2 * nx + 1);
+  for (int k = 0; k < ny; k++)
+    for (int i = 0; i < nx; i++) {
+      double cw, ce, cs, cn;
+      const double d = dd2_row(p, r, 1.0, i, k, &cw, &ce, &cs, &cn) - 1.0;
+      const double u = U[(long)k * nx + i];
+      const double uw = (i > 0) ? U[(long)k * nx + i - 1] : 0.0;
+      const double ue = (i < nx - 1) ? U[(long)k * nx + i + 1] : 0.0;
+      const double us = (k > 0) ? U[(long)(k - 1) * nx + i] : 0.0;
+      const double un = (k < ny - 1) ? U[(long)(k + 1) * nx + i] : 0.0;
+      /* with tau = 1 the couplings are minus the flux weights */
+      out[(long)k * nx + i] = -(cw * uw + ce * ue + cs * us + cn * un) - d * u;
+    }
+}
+
 /* One implicit substep (I - tau*A_j) V = U along every line of the split
  * term j, in place. j = 0: x-lines (dimensional) or colour 0 (domain
  * decomposition). */
@@ -116,6 +224,8 @@ static void implicit_substep(const or_problem* p, int j, double tau, double* U) 
       }
       ws_free(&w);
     }
+  } else if (p->dim == 2) {
+    dd2_substep(p, j, tau, U);
   } else {
     /* Domain decomposition (1D): the operator of colour j uses the face
      * coefficient rho_j * a. Where rho_j vanishes on both faces of a node the
@@ -163,6 +273,8 @@ void or_apply_Aj(const or_problem* p, int j, const double* U, double* out) {
       for (int col = 0; col < nx; col++)
         apply_line(ny, p->ay + col, nx, hy_of(p), react, U + col, nx, out + col, nx, 0);
     }
+  } else if (p->dim == 2) {
+    dd2_apply(p, j, U, out);
   } else {
     double* wface = (double*)malloc(sizeof(double) * (nx + 1));
     for (int f = 0; f <= nx; f++) wface[f] = p->rho[(long)j * (nx + 1) + f] * p->ax[f];

@@ -18,8 +18,10 @@
  *    x-face f of row j, between nodes f-1 and f (f = 0 and f = nx touch the
  *    boundary). ay[g*nx + i] is the y-face g of column i, between nodes
  *    (i,g-1) and (i,g).
- *  - Domain decomposition (1D only): rho[k*(nx+1) + f] is the partition of
- *    unity weight of colour k on face f.
+ *  - Domain decomposition, 1D: rho[k*(nx+1) + f] is the partition of unity
+ *    weight of colour k on face f. 2D (vertical strips, rho depends on x
+ *    only): rho[k*(2*nx+1) + m] samples colour k's weight on the half grid of
+ *    x, m = 2f on x-face f and m = 2i+1 at node column i.
  *  - Source term (F of eq. FIE_method and eq. DR_method, homogeneous boundary
  *    data): F(t) = sum_m g_m(t) S_m with n_forcing spatial factors S_m (grid
  *    functions) and g_m given at the time levels the steps use: fine step j of
@@ -45,11 +47,12 @@ typedef struct {
   int coarse_steps;   /* FIE steps inside one coarse propagator call */
   int split;          /* 0: dimensional splitting, 1: domain decomposition */
   int fine_method;    /* 0: FIE, 1: Douglas-Rachford */
-  double c;           /* linear reaction coefficient (dimensional splitting) */
+  double c;           /* linear reaction coefficient (not used by the 1D DD split) */
   const double* ax;   /* ny*(nx+1) x-face coefficients */
   const double* ay;   /* (ny+1)*nx y-face coefficients, NULL when dim == 1 */
   int n_colors;       /* domain decomposition: number of split terms M */
-  const double* rho;  /* domain decomposition: n_colors*(nx+1) face weights */
+  const double* rho;  /* domain decomposition: n_colors*(nx+1) (1D) or
+                         n_colors*(2*nx+1) (2D) partition of unity samples */
   int n_forcing;            /* separable source terms; 0: F = 0 */
   const double* fS;         /* n_forcing*nx*ny spatial factors S_m */
   const double* fg_fine;    /* n_forcing*(n_slices*fine_steps) values g_m */

@@ -21,7 +21,7 @@ import scipy.fft
 __all__ = [
     "smooth_field_1d", "smooth_field_2d", "sine_modes_2d", "sine_series_1d",
     "linear_pou_1d", "Workload", "config1", "config2", "config3", "config4", "config5",
-    "small_dim2", "small_dd1",
+    "small_dim2", "small_dd1", "strip_pou_2d", "small_dd2", "dd2_manufactured",
 ]
 
 
@@ -112,6 +112,46 @@ def linear_pou_1d(n: int, n_cores: int, overlap: int, n_colors: int) -> np.ndarr
     return rho
 
 
+def strip_pou_2d(n: int, q: int, beta: float, n_colors: int = 2) -> np.ndarray:
+    """Partition of unity of the 2D domain decomposition into vertical strips:
+    n_colors * q equal cores of [0, 1] in x, core k of colour k % n_colors; across
+    each interior core boundary b the left core's weight falls from 1 to 0 over
+    [b - beta/2, b + beta/2] as cos^2(pi/2 (x - b + beta/2)/beta) and the right
+    core's rises as one minus it, so every colour's support is q strips, each
+    overlapping its neighbours by beta. Sampled on the half grid of x:
+    rho[k, m] at x = (m + 1) h / 2, m = 0..2n (m = 2f: x-face f, m = 2i+1: node i);
+    weights are exactly 0 or 1 outside the overlaps and sum to 1 everywhere."""
+    n_cores = n_colors * q
+    assert 0.0 < beta < 1.0 / n_cores
+    x = (np.arange(2 * n + 1) + 1) * (0.5 / (n + 1))
+    chi = np.zeros((n_cores, 2 * n + 1))
+    for k in range(n_cores):
+        left = np.ones_like(x)
+        right = np.ones_like(x)
+        if k > 0:
+            a = k / n_cores - beta / 2
+            t = np.clip((x - a) / beta, 0.0, 1.0)
+            left = 1.0 - np.cos(0.5 * np.pi * t) ** 2
+            left[x <= a] = 0.0
+            left[x >= a + beta] = 1.0
+        if k < n_cores - 1:
+            a = (k + 1) / n_cores - beta / 2
+            t = np.clip((x - a) / beta, 0.0, 1.0)
+            right = np.cos(0.5 * np.pi * t) ** 2
+            right[x <= a] = 1.0
+            right[x >= a + beta] = 0.0
+        chi[k] = np.minimum(left, right)
+    # make each overlap's pair sum to exactly one (the right weight is 1 - left)
+    for k in range(n_cores - 1):
+        a = (k + 1) / n_cores - beta / 2
+        m = (x > a) & (x < a + beta)
+        chi[k + 1, m] = 1.0 - chi[k, m]
+    rho = np.zeros((n_colors, 2 * n + 1))
+    for k in range(n_cores):
+        rho[k % n_colors] += chi[k]
+    return rho
+
+
 @dataclass
 class Workload:
     """One problem instance: shapes, times and input arrays (all float64 numpy)."""
@@ -129,7 +169,7 @@ class Workload:
     ax: Optional[np.ndarray] = None      # faces, (ny, nx+1)
     ay: Optional[np.ndarray] = None      # faces, (ny+1, nx)
     theta: Optional[np.ndarray] = None   # nodal log-coefficient on the extended grid
-    rho: Optional[np.ndarray] = None     # (M, nx+1)
+    rho: Optional[np.ndarray] = None     # (M, nx+1) in 1D, (M, 2nx+1) in 2D
     u0: Optional[np.ndarray] = None
     k_max: int = 0
     tol: float = 0.0
@@ -247,6 +287,31 @@ def small_dd1(n: int, n_cores: int, n_colors: int, overlap: int, n_slices: int, 
     return Workload(f"smalldd_{n}_M{n_colors}_q{n_cores // n_colors}", 1, n, 1, T, n_slices,
                     fine_steps, split="dd", theta=theta, rho=rho,
                     u0=sine_series_1d(n, seed=seed + 1, kmax=min(n, 64)), k_max=n_slices, tol=0.0)
+
+
+def small_dd2(nx: int, ny: int, q: int, beta: float, n_slices: int, fine_steps: int,
+              seed: int = 0, T: float = 0.01, n_colors: int = 2, variable: bool = True,
+              c: float = 0.0) -> Workload:
+    """Small 2D domain-decomposition case (vertical strips) for tests: log-normal
+    coefficient field (or a = 1), seeded sine-mode u0 plus small white noise."""
+    w = small_dim2(nx, ny, n_slices, fine_steps, seed=seed, T=T, variable=variable, c=c)
+    w.name = f"smalldd2_{nx}x{ny}_M{n_colors}_q{q}_N{n_slices}_s{fine_steps}"
+    w.split = "dd"
+    w.rho = strip_pou_2d(nx, q, beta, n_colors)
+    return w
+
+
+def dd2_manufactured(n: int = 999, n_slices: int = 20, fine_steps: int = 20, q: int = 2,
+                     beta: float = 1.0 / 16, coarse_steps: int = 1) -> Workload:
+    """The paper's 2D domain-decomposition runs (section 5, constant diagonal D):
+    the manufactured test problem split into two subdomains of q vertical strips
+    each with overlap beta, for both propagators. Defaults: h = 1e-3, DT = 0.05,
+    dt = 2.5e-3, q = 2, beta = 1/16."""
+    w = manufactured2d(n, n_slices, fine_steps, coarse_steps=coarse_steps)
+    w.name = f"dd2d_{n}_M2_q{q}_N{n_slices}_s{fine_steps}"
+    w.split = "dd"
+    w.rho = strip_pou_2d(n, q, beta, 2)
+    return w
 
 
 def step_end_times(T: float, n_slices: int, steps: int) -> np.ndarray:
