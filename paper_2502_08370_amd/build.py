@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpr.so")
-SOURCES = ["pr_api.hip", "pr_kernels_dim.hip", "pr_kernels_dd.hip", "pr_kernels_adj.hip"]
+SOURCES = ["pr_api.hip", "pr_kernels_dim.hip", "pr_kernels_dd.hip", "pr_kernels_dd2.hip",
+           "pr_kernels_adj.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

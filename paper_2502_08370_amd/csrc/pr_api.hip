@@ -124,6 +124,24 @@ struct Instance {
   DBuf Yb1, Za1, Yin1, Xin1;  // single-state carries
   DDInst hdd{}, hdd1{};       // interleaved fine workspace / single state (tmp)
   DDInst* d_dd = nullptr;     // device copies [hdd, hdd1]
+  // domain decomposition (2D, vertical strips; dd is also set)
+  bool dd2 = false;
+  struct Strip2 {
+    int colour, col0, w, W;
+    long bc0;  // first entry of the strip's coupling vectors in the bc arrays
+    // factor-pool offsets per level l and alive row a (-1: not stored)
+    std::vector<std::vector<long>> dinv, m2, m3, bm, cm;
+  };
+  std::vector<Strip2> strips2;
+  struct Phase2 {
+    int mode;  // DD2_* (units) or -1 (level-0 kept rows)
+    int off, cnt;
+  };
+  std::vector<std::vector<Phase2>> phases2;  // per colour, in launch order
+  DArr<DD2Unit> units2;
+  DArr<DD2Row> rows2;
+  DBuf pool2f, pool2c, bc2f, bc2c, rho2, Zs, Ys, Y1;
+  int Npad2 = 16;
   // adjoint workspace (allocated on the first pr_adjoint call)
   DBuf adjWV, adjCkpt, adjLam, adjMu, adjGax, adjGay;
   // parallel-in-time adjoint: forward snapshots of every step of every slice,
@@ -247,21 +265,23 @@ pr_status validate(const pr_problem_desc& d, int idx) {
     return fail(PR_EUNSUPPORTED, "instance %d: dimensional splitting supports nx, ny <= %d", idx,
                 kMaxCoarseLine);
   if (d.split == PR_SPLIT_DD) {
-    if (d.dim != 1) return fail(PR_EUNSUPPORTED, "instance %d: DD splitting is 1D only", idx);
-    if (d.c != 0.0) return fail(PR_EUNSUPPORTED, "instance %d: DD splitting needs c = 0", idx);
+    if (d.dim == 1 && d.c != 0.0)
+      return fail(PR_EUNSUPPORTED, "instance %d: 1D DD splitting needs c = 0", idx);
     if (d.n_colors < 1 || d.n_colors > 64)
       return fail(PR_EINVAL, "instance %d: n_colors must be in 1..64", idx);
     if (!d.rho) return fail(PR_EINVAL, "instance %d: rho is NULL", idx);
-    for (int f = 0; f <= d.nx; f++) {
+    // 1D: one weight per face; 2D: samples on the half grid of x
+    const int nr = d.dim == 1 ? d.nx + 1 : 2 * d.nx + 1;
+    for (int f = 0; f < nr; f++) {
       double sum = 0.0;
       for (int k = 0; k < d.n_colors; k++) {
-        double r = d.rho[(size_t)k * (d.nx + 1) + f];
+        double r = d.rho[(size_t)k * nr + f];
         if (!(r >= 0.0 && r <= 1.0))
           return fail(PR_EINVAL, "instance %d: rho[%d][%d] = %g outside [0, 1]", idx, k, f, r);
         sum += r;
       }
       if (std::fabs(sum - 1.0) > 1e-14)
-        return fail(PR_EINVAL, "instance %d: partition of unity sums to %.17g on face %d", idx,
+        return fail(PR_EINVAL, "instance %d: partition of unity sums to %.17g at sample %d", idx,
                     sum, f);
     }
   }
@@ -668,6 +688,347 @@ pr_status dd_fie_step(pr_problem_s* P, Instance& I, bool coarse, int which, int 
   return PR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// 2D domain decomposition (vertical strips). Strips of colour k are the maximal
+// runs of columns where rho_k is nonzero on the node or on one of its x-faces.
+
+// Factor-pool slots of one strip: every matrix the block cyclic reduction
+// stores, W x W each. Level l has n_l = ny >> l alive rows r = 2^l (a+1) - 1.
+long dd2_slots(Instance::Strip2& S, int ny, long next) {
+  const long sz = (long)S.W * S.W;
+  S.dinv.clear(); S.m2.clear(); S.m3.clear(); S.bm.clear(); S.cm.clear();
+  for (int l = 0; (ny >> l) > 0; l++) {
+    const int n = ny >> l;
+    std::vector<long> di(n, -1), m2(n, -1), m3(n, -1), bm(n, -1), cm(n, -1);
+    for (int a = 0; a < n; a++) {
+      if (a % 2 == 0) {
+        di[a] = next; next += sz;
+        if (l > 0 && a >= 1) { m2[a] = next; next += sz; }
+        if (l > 0 && a + 1 < n) { m3[a] = next; next += sz; }
+      } else if (l > 0) {
+        bm[a] = next; next += sz;
+        if (a + 1 < n) { cm[a] = next; next += sz; }
+      }
+    }
+    S.dinv.push_back(di); S.m2.push_back(m2); S.m3.push_back(m3);
+    S.bm.push_back(bm); S.cm.push_back(cm);
+  }
+  return next;
+}
+
+// Launch schedule of one colour: forward levels (eliminated rows y = D^-1 r,
+// then kept rows r -= B y_- + C y_+), then back substitution from the top
+// level down. Each output row block is split into units of nmb row tiles;
+// launches with few row blocks use smaller units so more waves share them.
+void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
+                  std::vector<DD2Row>& rows) {
+  const int ny = I.d.ny;
+  std::vector<Instance::Phase2> ph;
+  auto add_units = [&](int mode, const std::vector<DD2Unit>& tasks) {
+    if (tasks.empty()) return;
+    long tiles4 = 0;
+    for (auto& t : tasks) tiles4 += (t.W / 16 + 3) / 4;
+    const int nmb = tiles4 >= 512 ? 4 : (tiles4 >= 128 ? 2 : 1);
+    const int off = (int)units.size();
+    for (auto t : tasks)
+      for (int mb = 0; mb < t.W / 16; mb += nmb) {
+        t.mb0 = mb;
+        t.nmb = std::min(nmb, t.W / 16 - mb);
+        units.push_back(t);
+      }
+    ph.push_back({mode, off, (int)units.size() - off});
+  };
+  int L = 0;
+  while ((ny >> L) > 0) L++;
+  for (int l = 0; l < L; l++) {
+    const int n = ny >> l, st = 1 << l;
+    std::vector<DD2Unit> ap, kup;
+    std::vector<DD2Row> k0;
+    for (auto& S : I.strips2) {
+      if (S.colour != colour) continue;
+      for (int a = 0; a < n; a++) {
+        const int r = st * (a + 1) - 1;
+        DD2Unit u{S.col0, S.w, S.W, r, 0, 0, -1, -1, -1, -1, -1, S.bc0 + (long)r * 2 * S.W};
+        if (a % 2 == 0) {
+          u.A0 = S.dinv[l][a];
+          ap.push_back(u);
+        } else if (l == 0) {
+          k0.push_back(DD2Row{S.col0, S.w, S.W, r, r - 1, r + 1 < ny ? r + 1 : -1,
+                              S.bc0 + (long)r * 2 * S.W});
+        } else {
+          u.rowm = r - st; u.A1 = S.bm[l][a];
+          if (a + 1 < n) { u.rowp = r + st; u.A2 = S.cm[l][a]; }
+          kup.push_back(u);
+        }
+      }
+    }
+    add_units(DD2_APPLY, ap);
+    if (!k0.empty()) {
+      ph.push_back({-1, (int)rows.size(), (int)k0.size()});
+      rows.insert(rows.end(), k0.begin(), k0.end());
+    }
+    add_units(DD2_KUP, kup);
+  }
+  for (int l = L - 1; l >= 0; l--) {
+    const int n = ny >> l, st = 1 << l;
+    std::vector<DD2Unit> bk;
+    for (auto& S : I.strips2) {
+      if (S.colour != colour) continue;
+      for (int a = 0; a < n; a += 2) {
+        const int r = st * (a + 1) - 1;
+        DD2Unit u{S.col0, S.w, S.W, r, 0, 0, -1, -1, -1, -1, -1, S.bc0 + (long)r * 2 * S.W};
+        if (l == 0) {
+          u.A0 = S.dinv[0][a];
+          u.rowm = r >= 1 ? r - 1 : -1;
+          u.rowp = r + 1 < ny ? r + 1 : -1;
+        } else {
+          if (a >= 1) { u.rowm = r - st; u.A1 = S.m2[l][a]; }
+          if (a + 1 < n) { u.rowp = r + st; u.A2 = S.m3[l][a]; }
+        }
+        bk.push_back(u);
+      }
+    }
+    add_units(l == 0 ? DD2_BACK0 : DD2_BACK, bk);
+  }
+  I.phases2[colour] = ph;
+}
+
+pr_status setup_dd2_instance(Instance& I, const double* rho_host, hipStream_t s) {
+  const pr_problem_desc& d = I.d;
+  const int nx = d.nx, ny = d.ny, N = d.n_slices, K = d.n_colors;
+  const size_t npts = (size_t)nx * ny;
+  I.dd = true;
+  I.dd2 = true;
+  I.n_colors = K;
+  I.npts = (int)npts;
+  I.dt = d.T / d.n_slices / d.fine_steps;
+  I.tauG = d.T / d.n_slices / d.coarse_steps;
+  I.strips2.clear();
+  for (int k = 0; k < K; k++) {
+    const double* r = rho_host + (size_t)k * (2 * nx + 1);
+    auto active = [&](int i) { return r[2 * i] > 0.0 || r[2 * i + 1] > 0.0 || r[2 * i + 2] > 0.0; };
+    int i = 0;
+    while (i < nx) {
+      if (!active(i)) { i++; continue; }
+      int j = i;
+      while (j < nx && active(j)) j++;
+      Instance::Strip2 S;
+      S.colour = k; S.col0 = i; S.w = j - i; S.W = (S.w + 15) / 16 * 16; S.bc0 = 0;
+      if (S.W > kDD2MaxW)
+        return fail(PR_EUNSUPPORTED, "2D DD strip of %d columns (at most %d)", S.w, kDD2MaxW);
+      I.strips2.push_back(S);
+      i = j;
+    }
+  }
+  long next = 0, bcn = 0;
+  for (auto& S : I.strips2) {
+    next = dd2_slots(S, ny, next);
+    S.bc0 = bcn;
+    bcn += (long)ny * 2 * S.W;
+  }
+  std::vector<DD2Unit> units;
+  std::vector<DD2Row> rows;
+  I.phases2.assign(K, {});
+  for (int k = 0; k < K; k++) dd2_schedule(I, k, units, rows);
+  HIPOK(I.units2.upload(units));
+  HIPOK(I.rows2.upload(rows));
+  HIPOK(I.pool2f.alloc((size_t)std::max(1L, next)));
+  HIPOK(I.pool2c.alloc((size_t)std::max(1L, next)));
+  HIPOK(I.bc2f.alloc((size_t)std::max(1L, bcn)));
+  HIPOK(I.bc2c.alloc((size_t)std::max(1L, bcn)));
+  HIPOK(I.rho2.alloc((size_t)K * (2 * nx + 1)));
+  HIPOK(hipMemcpy(I.rho2.p, rho_host, I.rho2.n * sizeof(double), hipMemcpyHostToDevice));
+  HIPOK(I.ax.alloc((size_t)ny * (nx + 1)));
+  HIPOK(I.ay.alloc((size_t)(ny + 1) * nx));
+  I.Npad2 = (N + 15) / 16 * 16;
+  HIPOK(I.Zs.alloc(npts * I.Npad2));
+  HIPOK(I.Ys.alloc(npts * I.Npad2));
+  HIPOK(I.Y1.alloc(npts));
+  HIPOK(I.tmp.alloc(npts));
+  DimInst& h = I.h;
+  h.nx = nx; h.ny = ny; h.N = N; h.L = 1; h.B = 1; h.M = 1;
+  h.steps = d.fine_steps;
+  h.tmp = I.tmp.p;
+  return setup_forcing(I, d, s);
+}
+
+// Block cyclic reduction set-up of every strip at tau = dt (fine) and
+// tau = DT / coarse_steps (coarse), in the order the solve consumes it.
+pr_status factorize_dd2_instance(Instance& I, const double* coef_x, const double* coef_y,
+                                 hipStream_t s) {
+  const pr_problem_desc& d = I.d;
+  const int nx = d.nx, ny = d.ny;
+  if (d.coef_mode == PR_COEF_NODAL_LOG) {
+    HIPOK(launch_faces_from_theta_2d(coef_x, nx, ny, I.ax.p, I.ay.p, s));
+  } else {
+    HIPOK(hipMemcpyAsync(I.ax.p, coef_x, I.ax.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPOK(hipMemcpyAsync(I.ay.p, coef_y, I.ay.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  int Wmax = 16;
+  for (auto& S : I.strips2) Wmax = std::max(Wmax, S.W);
+  const long W2 = (long)Wmax * Wmax;
+  const int nE0 = (ny + 1) / 2, n1 = ny / 2, nE1 = (n1 + 1) / 2;
+  DBuf aug0, augL, D[2], B[2], C[2];
+  HIPOK(aug0.alloc((size_t)nE0 * 2 * W2));
+  if (n1 > 0) {
+    HIPOK(augL.alloc((size_t)nE1 * 4 * W2));
+    for (int q = 0; q < 2; q++) {
+      HIPOK(D[q].alloc((size_t)n1 * W2));
+      HIPOK(B[q].alloc((size_t)n1 * W2));
+      HIPOK(C[q].alloc((size_t)n1 * W2));
+    }
+  }
+  std::vector<std::unique_ptr<DArr<DD2Copy>>> keep_c;
+  std::vector<std::unique_ptr<DArr<DD2Gemm>>> keep_g;
+  auto store = [&](const std::vector<DD2Copy>& jobs, int W) -> pr_status {
+    if (jobs.empty()) return PR_OK;
+    keep_c.push_back(std::make_unique<DArr<DD2Copy>>());
+    HIPOK(keep_c.back()->upload(jobs));
+    HIPOK(launch_dd2_store(keep_c.back()->p, (int)jobs.size(), W, s));
+    return PR_OK;
+  };
+  auto gemm = [&](const std::vector<DD2Gemm>& jobs, int W) -> pr_status {
+    if (jobs.empty()) return PR_OK;
+    keep_g.push_back(std::make_unique<DArr<DD2Gemm>>());
+    HIPOK(keep_g.back()->upload(jobs));
+    HIPOK(launch_dd2_gemm(keep_g.back()->p, (int)jobs.size(), W, s));
+    return PR_OK;
+  };
+  const double hx = 1.0 / (nx + 1), hy = 1.0 / (ny + 1);
+  for (int coarse = 0; coarse < 2; coarse++) {
+    const double tau = coarse ? I.tauG : I.dt;
+    double* pool = coarse ? I.pool2c.p : I.pool2f.p;
+    double* bcp = coarse ? I.bc2c.p : I.bc2f.p;
+    for (auto& S : I.strips2) {
+      const int W = S.W;
+      const long w2 = (long)W * W;
+      DD2Geo g{I.ax.p, I.ay.p, I.rho2.p + (long)S.colour * (2 * nx + 1), nx, ny,
+               S.col0, S.w, W, 0, tau / (hx * hx), tau / (hy * hy), tau * d.c};
+      HIPOK(launch_dd2_bc(g, bcp + S.bc0, s));
+      // level 0: inverses of the eliminated rows, then the level-1 blocks
+      HIPOK(launch_dd2_build0(g, nE0, aug0.p, 2 * w2, s));
+      HIPOK(launch_dd2_gj(aug0.p, 2 * w2, nE0, W, 2 * W, s));
+      {
+        std::vector<DD2Copy> jobs;
+        for (int e = 0; e < nE0; e++)
+          jobs.push_back(DD2Copy{aug0.p + e * 2 * w2 + W, pool + S.dinv[0][2 * e], 2 * W, 0});
+        pr_status st = store(jobs, W);
+        if (st != PR_OK) return st;
+      }
+      if (n1 == 0) continue;
+      HIPOK(launch_dd2_scale0(g, bcp + S.bc0, aug0.p, 2 * w2, D[0].p, B[0].p, C[0].p, s));
+      int cur = 0;
+      for (int l = 1; (ny >> l) > 0; l++) {
+        const int n = ny >> l, nE = (n + 1) / 2;
+        double *Dc = D[cur].p, *Bc = B[cur].p, *Cc = C[cur].p;
+        HIPOK(launch_dd2_aug(Dc, Bc, Cc, nE, W, augL.p, s));
+        HIPOK(launch_dd2_gj(augL.p, 4 * w2, nE, W, 4 * W, s));
+        std::vector<DD2Copy> jobs;
+        for (int a = 0; a < n; a++) {
+          if (a % 2 == 0) {
+            const double* A = augL.p + (long)(a / 2) * 4 * w2;
+            jobs.push_back(DD2Copy{A + W, pool + S.dinv[l][a], 4 * W, 0});
+            if (S.m2[l][a] >= 0) jobs.push_back(DD2Copy{A + 2 * W, pool + S.m2[l][a], 4 * W, 0});
+            if (S.m3[l][a] >= 0) jobs.push_back(DD2Copy{A + 3 * W, pool + S.m3[l][a], 4 * W, 0});
+          } else {
+            jobs.push_back(DD2Copy{Bc + a * w2, pool + S.bm[l][a], W, 0});
+            if (S.cm[l][a] >= 0) jobs.push_back(DD2Copy{Cc + a * w2, pool + S.cm[l][a], W, 0});
+          }
+        }
+        pr_status st = store(jobs, W);
+        if (st != PR_OK) return st;
+        const int nn = n / 2;
+        if (nn == 0) break;
+        // kept row a -> alive row (a - 1) / 2 of level l + 1:
+        //   D' = D_a - B_a M3_{a-1} - C_a M2_{a+1}, B' = -B_a M2_{a-1}, C' = -C_a M3_{a+1}
+        const int nxt = 1 - cur;
+        std::vector<DD2Gemm> g1, g2;
+        for (int a = 1; a < n; a += 2) {
+          const long o = (long)((a - 1) / 2) * w2;
+          const double* Em = augL.p + (long)((a - 1) / 2) * 4 * w2;
+          g1.push_back(DD2Gemm{Bc + a * w2, Em + 3 * W, Dc + a * w2, D[nxt].p + o, W, 4 * W, W, W, -1.0});
+          g1.push_back(DD2Gemm{Bc + a * w2, Em + 2 * W, nullptr, B[nxt].p + o, W, 4 * W, W, W, -1.0});
+          if (a + 1 < n) {
+            const double* Ep = augL.p + (long)((a + 1) / 2) * 4 * w2;
+            g1.push_back(DD2Gemm{Cc + a * w2, Ep + 3 * W, nullptr, C[nxt].p + o, W, 4 * W, W, W, -1.0});
+            g2.push_back(DD2Gemm{Cc + a * w2, Ep + 2 * W, D[nxt].p + o, D[nxt].p + o, W, 4 * W, W, W, -1.0});
+          } else {
+            HIPOK(launch_fill_zero(C[nxt].p + o, w2, s));
+          }
+        }
+        st = gemm(g1, W);
+        if (st != PR_OK) return st;
+        st = gemm(g2, W);
+        if (st != PR_OK) return st;
+        cur = nxt;
+      }
+    }
+  }
+  HIPOK(hipStreamSynchronize(s));  // set-up buffers and job lists are released on return
+  return PR_OK;
+}
+
+// One colour's substep (I - tau A_k) over the strips of colour k: fine or
+// coarse factors; the slice-minor fine workspace or the single state in tmp.
+pr_status dd2_substep(pr_problem_s* P, Instance& I, bool coarse, bool single, int colour,
+                      hipStream_t s) {
+  const double* pool = coarse ? I.pool2c.p : I.pool2f.p;
+  const double* bc = coarse ? I.bc2c.p : I.bc2f.p;
+  double* Z = single ? I.tmp.p : I.Zs.p;
+  double* Y = single ? I.Y1.p : I.Ys.p;
+  const int Npad = single ? 1 : I.Npad2;
+  PhaseTimer pt(P, single ? PH_COARSE_X : PH_FINE, s);
+  for (const auto& ph : I.phases2[colour]) {
+    if (ph.mode < 0)
+      HIPOK(launch_dd2_kup0(I.rows2.p + ph.off, ph.cnt, bc, Z, Y, I.d.nx, Npad, s));
+    else
+      HIPOK(launch_dd2_solve(ph.mode, I.units2.p + ph.off, ph.cnt, pool, bc, Z, Y, I.d.nx, Npad,
+                             single, s));
+  }
+  return PR_OK;
+}
+
+// One FIE step of the single state in tmp (source at table entry gidx).
+pr_status dd2_step_single(pr_problem_s* P, int i, bool coarse, long gidx, hipStream_t s) {
+  Instance& I = *P->inst[i];
+  if (I.h.nforce) {
+    const long stride = coarse ? (long)I.d.n_slices * I.d.coarse_steps
+                               : (long)I.d.n_slices * I.d.fine_steps;
+    HIPOK(launch_force_state(P->d_inst + i, I.h, I.tmp.p, coarse ? I.fgc.p : I.fgf.p, gidx, stride,
+                             s));
+  }
+  for (int k = 0; k < I.n_colors; k++) {
+    pr_status st = dd2_substep(P, I, coarse, true, k, s);
+    if (st != PR_OK) return st;
+  }
+  return PR_OK;
+}
+
+// Fine propagation of every slice of a 2D DD instance: slice-minor workspace,
+// fine steps with the source on the first substep, back to slices.
+pr_status dd2_fine(pr_problem_s* P, Instance& I, const double* U, double* out, hipStream_t s) {
+  const long npts = I.npts;
+  const int N = I.d.n_slices, Np = I.Npad2;
+  {
+    PhaseTimer pt(P, PH_TRANSPOSE, s);
+    HIPOK(launch_dd2_to_sm(U, I.Zs.p, npts, N, Np, s));
+  }
+  for (int t = 0; t < I.d.fine_steps; t++) {
+    if (I.h.nforce) {
+      PhaseTimer pt(P, PH_FINE, s);
+      HIPOK(launch_dd2_force_sm(I.fS.p, I.fgf.p, (long)N * I.d.fine_steps, I.d.fine_steps, t,
+                                I.Zs.p, npts, N, Np, s));
+    }
+    for (int k = 0; k < I.n_colors; k++) {
+      pr_status st = dd2_substep(P, I, false, false, k, s);
+      if (st != PR_OK) return st;
+    }
+  }
+  PhaseTimer pt(P, PH_TRANSPOSE, s);
+  HIPOK(launch_dd2_from_sm(I.Zs.p, out, npts, N, Np, s));
+  return PR_OK;
+}
+
 // Work list of one direction for the instances in `members` (all-slices
 // variant): items (inst, b, group), ordered so that line groups whose values
 // share the previous sweep's chunk carries run on the same XCD (workgroups are
@@ -728,6 +1089,11 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
     const double* U = in_base + (in_states_layout ? I.off_states : I.off_slices);
+    if (I.dd2) {
+      pr_status st = dd2_fine(P, I, U, out_base + I.off_slices, s);
+      if (st != PR_OK) return st;
+      continue;
+    }
     PhaseTimer pt(P, PH_TRANSPOSE, s);
     HIPOK(launch_to_interleaved(P->d_inst + i, I.h, U, s));
   }
@@ -758,7 +1124,7 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   }
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
-    if (!I.dd) continue;
+    if (!I.dd || I.dd2) continue;
     for (int t = 0; t < I.d.fine_steps; t++) {
       if (I.h.nforce) {
         PhaseTimer pt(P, PH_FINE, s);
@@ -770,6 +1136,7 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   }
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
+    if (I.dd2) continue;
     PhaseTimer pt(P, PH_TRANSPOSE, s);
     if (I.dd)
       HIPOK(launch_dd_from_interleaved(I.d_dd, I.hdd, I.ffine.view(), out_base + I.off_slices, s));
@@ -787,6 +1154,11 @@ pr_status coarse_apply_dd(pr_problem_s* P, int i, int n, const double* src, int 
   HIPOK(launch_copy(src, I.tmp.p, I.npts, s));
   const int cs = I.d.coarse_steps;
   for (int c = 0; c < cs; c++) {
+    if (I.dd2) {
+      pr_status st = dd2_step_single(P, i, true, (long)n * cs + c, s);
+      if (st != PR_OK) return st;
+      continue;
+    }
     if (I.h.nforce)
       HIPOK(launch_force_state(P->d_inst + i, I.h, I.tmp.p, I.fgc.p, (long)n * cs + c,
                                (long)I.d.n_slices * cs, s));
@@ -1073,7 +1445,11 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
     I->off_u0 = ou; I->off_slices = osl; I->off_states = ost;
     ou += npts; osl += npts * descs[i].n_slices; ost += npts * (descs[i].n_slices + 1);
     pr_status st;
-    if (descs[i].split == PR_SPLIT_DD) {
+    if (descs[i].split == PR_SPLIT_DD && descs[i].dim == 2) {
+      st = setup_dd2_instance(*I, descs[i].rho, s);
+      if (st != PR_OK) return st;
+      st = factorize_dd2_instance(*I, descs[i].coef_x, descs[i].coef_y, s);
+    } else if (descs[i].split == PR_SPLIT_DD) {
       st = setup_dd_instance(P.get(), *I, descs[i].rho, s);
       if (st != PR_OK) return st;
       st = factorize_dd_instance(*I, descs[i].coef_x, s);
@@ -1173,6 +1549,7 @@ pr_status pr_set_coefficients(pr_problem p, int instance, const double* coef_x,
     delete p->adjT;
     p->adjT = nullptr;
   }
+  if (I.dd2) return factorize_dd2_instance(I, coef_x, coef_y, as_stream(hip_stream));
   if (I.dd) return factorize_dd_instance(I, coef_x, as_stream(hip_stream));
   return factorize_instance(p, I, coef_x, coef_y, as_stream(hip_stream));
 }
@@ -1369,6 +1746,11 @@ pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hi
       for (int k = 0; k < I.d.n_slices; k++) {
         HIPOK(launch_copy(U + I.off_states + (size_t)k * I.npts, I.tmp.p, I.npts, s));
         for (int t = 0; t < I.d.fine_steps; t++) {
+          if (I.dd2) {
+            pr_status st = dd2_step_single(p, i, false, (long)k * I.d.fine_steps + t, s);
+            if (st != PR_OK) return st;
+            continue;
+          }
           if (I.h.nforce)
             HIPOK(launch_force_state(dI, I.h, I.tmp.p, I.fgf.p, (long)k * I.d.fine_steps + t,
                                      (long)I.d.n_slices * I.d.fine_steps, s));

@@ -216,6 +216,105 @@ int update_blocks(size_t n);
 hipError_t launch_update(const double* g, const double* F, double* G_old, double* U_next,
                          size_t n, int mode, unsigned long long* partial, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Domain-decomposition splitting in 2D with vertical strips (section 2.1, the
+// subdomains of Fig. fig:domaindecomposition). The partition of unity depends
+// on x only and is sampled on the half grid of x (x-faces and node columns).
+// The substep of colour k solves (I - tau A_k) on each strip of colour k (a
+// maximal run of columns where rho_k is nonzero on the node or an x-face) and
+// leaves every other column unchanged. A strip of w columns is a 5-point
+// system, block tridiagonal in y with w x w blocks: D_r (tridiagonal in x) on
+// the diagonal and the diagonal y couplings b_r (to row r-1) and c_r (to row
+// r+1) beside it. It is solved exactly by block cyclic reduction in y: at level
+// l the rows alive are r = 2^l (a+1) - 1; even a are eliminated, odd a kept,
+// neighbours at distance 2^l. Per eliminated row the solve forms y = D^-1 r;
+// per kept row r -= B y_- + C y_+; going back down, x = y - M2 x_- - M3 x_+
+// with M2 = D^-1 B, M3 = D^-1 C (at level 0, where B and C are diagonal, the
+// back substitution is x = y - D^-1 (b x_- + c x_+) and the kept-row update is
+// elementwise). All these w x w matrices are precomputed per tau ("factor
+// pool") in the operand layout of the FP64 MFMA (16x16x4): element (o, k) of a
+// matrix padded to W (a multiple of 16) sits at dd2_frag(W, o, k). The solve
+// streams each matrix once per substep for all slices, which sit contiguously
+// at every grid node ("slice-minor" layout Zs[node][b], b < Npad).
+constexpr int kDD2MaxW = 1024;  // widest padded strip
+
+__host__ __device__ inline long dd2_frag(int W, int o, int k) {
+  return ((long)(k >> 2) * (W >> 4) + (o >> 4)) * 64 + (k & 3) * 16 + (o & 15);
+}
+
+// One wave's share of a solve launch: rows [16 mb0, 16 (mb0 + nmb)) of the
+// output of block row `row` of the strip at columns [col0, col0 + w).
+struct DD2Unit {
+  int col0, w, W, row;
+  int mb0, nmb, rowm, rowp;  // neighbour block rows (-1: none)
+  long A0, A1, A2;           // matrix offsets in the factor pool (per mode)
+  long bc;                   // offset of the row's coupling vectors b, c
+};
+
+// Kept row of level 0 (elementwise update r -= b y_- + c y_+).
+struct DD2Row {
+  int col0, w, W, row, rowm, rowp;
+  long bc;  // b_row at bc, c_row at bc + W
+};
+
+// Strip geometry and coefficients for the set-up kernels.
+struct DD2Geo {
+  const double* ax;   // x-faces [ny][nx+1]
+  const double* ay;   // y-faces [ny+1][nx]
+  const double* rho;  // this colour's half-grid weights [2nx+1]
+  int nx, ny;
+  int col0, w, W, pad;
+  double tx, ty;      // tau / h_x^2, tau / h_y^2
+  double tc;          // tau * c
+};
+
+// Set-up jobs: C = base + sgn * A B over W x W blocks (base NULL: 0), and
+// dense-to-pool copies.
+struct DD2Gemm {
+  const double* A; const double* B; const double* base; double* C;
+  int lda, ldb, ldbase, ldc;
+  double sgn;
+};
+struct DD2Copy {
+  const double* src; double* dst;
+  int ld, pad;
+};
+
+enum { DD2_APPLY = 0, DD2_KUP = 1, DD2_BACK = 2, DD2_BACK0 = 3 };
+
+// ---- launchers (pr_kernels_dd2.hip) ----
+// Coupling vectors of every block row: bc[r][0][o] = b_r, bc[r][1][o] = c_r
+// (zero past w, b_0 = c_{ny-1} = 0).
+hipError_t launch_dd2_bc(const DD2Geo& g, double* bc, hipStream_t s);
+// [D_r | I] for the level-0 eliminated rows r = 2m, m < n (row stride 2W).
+hipError_t launch_dd2_build0(const DD2Geo& g, int n, double* aug, long mstride, hipStream_t s);
+// Gauss-Jordan on n augmented matrices [D | R] (W rows, LD columns): D -> I, R -> D^-1 R.
+hipError_t launch_dd2_gj(double* aug, long mstride, int n, int W, int LD, hipStream_t s);
+// Level-1 blocks of the level-0 kept rows r = 2a + 1 (a < ny / 2) from the
+// level-0 inverses (columns [W, 2W) of aug0): D, B, C with leading dimension W.
+hipError_t launch_dd2_scale0(const DD2Geo& g, const double* bc, const double* aug0, long mstride,
+                             double* Dn, double* Bn, double* Cn, hipStream_t s);
+// [D_a | I | B_a | C_a] (row stride 4W) for the eliminated rows a = 2e, e < nE.
+hipError_t launch_dd2_aug(const double* D, const double* B, const double* C, int nE, int W,
+                          double* aug, hipStream_t s);
+hipError_t launch_dd2_gemm(const DD2Gemm* jobs, int n, int W, hipStream_t s);
+hipError_t launch_dd2_store(const DD2Copy* jobs, int n, int W, hipStream_t s);
+// One solve phase over a unit list (mode DD2_*), all slice columns.
+// single: one state in natural layout (Npad = 1).
+hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const double* pool,
+                            const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
+                            hipStream_t s);
+hipError_t launch_dd2_kup0(const DD2Row* rows, int n_rows, const double* bc, double* Z,
+                           const double* Y, int nx, int Npad, hipStream_t s);
+// Natural [N][npts] <-> slice-minor [npts][Npad] (padding columns written as 0).
+hipError_t launch_dd2_to_sm(const double* U, double* Zs, long npts, int N, int Npad,
+                            hipStream_t s);
+hipError_t launch_dd2_from_sm(const double* Zs, double* U, long npts, int N, int Npad,
+                              hipStream_t s);
+// Zs[p][b] += sum_m gtab[m * gstride + b * steps + t] S_m[p] for b < N.
+hipError_t launch_dd2_force_sm(const double* fS, const double* gtab, long gstride, int steps,
+                               int t, double* Zs, long npts, int N, int Npad, hipStream_t s);
+
 // ---- adjoint (pr_kernels_adj.hip) ----
 hipError_t launch_face_grad_x(const double* nu, const double* W, int nx, int ny, double coef,
                               double* gax, hipStream_t s);

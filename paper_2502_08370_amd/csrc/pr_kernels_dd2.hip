@@ -1,0 +1,524 @@
+// HIP kernels of the 2D domain-decomposition split into vertical strips
+// (arXiv 2502.08370, section 2.1: L_k u = div(rho_k D grad u) - rho_k c u with a
+// partition of unity rho_k of overlapping strips; eq. FIE_method for the
+// substeps). Each strip system is solved exactly by block cyclic reduction in
+// y; the set-up kernels precompute every block the solve needs, the solve
+// kernels stream those blocks through the FP64 matrix cores with all slices as
+// the columns of the product.
+#include "pr_internal.h"
+
+#include <algorithm>
+
+namespace prk {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ set-up ---
+
+// Flux weights of node (i, r) for colour weights rho (half grid of x): west and
+// east x-faces (rho on the face), south and north y-faces (rho at the node).
+struct Flux {
+  double w, e, s, n, react;
+};
+
+__device__ inline Flux node_flux(const DD2Geo& g, int i, int r) {
+  Flux f;
+  const double rn = g.rho[2 * i + 1];
+  f.w = g.tx * g.rho[2 * i] * g.ax[(long)r * (g.nx + 1) + i];
+  f.e = g.tx * g.rho[2 * i + 2] * g.ax[(long)r * (g.nx + 1) + i + 1];
+  f.s = g.ty * rn * g.ay[(long)r * g.nx + i];
+  f.n = g.ty * rn * g.ay[(long)(r + 1) * g.nx + i];
+  f.react = g.tc * rn;
+  return f;
+}
+
+// Entry (o, k) of the level-0 diagonal block D_r = I - tau A restricted to block
+// row r (tridiagonal in x); identity on the padding o >= w.
+__device__ inline double d0_entry(const DD2Geo& g, int r, int o, int k) {
+  if (o >= g.w || k >= g.w) return o == k ? 1.0 : 0.0;
+  const int d = k - o;
+  if (d < -1 || d > 1) return 0.0;
+  const Flux f = node_flux(g, g.col0 + o, r);
+  if (d == 0) return 1.0 + f.w + f.e + f.s + f.n + f.react;
+  return d < 0 ? -f.w : -f.e;
+}
+
+__global__ void k_dd2_bc(DD2Geo g, double* __restrict__ bc) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= (long)g.ny * g.W) return;
+  const int r = (int)(t / g.W), o = (int)(t % g.W);
+  double b = 0.0, c = 0.0;
+  if (o < g.w) {
+    const Flux f = node_flux(g, g.col0 + o, r);
+    if (r > 0) b = -f.s;
+    if (r + 1 < g.ny) c = -f.n;
+  }
+  bc[((long)r * 2 + 0) * g.W + o] = b;
+  bc[((long)r * 2 + 1) * g.W + o] = c;
+}
+
+__global__ void k_dd2_build0(DD2Geo g, double* __restrict__ aug, long mstride) {
+  const int m = blockIdx.y, r = 2 * m;
+  const int LD = 2 * g.W;
+  double* A = aug + m * mstride;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)g.W * LD;
+       t += (long)gridDim.x * blockDim.x) {
+    const int o = (int)(t / LD), col = (int)(t % LD);
+    A[t] = col < g.W ? d0_entry(g, r, o, col) : (col - g.W == o ? 1.0 : 0.0);
+  }
+}
+
+// Gauss-Jordan elimination without pivoting (the blocks are strictly
+// diagonally dominant M-matrices at every level of the reduction), one
+// workgroup per matrix. Pivot p: the pivot row is scaled into LDS, then every
+// other row subtracts its multiple of it from column p+1 on (columns < p of
+// the left part are already unit columns; column p is not read again).
+__global__ __launch_bounds__(256) void k_dd2_gj(double* __restrict__ aug, long mstride, int W,
+                                                int LD) {
+  __shared__ double rp[4 * kDD2MaxW];
+  __shared__ double f[kDD2MaxW];
+  double* A = aug + blockIdx.x * mstride;
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  for (int p = 0; p < W; p++) {
+    const double inv = 1.0 / A[(long)p * LD + p];
+    for (int q = tid; q < W; q += blockDim.x) f[q] = A[(long)q * LD + p];
+    for (int c = p + 1 + tid; c < LD; c += blockDim.x) rp[c] = A[(long)p * LD + c] * inv;
+    __syncthreads();
+    for (int q = wave; q < W; q += blockDim.x / kWave) {
+      double* row = A + (long)q * LD;
+      if (q == p) {
+        for (int c = p + 1 + lane; c < LD; c += kWave) row[c] = rp[c];
+      } else {
+        const double fq = f[q];
+        for (int c = p + 1 + lane; c < LD; c += kWave) row[c] = row[c] - fq * rp[c];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Level-0 kept row r = 2a + 1 reduced onto level 1:
+//   D' = D_r - b_r Dinv_{r-1} c_{r-1} - c_r Dinv_{r+1} b_{r+1}
+//   B' = -b_r Dinv_{r-1} b_{r-1},  C' = -c_r Dinv_{r+1} c_{r+1}
+// (diagonal couplings as row / column scalings of the dense inverses).
+__global__ void k_dd2_scale0(DD2Geo g, const double* __restrict__ bc,
+                             const double* __restrict__ aug0, long mstride, double* __restrict__ Dn,
+                             double* __restrict__ Bn, double* __restrict__ Cn) {
+  const int a = blockIdx.y, r = 2 * a + 1, W = g.W;
+  const bool up = r + 1 < g.ny;
+  const double* Im = aug0 + (long)(r / 2) * mstride + W;   // Dinv of row r - 1 (ld 2W)
+  const double* Ip = aug0 + (long)((r + 1) / 2) * mstride + W;
+  const double* b_r = bc + ((long)r * 2 + 0) * W;
+  const double* c_r = bc + ((long)r * 2 + 1) * W;
+  const double* b_m = bc + ((long)(r - 1) * 2 + 0) * W;
+  const double* c_m = bc + ((long)(r - 1) * 2 + 1) * W;
+  const double* b_p = up ? bc + ((long)(r + 1) * 2 + 0) * W : nullptr;
+  const double* c_p = up ? bc + ((long)(r + 1) * 2 + 1) * W : nullptr;
+  const long base = (long)a * W * W;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)W * W;
+       t += (long)gridDim.x * blockDim.x) {
+    const int o = (int)(t / W), k = (int)(t % W);
+    const double im = Im[(long)o * 2 * W + k];
+    double d = d0_entry(g, r, o, k) - b_r[o] * im * c_m[k];
+    double bb = -(b_r[o] * im * b_m[k]);
+    double cc = 0.0;
+    if (up) {
+      const double ip = Ip[(long)o * 2 * W + k];
+      d = d - c_r[o] * ip * b_p[k];
+      cc = -(c_r[o] * ip * c_p[k]);
+    }
+    Dn[base + t] = d;
+    Bn[base + t] = bb;
+    Cn[base + t] = cc;
+  }
+}
+
+__global__ void k_dd2_aug(const double* __restrict__ D, const double* __restrict__ B,
+                          const double* __restrict__ C, int W, double* __restrict__ aug) {
+  const int e = blockIdx.y, a = 2 * e;
+  const int LD = 4 * W;
+  const long src = (long)a * W * W;
+  double* A = aug + (long)e * W * LD;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)W * LD;
+       t += (long)gridDim.x * blockDim.x) {
+    const int o = (int)(t / LD), col = (int)(t % LD);
+    const int part = col / W, k = col % W;
+    double v;
+    if (part == 0)
+      v = D[src + (long)o * W + k];
+    else if (part == 1)
+      v = (o == k) ? 1.0 : 0.0;
+    else if (part == 2)
+      v = B[src + (long)o * W + k];
+    else
+      v = C[src + (long)o * W + k];
+    A[t] = v;
+  }
+}
+
+// C = base + sgn * A B over W x W blocks: 64 x 64 output tile per workgroup,
+// 4 x 4 per thread (rows ty + 16 i, columns tx + 16 j), k in LDS panels of 16.
+__global__ __launch_bounds__(256) void k_dd2_gemm(const DD2Gemm* __restrict__ jobs, int W) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const DD2Gemm J = jobs[blockIdx.y];
+  const int tiles = (W + 63) / 64;
+  const int o0 = (blockIdx.x / tiles) * 64, c0 = (blockIdx.x % tiles) * 64;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < W; k0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int kk = e % 16, oo = e / 16;  // A tile: consecutive threads walk k
+      const int o = o0 + oo;
+      As[kk][oo] = o < W ? J.A[(long)o * J.lda + k0 + kk] : 0.0;
+      const int cc = e % 64, kb = e / 64;  // B tile: consecutive threads walk columns
+      const int c = c0 + cc;
+      Bs[kb][cc] = c < W ? J.B[(long)(k0 + kb) * J.ldb + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk++) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; j++) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; i++)
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int o = o0 + ty + 16 * i, c = c0 + tx + 16 * j;
+      if (o < W && c < W) {
+        const double b = J.base ? J.base[(long)o * J.ldbase + c] : 0.0;
+        J.C[(long)o * J.ldc + c] = b + J.sgn * acc[i][j];
+      }
+    }
+}
+
+__global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
+  const DD2Copy J = jobs[blockIdx.y];
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)W * W;
+       t += (long)gridDim.x * blockDim.x) {
+    const int o = (int)(t / W), k = (int)(t % W);
+    J.dst[dd2_frag(W, o, k)] = J.src[(long)o * J.ld + k];
+  }
+}
+
+// ------------------------------------------------------------------- solve ---
+
+// One wave per unit. The unit's output is rows [16 mb0, 16 (mb0 + nmb)) of
+// block row U.row against TN tiles of 16 slice columns starting at b0:
+//   APPLY: Y[row] = A0 Z[row]
+//   KUP:   Z[row] = Z[row] - A1 Y[rowm] - A2 Y[rowp]
+//   BACK:  Z[row] = Y[row] - A1 Z[rowm] - A2 Z[rowp]
+//   BACK0: Z[row] = Y[row] - A0 (b_row Z[rowm] + c_row Z[rowp])
+// v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16] and X[l / 16][l % 16]
+// and holds D[4 v + l / 16][l % 16] in accumulator register v. Pool matrices
+// are stored in exactly that A order, so each (k-block, row tile) fragment is
+// one contiguous 512-byte load. Inputs past the strip width are read at the
+// last column (finite values) and meet zero matrix entries. Single-state solves
+// (Npad = 1) feed zeros into the 15 unused columns.
+template <int MODE, int TN, bool SINGLE>
+__global__ __launch_bounds__(256) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
+                                                   const double* __restrict__ pool,
+                                                   const double* __restrict__ bcp,
+                                                   double* __restrict__ Z, double* __restrict__ Y,
+                                                   int nx, int Npad, int b0) {
+  const int lane = threadIdx.x % kWave;
+  const int u = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (u >= n_units) return;
+  const DD2Unit U = units[u];
+  const int W = U.W, w = U.w, mbW = W >> 4, nkb = W >> 2;
+  const int kq = lane >> 4, cl = lane & 15;
+  d4 acc[4][TN];
+#pragma unroll
+  for (int r = 0; r < 4; r++)
+#pragma unroll
+    for (int nt = 0; nt < TN; nt++) acc[r][nt] = d4{0.0, 0.0, 0.0, 0.0};
+  const long col_off = SINGLE ? 0 : (long)b0 + cl;
+  constexpr int n_terms = (MODE == DD2_KUP || MODE == DD2_BACK) ? 2 : 1;
+  for (int term = 0; term < n_terms; term++) {
+    long aoff;
+    int rx;
+    if (MODE == DD2_APPLY) {
+      aoff = U.A0; rx = U.row;
+    } else if (MODE == DD2_BACK0) {
+      aoff = U.A0; rx = U.row;
+    } else {
+      aoff = term == 0 ? U.A1 : U.A2;
+      rx = term == 0 ? U.rowm : U.rowp;
+    }
+    if (rx < 0) continue;
+    const double* Xb = (MODE == DD2_KUP) ? Y : Z;
+    const double* A = pool + aoff + (long)U.mb0 * 64 + lane;
+    const double* X = Xb + ((long)rx * nx + U.col0) * Npad + col_off;
+    // BACK0: X = b_row * Z[rowm] + c_row * Z[rowp]
+    const double* Xm = (MODE == DD2_BACK0 && U.rowm >= 0)
+                           ? Z + ((long)U.rowm * nx + U.col0) * Npad + col_off : nullptr;
+    const double* Xp = (MODE == DD2_BACK0 && U.rowp >= 0)
+                           ? Z + ((long)U.rowp * nx + U.col0) * Npad + col_off : nullptr;
+    const double* vb = bcp + U.bc;
+    const double* vc = bcp + U.bc + W;
+    for (int kb = 0; kb < nkb; kb++) {
+      const int k = min(kb * 4 + kq, w - 1);
+      double xv[TN];
+#pragma unroll
+      for (int nt = 0; nt < TN; nt++) {
+        const long xo = SINGLE ? (long)k : (long)k * Npad + nt * 16;
+        double v;
+        if (MODE == DD2_BACK0) {
+          const double zm = Xm ? Xm[xo] : 0.0;
+          const double zp = Xp ? Xp[xo] : 0.0;
+          v = vb[k] * zm + vc[k] * zp;
+        } else {
+          v = X[xo];
+        }
+        xv[nt] = (SINGLE && cl != 0) ? 0.0 : v;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        if (r < U.nmb) {
+          const double a = A[((long)kb * mbW + r) * 64];
+#pragma unroll
+          for (int nt = 0; nt < TN; nt++)
+            acc[r][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xv[nt], acc[r][nt], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    if (r >= U.nmb) continue;
+#pragma unroll
+    for (int nt = 0; nt < TN; nt++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int o = (U.mb0 + r) * 16 + 4 * v + kq;
+        if (o >= w || (SINGLE && cl != 0)) continue;
+        const long idx = ((long)U.row * nx + U.col0 + o) * Npad + (SINGLE ? 0 : b0 + nt * 16 + cl);
+        const double val = acc[r][nt][v];
+        if (MODE == DD2_APPLY)
+          Y[idx] = val;
+        else if (MODE == DD2_KUP)
+          Z[idx] = Z[idx] - val;
+        else
+          Z[idx] = Y[idx] - val;
+      }
+  }
+}
+
+// Level-0 kept rows: Z[row] -= b_row Y[rowm] + c_row Y[rowp], one workgroup per row.
+__global__ void k_dd2_kup0(const DD2Row* __restrict__ rows, const double* __restrict__ bcp,
+                           double* __restrict__ Z, const double* __restrict__ Y, int nx,
+                           int Npad) {
+  const DD2Row R = rows[blockIdx.x];
+  const double* vb = bcp + R.bc;
+  const double* vc = bcp + R.bc + R.W;
+  const long n = (long)R.w * Npad;
+  const long base = ((long)R.row * nx + R.col0) * Npad;
+  const long bm = ((long)R.rowm * nx + R.col0) * Npad;
+  const long bp = R.rowp >= 0 ? ((long)R.rowp * nx + R.col0) * Npad : -1;
+  for (long t = threadIdx.x; t < n; t += blockDim.x) {
+    const int o = (int)(t / Npad);
+    double v = Z[base + t] - vb[o] * Y[bm + t];
+    if (bp >= 0) v = v - vc[o] * Y[bp + t];
+    Z[base + t] = v;
+  }
+}
+
+// [N][npts] -> [npts][Npad] through a 64 x 64 LDS tile (rows: slices, columns: points).
+__global__ void k_dd2_to_sm(const double* __restrict__ U, double* __restrict__ Zs, long npts,
+                            int N, int Npad) {
+  __shared__ double tile[64][65];
+  const long p0 = blockIdx.x * 64L;
+  const int b0 = blockIdx.y * 64;
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+  for (int bb = ty; bb < 64; bb += blockDim.x / 64) {
+    const int b = b0 + bb;
+    const long p = p0 + tx;
+    tile[bb][tx] = (b < N && p < npts) ? U[(long)b * npts + p] : 0.0;
+  }
+  __syncthreads();
+  for (int pp = ty; pp < 64; pp += blockDim.x / 64) {
+    const long p = p0 + pp;
+    const int b = b0 + tx;
+    if (p < npts && b < Npad) Zs[p * Npad + b] = tile[tx][pp];
+  }
+}
+
+__global__ void k_dd2_from_sm(const double* __restrict__ Zs, double* __restrict__ U, long npts,
+                              int N, int Npad) {
+  __shared__ double tile[64][65];
+  const long p0 = blockIdx.x * 64L;
+  const int b0 = blockIdx.y * 64;
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+  for (int pp = ty; pp < 64; pp += blockDim.x / 64) {
+    const long p = p0 + pp;
+    const int b = b0 + tx;
+    tile[pp][tx] = (p < npts && b < Npad) ? Zs[p * Npad + b] : 0.0;
+  }
+  __syncthreads();
+  for (int bb = ty; bb < 64; bb += blockDim.x / 64) {
+    const int b = b0 + bb;
+    const long p = p0 + tx;
+    if (b < N && p < npts) U[(long)b * npts + p] = tile[tx][bb];
+  }
+}
+
+__global__ void k_dd2_force_sm(const double* __restrict__ fS, const double* __restrict__ gtab,
+                               long gstride, int steps, int t, double* __restrict__ Zs, long npts,
+                               int N, int Npad) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= npts * Npad) return;
+  const long p = e / Npad;
+  const int b = (int)(e % Npad);
+  if (b >= N) return;
+  double v = Zs[e];
+#pragma unroll
+  for (int m = 0; m < kMaxForcing; m++)
+    v = fma(gtab[m * gstride + (long)b * steps + t], fS[m * npts + p], v);
+  Zs[e] = v;
+}
+
+unsigned grid_for(long n, int per_block, unsigned cap = 65535u) {
+  long g = (n + per_block - 1) / per_block;
+  return (unsigned)std::max<long>(1, std::min<long>(g, cap));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers ---
+
+hipError_t launch_dd2_bc(const DD2Geo& g, double* bc, hipStream_t s) {
+  hipLaunchKernelGGL(k_dd2_bc, dim3(grid_for((long)g.ny * g.W, 256, 1u << 30)), dim3(256), 0, s,
+                     g, bc);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_build0(const DD2Geo& g, int n, double* aug, long mstride, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dd2_build0, dim3(grid_for((long)g.W * 2 * g.W, 256, 256), n), dim3(256), 0,
+                     s, g, aug, mstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_gj(double* aug, long mstride, int n, int W, int LD, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (W > kDD2MaxW || LD > 4 * kDD2MaxW) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dd2_gj, dim3(n), dim3(256), 0, s, aug, mstride, W, LD);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_scale0(const DD2Geo& g, const double* bc, const double* aug0, long mstride,
+                             double* Dn, double* Bn, double* Cn, hipStream_t s) {
+  const int n = g.ny / 2;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dd2_scale0, dim3(grid_for((long)g.W * g.W, 256, 256), n), dim3(256), 0, s,
+                     g, bc, aug0, mstride, Dn, Bn, Cn);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_aug(const double* D, const double* B, const double* C, int nE, int W,
+                          double* aug, hipStream_t s) {
+  if (nE <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dd2_aug, dim3(grid_for((long)W * 4 * W, 256, 256), nE), dim3(256), 0, s,
+                     D, B, C, W, aug);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_gemm(const DD2Gemm* jobs, int n, int W, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int tiles = (W + 63) / 64;
+  hipLaunchKernelGGL(k_dd2_gemm, dim3(tiles * tiles, n), dim3(256), 0, s, jobs, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_store(const DD2Copy* jobs, int n, int W, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dd2_store, dim3(grid_for((long)W * W, 256, 256), n), dim3(256), 0, s, jobs,
+                     W);
+  return hipGetLastError();
+}
+
+namespace {
+template <int MODE, bool SINGLE>
+hipError_t solve_tn(int tn, const DD2Unit* units, int n_units, const double* pool,
+                    const double* bc, double* Z, double* Y, int nx, int Npad, int b0,
+                    hipStream_t s) {
+  const dim3 grid((n_units + 3) / 4), block(256);
+  switch (tn) {
+    case 1: hipLaunchKernelGGL((k_dd2_solve<MODE, 1, SINGLE>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
+    case 2: hipLaunchKernelGGL((k_dd2_solve<MODE, 2, SINGLE>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
+    case 3: hipLaunchKernelGGL((k_dd2_solve<MODE, 3, SINGLE>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
+    default: hipLaunchKernelGGL((k_dd2_solve<MODE, 4, SINGLE>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
+  }
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t solve_mode(const DD2Unit* units, int n_units, const double* pool, const double* bc,
+                      double* Z, double* Y, int nx, int Npad, bool single, hipStream_t s) {
+  if (single) return solve_tn<MODE, true>(1, units, n_units, pool, bc, Z, Y, nx, 1, 0, s);
+  for (int b0 = 0; b0 < Npad; b0 += 64) {
+    const int tn = std::min(4, (Npad - b0) / 16);
+    hipError_t e = solve_tn<MODE, false>(tn, units, n_units, pool, bc, Z, Y, nx, Npad, b0, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const double* pool,
+                            const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
+                            hipStream_t s) {
+  if (n_units <= 0) return hipSuccess;
+  if (!single && Npad % 16 != 0) return hipErrorInvalidValue;
+  switch (mode) {
+    case DD2_APPLY: return solve_mode<DD2_APPLY>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+    case DD2_KUP: return solve_mode<DD2_KUP>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+    case DD2_BACK: return solve_mode<DD2_BACK>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+    case DD2_BACK0: return solve_mode<DD2_BACK0>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_dd2_kup0(const DD2Row* rows, int n_rows, const double* bc, double* Z,
+                           const double* Y, int nx, int Npad, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dd2_kup0, dim3(n_rows), dim3(256), 0, s, rows, bc, Z, Y, nx, Npad);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_to_sm(const double* U, double* Zs, long npts, int N, int Npad,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_dd2_to_sm, dim3((unsigned)((npts + 63) / 64), (Npad + 63) / 64), dim3(256),
+                     0, s, U, Zs, npts, N, Npad);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_from_sm(const double* Zs, double* U, long npts, int N, int Npad,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_dd2_from_sm, dim3((unsigned)((npts + 63) / 64), (Npad + 63) / 64),
+                     dim3(256), 0, s, Zs, U, npts, N, Npad);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_force_sm(const double* fS, const double* gtab, long gstride, int steps,
+                               int t, double* Zs, long npts, int N, int Npad, hipStream_t s) {
+  const long n = npts * Npad;
+  hipLaunchKernelGGL(k_dd2_force_sm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fS, gtab,
+                     gstride, steps, t, Zs, npts, N, Npad);
+  return hipGetLastError();
+}
+
+}  // namespace prk

@@ -1,0 +1,211 @@
+"""GPU parity of the 2D domain-decomposition split into vertical strips
+(section 2.1, Fig. fig:domaindecomposition; substeps of eq. FIE_method solved
+by block cyclic reduction over each strip) against the oracle's banded
+elimination: the fine map over all slices, the sequential fine solve, the
+coarse sweep, parareal, source terms, handles mixing split kinds, and
+coefficient updates. Relative infinity-norm error <= 1e-12. At the paper's
+size (h = 1e-3, q = 2, beta = 1/16, N = 20) the fine map is checked by the
+residual of the FIE step, which holds at any size."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import TOL, gpu_problem, oracle_problem, relerr, slice_inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda").reshape(-1)
+
+
+def fine_parity(w, seed=0):
+    P, O = gpu_problem(w), oracle_problem(w)
+    Uin = slice_inputs(w, seed=seed)
+    F = P.new_slices()
+    P.fine_propagate(dev(Uin), F)
+    torch.cuda.synchronize()
+    ref = O.fine_batch(Uin)
+    return relerr(F.cpu().numpy().reshape(ref.shape), ref)
+
+
+# (nx, ny, q, beta, N, s, colours, c): strips of 1..7 row tiles, 1..7 reduction
+# levels, slice counts that are not multiples of 16 and one above 64
+CASES = [
+    (40, 33, 2, 0.1, 5, 2, 2, 0.0),
+    (97, 61, 2, 0.08, 20, 2, 2, 0.0),
+    (64, 1, 2, 0.1, 3, 3, 2, 0.0),
+    (30, 2, 1, 0.2, 17, 2, 2, 1.0),
+    (120, 17, 3, 0.04, 70, 1, 2, 0.0),
+    (75, 40, 2, 0.05, 9, 2, 3, 2.5),
+    (9, 25, 1, 0.2, 4, 3, 2, 0.0),
+]
+
+
+@pytest.mark.parametrize("nx,ny,q,beta,N,s,M,c", CASES)
+def test_dd2_fine_propagate(nx, ny, q, beta, N, s, M, c):
+    w = W.small_dd2(nx, ny, q, beta, N, s, seed=nx + ny, n_colors=M, c=c)
+    assert fine_parity(w, seed=N) <= TOL
+
+
+def test_dd2_single_colour_full_width():
+    """One colour with rho = 1: a single strip spanning the grid (implicit Euler)."""
+    nx, ny = 130, 21
+    w = W.small_dd2(nx, ny, 1, 0.1, 4, 2, seed=4)
+    w.rho = np.ones((1, 2 * nx + 1))
+    assert fine_parity(w) <= TOL
+
+
+def test_dd2_constant_coefficient():
+    w = W.small_dd2(81, 47, 2, 1.0 / 16, 6, 2, seed=2, variable=False)
+    assert fine_parity(w) <= TOL
+
+
+@pytest.mark.parametrize("fine_only", [False, True])
+def test_dd2_sequential_and_parareal(fine_only):
+    w = W.small_dd2(50, 37, 2, 0.08, 6, 3, seed=11)
+    w.coarse_steps = 2
+    P, O = gpu_problem(w), oracle_problem(w)
+    Seq = P.new_states()
+    P.sequential_fine(dev(w.u0), Seq)
+    torch.cuda.synchronize()
+    ref = O.sequential_fine(w.u0)
+    assert relerr(Seq.cpu().numpy().reshape(ref.shape), ref) <= TOL
+    if fine_only:
+        return
+    U = P.new_states()
+    k, inc = P.parareal_iterate(dev(w.u0), U, k_max=3, tol=0.0)
+    torch.cuda.synchronize()
+    Uo, ko, hist = O.parareal(w.u0, 3)
+    assert k[0] == ko
+    assert relerr(U.cpu().numpy().reshape(Uo.shape), Uo) <= TOL
+    assert abs(inc[0] - hist[-1]) <= TOL * np.abs(Uo).max()
+
+
+def test_dd2_parareal_finite_termination():
+    w = W.small_dd2(33, 29, 2, 0.1, 5, 2, seed=12)
+    P = gpu_problem(w)
+    U, Seq = P.new_states(), P.new_states()
+    k, _ = P.parareal_iterate(dev(w.u0), U, k_max=w.n_slices, tol=0.0)
+    P.sequential_fine(dev(w.u0), Seq)
+    torch.cuda.synchronize()
+    assert k[0] == w.n_slices
+    seq = Seq.cpu().numpy()
+    assert np.abs(U.cpu().numpy() - seq).max() <= 1e-13 * np.abs(seq).max()
+
+
+def test_dd2_coarse_sweep():
+    w = W.small_dd2(45, 26, 2, 0.1, 5, 2, seed=13)
+    w.coarse_steps = 3
+    P, O = gpu_problem(w), oracle_problem(w)
+    N, nx, ny = w.n_slices, w.nx, w.ny
+    U0 = np.zeros((N + 1, ny, nx))
+    U0[0] = w.u0
+    G0 = np.zeros((N, ny, nx))
+    O.coarse_sweep(None, G0, U0)
+    U = dev(np.concatenate([w.u0[None], np.zeros((N, ny, nx))]))
+    G = P.new_slices()
+    P.coarse_sweep(None, G, U)
+    torch.cuda.synchronize()
+    assert relerr(U.cpu().numpy().reshape(U0.shape), U0) <= TOL
+    assert relerr(G.cpu().numpy().reshape(G0.shape), G0) <= TOL
+
+
+def test_dd2_with_source():
+    w = W.small_dd2(60, 31, 2, 0.08, 7, 3, seed=14)
+    w.coarse_steps = 2
+    rng = np.random.default_rng(3)
+    w.forcing = (rng.standard_normal((2, w.ny, w.nx)), rng.standard_normal((2, 7 * 3)),
+                 rng.standard_normal((2, 7 * 2)))
+    assert fine_parity(w) <= TOL
+    P, O = gpu_problem(w), oracle_problem(w)
+    U = P.new_states()
+    k, inc = P.parareal_iterate(dev(w.u0), U, k_max=2, tol=0.0)
+    torch.cuda.synchronize()
+    Uo, ko, _ = O.parareal(w.u0, 2)
+    assert relerr(U.cpu().numpy().reshape(Uo.shape), Uo) <= TOL
+
+
+def test_dd2_manufactured_matches_oracle():
+    w = W.dd2_manufactured(n=63, n_slices=8, fine_steps=8, q=2, beta=1.0 / 8)
+    P, O = gpu_problem(w), oracle_problem(w)
+    U = P.new_states()
+    k, inc = P.parareal_iterate(dev(w.u0), U, k_max=3, tol=0.0)
+    torch.cuda.synchronize()
+    Uo, ko, _ = O.parareal(w.u0, 3)
+    assert relerr(U.cpu().numpy().reshape(Uo.shape), Uo) <= TOL
+
+
+def test_dd2_mixed_handle():
+    ws = [W.small_dd2(40, 20, 2, 0.1, 4, 2, seed=1), W.small_dim2(37, 29, 6, 3, seed=2),
+          W.small_dd1(200, 4, 2, 8, 5, 3, seed=3), W.small_dd2(25, 50, 1, 0.15, 3, 3, seed=4)]
+    P = gpu_problem(ws)
+    u0 = P.pack_u0([w.u0 for w in ws])
+    U = P.new_states()
+    k, inc = P.parareal_iterate(u0, U, k_max=2, tol=0.0)
+    torch.cuda.synchronize()
+    for i, w in enumerate(ws):
+        Uo, ko, _ = oracle_problem(w).parareal(w.u0, 2)
+        assert k[i] == ko
+        assert relerr(P.view(U, i, "states").cpu().numpy(), Uo) <= TOL
+
+
+def test_dd2_set_coefficients():
+    w = W.small_dd2(44, 30, 2, 0.1, 4, 2, seed=5)
+    P = gpu_problem(w)
+    theta2 = 0.4 * W.smooth_field_2d(w.nx + 2, w.ny + 2, ell=0.2, K=6, seed=99)
+    P.set_coefficients(0, dev(theta2))
+    w.theta = theta2
+    O = oracle_problem(w)
+    Uin = slice_inputs(w, seed=1)
+    F = P.new_slices()
+    P.fine_propagate(dev(Uin), F)
+    torch.cuda.synchronize()
+    ref = O.fine_batch(Uin)
+    assert relerr(F.cpu().numpy().reshape(ref.shape), ref) <= TOL
+
+
+def test_dd2_rejects_bad_partition():
+    import paper_2502_08370_amd as pr
+    w = W.small_dd2(20, 10, 2, 0.1, 2, 2, seed=6)
+    rho = w.rho.copy()
+    rho[0, 5] += 0.25  # weights no longer sum to one at that sample
+    d = dict(dim=2, nx=20, ny=10, T=0.01, n_slices=2, fine_steps=2, split="dd", theta=w.theta,
+             rho=rho)
+    with pytest.raises(pr.PrError):
+        pr.Problem([d])
+
+
+def test_dd2_paper_size_residual():
+    """h = 1e-3 (999^2), q = 2, beta = 1/16, N = 20 slices, dt = 2.5e-3, one fine
+    step per slice on seeded slice states: w = S_1 S_0 u with S_k = (I - dt A_k)^-1,
+    so (I - dt A_0)(I - dt A_1) w = u, applied with the oracle's stencils."""
+    n, N = 999, 20
+    w = W.dd2_manufactured(n=n, n_slices=N, fine_steps=1)
+    w.T = N * 2.5e-3
+    w.forcing = None
+    P = gpu_problem(w)
+    O = oracle_problem(w)
+    rng = np.random.default_rng(7)
+    idx = [0, 7, 19]
+    Uin = np.zeros((N, n, n))
+    for b in idx:
+        Uin[b] = W.sine_modes_2d(n, n, seed=b) + 0.01 * rng.standard_normal((n, n))
+    F = P.new_slices()
+    P.fine_propagate(dev(Uin), F)
+    torch.cuda.synchronize()
+    Fo = F.cpu().numpy().reshape(N, n, n)
+    dt = w.T / N
+    for b in idx:
+        v = Fo[b]
+        t1 = v - dt * O.apply_Aj(1, v)
+        back = t1 - dt * O.apply_Aj(0, t1)
+        # forward error eps * |w| grows by at most |I - dt A_0| |I - dt A_1| ~ (1 + 8 dt/h^2)^2
+        bound = 1e-12 * (1 + 8 * dt * (n + 1) ** 2) ** 2 * np.abs(v).max()
+        assert np.abs(back - Uin[b]).max() <= bound
+        assert np.abs(back - Uin[b]).max() <= 1e-6 * np.abs(Uin[b]).max()
