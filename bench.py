@@ -57,6 +57,50 @@ def covered_nodes(w):
     return tot
 
 
+def dd2_strips(w):
+    """Strips (colour, first column, width) of the 2D strip decomposition: maximal runs of
+    columns where the colour's weight is nonzero on the node or an x-face."""
+    out = []
+    for k, r in enumerate(w.rho):
+        act = (r[0:-1:2] > 0) | (r[1::2] > 0) | (r[2::2] > 0)
+        i = 0
+        while i < w.nx:
+            if not act[i]:
+                i += 1
+                continue
+            j = i
+            while j < w.nx and act[j]:
+                j += 1
+            out.append((k, i, j - i))
+            i = j
+    return out
+
+
+def dd2_substep_bytes(w, N):
+    """Algorithmic bytes of one colour substep of the strip solver, averaged over the
+    colours: every w x w block the block cyclic reduction stores (padded to W, a
+    multiple of 16) read once, the level-0 inverses twice (forward and back), plus one
+    read and one write of every node of the colour's strips for each slice."""
+    ny = w.ny
+    tot = []
+    for k in range(len(w.rho)):
+        b = 0.0
+        for kk, i0, ws in dd2_strips(w):
+            if kk != k:
+                continue
+            Wp = (ws + 15) // 16 * 16
+            mats = 2 * ((ny + 1) // 2)
+            l = 1
+            while (ny >> l) > 0:
+                n = ny >> l
+                for a in range(n):
+                    mats += (1 + (a >= 1) + (a + 1 < n)) if a % 2 == 0 else (1 + (a + 1 < n))
+                l += 1
+            b += 8.0 * Wp * Wp * mats + 16.0 * ws * ny * N
+        tot.append(b)
+    return float(np.mean(tot))
+
+
 def measured_traffic(kernel_src, summary):
     """HBM bytes per launch from the committed byte-counter summary, or None when the
     kernel source has changed since the counters were taken (or no summary exists)."""
@@ -88,6 +132,26 @@ def cpu_baseline(w, budget_s):
     return {"value": pts / el / 1e9, "unit": "Gpts/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle FIE steps on one {shape} slice: {steps} fine steps "
                       f"({pts:.3g} point-updates) in {el:.2f} s",
+            "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+
+
+def cpu_baseline_dd2(w):
+    """Oracle on a bounded sample of the strip workload: one FIE step of a grid the size
+    of the workload's widest strip with a single colour (rho = 1), i.e. one strip solve
+    (banded elimination, factor and solve, as the oracle does every substep)."""
+    import oracle
+    ws = max(width for _, _, width in dd2_strips(w))
+    P = oracle.Problem(dim=2, nx=ws, ny=w.ny, T=w.T, n_slices=1, fine_steps=1, split="dd",
+                       ax=np.ones((w.ny, ws + 1)), ay=np.ones((w.ny + 1, ws)),
+                       rho=np.ones((1, 2 * ws + 1)))
+    u = np.ascontiguousarray(w.u0[:, :ws])
+    t0 = time.perf_counter()
+    P.fie_step(u, w.T / w.n_slices / w.fine_steps)
+    el = time.perf_counter() - t0
+    pts = ws * w.ny
+    return {"value": pts / el / 1e9, "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle solve of one {ws}x{w.ny} strip (the widest strip of the "
+                      f"workload, one colour substep of one component) in {el:.2f} s",
             "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
 
 
@@ -237,14 +301,17 @@ def bench_adjoint(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["varcoef2d", "dd1d", "batch", "manufactured", "adjoint"],
+    ap.add_argument("--workload", choices=["varcoef2d", "dd1d", "dd2d", "batch", "manufactured",
+                                           "adjoint"],
                     default="varcoef2d",
                     help="varcoef2d: 2D variable coefficient 1023^2, N=64, s=64 (default); "
                          "dd1d: 1D domain decomposition 2^20 nodes, 8 components, N=32, s=128; "
                          "batch: 256 uneven 2D instances, batched parareal vs a loop of "
                          "single-instance launches; manufactured: the paper's test problem "
                          "(h = 1e-3, DT = 0.05, dt = 2.5e-3, T = 1, source term), errors "
-                         "against the exact solution; adjoint: serial vs parallel-in-time "
+                         "against the exact solution; dd2d: the same problem split into two "
+                         "subdomains of q = 2 vertical strips with overlap 1/16 (the paper's 2D "
+                         "domain-decomposition runs); adjoint: serial vs parallel-in-time "
                          "adjoint on 511^2, N=32, s=32")
     ap.add_argument("--fine", choices=["fie", "dr"], default="fie",
                     help="fine propagator (eq. FIE_method or eq. DR_method)")
@@ -280,13 +347,16 @@ def main():
         w = W.config3()
     elif args.workload == "manufactured":
         w = W.manufactured2d(999, 20, 20)
+    elif args.workload == "dd2d":
+        w = W.dd2_manufactured(999, 20, 20, q=2, beta=1.0 / 16)
     else:
         w = W.config2(n=args.n, n_slices=args.slices, fine_steps=args.fine_steps)
     w.fine = args.fine
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(w, args.cpu_seconds)
+        cpu = (cpu_baseline_dd2(w) if (w.split == "dd" and w.dim == 2)
+               else cpu_baseline(w, args.cpu_seconds))
         log(f"  {cpu['sample']}: {cpu['value']:.4f} Gpts/s")
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -302,7 +372,11 @@ def main():
         inst["rho"] = w.rho
     if w.forcing is not None:
         inst["forcing"] = w.forcing
+    t_setup = time.perf_counter()
     prob = pr.Problem([inst])
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    log(f"problem set-up (factorisations) {t_setup:.3f} s")
     u0 = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
     U = prob.new_states()
     G = prob.new_slices()
@@ -338,7 +412,10 @@ def main():
     value = fine_pts / (ms_step * 1e-3) / 1e9
     sweep_ms, sweep_n = phases["fine_sweep"]
     sweep_avg_ms = sweep_ms / sweep_n
-    if w.split == "dd":
+    dd2 = w.split == "dd" and w.dim == 2
+    if dd2:
+        bytes_per_sweep = dd2_substep_bytes(w, N)
+    elif w.split == "dd":
         # one colour substep reads and writes each node of that colour's components once
         bytes_per_sweep = 16.0 * float(np.mean(covered_nodes(w))) * N
     else:
@@ -350,6 +427,9 @@ def main():
     if w.split != "dd" and (w.nx, w.n_slices, w.fine_steps) == (1023, 64, 64):
         tb = measured_traffic(os.path.join(csrc, "pr_kernels_dim.hip"),
                               os.path.join(ROOT, "profiles", "pmc_fine_sweep_varcoef2d_1023_N64_s64.json"))
+    elif dd2 and (w.nx, w.n_slices, w.fine_steps) == (999, 20, 20):
+        tb = measured_traffic(os.path.join(csrc, "pr_kernels_dd2.hip"),
+                              os.path.join(ROOT, "profiles", "pmc_dd2_substep_dd2d_999_M2_q2_N20_s20.json"))
     elif w.split == "dd" and (w.nx, w.n_slices, w.fine_steps) == (1 << 20, 32, 128):
         tb = measured_traffic(os.path.join(csrc, "pr_kernels_dd.hip"),
                               os.path.join(ROOT, "profiles", "pmc_dd_substep_dd1d_1048576_M2_N32_s128.json"))
@@ -366,12 +446,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": f"{w.nx}x{w.ny}" if w.dim == 2 else f"{w.nx}",
                    "slices": N, "fine_steps": s, "coarse_steps": 1,
-                   "split": "domain decomposition" if w.split == "dd" else "dimensional",
+                   "split": ("domain decomposition, vertical strips" if dd2 else
+                             "domain decomposition" if w.split == "dd" else "dimensional"),
                    "integrators": "FIE/" + w.fine.upper(),
                    "step": "one parareal iteration: F^s on all slices + serial coarse sweep "
                            "with correction and increment"},
         "roofline": {"bound": "hbm",
-                     "kernel": ("dd substep (k_dd_local + k_dd_runmaps + k_dd_runscan + "
+                     "kernel": ("dd2 substep (k_dd2_solve phases + k_dd2_kup0)" if dd2 else
+                                "dd substep (k_dd_local + k_dd_runmaps + k_dd_runscan + "
                                 "k_dd_segcarries)" if w.split == "dd" else "k_fine_sweep"),
                      "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -381,6 +463,7 @@ def main():
         "fine_propagator": {"gpts": round(fine_pts / (fine_ms * 1e-3) / 1e9, 3),
                             "ms": round(fine_ms, 4)},
         "coarse_sweep_ms": round(coarse_ms, 4),
+        "setup_s": round(t_setup, 3),
         "cpu_baseline": cpu,
     }
 

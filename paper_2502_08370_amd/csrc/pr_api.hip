@@ -136,6 +136,7 @@ struct Instance {
   struct Phase2 {
     int mode;  // DD2_* (units) or -1 (level-0 kept rows)
     int off, cnt;
+    bool ksplit;  // few units: split each unit's k-blocks over a workgroup
   };
   std::vector<std::vector<Phase2>> phases2;  // per colour, in launch order
   DArr<DD2Unit> units2;
@@ -716,6 +717,9 @@ long dd2_slots(Instance::Strip2& S, int ny, long next) {
   return next;
 }
 
+// Launches with fewer units than this split each unit over a workgroup.
+constexpr int kDD2SplitUnits = 2048;
+
 // Launch schedule of one colour: forward levels (eliminated rows y = D^-1 r,
 // then kept rows r -= B y_- + C y_+), then back substitution from the top
 // level down. Each output row block is split into units of nmb row tiles;
@@ -736,7 +740,8 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
         t.nmb = std::min(nmb, t.W / 16 - mb);
         units.push_back(t);
       }
-    ph.push_back({mode, off, (int)units.size() - off});
+    const int cnt = (int)units.size() - off;
+    ph.push_back({mode, off, cnt, cnt < kDD2SplitUnits});
   };
   int L = 0;
   while ((ny >> L) > 0) L++;
@@ -764,7 +769,7 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
     }
     add_units(DD2_APPLY, ap);
     if (!k0.empty()) {
-      ph.push_back({-1, (int)rows.size(), (int)k0.size()});
+      ph.push_back({-1, (int)rows.size(), (int)k0.size(), false});
       rows.insert(rows.end(), k0.begin(), k0.end());
     }
     add_units(DD2_KUP, kup);
@@ -983,7 +988,7 @@ pr_status dd2_substep(pr_problem_s* P, Instance& I, bool coarse, bool single, in
       HIPOK(launch_dd2_kup0(I.rows2.p + ph.off, ph.cnt, bc, Z, Y, I.d.nx, Npad, s));
     else
       HIPOK(launch_dd2_solve(ph.mode, I.units2.p + ph.off, ph.cnt, pool, bc, Z, Y, I.d.nx, Npad,
-                             single, s));
+                             single, ph.ksplit, s));
   }
   return PR_OK;
 }
@@ -1015,7 +1020,7 @@ pr_status dd2_fine(pr_problem_s* P, Instance& I, const double* U, double* out, h
   }
   for (int t = 0; t < I.d.fine_steps; t++) {
     if (I.h.nforce) {
-      PhaseTimer pt(P, PH_FINE, s);
+      PhaseTimer pt(P, PH_OTHER, s);
       HIPOK(launch_dd2_force_sm(I.fS.p, I.fgf.p, (long)N * I.d.fine_steps, I.d.fine_steps, t,
                                 I.Zs.p, npts, N, Np, s));
     }

@@ -300,10 +300,11 @@ hipError_t launch_dd2_aug(const double* D, const double* B, const double* C, int
 hipError_t launch_dd2_gemm(const DD2Gemm* jobs, int n, int W, hipStream_t s);
 hipError_t launch_dd2_store(const DD2Copy* jobs, int n, int W, hipStream_t s);
 // One solve phase over a unit list (mode DD2_*), all slice columns.
-// single: one state in natural layout (Npad = 1).
+// single: one state in natural layout (Npad = 1). ksplit: one workgroup per
+// unit with the k-blocks split over its four waves (for launches with few units).
 hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const double* pool,
                             const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
-                            hipStream_t s);
+                            bool ksplit, hipStream_t s);
 hipError_t launch_dd2_kup0(const DD2Row* rows, int n_rows, const double* bc, double* Z,
                            const double* Y, int nx, int Npad, hipStream_t s);
 // Natural [N][npts] <-> slice-minor [npts][Npad] (padding columns written as 0).

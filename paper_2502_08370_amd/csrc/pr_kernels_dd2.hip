@@ -216,8 +216,8 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 
 // ------------------------------------------------------------------- solve ---
 
-// One wave per unit. The unit's output is rows [16 mb0, 16 (mb0 + nmb)) of
-// block row U.row against TN tiles of 16 slice columns starting at b0:
+// Solve phase kernel. A unit's output is rows [16 mb0, 16 (mb0 + nmb)) of block
+// row U.row against TN tiles of 16 slice columns starting at b0:
 //   APPLY: Y[row] = A0 Z[row]
 //   KUP:   Z[row] = Z[row] - A1 Y[rowm] - A2 Y[rowp]
 //   BACK:  Z[row] = Y[row] - A1 Z[rowm] - A2 Z[rowp]
@@ -228,18 +228,68 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // one contiguous 512-byte load. Inputs past the strip width are read at the
 // last column (finite values) and meet zero matrix entries. Single-state solves
 // (Npad = 1) feed zeros into the 15 unused columns.
+// KSPLIT = 1: four units per workgroup, one per wave. KSPLIT = 4: one unit per
+// workgroup, the k-blocks dealt to the four waves and the partial products
+// summed through LDS (four times shorter dependent chains for launches with
+// few units). The loads of k-block kb + PF are issued right after the products
+// of kb (PF = 1 measured best: deeper rings cost occupancy and were slower).
+template <int MODE, int TN>
+struct Frag {
+  double a[4];
+  double x[TN];
+};
+
+// Loads of k-block kb (clamped into [0, kb_end) so every address is valid; a
+// block past the end contributes a zero A fragment).
 template <int MODE, int TN, bool SINGLE>
+__device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, long mbW,
+                                          const double* X, const double* Xm, const double* Xp,
+                                          const double* vb, const double* vc, int kb, int kb_end,
+                                          int kq, int cl, int w, int nmb, int Npad) {
+  const bool live = kb < kb_end;
+  kb = min(kb, kb_end - 1);
+  const int k = min(kb * 4 + kq, w - 1);
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    // the factor stream is read once: keep it out of the caches' way
+    const double a = __builtin_nontemporal_load(&A[((long)kb * mbW + min(r, nmb - 1)) * 64]);
+    f.a[r] = (live && r < nmb) ? a : 0.0;
+  }
+#pragma unroll
+  for (int nt = 0; nt < TN; nt++) {
+    const long xo = SINGLE ? (long)k : (long)k * Npad + nt * 16;
+    double v;
+    if (MODE == DD2_BACK0) {
+      const double zm = Xm[xo];
+      const double zp = Xp[xo];
+      v = vb[k] * zm + vc[k] * zp;
+    } else {
+      v = X[xo];
+    }
+    f.x[nt] = (SINGLE && cl != 0) ? 0.0 : v;
+  }
+}
+
+template <int MODE, int TN, bool SINGLE, int KSPLIT, int PF = 1>
 __global__ __launch_bounds__(256) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
                                                    const double* __restrict__ pool,
                                                    const double* __restrict__ bcp,
                                                    double* __restrict__ Z, double* __restrict__ Y,
                                                    int nx, int Npad, int b0) {
   const int lane = threadIdx.x % kWave;
-  const int u = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (u >= n_units) return;
+  // the wave index is uniform across the wave: say so, so that the unit's fields
+  // live in scalar registers and its guards are scalar branches
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int u = KSPLIT == 1 ? blockIdx.x * 4 + wave : blockIdx.x;
+  if (u >= n_units) return;  // no barrier follows for KSPLIT = 1; KSPLIT = 4 units are whole
   const DD2Unit U = units[u];
-  const int W = U.W, w = U.w, mbW = W >> 4, nkb = W >> 2;
+  const int W = U.W, w = U.w, nmb = U.nmb;
+  const long mbW = W >> 4;
+  const int nkb = W >> 2;
   const int kq = lane >> 4, cl = lane & 15;
+  // this wave's k-blocks
+  const int kb_lo = KSPLIT == 1 ? 0 : (nkb * wave) / KSPLIT;
+  const int kb_hi = KSPLIT == 1 ? nkb : (nkb * (wave + 1)) / KSPLIT;
   d4 acc[4][TN];
 #pragma unroll
   for (int r = 0; r < 4; r++)
@@ -247,58 +297,75 @@ __global__ __launch_bounds__(256) void k_dd2_solve(const DD2Unit* __restrict__ u
     for (int nt = 0; nt < TN; nt++) acc[r][nt] = d4{0.0, 0.0, 0.0, 0.0};
   const long col_off = SINGLE ? 0 : (long)b0 + cl;
   constexpr int n_terms = (MODE == DD2_KUP || MODE == DD2_BACK) ? 2 : 1;
+#pragma unroll 1
   for (int term = 0; term < n_terms; term++) {
     long aoff;
     int rx;
-    if (MODE == DD2_APPLY) {
-      aoff = U.A0; rx = U.row;
-    } else if (MODE == DD2_BACK0) {
+    if (MODE == DD2_APPLY || MODE == DD2_BACK0) {
       aoff = U.A0; rx = U.row;
     } else {
       aoff = term == 0 ? U.A1 : U.A2;
       rx = term == 0 ? U.rowm : U.rowp;
     }
-    if (rx < 0) continue;
+    if (rx < 0 || kb_lo >= kb_hi) continue;
     const double* Xb = (MODE == DD2_KUP) ? Y : Z;
     const double* A = pool + aoff + (long)U.mb0 * 64 + lane;
     const double* X = Xb + ((long)rx * nx + U.col0) * Npad + col_off;
-    // BACK0: X = b_row * Z[rowm] + c_row * Z[rowp]
-    const double* Xm = (MODE == DD2_BACK0 && U.rowm >= 0)
-                           ? Z + ((long)U.rowm * nx + U.col0) * Npad + col_off : nullptr;
-    const double* Xp = (MODE == DD2_BACK0 && U.rowp >= 0)
-                           ? Z + ((long)U.rowp * nx + U.col0) * Npad + col_off : nullptr;
+    // BACK0: X = b_row * Z[rowm] + c_row * Z[rowp]; a missing neighbour reads
+    // the row itself with a zero coupling (b_0 = c_{ny-1} = 0)
+    const double* Xm = Z + ((long)(U.rowm >= 0 ? U.rowm : U.row) * nx + U.col0) * Npad + col_off;
+    const double* Xp = Z + ((long)(U.rowp >= 0 ? U.rowp : U.row) * nx + U.col0) * Npad + col_off;
     const double* vb = bcp + U.bc;
     const double* vc = bcp + U.bc + W;
-    for (int kb = 0; kb < nkb; kb++) {
-      const int k = min(kb * 4 + kq, w - 1);
-      double xv[TN];
+    // ring of PF k-blocks in flight; the loop runs whole rounds (zero blocks pad the last)
+    Frag<MODE, TN> buf[PF];
 #pragma unroll
-      for (int nt = 0; nt < TN; nt++) {
-        const long xo = SINGLE ? (long)k : (long)k * Npad + nt * 16;
-        double v;
-        if (MODE == DD2_BACK0) {
-          const double zm = Xm ? Xm[xo] : 0.0;
-          const double zp = Xp ? Xp[xo] : 0.0;
-          v = vb[k] * zm + vc[k] * zp;
-        } else {
-          v = X[xo];
-        }
-        xv[nt] = (SINGLE && cl != 0) ? 0.0 : v;
-      }
+    for (int p = 0; p < PF; p++)
+      load_frag<MODE, TN, SINGLE>(buf[p], A, mbW, X, Xm, Xp, vb, vc, kb_lo + p, kb_hi, kq, cl, w,
+                                  nmb, Npad);
+#pragma unroll 1
+    for (int kb = kb_lo; kb < kb_hi; kb += PF) {
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        if (r < U.nmb) {
-          const double a = A[((long)kb * mbW + r) * 64];
+      for (int p = 0; p < PF; p++) {
+        // branch-free: row tiles past nmb multiply zero fragments
+#pragma unroll
+        for (int r = 0; r < 4; r++)
 #pragma unroll
           for (int nt = 0; nt < TN; nt++)
-            acc[r][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xv[nt], acc[r][nt], 0, 0, 0);
-        }
+            acc[r][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(buf[p].a[r], buf[p].x[nt],
+                                                              acc[r][nt], 0, 0, 0);
+        load_frag<MODE, TN, SINGLE>(buf[p], A, mbW, X, Xm, Xp, vb, vc, kb + p + PF, kb_hi, kq,
+                                    cl, w, nmb, Npad);
       }
     }
   }
+  if (KSPLIT > 1) {
+    // waves 1..3 leave their partial products in LDS; wave 0 adds them
+    __shared__ double part[(KSPLIT > 1 ? KSPLIT - 1 : 1) * 4 * TN * 4 * kWave];
+    if (wave > 0) {
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+#pragma unroll
+        for (int nt = 0; nt < TN; nt++)
+#pragma unroll
+          for (int v = 0; v < 4; v++)
+            part[((((wave - 1) * 4 + r) * TN + nt) * 4 + v) * kWave + lane] = acc[r][nt][v];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll 1
+    for (int q = 0; q < KSPLIT - 1; q++)
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+#pragma unroll
+        for (int nt = 0; nt < TN; nt++)
+#pragma unroll
+          for (int v = 0; v < 4; v++)
+            acc[r][nt][v] += part[(((q * 4 + r) * TN + nt) * 4 + v) * kWave + lane];
+  }
 #pragma unroll
   for (int r = 0; r < 4; r++) {
-    if (r >= U.nmb) continue;
+    if (r >= nmb) continue;
 #pragma unroll
     for (int nt = 0; nt < TN; nt++)
 #pragma unroll
@@ -451,45 +518,54 @@ hipError_t launch_dd2_store(const DD2Copy* jobs, int n, int W, hipStream_t s) {
 }
 
 namespace {
-template <int MODE, bool SINGLE>
+template <int MODE, bool SINGLE, int KSPLIT>
 hipError_t solve_tn(int tn, const DD2Unit* units, int n_units, const double* pool,
                     const double* bc, double* Z, double* Y, int nx, int Npad, int b0,
                     hipStream_t s) {
-  const dim3 grid((n_units + 3) / 4), block(256);
+  const dim3 grid(KSPLIT == 1 ? (n_units + 3) / 4 : n_units), block(256);
   switch (tn) {
-    case 1: hipLaunchKernelGGL((k_dd2_solve<MODE, 1, SINGLE>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
-    case 2: hipLaunchKernelGGL((k_dd2_solve<MODE, 2, SINGLE>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
-    case 3: hipLaunchKernelGGL((k_dd2_solve<MODE, 3, SINGLE>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
-    default: hipLaunchKernelGGL((k_dd2_solve<MODE, 4, SINGLE>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
+    case 1: hipLaunchKernelGGL((k_dd2_solve<MODE, 1, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
+    case 2: hipLaunchKernelGGL((k_dd2_solve<MODE, 2, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
+    case 3: hipLaunchKernelGGL((k_dd2_solve<MODE, 3, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
+    default: hipLaunchKernelGGL((k_dd2_solve<MODE, 4, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
   }
   return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, int KSPLIT>
 hipError_t solve_mode(const DD2Unit* units, int n_units, const double* pool, const double* bc,
                       double* Z, double* Y, int nx, int Npad, bool single, hipStream_t s) {
-  if (single) return solve_tn<MODE, true>(1, units, n_units, pool, bc, Z, Y, nx, 1, 0, s);
+  if (single) return solve_tn<MODE, true, KSPLIT>(1, units, n_units, pool, bc, Z, Y, nx, 1, 0, s);
   for (int b0 = 0; b0 < Npad; b0 += 64) {
     const int tn = std::min(4, (Npad - b0) / 16);
-    hipError_t e = solve_tn<MODE, false>(tn, units, n_units, pool, bc, Z, Y, nx, Npad, b0, s);
+    hipError_t e =
+        solve_tn<MODE, false, KSPLIT>(tn, units, n_units, pool, bc, Z, Y, nx, Npad, b0, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <int KSPLIT>
+hipError_t solve_split(int mode, const DD2Unit* units, int n_units, const double* pool,
+                       const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
+                       hipStream_t s) {
+  switch (mode) {
+    case DD2_APPLY: return solve_mode<DD2_APPLY, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+    case DD2_KUP: return solve_mode<DD2_KUP, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+    case DD2_BACK: return solve_mode<DD2_BACK, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+    case DD2_BACK0: return solve_mode<DD2_BACK0, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 }  // namespace
 
 hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const double* pool,
                             const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
-                            hipStream_t s) {
+                            bool ksplit, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   if (!single && Npad % 16 != 0) return hipErrorInvalidValue;
-  switch (mode) {
-    case DD2_APPLY: return solve_mode<DD2_APPLY>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
-    case DD2_KUP: return solve_mode<DD2_KUP>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
-    case DD2_BACK: return solve_mode<DD2_BACK>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
-    case DD2_BACK0: return solve_mode<DD2_BACK0>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (ksplit) return solve_split<4>(mode, units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+  return solve_split<1>(mode, units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
 }
 
 hipError_t launch_dd2_kup0(const DD2Row* rows, int n_rows, const double* bc, double* Z,
