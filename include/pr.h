@@ -10,7 +10,9 @@
  * the parareal algorithm (section 3) whose coarse propagator G and fine
  * propagator F are fractional implicit Euler (FIE, eq. FIE_method) under
  * dimensional splitting (A_1 = x-direction, A_2 = y-direction) or overlapping
- * domain-decomposition splitting with a partition of unity (section 2.1).
+ * domain-decomposition splitting with a partition of unity (section 2.1): in
+ * 1D, components are intervals; in 2D, vertical strips (the subdomains of
+ * Fig. fig:domaindecomposition), the partition of unity depending on x only.
  *
  * Discretisation: second-order finite differences on the interior nodes of a
  * uniform grid, h_x = 1/(nx+1), h_y = 1/(ny+1), diffusion coefficient given on
@@ -23,7 +25,9 @@
  *   y-faces         ay[g*nx + i], face g between nodes (i,g-1) and (i,g)
  *   nodal theta     theta[(j+1)*(nx+2) + (i+1)] with boundary nodes included
  *                   ((ny+2)*(nx+2) values; nx+2 values in 1D)
- *   PoU weights     rho[k*(nx+1) + f], colour k, face f (1D DD only)
+ *   PoU weights     1D DD: rho[k*(nx+1) + f], colour k, face f
+ *                   2D DD: rho[k*(2*nx+1) + m], colour k, half-grid sample m
+ *                   of x: m = 2f is x-face f, m = 2i+1 is node column i
  * A problem handle may hold several independent instances ("batch"); their
  * states are packed one after the other at the offsets pr_query_layout
  * returns.
@@ -78,19 +82,28 @@ enum { PR_COEF_FACES = 0, PR_COEF_NODAL_LOG = 1 };
  *   coarse_steps   FIE steps taken by one application of G (>= 1)
  *   fine           PR_FIE or PR_DR (the Douglas-Rachford fine propagator needs
  *                  PR_SPLIT_DIM; the coarse propagator is always FIE)
- *   split          PR_SPLIT_DIM (dim 1 or 2) or PR_SPLIT_DD (dim 1 only)
+ *   split          PR_SPLIT_DIM (dim 2) or PR_SPLIT_DD (dim 1 or 2)
  *   coef_mode      PR_COEF_FACES: coef_x = ax, coef_y = ay (NULL in 1D)
  *                  PR_COEF_NODAL_LOG: coef_x = theta, coef_y unused
  *   coef_x, coef_y device pointers, read during pr_create_problem /
  *                  pr_set_coefficients only
  *   c              reaction coefficient >= 0; split equally over the M
- *                  dimensional terms (c/M per substep); must be 0 for DD
+ *                  dimensional terms (c/M per substep); weighted by rho_k in
+ *                  the 2D DD terms; must be 0 for 1D DD
  *   n_colors       DD: number M of split terms (colours), 1..64
- *   rho            DD: HOST pointer to the partition-of-unity face weights
- *                  [n_colors][nx+1], each in [0,1], summing to 1 on every
- *                  face (|sum - 1| <= 1e-14). The connected components of
- *                  colour k are the maximal runs of faces with rho_k > 0;
- *                  each component is one independent tridiagonal system.
+ *   rho            DD: HOST pointer to the partition-of-unity weights, each in
+ *                  [0,1], summing to 1 at every sample (|sum - 1| <= 1e-14).
+ *                  1D: [n_colors][nx+1] face weights; the components of colour
+ *                  k are the maximal runs of faces with rho_k > 0, each one
+ *                  independent tridiagonal system. 2D: [n_colors][2*nx+1]
+ *                  samples on the half grid of x (x-fluxes take rho at their
+ *                  face, y-fluxes and the reaction rho at the node column);
+ *                  the strips of colour k are the maximal runs of columns with
+ *                  rho_k > 0 on the node or on one of its x-faces, each one
+ *                  independent 5-point system (at most 1024 columns wide),
+ *                  solved exactly by block cyclic reduction in y with
+ *                  precomputed w x w blocks: about 3 ny w^2 doubles of device
+ *                  memory per strip and step size.
  *   n_forcing      number of separable source terms, 0..PR_MAX_FORCING: the
  *                  source of eq. FIE_method / eq. DR_method (homogeneous
  *                  boundary data) is F(t) = sum_m g_m(t) S_m, and tau F at the

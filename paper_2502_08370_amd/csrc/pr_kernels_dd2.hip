@@ -231,8 +231,9 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // KSPLIT = 1: four units per workgroup, one per wave. KSPLIT = 4: one unit per
 // workgroup, the k-blocks dealt to the four waves and the partial products
 // summed through LDS (four times shorter dependent chains for launches with
-// few units). The loads of k-block kb + PF are issued right after the products
-// of kb (PF = 1 measured best: deeper rings cost occupancy and were slower).
+// few units). The loads of k-block kb + 1 are issued before the products of kb
+// (measured faster than deeper prefetch rings, which cost occupancy, and than
+// non-temporal loads of the factor stream).
 template <int MODE, int TN>
 struct Frag {
   double a[4];
@@ -240,7 +241,7 @@ struct Frag {
 };
 
 // Loads of k-block kb (clamped into [0, kb_end) so every address is valid; a
-// block past the end contributes a zero A fragment).
+// block past the end, or a row tile past nmb, contributes a zero A fragment).
 template <int MODE, int TN, bool SINGLE>
 __device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, long mbW,
                                           const double* X, const double* Xm, const double* Xp,
@@ -252,8 +253,7 @@ __device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, lo
 #pragma unroll
   for (int r = 0; r < 4; r++) {
     // the factor stream is read once: keep it out of the caches' way
-    const double a = __builtin_nontemporal_load(&A[((long)kb * mbW + min(r, nmb - 1)) * 64]);
-    f.a[r] = (live && r < nmb) ? a : 0.0;
+    f.a[r] = (live && r < nmb) ? A[((long)kb * mbW + r) * 64] : 0.0;
   }
 #pragma unroll
   for (int nt = 0; nt < TN; nt++) {
@@ -270,7 +270,7 @@ __device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, lo
   }
 }
 
-template <int MODE, int TN, bool SINGLE, int KSPLIT, int PF = 1>
+template <int MODE, int TN, bool SINGLE, int KSPLIT>
 __global__ __launch_bounds__(256) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
                                                    const double* __restrict__ pool,
                                                    const double* __restrict__ bcp,
@@ -317,26 +317,20 @@ __global__ __launch_bounds__(256) void k_dd2_solve(const DD2Unit* __restrict__ u
     const double* Xp = Z + ((long)(U.rowp >= 0 ? U.rowp : U.row) * nx + U.col0) * Npad + col_off;
     const double* vb = bcp + U.bc;
     const double* vc = bcp + U.bc + W;
-    // ring of PF k-blocks in flight; the loop runs whole rounds (zero blocks pad the last)
-    Frag<MODE, TN> buf[PF];
+    Frag<MODE, TN> cur, nxt;
+    load_frag<MODE, TN, SINGLE>(cur, A, mbW, X, Xm, Xp, vb, vc, kb_lo, kb_hi, kq, cl, w, nmb, Npad);
+    for (int kb = kb_lo; kb < kb_hi; kb++) {
+      if (kb + 1 < kb_hi)
+        load_frag<MODE, TN, SINGLE>(nxt, A, mbW, X, Xm, Xp, vb, vc, kb + 1, kb_hi, kq, cl, w, nmb, Npad);
 #pragma unroll
-    for (int p = 0; p < PF; p++)
-      load_frag<MODE, TN, SINGLE>(buf[p], A, mbW, X, Xm, Xp, vb, vc, kb_lo + p, kb_hi, kq, cl, w,
-                                  nmb, Npad);
-#pragma unroll 1
-    for (int kb = kb_lo; kb < kb_hi; kb += PF) {
-#pragma unroll
-      for (int p = 0; p < PF; p++) {
-        // branch-free: row tiles past nmb multiply zero fragments
-#pragma unroll
-        for (int r = 0; r < 4; r++)
+      for (int r = 0; r < 4; r++) {
+        if (r < nmb) {
 #pragma unroll
           for (int nt = 0; nt < TN; nt++)
-            acc[r][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(buf[p].a[r], buf[p].x[nt],
-                                                              acc[r][nt], 0, 0, 0);
-        load_frag<MODE, TN, SINGLE>(buf[p], A, mbW, X, Xm, Xp, vb, vc, kb + p + PF, kb_hi, kq,
-                                    cl, w, nmb, Npad);
+            acc[r][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.a[r], cur.x[nt], acc[r][nt], 0, 0, 0);
+        }
       }
+      cur = nxt;
     }
   }
   if (KSPLIT > 1) {
