@@ -136,7 +136,8 @@ struct Instance {
   struct Phase2 {
     int mode;  // DD2_* (units) or -1 (level-0 kept rows)
     int off, cnt;
-    bool ksplit;  // few units: split each unit's k-blocks over a workgroup
+    int split;  // see launch_dd2_solve
+    int waves;  // split 0: waves per workgroup
   };
   std::vector<std::vector<Phase2>> phases2;  // per colour, in launch order
   DArr<DD2Unit> units2;
@@ -731,9 +732,23 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
   auto add_units = [&](int mode, const std::vector<DD2Unit>& tasks) {
     if (tasks.empty()) return;
     long tiles4 = 0;
-    for (auto& t : tasks) tiles4 += (t.W / 16 + 3) / 4;
-    const int nmb = tiles4 >= 512 ? 4 : (tiles4 >= 128 ? 2 : 1);
+    int max_tiles = 0;
+    for (auto& t : tasks) {
+      tiles4 += (t.W / 16 + 3) / 4;
+      max_tiles = std::max(max_tiles, t.W / 16);
+    }
     const int off = (int)units.size();
+    if (tiles4 >= kDD2SplitUnits && max_tiles <= 32) {
+      // many units: one workgroup per block row
+      for (auto t : tasks) {
+        t.mb0 = 0;
+        t.nmb = t.W / 16;
+        units.push_back(t);
+      }
+      ph.push_back({mode, off, (int)units.size() - off, 0, (max_tiles + 3) / 4});
+      return;
+    }
+    const int nmb = tiles4 >= 512 ? 4 : (tiles4 >= 128 ? 2 : 1);
     for (auto t : tasks)
       for (int mb = 0; mb < t.W / 16; mb += nmb) {
         t.mb0 = mb;
@@ -741,7 +756,7 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
         units.push_back(t);
       }
     const int cnt = (int)units.size() - off;
-    ph.push_back({mode, off, cnt, cnt < kDD2SplitUnits});
+    ph.push_back({mode, off, cnt, cnt < kDD2SplitUnits ? 4 : 1, 0});
   };
   int L = 0;
   while ((ny >> L) > 0) L++;
@@ -769,7 +784,7 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
     }
     add_units(DD2_APPLY, ap);
     if (!k0.empty()) {
-      ph.push_back({-1, (int)rows.size(), (int)k0.size(), false});
+      ph.push_back({-1, (int)rows.size(), (int)k0.size(), 0, 0});
       rows.insert(rows.end(), k0.begin(), k0.end());
     }
     add_units(DD2_KUP, kup);
@@ -988,7 +1003,7 @@ pr_status dd2_substep(pr_problem_s* P, Instance& I, bool coarse, bool single, in
       HIPOK(launch_dd2_kup0(I.rows2.p + ph.off, ph.cnt, bc, Z, Y, I.d.nx, Npad, s));
     else
       HIPOK(launch_dd2_solve(ph.mode, I.units2.p + ph.off, ph.cnt, pool, bc, Z, Y, I.d.nx, Npad,
-                             single, ph.ksplit, s));
+                             single, ph.split, ph.waves, s));
   }
   return PR_OK;
 }

@@ -300,11 +300,13 @@ hipError_t launch_dd2_aug(const double* D, const double* B, const double* C, int
 hipError_t launch_dd2_gemm(const DD2Gemm* jobs, int n, int W, hipStream_t s);
 hipError_t launch_dd2_store(const DD2Copy* jobs, int n, int W, hipStream_t s);
 // One solve phase over a unit list (mode DD2_*), all slice columns.
-// single: one state in natural layout (Npad = 1). ksplit: one workgroup per
-// unit with the k-blocks split over its four waves (for launches with few units).
+// single: one state in natural layout (Npad = 1). split = 0: each unit is a
+// whole block row (nmb = W/16 <= 32), one workgroup of `waves` waves (4 row
+// tiles each); 1: four units of <= 4 row tiles per workgroup; 4: one unit per
+// workgroup with its k-blocks split over four waves (launches with few units).
 hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const double* pool,
                             const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
-                            bool ksplit, hipStream_t s);
+                            int split, int waves, hipStream_t s);
 hipError_t launch_dd2_kup0(const DD2Row* rows, int n_rows, const double* bc, double* Z,
                            const double* Y, int nx, int Npad, hipStream_t s);
 // Natural [N][npts] <-> slice-minor [npts][Npad] (padding columns written as 0).

@@ -228,10 +228,12 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // one contiguous 512-byte load. Inputs past the strip width are read at the
 // last column (finite values) and meet zero matrix entries. Single-state solves
 // (Npad = 1) feed zeros into the 15 unused columns.
-// KSPLIT = 1: four units per workgroup, one per wave. KSPLIT = 4: one unit per
-// workgroup, the k-blocks dealt to the four waves and the partial products
-// summed through LDS (four times shorter dependent chains for launches with
-// few units). The loads of k-block kb + 1 are issued before the products of kb
+// KSPLIT = 0: one block row per workgroup, wave i taking its row tiles
+// [4i, 4i + 4) (the waves share the row's right-hand sides through the CU's
+// cache). KSPLIT = 1: four units per workgroup, one per wave. KSPLIT = 4: one
+// unit per workgroup, the k-blocks dealt to the four waves and the partial
+// products summed through LDS (four times shorter dependent chains for
+// launches with few units). The loads of k-block kb + 1 are issued before the products of kb
 // (measured faster than deeper prefetch rings, which cost occupancy, and than
 // non-temporal loads of the factor stream).
 template <int MODE, int TN>
@@ -271,7 +273,7 @@ __device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, lo
 }
 
 template <int MODE, int TN, bool SINGLE, int KSPLIT>
-__global__ __launch_bounds__(256) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
+__global__ __launch_bounds__(KSPLIT == 0 ? 512 : 256) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
                                                    const double* __restrict__ pool,
                                                    const double* __restrict__ bcp,
                                                    double* __restrict__ Z, double* __restrict__ Y,
@@ -281,15 +283,19 @@ __global__ __launch_bounds__(256) void k_dd2_solve(const DD2Unit* __restrict__ u
   // live in scalar registers and its guards are scalar branches
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int u = KSPLIT == 1 ? blockIdx.x * 4 + wave : blockIdx.x;
-  if (u >= n_units) return;  // no barrier follows for KSPLIT = 1; KSPLIT = 4 units are whole
+  if (u >= n_units) return;  // no barrier follows for KSPLIT <= 1; KSPLIT = 4 units are whole
   const DD2Unit U = units[u];
-  const int W = U.W, w = U.w, nmb = U.nmb;
+  const int W = U.W, w = U.w;
+  // KSPLIT = 0: the unit is a whole block row; wave i takes its row tiles [4i, 4i + 4)
+  const int mb0 = KSPLIT == 0 ? U.mb0 + 4 * wave : U.mb0;
+  const int nmb = KSPLIT == 0 ? min(4, U.nmb - 4 * wave) : U.nmb;
+  if (nmb <= 0) return;
   const long mbW = W >> 4;
   const int nkb = W >> 2;
   const int kq = lane >> 4, cl = lane & 15;
   // this wave's k-blocks
-  const int kb_lo = KSPLIT == 1 ? 0 : (nkb * wave) / KSPLIT;
-  const int kb_hi = KSPLIT == 1 ? nkb : (nkb * (wave + 1)) / KSPLIT;
+  const int kb_lo = KSPLIT <= 1 ? 0 : (nkb * wave) / KSPLIT;
+  const int kb_hi = KSPLIT <= 1 ? nkb : (nkb * (wave + 1)) / KSPLIT;
   d4 acc[4][TN];
 #pragma unroll
   for (int r = 0; r < 4; r++)
@@ -309,7 +315,7 @@ __global__ __launch_bounds__(256) void k_dd2_solve(const DD2Unit* __restrict__ u
     }
     if (rx < 0 || kb_lo >= kb_hi) continue;
     const double* Xb = (MODE == DD2_KUP) ? Y : Z;
-    const double* A = pool + aoff + (long)U.mb0 * 64 + lane;
+    const double* A = pool + aoff + (long)mb0 * 64 + lane;
     const double* X = Xb + ((long)rx * nx + U.col0) * Npad + col_off;
     // BACK0: X = b_row * Z[rowm] + c_row * Z[rowp]; a missing neighbour reads
     // the row itself with a zero coupling (b_0 = c_{ny-1} = 0)
@@ -364,7 +370,7 @@ __global__ __launch_bounds__(256) void k_dd2_solve(const DD2Unit* __restrict__ u
     for (int nt = 0; nt < TN; nt++)
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        const int o = (U.mb0 + r) * 16 + 4 * v + kq;
+        const int o = (mb0 + r) * 16 + 4 * v + kq;
         if (o >= w || (SINGLE && cl != 0)) continue;
         const long idx = ((long)U.row * nx + U.col0 + o) * Npad + (SINGLE ? 0 : b0 + nt * 16 + cl);
         const double val = acc[r][nt][v];
@@ -514,9 +520,10 @@ hipError_t launch_dd2_store(const DD2Copy* jobs, int n, int W, hipStream_t s) {
 namespace {
 template <int MODE, bool SINGLE, int KSPLIT>
 hipError_t solve_tn(int tn, const DD2Unit* units, int n_units, const double* pool,
-                    const double* bc, double* Z, double* Y, int nx, int Npad, int b0,
+                    const double* bc, double* Z, double* Y, int nx, int Npad, int b0, int waves,
                     hipStream_t s) {
-  const dim3 grid(KSPLIT == 1 ? (n_units + 3) / 4 : n_units), block(256);
+  const dim3 grid(KSPLIT == 1 ? (n_units + 3) / 4 : n_units),
+      block(KSPLIT == 0 ? kWave * waves : 256);
   switch (tn) {
     case 1: hipLaunchKernelGGL((k_dd2_solve<MODE, 1, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
     case 2: hipLaunchKernelGGL((k_dd2_solve<MODE, 2, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
@@ -528,12 +535,14 @@ hipError_t solve_tn(int tn, const DD2Unit* units, int n_units, const double* poo
 
 template <int MODE, int KSPLIT>
 hipError_t solve_mode(const DD2Unit* units, int n_units, const double* pool, const double* bc,
-                      double* Z, double* Y, int nx, int Npad, bool single, hipStream_t s) {
-  if (single) return solve_tn<MODE, true, KSPLIT>(1, units, n_units, pool, bc, Z, Y, nx, 1, 0, s);
+                      double* Z, double* Y, int nx, int Npad, bool single, int waves,
+                      hipStream_t s) {
+  if (single)
+    return solve_tn<MODE, true, KSPLIT>(1, units, n_units, pool, bc, Z, Y, nx, 1, 0, waves, s);
   for (int b0 = 0; b0 < Npad; b0 += 64) {
     const int tn = std::min(4, (Npad - b0) / 16);
-    hipError_t e =
-        solve_tn<MODE, false, KSPLIT>(tn, units, n_units, pool, bc, Z, Y, nx, Npad, b0, s);
+    hipError_t e = solve_tn<MODE, false, KSPLIT>(tn, units, n_units, pool, bc, Z, Y, nx, Npad, b0,
+                                                 waves, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -542,12 +551,12 @@ hipError_t solve_mode(const DD2Unit* units, int n_units, const double* pool, con
 template <int KSPLIT>
 hipError_t solve_split(int mode, const DD2Unit* units, int n_units, const double* pool,
                        const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
-                       hipStream_t s) {
+                       int waves, hipStream_t s) {
   switch (mode) {
-    case DD2_APPLY: return solve_mode<DD2_APPLY, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
-    case DD2_KUP: return solve_mode<DD2_KUP, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
-    case DD2_BACK: return solve_mode<DD2_BACK, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
-    case DD2_BACK0: return solve_mode<DD2_BACK0, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+    case DD2_APPLY: return solve_mode<DD2_APPLY, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, waves, s);
+    case DD2_KUP: return solve_mode<DD2_KUP, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, waves, s);
+    case DD2_BACK: return solve_mode<DD2_BACK, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, waves, s);
+    case DD2_BACK0: return solve_mode<DD2_BACK0, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, waves, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -555,11 +564,15 @@ hipError_t solve_split(int mode, const DD2Unit* units, int n_units, const double
 
 hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const double* pool,
                             const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
-                            bool ksplit, hipStream_t s) {
+                            int split, int waves, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   if (!single && Npad % 16 != 0) return hipErrorInvalidValue;
-  if (ksplit) return solve_split<4>(mode, units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
-  return solve_split<1>(mode, units, n_units, pool, bc, Z, Y, nx, Npad, single, s);
+  if (split == 4) return solve_split<4>(mode, units, n_units, pool, bc, Z, Y, nx, Npad, single, 0, s);
+  if (split == 0) {
+    if (waves < 1 || waves > 8) return hipErrorInvalidValue;
+    return solve_split<0>(mode, units, n_units, pool, bc, Z, Y, nx, Npad, single, waves, s);
+  }
+  return solve_split<1>(mode, units, n_units, pool, bc, Z, Y, nx, Npad, single, 0, s);
 }
 
 hipError_t launch_dd2_kup0(const DD2Row* rows, int n_rows, const double* bc, double* Z,

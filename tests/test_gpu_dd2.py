@@ -53,6 +53,13 @@ def test_dd2_fine_propagate(nx, ny, q, beta, N, s, M, c):
     assert fine_parity(w, seed=N) <= TOL
 
 
+def test_dd2_tall_strips():
+    """Strips of 6 row tiles over 2100 rows: the large first-level launches take one
+    workgroup per block row (two waves of row tiles)."""
+    w = W.small_dd2(160, 2100, 1, 0.1, 2, 1, seed=21)
+    assert fine_parity(w, seed=3) <= TOL
+
+
 def test_dd2_single_colour_full_width():
     """One colour with rho = 1: a single strip spanning the grid (implicit Euler)."""
     nx, ny = 130, 21
