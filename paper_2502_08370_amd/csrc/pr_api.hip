@@ -926,8 +926,7 @@ pr_status factorize_dd2_instance(Instance& I, const double* coef_x, const double
                S.col0, S.w, W, 0, tau / (hx * hx), tau / (hy * hy), tau * d.c};
       HIPOK(launch_dd2_bc(g, bcp + S.bc0, s));
       // level 0: inverses of the eliminated rows, then the level-1 blocks
-      HIPOK(launch_dd2_build0(g, nE0, aug0.p, 2 * w2, s));
-      HIPOK(launch_dd2_gj(aug0.p, 2 * w2, nE0, W, 2 * W, s));
+      HIPOK(launch_dd2_tri_inv(g, nE0, aug0.p, 2 * w2, s));
       {
         std::vector<DD2Copy> jobs;
         for (int e = 0; e < nE0; e++)

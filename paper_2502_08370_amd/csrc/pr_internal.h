@@ -286,8 +286,9 @@ enum { DD2_APPLY = 0, DD2_KUP = 1, DD2_BACK = 2, DD2_BACK0 = 3 };
 // Coupling vectors of every block row: bc[r][0][o] = b_r, bc[r][1][o] = c_r
 // (zero past w, b_0 = c_{ny-1} = 0).
 hipError_t launch_dd2_bc(const DD2Geo& g, double* bc, hipStream_t s);
-// [D_r | I] for the level-0 eliminated rows r = 2m, m < n (row stride 2W).
-hipError_t launch_dd2_build0(const DD2Geo& g, int n, double* aug, long mstride, hipStream_t s);
+// Inverses of the level-0 blocks (tridiagonal) of the eliminated rows r = 2m,
+// m < n, into columns [W, 2W) of the matrix at aug + m * mstride (row stride 2W).
+hipError_t launch_dd2_tri_inv(const DD2Geo& g, int n, double* aug, long mstride, hipStream_t s);
 // Gauss-Jordan on n augmented matrices [D | R] (W rows, LD columns): D -> I, R -> D^-1 R.
 hipError_t launch_dd2_gj(double* aug, long mstride, int n, int W, int LD, hipStream_t s);
 // Level-1 blocks of the level-0 kept rows r = 2a + 1 (a < ny / 2) from the

@@ -60,41 +60,94 @@ __global__ void k_dd2_bc(DD2Geo g, double* __restrict__ bc) {
   bc[((long)r * 2 + 1) * g.W + o] = c;
 }
 
-__global__ void k_dd2_build0(DD2Geo g, double* __restrict__ aug, long mstride) {
-  const int m = blockIdx.y, r = 2 * m;
-  const int LD = 2 * g.W;
-  double* A = aug + m * mstride;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < (long)g.W * LD;
-       t += (long)gridDim.x * blockDim.x) {
-    const int o = (int)(t / LD), col = (int)(t % LD);
-    A[t] = col < g.W ? d0_entry(g, r, o, col) : (col - g.W == o ? 1.0 : 0.0);
+// Inverses of the level-0 blocks, which are tridiagonal: one LU (pivots and
+// multipliers, a short recurrence in LDS) per block, then one Thomas solve per
+// column of the identity, thread per column (for a fixed row the threads write
+// consecutive entries). The inverse lands in columns [W, 2W) of the matrix at
+// aug + m * mstride (row stride 2W), where the consumers read it.
+__global__ __launch_bounds__(256) void k_dd2_tri_inv(DD2Geo g, double* __restrict__ aug,
+                                                     long mstride) {
+  __shared__ double piv[kDD2MaxW], mul[kDD2MaxW], sup[kDD2MaxW];
+  const int m = blockIdx.x, r = 2 * m, W = g.W, LD = 2 * W;
+  double* A = aug + m * mstride + W;
+  for (int o = threadIdx.x; o < W; o += blockDim.x) {
+    piv[o] = d0_entry(g, r, o, o);                         // diagonal
+    mul[o] = o > 0 ? d0_entry(g, r, o, o - 1) : 0.0;       // sub-diagonal
+    sup[o] = o + 1 < W ? d0_entry(g, r, o, o + 1) : 0.0;   // super-diagonal
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int o = 1; o < W; o++) {
+      const double f = mul[o] / piv[o - 1];
+      mul[o] = f;
+      piv[o] = piv[o] - f * sup[o - 1];
+    }
+  __syncthreads();
+  for (int j = threadIdx.x; j < W; j += blockDim.x) {
+    double y = 0.0;
+    for (int o = 0; o < W; o++) {  // forward: L y = e_j
+      y = (o == j) ? 1.0 : (o > j ? -mul[o] * y : 0.0);
+      A[(long)o * LD + j] = y;
+    }
+    double x = 0.0;
+    for (int o = W - 1; o >= 0; o--) {  // back: U x = y
+      x = (A[(long)o * LD + j] - sup[o] * x) / piv[o];
+      A[(long)o * LD + j] = x;
+    }
   }
 }
 
 // Gauss-Jordan elimination without pivoting (the blocks are strictly
 // diagonally dominant M-matrices at every level of the reduction), one
-// workgroup per matrix. Pivot p: the pivot row is scaled into LDS, then every
-// other row subtracts its multiple of it from column p+1 on (columns < p of
-// the left part are already unit columns; column p is not read again).
-__global__ __launch_bounds__(256) void k_dd2_gj(double* __restrict__ aug, long mstride, int W,
-                                                int LD) {
-  __shared__ double rp[4 * kDD2MaxW];
-  __shared__ double f[kDD2MaxW];
+// workgroup per matrix, in panels of np pivots: the panel's rows P are reduced
+// among themselves in LDS (P <- B^-1 P, B their pivot block), then every other
+// row q takes row_q -= f_q P with f_q its panel-column values before the panel
+// (so the panel columns of row q vanish and the result equals np single
+// steps), one pass over the matrix per panel. Columns left of the panel are
+// finished unit columns and are never read again.
+__global__ __launch_bounds__(512) void k_dd2_gj(double* __restrict__ aug, long mstride, int W,
+                                                int LD, int np_max) {
+  extern __shared__ double lds[];
+  double* panel = lds;                      // [np_max][LD]
+  double* fq = lds + (long)np_max * LD;     // [np_max][W]
   double* A = aug + blockIdx.x * mstride;
-  const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-  for (int p = 0; p < W; p++) {
-    const double inv = 1.0 / A[(long)p * LD + p];
-    for (int q = tid; q < W; q += blockDim.x) f[q] = A[(long)q * LD + p];
-    for (int c = p + 1 + tid; c < LD; c += blockDim.x) rp[c] = A[(long)p * LD + c] * inv;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int p0 = 0; p0 < W; p0 += np_max) {
+    const int np = min(np_max, W - p0), span = LD - p0;
+    for (int e = tid; e < np * span; e += nt) {
+      const int j = e / span, c = p0 + e % span;
+      panel[j * LD + c] = A[(long)(p0 + j) * LD + c];
+    }
+    for (int e = tid; e < W * np; e += nt) {
+      const int q = e / np, j = e % np;
+      fq[j * W + q] = A[(long)q * LD + p0 + j];
+    }
     __syncthreads();
-    for (int q = wave; q < W; q += blockDim.x / kWave) {
-      double* row = A + (long)q * LD;
-      if (q == p) {
-        for (int c = p + 1 + lane; c < LD; c += kWave) row[c] = rp[c];
-      } else {
-        const double fq = f[q];
-        for (int c = p + 1 + lane; c < LD; c += kWave) row[c] = row[c] - fq * rp[c];
+    for (int t = 0; t < np; t++) {
+      const double inv = 1.0 / panel[t * LD + p0 + t];
+      __syncthreads();
+      for (int c = p0 + tid; c < LD; c += nt) panel[t * LD + c] *= inv;
+      __syncthreads();
+      for (int e = tid; e < (np - 1) * span; e += nt) {
+        int j = e / span;
+        j += (j >= t);
+        const int c = p0 + e % span;
+        if (c != p0 + t) panel[j * LD + c] -= panel[j * LD + p0 + t] * panel[t * LD + c];
       }
+      __syncthreads();
+      if (tid < np && tid != t) panel[tid * LD + p0 + t] = 0.0;
+      __syncthreads();
+    }
+    for (int e = tid; e < W * span; e += nt) {
+      const int q = e / span, c = p0 + e % span;
+      double v;
+      if (q >= p0 && q < p0 + np) {
+        v = panel[(q - p0) * LD + c];
+      } else {
+        v = A[(long)q * LD + c];
+        for (int t = 0; t < np; t++) v -= fq[t * W + q] * panel[t * LD + c];
+      }
+      A[(long)q * LD + c] = v;
     }
     __syncthreads();
   }
@@ -472,17 +525,20 @@ hipError_t launch_dd2_bc(const DD2Geo& g, double* bc, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_dd2_build0(const DD2Geo& g, int n, double* aug, long mstride, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dd2_build0, dim3(grid_for((long)g.W * 2 * g.W, 256, 256), n), dim3(256), 0,
-                     s, g, aug, mstride);
-  return hipGetLastError();
-}
-
 hipError_t launch_dd2_gj(double* aug, long mstride, int n, int W, int LD, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (W > kDD2MaxW || LD > 4 * kDD2MaxW) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dd2_gj, dim3(n), dim3(256), 0, s, aug, mstride, W, LD);
+  // panel of up to 8 pivots within ~96 KB of LDS (panel rows + multipliers)
+  const int np_max = std::max(1, std::min(8, (96 * 1024) / (8 * (LD + W))));
+  const size_t lds = (size_t)np_max * (LD + W) * sizeof(double);
+  hipLaunchKernelGGL(k_dd2_gj, dim3(n), dim3(512), lds, s, aug, mstride, W, LD, np_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_tri_inv(const DD2Geo& g, int n, double* aug, long mstride, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (g.W > kDD2MaxW) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dd2_tri_inv, dim3(n), dim3(256), 0, s, g, aug, mstride);
   return hipGetLastError();
 }
 
