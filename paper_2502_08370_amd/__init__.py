@@ -60,7 +60,8 @@ class Problem:
     Each instance is a dict with keys: dim, nx, ny, T, n_slices, fine_steps,
     coarse_steps (1), split ('dim' | 'dd'), fine ('fie' | 'dr'), c (0.0), and
     either ax / ay (face coefficients) or theta (nodal log coefficient), plus rho
-    (partition-of-unity face weights, host array) for 'dd', and optionally
+    (partition of unity, host array) for 'dd': (M, nx+1) face weights in 1D,
+    (M, 2*nx+1) samples on the half grid of x in 2D (vertical strips), and optionally
     forcing = (S, g_fine, g_coarse): the source F(t) = sum_m g_m(t) S_m with S
     of shape (m, ny, nx), g_fine (m, n_slices*fine_steps) and g_coarse
     (m, n_slices*coarse_steps) at the step end times (m <= 2).
