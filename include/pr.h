@@ -80,8 +80,8 @@ enum { PR_COEF_FACES = 0, PR_COEF_NODAL_LOG = 1 };
  *   n_slices       N_c: coarse intervals, DT = T / N_c
  *   fine_steps     s: fine steps per coarse interval, dt = DT / s
  *   coarse_steps   FIE steps taken by one application of G (>= 1)
- *   fine           PR_FIE or PR_DR (the Douglas-Rachford fine propagator needs
- *                  PR_SPLIT_DIM; the coarse propagator is always FIE)
+ *   fine           PR_FIE or PR_DR (the Douglas-Rachford fine propagator needs a
+ *                  2D split; the coarse propagator is always FIE)
  *   split          PR_SPLIT_DIM (dim 2) or PR_SPLIT_DD (dim 1 or 2)
  *   coef_mode      PR_COEF_FACES: coef_x = ax, coef_y = ay (NULL in 1D)
  *                  PR_COEF_NODAL_LOG: coef_x = theta, coef_y unused

@@ -143,6 +143,7 @@ struct Instance {
   DArr<DD2Unit> units2;
   DArr<DD2Row> rows2;
   DBuf pool2f, pool2c, bc2f, bc2c, rho2, Zs, Ys, Y1;
+  DBuf drS2, drS1;  // Douglas-Rachford terms tau A_k U_n of colours k >= 1 (batch / single)
   int Npad2 = 16;
   // adjoint workspace (allocated on the first pr_adjoint call)
   DBuf adjWV, adjCkpt, adjLam, adjMu, adjGax, adjGay;
@@ -245,9 +246,9 @@ pr_status validate(const pr_problem_desc& d, int idx) {
   if (d.n_slices < 1 || d.fine_steps < 1 || d.coarse_steps < 1)
     return fail(PR_EINVAL, "instance %d: n_slices, fine_steps, coarse_steps must be >= 1", idx);
   if (d.fine != PR_FIE && d.fine != PR_DR) return fail(PR_EINVAL, "instance %d: bad fine", idx);
-  if (d.fine == PR_DR && d.split != PR_SPLIT_DIM)
+  if (d.fine == PR_DR && d.split == PR_SPLIT_DD && d.dim == 1)
     return fail(PR_EUNSUPPORTED,
-                "instance %d: the Douglas-Rachford fine propagator needs the dimensional split", idx);
+                "instance %d: the Douglas-Rachford fine propagator needs a 2D split", idx);
   if (d.split != PR_SPLIT_DIM && d.split != PR_SPLIT_DD)
     return fail(PR_EINVAL, "instance %d: bad split", idx);
   if (d.n_forcing < 0 || d.n_forcing > PR_MAX_FORCING)
@@ -865,6 +866,10 @@ pr_status setup_dd2_instance(Instance& I, const double* rho_host, hipStream_t s)
   HIPOK(I.Ys.alloc(npts * I.Npad2));
   HIPOK(I.Y1.alloc(npts));
   HIPOK(I.tmp.alloc(npts));
+  if (d.fine == PR_DR && K > 1) {
+    HIPOK(I.drS2.alloc((size_t)(K - 1) * npts * I.Npad2));
+    HIPOK(I.drS1.alloc((size_t)(K - 1) * npts));
+  }
   DimInst& h = I.h;
   h.nx = nx; h.ny = ny; h.N = N; h.L = 1; h.B = 1; h.M = 1;
   h.steps = d.fine_steps;
@@ -1007,9 +1012,34 @@ pr_status dd2_substep(pr_problem_s* P, Instance& I, bool coarse, bool single, in
   return PR_OK;
 }
 
-// One FIE step of the single state in tmp (source at table entry gidx).
+// Douglas-Rachford terms of a fine step (eq. DR_method): S_k = dt A_k U_n for
+// colours k >= 1 from the step's input Z (slice-minor, Npad columns), and
+// Z += sum_k S_k, so that the first colour solves U_n + dt (A - A_0) U_n
+// (+ dt F); colour k >= 1 then solves its input minus S_k.
+pr_status dd2_dr_terms(Instance& I, double* Z, double* S, int Npad, hipStream_t s) {
+  const int nx = I.d.nx, ny = I.d.ny;
+  const long n = (long)nx * ny * Npad;
+  const double hx = 1.0 / (nx + 1), hy = 1.0 / (ny + 1);
+  for (int k = 1; k < I.n_colors; k++) {
+    DD2Geo g{I.ax.p, I.ay.p, I.rho2.p + (long)k * (2 * nx + 1), nx, ny, 0, 0, 0, 0,
+             I.dt / (hx * hx), I.dt / (hy * hy), I.dt * I.d.c};
+    HIPOK(launch_dd2_stencil(g, Z, S + (k - 1) * n, Npad, s));
+  }
+  for (int k = 1; k < I.n_colors; k++) HIPOK(launch_dd2_axpy(Z, S + (k - 1) * n, 1.0, n, s));
+  return PR_OK;
+}
+
+// One step of the single state in tmp (source at table entry gidx): FIE, or the
+// Douglas-Rachford fine step when the instance's fine propagator is DR.
 pr_status dd2_step_single(pr_problem_s* P, int i, bool coarse, long gidx, hipStream_t s) {
   Instance& I = *P->inst[i];
+  const bool dr = !coarse && I.d.fine == PR_DR && I.n_colors > 1;
+  const long n = I.npts;
+  if (dr) {
+    PhaseTimer pt(P, PH_OTHER, s);
+    pr_status st = dd2_dr_terms(I, I.tmp.p, I.drS1.p, 1, s);
+    if (st != PR_OK) return st;
+  }
   if (I.h.nforce) {
     const long stride = coarse ? (long)I.d.n_slices * I.d.coarse_steps
                                : (long)I.d.n_slices * I.d.fine_steps;
@@ -1017,6 +1047,7 @@ pr_status dd2_step_single(pr_problem_s* P, int i, bool coarse, long gidx, hipStr
                              s));
   }
   for (int k = 0; k < I.n_colors; k++) {
+    if (dr && k > 0) HIPOK(launch_dd2_axpy(I.tmp.p, I.drS1.p + (k - 1) * n, -1.0, n, s));
     pr_status st = dd2_substep(P, I, coarse, true, k, s);
     if (st != PR_OK) return st;
   }
@@ -1032,13 +1063,24 @@ pr_status dd2_fine(pr_problem_s* P, Instance& I, const double* U, double* out, h
     PhaseTimer pt(P, PH_TRANSPOSE, s);
     HIPOK(launch_dd2_to_sm(U, I.Zs.p, npts, N, Np, s));
   }
+  const bool dr = I.d.fine == PR_DR && I.n_colors > 1;
+  const long n = npts * Np;
   for (int t = 0; t < I.d.fine_steps; t++) {
+    if (dr) {
+      PhaseTimer pt(P, PH_OTHER, s);
+      pr_status st = dd2_dr_terms(I, I.Zs.p, I.drS2.p, Np, s);
+      if (st != PR_OK) return st;
+    }
     if (I.h.nforce) {
       PhaseTimer pt(P, PH_OTHER, s);
       HIPOK(launch_dd2_force_sm(I.fS.p, I.fgf.p, (long)N * I.d.fine_steps, I.d.fine_steps, t,
                                 I.Zs.p, npts, N, Np, s));
     }
     for (int k = 0; k < I.n_colors; k++) {
+      if (dr && k > 0) {
+        PhaseTimer pt(P, PH_OTHER, s);
+        HIPOK(launch_dd2_axpy(I.Zs.p, I.drS2.p + (k - 1) * n, -1.0, n, s));
+      }
       pr_status st = dd2_substep(P, I, false, false, k, s);
       if (st != PR_OK) return st;
     }

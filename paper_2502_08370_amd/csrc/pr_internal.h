@@ -315,6 +315,12 @@ hipError_t launch_dd2_to_sm(const double* U, double* Zs, long npts, int N, int N
                             hipStream_t s);
 hipError_t launch_dd2_from_sm(const double* Zs, double* U, long npts, int N, int Npad,
                               hipStream_t s);
+// Douglas-Rachford term S = tau A_k U of colour k (g.rho = colour k's weights,
+// g.tx / g.ty / g.tc at the step tau) over the whole grid, slice-minor [node][Npad].
+hipError_t launch_dd2_stencil(const DD2Geo& g, const double* U, double* S, int Npad,
+                              hipStream_t s);
+// Z += a S over n entries.
+hipError_t launch_dd2_axpy(double* Z, const double* S, double a, long n, hipStream_t s);
 // Zs[p][b] += sum_m gtab[m * gstride + b * steps + t] S_m[p] for b < N.
 hipError_t launch_dd2_force_sm(const double* fS, const double* gtab, long gstride, int steps,
                                int t, double* Zs, long npts, int N, int Npad, hipStream_t s);

@@ -510,6 +510,33 @@ __global__ void k_dd2_force_sm(const double* __restrict__ fS, const double* __re
   Zs[e] = v;
 }
 
+// Douglas-Rachford terms of the strip split: S = tau A_k U for colour k's
+// weights over the whole grid (zero off the colour's support), slice-minor
+// [node][Npad] (Npad = 1: one state in natural layout). A_k is the operator of
+// the set-up kernels: x-fluxes weighted by rho on the face, y-fluxes and the
+// reaction by rho at the node column.
+__global__ void k_dd2_stencil(DD2Geo g, const double* __restrict__ U, double* __restrict__ S,
+                              int Npad) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long npts = (long)g.nx * g.ny;
+  if (e >= npts * Npad) return;
+  const long p = e / Npad;
+  const int i = (int)(p % g.nx), k = (int)(p / g.nx);
+  const Flux f = node_flux(g, i, k);
+  const double u = U[e];
+  const double uw = i > 0 ? U[e - Npad] : 0.0;
+  const double ue = i + 1 < g.nx ? U[e + Npad] : 0.0;
+  const double us = k > 0 ? U[e - (long)g.nx * Npad] : 0.0;
+  const double un = k + 1 < g.ny ? U[e + (long)g.nx * Npad] : 0.0;
+  S[e] = f.w * (uw - u) + f.e * (ue - u) + f.s * (us - u) + f.n * (un - u) - f.react * u;
+}
+
+__global__ void k_dd2_axpy(double* __restrict__ Z, const double* __restrict__ S, double a,
+                           long n) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < n) Z[e] = fma(a, S[e], Z[e]);
+}
+
 unsigned grid_for(long n, int per_block, unsigned cap = 65535u) {
   long g = (n + per_block - 1) / per_block;
   return (unsigned)std::max<long>(1, std::min<long>(g, cap));
@@ -657,6 +684,20 @@ hipError_t launch_dd2_force_sm(const double* fS, const double* gtab, long gstrid
   const long n = npts * Npad;
   hipLaunchKernelGGL(k_dd2_force_sm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fS, gtab,
                      gstride, steps, t, Zs, npts, N, Npad);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_stencil(const DD2Geo& g, const double* U, double* S, int Npad,
+                              hipStream_t s) {
+  const long n = (long)g.nx * g.ny * Npad;
+  hipLaunchKernelGGL(k_dd2_stencil, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, U, S,
+                     Npad);
+  return hipGetLastError();
+}
+
+hipError_t launch_dd2_axpy(double* Z, const double* S, double a, long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dd2_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Z, S, a, n);
   return hipGetLastError();
 }
 

@@ -53,6 +53,37 @@ def test_dd2_fine_propagate(nx, ny, q, beta, N, s, M, c):
     assert fine_parity(w, seed=N) <= TOL
 
 
+@pytest.mark.parametrize("nx,ny,q,beta,N,s,M,forced", [(40, 33, 2, 0.1, 5, 2, 2, False),
+                                                        (75, 40, 2, 0.05, 9, 2, 3, True),
+                                                        (97, 61, 2, 0.08, 20, 2, 2, True)])
+def test_dd2_dr_fine_propagate(nx, ny, q, beta, N, s, M, forced):
+    """Douglas-Rachford fine propagator (eq. DR_method) over the strip split."""
+    w = W.small_dd2(nx, ny, q, beta, N, s, seed=nx + 3, n_colors=M, c=0.7)
+    w.fine = "dr"
+    if forced:
+        rng = np.random.default_rng(nx)
+        w.forcing = (rng.standard_normal((2, ny, nx)), rng.standard_normal((2, N * s)),
+                     rng.standard_normal((2, N)))
+    assert fine_parity(w, seed=N) <= TOL
+
+
+def test_dd2_dr_sequential_and_parareal():
+    w = W.small_dd2(50, 37, 2, 0.08, 6, 3, seed=17)
+    w.fine = "dr"
+    w.coarse_steps = 2
+    P, O = gpu_problem(w), oracle_problem(w)
+    Seq = P.new_states()
+    P.sequential_fine(dev(w.u0), Seq)
+    U = P.new_states()
+    k, inc = P.parareal_iterate(dev(w.u0), U, k_max=3, tol=0.0)
+    torch.cuda.synchronize()
+    ref = O.sequential_fine(w.u0)
+    assert relerr(Seq.cpu().numpy().reshape(ref.shape), ref) <= TOL
+    Uo, ko, hist = O.parareal(w.u0, 3)
+    assert k[0] == ko
+    assert relerr(U.cpu().numpy().reshape(Uo.shape), Uo) <= TOL
+
+
 def test_dd2_tall_strips():
     """Strips of 6 row tiles over 2100 rows: the large first-level launches take one
     workgroup per block row (two waves of row tiles)."""

@@ -155,3 +155,24 @@ def test_dd2_parareal_finite_termination():
     seq = P.sequential_fine(w.u0)
     assert k == w.n_slices
     assert np.abs(U - seq).max() <= 1e-13 * np.abs(seq).max()
+
+
+def test_dd2_dr_keeps_the_forced_steady_state():
+    """Douglas-Rachford (eq. DR_method) with a time-independent source F leaves
+    U* = -A^{-1} F unchanged for any partition of unity: (I + tau A)U* + tau F = U*
+    and every substep then solves (I - tau A_j)U* = U* - tau A_j U*."""
+    nx, ny = 14, 11
+    w = W.small_dd2(nx, ny, 2, 0.12, 1, 1, seed=12, c=0.5)
+    ax, ay = oracle.faces_from_theta(nx, ny, w.theta)
+    Pd = oracle.Problem(dim=2, nx=nx, ny=ny, T=1.0, n_slices=1, fine_steps=1, c=w.c, ax=ax, ay=ay)
+    n = nx * ny
+    A = np.stack([Pd.apply_A(e.reshape(ny, nx)).ravel() for e in np.eye(n)], axis=1)
+    F = np.random.default_rng(5).standard_normal(n)
+    ustar = np.linalg.solve(A, -F).reshape(ny, nx)
+    for rho in (w.rho, W.strip_pou_2d(nx, 1, 0.2, 3)):
+        P = oracle.Problem(dim=2, nx=nx, ny=ny, T=1.0, n_slices=1, fine_steps=1, split="dd",
+                           fine="dr", c=w.c, ax=ax, ay=ay, rho=rho)
+        got = P.dr_step(ustar, 7e-3, F=F.reshape(ny, nx))
+        assert np.abs(got - ustar).max() <= 1e-11 * np.abs(ustar).max()
+        # and FIE does not (the splitting error of a Lie step)
+        assert np.abs(P.fie_step(ustar, 7e-3, F=F.reshape(ny, nx)) - ustar).max() > 1e-6 * np.abs(ustar).max()
