@@ -247,3 +247,27 @@ def test_dd2_paper_size_residual():
         bound = 1e-12 * (1 + 8 * dt * (n + 1) ** 2) ** 2 * np.abs(v).max()
         assert np.abs(back - Uin[b]).max() <= bound
         assert np.abs(back - Uin[b]).max() <= 1e-6 * np.abs(Uin[b]).max()
+
+
+def test_dd2_fine_error_matches_the_paper_on_gpu():
+    """The GPU sequential fine solve of the paper's DD-split scalability runs
+    reproduces the fine-approximation error the paper prints (five digits)."""
+    import os
+    g = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "dd2_fine_error_h001.txt")):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            k, v = (t.strip() for t in line.split("="))
+            g[k] = float(v)
+    n, N, s = int(g["n"]), int(g["n_slices"]), int(g["fine_steps"])
+    w = W.dd2_manufactured(n=n, n_slices=N, fine_steps=s, q=int(g["q"]), beta=g["beta"])
+    P = gpu_problem(w)
+    U = P.new_states()
+    P.sequential_fine(dev(w.u0), U)
+    torch.cuda.synchronize()
+    U = U.cpu().numpy().reshape(N + 1, n, n)
+    h = 1.0 / (n + 1)
+    err = max(np.sqrt(((U[k] - np.sin(2 * np.pi * k / N) * w.extra["exact_space"]) ** 2).sum()) * h
+              for k in range(1, N + 1))
+    assert abs(err - g["error"]) <= 0.5e-7
+

@@ -176,3 +176,47 @@ def test_dd2_dr_keeps_the_forced_steady_state():
         assert np.abs(got - ustar).max() <= 1e-11 * np.abs(ustar).max()
         # and FIE does not (the splitting error of a Lie step)
         assert np.abs(P.fie_step(ustar, 7e-3, F=F.reshape(ny, nx)) - ustar).max() > 1e-6 * np.abs(ustar).max()
+
+
+def read_golden(name):
+    import os
+    vals = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", name)):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            k, v = (t.strip() for t in line.split("="))
+            vals[k] = float(v)
+    return vals
+
+
+def manufactured_error(n, N, s, q, beta, fine_map):
+    """Maximum over the coarse time levels of the discrete 2-norm error of the
+    fine solution of the paper's test problem (section 5)."""
+    w = W.dd2_manufactured(n=n, n_slices=N, fine_steps=s, q=q, beta=beta)
+    h = 1.0 / (n + 1)
+    u = w.u0.copy()
+    err = 0.0
+    for k in range(N):
+        u = fine_map(w, u, k)
+        ex = np.sin(2 * np.pi * (k + 1) / N) * w.extra["exact_space"]
+        err = max(err, np.sqrt(((u - ex) ** 2).sum()) * h)
+    return err
+
+
+def test_dd2_fine_error_matches_the_paper():
+    """The paper prints the error of its fine approximation for the DD-split
+    scalability runs; the oracle reproduces all printed digits."""
+    g = read_golden("dd2_fine_error_h001.txt")
+    n, N, s = int(g["n"]), int(g["n_slices"]), int(g["fine_steps"])
+    cache = {}
+
+    def fine(w, u, k):
+        if "P" not in cache:
+            cache["P"] = oracle.Problem(dim=2, nx=n, ny=n, T=1.0, n_slices=N, fine_steps=s,
+                                        split="dd", ax=np.ones((n, n + 1)),
+                                        ay=np.ones((n + 1, n)), rho=w.rho, forcing=w.forcing)
+        return cache["P"].fine(u, k)
+
+    err = manufactured_error(n, N, s, int(g["q"]), g["beta"], fine)
+    # within half a unit of the last printed digit
+    assert abs(err - g["error"]) <= 0.5e-7
