@@ -84,6 +84,53 @@ def test_dd2_dr_sequential_and_parareal():
     assert relerr(U.cpu().numpy().reshape(Uo.shape), Uo) <= TOL
 
 
+def test_dd2_one_column_strip():
+    """A colour whose support is a single node column (a strip of width 1)."""
+    nx, ny = 21, 17
+    w = W.small_dd2(nx, ny, 1, 0.2, 3, 2, seed=31)
+    rho = np.zeros((2, 2 * nx + 1))
+    rho[0] = 1.0
+    rho[1, 2 * 9 + 1] = 0.5  # node column 9 only
+    rho[0, 2 * 9 + 1] = 0.5
+    w.rho = rho
+    assert fine_parity(w) <= TOL
+    w.fine = "dr"
+    assert fine_parity(w) <= TOL
+
+
+def test_dd2_dr_three_colours_after_coefficient_update():
+    w = W.small_dd2(60, 23, 1, 0.1, 4, 2, seed=33, n_colors=3, c=0.3)
+    w.fine = "dr"
+    P = gpu_problem(w)
+    theta2 = 0.3 * W.smooth_field_2d(w.nx + 2, w.ny + 2, ell=0.25, K=5, seed=77)
+    P.set_coefficients(0, dev(theta2))
+    w.theta = theta2
+    Uin = slice_inputs(w, seed=2)
+    F = P.new_slices()
+    P.fine_propagate(dev(Uin), F)
+    torch.cuda.synchronize()
+    ref = oracle_problem(w).fine_batch(Uin)
+    assert relerr(F.cpu().numpy().reshape(ref.shape), ref) <= TOL
+
+
+def test_dd2_dr_mixed_handle():
+    a = W.small_dd2(40, 20, 2, 0.1, 4, 2, seed=41)
+    a.fine = "dr"
+    b = W.small_dim2(30, 26, 5, 3, seed=42)
+    b.fine = "dr"
+    c = W.small_dd2(33, 28, 1, 0.15, 3, 2, seed=43)
+    ws = [a, b, c]
+    P = gpu_problem(ws)
+    u0 = P.pack_u0([w.u0 for w in ws])
+    U = P.new_states()
+    k, inc = P.parareal_iterate(u0, U, k_max=2, tol=0.0)
+    torch.cuda.synchronize()
+    for i, w in enumerate(ws):
+        Uo, ko, _ = oracle_problem(w).parareal(w.u0, 2)
+        assert k[i] == ko
+        assert relerr(P.view(U, i, "states").cpu().numpy(), Uo) <= TOL
+
+
 def test_dd2_tall_strips():
     """Strips of 6 row tiles over 2100 rows: the large first-level launches take one
     workgroup per block row (two waves of row tiles)."""
