@@ -330,7 +330,7 @@ def main():
                     help="skip the parareal-to-tolerance vs sequential comparison")
     args = ap.parse_args()
     if args.gpus != 1:
-        log(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        log(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
             "(slices would shard across GPUs with one state handed forward per coarse sweep; "
             "not built).")
         sys.exit(2)

@@ -66,7 +66,7 @@ typedef enum {
   PR_ENOMEM = 2,        /* device or host allocation failed */
   PR_EDEVICE = 3,       /* a HIP call failed */
   PR_ENUMERIC = 4,      /* NaN or Inf detected in a parareal increment */
-  PR_EUNSUPPORTED = 5   /* valid request outside what this build implements */
+  PR_EUNSUPPORTED = 5   /* valid request outside what the library implements */
 } pr_status;
 
 enum { PR_SPLIT_DIM = 0, PR_SPLIT_DD = 1 };          /* section 2.1 */
