@@ -287,8 +287,7 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // unit per workgroup, the k-blocks dealt to the four waves and the partial
 // products summed through LDS (four times shorter dependent chains for
 // launches with few units). The loads of k-block kb + 1 are issued before the products of kb
-// (measured faster than deeper prefetch rings, which cost occupancy, and than
-// non-temporal loads of the factor stream).
+// (measured faster than deeper prefetch rings, which cost occupancy).
 template <int MODE, int TN>
 struct Frag {
   double a[4];
@@ -297,7 +296,7 @@ struct Frag {
 
 // Loads of k-block kb (clamped into [0, kb_end) so every address is valid; a
 // block past the end, or a row tile past nmb, contributes a zero A fragment).
-template <int MODE, int TN, bool SINGLE>
+template <int MODE, int TN, bool SINGLE, bool NT>
 __device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, long mbW,
                                           const double* X, const double* Xm, const double* Xp,
                                           const double* vb, const double* vc, int kb, int kb_end,
@@ -308,7 +307,10 @@ __device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, lo
 #pragma unroll
   for (int r = 0; r < 4; r++) {
     // the factor stream is read once: keep it out of the caches' way
-    f.a[r] = (live && r < nmb) ? A[((long)kb * mbW + r) * 64] : 0.0;
+    // the factor stream is read once (non-temporal where measured faster: launches
+    // without split-K; the split ones read their blocks in shorter pieces)
+    f.a[r] = (live && r < nmb) ? (NT ? __builtin_nontemporal_load(&A[((long)kb * mbW + r) * 64])
+                                     : A[((long)kb * mbW + r) * 64]) : 0.0;
   }
 #pragma unroll
   for (int nt = 0; nt < TN; nt++) {
@@ -377,10 +379,10 @@ __global__ __launch_bounds__(KSPLIT == 0 ? 512 : 256) void k_dd2_solve(const DD2
     const double* vb = bcp + U.bc;
     const double* vc = bcp + U.bc + W;
     Frag<MODE, TN> cur, nxt;
-    load_frag<MODE, TN, SINGLE>(cur, A, mbW, X, Xm, Xp, vb, vc, kb_lo, kb_hi, kq, cl, w, nmb, Npad);
+    load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(cur, A, mbW, X, Xm, Xp, vb, vc, kb_lo, kb_hi, kq, cl, w, nmb, Npad);
     for (int kb = kb_lo; kb < kb_hi; kb++) {
       if (kb + 1 < kb_hi)
-        load_frag<MODE, TN, SINGLE>(nxt, A, mbW, X, Xm, Xp, vb, vc, kb + 1, kb_hi, kq, cl, w, nmb, Npad);
+        load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(nxt, A, mbW, X, Xm, Xp, vb, vc, kb + 1, kb_hi, kq, cl, w, nmb, Npad);
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         if (r < nmb) {
