@@ -78,9 +78,11 @@ def dd2_strips(w):
 
 def dd2_substep_bytes(w, N):
     """Algorithmic bytes of one colour substep of the strip solver, averaged over the
-    colours: every w x w block the block cyclic reduction stores (padded to W, a
-    multiple of 16) read once, the level-0 inverses twice (forward and back), plus one
-    read and one write of every node of the colour's strips for each slice."""
+    colours: every dense w x w block the block cyclic reduction stores at levels >= 1
+    (padded to W, a multiple of 16) read once; at level 0 the LU of each eliminated
+    row read twice (3 vectors forward and back, plus its 2 coupling vectors in the
+    back substitution) and the 2 coupling vectors of each kept row; plus one read
+    and one write of every node of the colour's strips for each slice."""
     ny = w.ny
     tot = []
     for k in range(len(w.rho)):
@@ -89,14 +91,15 @@ def dd2_substep_bytes(w, N):
             if kk != k:
                 continue
             Wp = (ws + 15) // 16 * 16
-            mats = 2 * ((ny + 1) // 2)
+            mats = 0
             l = 1
             while (ny >> l) > 0:
                 n = ny >> l
                 for a in range(n):
                     mats += (1 + (a >= 1) + (a + 1 < n)) if a % 2 == 0 else (1 + (a + 1 < n))
                 l += 1
-            b += 8.0 * Wp * Wp * mats + 16.0 * ws * ny * N
+            vecs = 8 * ((ny + 1) // 2) + 2 * (ny // 2)
+            b += 8.0 * Wp * (Wp * mats + vecs) + 16.0 * ws * ny * N
         tot.append(b)
     return float(np.mean(tot))
 
@@ -452,7 +455,7 @@ def main():
                    "step": "one parareal iteration: F^s on all slices + serial coarse sweep "
                            "with correction and increment"},
         "roofline": {"bound": "hbm",
-                     "kernel": ("dd2 substep (k_dd2_solve phases + k_dd2_kup0)" if dd2 else
+                     "kernel": ("dd2 substep (k_dd2_solve phases + k_dd2_tri0 + k_dd2_kup0)" if dd2 else
                                 "dd substep (k_dd_local + k_dd_runmaps + k_dd_runscan + "
                                 "k_dd_segcarries)" if w.split == "dd" else "k_fine_sweep"),
                      "achieved": round(achieved, 1),

@@ -128,21 +128,24 @@ struct Instance {
   bool dd2 = false;
   struct Strip2 {
     int colour, col0, w, W;
-    long bc0;  // first entry of the strip's coupling vectors in the bc arrays
-    // factor-pool offsets per level l and alive row a (-1: not stored)
+    long bc0;   // first entry of the strip's coupling vectors in the bc arrays
+    long tri0;  // first entry of the strip's level-0 LU (3 W per eliminated row) in the tri arrays
+    // factor-pool offsets per level l >= 1 and alive row a (-1: not stored)
     std::vector<std::vector<long>> dinv, m2, m3, bm, cm;
   };
   std::vector<Strip2> strips2;
   struct Phase2 {
-    int mode;  // DD2_* (units) or -1 (level-0 kept rows)
+    int mode;  // DD2_APPLY / DD2_KUP / DD2_BACK (units) or DD2_KUP0 / DD2_TRI_* (level-0 rows)
     int off, cnt;
-    int split;  // see launch_dd2_solve
-    int waves;  // split 0: waves per workgroup
+    int split;   // see launch_dd2_solve (all slices)
+    int split1;  // the same for the single state
+    int waves;   // split 0: waves per workgroup
+    int wmax;   // level-0 row phases: widest row
   };
   std::vector<std::vector<Phase2>> phases2;  // per colour, in launch order
   DArr<DD2Unit> units2;
   DArr<DD2Row> rows2;
-  DBuf pool2f, pool2c, bc2f, bc2c, rho2, Zs, Ys, Y1;
+  DBuf pool2f, pool2c, bc2f, bc2c, tri2f, tri2c, rho2, Zs, Ys, Y1;
   DBuf drS2, drS1;  // Douglas-Rachford terms tau A_k U_n of colours k >= 1 (batch / single)
   int Npad2 = 16;
   // adjoint workspace (allocated on the first pr_adjoint call)
@@ -695,8 +698,10 @@ pr_status dd_fie_step(pr_problem_s* P, Instance& I, bool coarse, int which, int 
 // 2D domain decomposition (vertical strips). Strips of colour k are the maximal
 // runs of columns where rho_k is nonzero on the node or on one of its x-faces.
 
-// Factor-pool slots of one strip: every matrix the block cyclic reduction
-// stores, W x W each. Level l has n_l = ny >> l alive rows r = 2^l (a+1) - 1.
+// Factor-pool slots of one strip: every dense matrix the block cyclic
+// reduction stores, W x W each (levels >= 1; level 0 keeps the LU of its
+// tridiagonal blocks instead). Level l has n_l = ny >> l alive rows
+// r = 2^l (a+1) - 1.
 long dd2_slots(Instance::Strip2& S, int ny, long next) {
   const long sz = (long)S.W * S.W;
   S.dinv.clear(); S.m2.clear(); S.m3.clear(); S.bm.clear(); S.cm.clear();
@@ -704,11 +709,12 @@ long dd2_slots(Instance::Strip2& S, int ny, long next) {
     const int n = ny >> l;
     std::vector<long> di(n, -1), m2(n, -1), m3(n, -1), bm(n, -1), cm(n, -1);
     for (int a = 0; a < n; a++) {
+      if (l == 0) continue;
       if (a % 2 == 0) {
         di[a] = next; next += sz;
-        if (l > 0 && a >= 1) { m2[a] = next; next += sz; }
-        if (l > 0 && a + 1 < n) { m3[a] = next; next += sz; }
-      } else if (l > 0) {
+        if (a >= 1) { m2[a] = next; next += sz; }
+        if (a + 1 < n) { m3[a] = next; next += sz; }
+      } else {
         bm[a] = next; next += sz;
         if (a + 1 < n) { cm[a] = next; next += sz; }
       }
@@ -719,8 +725,12 @@ long dd2_slots(Instance::Strip2& S, int ny, long next) {
   return next;
 }
 
-// Launches with fewer units than this split each unit over a workgroup.
+// Launches with fewer units than this split each unit's k-range over the four
+// waves of a workgroup, and below kDD2Split8Units (all slices) or
+// kDD2Split8Single (single state) over eight (measured).
 constexpr int kDD2SplitUnits = 2048;
+constexpr int kDD2Split8Units = 320;
+constexpr int kDD2Split8Single = 640;
 
 // Launch schedule of one colour: forward levels (eliminated rows y = D^-1 r,
 // then kept rows r -= B y_- + C y_+), then back substitution from the top
@@ -746,7 +756,7 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
         t.nmb = t.W / 16;
         units.push_back(t);
       }
-      ph.push_back({mode, off, (int)units.size() - off, 0, (max_tiles + 3) / 4});
+      ph.push_back({mode, off, (int)units.size() - off, 0, 0, (max_tiles + 3) / 4, 0});
       return;
     }
     const int nmb = tiles4 >= 512 ? 4 : (tiles4 >= 128 ? 2 : 1);
@@ -757,25 +767,34 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
         units.push_back(t);
       }
     const int cnt = (int)units.size() - off;
-    ph.push_back({mode, off, cnt, cnt < kDD2SplitUnits ? 4 : 1, 0});
+    const int split = cnt < kDD2SplitUnits ? 4 : 1;
+    ph.push_back({mode, off, cnt, cnt < kDD2Split8Units ? 8 : split,
+                  cnt < kDD2Split8Single ? 8 : split, 0, 0});
   };
   int L = 0;
   while ((ny >> L) > 0) L++;
   for (int l = 0; l < L; l++) {
     const int n = ny >> l, st = 1 << l;
     std::vector<DD2Unit> ap, kup;
-    std::vector<DD2Row> k0;
+    std::vector<DD2Row> e0, k0;
     for (auto& S : I.strips2) {
       if (S.colour != colour) continue;
       for (int a = 0; a < n; a++) {
         const int r = st * (a + 1) - 1;
         DD2Unit u{S.col0, S.w, S.W, r, 0, 0, -1, -1, -1, -1, -1, S.bc0 + (long)r * 2 * S.W};
-        if (a % 2 == 0) {
+        if (l == 0) {
+          // level 0: row r = a, eliminated (even a, Thomas with its LU) or kept
+          DD2Row R{S.col0, S.w, S.W, r, r >= 1 ? r - 1 : -1, r + 1 < ny ? r + 1 : -1,
+                   S.bc0 + (long)r * 2 * S.W, -1};
+          if (a % 2 == 0) {
+            R.tri = S.tri0 + (long)(a / 2) * 3 * S.W;
+            e0.push_back(R);
+          } else {
+            k0.push_back(R);
+          }
+        } else if (a % 2 == 0) {
           u.A0 = S.dinv[l][a];
           ap.push_back(u);
-        } else if (l == 0) {
-          k0.push_back(DD2Row{S.col0, S.w, S.W, r, r - 1, r + 1 < ny ? r + 1 : -1,
-                              S.bc0 + (long)r * 2 * S.W});
         } else {
           u.rowm = r - st; u.A1 = S.bm[l][a];
           if (a + 1 < n) { u.rowp = r + st; u.A2 = S.cm[l][a]; }
@@ -783,33 +802,45 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
         }
       }
     }
+    auto add_rows = [&](int mode, const std::vector<DD2Row>& rs) {
+      if (rs.empty()) return;
+      int wm = 1;
+      for (auto& r : rs) wm = std::max(wm, r.w);
+      ph.push_back({mode, (int)rows.size(), (int)rs.size(), 0, 0, 0, wm});
+      rows.insert(rows.end(), rs.begin(), rs.end());
+    };
+    add_rows(DD2_TRI_APPLY, e0);
     add_units(DD2_APPLY, ap);
-    if (!k0.empty()) {
-      ph.push_back({-1, (int)rows.size(), (int)k0.size(), 0, 0});
-      rows.insert(rows.end(), k0.begin(), k0.end());
-    }
+    add_rows(DD2_KUP0, k0);
     add_units(DD2_KUP, kup);
   }
   for (int l = L - 1; l >= 0; l--) {
     const int n = ny >> l, st = 1 << l;
     std::vector<DD2Unit> bk;
+    std::vector<DD2Row> b0;
     for (auto& S : I.strips2) {
       if (S.colour != colour) continue;
       for (int a = 0; a < n; a += 2) {
         const int r = st * (a + 1) - 1;
-        DD2Unit u{S.col0, S.w, S.W, r, 0, 0, -1, -1, -1, -1, -1, S.bc0 + (long)r * 2 * S.W};
         if (l == 0) {
-          u.A0 = S.dinv[0][a];
-          u.rowm = r >= 1 ? r - 1 : -1;
-          u.rowp = r + 1 < ny ? r + 1 : -1;
-        } else {
-          if (a >= 1) { u.rowm = r - st; u.A1 = S.m2[l][a]; }
-          if (a + 1 < n) { u.rowp = r + st; u.A2 = S.m3[l][a]; }
+          b0.push_back(DD2Row{S.col0, S.w, S.W, r, r >= 1 ? r - 1 : -1, r + 1 < ny ? r + 1 : -1,
+                              S.bc0 + (long)r * 2 * S.W, S.tri0 + (long)(a / 2) * 3 * S.W});
+          continue;
         }
+        DD2Unit u{S.col0, S.w, S.W, r, 0, 0, -1, -1, -1, -1, -1, S.bc0 + (long)r * 2 * S.W};
+        if (a >= 1) { u.rowm = r - st; u.A1 = S.m2[l][a]; }
+        if (a + 1 < n) { u.rowp = r + st; u.A2 = S.m3[l][a]; }
         bk.push_back(u);
       }
     }
-    add_units(l == 0 ? DD2_BACK0 : DD2_BACK, bk);
+    if (l == 0) {
+      int wm = 1;
+      for (auto& r : b0) wm = std::max(wm, r.w);
+      ph.push_back({DD2_TRI_BACK, (int)rows.size(), (int)b0.size(), 0, 0, 0, wm});
+      rows.insert(rows.end(), b0.begin(), b0.end());
+    } else {
+      add_units(DD2_BACK, bk);
+    }
   }
   I.phases2[colour] = ph;
 }
@@ -841,11 +872,13 @@ pr_status setup_dd2_instance(Instance& I, const double* rho_host, hipStream_t s)
       i = j;
     }
   }
-  long next = 0, bcn = 0;
+  long next = 0, bcn = 0, trin = 0;
   for (auto& S : I.strips2) {
     next = dd2_slots(S, ny, next);
     S.bc0 = bcn;
     bcn += (long)ny * 2 * S.W;
+    S.tri0 = trin;
+    trin += (long)((ny + 1) / 2) * 3 * S.W;
   }
   std::vector<DD2Unit> units;
   std::vector<DD2Row> rows;
@@ -857,6 +890,8 @@ pr_status setup_dd2_instance(Instance& I, const double* rho_host, hipStream_t s)
   HIPOK(I.pool2c.alloc((size_t)std::max(1L, next)));
   HIPOK(I.bc2f.alloc((size_t)std::max(1L, bcn)));
   HIPOK(I.bc2c.alloc((size_t)std::max(1L, bcn)));
+  HIPOK(I.tri2f.alloc((size_t)std::max(1L, trin)));
+  HIPOK(I.tri2c.alloc((size_t)std::max(1L, trin)));
   HIPOK(I.rho2.alloc((size_t)K * (2 * nx + 1)));
   HIPOK(hipMemcpy(I.rho2.p, rho_host, I.rho2.n * sizeof(double), hipMemcpyHostToDevice));
   HIPOK(I.ax.alloc((size_t)ny * (nx + 1)));
@@ -924,21 +959,15 @@ pr_status factorize_dd2_instance(Instance& I, const double* coef_x, const double
     const double tau = coarse ? I.tauG : I.dt;
     double* pool = coarse ? I.pool2c.p : I.pool2f.p;
     double* bcp = coarse ? I.bc2c.p : I.bc2f.p;
+    double* trip = coarse ? I.tri2c.p : I.tri2f.p;
     for (auto& S : I.strips2) {
       const int W = S.W;
       const long w2 = (long)W * W;
       DD2Geo g{I.ax.p, I.ay.p, I.rho2.p + (long)S.colour * (2 * nx + 1), nx, ny,
                S.col0, S.w, W, 0, tau / (hx * hx), tau / (hy * hy), tau * d.c};
       HIPOK(launch_dd2_bc(g, bcp + S.bc0, s));
-      // level 0: inverses of the eliminated rows, then the level-1 blocks
-      HIPOK(launch_dd2_tri_inv(g, nE0, aug0.p, 2 * w2, s));
-      {
-        std::vector<DD2Copy> jobs;
-        for (int e = 0; e < nE0; e++)
-          jobs.push_back(DD2Copy{aug0.p + e * 2 * w2 + W, pool + S.dinv[0][2 * e], 2 * W, 0});
-        pr_status st = store(jobs, W);
-        if (st != PR_OK) return st;
-      }
+      // level 0: LU and inverses of the eliminated rows, then the level-1 blocks
+      HIPOK(launch_dd2_tri_inv(g, nE0, aug0.p, 2 * w2, trip + S.tri0, s));
       if (n1 == 0) continue;
       HIPOK(launch_dd2_scale0(g, bcp + S.bc0, aug0.p, 2 * w2, D[0].p, B[0].p, C[0].p, s));
       int cur = 0;
@@ -1002,12 +1031,18 @@ pr_status dd2_substep(pr_problem_s* P, Instance& I, bool coarse, bool single, in
   double* Y = single ? I.Y1.p : I.Ys.p;
   const int Npad = single ? 1 : I.Npad2;
   PhaseTimer pt(P, single ? PH_COARSE_X : PH_FINE, s);
+  const double* tri = coarse ? I.tri2c.p : I.tri2f.p;
   for (const auto& ph : I.phases2[colour]) {
-    if (ph.mode < 0)
-      HIPOK(launch_dd2_kup0(I.rows2.p + ph.off, ph.cnt, bc, Z, Y, I.d.nx, Npad, s));
+    const DD2Row* rows = I.rows2.p + ph.off;
+    if (ph.mode == DD2_KUP0)
+      HIPOK(launch_dd2_kup0(rows, ph.cnt, bc, Z, Y, I.d.nx, Npad, s));
+    else if (ph.mode == DD2_TRI_APPLY || ph.mode == DD2_TRI_BACK)
+      // the single state: one wave per row; all slices: one lane per (row, slice)
+      HIPOK(launch_dd2_tri0(ph.mode == DD2_TRI_BACK, rows, ph.cnt, ph.wmax, single, tri, bc, Z, Y,
+                            I.d.nx, Npad, s));
     else
-      HIPOK(launch_dd2_solve(ph.mode, I.units2.p + ph.off, ph.cnt, pool, bc, Z, Y, I.d.nx, Npad,
-                             single, ph.split, ph.waves, s));
+      HIPOK(launch_dd2_solve(ph.mode, I.units2.p + ph.off, ph.cnt, pool, Z, Y, I.d.nx, Npad,
+                             single, single ? ph.split1 : ph.split, ph.waves, s));
   }
   return PR_OK;
 }

@@ -229,13 +229,16 @@ hipError_t launch_update(const double* g, const double* F, double* G_old, double
 // l the rows alive are r = 2^l (a+1) - 1; even a are eliminated, odd a kept,
 // neighbours at distance 2^l. Per eliminated row the solve forms y = D^-1 r;
 // per kept row r -= B y_- + C y_+; going back down, x = y - M2 x_- - M3 x_+
-// with M2 = D^-1 B, M3 = D^-1 C (at level 0, where B and C are diagonal, the
-// back substitution is x = y - D^-1 (b x_- + c x_+) and the kept-row update is
-// elementwise). All these w x w matrices are precomputed per tau ("factor
-// pool") in the operand layout of the FP64 MFMA (16x16x4): element (o, k) of a
-// matrix padded to W (a multiple of 16) sits at dd2_frag(W, o, k). The solve
-// streams each matrix once per substep for all slices, which sit contiguously
-// at every grid node ("slice-minor" layout Zs[node][b], b < Npad).
+// with M2 = D^-1 B, M3 = D^-1 C. At level 0, where D is tridiagonal and B, C
+// are diagonal, y = D^-1 r and the back substitution x = y - D^-1 (b x_- +
+// c x_+) are Thomas solves with the LU of D (multipliers, reciprocal pivots and
+// back factors, 3 W doubles per row, "tri" arrays) and the kept-row update is
+// elementwise. The blocks of levels >= 1 are dense (fill-in); they are
+// precomputed per tau ("factor pool") in the operand layout of the FP64 MFMA
+// (16x16x4): element (o, k) of a matrix padded to W (a multiple of 16) sits at
+// dd2_frag(W, o, k). The solve streams each matrix once per substep for all
+// slices, which sit contiguously at every grid node ("slice-minor" layout
+// Zs[node][b], b < Npad).
 constexpr int kDD2MaxW = 1024;  // widest padded strip
 
 __host__ __device__ inline long dd2_frag(int W, int o, int k) {
@@ -251,10 +254,13 @@ struct DD2Unit {
   long bc;                   // offset of the row's coupling vectors b, c
 };
 
-// Kept row of level 0 (elementwise update r -= b y_- + c y_+).
+// Row of level 0: a kept row (elementwise update r -= b y_- + c y_+) or an
+// eliminated row (Thomas solves with its LU at tri: multipliers m, reciprocal
+// pivots ip and back factors g, W doubles each).
 struct DD2Row {
   int col0, w, W, row, rowm, rowp;
-  long bc;  // b_row at bc, c_row at bc + W
+  long bc;   // b_row at bc, c_row at bc + W
+  long tri;  // eliminated rows: offset in the tri arrays (-1 for kept rows)
 };
 
 // Strip geometry and coefficients for the set-up kernels.
@@ -280,15 +286,19 @@ struct DD2Copy {
   int ld, pad;
 };
 
-enum { DD2_APPLY = 0, DD2_KUP = 1, DD2_BACK = 2, DD2_BACK0 = 3 };
+// Solve phases: MFMA phases over units (levels >= 1), then the row phases of
+// level 0.
+enum { DD2_APPLY = 0, DD2_KUP = 1, DD2_BACK = 2, DD2_KUP0 = 3, DD2_TRI_APPLY = 4, DD2_TRI_BACK = 5 };
 
 // ---- launchers (pr_kernels_dd2.hip) ----
 // Coupling vectors of every block row: bc[r][0][o] = b_r, bc[r][1][o] = c_r
 // (zero past w, b_0 = c_{ny-1} = 0).
 hipError_t launch_dd2_bc(const DD2Geo& g, double* bc, hipStream_t s);
 // Inverses of the level-0 blocks (tridiagonal) of the eliminated rows r = 2m,
-// m < n, into columns [W, 2W) of the matrix at aug + m * mstride (row stride 2W).
-hipError_t launch_dd2_tri_inv(const DD2Geo& g, int n, double* aug, long mstride, hipStream_t s);
+// m < n, into columns [W, 2W) of the matrix at aug + m * mstride (row stride 2W),
+// and their LU (m, ip, g; 3 W doubles per row) at tri + 3 W m.
+hipError_t launch_dd2_tri_inv(const DD2Geo& g, int n, double* aug, long mstride, double* tri,
+                              hipStream_t s);
 // Gauss-Jordan on n augmented matrices [D | R] (W rows, LD columns): D -> I, R -> D^-1 R.
 hipError_t launch_dd2_gj(double* aug, long mstride, int n, int W, int LD, hipStream_t s);
 // Level-1 blocks of the level-0 kept rows r = 2a + 1 (a < ny / 2) from the
@@ -300,16 +310,24 @@ hipError_t launch_dd2_aug(const double* D, const double* B, const double* C, int
                           double* aug, hipStream_t s);
 hipError_t launch_dd2_gemm(const DD2Gemm* jobs, int n, int W, hipStream_t s);
 hipError_t launch_dd2_store(const DD2Copy* jobs, int n, int W, hipStream_t s);
-// One solve phase over a unit list (mode DD2_*), all slice columns.
+// One MFMA solve phase (DD2_APPLY, DD2_KUP or DD2_BACK) over a unit list, all slice columns.
 // single: one state in natural layout (Npad = 1). split = 0: each unit is a
 // whole block row (nmb = W/16 <= 32), one workgroup of `waves` waves (4 row
-// tiles each); 1: four units of <= 4 row tiles per workgroup; 4: one unit per
-// workgroup with its k-blocks split over four waves (launches with few units).
+// tiles each); 1: four units of <= 4 row tiles per workgroup; 4 or 8: one unit
+// per workgroup with its k-blocks split over that many waves (launches with few
+// units).
 hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const double* pool,
-                            const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
-                            int split, int waves, hipStream_t s);
+                            double* Z, double* Y, int nx, int Npad, bool single, int split,
+                            int waves, hipStream_t s);
 hipError_t launch_dd2_kup0(const DD2Row* rows, int n_rows, const double* bc, double* Z,
                            const double* Y, int nx, int Npad, hipStream_t s);
+// Level-0 eliminated rows, Thomas solves along x for every slice column:
+// back = false: Y[r] = D_r^-1 Z[r]; back = true: Z[r] = Y[r] - D_r^-1 (b_r Z[r-1] + c_r Z[r+1]).
+// wmax: widest row of the list. per_line: one wave per (row, column) line with
+// the row spread over the lanes (affine scans); otherwise one lane per line.
+hipError_t launch_dd2_tri0(bool back, const DD2Row* rows, int n_rows, int wmax, bool per_line,
+                           const double* tri, const double* bc, double* Z, double* Y, int nx,
+                           int Npad, hipStream_t s);
 // Natural [N][npts] <-> slice-minor [npts][Npad] (padding columns written as 0).
 hipError_t launch_dd2_to_sm(const double* U, double* Zs, long npts, int N, int Npad,
                             hipStream_t s);

@@ -8,6 +8,7 @@
 #include "pr_internal.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace prk {
 namespace {
@@ -64,9 +65,11 @@ __global__ void k_dd2_bc(DD2Geo g, double* __restrict__ bc) {
 // multipliers, a short recurrence in LDS) per block, then one Thomas solve per
 // column of the identity, thread per column (for a fixed row the threads write
 // consecutive entries). The inverse lands in columns [W, 2W) of the matrix at
-// aug + m * mstride (row stride 2W), where the consumers read it.
+// aug + m * mstride (row stride 2W), where the level-1 set-up reads it; the LU
+// itself (multipliers m, reciprocal pivots ip, back factors g = -sup * ip) is
+// kept at tri + 3 W m for the level-0 solves.
 __global__ __launch_bounds__(256) void k_dd2_tri_inv(DD2Geo g, double* __restrict__ aug,
-                                                     long mstride) {
+                                                     long mstride, double* __restrict__ tri) {
   __shared__ double piv[kDD2MaxW], mul[kDD2MaxW], sup[kDD2MaxW];
   const int m = blockIdx.x, r = 2 * m, W = g.W, LD = 2 * W;
   double* A = aug + m * mstride + W;
@@ -83,6 +86,13 @@ __global__ __launch_bounds__(256) void k_dd2_tri_inv(DD2Geo g, double* __restric
       piv[o] = piv[o] - f * sup[o - 1];
     }
   __syncthreads();
+  double* T = tri + (long)m * 3 * W;
+  for (int o = threadIdx.x; o < W; o += blockDim.x) {
+    const double ip = 1.0 / piv[o];
+    T[o] = mul[o];
+    T[W + o] = ip;
+    T[2 * W + o] = -sup[o] * ip;
+  }
   for (int j = threadIdx.x; j < W; j += blockDim.x) {
     double y = 0.0;
     for (int o = 0; o < W; o++) {  // forward: L y = e_j
@@ -274,7 +284,6 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 //   APPLY: Y[row] = A0 Z[row]
 //   KUP:   Z[row] = Z[row] - A1 Y[rowm] - A2 Y[rowp]
 //   BACK:  Z[row] = Y[row] - A1 Z[rowm] - A2 Z[rowp]
-//   BACK0: Z[row] = Y[row] - A0 (b_row Z[rowm] + c_row Z[rowp])
 // v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16] and X[l / 16][l % 16]
 // and holds D[4 v + l / 16][l % 16] in accumulator register v. Pool matrices
 // are stored in exactly that A order, so each (k-block, row tile) fragment is
@@ -283,11 +292,12 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // (Npad = 1) feed zeros into the 15 unused columns.
 // KSPLIT = 0: one block row per workgroup, wave i taking its row tiles
 // [4i, 4i + 4) (the waves share the row's right-hand sides through the CU's
-// cache). KSPLIT = 1: four units per workgroup, one per wave. KSPLIT = 4: one
-// unit per workgroup, the k-blocks dealt to the four waves and the partial
-// products summed through LDS (four times shorter dependent chains for
-// launches with few units). The loads of k-block kb + 1 are issued before the products of kb
-// (measured faster than deeper prefetch rings, which cost occupancy).
+// cache). KSPLIT = 1: four units per workgroup, one per wave. KSPLIT = 4 or 8:
+// one unit per workgroup, the k-blocks dealt to KSPLIT waves and the partial
+// products summed through LDS in a tree (KSPLIT times shorter dependent chains
+// for launches with few units). The loads of k-block kb + 1 are issued before
+// the products of kb (measured faster than deeper prefetch rings, which cost
+// occupancy).
 template <int MODE, int TN>
 struct Frag {
   double a[4];
@@ -298,9 +308,8 @@ struct Frag {
 // block past the end, or a row tile past nmb, contributes a zero A fragment).
 template <int MODE, int TN, bool SINGLE, bool NT>
 __device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, long mbW,
-                                          const double* X, const double* Xm, const double* Xp,
-                                          const double* vb, const double* vc, int kb, int kb_end,
-                                          int kq, int cl, int w, int nmb, int Npad) {
+                                          const double* X, int kb, int kb_end, int kq, int cl,
+                                          int w, int nmb, int Npad) {
   const bool live = kb < kb_end;
   kb = min(kb, kb_end - 1);
   const int k = min(kb * 4 + kq, w - 1);
@@ -315,22 +324,14 @@ __device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, lo
 #pragma unroll
   for (int nt = 0; nt < TN; nt++) {
     const long xo = SINGLE ? (long)k : (long)k * Npad + nt * 16;
-    double v;
-    if (MODE == DD2_BACK0) {
-      const double zm = Xm[xo];
-      const double zp = Xp[xo];
-      v = vb[k] * zm + vc[k] * zp;
-    } else {
-      v = X[xo];
-    }
+    const double v = X[xo];
     f.x[nt] = (SINGLE && cl != 0) ? 0.0 : v;
   }
 }
 
 template <int MODE, int TN, bool SINGLE, int KSPLIT>
-__global__ __launch_bounds__(KSPLIT == 0 ? 512 : 256) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
+__global__ __launch_bounds__(KSPLIT == 0 || KSPLIT == 8 ? 512 : 256) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
                                                    const double* __restrict__ pool,
-                                                   const double* __restrict__ bcp,
                                                    double* __restrict__ Z, double* __restrict__ Y,
                                                    int nx, int Npad, int b0) {
   const int lane = threadIdx.x % kWave;
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(KSPLIT == 0 ? 512 : 256) void k_dd2_solve(const DD2
   // live in scalar registers and its guards are scalar branches
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int u = KSPLIT == 1 ? blockIdx.x * 4 + wave : blockIdx.x;
-  if (u >= n_units) return;  // no barrier follows for KSPLIT <= 1; KSPLIT = 4 units are whole
+  if (u >= n_units) return;  // no barrier follows for KSPLIT <= 1; split units are whole workgroups
   const DD2Unit U = units[u];
   const int W = U.W, w = U.w;
   // KSPLIT = 0: the unit is a whole block row; wave i takes its row tiles [4i, 4i + 4)
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(KSPLIT == 0 ? 512 : 256) void k_dd2_solve(const DD2
   for (int term = 0; term < n_terms; term++) {
     long aoff;
     int rx;
-    if (MODE == DD2_APPLY || MODE == DD2_BACK0) {
+    if (MODE == DD2_APPLY) {
       aoff = U.A0; rx = U.row;
     } else {
       aoff = term == 0 ? U.A1 : U.A2;
@@ -372,17 +373,11 @@ __global__ __launch_bounds__(KSPLIT == 0 ? 512 : 256) void k_dd2_solve(const DD2
     const double* Xb = (MODE == DD2_KUP) ? Y : Z;
     const double* A = pool + aoff + (long)mb0 * 64 + lane;
     const double* X = Xb + ((long)rx * nx + U.col0) * Npad + col_off;
-    // BACK0: X = b_row * Z[rowm] + c_row * Z[rowp]; a missing neighbour reads
-    // the row itself with a zero coupling (b_0 = c_{ny-1} = 0)
-    const double* Xm = Z + ((long)(U.rowm >= 0 ? U.rowm : U.row) * nx + U.col0) * Npad + col_off;
-    const double* Xp = Z + ((long)(U.rowp >= 0 ? U.rowp : U.row) * nx + U.col0) * Npad + col_off;
-    const double* vb = bcp + U.bc;
-    const double* vc = bcp + U.bc + W;
     Frag<MODE, TN> cur, nxt;
-    load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(cur, A, mbW, X, Xm, Xp, vb, vc, kb_lo, kb_hi, kq, cl, w, nmb, Npad);
+    load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(cur, A, mbW, X, kb_lo, kb_hi, kq, cl, w, nmb, Npad);
     for (int kb = kb_lo; kb < kb_hi; kb++) {
       if (kb + 1 < kb_hi)
-        load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(nxt, A, mbW, X, Xm, Xp, vb, vc, kb + 1, kb_hi, kq, cl, w, nmb, Npad);
+        load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(nxt, A, mbW, X, kb + 1, kb_hi, kq, cl, w, nmb, Npad);
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         if (r < nmb) {
@@ -395,28 +390,34 @@ __global__ __launch_bounds__(KSPLIT == 0 ? 512 : 256) void k_dd2_solve(const DD2
     }
   }
   if (KSPLIT > 1) {
-    // waves 1..3 leave their partial products in LDS; wave 0 adds them
-    __shared__ double part[(KSPLIT > 1 ? KSPLIT - 1 : 1) * 4 * TN * 4 * kWave];
-    if (wave > 0) {
-#pragma unroll
-      for (int r = 0; r < 4; r++)
-#pragma unroll
-        for (int nt = 0; nt < TN; nt++)
-#pragma unroll
-          for (int v = 0; v < 4; v++)
-            part[((((wave - 1) * 4 + r) * TN + nt) * 4 + v) * kWave + lane] = acc[r][nt][v];
-    }
-    __syncthreads();
-    if (wave > 0) return;
+    // tree over the waves: at each stage waves [half, 2 half) leave their
+    // partial products in LDS and waves [0, half) add them
+    constexpr int kSlots = KSPLIT > 1 ? KSPLIT / 2 : 1;
+    __shared__ double part[kSlots * 4 * TN * 4 * kWave];
 #pragma unroll 1
-    for (int q = 0; q < KSPLIT - 1; q++)
+    for (int half = KSPLIT / 2; half >= 1; half >>= 1) {
+      if (wave >= half && wave < 2 * half) {
 #pragma unroll
-      for (int r = 0; r < 4; r++)
+        for (int r = 0; r < 4; r++)
 #pragma unroll
-        for (int nt = 0; nt < TN; nt++)
+          for (int nt = 0; nt < TN; nt++)
 #pragma unroll
-          for (int v = 0; v < 4; v++)
-            acc[r][nt][v] += part[(((q * 4 + r) * TN + nt) * 4 + v) * kWave + lane];
+            for (int v = 0; v < 4; v++)
+              part[((((wave - half) * 4 + r) * TN + nt) * 4 + v) * kWave + lane] = acc[r][nt][v];
+      }
+      __syncthreads();
+      if (wave < half) {
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+          for (int nt = 0; nt < TN; nt++)
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+              acc[r][nt][v] += part[(((wave * 4 + r) * TN + nt) * 4 + v) * kWave + lane];
+      }
+      __syncthreads();
+    }
+    if (wave > 0) return;
   }
 #pragma unroll
   for (int r = 0; r < 4; r++) {
@@ -455,6 +456,179 @@ __global__ void k_dd2_kup0(const DD2Row* __restrict__ rows, const double* __rest
     double v = Z[base + t] - vb[o] * Y[bm + t];
     if (bp >= 0) v = v - vc[o] * Y[bp + t];
     Z[base + t] = v;
+  }
+}
+
+// Level-0 eliminated rows: D_r is tridiagonal in x, so its solves are Thomas
+// sweeps with the stored LU (z_o = rhs_o - m_o z_{o-1}, then
+// x_o = ip_o z_o + g_o x_{o+1}) along each line (row, slice column):
+//   BACK = false: Y[r] = D_r^-1 Z[r]
+//   BACK = true:  Z[r] = Y[r] - D_r^-1 (b_r Z[r-1] + c_r Z[r+1])
+// A missing neighbour row reads y of the row itself against a zero coupling.
+
+// One lane per line: the row is walked in chunks of kTriChunk positions whose
+// loads are issued together; the forward values are stored in the output row
+// and read back by the backward sweep of the same lane. The lanes of a row read
+// the same LU entries (one request per wave and address).
+constexpr int kTriChunk = 16;
+
+template <bool BACK>
+__global__ __launch_bounds__(64) void k_dd2_tri0(const DD2Row* __restrict__ rows, int n_rows,
+                                                 const double* __restrict__ tri,
+                                                 const double* __restrict__ bcp,
+                                                 double* __restrict__ Z, double* __restrict__ Y,
+                                                 int nx, int Npad) {
+  const long t = blockIdx.x * (long)kWave + threadIdx.x;
+  if (t >= (long)n_rows * Npad) return;
+  const DD2Row R = rows[t / Npad];
+  const int b = (int)(t % Npad), w = R.w;
+  const long sp = Npad;  // stride between consecutive columns of a row
+  const double* fm = tri + R.tri;
+  const double* fip = fm + R.W;
+  const double* fg = fm + 2 * R.W;
+  const long own = ((long)R.row * nx + R.col0) * Npad + b;
+  double* out = (BACK ? Z : Y) + own;
+  const double* src = Z + own;     // forward input without coupling (BACK = false)
+  const double* yr = Y + own;      // y of the row (BACK = true)
+  const double* zm = R.rowm >= 0 ? Z + ((long)R.rowm * nx + R.col0) * Npad + b : yr;
+  const double* zp = R.rowp >= 0 ? Z + ((long)R.rowp * nx + R.col0) * Npad + b : yr;
+  const double* vb = bcp + R.bc;
+  const double* vc = vb + R.W;
+  double z = 0.0;
+  for (int c0 = 0; c0 < w; c0 += kTriChunk) {
+    double v[kTriChunk], mm[kTriChunk];
+#pragma unroll
+    for (int j = 0; j < kTriChunk; j++) {
+      const int o = min(c0 + j, w - 1);  // clamped: past the end nothing is stored
+      mm[j] = fm[o];
+      v[j] = BACK ? vb[o] * zm[o * sp] + vc[o] * zp[o * sp] : src[o * sp];
+    }
+#pragma unroll
+    for (int j = 0; j < kTriChunk; j++) {
+      z = v[j] - mm[j] * z;
+      if (c0 + j < w) out[(c0 + j) * sp] = z;
+    }
+  }
+  double x = 0.0;
+  for (int c1 = w; c1 > 0; c1 -= kTriChunk) {  // positions c1 - 1, c1 - 2, ...
+    double zz[kTriChunk], ii[kTriChunk], gg[kTriChunk], yy[kTriChunk];
+#pragma unroll
+    for (int j = 0; j < kTriChunk; j++) {
+      const int o = max(c1 - 1 - j, 0);
+      zz[j] = out[o * sp];
+      ii[j] = fip[o];
+      gg[j] = fg[o];
+      yy[j] = BACK ? yr[o * sp] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kTriChunk; j++) {
+      x = ii[j] * zz[j] + gg[j] * x;
+      if (c1 - 1 - j >= 0) out[(c1 - 1 - j) * sp] = BACK ? yy[j] - x : x;
+    }
+  }
+}
+
+// Inclusive scans over the 64 lanes of the affine maps v -> a v + b: upwards
+// lane i ends with f_i o ... o f_0, downwards with f_i o f_{i+1} o ... o f_63.
+__device__ __forceinline__ void tri_scan_up(double& a, double& b, int lane) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double ap = __shfl_up(a, off, kWave);
+    const double bp = __shfl_up(b, off, kWave);
+    if (lane >= off) {
+      b = fma(a, bp, b);
+      a = a * ap;
+    }
+  }
+}
+
+__device__ __forceinline__ void tri_scan_down(double& a, double& b, int lane) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double an = __shfl_down(a, off, kWave);
+    const double bn = __shfl_down(b, off, kWave);
+    if (lane + off < kWave) {
+      b = fma(a, bn, b);
+      a = a * an;
+    }
+  }
+}
+
+// One wave per line: lane l holds positions [l K, l K + K) in registers (all
+// loads of the line in flight together). Each sweep composes the lane's affine
+// maps, scans them over the lanes to get the value entering the lane, and
+// re-runs its positions from it. Positions past the row end carry zero maps
+// (m = ip = g = 0), and g = 0 at the last position, so nothing crosses the end.
+template <bool BACK, int K>
+__global__ __launch_bounds__(256) void k_dd2_tri0w(const DD2Row* __restrict__ rows, int n_lines,
+                                                   const double* __restrict__ tri,
+                                                   const double* __restrict__ bcp,
+                                                   double* __restrict__ Z, double* __restrict__ Y,
+                                                   int nx, int Npad) {
+  const int lane = threadIdx.x % kWave;
+  const int line = (int)blockIdx.x * (blockDim.x / kWave) +
+                   __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (line >= n_lines) return;
+  const DD2Row R = rows[line / Npad];
+  const int b = line % Npad, w = R.w;
+  const long sp = Npad;
+  const double* fm = tri + R.tri;
+  const double* fip = fm + R.W;
+  const double* fg = fm + 2 * R.W;
+  const long own = ((long)R.row * nx + R.col0) * Npad + b;
+  double* out = (BACK ? Z : Y) + own;
+  const double* src = Z + own;
+  const double* yr = Y + own;
+  const double* zm = R.rowm >= 0 ? Z + ((long)R.rowm * nx + R.col0) * Npad + b : yr;
+  const double* zp = R.rowp >= 0 ? Z + ((long)R.rowp * nx + R.col0) * Npad + b : yr;
+  const double* vb = bcp + R.bc;
+  const double* vc = vb + R.W;
+  double v[K], mm[K], ii[K], gg[K], yy[K];
+#pragma unroll
+  for (int j = 0; j < K; j++) {
+    const int p = lane * K + j;
+    const bool in = p < w;
+    const int pc = in ? p : w - 1;  // loads stay unconditional and in range
+    const double m = fm[pc], ip = fip[pc], g = fg[pc];
+    const double r = BACK ? vb[pc] * zm[pc * sp] + vc[pc] * zp[pc * sp] : src[pc * sp];
+    const double y = BACK ? yr[pc * sp] : 0.0;
+    mm[j] = in ? m : 0.0;
+    ii[j] = in ? ip : 0.0;
+    gg[j] = in ? g : 0.0;
+    v[j] = in ? r : 0.0;
+    yy[j] = y;
+  }
+  // forward: z_p = v_p - m_p z_{p-1}
+  double A = 1.0, B = 0.0;
+#pragma unroll
+  for (int j = 0; j < K; j++) {
+    B = fma(-mm[j], B, v[j]);
+    A = -mm[j] * A;
+  }
+  tri_scan_up(A, B, lane);
+  double z = __shfl_up(B, 1, kWave);
+  if (lane == 0) z = 0.0;
+#pragma unroll
+  for (int j = 0; j < K; j++) {
+    z = fma(-mm[j], z, v[j]);
+    v[j] = z;
+  }
+  // backward: x_p = ip_p z_p + g_p x_{p+1}
+  A = 1.0;
+  B = 0.0;
+#pragma unroll
+  for (int j = K - 1; j >= 0; j--) {
+    B = fma(gg[j], B, ii[j] * v[j]);
+    A = gg[j] * A;
+  }
+  tri_scan_down(A, B, lane);
+  double x = __shfl_down(B, 1, kWave);
+  if (lane == kWave - 1) x = 0.0;
+#pragma unroll
+  for (int j = K - 1; j >= 0; j--) {
+    x = fma(gg[j], x, ii[j] * v[j]);
+    const int p = lane * K + j;
+    if (p < w) out[p * sp] = BACK ? yy[j] - x : x;
   }
 }
 
@@ -564,10 +738,11 @@ hipError_t launch_dd2_gj(double* aug, long mstride, int n, int W, int LD, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_dd2_tri_inv(const DD2Geo& g, int n, double* aug, long mstride, hipStream_t s) {
+hipError_t launch_dd2_tri_inv(const DD2Geo& g, int n, double* aug, long mstride, double* tri,
+                              hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (g.W > kDD2MaxW) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dd2_tri_inv, dim3(n), dim3(256), 0, s, g, aug, mstride);
+  hipLaunchKernelGGL(k_dd2_tri_inv, dim3(n), dim3(256), 0, s, g, aug, mstride, tri);
   return hipGetLastError();
 }
 
@@ -604,29 +779,27 @@ hipError_t launch_dd2_store(const DD2Copy* jobs, int n, int W, hipStream_t s) {
 
 namespace {
 template <int MODE, bool SINGLE, int KSPLIT>
-hipError_t solve_tn(int tn, const DD2Unit* units, int n_units, const double* pool,
-                    const double* bc, double* Z, double* Y, int nx, int Npad, int b0, int waves,
-                    hipStream_t s) {
+hipError_t solve_tn(int tn, const DD2Unit* units, int n_units, const double* pool, double* Z,
+                    double* Y, int nx, int Npad, int b0, int waves, hipStream_t s) {
   const dim3 grid(KSPLIT == 1 ? (n_units + 3) / 4 : n_units),
-      block(KSPLIT == 0 ? kWave * waves : 256);
+      block(KSPLIT == 0 ? kWave * waves : (KSPLIT == 1 ? 4 * kWave : KSPLIT * kWave));
   switch (tn) {
-    case 1: hipLaunchKernelGGL((k_dd2_solve<MODE, 1, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
-    case 2: hipLaunchKernelGGL((k_dd2_solve<MODE, 2, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
-    case 3: hipLaunchKernelGGL((k_dd2_solve<MODE, 3, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
-    default: hipLaunchKernelGGL((k_dd2_solve<MODE, 4, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, bc, Z, Y, nx, Npad, b0); break;
+    case 1: hipLaunchKernelGGL((k_dd2_solve<MODE, 1, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
+    case 2: hipLaunchKernelGGL((k_dd2_solve<MODE, 2, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
+    case 3: hipLaunchKernelGGL((k_dd2_solve<MODE, 3, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
+    default: hipLaunchKernelGGL((k_dd2_solve<MODE, 4, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
   }
   return hipGetLastError();
 }
 
 template <int MODE, int KSPLIT>
-hipError_t solve_mode(const DD2Unit* units, int n_units, const double* pool, const double* bc,
-                      double* Z, double* Y, int nx, int Npad, bool single, int waves,
-                      hipStream_t s) {
+hipError_t solve_mode(const DD2Unit* units, int n_units, const double* pool, double* Z,
+                      double* Y, int nx, int Npad, bool single, int waves, hipStream_t s) {
   if (single)
-    return solve_tn<MODE, true, KSPLIT>(1, units, n_units, pool, bc, Z, Y, nx, 1, 0, waves, s);
+    return solve_tn<MODE, true, KSPLIT>(1, units, n_units, pool, Z, Y, nx, 1, 0, waves, s);
   for (int b0 = 0; b0 < Npad; b0 += 64) {
     const int tn = std::min(4, (Npad - b0) / 16);
-    hipError_t e = solve_tn<MODE, false, KSPLIT>(tn, units, n_units, pool, bc, Z, Y, nx, Npad, b0,
+    hipError_t e = solve_tn<MODE, false, KSPLIT>(tn, units, n_units, pool, Z, Y, nx, Npad, b0,
                                                  waves, s);
     if (e != hipSuccess) return e;
   }
@@ -635,35 +808,73 @@ hipError_t solve_mode(const DD2Unit* units, int n_units, const double* pool, con
 
 template <int KSPLIT>
 hipError_t solve_split(int mode, const DD2Unit* units, int n_units, const double* pool,
-                       const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
-                       int waves, hipStream_t s) {
+                       double* Z, double* Y, int nx, int Npad, bool single, int waves,
+                       hipStream_t s) {
   switch (mode) {
-    case DD2_APPLY: return solve_mode<DD2_APPLY, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, waves, s);
-    case DD2_KUP: return solve_mode<DD2_KUP, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, waves, s);
-    case DD2_BACK: return solve_mode<DD2_BACK, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, waves, s);
-    case DD2_BACK0: return solve_mode<DD2_BACK0, KSPLIT>(units, n_units, pool, bc, Z, Y, nx, Npad, single, waves, s);
+    case DD2_APPLY: return solve_mode<DD2_APPLY, KSPLIT>(units, n_units, pool, Z, Y, nx, Npad, single, waves, s);
+    case DD2_KUP: return solve_mode<DD2_KUP, KSPLIT>(units, n_units, pool, Z, Y, nx, Npad, single, waves, s);
+    case DD2_BACK: return solve_mode<DD2_BACK, KSPLIT>(units, n_units, pool, Z, Y, nx, Npad, single, waves, s);
     default: return hipErrorInvalidValue;
   }
 }
 }  // namespace
 
 hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const double* pool,
-                            const double* bc, double* Z, double* Y, int nx, int Npad, bool single,
-                            int split, int waves, hipStream_t s) {
+                            double* Z, double* Y, int nx, int Npad, bool single, int split,
+                            int waves, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   if (!single && Npad % 16 != 0) return hipErrorInvalidValue;
-  if (split == 4) return solve_split<4>(mode, units, n_units, pool, bc, Z, Y, nx, Npad, single, 0, s);
+  if (split == 8) return solve_split<8>(mode, units, n_units, pool, Z, Y, nx, Npad, single, 0, s);
+  if (split == 4) return solve_split<4>(mode, units, n_units, pool, Z, Y, nx, Npad, single, 0, s);
   if (split == 0) {
     if (waves < 1 || waves > 8) return hipErrorInvalidValue;
-    return solve_split<0>(mode, units, n_units, pool, bc, Z, Y, nx, Npad, single, waves, s);
+    return solve_split<0>(mode, units, n_units, pool, Z, Y, nx, Npad, single, waves, s);
   }
-  return solve_split<1>(mode, units, n_units, pool, bc, Z, Y, nx, Npad, single, 0, s);
+  return solve_split<1>(mode, units, n_units, pool, Z, Y, nx, Npad, single, 0, s);
 }
 
 hipError_t launch_dd2_kup0(const DD2Row* rows, int n_rows, const double* bc, double* Z,
                            const double* Y, int nx, int Npad, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_dd2_kup0, dim3(n_rows), dim3(256), 0, s, rows, bc, Z, Y, nx, Npad);
+  return hipGetLastError();
+}
+
+namespace {
+template <bool BACK>
+hipError_t tri0_wave(int K, const DD2Row* rows, int n_lines, const double* tri, const double* bc,
+                     double* Z, double* Y, int nx, int Npad, hipStream_t s) {
+  const dim3 grid((unsigned)((n_lines + 3) / 4)), block(4 * kWave);
+  switch (K) {
+    case 1: hipLaunchKernelGGL((k_dd2_tri0w<BACK, 1>), grid, block, 0, s, rows, n_lines, tri, bc, Z, Y, nx, Npad); break;
+    case 2: hipLaunchKernelGGL((k_dd2_tri0w<BACK, 2>), grid, block, 0, s, rows, n_lines, tri, bc, Z, Y, nx, Npad); break;
+    case 4: hipLaunchKernelGGL((k_dd2_tri0w<BACK, 4>), grid, block, 0, s, rows, n_lines, tri, bc, Z, Y, nx, Npad); break;
+    case 8: hipLaunchKernelGGL((k_dd2_tri0w<BACK, 8>), grid, block, 0, s, rows, n_lines, tri, bc, Z, Y, nx, Npad); break;
+    case 16: hipLaunchKernelGGL((k_dd2_tri0w<BACK, 16>), grid, block, 0, s, rows, n_lines, tri, bc, Z, Y, nx, Npad); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_dd2_tri0(bool back, const DD2Row* rows, int n_rows, int wmax, bool per_line,
+                           const double* tri, const double* bc, double* Z, double* Y, int nx,
+                           int Npad, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  if (Npad < 1 || wmax < 1 || wmax > kDD2MaxW) return hipErrorInvalidValue;
+  const long lines = (long)n_rows * Npad;
+  if (lines > INT_MAX) return hipErrorInvalidValue;
+  if (per_line) {
+    int K = 1;
+    while (K * kWave < wmax) K *= 2;
+    return back ? tri0_wave<true>(K, rows, (int)lines, tri, bc, Z, Y, nx, Npad, s)
+                : tri0_wave<false>(K, rows, (int)lines, tri, bc, Z, Y, nx, Npad, s);
+  }
+  const dim3 grid((unsigned)((lines + kWave - 1) / kWave)), block(kWave);
+  if (back)
+    hipLaunchKernelGGL(k_dd2_tri0<true>, grid, block, 0, s, rows, n_rows, tri, bc, Z, Y, nx, Npad);
+  else
+    hipLaunchKernelGGL(k_dd2_tri0<false>, grid, block, 0, s, rows, n_rows, tri, bc, Z, Y, nx, Npad);
   return hipGetLastError();
 }
 
