@@ -298,6 +298,10 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // for launches with few units). The loads of k-block kb + 1 are issued before
 // the products of kb (measured faster than deeper prefetch rings, which cost
 // occupancy).
+// k-blocks loaded ahead in the whole-row launches (KSPLIT = 0), whose grids
+// leave room for the extra registers; the split launches keep one.
+constexpr int kRowPrefetch = 2;
+
 template <int MODE, int TN>
 struct Frag {
   double a[4];
@@ -373,20 +377,25 @@ __global__ __launch_bounds__(KSPLIT == 0 || KSPLIT == 8 ? 512 : 256) void k_dd2_
     const double* Xb = (MODE == DD2_KUP) ? Y : Z;
     const double* A = pool + aoff + (long)mb0 * 64 + lane;
     const double* X = Xb + ((long)rx * nx + U.col0) * Npad + col_off;
-    Frag<MODE, TN> cur, nxt;
-    load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(cur, A, mbW, X, kb_lo, kb_hi, kq, cl, w, nmb, Npad);
+    // ring of PF k-blocks in flight ahead of the one being multiplied
+    constexpr int PF = KSPLIT == 0 ? kRowPrefetch : 1;
+    Frag<MODE, TN> ring[PF + 1];
+#pragma unroll
+    for (int q = 0; q < PF; q++)
+      load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(ring[q], A, mbW, X, kb_lo + q, kb_hi, kq, cl, w, nmb, Npad);
     for (int kb = kb_lo; kb < kb_hi; kb++) {
-      if (kb + 1 < kb_hi)
-        load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(nxt, A, mbW, X, kb + 1, kb_hi, kq, cl, w, nmb, Npad);
+      if (kb + PF < kb_hi)
+        load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(ring[PF], A, mbW, X, kb + PF, kb_hi, kq, cl, w, nmb, Npad);
 #pragma unroll
       for (int r = 0; r < 4; r++) {
         if (r < nmb) {
 #pragma unroll
           for (int nt = 0; nt < TN; nt++)
-            acc[r][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.a[r], cur.x[nt], acc[r][nt], 0, 0, 0);
+            acc[r][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[0].a[r], ring[0].x[nt], acc[r][nt], 0, 0, 0);
         }
       }
-      cur = nxt;
+#pragma unroll
+      for (int q = 0; q < PF; q++) ring[q] = ring[q + 1];
     }
   }
   if (KSPLIT > 1) {
