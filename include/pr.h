@@ -102,8 +102,8 @@ enum { PR_COEF_FACES = 0, PR_COEF_NODAL_LOG = 1 };
  *                  rho_k > 0 on the node or on one of its x-faces, each one
  *                  independent 5-point system (at most 1024 columns wide),
  *                  solved exactly by block cyclic reduction in y with
- *                  precomputed w x w blocks: about 3 ny w^2 doubles of device
- *                  memory per strip and step size.
+ *                  precomputed w x w blocks: about 2.5 ny w^2 doubles of
+ *                  device memory per strip and step size.
  *   n_forcing      number of separable source terms, 0..PR_MAX_FORCING: the
  *                  source of eq. FIE_method / eq. DR_method (homogeneous
  *                  boundary data) is F(t) = sum_m g_m(t) S_m, and tau F at the
