@@ -726,11 +726,14 @@ long dd2_slots(Instance::Strip2& S, int ny, long next) {
 }
 
 // Launches with fewer units than this split each unit's k-range over the four
-// waves of a workgroup, and below kDD2Split8Units (all slices) or
-// kDD2Split8Single (single state) over eight (measured).
+// waves of a workgroup, below kDD2Split8Units (all slices) or kDD2Split8Single
+// (single state) over eight, and below the Split16 counts over sixteen
+// (measured).
 constexpr int kDD2SplitUnits = 2048;
 constexpr int kDD2Split8Units = 320;
 constexpr int kDD2Split8Single = 640;
+constexpr int kDD2Split16Units = 160;
+constexpr int kDD2Split16Single = 320;
 
 // Launch schedule of one colour: forward levels (eliminated rows y = D^-1 r,
 // then kept rows r -= B y_- + C y_+), then back substitution from the top
@@ -768,8 +771,9 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
       }
     const int cnt = (int)units.size() - off;
     const int split = cnt < kDD2SplitUnits ? 4 : 1;
-    ph.push_back({mode, off, cnt, cnt < kDD2Split8Units ? 8 : split,
-                  cnt < kDD2Split8Single ? 8 : split, 0, 0});
+    ph.push_back({mode, off, cnt,
+                  cnt < kDD2Split16Units ? 16 : (cnt < kDD2Split8Units ? 8 : split),
+                  cnt < kDD2Split16Single ? 16 : (cnt < kDD2Split8Single ? 8 : split), 0, 0});
   };
   int L = 0;
   while ((ny >> L) > 0) L++;

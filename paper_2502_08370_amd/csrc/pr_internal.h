@@ -313,9 +313,9 @@ hipError_t launch_dd2_store(const DD2Copy* jobs, int n, int W, hipStream_t s);
 // One MFMA solve phase (DD2_APPLY, DD2_KUP or DD2_BACK) over a unit list, all slice columns.
 // single: one state in natural layout (Npad = 1). split = 0: each unit is a
 // whole block row (nmb = W/16 <= 32), one workgroup of `waves` waves (4 row
-// tiles each); 1: four units of <= 4 row tiles per workgroup; 4 or 8: one unit
-// per workgroup with its k-blocks split over that many waves (launches with few
-// units).
+// tiles each); 1: four units of <= 4 row tiles per workgroup; 4, 8 or 16: one
+// unit per workgroup with its k-blocks split over that many waves (launches with
+// few units; 16 is taken as 8 for more than two column tiles).
 hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const double* pool,
                             double* Z, double* Y, int nx, int Npad, bool single, int split,
                             int waves, hipStream_t s);

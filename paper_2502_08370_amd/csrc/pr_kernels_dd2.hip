@@ -292,8 +292,8 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // (Npad = 1) feed zeros into the 15 unused columns.
 // KSPLIT = 0: one block row per workgroup, wave i taking its row tiles
 // [4i, 4i + 4) (the waves share the row's right-hand sides through the CU's
-// cache). KSPLIT = 1: four units per workgroup, one per wave. KSPLIT = 4 or 8:
-// one unit per workgroup, the k-blocks dealt to KSPLIT waves and the partial
+// cache). KSPLIT = 1: four units per workgroup, one per wave. KSPLIT = 4, 8 or
+// 16: one unit per workgroup, the k-blocks dealt to KSPLIT waves and the partial
 // products summed through LDS in a tree (KSPLIT times shorter dependent chains
 // for launches with few units). The loads of k-block kb + 1 are issued before
 // the products of kb (measured faster than deeper prefetch rings, which cost
@@ -334,7 +334,7 @@ __device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, lo
 }
 
 template <int MODE, int TN, bool SINGLE, int KSPLIT>
-__global__ __launch_bounds__(KSPLIT == 0 || KSPLIT == 8 ? 512 : 256) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
+__global__ __launch_bounds__(KSPLIT == 16 ? 1024 : (KSPLIT == 0 || KSPLIT == 8 ? 512 : 256)) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
                                                    const double* __restrict__ pool,
                                                    double* __restrict__ Z, double* __restrict__ Y,
                                                    int nx, int Npad, int b0) {
@@ -792,13 +792,24 @@ hipError_t solve_tn(int tn, const DD2Unit* units, int n_units, const double* poo
                     double* Y, int nx, int Npad, int b0, int waves, hipStream_t s) {
   const dim3 grid(KSPLIT == 1 ? (n_units + 3) / 4 : n_units),
       block(KSPLIT == 0 ? kWave * waves : (KSPLIT == 1 ? 4 * kWave : KSPLIT * kWave));
-  switch (tn) {
-    case 1: hipLaunchKernelGGL((k_dd2_solve<MODE, 1, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
-    case 2: hipLaunchKernelGGL((k_dd2_solve<MODE, 2, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
-    case 3: hipLaunchKernelGGL((k_dd2_solve<MODE, 3, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
-    default: hipLaunchKernelGGL((k_dd2_solve<MODE, 4, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
+  if constexpr (KSPLIT == 16) {
+    // sixteen waves leave 128 registers per lane and 160 KB of LDS: enough for
+    // at most two column tiles; wider launches split eight ways
+    if (tn > 2) return solve_tn<MODE, SINGLE, 8>(tn, units, n_units, pool, Z, Y, nx, Npad, b0, 0, s);
+    if (tn == 1)
+      hipLaunchKernelGGL((k_dd2_solve<MODE, 1, SINGLE, 16>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0);
+    else
+      hipLaunchKernelGGL((k_dd2_solve<MODE, 2, SINGLE, 16>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0);
+    return hipGetLastError();
+  } else {
+    switch (tn) {
+      case 1: hipLaunchKernelGGL((k_dd2_solve<MODE, 1, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
+      case 2: hipLaunchKernelGGL((k_dd2_solve<MODE, 2, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
+      case 3: hipLaunchKernelGGL((k_dd2_solve<MODE, 3, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
+      default: hipLaunchKernelGGL((k_dd2_solve<MODE, 4, SINGLE, KSPLIT>), grid, block, 0, s, units, n_units, pool, Z, Y, nx, Npad, b0); break;
+    }
+    return hipGetLastError();
   }
-  return hipGetLastError();
 }
 
 template <int MODE, int KSPLIT>
@@ -833,6 +844,7 @@ hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const d
                             int waves, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   if (!single && Npad % 16 != 0) return hipErrorInvalidValue;
+  if (split == 16) return solve_split<16>(mode, units, n_units, pool, Z, Y, nx, Npad, single, 0, s);
   if (split == 8) return solve_split<8>(mode, units, n_units, pool, Z, Y, nx, Npad, single, 0, s);
   if (split == 4) return solve_split<4>(mode, units, n_units, pool, Z, Y, nx, Npad, single, 0, s);
   if (split == 0) {
