@@ -537,6 +537,126 @@ __global__ __launch_bounds__(64) void k_dd2_tri0(const DD2Row* __restrict__ rows
   }
 }
 
+// Staged in LDS, for all slice columns: one workgroup per (row, group of 16
+// columns). The row's right-hand sides (w x 16, coalesced rows of 128 bytes)
+// and LU land in LDS; wave v takes columns 4v..4v+3 with 16 lanes per column,
+// lane q holding the segment [qK, qK + K) of the row (K = ceil(w / 16)); each
+// sweep composes the segment's affine maps, scans them over the 16 lanes and
+// re-runs the segment from its incoming value; the result leaves through LDS.
+constexpr int kTriStage = 17;  // LDS row stride (doubles) of the staged tile
+constexpr int kTriStageMaxW = 512;
+
+__host__ __device__ inline size_t tri0s_lds_bytes(int wmax) {
+  return (size_t)wmax * (kTriStage + 3) * sizeof(double);
+}
+
+template <bool BACK>
+__global__ __launch_bounds__(256) void k_dd2_tri0s(const DD2Row* __restrict__ rows,
+                                                   const double* __restrict__ tri,
+                                                   const double* __restrict__ bcp,
+                                                   double* __restrict__ Z, double* __restrict__ Y,
+                                                   int nx, int Npad) {
+  extern __shared__ double lds[];
+  const DD2Row R = rows[blockIdx.x];
+  const int b0 = (int)blockIdx.y * 16;
+  const int w = R.w, tid = threadIdx.x;
+  double* T = lds;                          // [w][kTriStage]
+  double* Fm = lds + (long)w * kTriStage;   // [w] multipliers
+  double* Fi = Fm + w;                      // [w] reciprocal pivots
+  double* Fg = Fi + w;                      // [w] back factors
+  const double* fm = tri + R.tri;
+  const long own = ((long)R.row * nx + R.col0) * Npad + b0;
+  const double* zm = Z + ((long)(R.rowm >= 0 ? R.rowm : R.row) * nx + R.col0) * Npad + b0;
+  const double* zp = Z + ((long)(R.rowp >= 0 ? R.rowp : R.row) * nx + R.col0) * Npad + b0;
+  const double* vb = bcp + R.bc;
+  const double* vc = vb + R.W;
+  // right-hand sides and LU into LDS (a missing neighbour row meets a zero coupling)
+  const int n = w * 16;
+  constexpr int U = 8;
+  for (int e0 = tid; e0 < n; e0 += U * 256) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int e = min(e0 + u * 256, n - 1);
+      const int p = e >> 4, c = e & 15;
+      v[u] = BACK ? vb[p] * zm[(long)p * Npad + c] + vc[p] * zp[(long)p * Npad + c]
+                  : Z[own + (long)p * Npad + c];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int e = e0 + u * 256;
+      if (e < n) T[(e >> 4) * kTriStage + (e & 15)] = v[u];
+    }
+  }
+  for (int p = tid; p < w; p += 256) {
+    Fm[p] = fm[p];
+    Fi[p] = fm[R.W + p];
+    Fg[p] = fm[2 * R.W + p];
+  }
+  __syncthreads();
+  const int lane = tid % kWave, q = lane & 15;
+  const int c = (tid / kWave) * 4 + (lane >> 4);
+  const int K = (w + 15) >> 4;
+  const int p0 = q * K, p1 = min(p0 + K, w);
+  // forward: z_p = v_p - m_p z_{p-1}
+  double A = 1.0, B = 0.0;
+#pragma unroll 4
+  for (int p = p0; p < p1; p++) {
+    const double m = Fm[p];
+    B = fma(-m, B, T[p * kTriStage + c]);
+    A = -m * A;
+  }
+#pragma unroll
+  for (int d = 1; d < 16; d <<= 1) {
+    const double ap = __shfl_up(A, d, 16);
+    const double bp = __shfl_up(B, d, 16);
+    if (q >= d) {
+      B = fma(A, bp, B);
+      A = A * ap;
+    }
+  }
+  double z = __shfl_up(B, 1, 16);
+  if (q == 0) z = 0.0;
+#pragma unroll 4
+  for (int p = p0; p < p1; p++) {
+    z = fma(-Fm[p], z, T[p * kTriStage + c]);
+    T[p * kTriStage + c] = z;
+  }
+  // backward: x_p = ip_p z_p + g_p x_{p+1}
+  A = 1.0;
+  B = 0.0;
+#pragma unroll 4
+  for (int p = p1 - 1; p >= p0; p--) {
+    const double g = Fg[p];
+    B = fma(g, B, Fi[p] * T[p * kTriStage + c]);
+    A = g * A;
+  }
+#pragma unroll
+  for (int d = 1; d < 16; d <<= 1) {
+    const double an = __shfl_down(A, d, 16);
+    const double bn = __shfl_down(B, d, 16);
+    if (q + d < 16) {
+      B = fma(A, bn, B);
+      A = A * an;
+    }
+  }
+  double x = __shfl_down(B, 1, 16);
+  if (q == 15) x = 0.0;
+#pragma unroll 4
+  for (int p = p1 - 1; p >= p0; p--) {
+    x = fma(Fg[p], x, Fi[p] * T[p * kTriStage + c]);
+    T[p * kTriStage + c] = x;
+  }
+  __syncthreads();
+  double* out = (BACK ? Z : Y) + own;
+  const double* yr = Y + own;
+  for (int e = tid; e < n; e += 256) {
+    const long o = (long)(e >> 4) * Npad + (e & 15);
+    const double v = T[(e >> 4) * kTriStage + (e & 15)];
+    out[o] = BACK ? yr[o] - v : v;
+  }
+}
+
 // Inclusive scans over the 64 lanes of the affine maps v -> a v + b: upwards
 // lane i ends with f_i o ... o f_0, downwards with f_i o f_{i+1} o ... o f_63.
 __device__ __forceinline__ void tri_scan_up(double& a, double& b, int lane) {
@@ -885,6 +1005,15 @@ hipError_t launch_dd2_tri0(bool back, const DD2Row* rows, int n_rows, int wmax, 
   if (Npad < 1 || wmax < 1 || wmax > kDD2MaxW) return hipErrorInvalidValue;
   const long lines = (long)n_rows * Npad;
   if (lines > INT_MAX) return hipErrorInvalidValue;
+  if (!per_line && Npad % 16 == 0 && wmax <= kTriStageMaxW) {
+    const dim3 grid((unsigned)n_rows, (unsigned)(Npad / 16)), block(256);
+    const size_t lds = tri0s_lds_bytes(wmax);
+    if (back)
+      hipLaunchKernelGGL(k_dd2_tri0s<true>, grid, block, lds, s, rows, tri, bc, Z, Y, nx, Npad);
+    else
+      hipLaunchKernelGGL(k_dd2_tri0s<false>, grid, block, lds, s, rows, tri, bc, Z, Y, nx, Npad);
+    return hipGetLastError();
+  }
   if (per_line) {
     int K = 1;
     while (K * kWave < wmax) K *= 2;

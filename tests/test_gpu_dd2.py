@@ -146,6 +146,26 @@ def test_dd2_single_colour_full_width():
     assert fine_parity(w) <= TOL
 
 
+def test_dd2_wide_strip():
+    """A strip of 560 columns (padded 576): the all-slice level-0 sweeps take the
+    one-lane-per-line form (the LDS-staged form holds at most 512), the single-state
+    ones sixteen positions per lane. The strip system's condition number is about
+    1 + 8 tau / h^2, so FP64 rounding in any exact solver is of order that times the
+    unit roundoff; tau = 1e-3 / 3 keeps it near 840, well inside the bound."""
+    nx, ny = 560, 5
+    w = W.small_dd2(nx, ny, 1, 0.1, 3, 1, seed=6, T=1e-3)
+    w.rho = np.ones((1, 2 * nx + 1))
+    err = fine_parity(w)
+    print(f"wide strip: relative error {err:.3e}", flush=True)
+    assert err <= TOL
+    P, O = gpu_problem(w), oracle_problem(w)
+    Seq = P.new_states()
+    P.sequential_fine(dev(w.u0), Seq)
+    torch.cuda.synchronize()
+    ref = O.sequential_fine(w.u0)
+    assert relerr(Seq.cpu().numpy().reshape(ref.shape), ref) <= TOL
+
+
 def test_dd2_constant_coefficient():
     w = W.small_dd2(81, 47, 2, 1.0 / 16, 6, 2, seed=2, variable=False)
     assert fine_parity(w) <= TOL
