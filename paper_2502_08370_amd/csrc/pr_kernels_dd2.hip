@@ -540,14 +540,17 @@ __global__ __launch_bounds__(64) void k_dd2_tri0(const DD2Row* __restrict__ rows
 // Staged in LDS, for all slice columns: one workgroup per (row, group of 16
 // columns). The row's right-hand sides (w x 16, coalesced rows of 128 bytes)
 // and LU land in LDS; wave v takes columns 4v..4v+3 with 16 lanes per column,
-// lane q holding the segment [qK, qK + K) of the row (K = ceil(w / 16)); each
-// sweep composes the segment's affine maps, scans them over the 16 lanes and
-// re-runs the segment from its incoming value; the result leaves through LDS.
-constexpr int kTriStage = 17;  // LDS row stride (doubles) of the staged tile
+// lane q holding the segment [qK, qK + K) of the row; each sweep composes the
+// segment's affine maps, scans them over the 16 lanes and re-runs the segment
+// from its incoming value; the result leaves through LDS. The tile is stored
+// column by column with an odd column stride and K is odd, so that the lanes of
+// a wave (16 segments x 4 columns, or 16 columns x 4 positions when loading)
+// fall on different LDS banks.
 constexpr int kTriStageMaxW = 512;
 
+__host__ __device__ inline int tri0s_stride(int w) { return w | 1; }
 __host__ __device__ inline size_t tri0s_lds_bytes(int wmax) {
-  return (size_t)wmax * (kTriStage + 3) * sizeof(double);
+  return ((size_t)16 * tri0s_stride(wmax) + 3 * (size_t)wmax) * sizeof(double);
 }
 
 template <bool BACK>
@@ -560,10 +563,11 @@ __global__ __launch_bounds__(256) void k_dd2_tri0s(const DD2Row* __restrict__ ro
   const DD2Row R = rows[blockIdx.x];
   const int b0 = (int)blockIdx.y * 16;
   const int w = R.w, tid = threadIdx.x;
-  double* T = lds;                          // [w][kTriStage]
-  double* Fm = lds + (long)w * kTriStage;   // [w] multipliers
-  double* Fi = Fm + w;                      // [w] reciprocal pivots
-  double* Fg = Fi + w;                      // [w] back factors
+  const int S = tri0s_stride(w);
+  double* T = lds;                     // [16][S]: column c at T + c S
+  double* Fm = lds + 16 * S;           // [w] multipliers
+  double* Fi = Fm + w;                 // [w] reciprocal pivots
+  double* Fg = Fi + w;                 // [w] back factors
   const double* fm = tri + R.tri;
   const long own = ((long)R.row * nx + R.col0) * Npad + b0;
   const double* zm = Z + ((long)(R.rowm >= 0 ? R.rowm : R.row) * nx + R.col0) * Npad + b0;
@@ -572,7 +576,7 @@ __global__ __launch_bounds__(256) void k_dd2_tri0s(const DD2Row* __restrict__ ro
   const double* vc = vb + R.W;
   // right-hand sides and LU into LDS (a missing neighbour row meets a zero coupling)
   const int n = w * 16;
-  constexpr int U = 8;
+  constexpr int U = BACK ? 8 : 16;
   for (int e0 = tid; e0 < n; e0 += U * 256) {
     double v[U];
 #pragma unroll
@@ -585,7 +589,7 @@ __global__ __launch_bounds__(256) void k_dd2_tri0s(const DD2Row* __restrict__ ro
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int e = e0 + u * 256;
-      if (e < n) T[(e >> 4) * kTriStage + (e & 15)] = v[u];
+      if (e < n) T[(e & 15) * S + (e >> 4)] = v[u];
     }
   }
   for (int p = tid; p < w; p += 256) {
@@ -596,14 +600,15 @@ __global__ __launch_bounds__(256) void k_dd2_tri0s(const DD2Row* __restrict__ ro
   __syncthreads();
   const int lane = tid % kWave, q = lane & 15;
   const int c = (tid / kWave) * 4 + (lane >> 4);
-  const int K = (w + 15) >> 4;
-  const int p0 = q * K, p1 = min(p0 + K, w);
+  const int K = ((w + 15) >> 4) | 1;
+  const int p0 = min(q * K, w), p1 = min(p0 + K, w);
+  double* Tc = T + c * S;
   // forward: z_p = v_p - m_p z_{p-1}
   double A = 1.0, B = 0.0;
 #pragma unroll 4
   for (int p = p0; p < p1; p++) {
     const double m = Fm[p];
-    B = fma(-m, B, T[p * kTriStage + c]);
+    B = fma(-m, B, Tc[p]);
     A = -m * A;
   }
 #pragma unroll
@@ -619,8 +624,8 @@ __global__ __launch_bounds__(256) void k_dd2_tri0s(const DD2Row* __restrict__ ro
   if (q == 0) z = 0.0;
 #pragma unroll 4
   for (int p = p0; p < p1; p++) {
-    z = fma(-Fm[p], z, T[p * kTriStage + c]);
-    T[p * kTriStage + c] = z;
+    z = fma(-Fm[p], z, Tc[p]);
+    Tc[p] = z;
   }
   // backward: x_p = ip_p z_p + g_p x_{p+1}
   A = 1.0;
@@ -628,7 +633,7 @@ __global__ __launch_bounds__(256) void k_dd2_tri0s(const DD2Row* __restrict__ ro
 #pragma unroll 4
   for (int p = p1 - 1; p >= p0; p--) {
     const double g = Fg[p];
-    B = fma(g, B, Fi[p] * T[p * kTriStage + c]);
+    B = fma(g, B, Fi[p] * Tc[p]);
     A = g * A;
   }
 #pragma unroll
@@ -644,16 +649,27 @@ __global__ __launch_bounds__(256) void k_dd2_tri0s(const DD2Row* __restrict__ ro
   if (q == 15) x = 0.0;
 #pragma unroll 4
   for (int p = p1 - 1; p >= p0; p--) {
-    x = fma(Fg[p], x, Fi[p] * T[p * kTriStage + c]);
-    T[p * kTriStage + c] = x;
+    x = fma(Fg[p], x, Fi[p] * Tc[p]);
+    Tc[p] = x;
   }
   __syncthreads();
   double* out = (BACK ? Z : Y) + own;
   const double* yr = Y + own;
-  for (int e = tid; e < n; e += 256) {
-    const long o = (long)(e >> 4) * Npad + (e & 15);
-    const double v = T[(e >> 4) * kTriStage + (e & 15)];
-    out[o] = BACK ? yr[o] - v : v;
+  constexpr int V = 8;
+  for (int e0 = tid; e0 < n; e0 += V * 256) {
+    double yv[V];
+#pragma unroll
+    for (int u = 0; u < V; u++) {
+      const int e = min(e0 + u * 256, n - 1);
+      yv[u] = BACK ? yr[(long)(e >> 4) * Npad + (e & 15)] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < V; u++) {
+      const int e = e0 + u * 256;
+      if (e >= n) continue;
+      const double v = T[(e & 15) * S + (e >> 4)];
+      out[(long)(e >> 4) * Npad + (e & 15)] = BACK ? yv[u] - v : v;
+    }
   }
 }
 
