@@ -759,7 +759,8 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
         t.nmb = t.W / 16;
         units.push_back(t);
       }
-      ph.push_back({mode, off, (int)units.size() - off, 0, 0, (max_tiles + 3) / 4, 0});
+      ph.push_back({mode, off, (int)units.size() - off, 0, 0,
+                    (max_tiles + kDD2WholeRowTiles - 1) / kDD2WholeRowTiles, 0});
       return;
     }
     const int nmb = tiles4 >= 512 ? 4 : (tiles4 >= 128 ? 2 : 1);

@@ -240,6 +240,7 @@ hipError_t launch_update(const double* g, const double* F, double* G_old, double
 // slices, which sit contiguously at every grid node ("slice-minor" layout
 // Zs[node][b], b < Npad).
 constexpr int kDD2MaxW = 1024;  // widest padded strip
+constexpr int kDD2WholeRowTiles = 2;  // row tiles per wave in the whole-row solve launches
 
 __host__ __device__ inline long dd2_frag(int W, int o, int k) {
   return ((long)(k >> 2) * (W >> 4) + (o >> 4)) * 64 + (k & 3) * 16 + (o & 15);
@@ -312,8 +313,8 @@ hipError_t launch_dd2_gemm(const DD2Gemm* jobs, int n, int W, hipStream_t s);
 hipError_t launch_dd2_store(const DD2Copy* jobs, int n, int W, hipStream_t s);
 // One MFMA solve phase (DD2_APPLY, DD2_KUP or DD2_BACK) over a unit list, all slice columns.
 // single: one state in natural layout (Npad = 1). split = 0: each unit is a
-// whole block row (nmb = W/16 <= 32), one workgroup of `waves` waves (4 row
-// tiles each); 1: four units of <= 4 row tiles per workgroup; 4, 8 or 16: one
+// whole block row (nmb = W/16 <= 32), one workgroup of `waves` waves
+// (kDD2WholeRowTiles row tiles each); 1: four units of <= 4 row tiles per workgroup; 4, 8 or 16: one
 // unit per workgroup with its k-blocks split over that many waves (launches with
 // few units; 16 is taken as 8 for more than two column tiles).
 hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const double* pool,

@@ -291,7 +291,7 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // last column (finite values) and meet zero matrix entries. Single-state solves
 // (Npad = 1) feed zeros into the 15 unused columns.
 // KSPLIT = 0: one block row per workgroup, wave i taking its row tiles
-// [4i, 4i + 4) (the waves share the row's right-hand sides through the CU's
+// [RT i, RT i + RT) (the waves share the row's right-hand sides through the CU's
 // cache). KSPLIT = 1: four units per workgroup, one per wave. KSPLIT = 4, 8 or
 // 16: one unit per workgroup, the k-blocks dealt to KSPLIT waves and the partial
 // products summed through LDS in a tree (KSPLIT times shorter dependent chains
@@ -302,24 +302,23 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // leave room for the extra registers; the split launches keep one.
 constexpr int kRowPrefetch = 2;
 
-template <int MODE, int TN>
+template <int MODE, int TN, int RT>
 struct Frag {
-  double a[4];
+  double a[RT];
   double x[TN];
 };
 
 // Loads of k-block kb (clamped into [0, kb_end) so every address is valid; a
 // block past the end, or a row tile past nmb, contributes a zero A fragment).
-template <int MODE, int TN, bool SINGLE, bool NT>
-__device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, long mbW,
+template <int MODE, int TN, int RT, bool SINGLE, bool NT>
+__device__ __forceinline__ void load_frag(Frag<MODE, TN, RT>& f, const double* A, long mbW,
                                           const double* X, int kb, int kb_end, int kq, int cl,
                                           int w, int nmb, int Npad) {
   const bool live = kb < kb_end;
   kb = min(kb, kb_end - 1);
   const int k = min(kb * 4 + kq, w - 1);
 #pragma unroll
-  for (int r = 0; r < 4; r++) {
-    // the factor stream is read once: keep it out of the caches' way
+  for (int r = 0; r < RT; r++) {
     // the factor stream is read once (non-temporal where measured faster: launches
     // without split-K; the split ones read their blocks in shorter pieces)
     f.a[r] = (live && r < nmb) ? (NT ? __builtin_nontemporal_load(&A[((long)kb * mbW + r) * 64])
@@ -334,10 +333,12 @@ __device__ __forceinline__ void load_frag(Frag<MODE, TN>& f, const double* A, lo
 }
 
 template <int MODE, int TN, bool SINGLE, int KSPLIT>
-__global__ __launch_bounds__(KSPLIT == 16 ? 1024 : (KSPLIT == 0 || KSPLIT == 8 ? 512 : 256)) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
+__global__ __launch_bounds__(KSPLIT == 16 || (KSPLIT == 0 && kDD2WholeRowTiles == 2) ? 1024 : (KSPLIT == 0 || KSPLIT == 8 ? 512 : 256)) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
                                                    const double* __restrict__ pool,
                                                    double* __restrict__ Z, double* __restrict__ Y,
                                                    int nx, int Npad, int b0) {
+  // row tiles per wave
+  constexpr int RT = KSPLIT == 0 ? kDD2WholeRowTiles : 4;
   const int lane = threadIdx.x % kWave;
   // the wave index is uniform across the wave: say so, so that the unit's fields
   // live in scalar registers and its guards are scalar branches
@@ -346,9 +347,9 @@ __global__ __launch_bounds__(KSPLIT == 16 ? 1024 : (KSPLIT == 0 || KSPLIT == 8 ?
   if (u >= n_units) return;  // no barrier follows for KSPLIT <= 1; split units are whole workgroups
   const DD2Unit U = units[u];
   const int W = U.W, w = U.w;
-  // KSPLIT = 0: the unit is a whole block row; wave i takes its row tiles [4i, 4i + 4)
-  const int mb0 = KSPLIT == 0 ? U.mb0 + 4 * wave : U.mb0;
-  const int nmb = KSPLIT == 0 ? min(4, U.nmb - 4 * wave) : U.nmb;
+  // KSPLIT = 0: the unit is a whole block row; wave i takes its row tiles [RT i, RT i + RT)
+  const int mb0 = KSPLIT == 0 ? U.mb0 + RT * wave : U.mb0;
+  const int nmb = KSPLIT == 0 ? min(RT, U.nmb - RT * wave) : U.nmb;
   if (nmb <= 0) return;
   const long mbW = W >> 4;
   const int nkb = W >> 2;
@@ -356,9 +357,9 @@ __global__ __launch_bounds__(KSPLIT == 16 ? 1024 : (KSPLIT == 0 || KSPLIT == 8 ?
   // this wave's k-blocks
   const int kb_lo = KSPLIT <= 1 ? 0 : (nkb * wave) / KSPLIT;
   const int kb_hi = KSPLIT <= 1 ? nkb : (nkb * (wave + 1)) / KSPLIT;
-  d4 acc[4][TN];
+  d4 acc[RT][TN];
 #pragma unroll
-  for (int r = 0; r < 4; r++)
+  for (int r = 0; r < RT; r++)
 #pragma unroll
     for (int nt = 0; nt < TN; nt++) acc[r][nt] = d4{0.0, 0.0, 0.0, 0.0};
   const long col_off = SINGLE ? 0 : (long)b0 + cl;
@@ -379,15 +380,15 @@ __global__ __launch_bounds__(KSPLIT == 16 ? 1024 : (KSPLIT == 0 || KSPLIT == 8 ?
     const double* X = Xb + ((long)rx * nx + U.col0) * Npad + col_off;
     // ring of PF k-blocks in flight ahead of the one being multiplied
     constexpr int PF = KSPLIT == 0 ? kRowPrefetch : 1;
-    Frag<MODE, TN> ring[PF + 1];
+    Frag<MODE, TN, RT> ring[PF + 1];
 #pragma unroll
     for (int q = 0; q < PF; q++)
-      load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(ring[q], A, mbW, X, kb_lo + q, kb_hi, kq, cl, w, nmb, Npad);
+      load_frag<MODE, TN, RT, SINGLE, (KSPLIT <= 1)>(ring[q], A, mbW, X, kb_lo + q, kb_hi, kq, cl, w, nmb, Npad);
     for (int kb = kb_lo; kb < kb_hi; kb++) {
       if (kb + PF < kb_hi)
-        load_frag<MODE, TN, SINGLE, (KSPLIT <= 1)>(ring[PF], A, mbW, X, kb + PF, kb_hi, kq, cl, w, nmb, Npad);
+        load_frag<MODE, TN, RT, SINGLE, (KSPLIT <= 1)>(ring[PF], A, mbW, X, kb + PF, kb_hi, kq, cl, w, nmb, Npad);
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
+      for (int r = 0; r < RT; r++) {
         if (r < nmb) {
 #pragma unroll
           for (int nt = 0; nt < TN; nt++)
@@ -402,34 +403,34 @@ __global__ __launch_bounds__(KSPLIT == 16 ? 1024 : (KSPLIT == 0 || KSPLIT == 8 ?
     // tree over the waves: at each stage waves [half, 2 half) leave their
     // partial products in LDS and waves [0, half) add them
     constexpr int kSlots = KSPLIT > 1 ? KSPLIT / 2 : 1;
-    __shared__ double part[kSlots * 4 * TN * 4 * kWave];
+    __shared__ double part[kSlots * RT * TN * 4 * kWave];
 #pragma unroll 1
     for (int half = KSPLIT / 2; half >= 1; half >>= 1) {
       if (wave >= half && wave < 2 * half) {
 #pragma unroll
-        for (int r = 0; r < 4; r++)
+        for (int r = 0; r < RT; r++)
 #pragma unroll
           for (int nt = 0; nt < TN; nt++)
 #pragma unroll
             for (int v = 0; v < 4; v++)
-              part[((((wave - half) * 4 + r) * TN + nt) * 4 + v) * kWave + lane] = acc[r][nt][v];
+              part[((((wave - half) * RT + r) * TN + nt) * 4 + v) * kWave + lane] = acc[r][nt][v];
       }
       __syncthreads();
       if (wave < half) {
 #pragma unroll
-        for (int r = 0; r < 4; r++)
+        for (int r = 0; r < RT; r++)
 #pragma unroll
           for (int nt = 0; nt < TN; nt++)
 #pragma unroll
             for (int v = 0; v < 4; v++)
-              acc[r][nt][v] += part[(((wave * 4 + r) * TN + nt) * 4 + v) * kWave + lane];
+              acc[r][nt][v] += part[(((wave * RT + r) * TN + nt) * 4 + v) * kWave + lane];
       }
       __syncthreads();
     }
     if (wave > 0) return;
   }
 #pragma unroll
-  for (int r = 0; r < 4; r++) {
+  for (int r = 0; r < RT; r++) {
     if (r >= nmb) continue;
 #pragma unroll
     for (int nt = 0; nt < TN; nt++)
@@ -984,7 +985,7 @@ hipError_t launch_dd2_solve(int mode, const DD2Unit* units, int n_units, const d
   if (split == 8) return solve_split<8>(mode, units, n_units, pool, Z, Y, nx, Npad, single, 0, s);
   if (split == 4) return solve_split<4>(mode, units, n_units, pool, Z, Y, nx, Npad, single, 0, s);
   if (split == 0) {
-    if (waves < 1 || waves > 8) return hipErrorInvalidValue;
+    if (waves < 1 || waves * kDD2WholeRowTiles > 32) return hipErrorInvalidValue;
     return solve_split<0>(mode, units, n_units, pool, Z, Y, nx, Npad, single, waves, s);
   }
   return solve_split<1>(mode, units, n_units, pool, Z, Y, nx, Npad, single, 0, s);
