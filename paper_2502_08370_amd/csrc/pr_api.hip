@@ -729,11 +729,13 @@ long dd2_slots(Instance::Strip2& S, int ny, long next) {
 // waves of a workgroup, below kDD2Split8Units (all slices) or kDD2Split8Single
 // (single state) over eight, and below the Split16 counts over sixteen
 // (measured).
-constexpr int kDD2SplitUnits = 2048;
-constexpr int kDD2Split8Units = 320;
-constexpr int kDD2Split8Single = 640;
-constexpr int kDD2Split16Units = 160;
-constexpr int kDD2Split16Single = 320;
+constexpr int kDD2SplitUnits = 4096;
+// Launches with at least this many four-tile units take one workgroup per block row.
+constexpr int kDD2WholeRowUnits = 2048;
+constexpr int kDD2Split8Units = 640;
+constexpr int kDD2Split8Single = 1280;
+constexpr int kDD2Split16Units = 320;
+constexpr int kDD2Split16Single = 640;
 
 // Launch schedule of one colour: forward levels (eliminated rows y = D^-1 r,
 // then kept rows r -= B y_- + C y_+), then back substitution from the top
@@ -752,7 +754,7 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
       max_tiles = std::max(max_tiles, t.W / 16);
     }
     const int off = (int)units.size();
-    if (tiles4 >= kDD2SplitUnits && max_tiles <= 32) {
+    if (tiles4 >= kDD2WholeRowUnits && max_tiles <= 32) {
       // many units: one workgroup per block row
       for (auto t : tasks) {
         t.mb0 = 0;
@@ -763,7 +765,7 @@ void dd2_schedule(Instance& I, int colour, std::vector<DD2Unit>& units,
                     (max_tiles + kDD2WholeRowTiles - 1) / kDD2WholeRowTiles, 0});
       return;
     }
-    const int nmb = tiles4 >= 512 ? 4 : (tiles4 >= 128 ? 2 : 1);
+    const int nmb = std::min(kDD2SplitTiles, tiles4 >= 512 ? 4 : (tiles4 >= 128 ? 2 : 1));
     for (auto t : tasks)
       for (int mb = 0; mb < t.W / 16; mb += nmb) {
         t.mb0 = mb;

@@ -241,6 +241,7 @@ hipError_t launch_update(const double* g, const double* F, double* G_old, double
 // Zs[node][b], b < Npad).
 constexpr int kDD2MaxW = 1024;  // widest padded strip
 constexpr int kDD2WholeRowTiles = 2;  // row tiles per wave in the whole-row solve launches
+constexpr int kDD2SplitTiles = 2;     // most row tiles per unit in the other launches
 
 __host__ __device__ inline long dd2_frag(int W, int o, int k) {
   return ((long)(k >> 2) * (W >> 4) + (o >> 4)) * 64 + (k & 3) * 16 + (o & 15);

@@ -338,7 +338,7 @@ __global__ __launch_bounds__(KSPLIT == 16 || (KSPLIT == 0 && kDD2WholeRowTiles =
                                                    double* __restrict__ Z, double* __restrict__ Y,
                                                    int nx, int Npad, int b0) {
   // row tiles per wave
-  constexpr int RT = KSPLIT == 0 ? kDD2WholeRowTiles : 4;
+  constexpr int RT = KSPLIT == 0 ? kDD2WholeRowTiles : kDD2SplitTiles;
   const int lane = threadIdx.x % kWave;
   // the wave index is uniform across the wave: say so, so that the unit's fields
   // live in scalar registers and its guards are scalar branches
