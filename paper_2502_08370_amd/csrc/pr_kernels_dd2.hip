@@ -295,12 +295,13 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // cache). KSPLIT = 1: four units per workgroup, one per wave. KSPLIT = 4, 8 or
 // 16: one unit per workgroup, the k-blocks dealt to KSPLIT waves and the partial
 // products summed through LDS in a tree (KSPLIT times shorter dependent chains
-// for launches with few units). The loads of k-block kb + 1 are issued before
-// the products of kb (measured faster than deeper prefetch rings, which cost
-// occupancy).
-// k-blocks loaded ahead in the whole-row launches (KSPLIT = 0), whose grids
-// leave room for the extra registers; the split launches keep one.
+// for launches with few units). The loads of the next k-blocks are issued
+// before the products of the current one.
+// k-blocks loaded ahead of the one being multiplied, in the whole-row launches
+// (KSPLIT = 0) and in the others (measured: three in the whole-row launches
+// cost more registers than they hide).
 constexpr int kRowPrefetch = 2;
+constexpr int kSplitPrefetch = 2;
 
 template <int MODE, int TN, int RT>
 struct Frag {
@@ -379,7 +380,7 @@ __global__ __launch_bounds__(KSPLIT == 16 || (KSPLIT == 0 && kDD2WholeRowTiles =
     const double* A = pool + aoff + (long)mb0 * 64 + lane;
     const double* X = Xb + ((long)rx * nx + U.col0) * Npad + col_off;
     // ring of PF k-blocks in flight ahead of the one being multiplied
-    constexpr int PF = KSPLIT == 0 ? kRowPrefetch : 1;
+    constexpr int PF = KSPLIT == 0 ? kRowPrefetch : kSplitPrefetch;
     Frag<MODE, TN, RT> ring[PF + 1];
 #pragma unroll
     for (int q = 0; q < PF; q++)
