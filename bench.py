@@ -455,7 +455,7 @@ def main():
                    "step": "one parareal iteration: F^s on all slices + serial coarse sweep "
                            "with correction and increment"},
         "roofline": {"bound": "hbm",
-                     "kernel": ("dd2 substep (k_dd2_solve phases + k_dd2_tri0 + k_dd2_kup0)" if dd2 else
+                     "kernel": ("dd2 substep (k_dd2_solve phases + k_dd2_tri0s + k_dd2_kup0)" if dd2 else
                                 "dd substep (k_dd_local + k_dd_runmaps + k_dd_runscan + "
                                 "k_dd_segcarries)" if w.split == "dd" else "k_fine_sweep"),
                      "achieved": round(achieved, 1),
