@@ -297,11 +297,19 @@ __global__ void k_dd2_store(const DD2Copy* __restrict__ jobs, int W) {
 // products summed through LDS in a tree (KSPLIT times shorter dependent chains
 // for launches with few units). The loads of the next k-blocks are issued
 // before the products of the current one.
+
 // k-blocks loaded ahead of the one being multiplied, in the whole-row launches
 // (KSPLIT = 0) and in the others (measured: three in the whole-row launches
 // cost more registers than they hide).
 constexpr int kRowPrefetch = 2;
 constexpr int kSplitPrefetch = 2;
+
+// Workgroup size of a solve launch: whole-row launches hold up to 32 row tiles
+// (W <= 512), RT per wave; split launches one wave per k-range share.
+template <int KSPLIT>
+constexpr int solve_threads() {
+  return KSPLIT == 0 ? kWave * (32 / kDD2WholeRowTiles) : (KSPLIT == 1 ? 4 * kWave : KSPLIT * kWave);
+}
 
 template <int MODE, int TN, int RT>
 struct Frag {
@@ -334,10 +342,9 @@ __device__ __forceinline__ void load_frag(Frag<MODE, TN, RT>& f, const double* A
 }
 
 template <int MODE, int TN, bool SINGLE, int KSPLIT>
-__global__ __launch_bounds__(KSPLIT == 16 || (KSPLIT == 0 && kDD2WholeRowTiles == 2) ? 1024 : (KSPLIT == 0 || KSPLIT == 8 ? 512 : 256)) void k_dd2_solve(const DD2Unit* __restrict__ units, int n_units,
-                                                   const double* __restrict__ pool,
-                                                   double* __restrict__ Z, double* __restrict__ Y,
-                                                   int nx, int Npad, int b0) {
+__global__ __launch_bounds__(solve_threads<KSPLIT>()) void k_dd2_solve(
+    const DD2Unit* __restrict__ units, int n_units, const double* __restrict__ pool,
+    double* __restrict__ Z, double* __restrict__ Y, int nx, int Npad, int b0) {
   // row tiles per wave
   constexpr int RT = KSPLIT == 0 ? kDD2WholeRowTiles : kDD2SplitTiles;
   const int lane = threadIdx.x % kWave;
@@ -929,7 +936,7 @@ template <int MODE, bool SINGLE, int KSPLIT>
 hipError_t solve_tn(int tn, const DD2Unit* units, int n_units, const double* pool, double* Z,
                     double* Y, int nx, int Npad, int b0, int waves, hipStream_t s) {
   const dim3 grid(KSPLIT == 1 ? (n_units + 3) / 4 : n_units),
-      block(KSPLIT == 0 ? kWave * waves : (KSPLIT == 1 ? 4 * kWave : KSPLIT * kWave));
+      block(KSPLIT == 0 ? kWave * waves : solve_threads<KSPLIT>());
   if constexpr (KSPLIT == 16) {
     // sixteen waves leave 128 registers per lane and 160 KB of LDS: enough for
     // at most two column tiles; wider launches split eight ways
