@@ -50,6 +50,34 @@ def test_fine_propagate(nx, ny, N, s, var):
     assert relerr(F.cpu().numpy().reshape(ref.shape), ref) <= TOL
 
 
+def test_varcoef2d_full_size_sampled():
+    """The 1023^2, N = 64, s = 64 workload at its real shape, in the benchmark's
+    launch configuration: all 64 slices propagated on the GPU, slices 0, 37 and 63
+    compared with the oracle; the coarse propagator's first step of the initial
+    guess too."""
+    w = W.config2()
+    P, O = gpu_problem(w), oracle_problem(w)
+    rng = np.random.default_rng(0)
+    u0 = np.asarray(w.u0, dtype=np.float64).reshape(w.ny, w.nx)
+    Uin = np.stack([u0 * (1 + 0.01 * k) for k in range(w.n_slices)])
+    Uin[37] += 0.01 * rng.standard_normal(u0.shape)
+    F = P.new_slices()
+    P.fine_propagate(dev(Uin), F)
+    torch.cuda.synchronize()
+    got = F.cpu().numpy().reshape(Uin.shape)
+    for k in (0, 37, w.n_slices - 1):
+        ref = O.fine(Uin[k])
+        assert relerr(got[k], ref.reshape(got[k].shape)) <= TOL, k
+    U = P.new_states()
+    G = P.new_slices()
+    npts = w.nx * w.ny
+    U[:npts].copy_(dev(u0))
+    P.coarse_sweep(None, G, U)
+    torch.cuda.synchronize()
+    g1 = U.cpu().numpy()[npts: 2 * npts]
+    assert relerr(g1, O.coarse(u0).reshape(-1)) <= TOL
+
+
 def test_fine_propagate_reaction_and_stiff():
     """c > 0 (split equally over the two substeps) and a stiff fine step."""
     w = W.small_dim2(57, 41, n_slices=4, fine_steps=2, seed=3, c=2.5, T=2.0)
