@@ -35,7 +35,7 @@ def fine_parity(w, seed=0):
 
 
 # (nx, ny, q, beta, N, s, colours, c): strips of 1..7 row tiles, 1..7 reduction
-# levels, slice counts that are not multiples of 16 and one above 64
+# levels, slice counts that are not multiples of 16 (1 to 5 column tiles of 16)
 CASES = [
     (40, 33, 2, 0.1, 5, 2, 2, 0.0),
     (97, 61, 2, 0.08, 20, 2, 2, 0.0),
@@ -44,6 +44,7 @@ CASES = [
     (120, 17, 3, 0.04, 70, 1, 2, 0.0),
     (75, 40, 2, 0.05, 9, 2, 3, 2.5),
     (9, 25, 1, 0.2, 4, 3, 2, 0.0),
+    (60, 30, 2, 0.1, 40, 2, 2, 0.0),  # three column tiles (the 16-way split runs 8-way)
 ]
 
 
