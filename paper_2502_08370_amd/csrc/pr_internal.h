@@ -121,7 +121,7 @@ struct FactorJob {
 // with Yin the forward-elimination value just before the segment and Xin the
 // solution just after it; chi_i is the back-substituted product of forward
 // multipliers and phi_i the product of back-substitution multipliers.
-constexpr int kDDSeg = 64;
+constexpr int kDDSeg = 32;
 
 struct DDSeg {
   int lo, len;    // first node, node count (<= kDDSeg)

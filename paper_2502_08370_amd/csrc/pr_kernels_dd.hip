@@ -51,6 +51,37 @@ __device__ __forceinline__ void affine_scan_down(double& a, double& b, int lane)
   }
 }
 
+// The same scans within groups of WIDTH lanes (lane = index in the group).
+template <int WIDTH>
+__device__ __forceinline__ void group_scan_up(double& a, double& b, int lane) {
+#pragma unroll
+  for (int off = 1; off < WIDTH; off <<= 1) {
+    double ap = __shfl_up(a, off, WIDTH);
+    double bp = __shfl_up(b, off, WIDTH);
+    if (lane >= off) {
+      b = fma(a, bp, b);
+      a = a * ap;
+    }
+  }
+}
+
+template <int WIDTH>
+__device__ __forceinline__ void group_scan_down(double& a, double& b, int lane) {
+#pragma unroll
+  for (int off = 1; off < WIDTH; off <<= 1) {
+    double an = __shfl_down(a, off, WIDTH);
+    double bn = __shfl_down(b, off, WIDTH);
+    if (lane + off < WIDTH) {
+      b = fma(a, bn, b);
+      a = a * an;
+    }
+  }
+}
+
+// Single-state segment kernels: a segment per group of kDDSeg lanes, lane = node.
+constexpr int kSegsPerWave = kWave / kDDSeg;
+static_assert(kWave % kDDSeg == 0, "segments tile a wave");
+
 __device__ __forceinline__ unsigned long long abs_bits(double v) {
   return static_cast<unsigned long long>(__double_as_longlong(fabs(v)));
 }
@@ -363,9 +394,10 @@ __global__ __launch_bounds__(kWave) void k_dd_runmaps(const DDInst* __restrict__
 }
 
 // 2b: chains the runs of one component for one slice, 64 runs per wave step.
-// Components of up to kScanChunks * 64 runs take a path that issues every load
-// up front and keeps the forward results in registers.
-constexpr int kScanChunks = 4;
+// Components of up to kScanChunks * 64 runs (2^17-node components in 32-node
+// segments have 257) take a path that issues every load up front and keeps the
+// forward results in registers.
+constexpr int kScanChunks = 5;
 
 __global__ __launch_bounds__(kWave) void k_dd_runscan(const DDInst* __restrict__ insts,
                                                       const int* __restrict__ comp_run_first,
@@ -542,19 +574,20 @@ __global__ __launch_bounds__(kWave) void k_dd_correct(const DDInst* __restrict__
   }
 }
 
-// Single state (L = 1): one wave per segment, lane = node. The zero-carry
-// segment solve is one forward and one backward affine scan across the lanes.
+// Single state (L = 1): kDDSeg lanes per segment, lane = node. The zero-carry
+// segment solve is one forward and one backward affine scan across those lanes.
 __global__ __launch_bounds__(4 * kWave) void k_dd_local1(const DDInst* __restrict__ insts,
                                                          DDFactors f, int colour, int seg_begin,
                                                          int seg_count) {
   const DDInst& I = insts[0];
   const int lane = threadIdx.x & (kWave - 1);
-  const int w = blockIdx.x * 4 + threadIdx.x / kWave;
-  if (w >= seg_count) return;  // whole wave; no block-level barrier follows
+  const int gl = lane % kDDSeg;  // node within the segment
+  const int w = (int)(blockIdx.x * 4 + threadIdx.x / kWave) * kSegsPerWave + lane / kDDSeg;
+  if (w >= seg_count) return;  // whole lane group; no block-level barrier follows
   const int si = seg_begin + w;
   const DDSeg sg = I.segs[si];
-  const bool ok = lane < sg.len;
-  const long node = sg.lo + (ok ? lane : 0);
+  const bool ok = gl < sg.len;
+  const long node = sg.lo + (ok ? gl : 0);
   const long cb = (long)colour * I.n;
   const double em = gp(f.G)[cb + (node > 0 ? node - 1 : 0)];
   const double e = node > 0 ? em : 0.0;  // e = g of the previous node
@@ -563,16 +596,16 @@ __global__ __launch_bounds__(4 * kWave) void k_dd_local1(const DDInst* __restric
   // forward: y_t = e_t y_{t-1} + d_t from y = 0 before the segment (e = 1,
   // d = 0 past its end)
   double a = ok ? e : 1.0, bb = ok ? z0 : 0.0;
-  affine_scan_up(a, bb, lane);
+  group_scan_up<kDDSeg>(a, bb, gl);
   const double y = bb;
   // backward: z_t = g_t z_{t+1} + r_t y_t from z = 0 after the segment
   a = ok ? g : 0.0;
   bb = ok ? r * y : 0.0;
-  affine_scan_down(a, bb, lane);
+  group_scan_down<kDDSeg>(a, bb, gl);
   const double z = bb;
   if (ok) gp(I.Z)[node] = z;
-  const double ylast = lane_value(y, sg.len - 1), zfirst = lane_value(z, 0);
-  if (lane == 0) {
+  const double ylast = __shfl(y, sg.len - 1, kDDSeg), zfirst = __shfl(z, 0, kDDSeg);
+  if (gl == 0) {
     gp(I.Yb)[si] = ylast;
     gp(I.Za)[si] = zfirst;
   }
@@ -583,12 +616,13 @@ __global__ __launch_bounds__(4 * kWave) void k_dd_correct1(const DDInst* __restr
                                                            int seg_begin, int seg_count) {
   const DDInst& I = insts[0];
   const int lane = threadIdx.x & (kWave - 1);
-  const int w = blockIdx.x * 4 + threadIdx.x / kWave;
+  const int gl = lane % kDDSeg;
+  const int w = (int)(blockIdx.x * 4 + threadIdx.x / kWave) * kSegsPerWave + lane / kDDSeg;
   if (w >= seg_count) return;
   const int si = seg_begin + w;
   const DDSeg sg = I.segs[si];
-  if (lane >= sg.len) return;
-  const long node = sg.lo + lane;
+  if (gl >= sg.len) return;
+  const long node = sg.lo + gl;
   const long cb = (long)colour * I.n;
   const double yin = gp(I.Yin)[si], xin = gp(I.Xin)[si];
   gp(I.Z)[node] =
@@ -685,8 +719,8 @@ hipError_t launch_dd_local(const DDInst* d, const DDInst& h, const DDFactors& f,
   switch (h.L) {
     case 1:
       if (defer) return hipErrorInvalidValue;  // single states are corrected in place
-      hipLaunchKernelGGL(k_dd_local1, dim3((seg_count + 3) / 4), dim3(4 * kWave), 0, s, d, f,
-                         colour, seg_begin, seg_count);
+      hipLaunchKernelGGL(k_dd_local1, dim3((seg_count + 4 * kSegsPerWave - 1) / (4 * kSegsPerWave)),
+                         dim3(4 * kWave), 0, s, d, f, colour, seg_begin, seg_count);
       return hipGetLastError();
     case 8: return dd_local_l<8>(d, h, f, colour, seg_begin, seg_count, defer, stale_ok, s);
     case 16: return dd_local_l<16>(d, h, f, colour, seg_begin, seg_count, defer, stale_ok, s);
@@ -759,8 +793,9 @@ hipError_t launch_dd_correct(const DDInst* d, const DDInst& h, const DDFactors& 
   if (seg_count <= 0) return hipSuccess;
   switch (h.L) {
     case 1:
-      hipLaunchKernelGGL(k_dd_correct1, dim3((seg_count + 3) / 4), dim3(4 * kWave), 0, s, d, f,
-                         colour, seg_begin, seg_count);
+      hipLaunchKernelGGL(k_dd_correct1,
+                         dim3((seg_count + 4 * kSegsPerWave - 1) / (4 * kSegsPerWave)),
+                         dim3(4 * kWave), 0, s, d, f, colour, seg_begin, seg_count);
       return hipGetLastError();
     case 8: return dd_correct_t<8>(d, h, f, colour, seg_begin, seg_count, s);
     case 16: return dd_correct_t<16>(d, h, f, colour, seg_begin, seg_count, s);
