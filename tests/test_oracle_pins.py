@@ -377,6 +377,69 @@ def test_operator_second_order_consistency():
     assert errs[-1] < 1e-3
 
 
+# ------------------------------------------------- face rule from theta ---
+def test_faces_from_theta_closed_form_2d():
+    """Face coefficients from a nodal log coefficient (section 2.1, D = e^theta I, face
+    value = mean of e^theta over the face's two nodes). With e^theta = 1 + x + 3y^2 the
+    mean is a polynomial of the face's coordinates: x-face f of interior row j sits
+    between nodes x = f h_x and (f+1) h_x at y = (j+1) h_y, y-face g of column i between
+    y = g h_y and (g+1) h_y at x = (i+1) h_x. nx != ny and the different x and y
+    dependence make a row/column swap or a one-node shift fail."""
+    nx, ny = 7, 5
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    xe = np.arange(nx + 2) * hx
+    ye = np.arange(ny + 2) * hy
+    theta = np.log(1.0 + xe[None, :] + 3.0 * ye[:, None] ** 2)  # [y, x], boundary included
+    ax, ay = oracle.faces_from_theta(nx, ny, theta)
+    assert ax.shape == (ny, nx + 1) and ay.shape == (ny + 1, nx)
+    for j in range(ny):
+        y = (j + 1) * hy
+        for f in range(nx + 1):
+            want = 1.0 + (f + 0.5) * hx + 3.0 * y * y
+            assert abs(ax[j, f] - want) <= 4e-16 * want, (j, f, ax[j, f], want)
+    for g in range(ny + 1):
+        y2 = 0.5 * ((g * hy) ** 2 + ((g + 1) * hy) ** 2)
+        for i in range(nx):
+            want = 1.0 + (i + 1) * hx + 3.0 * y2
+            assert abs(ay[g, i] - want) <= 4e-16 * want, (g, i, ay[g, i], want)
+
+
+def test_faces_from_theta_closed_form_1d():
+    """1D face rule: face f joins extended nodes f and f+1 (x = f h, (f+1) h); with
+    e^theta = 1 + x + 2x^2 the face value is 1 + (f + 1/2) h + (f^2 + (f+1)^2) h^2."""
+    nx = 9
+    h = 1.0 / (nx + 1)
+    x = np.arange(nx + 2) * h
+    ax, _ = oracle.faces_from_theta(nx, 1, np.log(1.0 + x + 2.0 * x * x), dim=1)
+    for f in range(nx + 1):
+        want = 1.0 + (f + 0.5) * h + (f * f + (f + 1) ** 2) * h * h
+        assert abs(ax[0, f] - want) <= 4e-16 * want, (f, ax[0, f], want)
+
+
+def test_faces_from_theta_operator_consistency():
+    """The face rule feeds the operator of section 2.1 in the right direction: with
+    D = e^theta I, e^theta = 1 + x + 3y^2, the discrete A applied to u = sin(pi x)
+    sin(2 pi y) approximates div(D grad u) to second order in h (an x/y swap of the
+    faces gives an O(1) error)."""
+    errs = []
+    pi = np.pi
+    for n in (31, 63, 127):
+        h = 1.0 / (n + 1)
+        e = np.arange(n + 2) * h
+        theta = np.log(1.0 + e[None, :] + 3.0 * e[:, None] ** 2)
+        ax, ay = oracle.faces_from_theta(n, n, theta)
+        P = oracle.Problem(dim=2, nx=n, ny=n, T=1, n_slices=1, fine_steps=1, ax=ax, ay=ay)
+        x = e[1:-1]
+        X, Y = np.meshgrid(x, x)  # [y, x]
+        u = np.sin(pi * X) * np.sin(2 * pi * Y)
+        a = 1.0 + X + 3.0 * Y ** 2
+        Lu = (1.0 * pi * np.cos(pi * X) * np.sin(2 * pi * Y) - a * pi ** 2 * u
+              + 6.0 * Y * 2 * pi * np.sin(pi * X) * np.cos(2 * pi * Y) - a * 4 * pi ** 2 * u)
+        errs.append(np.abs(P.apply_A(u) - Lu).max() / np.abs(Lu).max())
+    assert 3.6 < errs[0] / errs[1] < 4.4 and 3.6 < errs[1] / errs[2] < 4.4
+    assert errs[-1] < 1e-3
+
+
 # ------------------------------------------------ P6: M-matrix invariants ---
 @pytest.mark.parametrize("kind", ["dim", "dd"])
 def test_maximum_principle_positivity_linearity(kind):
