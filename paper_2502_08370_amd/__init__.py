@@ -45,12 +45,44 @@ def _dev_f64(a, device):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
 
 
+def _check_coef(dim, nx, ny, mode, cx, cy, device):
+    """Coefficient arrays the library reads: nodal theta on the grid with its boundary
+    nodes, or the x-faces and (2D) the y-faces."""
+    if mode == B.PR_COEF_NODAL_LOG:
+        _check(cx, device, (nx + 2) * (ny + 2) if dim == 2 else nx + 2, "theta")
+    else:
+        _check(cx, device, ny * (nx + 1), "ax")
+        if dim == 2:
+            _check(cy, device, (ny + 1) * nx, "ay")
+
+
 _OPTS = {"graph": B.PR_OPT_GRAPH, "fine_chunk": B.PR_OPT_FINE_CHUNK, "lanes": B.PR_OPT_LANES,
          "blocks_per_pass": B.PR_OPT_BLOCKS_PER_PASS}
 
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check(t, device, count, name, optional=False):
+    """The library reads and writes raw device pointers: refuse, before any launch,
+    a tensor that is not a contiguous float64 tensor of exactly `count` elements
+    on the handle's device."""
+    torch = _torch()
+    if t is None:
+        if optional:
+            return
+        raise PrError(B.PR_EINVAL, f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise PrError(B.PR_EINVAL, f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise PrError(B.PR_EINVAL, f"{name} must be float64, got {t.dtype}")
+    if t.device.type != device.type or (device.index is not None and t.device.index != device.index):
+        raise PrError(B.PR_EINVAL, f"{name} is on {t.device}, the handle on {device}")
+    if not t.is_contiguous():
+        raise PrError(B.PR_EINVAL, f"{name} must be contiguous")
+    if t.numel() != count:
+        raise PrError(B.PR_EINVAL, f"{name} has {t.numel()} elements, expected {count}")
 
 
 class Problem:
@@ -72,6 +104,8 @@ class Problem:
         if isinstance(instances, dict):
             instances = [instances]
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         n = len(instances)
         descs = (B.PrProblemDesc * n)()
         keep = []
@@ -93,6 +127,7 @@ class Problem:
                 d.coef_mode = B.PR_COEF_FACES
                 cx = _dev_f64(ins["ax"], self.device)
                 cy = _dev_f64(ins.get("ay"), self.device)
+            _check_coef(d.dim, d.nx, d.ny, d.coef_mode, cx, cy, self.device)
             keep += [cx, cy]
             d.coef_x, d.coef_y = _ptr(cx), _ptr(cy)
             rho = ins.get("rho")
@@ -114,7 +149,9 @@ class Problem:
                 d.forcing_time_fine = C.c_void_p(gf.ctypes.data)
                 d.forcing_time_coarse = C.c_void_p(gc.ctypes.data)
             self.instances.append(dict(dim=d.dim, nx=d.nx, ny=d.ny, n_slices=d.n_slices,
-                                       coef_mode=d.coef_mode))
+                                       fine_steps=d.fine_steps, coarse_steps=d.coarse_steps,
+                                       fine=d.fine, split=d.split, n_forcing=d.n_forcing,
+                                       n_colors=d.n_colors, coef_mode=d.coef_mode))
         h = C.c_void_p()
         B.check(B.lib().pr_create_problem(descs, n, _stream(stream), C.byref(h)))
         self._h = h
@@ -171,17 +208,28 @@ class Problem:
 
     def set_coefficients(self, i, coef_x, coef_y=None, stream=None):
         cx, cy = _dev_f64(coef_x, self.device), _dev_f64(coef_y, self.device)
+        ins = self.instances[i]
+        _check_coef(ins["dim"], ins["nx"], ins["ny"], ins["coef_mode"], cx, cy, self.device)
         B.check(B.lib().pr_set_coefficients(self._h, int(i), _ptr(cx), _ptr(cy), _stream(stream)))
         _torch().cuda.current_stream().synchronize()
 
     def fine_propagate(self, U_in, F_out, stream=None):
+        n = self.totals["slices"]
+        _check(U_in, self.device, n, "U_in")
+        _check(F_out, self.device, n, "F_out")
         B.check(B.lib().pr_fine_propagate(self._h, _ptr(U_in), _ptr(F_out), _stream(stream)))
 
     def coarse_sweep(self, F, G_old, U, inc=None, stream=None):
+        _check(F, self.device, self.totals["slices"], "F", optional=True)
+        _check(G_old, self.device, self.totals["slices"], "G_old")
+        _check(U, self.device, self.totals["states"], "U")
+        _check(inc, self.device, len(self.layout), "inc", optional=True)
         B.check(B.lib().pr_coarse_sweep(self._h, _ptr(F), _ptr(G_old), _ptr(U), _ptr(inc),
                                         _stream(stream)))
 
     def parareal_iterate(self, u0, U, k_max, tol=0.0, stream=None):
+        _check(u0, self.device, self.totals["u0"], "u0")
+        _check(U, self.device, self.totals["states"], "U")
         n = len(self.layout)
         k = (C.c_int * n)()
         inc = (C.c_double * n)()
@@ -190,6 +238,8 @@ class Problem:
         return list(k), list(inc)
 
     def sequential_fine(self, u0, U, stream=None):
+        _check(u0, self.device, self.totals["u0"], "u0")
+        _check(U, self.device, self.totals["states"], "U")
         B.check(B.lib().pr_sequential_fine(self._h, _ptr(u0), _ptr(U), _stream(stream)))
 
     def set_option(self, name, value):
@@ -207,7 +257,12 @@ class Problem:
         path (JSON), reuse a previous choice for the same shapes."""
         import json
         import os
-        key = json.dumps(sorted((ins["nx"], ins["ny"], ins["n_slices"]) for ins in self.instances))
+        # everything that selects the kernels and their work: shapes, steps, integrator,
+        # split, colours and source terms
+        key = json.dumps(sorted(tuple(ins[k] for k in ("dim", "nx", "ny", "n_slices", "fine_steps",
+                                                         "coarse_steps", "fine", "split",
+                                                         "n_colors", "n_forcing"))
+                                for ins in self.instances))
         if cache and os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
@@ -241,7 +296,24 @@ class Problem:
         return {B.PHASE_NAMES[i]: (out.ms[i], out.count[i]) for i in range(B.PROFILE_PHASES)
                 if out.count[i]}
 
+    def _check_adjoint(self, u0, lambda_T, grad_u0, grad_coef, U_ckpt):
+        n = self.totals["u0"]
+        for t, name in ((u0, "u0"), (lambda_T, "lambda_T"), (grad_u0, "grad_u0")):
+            _check(t, self.device, n, name)
+        _check(grad_coef, self.device, self.coef_count(0), "grad_coef")
+        _check(U_ckpt, self.device, self.totals["states"], "U_ckpt", optional=True)
+
+    def coef_count(self, i):
+        """Entries of instance i's coefficient (and coefficient gradient): nodal theta
+        (nx+2)(ny+2) (nx+2 in 1D), or the x-faces followed by the y-faces."""
+        ins = self.instances[i]
+        nx, ny = ins["nx"], ins["ny"]
+        if ins["coef_mode"] == B.PR_COEF_NODAL_LOG:
+            return (nx + 2) * (ny + 2) if ins["dim"] == 2 else nx + 2
+        return ny * (nx + 1) + ((ny + 1) * nx if ins["dim"] == 2 else 0)
+
     def adjoint(self, u0, lambda_T, grad_u0, grad_coef, U_ckpt=None, stream=None):
+        self._check_adjoint(u0, lambda_T, grad_u0, grad_coef, U_ckpt)
         B.check(B.lib().pr_adjoint(self._h, _ptr(u0), _ptr(lambda_T), _ptr(grad_u0),
                                    _ptr(grad_coef), _ptr(U_ckpt), _stream(stream)))
 
@@ -250,6 +322,7 @@ class Problem:
         """Parallel-in-time adjoint (pr_adjoint_parallel): k_max = 0 computes the
         boundary adjoints exactly, k_max > 0 by parareal on the backward problem.
         Returns the number of backward parareal corrections done."""
+        self._check_adjoint(u0, lambda_T, grad_u0, grad_coef, U_ckpt)
         k = C.c_int(0)
         B.check(B.lib().pr_adjoint_parallel(self._h, _ptr(u0), _ptr(lambda_T), _ptr(grad_u0),
                                             _ptr(grad_coef), _ptr(U_ckpt), int(k_max), float(tol),

@@ -21,23 +21,29 @@ class FineMap(torch.autograd.Function):
     def forward(ctx, u0, theta, problem: Problem):
         ins = problem.instances[0]
         shape = (ins["ny"], ins["nx"])
-        problem.set_coefficients(0, theta)
+        u64 = u0.detach().to(device=problem.device, dtype=torch.float64).reshape(-1).contiguous()
+        th64 = theta.detach().to(device=problem.device, dtype=torch.float64).reshape(-1).contiguous()
+        problem.set_coefficients(0, th64)
         U = problem.new_states()
-        problem.sequential_fine(u0.reshape(-1).contiguous(), U)
+        problem.sequential_fine(u64, U)
         ctx.problem = problem
-        ctx.save_for_backward(u0, theta)
+        ctx.u_meta = (u0.shape, u0.dtype, u0.device)
+        ctx.th_meta = (theta.shape, theta.dtype, theta.device)
+        ctx.save_for_backward(u64, th64)
         npts = ins["nx"] * ins["ny"]
         return U[-npts:].view(shape).clone()
 
     @staticmethod
     def backward(ctx, gT):
-        u0, theta = ctx.saved_tensors
+        u64, th64 = ctx.saved_tensors
         problem = ctx.problem
-        problem.set_coefficients(0, theta)
-        g0 = torch.empty_like(u0, dtype=torch.float64).reshape(-1)
-        gth = torch.empty_like(theta, dtype=torch.float64).reshape(-1)
-        problem.adjoint(u0.reshape(-1).contiguous(), gT.reshape(-1).contiguous().double(), g0, gth)
-        return g0.view(u0.shape), gth.view(theta.shape), None
+        problem.set_coefficients(0, th64)
+        g0 = torch.empty_like(u64)
+        gth = torch.empty_like(th64)
+        lam = gT.detach().to(device=problem.device, dtype=torch.float64).reshape(-1).contiguous()
+        problem.adjoint(u64, lam, g0, gth)
+        (us, ud, udev), (ts, td, tdev) = ctx.u_meta, ctx.th_meta
+        return g0.view(us).to(device=udev, dtype=ud), gth.view(ts).to(device=tdev, dtype=td), None
 
 
 def fine_map(u0, theta, problem):

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -18,16 +19,32 @@ using namespace prk;
 
 namespace {
 
-thread_local std::string g_err;
+// Message of the last failure on this thread: a fixed buffer, so that
+// recording an error can never throw.
+thread_local char g_err[512];
 
 pr_status fail(pr_status st, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
   va_end(ap);
-  g_err = buf;
   return st;
+}
+
+// Every entry point of the C ABI runs its body through guarded(): a C++
+// exception (a host allocation inside std::vector, say) becomes a status and
+// never unwinds into the caller.
+template <class Fn>
+pr_status guarded(Fn&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(PR_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(PR_EDEVICE, "internal error: %s", e.what());
+  } catch (...) {
+    return fail(PR_EDEVICE, "internal error: unknown C++ exception");
+  }
 }
 
 #define HIPOK(expr)                                                                  \
@@ -1486,455 +1503,514 @@ pr_status apply_layout(pr_problem_s* P, int lanes_cap, int M) {
   return build_schedules(P);
 }
 
-}  // namespace
 
-extern "C" {
+// ------------------------------------------------------ serial adjoint ---
+// Workspace of the serial adjoint: the post-x (W) and post-y (V) states of
+// every fine step of one slice, lambda, mu, the face-gradient accumulators and
+// the slice-boundary checkpoints.
+struct AdjWork {
+  double *W, *V, *lam, *mu, *gax, *gay, *ckpt;
+};
 
-const char* pr_last_error(void) { return g_err.c_str(); }
-
-pr_status pr_profile_control(pr_problem p, int mode) {
-  if (!p) return fail(PR_EINVAL, "NULL handle");
-  if (mode == 0 || mode == 1) {
-    p->prof = mode == 1;
-  } else if (mode == 2) {
-    pr_profile z{};
-    p->acc = z;
-    HIPOK(hipDeviceSynchronize());
-    for (auto& r : p->recs) {
-      p->ev_free.push_back(r.a);
-      p->ev_free.push_back(r.b);
-    }
-    p->recs.clear();
-  } else {
-    return fail(PR_EINVAL, "mode must be 0, 1 or 2");
-  }
-  return PR_OK;
-}
-
-pr_status pr_profile_read(pr_problem p, pr_profile* out) {
-  if (!p || !out) return fail(PR_EINVAL, "NULL argument");
-  for (auto& r : p->recs) {
-    HIPOK(hipEventSynchronize(r.b));
-    float ms = 0.f;
-    HIPOK(hipEventElapsedTime(&ms, r.a, r.b));
-    p->acc.ms[r.phase] += ms;
-    p->acc.count[r.phase] += 1;
-    p->ev_free.push_back(r.a);
-    p->ev_free.push_back(r.b);
-  }
-  p->recs.clear();
-  *out = p->acc;
-  return PR_OK;
-}
-
-pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void* hip_stream,
-                            pr_problem* out) {
-  if (!out) return fail(PR_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!descs || n_instances < 1) return fail(PR_EINVAL, "need at least one descriptor");
-  for (int i = 0; i < n_instances; i++) {
-    pr_status st = validate(descs[i], i);
-    if (st != PR_OK) return st;
-  }
-  hipStream_t s = as_stream(hip_stream);
-  std::unique_ptr<pr_problem_s> P(new (std::nothrow) pr_problem_s());
-  if (!P) return fail(PR_ENOMEM, "host allocation failed");
-  size_t ou = 0, osl = 0, ost = 0;
-  for (int i = 0; i < n_instances; i++) {
-    auto I = std::make_unique<Instance>();
-    I->d = descs[i];
-    I->d.coef_x = I->d.coef_y = I->d.rho = nullptr;
-    const size_t npts = (size_t)descs[i].nx * descs[i].ny;
-    I->off_u0 = ou; I->off_slices = osl; I->off_states = ost;
-    ou += npts; osl += npts * descs[i].n_slices; ost += npts * (descs[i].n_slices + 1);
-    pr_status st;
-    if (descs[i].split == PR_SPLIT_DD && descs[i].dim == 2) {
-      st = setup_dd2_instance(*I, descs[i].rho, s);
-      if (st != PR_OK) return st;
-      st = factorize_dd2_instance(*I, descs[i].coef_x, descs[i].coef_y, s);
-    } else if (descs[i].split == PR_SPLIT_DD) {
-      st = setup_dd_instance(P.get(), *I, descs[i].rho, s);
-      if (st != PR_OK) return st;
-      st = factorize_dd_instance(*I, descs[i].coef_x, s);
-    } else {
-      st = setup_dim_instance(P.get(), *I, s);
-      if (st != PR_OK) return st;
-      st = factorize_instance(P.get(), *I, descs[i].coef_x, descs[i].coef_y, s);
-    }
-    if (st != PR_OK) return st;
-    P->inst.push_back(std::move(I));
-  }
-  P->tot_u0 = ou; P->tot_slices = osl; P->tot_states = ost;
-  HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_active), n_instances * sizeof(int)));
-  HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_inst), n_instances * sizeof(DimInst)));
-  for (int i = 0; i < n_instances; i++) {
-    DimInst& h = P->inst[i]->h;
-    h.idx = i;
-    h.cs = P->inst[i]->d.coarse_steps;
-    h.npts = P->inst[i]->npts;
-    h.off_slices = (long)P->inst[i]->off_slices;
-    h.off_states = (long)P->inst[i]->off_states;
-    h.active = P->d_active;
-  }
-  // per-block increment maxima of the coarse sweeps: one per column block of
-  // the batched y launches, one per block of the DD update kernel
-  for (auto& I : P->inst) {
-    I->h.n_incp = I->dd ? update_blocks(I->npts)
-                        : (I->d.nx + kCoarseColsPerBlock - 1) / kCoarseColsPerBlock;
-    P->n_incp += I->h.n_incp;
-  }
-  HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_incp), P->n_incp * sizeof(unsigned long long)));
-  {
-    size_t o = 0;
-    for (auto& I : P->inst) {
-      I->h.incp = P->d_incp + o;
-      o += I->h.n_incp;
-    }
-  }
-  {
-    pr_status st = set_all_active(P.get(), s);
-    if (st != PR_OK) return st;
-    st = build_schedules(P.get());
-    if (st != PR_OK) return st;
-  }
-  HIPOK(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
-  // parareal workspace
-  HIPOK(P->F.alloc(osl));
-  HIPOK(P->Gold.alloc(osl));
-  HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_inc), n_instances * sizeof(unsigned long long)));
-  HIPOK(hipHostMalloc(reinterpret_cast<void**>(&P->h_inc), n_instances * sizeof(double)));
-  HIPOK(hipStreamSynchronize(s));
-  *out = P.release();
-  return PR_OK;
-}
-
-pr_status pr_destroy_problem(pr_problem p) {
-  if (!p) return PR_OK;
-  (void)hipDeviceSynchronize();
-  delete p;
-  return PR_OK;
-}
-
-pr_status pr_num_instances(pr_problem p, int* n) {
-  if (!p || !n) return fail(PR_EINVAL, "NULL argument");
-  *n = (int)p->inst.size();
-  return PR_OK;
-}
-
-pr_status pr_query_layout(pr_problem p, pr_instance_layout* per, size_t* totals) {
-  if (!p) return fail(PR_EINVAL, "NULL handle");
-  if (per)
-    for (size_t i = 0; i < p->inst.size(); i++) {
-      const Instance& I = *p->inst[i];
-      per[i].u0_offset = I.off_u0;
-      per[i].slices_offset = I.off_slices;
-      per[i].states_offset = I.off_states;
-      per[i].npts = I.npts;
-      per[i].n_slices = I.d.n_slices;
-    }
-  if (totals) {
-    totals[0] = p->tot_u0;
-    totals[1] = p->tot_slices;
-    totals[2] = p->tot_states;
-  }
-  return PR_OK;
-}
-
-pr_status pr_set_coefficients(pr_problem p, int instance, const double* coef_x,
-                              const double* coef_y, void* hip_stream) {
-  if (!p) return fail(PR_EINVAL, "NULL handle");
-  if (instance < 0 || instance >= (int)p->inst.size()) return fail(PR_EINVAL, "bad instance");
-  Instance& I = *p->inst[instance];
-  if (!coef_x || (I.d.dim == 2 && I.d.coef_mode == PR_COEF_FACES && !coef_y))
-    return fail(PR_EINVAL, "NULL coefficient pointer");
-  if (p->adjT) {  // the transposed problem of the parallel adjoint is rebuilt on demand
-    (void)hipDeviceSynchronize();
-    delete p->adjT;
-    p->adjT = nullptr;
-  }
-  if (I.dd2) return factorize_dd2_instance(I, coef_x, coef_y, as_stream(hip_stream));
-  if (I.dd) return factorize_dd_instance(I, coef_x, as_stream(hip_stream));
-  return factorize_instance(p, I, coef_x, coef_y, as_stream(hip_stream));
-}
-
-pr_status pr_fine_propagate(pr_problem p, const double* U_in, double* F_out, void* hip_stream) {
-  if (!p || !U_in || !F_out) return fail(PR_EINVAL, "NULL argument");
-  if (U_in == F_out) return fail(PR_EINVAL, "U_in and F_out must not overlap");
-  return fine_all(p, U_in, false, F_out, as_stream(hip_stream));
-}
-
-pr_status pr_coarse_sweep(pr_problem p, const double* F, double* G_old, double* U, double* inc_dev,
-                          void* hip_stream) {
-  if (!p || !G_old || !U) return fail(PR_EINVAL, "NULL argument");
-  hipStream_t s = as_stream(hip_stream);
-  return coarse_sweep_impl(p, F, G_old, U, reinterpret_cast<unsigned long long*>(inc_dev), s,
-                           nullptr);
-}
-
-pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_max, double tol,
-                              int* k_done, double* inc, void* hip_stream) {
-  if (!p || !u0 || !U || !k_done || !inc) return fail(PR_EINVAL, "NULL argument");
-  if (k_max < 0) return fail(PR_EINVAL, "k_max must be >= 0");
-  if (!(tol >= 0)) return fail(PR_EINVAL, "tol must be >= 0");
-  // the work runs on the library's stream once the caller's stream has drained
-  HIPOK(hipStreamSynchronize(as_stream(hip_stream)));
-  hipStream_t s = p->gstream;
-  const int n = (int)p->inst.size();
-  pr_status st = set_all_active(p, s);
-  if (st != PR_OK) return st;
-  for (int i = 0; i < n; i++) {
-    Instance& I = *p->inst[i];
-    HIPOK(launch_copy(u0 + I.off_u0, U + I.off_states, I.npts, s));
-    k_done[i] = 0;
-    inc[i] = 0.0;
-  }
-  st = coarse_sweep_impl(p, nullptr, p->Gold.p, U, p->d_inc, s, nullptr);  // initial guess
-  if (st != PR_OK) return st;
-  std::vector<char> active(n, 1);
-  int n_active = n;
-  // one parareal correction: F on all active slices, coarse sweep with the
-  // correction and increment, device mask update, increment to the host
-  auto correction = [&]() -> pr_status {
-    pr_status r = fine_all(p, U, true, p->F.p, s);
-    if (r != PR_OK) return r;
-    r = coarse_sweep_impl(p, p->F.p, p->Gold.p, U, p->d_inc, s, &active);
-    if (r != PR_OK) return r;
-    HIPOK(launch_mask_update(reinterpret_cast<const double*>(p->d_inc), p->d_active, n, tol, s));
-    HIPOK(hipMemcpyAsync(p->h_inc, p->d_inc, n * sizeof(double), hipMemcpyDeviceToHost, s));
-    return PR_OK;
-  };
-  const bool graph = p->use_graph && !p->any_dd && !p->prof && k_max > 0;
-  if (graph && (!p->gexec || p->graph_tol != tol || p->graph_U != U)) {
-    if (p->gexec) {
-      (void)hipGraphExecDestroy(p->gexec);
-      p->gexec = nullptr;
-    }
-    if (p->graph) {
-      (void)hipGraphDestroy(p->graph);
-      p->graph = nullptr;
-    }
-    HIPOK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    pr_status r = correction();
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &g);
-    if (r != PR_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return r;
-    }
-    HIPOK(e);
-    p->graph = g;
-    HIPOK(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
-    p->graph_tol = tol;
-    p->graph_U = U;
-  }
-  pr_status result = PR_OK;
-  for (int k = 0; k < k_max && n_active > 0; k++) {
-    if (graph) {
-      HIPOK(hipGraphLaunch(p->gexec, s));
-    } else {
-      st = correction();
-      if (st != PR_OK) return st;
-    }
-    HIPOK(hipStreamSynchronize(s));
-    for (int i = 0; i < n; i++) {
-      if (!active[i]) continue;
-      const double v = p->h_inc[i];
-      k_done[i] = k + 1;
-      inc[i] = v;
-      if (!std::isfinite(v)) result = fail(PR_ENUMERIC, "instance %d: non-finite increment", i);
-      if (v < tol) {
-        active[i] = 0;
-        n_active--;
-      }
-    }
-    if (result != PR_OK) break;
-  }
-  st = set_all_active(p, s);
-  if (st != PR_OK) return st;
-  return result;
-}
-
-pr_status pr_set_option(pr_problem p, int option, int value) {
-  if (!p) return fail(PR_EINVAL, "NULL handle");
-  switch (option) {
-    case PR_OPT_GRAPH:
-      if (value != 0 && value != 1) return fail(PR_EINVAL, "graph option must be 0 or 1");
-      p->use_graph = value == 1;
-      return PR_OK;
-    case PR_OPT_FINE_CHUNK:
-      if (value != 16 && value != 32) return fail(PR_EINVAL, "fine chunk must be 16 or 32");
-      return apply_layout(p, p->lanes_cap, value);
-    case PR_OPT_LANES:
-      if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
-        return fail(PR_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
-      return apply_layout(p, value, p->M);
-    case PR_OPT_BLOCKS_PER_PASS:
-      if (value < 0) return fail(PR_EINVAL, "blocks per pass must be >= 0");
-      p->blocks_per_pass = value;
-      return apply_layout(p, p->lanes_cap, p->M);
-    default:
-      return fail(PR_EINVAL, "unknown option %d", option);
-  }
-}
-
-pr_status pr_get_option(pr_problem p, int option, int* value) {
-  if (!p || !value) return fail(PR_EINVAL, "NULL argument");
-  switch (option) {
-    case PR_OPT_GRAPH: *value = p->use_graph ? 1 : 0; return PR_OK;
-    case PR_OPT_FINE_CHUNK: *value = p->M; return PR_OK;
-    case PR_OPT_LANES: *value = p->lanes_cap; return PR_OK;
-    case PR_OPT_BLOCKS_PER_PASS: *value = p->blocks_per_pass; return PR_OK;
-    default: return fail(PR_EINVAL, "unknown option %d", option);
-  }
-}
-
-pr_status pr_autotune(pr_problem p, void* hip_stream, int* lanes, int* chunk, float* best_ms) {
-  if (!p) return fail(PR_EINVAL, "NULL handle");
-  hipStream_t s = as_stream(hip_stream);
-  int Lmax = 8;
-  for (auto& I : p->inst)
-    if (!I->dd) Lmax = std::max(Lmax, I->Ldef);
-  hipEvent_t e0, e1;
-  HIPOK(hipEventCreate(&e0));
-  HIPOK(hipEventCreate(&e1));
-  float best = -1.f;
-  int bl = p->lanes_cap, bm = p->M;
-  const bool prof = p->prof;
-  p->prof = false;
-  pr_status st = PR_OK;
-  for (int L = 8; L <= Lmax && st == PR_OK; L <<= 1)
-    for (int M : {16, 32}) {
-      st = apply_layout(p, L == Lmax ? 0 : L, M);
-      if (st != PR_OK) break;
-      float ms_min = -1.f;
-      for (int rep = 0; rep < 3 && st == PR_OK; rep++) {
-        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(PR_EDEVICE, "event record"); break; }
-        st = fine_all(p, p->Gold.p, false, p->F.p, s);
-        if (st != PR_OK) break;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-          st = fail(PR_EDEVICE, "event sync");
-          break;
-        }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0 && (ms_min < 0 || ms < ms_min)) ms_min = ms;  // first run warms up
-      }
-      if (st == PR_OK && (best < 0 || ms_min < best)) {
-        best = ms_min;
-        bl = L == Lmax ? 0 : L;
-        bm = M;
-      }
-    }
-  p->prof = prof;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st != PR_OK) return st;
-  st = apply_layout(p, bl, bm);
-  if (st != PR_OK) return st;
-  if (lanes) *lanes = bl;
-  if (chunk) *chunk = bm;
-  if (best_ms) *best_ms = best;
-  return PR_OK;
-}
-
-pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hip_stream) {
-  if (!p || !u0 || !U) return fail(PR_EINVAL, "NULL argument");
-  hipStream_t s = as_stream(hip_stream);
-  const int n = (int)p->inst.size();
-  for (int i = 0; i < n; i++) {
-    Instance& I = *p->inst[i];
-    const DimInst* dI = p->d_inst + i;
-    HIPOK(launch_copy(u0 + I.off_u0, U + I.off_states, I.npts, s));
-    if (I.dd) {
-      for (int k = 0; k < I.d.n_slices; k++) {
-        HIPOK(launch_copy(U + I.off_states + (size_t)k * I.npts, I.tmp.p, I.npts, s));
-        for (int t = 0; t < I.d.fine_steps; t++) {
-          if (I.dd2) {
-            pr_status st = dd2_step_single(p, i, false, (long)k * I.d.fine_steps + t, s);
-            if (st != PR_OK) return st;
-            continue;
-          }
-          if (I.h.nforce)
-            HIPOK(launch_force_state(dI, I.h, I.tmp.p, I.fgf.p, (long)k * I.d.fine_steps + t,
-                                     (long)I.d.n_slices * I.d.fine_steps, s));
-          pr_status st = dd_fie_step(p, I, false, 1, 0, s);
-          if (st != PR_OK) return st;
-        }
-        HIPOK(launch_copy(I.tmp.p, U + I.off_states + (size_t)(k + 1) * I.npts, I.npts, s));
-      }
-      continue;
-    }
-    pr_status st = seq_fine_dim(p, i, u0 + I.off_u0, U + I.off_states, s);
-    if (st != PR_OK) return st;
-  }
-  return PR_OK;
-}
-
-pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, double* grad_u0,
-                     double* grad_coef, double* U_ckpt, void* hip_stream) {
+pr_status check_adjoint_args(pr_problem_s* p, const double* u0, const double* lambda_T,
+                             const double* grad_u0, const double* grad_coef, const char* who) {
   if (!p || !u0 || !lambda_T || !grad_u0 || !grad_coef) return fail(PR_EINVAL, "NULL argument");
-  if (p->inst.size() != 1) return fail(PR_EUNSUPPORTED, "pr_adjoint needs a single-instance handle");
-  Instance& I = *p->inst[0];
+  if (p->inst.size() != 1) return fail(PR_EUNSUPPORTED, "%s needs a single-instance handle", who);
+  const Instance& I = *p->inst[0];
   if (I.dd || I.d.dim != 2)
-    return fail(PR_EUNSUPPORTED, "pr_adjoint supports 2D dimensional splitting");
+    return fail(PR_EUNSUPPORTED, "%s supports 2D dimensional splitting", who);
   if (I.d.fine != PR_FIE)
-    return fail(PR_EUNSUPPORTED, "pr_adjoint supports the FIE fine propagator only");
-  hipStream_t s = as_stream(hip_stream);
+    return fail(PR_EUNSUPPORTED, "%s supports the FIE fine propagator only", who);
+  return PR_OK;
+}
+
+// Adjoint of the fine map (transpose of eq. FIE_method, in reverse substep
+// order): forward checkpoints at the slice boundaries, then per slice in
+// reverse the recompute of its W and V states and its reverse steps, each
+// followed by the face-gradient accumulation; the theta chain rule (or a copy
+// of the face gradients) at the end. Every part of w is written before it is
+// read; the accumulators are cleared here.
+pr_status adjoint_serial(pr_problem_s* p, const double* u0, const double* lambda_T,
+                         double* grad_u0, double* grad_coef, const AdjWork& w, hipStream_t s) {
+  Instance& I = *p->inst[0];
   const int nx = I.d.nx, ny = I.d.ny, N = I.d.n_slices, S = I.d.fine_steps;
   const size_t npts = I.npts;
-  // workspace: post-x and post-y states of one slice's fine steps, checkpoints, lambda, mu
-  if (I.adjWV.n != 2 * (size_t)S * npts) HIPOK(I.adjWV.alloc(2 * (size_t)S * npts));
-  if (!U_ckpt && I.adjCkpt.n != (size_t)(N + 1) * npts) HIPOK(I.adjCkpt.alloc((size_t)(N + 1) * npts));
-  if (I.adjLam.n != npts) HIPOK(I.adjLam.alloc(npts));
-  if (I.adjMu.n != npts) HIPOK(I.adjMu.alloc(npts));
-  if (I.adjGax.n != (size_t)ny * (nx + 1)) HIPOK(I.adjGax.alloc((size_t)ny * (nx + 1)));
-  if (I.adjGay.n != (size_t)(ny + 1) * nx) HIPOK(I.adjGay.alloc((size_t)(ny + 1) * nx));
-  double* ckpt = U_ckpt ? U_ckpt : I.adjCkpt.p;
+  const size_t ngx = (size_t)ny * (nx + 1), ngy = (size_t)(ny + 1) * nx;
   const DimInst* dI = p->d_inst;
-  // forward: checkpoints at the slice boundaries
-  pr_status st = seq_fine_dim(p, 0, u0, ckpt, s);
+  pr_status st = seq_fine_dim(p, 0, u0, w.ckpt, s);
   if (st != PR_OK) return st;
-  HIPOK(launch_fill_zero(I.adjGax.p, I.adjGax.n, s));
-  HIPOK(launch_fill_zero(I.adjGay.p, I.adjGay.n, s));
-  HIPOK(launch_copy(lambda_T, I.adjLam.p, npts, s));
+  HIPOK(launch_fill_zero(w.gax, ngx, s));
+  HIPOK(launch_fill_zero(w.gay, ngy, s));
+  HIPOK(launch_copy(lambda_T, w.lam, npts, s));
   const double hx = 1.0 / (nx + 1), hy = 1.0 / (ny + 1);
   const double cx = I.dt / (hx * hx), cy = I.dt / (hy * hy);
-  double* Wst = I.adjWV.p;                       // W_t = state after the x substep of step t
-  double* Vst = I.adjWV.p + (size_t)S * npts;    // V_t = state after the y substep
   for (int n = N - 1; n >= 0; n--) {
     // recompute the slice's fine steps from its checkpoint
     for (int t = 0; t < S; t++) {
-      const double* prev = t == 0 ? ckpt + (size_t)n * npts : Vst + (size_t)(t - 1) * npts;
+      const double* prev = t == 0 ? w.ckpt + (size_t)n * npts : w.V + (size_t)(t - 1) * npts;
       {
         PhaseTimer pt(p, PH_COARSE_X, s);
-        HIPOK(launch_coarse_x(dI, I.h, prev, Wst + (size_t)t * npts, true, s,
+        HIPOK(launch_coarse_x(dI, I.h, prev, w.W + (size_t)t * npts, true, s,
                               I.h.nforce ? I.fgf.p : nullptr, (long)n * S + t, (long)N * S));
       }
       PhaseTimer pt(p, PH_COARSE_Y, s);
-      HIPOK(launch_coarse_y(dI, I.h, Wst + (size_t)t * npts, Vst + (size_t)t * npts, true, s));
+      HIPOK(launch_coarse_y(dI, I.h, w.W + (size_t)t * npts, w.V + (size_t)t * npts, true, s));
     }
     // reverse the steps: transposed (= same, symmetric) solves in reverse substep order
     for (int t = S - 1; t >= 0; t--) {
       {
         PhaseTimer pt(p, PH_COARSE_Y, s);
-        HIPOK(launch_coarse_y(dI, I.h, I.adjLam.p, I.adjMu.p, true, s));
+        HIPOK(launch_coarse_y(dI, I.h, w.lam, w.mu, true, s));
       }
-      HIPOK(launch_face_grad_y(I.adjMu.p, Vst + (size_t)t * npts, nx, ny, cy, I.adjGay.p, s));
+      HIPOK(launch_face_grad_y(w.mu, w.V + (size_t)t * npts, nx, ny, cy, w.gay, s));
       {
         PhaseTimer pt(p, PH_COARSE_X, s);
-        HIPOK(launch_coarse_x(dI, I.h, I.adjMu.p, I.adjLam.p, true, s));
+        HIPOK(launch_coarse_x(dI, I.h, w.mu, w.lam, true, s));
       }
-      HIPOK(launch_face_grad_x(I.adjLam.p, Wst + (size_t)t * npts, nx, ny, cx, I.adjGax.p, s));
+      HIPOK(launch_face_grad_x(w.lam, w.W + (size_t)t * npts, nx, ny, cx, w.gax, s));
     }
   }
-  HIPOK(launch_copy(I.adjLam.p, grad_u0, npts, s));
+  HIPOK(launch_copy(w.lam, grad_u0, npts, s));
   if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
-    HIPOK(launch_theta_chain(I.theta.p, I.adjGax.p, I.adjGay.p, nx, ny, grad_coef, s));
+    HIPOK(launch_theta_chain(I.theta.p, w.gax, w.gay, nx, ny, grad_coef, s));
   } else {
-    HIPOK(launch_copy(I.adjGax.p, grad_coef, I.adjGax.n, s));
-    HIPOK(launch_copy(I.adjGay.p, grad_coef + I.adjGax.n, I.adjGay.n, s));
+    HIPOK(launch_copy(w.gax, grad_coef, ngx, s));
+    HIPOK(launch_copy(w.gay, grad_coef + ngx, ngy, s));
   }
   return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pr_last_error(void) { return g_err; }
+
+pr_status pr_profile_control(pr_problem p, int mode) {
+  return guarded([&]() -> pr_status {
+    if (!p) return fail(PR_EINVAL, "NULL handle");
+    if (mode == 0 || mode == 1) {
+      p->prof = mode == 1;
+    } else if (mode == 2) {
+      pr_profile z{};
+      p->acc = z;
+      HIPOK(hipDeviceSynchronize());
+      for (auto& r : p->recs) {
+        p->ev_free.push_back(r.a);
+        p->ev_free.push_back(r.b);
+      }
+      p->recs.clear();
+    } else {
+      return fail(PR_EINVAL, "mode must be 0, 1 or 2");
+    }
+    return PR_OK;
+  });
+}
+
+pr_status pr_profile_read(pr_problem p, pr_profile* out) {
+  return guarded([&]() -> pr_status {
+    if (!p || !out) return fail(PR_EINVAL, "NULL argument");
+    for (auto& r : p->recs) {
+      HIPOK(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      HIPOK(hipEventElapsedTime(&ms, r.a, r.b));
+      p->acc.ms[r.phase] += ms;
+      p->acc.count[r.phase] += 1;
+      p->ev_free.push_back(r.a);
+      p->ev_free.push_back(r.b);
+    }
+    p->recs.clear();
+    *out = p->acc;
+    return PR_OK;
+  });
+}
+
+pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void* hip_stream,
+                            pr_problem* out) {
+  return guarded([&]() -> pr_status {
+    if (!out) return fail(PR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!descs || n_instances < 1) return fail(PR_EINVAL, "need at least one descriptor");
+    for (int i = 0; i < n_instances; i++) {
+      pr_status st = validate(descs[i], i);
+      if (st != PR_OK) return st;
+    }
+    hipStream_t s = as_stream(hip_stream);
+    std::unique_ptr<pr_problem_s> P(new (std::nothrow) pr_problem_s());
+    if (!P) return fail(PR_ENOMEM, "host allocation failed");
+    size_t ou = 0, osl = 0, ost = 0;
+    for (int i = 0; i < n_instances; i++) {
+      auto I = std::make_unique<Instance>();
+      I->d = descs[i];
+      I->d.coef_x = I->d.coef_y = I->d.rho = nullptr;
+      const size_t npts = (size_t)descs[i].nx * descs[i].ny;
+      I->off_u0 = ou; I->off_slices = osl; I->off_states = ost;
+      ou += npts; osl += npts * descs[i].n_slices; ost += npts * (descs[i].n_slices + 1);
+      pr_status st;
+      if (descs[i].split == PR_SPLIT_DD && descs[i].dim == 2) {
+        st = setup_dd2_instance(*I, descs[i].rho, s);
+        if (st != PR_OK) return st;
+        st = factorize_dd2_instance(*I, descs[i].coef_x, descs[i].coef_y, s);
+      } else if (descs[i].split == PR_SPLIT_DD) {
+        st = setup_dd_instance(P.get(), *I, descs[i].rho, s);
+        if (st != PR_OK) return st;
+        st = factorize_dd_instance(*I, descs[i].coef_x, s);
+      } else {
+        st = setup_dim_instance(P.get(), *I, s);
+        if (st != PR_OK) return st;
+        st = factorize_instance(P.get(), *I, descs[i].coef_x, descs[i].coef_y, s);
+      }
+      if (st != PR_OK) return st;
+      P->inst.push_back(std::move(I));
+    }
+    P->tot_u0 = ou; P->tot_slices = osl; P->tot_states = ost;
+    HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_active), n_instances * sizeof(int)));
+    HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_inst), n_instances * sizeof(DimInst)));
+    for (int i = 0; i < n_instances; i++) {
+      DimInst& h = P->inst[i]->h;
+      h.idx = i;
+      h.cs = P->inst[i]->d.coarse_steps;
+      h.npts = P->inst[i]->npts;
+      h.off_slices = (long)P->inst[i]->off_slices;
+      h.off_states = (long)P->inst[i]->off_states;
+      h.active = P->d_active;
+    }
+    // per-block increment maxima of the coarse sweeps: one per column block of
+    // the batched y launches, one per block of the DD update kernel
+    for (auto& I : P->inst) {
+      I->h.n_incp = I->dd ? update_blocks(I->npts)
+                          : (I->d.nx + kCoarseColsPerBlock - 1) / kCoarseColsPerBlock;
+      P->n_incp += I->h.n_incp;
+    }
+    HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_incp), P->n_incp * sizeof(unsigned long long)));
+    {
+      size_t o = 0;
+      for (auto& I : P->inst) {
+        I->h.incp = P->d_incp + o;
+        o += I->h.n_incp;
+      }
+    }
+    {
+      pr_status st = set_all_active(P.get(), s);
+      if (st != PR_OK) return st;
+      st = build_schedules(P.get());
+      if (st != PR_OK) return st;
+    }
+    HIPOK(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
+    // parareal workspace
+    HIPOK(P->F.alloc(osl));
+    HIPOK(P->Gold.alloc(osl));
+    HIPOK(hipMalloc(reinterpret_cast<void**>(&P->d_inc), n_instances * sizeof(unsigned long long)));
+    HIPOK(hipHostMalloc(reinterpret_cast<void**>(&P->h_inc), n_instances * sizeof(double)));
+    HIPOK(hipStreamSynchronize(s));
+    *out = P.release();
+    return PR_OK;
+  });
+}
+
+pr_status pr_destroy_problem(pr_problem p) {
+  return guarded([&]() -> pr_status {
+    if (!p) return PR_OK;
+    (void)hipDeviceSynchronize();
+    delete p;
+    return PR_OK;
+  });
+}
+
+pr_status pr_num_instances(pr_problem p, int* n) {
+  return guarded([&]() -> pr_status {
+    if (!p || !n) return fail(PR_EINVAL, "NULL argument");
+    *n = (int)p->inst.size();
+    return PR_OK;
+  });
+}
+
+pr_status pr_query_layout(pr_problem p, pr_instance_layout* per, size_t* totals) {
+  return guarded([&]() -> pr_status {
+    if (!p) return fail(PR_EINVAL, "NULL handle");
+    if (per)
+      for (size_t i = 0; i < p->inst.size(); i++) {
+        const Instance& I = *p->inst[i];
+        per[i].u0_offset = I.off_u0;
+        per[i].slices_offset = I.off_slices;
+        per[i].states_offset = I.off_states;
+        per[i].npts = I.npts;
+        per[i].n_slices = I.d.n_slices;
+      }
+    if (totals) {
+      totals[0] = p->tot_u0;
+      totals[1] = p->tot_slices;
+      totals[2] = p->tot_states;
+    }
+    return PR_OK;
+  });
+}
+
+pr_status pr_set_coefficients(pr_problem p, int instance, const double* coef_x,
+                              const double* coef_y, void* hip_stream) {
+  return guarded([&]() -> pr_status {
+    if (!p) return fail(PR_EINVAL, "NULL handle");
+    if (instance < 0 || instance >= (int)p->inst.size()) return fail(PR_EINVAL, "bad instance");
+    Instance& I = *p->inst[instance];
+    if (!coef_x || (I.d.dim == 2 && I.d.coef_mode == PR_COEF_FACES && !coef_y))
+      return fail(PR_EINVAL, "NULL coefficient pointer");
+    if (p->adjT) {  // the transposed problem of the parallel adjoint is rebuilt on demand
+      (void)hipDeviceSynchronize();
+      delete p->adjT;
+      p->adjT = nullptr;
+    }
+    if (I.dd2) return factorize_dd2_instance(I, coef_x, coef_y, as_stream(hip_stream));
+    if (I.dd) return factorize_dd_instance(I, coef_x, as_stream(hip_stream));
+    return factorize_instance(p, I, coef_x, coef_y, as_stream(hip_stream));
+  });
+}
+
+pr_status pr_fine_propagate(pr_problem p, const double* U_in, double* F_out, void* hip_stream) {
+  return guarded([&]() -> pr_status {
+    if (!p || !U_in || !F_out) return fail(PR_EINVAL, "NULL argument");
+    if (U_in == F_out) return fail(PR_EINVAL, "U_in and F_out must not overlap");
+    return fine_all(p, U_in, false, F_out, as_stream(hip_stream));
+  });
+}
+
+pr_status pr_coarse_sweep(pr_problem p, const double* F, double* G_old, double* U, double* inc_dev,
+                          void* hip_stream) {
+  return guarded([&]() -> pr_status {
+    if (!p || !G_old || !U) return fail(PR_EINVAL, "NULL argument");
+    hipStream_t s = as_stream(hip_stream);
+    return coarse_sweep_impl(p, F, G_old, U, reinterpret_cast<unsigned long long*>(inc_dev), s,
+                             nullptr);
+  });
+}
+
+pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_max, double tol,
+                              int* k_done, double* inc, void* hip_stream) {
+  return guarded([&]() -> pr_status {
+    if (!p || !u0 || !U || !k_done || !inc) return fail(PR_EINVAL, "NULL argument");
+    if (k_max < 0) return fail(PR_EINVAL, "k_max must be >= 0");
+    if (!(tol >= 0)) return fail(PR_EINVAL, "tol must be >= 0");
+    // the work runs on the library's stream once the caller's stream has drained
+    HIPOK(hipStreamSynchronize(as_stream(hip_stream)));
+    hipStream_t s = p->gstream;
+    const int n = (int)p->inst.size();
+    pr_status st = set_all_active(p, s);
+    if (st != PR_OK) return st;
+    for (int i = 0; i < n; i++) {
+      Instance& I = *p->inst[i];
+      HIPOK(launch_copy(u0 + I.off_u0, U + I.off_states, I.npts, s));
+      k_done[i] = 0;
+      inc[i] = 0.0;
+    }
+    st = coarse_sweep_impl(p, nullptr, p->Gold.p, U, p->d_inc, s, nullptr);  // initial guess
+    if (st != PR_OK) return st;
+    std::vector<char> active(n, 1);
+    int n_active = n;
+    // one parareal correction: F on all active slices, coarse sweep with the
+    // correction and increment, device mask update, increment to the host
+    auto correction = [&]() -> pr_status {
+      pr_status r = fine_all(p, U, true, p->F.p, s);
+      if (r != PR_OK) return r;
+      r = coarse_sweep_impl(p, p->F.p, p->Gold.p, U, p->d_inc, s, &active);
+      if (r != PR_OK) return r;
+      HIPOK(launch_mask_update(reinterpret_cast<const double*>(p->d_inc), p->d_active, n, tol, s));
+      HIPOK(hipMemcpyAsync(p->h_inc, p->d_inc, n * sizeof(double), hipMemcpyDeviceToHost, s));
+      return PR_OK;
+    };
+    const bool graph = p->use_graph && !p->any_dd && !p->prof && k_max > 0;
+    if (graph && (!p->gexec || p->graph_tol != tol || p->graph_U != U)) {
+      if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+      }
+      if (p->graph) {
+        (void)hipGraphDestroy(p->graph);
+        p->graph = nullptr;
+      }
+      HIPOK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      pr_status r = correction();
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(s, &g);
+      if (r != PR_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+      }
+      HIPOK(e);
+      p->graph = g;
+      HIPOK(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+      p->graph_tol = tol;
+      p->graph_U = U;
+    }
+    pr_status result = PR_OK;
+    for (int k = 0; k < k_max && n_active > 0; k++) {
+      if (graph) {
+        HIPOK(hipGraphLaunch(p->gexec, s));
+      } else {
+        st = correction();
+        if (st != PR_OK) return st;
+      }
+      HIPOK(hipStreamSynchronize(s));
+      for (int i = 0; i < n; i++) {
+        if (!active[i]) continue;
+        const double v = p->h_inc[i];
+        k_done[i] = k + 1;
+        inc[i] = v;
+        if (!std::isfinite(v)) result = fail(PR_ENUMERIC, "instance %d: non-finite increment", i);
+        if (v < tol) {
+          active[i] = 0;
+          n_active--;
+        }
+      }
+      if (result != PR_OK) break;
+    }
+    st = set_all_active(p, s);
+    if (st != PR_OK) return st;
+    return result;
+  });
+}
+
+pr_status pr_set_option(pr_problem p, int option, int value) {
+  return guarded([&]() -> pr_status {
+    if (!p) return fail(PR_EINVAL, "NULL handle");
+    switch (option) {
+      case PR_OPT_GRAPH:
+        if (value != 0 && value != 1) return fail(PR_EINVAL, "graph option must be 0 or 1");
+        p->use_graph = value == 1;
+        return PR_OK;
+      case PR_OPT_FINE_CHUNK:
+        if (value != 16 && value != 32) return fail(PR_EINVAL, "fine chunk must be 16 or 32");
+        return apply_layout(p, p->lanes_cap, value);
+      case PR_OPT_LANES:
+        if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
+          return fail(PR_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
+        return apply_layout(p, value, p->M);
+      case PR_OPT_BLOCKS_PER_PASS:
+        if (value < 0) return fail(PR_EINVAL, "blocks per pass must be >= 0");
+        p->blocks_per_pass = value;
+        return apply_layout(p, p->lanes_cap, p->M);
+      default:
+        return fail(PR_EINVAL, "unknown option %d", option);
+    }
+  });
+}
+
+pr_status pr_get_option(pr_problem p, int option, int* value) {
+  return guarded([&]() -> pr_status {
+    if (!p || !value) return fail(PR_EINVAL, "NULL argument");
+    switch (option) {
+      case PR_OPT_GRAPH: *value = p->use_graph ? 1 : 0; return PR_OK;
+      case PR_OPT_FINE_CHUNK: *value = p->M; return PR_OK;
+      case PR_OPT_LANES: *value = p->lanes_cap; return PR_OK;
+      case PR_OPT_BLOCKS_PER_PASS: *value = p->blocks_per_pass; return PR_OK;
+      default: return fail(PR_EINVAL, "unknown option %d", option);
+    }
+  });
+}
+
+pr_status pr_autotune(pr_problem p, void* hip_stream, int* lanes, int* chunk, float* best_ms) {
+  return guarded([&]() -> pr_status {
+    if (!p) return fail(PR_EINVAL, "NULL handle");
+    hipStream_t s = as_stream(hip_stream);
+    int Lmax = 8;
+    for (auto& I : p->inst)
+      if (!I->dd) Lmax = std::max(Lmax, I->Ldef);
+    hipEvent_t e0, e1;
+    HIPOK(hipEventCreate(&e0));
+    HIPOK(hipEventCreate(&e1));
+    float best = -1.f;
+    int bl = p->lanes_cap, bm = p->M;
+    const bool prof = p->prof;
+    p->prof = false;
+    pr_status st = PR_OK;
+    for (int L = 8; L <= Lmax && st == PR_OK; L <<= 1)
+      for (int M : {16, 32}) {
+        st = apply_layout(p, L == Lmax ? 0 : L, M);
+        if (st != PR_OK) break;
+        float ms_min = -1.f;
+        for (int rep = 0; rep < 3 && st == PR_OK; rep++) {
+          if (hipEventRecord(e0, s) != hipSuccess) { st = fail(PR_EDEVICE, "event record"); break; }
+          st = fine_all(p, p->Gold.p, false, p->F.p, s);
+          if (st != PR_OK) break;
+          if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            st = fail(PR_EDEVICE, "event sync");
+            break;
+          }
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0 && (ms_min < 0 || ms < ms_min)) ms_min = ms;  // first run warms up
+        }
+        if (st == PR_OK && (best < 0 || ms_min < best)) {
+          best = ms_min;
+          bl = L == Lmax ? 0 : L;
+          bm = M;
+        }
+      }
+    p->prof = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PR_OK) return st;
+    st = apply_layout(p, bl, bm);
+    if (st != PR_OK) return st;
+    if (lanes) *lanes = bl;
+    if (chunk) *chunk = bm;
+    if (best_ms) *best_ms = best;
+    return PR_OK;
+  });
+}
+
+pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hip_stream) {
+  return guarded([&]() -> pr_status {
+    if (!p || !u0 || !U) return fail(PR_EINVAL, "NULL argument");
+    hipStream_t s = as_stream(hip_stream);
+    const int n = (int)p->inst.size();
+    for (int i = 0; i < n; i++) {
+      Instance& I = *p->inst[i];
+      const DimInst* dI = p->d_inst + i;
+      HIPOK(launch_copy(u0 + I.off_u0, U + I.off_states, I.npts, s));
+      if (I.dd) {
+        for (int k = 0; k < I.d.n_slices; k++) {
+          HIPOK(launch_copy(U + I.off_states + (size_t)k * I.npts, I.tmp.p, I.npts, s));
+          for (int t = 0; t < I.d.fine_steps; t++) {
+            if (I.dd2) {
+              pr_status st = dd2_step_single(p, i, false, (long)k * I.d.fine_steps + t, s);
+              if (st != PR_OK) return st;
+              continue;
+            }
+            if (I.h.nforce)
+              HIPOK(launch_force_state(dI, I.h, I.tmp.p, I.fgf.p, (long)k * I.d.fine_steps + t,
+                                       (long)I.d.n_slices * I.d.fine_steps, s));
+            pr_status st = dd_fie_step(p, I, false, 1, 0, s);
+            if (st != PR_OK) return st;
+          }
+          HIPOK(launch_copy(I.tmp.p, U + I.off_states + (size_t)(k + 1) * I.npts, I.npts, s));
+        }
+        continue;
+      }
+      pr_status st = seq_fine_dim(p, i, u0 + I.off_u0, U + I.off_states, s);
+      if (st != PR_OK) return st;
+    }
+    return PR_OK;
+  });
+}
+
+pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, double* grad_u0,
+                     double* grad_coef, double* U_ckpt, void* hip_stream) {
+  return guarded([&]() -> pr_status {
+    pr_status st = check_adjoint_args(p, u0, lambda_T, grad_u0, grad_coef, "pr_adjoint");
+    if (st != PR_OK) return st;
+    Instance& I = *p->inst[0];
+    const int nx = I.d.nx, ny = I.d.ny, N = I.d.n_slices, S = I.d.fine_steps;
+    const size_t npts = I.npts;
+    // workspace: post-x and post-y states of one slice's fine steps, checkpoints, lambda, mu
+    if (I.adjWV.n != 2 * (size_t)S * npts) HIPOK(I.adjWV.alloc(2 * (size_t)S * npts));
+    if (!U_ckpt && I.adjCkpt.n != (size_t)(N + 1) * npts) HIPOK(I.adjCkpt.alloc((size_t)(N + 1) * npts));
+    if (I.adjLam.n != npts) HIPOK(I.adjLam.alloc(npts));
+    if (I.adjMu.n != npts) HIPOK(I.adjMu.alloc(npts));
+    if (I.adjGax.n != (size_t)ny * (nx + 1)) HIPOK(I.adjGax.alloc((size_t)ny * (nx + 1)));
+    if (I.adjGay.n != (size_t)(ny + 1) * nx) HIPOK(I.adjGay.alloc((size_t)(ny + 1) * nx));
+    AdjWork w{I.adjWV.p, I.adjWV.p + (size_t)S * npts, I.adjLam.p, I.adjMu.p, I.adjGax.p,
+              I.adjGay.p, U_ckpt ? U_ckpt : I.adjCkpt.p};
+    return adjoint_serial(p, u0, lambda_T, grad_u0, grad_coef, w, as_stream(hip_stream));
+  });
 }
 
 // Parallel-in-time adjoint (not in the paper; derived from the transpose of
@@ -1951,176 +2027,178 @@ pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, dou
 pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lambda_T,
                               double* grad_u0, double* grad_coef, double* U_ckpt, int k_max,
                               double tol, int* k_done, void* hip_stream) {
-  if (!p || !u0 || !lambda_T || !grad_u0 || !grad_coef) return fail(PR_EINVAL, "NULL argument");
-  if (p->inst.size() != 1)
-    return fail(PR_EUNSUPPORTED, "pr_adjoint_parallel needs a single-instance handle");
-  if (k_max < 0 || !(tol >= 0)) return fail(PR_EINVAL, "k_max must be >= 0 and tol >= 0");
-  Instance& I = *p->inst[0];
-  if (I.dd || I.d.dim != 2)
-    return fail(PR_EUNSUPPORTED, "pr_adjoint_parallel supports 2D dimensional splitting");
-  if (I.d.fine != PR_FIE)
-    return fail(PR_EUNSUPPORTED, "pr_adjoint_parallel supports the FIE fine propagator only");
-  hipStream_t s = as_stream(hip_stream);
-  const int nx = I.d.nx, ny = I.d.ny, N = I.d.n_slices, S = I.d.fine_steps;
-  const size_t npts = I.npts;
-  const DimInst& h = I.h;
-  const pr_problem_s::Group& g = p->groups.at(0);
-  HIPOK(hipStreamSynchronize(s));
-  // 1. workspaces and per-step descriptors (the library's work of earlier calls
-  //    has drained: nothing reads them while they change)
-  const size_t slabs = (size_t)h.B * h.slab;
-  const size_t nsx = (size_t)h.B * ny * h.Px * h.L, nsy = (size_t)h.B * nx * h.Py * h.L;
-  if (I.pSnap.n != 2 * (size_t)S * slabs || I.pSigX.n != (size_t)S * nsx) {
-    HIPOK(I.pSnap.alloc(2 * (size_t)S * slabs));
-    HIPOK(I.pSigX.alloc((size_t)S * nsx));
-    HIPOK(I.pSigY.alloc((size_t)S * nsy));
-    HIPOK(I.pInit.alloc(slabs));
-    HIPOK(I.pLam.alloc(slabs));
-    HIPOK(I.pSigXa.alloc(nsx));
-    HIPOK(I.pSigYa.alloc(nsy));
-  }
-  auto snap = [&](int k) { return I.pSnap.p + (size_t)k * slabs; };
-  // descriptors: [0] checkpoints, [1 + 2t] x step t, [2 + 2t] y step t,
-  // [2S + 1 + 2t] W_t, [2S + 2 + 2t] V_t, [4S + 1] adjoint workspace
-  std::vector<DimInst>& D = I.pDescHost;
-  D.assign(4 * (size_t)S + 2, h);
-  for (auto& d : D) {
-    d.active = nullptr;
-    d.zout = 0;
-  }
-  D[0].Z = I.pInit.p;
-  for (int t = 0; t < S; t++) {
-    DimInst& dx = D[1 + 2 * t];
-    dx.Z = t == 0 ? I.pInit.p : snap(2 * t - 1);
-    dx.zout = (long)(snap(2 * t) - dx.Z);
-    dx.sigY = t == 0 ? I.pSigY.p : I.pSigY.p + (size_t)(t - 1) * nsy;
-    dx.sigX = I.pSigX.p + (size_t)t * nsx;
-    DimInst& dy = D[2 + 2 * t];
-    dy.Z = snap(2 * t);
-    dy.zout = (long)(snap(2 * t + 1) - dy.Z);
-    dy.sigX = I.pSigX.p + (size_t)t * nsx;
-    dy.sigY = I.pSigY.p + (size_t)t * nsy;
-    DimInst& gw = D[2 * S + 1 + 2 * t];
-    gw.Z = snap(2 * t);
-    gw.sigX = I.pSigX.p + (size_t)t * nsx;
-    DimInst& gv = D[2 * S + 2 + 2 * t];
-    gv.Z = snap(2 * t + 1);
-    gv.sigY = I.pSigY.p + (size_t)t * nsy;
-  }
-  DimInst& da = D[4 * S + 1];
-  da.Z = I.pLam.p;
-  da.sigX = I.pSigXa.p;
-  da.sigY = I.pSigYa.p;
-  da.nforce = 0;
-  HIPOK(I.pDesc.upload(D));
-  // 2. transposed problem (once per handle): nx <-> ny, coefficients transposed
-  if (!p->adjT) {
-    pr_problem_desc dT = I.d;
-    dT.nx = ny;
-    dT.ny = nx;
-    dT.n_forcing = 0;
-    dT.forcing_space = dT.forcing_time_fine = dT.forcing_time_coarse = nullptr;
-    dT.rho = nullptr;
-    if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
-      HIPOK(I.pCoefT0.alloc((size_t)(nx + 2) * (ny + 2)));
-      HIPOK(launch_transpose_states(I.theta.p, I.pCoefT0.p, nx + 2, ny + 2, 1, s));
-      dT.coef_x = I.pCoefT0.p;
-      dT.coef_y = nullptr;
-    } else {  // x-faces of the transposed grid are the y-faces, and back
-      HIPOK(I.pCoefT0.alloc((size_t)nx * (ny + 1)));
-      HIPOK(I.pCoefT1.alloc((size_t)(nx + 1) * ny));
-      HIPOK(launch_transpose_states(I.ay.p, I.pCoefT0.p, nx, ny + 1, 1, s));
-      HIPOK(launch_transpose_states(I.ax.p, I.pCoefT1.p, nx + 1, ny, 1, s));
-      dT.coef_x = I.pCoefT0.p;
-      dT.coef_y = I.pCoefT1.p;
-    }
+  return guarded([&]() -> pr_status {
+    if (!p || !u0 || !lambda_T || !grad_u0 || !grad_coef) return fail(PR_EINVAL, "NULL argument");
+    if (p->inst.size() != 1)
+      return fail(PR_EUNSUPPORTED, "pr_adjoint_parallel needs a single-instance handle");
+    if (k_max < 0 || !(tol >= 0)) return fail(PR_EINVAL, "k_max must be >= 0 and tol >= 0");
+    Instance& I = *p->inst[0];
+    if (I.dd || I.d.dim != 2)
+      return fail(PR_EUNSUPPORTED, "pr_adjoint_parallel supports 2D dimensional splitting");
+    if (I.d.fine != PR_FIE)
+      return fail(PR_EUNSUPPORTED, "pr_adjoint_parallel supports the FIE fine propagator only");
+    hipStream_t s = as_stream(hip_stream);
+    const int nx = I.d.nx, ny = I.d.ny, N = I.d.n_slices, S = I.d.fine_steps;
+    const size_t npts = I.npts;
+    const DimInst& h = I.h;
+    const pr_problem_s::Group& g = p->groups.at(0);
     HIPOK(hipStreamSynchronize(s));
-    pr_problem hT = nullptr;
-    pr_status st = pr_create_problem(&dT, 1, hip_stream, &hT);
+    // 1. workspaces and per-step descriptors (the library's work of earlier calls
+    //    has drained: nothing reads them while they change)
+    const size_t slabs = (size_t)h.B * h.slab;
+    const size_t nsx = (size_t)h.B * ny * h.Px * h.L, nsy = (size_t)h.B * nx * h.Py * h.L;
+    if (I.pSnap.n != 2 * (size_t)S * slabs || I.pSigX.n != (size_t)S * nsx) {
+      HIPOK(I.pSnap.alloc(2 * (size_t)S * slabs));
+      HIPOK(I.pSigX.alloc((size_t)S * nsx));
+      HIPOK(I.pSigY.alloc((size_t)S * nsy));
+      HIPOK(I.pInit.alloc(slabs));
+      HIPOK(I.pLam.alloc(slabs));
+      HIPOK(I.pSigXa.alloc(nsx));
+      HIPOK(I.pSigYa.alloc(nsy));
+    }
+    auto snap = [&](int k) { return I.pSnap.p + (size_t)k * slabs; };
+    // descriptors: [0] checkpoints, [1 + 2t] x step t, [2 + 2t] y step t,
+    // [2S + 1 + 2t] W_t, [2S + 2 + 2t] V_t, [4S + 1] adjoint workspace
+    std::vector<DimInst>& D = I.pDescHost;
+    D.assign(4 * (size_t)S + 2, h);
+    for (auto& d : D) {
+      d.active = nullptr;
+      d.zout = 0;
+    }
+    D[0].Z = I.pInit.p;
+    for (int t = 0; t < S; t++) {
+      DimInst& dx = D[1 + 2 * t];
+      dx.Z = t == 0 ? I.pInit.p : snap(2 * t - 1);
+      dx.zout = (long)(snap(2 * t) - dx.Z);
+      dx.sigY = t == 0 ? I.pSigY.p : I.pSigY.p + (size_t)(t - 1) * nsy;
+      dx.sigX = I.pSigX.p + (size_t)t * nsx;
+      DimInst& dy = D[2 + 2 * t];
+      dy.Z = snap(2 * t);
+      dy.zout = (long)(snap(2 * t + 1) - dy.Z);
+      dy.sigX = I.pSigX.p + (size_t)t * nsx;
+      dy.sigY = I.pSigY.p + (size_t)t * nsy;
+      DimInst& gw = D[2 * S + 1 + 2 * t];
+      gw.Z = snap(2 * t);
+      gw.sigX = I.pSigX.p + (size_t)t * nsx;
+      DimInst& gv = D[2 * S + 2 + 2 * t];
+      gv.Z = snap(2 * t + 1);
+      gv.sigY = I.pSigY.p + (size_t)t * nsy;
+    }
+    DimInst& da = D[4 * S + 1];
+    da.Z = I.pLam.p;
+    da.sigX = I.pSigXa.p;
+    da.sigY = I.pSigYa.p;
+    da.nforce = 0;
+    HIPOK(I.pDesc.upload(D));
+    // 2. transposed problem (once per handle): nx <-> ny, coefficients transposed
+    if (!p->adjT) {
+      pr_problem_desc dT = I.d;
+      dT.nx = ny;
+      dT.ny = nx;
+      dT.n_forcing = 0;
+      dT.forcing_space = dT.forcing_time_fine = dT.forcing_time_coarse = nullptr;
+      dT.rho = nullptr;
+      if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
+        HIPOK(I.pCoefT0.alloc((size_t)(nx + 2) * (ny + 2)));
+        HIPOK(launch_transpose_states(I.theta.p, I.pCoefT0.p, nx + 2, ny + 2, 1, s));
+        dT.coef_x = I.pCoefT0.p;
+        dT.coef_y = nullptr;
+      } else {  // x-faces of the transposed grid are the y-faces, and back
+        HIPOK(I.pCoefT0.alloc((size_t)nx * (ny + 1)));
+        HIPOK(I.pCoefT1.alloc((size_t)(nx + 1) * ny));
+        HIPOK(launch_transpose_states(I.ay.p, I.pCoefT0.p, nx, ny + 1, 1, s));
+        HIPOK(launch_transpose_states(I.ax.p, I.pCoefT1.p, nx + 1, ny, 1, s));
+        dT.coef_x = I.pCoefT0.p;
+        dT.coef_y = I.pCoefT1.p;
+      }
+      HIPOK(hipStreamSynchronize(s));
+      pr_problem hT = nullptr;
+      pr_status st = pr_create_problem(&dT, 1, hip_stream, &hT);
+      if (st != PR_OK) return st;
+      p->adjT = hT;
+    }
+    // 3. boundary adjoints: states of the transposed problem from lambda_T^T.
+    //    The exact chain runs on a second stream, beside the forward checkpoints
+    //    of step 4 (the two serial chains are independent).
+    if (!p->astream) {
+      HIPOK(hipStreamCreateWithFlags(&p->astream, hipStreamNonBlocking));
+      HIPOK(hipEventCreateWithFlags(&p->aev[0], hipEventDisableTiming));
+      HIPOK(hipEventCreateWithFlags(&p->aev[1], hipEventDisableTiming));
+    }
+    if (I.pBnd.n != (size_t)(N + 1) * npts) {
+      HIPOK(I.pBnd.alloc((size_t)(N + 1) * npts));
+      HIPOK(I.pBndT.alloc((size_t)(N + 1) * npts));
+      HIPOK(I.pLamIn.alloc((size_t)N * npts));
+    }
+    HIPOK(launch_transpose_states(lambda_T, I.pBndT.p, nx, ny, 1, s));  // u0 of the transposed problem
+    pr_status st = PR_OK;
+    int kd = 0;
+    hipStream_t bs = s;  // stream of the boundary-adjoint chain
+    if (k_max == 0) {
+      bs = p->astream;
+      HIPOK(hipEventRecord(p->aev[0], s));
+      HIPOK(hipStreamWaitEvent(bs, p->aev[0], 0));
+      st = pr_sequential_fine(p->adjT, I.pBndT.p, I.pBndT.p, bs);
+    } else {
+      double incT = 0.0;
+      HIPOK(launch_copy(I.pBndT.p, I.pBnd.p, npts, s));  // pr_parareal_iterate reads u0 separately
+      st = pr_parareal_iterate(p->adjT, I.pBnd.p, I.pBndT.p, k_max, tol, &kd, &incT, hip_stream);
+    }
     if (st != PR_OK) return st;
-    p->adjT = hT;
-  }
-  // 3. boundary adjoints: states of the transposed problem from lambda_T^T.
-  //    The exact chain runs on a second stream, beside the forward checkpoints
-  //    of step 4 (the two serial chains are independent).
-  if (!p->astream) {
-    HIPOK(hipStreamCreateWithFlags(&p->astream, hipStreamNonBlocking));
-    HIPOK(hipEventCreateWithFlags(&p->aev[0], hipEventDisableTiming));
-    HIPOK(hipEventCreateWithFlags(&p->aev[1], hipEventDisableTiming));
-  }
-  if (I.pBnd.n != (size_t)(N + 1) * npts) {
-    HIPOK(I.pBnd.alloc((size_t)(N + 1) * npts));
-    HIPOK(I.pBndT.alloc((size_t)(N + 1) * npts));
-    HIPOK(I.pLamIn.alloc((size_t)N * npts));
-  }
-  HIPOK(launch_transpose_states(lambda_T, I.pBndT.p, nx, ny, 1, s));  // u0 of the transposed problem
-  pr_status st = PR_OK;
-  int kd = 0;
-  hipStream_t bs = s;  // stream of the boundary-adjoint chain
-  if (k_max == 0) {
-    bs = p->astream;
-    HIPOK(hipEventRecord(p->aev[0], s));
-    HIPOK(hipStreamWaitEvent(bs, p->aev[0], 0));
-    st = pr_sequential_fine(p->adjT, I.pBndT.p, I.pBndT.p, bs);
-  } else {
-    double incT = 0.0;
-    HIPOK(launch_copy(I.pBndT.p, I.pBnd.p, npts, s));  // pr_parareal_iterate reads u0 separately
-    st = pr_parareal_iterate(p->adjT, I.pBnd.p, I.pBndT.p, k_max, tol, &kd, &incT, hip_stream);
-  }
-  if (st != PR_OK) return st;
-  if (k_done) *k_done = kd;
-  // transposed state m is lambda_{N-m}^T
-  HIPOK(launch_transpose_states(I.pBndT.p, I.pBnd.p, ny, nx, N + 1, bs));
-  for (int n = 0; n < N; n++)  // slice n ends with lambda_{n+1} = state N-1-n
-    HIPOK(launch_copy(I.pBnd.p + (size_t)(N - 1 - n) * npts, I.pLamIn.p + (size_t)n * npts, npts,
-                      bs));
-  if (bs != s) HIPOK(hipEventRecord(p->aev[1], bs));
-  // 4. forward checkpoints at the slice boundaries (exact sequential fine solve)
-  if (!U_ckpt && I.adjCkpt.n != (size_t)(N + 1) * npts) HIPOK(I.adjCkpt.alloc((size_t)(N + 1) * npts));
-  double* ckpt = U_ckpt ? U_ckpt : I.adjCkpt.p;
-  st = seq_fine_dim(p, 0, u0, ckpt, s);
-  if (st != PR_OK) return st;
-  if (bs != s) HIPOK(hipStreamWaitEvent(s, p->aev[1], 0));
-  const DimInst* Dd = I.pDesc.p;
-  // 5. recompute every forward step of every slice (sources included)
-  HIPOK(launch_to_interleaved(Dd, h, ckpt, s));
-  for (int t = 0; t < S; t++) {
-    PhaseTimer pt(p, PH_FINE, s);
-    HIPOK(launch_fine_sweep(Dd + 1 + 2 * t, g.d_work[0], g.n_work[0], g.L, g.M, 0, t > 0, t, s, 0,
-                            g.ft != 0));
-    HIPOK(launch_fine_sweep(Dd + 2 + 2 * t, g.d_work[1], g.n_work[1], g.L, g.M, 1, 1, t, s, 0,
-                            false));
-  }
-  // 6. reverse steps of every slice from lambda_{n+1}: y solve, face gradients
-  //    with V_t, x solve, face gradients with W_t
-  if (I.adjGax.n != (size_t)ny * (nx + 1)) HIPOK(I.adjGax.alloc((size_t)ny * (nx + 1)));
-  if (I.adjGay.n != (size_t)(ny + 1) * nx) HIPOK(I.adjGay.alloc((size_t)(ny + 1) * nx));
-  HIPOK(launch_fill_zero(I.adjGax.p, I.adjGax.n, s));
-  HIPOK(launch_fill_zero(I.adjGay.p, I.adjGay.n, s));
-  const double hx = 1.0 / (nx + 1), hy = 1.0 / (ny + 1);
-  const double cx = I.dt / (hx * hx), cy = I.dt / (hy * hy);
-  const DimInst* Da = Dd + 4 * S + 1;
-  HIPOK(launch_to_interleaved(Da, h, I.pLamIn.p, s));
-  for (int t = S - 1; t >= 0; t--) {
-    {
+    if (k_done) *k_done = kd;
+    // transposed state m is lambda_{N-m}^T
+    HIPOK(launch_transpose_states(I.pBndT.p, I.pBnd.p, ny, nx, N + 1, bs));
+    for (int n = 0; n < N; n++)  // slice n ends with lambda_{n+1} = state N-1-n
+      HIPOK(launch_copy(I.pBnd.p + (size_t)(N - 1 - n) * npts, I.pLamIn.p + (size_t)n * npts, npts,
+                        bs));
+    if (bs != s) HIPOK(hipEventRecord(p->aev[1], bs));
+    // 4. forward checkpoints at the slice boundaries (exact sequential fine solve)
+    if (!U_ckpt && I.adjCkpt.n != (size_t)(N + 1) * npts) HIPOK(I.adjCkpt.alloc((size_t)(N + 1) * npts));
+    double* ckpt = U_ckpt ? U_ckpt : I.adjCkpt.p;
+    st = seq_fine_dim(p, 0, u0, ckpt, s);
+    if (st != PR_OK) return st;
+    if (bs != s) HIPOK(hipStreamWaitEvent(s, p->aev[1], 0));
+    const DimInst* Dd = I.pDesc.p;
+    // 5. recompute every forward step of every slice (sources included)
+    HIPOK(launch_to_interleaved(Dd, h, ckpt, s));
+    for (int t = 0; t < S; t++) {
       PhaseTimer pt(p, PH_FINE, s);
-      HIPOK(launch_fine_sweep(Da, g.d_work[1], g.n_work[1], g.L, g.M, 1, t < S - 1, t, s, 0, false));
+      HIPOK(launch_fine_sweep(Dd + 1 + 2 * t, g.d_work[0], g.n_work[0], g.L, g.M, 0, t > 0, t, s, 0,
+                              g.ft != 0));
+      HIPOK(launch_fine_sweep(Dd + 2 + 2 * t, g.d_work[1], g.n_work[1], g.L, g.M, 1, 1, t, s, 0,
+                              false));
     }
-    HIPOK(launch_grad_faces(1, Da, Dd + 2 * S + 2 + 2 * t, h, cy, I.adjGay.p, s));
-    {
-      PhaseTimer pt(p, PH_FINE, s);
-      HIPOK(launch_fine_sweep(Da, g.d_work[0], g.n_work[0], g.L, g.M, 0, 1, t, s, 0, false));
+    // 6. reverse steps of every slice from lambda_{n+1}: y solve, face gradients
+    //    with V_t, x solve, face gradients with W_t
+    if (I.adjGax.n != (size_t)ny * (nx + 1)) HIPOK(I.adjGax.alloc((size_t)ny * (nx + 1)));
+    if (I.adjGay.n != (size_t)(ny + 1) * nx) HIPOK(I.adjGay.alloc((size_t)(ny + 1) * nx));
+    HIPOK(launch_fill_zero(I.adjGax.p, I.adjGax.n, s));
+    HIPOK(launch_fill_zero(I.adjGay.p, I.adjGay.n, s));
+    const double hx = 1.0 / (nx + 1), hy = 1.0 / (ny + 1);
+    const double cx = I.dt / (hx * hx), cy = I.dt / (hy * hy);
+    const DimInst* Da = Dd + 4 * S + 1;
+    HIPOK(launch_to_interleaved(Da, h, I.pLamIn.p, s));
+    for (int t = S - 1; t >= 0; t--) {
+      {
+        PhaseTimer pt(p, PH_FINE, s);
+        HIPOK(launch_fine_sweep(Da, g.d_work[1], g.n_work[1], g.L, g.M, 1, t < S - 1, t, s, 0, false));
+      }
+      HIPOK(launch_grad_faces(1, Da, Dd + 2 * S + 2 + 2 * t, h, cy, I.adjGay.p, s));
+      {
+        PhaseTimer pt(p, PH_FINE, s);
+        HIPOK(launch_fine_sweep(Da, g.d_work[0], g.n_work[0], g.L, g.M, 0, 1, t, s, 0, false));
+      }
+      HIPOK(launch_grad_faces(0, Da, Dd + 2 * S + 1 + 2 * t, h, cx, I.adjGax.p, s));
     }
-    HIPOK(launch_grad_faces(0, Da, Dd + 2 * S + 1 + 2 * t, h, cx, I.adjGax.p, s));
-  }
-  HIPOK(launch_slice_xcorr(Da, h, 0, grad_u0, s));  // lambda_0
-  if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
-    HIPOK(launch_theta_chain(I.theta.p, I.adjGax.p, I.adjGay.p, nx, ny, grad_coef, s));
-  } else {
-    HIPOK(launch_copy(I.adjGax.p, grad_coef, I.adjGax.n, s));
-    HIPOK(launch_copy(I.adjGay.p, grad_coef + I.adjGax.n, I.adjGay.n, s));
-  }
-  return PR_OK;
+    HIPOK(launch_slice_xcorr(Da, h, 0, grad_u0, s));  // lambda_0
+    if (I.d.coef_mode == PR_COEF_NODAL_LOG) {
+      HIPOK(launch_theta_chain(I.theta.p, I.adjGax.p, I.adjGay.p, nx, ny, grad_coef, s));
+    } else {
+      HIPOK(launch_copy(I.adjGax.p, grad_coef, I.adjGax.n, s));
+      HIPOK(launch_copy(I.adjGay.p, grad_coef + I.adjGax.n, I.adjGay.n, s));
+    }
+    return PR_OK;
+  });
 }
 
 }  // extern "C"
