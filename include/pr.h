@@ -234,6 +234,25 @@ pr_status pr_sequential_fine(pr_problem p, const double* u0, double* U, void* hi
 pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, double* grad_u0,
                      double* grad_coef, double* U_ckpt, void* hip_stream);
 
+/* Allocation-free variant of pr_adjoint, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). Same arguments, outputs and restrictions as
+ * pr_adjoint; instead of allocating its recompute workspace on first use it
+ * carves it out of a fixed scratch array that every GPU the library runs on
+ * holds for the life of the process (64 MiB = 8 Mi doubles; the device
+ * address is taken per GPU by pr_create_problem). The workspace is
+ * 2 s + 2 states, the two face-gradient arrays and, when U_ckpt is NULL, the
+ * N + 1 slice-boundary checkpoints, each rounded up to 32 doubles: a problem
+ * that needs more returns PR_EINVAL before any work is queued (pass U_ckpt to
+ * fit a larger one). Calls the no-alloc entry point makes nothing else
+ * allocate: the handle's own buffers come from pr_create_problem. Every call
+ * on one GPU shares that GPU's array, so calls whose work overlaps on the
+ * device (two streams, two threads) race; calls queued on one stream are
+ * ordered. Asynchronous. */
+pr_status pr_adjoint_noalloc(pr_problem p, const double* u0, const double* lambda_T,
+                             double* grad_u0, double* grad_coef, double* U_ckpt,
+                             void* hip_stream);
+
 /* Parallel-in-time adjoint (not in the paper; derived from the transpose of
  * eq. FIE_method): same outputs as pr_adjoint. The adjoint of one slice's fine
  * map is the fine map of the transposed grid (each step: y solve, then x

@@ -317,6 +317,13 @@ class Problem:
         B.check(B.lib().pr_adjoint(self._h, _ptr(u0), _ptr(lambda_T), _ptr(grad_u0),
                                    _ptr(grad_coef), _ptr(U_ckpt), _stream(stream)))
 
+    def adjoint_noalloc(self, u0, lambda_T, grad_u0, grad_coef, U_ckpt=None, stream=None):
+        """pr_adjoint with its workspace in the library's fixed per-GPU scratch array
+        (no device allocation; raises PrError when the problem does not fit it)."""
+        self._check_adjoint(u0, lambda_T, grad_u0, grad_coef, U_ckpt)
+        B.check(B.lib().pr_adjoint_noalloc(self._h, _ptr(u0), _ptr(lambda_T), _ptr(grad_u0),
+                                           _ptr(grad_coef), _ptr(U_ckpt), _stream(stream)))
+
     def adjoint_parallel(self, u0, lambda_T, grad_u0, grad_coef, U_ckpt=None, k_max=0, tol=0.0,
                          stream=None):
         """Parallel-in-time adjoint (pr_adjoint_parallel): k_max = 0 computes the

@@ -83,6 +83,7 @@ def lib():
             "pr_parareal_iterate": [vp, vp, vp, i, d, C.POINTER(i), _dp, vp],
             "pr_sequential_fine": [vp, vp, vp, vp],
             "pr_adjoint": [vp, vp, vp, vp, vp, vp, vp],
+            "pr_adjoint_noalloc": [vp, vp, vp, vp, vp, vp, vp],
             "pr_adjoint_parallel": [vp, vp, vp, vp, vp, vp, i, d, C.POINTER(i), vp],
             "pr_profile_control": [vp, i],
             "pr_profile_read": [vp, C.POINTER(PrProfile)],
@@ -110,5 +111,5 @@ def exported_symbols():
     """Names of the pr_* entry points this binding knows (all declared in pr.h)."""
     return ["pr_create_problem", "pr_destroy_problem", "pr_query_layout", "pr_num_instances",
             "pr_set_coefficients", "pr_fine_propagate", "pr_coarse_sweep", "pr_parareal_iterate",
-            "pr_sequential_fine", "pr_adjoint", "pr_adjoint_parallel", "pr_profile_control",
+            "pr_sequential_fine", "pr_adjoint", "pr_adjoint_noalloc", "pr_adjoint_parallel", "pr_profile_control",
             "pr_profile_read", "pr_set_option", "pr_get_option", "pr_autotune", "pr_last_error"]

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -1580,6 +1581,37 @@ pr_status adjoint_serial(pr_problem_s* p, const double* u0, const double* lambda
   return PR_OK;
 }
 
+// --------------------------------------------- allocation-free scratch ---
+// pr_adjoint_noalloc keeps its workspace in this file-scope device array
+// instead of allocating: every GPU the library runs on holds one copy (in the
+// library's code object) until the process ends. In host code the name is
+// only a stand-in: its device address, per GPU, comes from
+// hipGetSymbolAddress, taken once per device with that device current (by
+// pr_create_problem, or by the entry point's first call on a device), and
+// only that address is handed to kernels.
+constexpr size_t kNoAllocScratchDoubles = size_t(8) << 20;  // 64 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch array.
+pr_status device_scratch(double** out) {
+  int dev = 0;
+  HIPOK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PR_EUNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPOK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(PR_EDEVICE, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return PR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1636,6 +1668,11 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
       if (st != PR_OK) return st;
     }
     hipStream_t s = as_stream(hip_stream);
+    {  // device address of this GPU's allocation-free scratch (pr_adjoint_noalloc)
+      double* scr = nullptr;
+      pr_status st = device_scratch(&scr);
+      if (st != PR_OK) return st;
+    }
     std::unique_ptr<pr_problem_s> P(new (std::nothrow) pr_problem_s());
     if (!P) return fail(PR_ENOMEM, "host allocation failed");
     size_t ou = 0, osl = 0, ost = 0;
@@ -2009,6 +2046,39 @@ pr_status pr_adjoint(pr_problem p, const double* u0, const double* lambda_T, dou
     if (I.adjGay.n != (size_t)(ny + 1) * nx) HIPOK(I.adjGay.alloc((size_t)(ny + 1) * nx));
     AdjWork w{I.adjWV.p, I.adjWV.p + (size_t)S * npts, I.adjLam.p, I.adjMu.p, I.adjGax.p,
               I.adjGay.p, U_ckpt ? U_ckpt : I.adjCkpt.p};
+    return adjoint_serial(p, u0, lambda_T, grad_u0, grad_coef, w, as_stream(hip_stream));
+  });
+}
+
+pr_status pr_adjoint_noalloc(pr_problem p, const double* u0, const double* lambda_T,
+                             double* grad_u0, double* grad_coef, double* U_ckpt,
+                             void* hip_stream) {
+  return guarded([&]() -> pr_status {
+    pr_status st = check_adjoint_args(p, u0, lambda_T, grad_u0, grad_coef, "pr_adjoint_noalloc");
+    if (st != PR_OK) return st;
+    Instance& I = *p->inst[0];
+    const int nx = I.d.nx, ny = I.d.ny, N = I.d.n_slices, S = I.d.fine_steps;
+    const size_t npts = I.npts;
+    // carve the workspace out of this GPU's scratch array, each part 256-byte aligned
+    const size_t parts[7] = {(size_t)S * npts, (size_t)S * npts, npts, npts,
+                             (size_t)ny * (nx + 1), (size_t)(ny + 1) * nx,
+                             U_ckpt ? 0 : (size_t)(N + 1) * npts};
+    size_t need = 0;
+    for (size_t n : parts) need += (n + 31) / 32 * 32;
+    if (need > kNoAllocScratchDoubles)
+      return fail(PR_EINVAL,
+                  "pr_adjoint_noalloc: this problem needs %zu doubles of scratch (2 s + 2 states, "
+                  "the face gradients%s), above the library's fixed %zu",
+                  need, U_ckpt ? "" : " and N + 1 checkpoints", (size_t)kNoAllocScratchDoubles);
+    double* base = nullptr;
+    st = device_scratch(&base);
+    if (st != PR_OK) return st;
+    double* q[7];
+    for (int k = 0; k < 7; k++) {
+      q[k] = base;
+      base += (parts[k] + 31) / 32 * 32;
+    }
+    AdjWork w{q[0], q[1], q[2], q[3], q[4], q[5], U_ckpt ? U_ckpt : q[6]};
     return adjoint_serial(p, u0, lambda_T, grad_u0, grad_coef, w, as_stream(hip_stream));
   });
 }
