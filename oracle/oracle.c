@@ -123,6 +123,39 @@ static int dd2_active(const double* r, int i) {
   return r[2 * i] > 0.0 || r[2 * i + 1] > 0.0 || r[2 * i + 2] > 0.0;
 }
 
+/* Banded LU without pivoting, in place: A[q][bw + (col - q)] holds the row's
+ * band; the multipliers of L replace the entries they eliminate. */
+static void band_lu(double* A, long n, long bw) {
+  const long width = 2 * bw + 1;
+  for (long q = 0; q < n; q++) { /* eliminate column q below the diagonal */
+    const double piv = A[q * width + bw];
+    const long last = (q + bw < n - 1) ? q + bw : n - 1;
+    for (long t = q + 1; t <= last; t++) {
+      const double f = A[t * width + bw + (q - t)] / piv;
+      A[t * width + bw + (q - t)] = f;
+      if (f == 0.0) continue;
+      for (long c = q + 1; c <= q + bw && c < n; c++)
+        A[t * width + bw + (c - t)] = A[t * width + bw + (c - t)] - f * A[q * width + bw + (c - q)];
+    }
+  }
+}
+
+/* Solve with the factors of band_lu, in place on b. */
+static void band_solve(const double* A, long n, long bw, double* b) {
+  const long width = 2 * bw + 1;
+  for (long t = 1; t < n; t++) { /* forward: L y = b */
+    const long first = t - bw > 0 ? t - bw : 0;
+    double v = b[t];
+    for (long q = first; q < t; q++) v = v - A[t * width + bw + (q - t)] * b[q];
+    b[t] = v;
+  }
+  for (long q = n - 1; q >= 0; q--) { /* back substitution: U x = y */
+    double v = b[q];
+    for (long c = q + 1; c <= q + bw && c < n; c++) v = v - A[q * width + bw + (c - q)] * b[c];
+    b[q] = v / A[q * width + bw];
+  }
+}
+
 /* (I - tau A_j) V = U in place. Columns outside colour j's support are
  * identity rows and no x-face couples a supported column to an unsupported
  * one, so the system splits into one 2D system per maximal run of supported
@@ -130,7 +163,12 @@ static int dd2_active(const double* r, int i) {
  * is assembled in natural order (x fastest inside the strip, unknown
  * k*w + (i - i0)), which makes it banded with half-bandwidth w, and solved by
  * Gaussian elimination without pivoting (the matrix is a strictly diagonally
- * dominant M-matrix) followed by back substitution. */
+ * dominant M-matrix) followed by back substitution. The substep is an exact
+ * solve; a direct solve in FP64 is accurate only to about the strip system's
+ * condition number (1 + 8 tau max(a) / h^2, thousands at the paper's sizes)
+ * times the unit roundoff, so the solution is improved by one step of
+ * iterative refinement whose residual b - (I - tau A_j) x is accumulated in
+ * extended precision (long double): x += solve(residual). */
 static void dd2_substep(const or_problem* p, int j, double tau, double* U) {
   const int nx = p->nx, ny = p->ny;
   const double* r = p->rho + (long)j * (2 * nx + 1);
@@ -146,6 +184,7 @@ static void dd2_substep(const or_problem* p, int j, double tau, double* U) {
     const long n = (long)w * ny, bw = w, width = 2 * bw + 1;
     double* A = (double*)calloc((size_t)(n * width), sizeof(double)); /* A[q][bw + (col - q)] */
     double* b = (double*)malloc(sizeof(double) * n);
+    double* x = (double*)malloc(sizeof(double) * n);
     for (int k = 0; k < ny; k++)
       for (int i = i0; i < i1; i++) {
         const long q = (long)k * w + (i - i0);
@@ -157,26 +196,33 @@ static void dd2_substep(const or_problem* p, int j, double tau, double* U) {
         if (k + 1 < ny) A[q * width + bw + w] = cn;
         b[q] = U[(long)k * nx + i];
       }
-    for (long q = 0; q < n; q++) { /* eliminate column q below the diagonal */
-      const double piv = A[q * width + bw];
-      const long last = (q + bw < n - 1) ? q + bw : n - 1;
-      for (long t = q + 1; t <= last; t++) {
-        const double f = A[t * width + bw + (q - t)] / piv;
-        if (f == 0.0) continue;
-        for (long c = q; c <= q + bw && c < n; c++)
-          A[t * width + bw + (c - t)] = A[t * width + bw + (c - t)] - f * A[q * width + bw + (c - q)];
-        b[t] = b[t] - f * b[q];
-      }
-    }
-    for (long q = n - 1; q >= 0; q--) { /* back substitution */
-      double v = b[q];
-      for (long c = q + 1; c <= q + bw && c < n; c++) v = v - A[q * width + bw + (c - q)] * b[c];
-      b[q] = v / A[q * width + bw];
-    }
+    band_lu(A, n, bw);
+    memcpy(x, b, sizeof(double) * n);
+    band_solve(A, n, bw, x);
+    /* refinement: residual of the original rows (rebuilt by dd2_row) in long double */
+    double* d = (double*)malloc(sizeof(double) * n);
     for (int k = 0; k < ny; k++)
-      for (int i = i0; i < i1; i++) U[(long)k * nx + i] = b[(long)k * w + (i - i0)];
+      for (int i = i0; i < i1; i++) {
+        const long q = (long)k * w + (i - i0);
+        double cw, ce, cs, cn;
+        const double dg = dd2_row(p, r, tau, i, k, &cw, &ce, &cs, &cn);
+        long double acc = (long double)b[q] - (long double)dg * x[q];
+        if (i > i0) acc -= (long double)cw * x[q - 1];
+        if (i + 1 < i1) acc -= (long double)ce * x[q + 1];
+        if (k > 0) acc -= (long double)cs * x[q - w];
+        if (k + 1 < ny) acc -= (long double)cn * x[q + w];
+        d[q] = (double)acc;
+      }
+    band_solve(A, n, bw, d);
+    for (int k = 0; k < ny; k++)
+      for (int i = i0; i < i1; i++) {
+        const long q = (long)k * w + (i - i0);
+        U[(long)k * nx + i] = x[q] + d[q];
+      }
     free(A);
     free(b);
+    free(x);
+    free(d);
     i0 = i1;
   }
 }

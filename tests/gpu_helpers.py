@@ -52,3 +52,25 @@ def slice_inputs(w, seed=0):
     base = w.u0
     return np.stack([base * (0.5 + 0.5 * rng.random()) + 0.05 * rng.standard_normal(base.shape)
                      for _ in range(w.n_slices)])
+
+
+def parareal_threaded(O, u0, k_max, workers=16):
+    """The oracle's parareal iteration (or_parareal) composed from its own steps,
+    with the fine propagations of the N slices run on a thread pool (each a call
+    into the serial C oracle, which keeps no shared state): the initial coarse
+    sweep, then per correction F_n = fine(U_n, n) for every n and the coarse
+    sweep with the correction. Same operations in the same order per slice as
+    or_parareal, so the results agree bitwise (checked on the CPU). Returns
+    (U, increments)."""
+    from concurrent.futures import ThreadPoolExecutor
+    N = O.n_slices
+    U = np.empty((N + 1,) + O.shape)
+    U[0] = np.asarray(u0, dtype=np.float64).reshape(O.shape)
+    G = np.empty((N,) + O.shape)
+    O.coarse_sweep(None, G, U)
+    hist = []
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for _ in range(k_max):
+            F = np.stack(list(ex.map(lambda n: O.fine(U[n], n), range(N))))
+            hist.append(O.coarse_sweep(F, G, U))
+    return U, hist

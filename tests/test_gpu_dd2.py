@@ -3,9 +3,10 @@
 by block cyclic reduction over each strip) against the oracle's banded
 elimination: the fine map over all slices, the sequential fine solve, the
 coarse sweep, parareal, source terms, handles mixing split kinds, and
-coefficient updates. Relative infinity-norm error <= 1e-12. At the paper's
-size (h = 1e-3, q = 2, beta = 1/16, N = 20) the fine map is checked by the
-residual of the FIE step, which holds at any size."""
+coefficient updates. Relative infinity-norm error <= 1e-12, also at the
+paper's size (h = 1e-3, q = 2, beta = 1/16, N = 20); on a 560-column strip whose
+system has condition number ~5000 the bound is 4 kappa u (the explicit inverses'
+rounding)."""
 import numpy as np
 import pytest
 
@@ -147,24 +148,36 @@ def test_dd2_single_colour_full_width():
     assert fine_parity(w) <= TOL
 
 
+def strip_bound(w, tau):
+    """Parity bound of the strip solver: max(1e-12, 4 kappa u), kappa = 1 + 4 tau
+    max(a) (1/h_x^2 + 1/h_y^2) the strip system's condition number and u the FP64 unit
+    roundoff. The oracle's strip solves are refined to the exact solution's rounding;
+    the block cyclic reduction applies explicit inverses of dense Schur complements,
+    whose rounding grows with kappa."""
+    ax, ay = oracle.faces_from_theta(w.nx, w.ny, w.theta)
+    amax = max(float(ax.max()), float(ay.max()))
+    kappa = 1 + 4 * tau * amax * ((w.nx + 1) ** 2 + (w.ny + 1) ** 2)
+    return max(TOL, 4 * kappa * 2.0 ** -53)
+
+
 def test_dd2_wide_strip():
-    """A strip of 560 columns (padded 576): the all-slice level-0 sweeps take the
-    one-lane-per-line form (the LDS-staged form holds at most 512), the single-state
-    ones sixteen positions per lane. The strip system's condition number is about
-    1 + 8 tau / h^2, so FP64 rounding in any exact solver is of order that times the
-    unit roundoff; tau = 1e-3 / 3 keeps it near 840, well inside the bound."""
+    """A strip of 560 columns (padded 576) at tau = 1/300: the all-slice level-0 sweeps
+    take the one-lane-per-line form (the LDS-staged form holds at most 512), the
+    single-state ones sixteen positions per lane. The strip system's condition number
+    is about 5000."""
     nx, ny = 560, 5
-    w = W.small_dd2(nx, ny, 1, 0.1, 3, 1, seed=6, T=1e-3)
+    w = W.small_dd2(nx, ny, 1, 0.1, 3, 1, seed=6, T=1e-2)
     w.rho = np.ones((1, 2 * nx + 1))
+    bound = strip_bound(w, w.T / w.n_slices)
     err = fine_parity(w)
-    print(f"wide strip: relative error {err:.3e}", flush=True)
-    assert err <= TOL
+    print(f"wide strip: relative error {err:.3e} (bound {bound:.2e})", flush=True)
+    assert err <= bound
     P, O = gpu_problem(w), oracle_problem(w)
     Seq = P.new_states()
     P.sequential_fine(dev(w.u0), Seq)
     torch.cuda.synchronize()
     ref = O.sequential_fine(w.u0)
-    assert relerr(Seq.cpu().numpy().reshape(ref.shape), ref) <= TOL
+    assert relerr(Seq.cpu().numpy().reshape(ref.shape), ref) <= bound
 
 
 def test_dd2_constant_coefficient():
@@ -287,10 +300,11 @@ def test_dd2_rejects_bad_partition():
         pr.Problem([d])
 
 
-def test_dd2_paper_size_residual():
-    """h = 1e-3 (999^2), q = 2, beta = 1/16, N = 20 slices, dt = 2.5e-3, one fine
-    step per slice on seeded slice states: w = S_1 S_0 u with S_k = (I - dt A_k)^-1,
-    so (I - dt A_0)(I - dt A_1) w = u, applied with the oracle's stencils."""
+def test_dd2_paper_size_one_step_against_the_oracle():
+    """h = 1e-3 (999^2), two subdomains of q = 2 vertical strips, beta = 1/16, N = 20
+    slices, dt = 2.5e-3 (the paper's DD runs): one FIE step of every slice in the
+    benchmark's launch configuration; slice 7 (seeded) compared element by element
+    with the oracle (about 40 s of oracle time), the other slices (zero) must stay zero."""
     n, N = 999, 20
     w = W.dd2_manufactured(n=n, n_slices=N, fine_steps=1)
     w.T = N * 2.5e-3
@@ -298,23 +312,18 @@ def test_dd2_paper_size_residual():
     P = gpu_problem(w)
     O = oracle_problem(w)
     rng = np.random.default_rng(7)
-    idx = [0, 7, 19]
     Uin = np.zeros((N, n, n))
-    for b in idx:
-        Uin[b] = W.sine_modes_2d(n, n, seed=b) + 0.01 * rng.standard_normal((n, n))
+    Uin[7] = W.sine_modes_2d(n, n, seed=7) + 0.01 * rng.standard_normal((n, n))
     F = P.new_slices()
     P.fine_propagate(dev(Uin), F)
     torch.cuda.synchronize()
     Fo = F.cpu().numpy().reshape(N, n, n)
-    dt = w.T / N
-    for b in idx:
-        v = Fo[b]
-        t1 = v - dt * O.apply_Aj(1, v)
-        back = t1 - dt * O.apply_Aj(0, t1)
-        # forward error eps * |w| grows by at most |I - dt A_0| |I - dt A_1| ~ (1 + 8 dt/h^2)^2
-        bound = 1e-12 * (1 + 8 * dt * (n + 1) ** 2) ** 2 * np.abs(v).max()
-        assert np.abs(back - Uin[b]).max() <= bound
-        assert np.abs(back - Uin[b]).max() <= 1e-6 * np.abs(Uin[b]).max()
+    print("999^2 strip step on the GPU done; oracle step (~40 s)", flush=True)
+    ref = O.fie_step(Uin[7], w.T / N)
+    err = relerr(Fo[7], ref)
+    print(f"999^2 q=2 beta=1/16: relative error {err:.3e}", flush=True)
+    assert err <= TOL
+    assert np.abs(np.delete(Fo, 7, axis=0)).max() == 0.0
 
 
 def test_dd2_fine_error_matches_the_paper_on_gpu():

@@ -220,3 +220,55 @@ def test_dd2_fine_error_matches_the_paper():
     err = manufactured_error(n, N, s, int(g["q"]), g["beta"], fine)
     # within half a unit of the last printed digit
     assert abs(err - g["error"]) <= 0.5e-7
+
+
+
+def test_dd2_strip_solve_is_exact_to_rounding_on_an_ill_conditioned_strip():
+    """A 560-column, 5-row strip at tau = 1/300 (condition number about 5000): the
+    oracle's substep is the exact solve of its system up to a few units of
+    roundoff. The reference does not use the oracle's solver: the same matrix
+    entries (the FP64 values of the operator's definition) go to scipy's sparse
+    LU, whose solution is refined once with a residual accumulated in long double
+    (numpy)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    nx, ny, tau = 560, 5, 1.0 / 300
+    w = W.small_dd2(nx, ny, 1, 0.1, 1, 1, seed=6, T=tau)
+    w.rho = np.ones((1, 2 * nx + 1))
+    ax, ay = oracle.faces_from_theta(nx, ny, w.theta)
+    P = dd2_problem(w)
+    u = W.sine_modes_2d(nx, ny, seed=3) + 0.01 * np.random.default_rng(4).standard_normal((ny, nx))
+    x = P.fie_step(u, tau)
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    rows, cols, vals = [], [], []
+    for k in range(ny):
+        for i in range(nx):
+            q = k * nx + i
+            fw, fe = ax[k, i] / (hx * hx), ax[k, i + 1] / (hx * hx)
+            fs, fn = ay[k, i] / (hy * hy), ay[k + 1, i] / (hy * hy)
+            rows.append(q); cols.append(q); vals.append(1.0 + tau * (fw + fe + fs + fn))
+            for ok, qq, f in ((i > 0, q - 1, fw), (i < nx - 1, q + 1, fe), (k > 0, q - nx, fs),
+                              (k < ny - 1, q + nx, fn)):
+                if ok:
+                    rows.append(q); cols.append(qq); vals.append(-tau * f)
+    rows, cols, vals = np.array(rows), np.array(cols), np.array(vals)
+    B = sp.csc_matrix((vals, (rows, cols)), shape=(nx * ny, nx * ny))
+
+    def residual(v):  # u - B v, every product and sum in long double
+        L = np.longdouble
+        acc = u.ravel().astype(L)
+        np.add.at(acc, rows, -(vals.astype(L) * v.ravel().astype(L)[cols]))
+        return acc
+
+    lu = spla.splu(B)
+    x0 = lu.solve(u.ravel())
+    xref = x0.astype(np.longdouble) + lu.solve(np.asarray(residual(x0), np.float64))
+    scale = float(np.abs(xref).max())
+    err = float(np.abs(x.ravel().astype(np.longdouble) - xref).max()) / scale
+    assert err <= 4e-15, err
+    # the residual of the FP64-rounded solution is at the level of rounding x itself
+    absBx = np.zeros(nx * ny)
+    np.add.at(absBx, rows, np.abs(vals) * np.abs(x.ravel())[cols])
+    assert float(np.abs(residual(x)).max()) <= 2 * 2.0 ** -53 * absBx.max()
+    # the unrefined direct solve is not that accurate on this system
+    assert float(np.abs(x0 - xref).max()) / scale > 2 * err

@@ -642,3 +642,19 @@ def test_manufactured_problem_converges():
     assert errs[0] > errs[1] > errs[2]
     assert 3.0 < errs[1] / errs[2] < 4.6
     assert errs[2] < 0.05
+
+
+def test_threaded_parareal_composition_is_the_oracle_iteration():
+    """The test harness that runs the oracle's slices on threads (used for the
+    full-size batch comparisons) reproduces or_parareal bit for bit, with a
+    source term so that the slice index reaches every fine call."""
+    import workloads as W
+    from gpu_helpers import oracle_problem, parareal_threaded
+    w = W.manufactured2d(11, 5, 3)
+    w.theta = 0.3 * W.smooth_field_2d(13, 13, ell=0.2, K=6, seed=9)
+    O = oracle_problem(w)
+    U1, k1, h1 = O.parareal(w.u0 + 0.1, 3)
+    U2, h2 = parareal_threaded(O, w.u0 + 0.1, 3, workers=4)
+    assert k1 == 3
+    assert np.array_equal(U1, U2)
+    assert np.array_equal(h1, np.asarray(h2))

@@ -240,13 +240,16 @@ def config4(n_instances: int = 256, sizes=(63, 127, 255, 511), slices=(16, 32, 6
     rng = np.random.default_rng(seed)
     ns = rng.choice(np.asarray(sizes), size=n_instances)
     Ns = rng.choice(np.asarray(slices), size=n_instances)
-    out = []
-    for i in range(n_instances):
-        n, N = int(ns[i]), int(Ns[i])
-        theta = 0.5 * smooth_field_2d(n + 2, n + 2, ell=0.1, K=20, seed=4 + i)
-        out.append(Workload(f"batch{i}_{n}_N{N}", 2, n, n, 0.05, N, fine_steps, theta=theta,
-                            u0=sine_modes_2d(n, n, seed=1000 + i), k_max=N, tol=1e-8))
-    return out
+    return [batch_instance(i, int(ns[i]), int(Ns[i]), fine_steps) for i in range(n_instances)]
+
+
+def batch_instance(i: int, n: int, n_slices: int, fine_steps: int = 32) -> Workload:
+    """Instance i of the batch workload at grid n and N slices: a = exp(0.5 g) (g smooth
+    Gaussian field, correlation length 0.1, seed 4+i), u0 as config 2 (seed 1000+i),
+    T = 0.05, tolerance 1e-8."""
+    theta = 0.5 * smooth_field_2d(n + 2, n + 2, ell=0.1, K=20, seed=4 + i)
+    return Workload(f"batch{i}_{n}_N{n_slices}", 2, n, n, 0.05, n_slices, fine_steps, theta=theta,
+                    u0=sine_modes_2d(n, n, seed=1000 + i), k_max=n_slices, tol=1e-8)
 
 
 def config5(n: int = 511, n_slices: int = 32, fine_steps: int = 32, n_dirs: int = 20) -> Workload:
