@@ -198,7 +198,14 @@ pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_m
 /* Tuning options (pr_set_option / pr_get_option):
  *   PR_OPT_GRAPH       1 (default): pr_parareal_iterate captures one correction
  *                      as a HIP graph and replays it; 0: direct launches
- *   PR_OPT_FINE_CHUNK  chunk length of the fine line sweeps: 16, 32 (default)
+ *   PR_OPT_FINE_CHUNK  chunk length of the fine line sweeps: 16, 20 (default), 24, 32
+ *   PR_OPT_TWISTED     1 (default): each fine line is solved by two waves, one
+ *                      eliminating from either end (twisted factorisation);
+ *                      0: one wave per line
+ *   PR_OPT_GROUPED     1 (default): with twisted sweeps, 64-slice blocks, the FIE
+ *                      fine propagator and a chunk of 20 or 24, four lines per
+ *                      workgroup share the loads of their pending-correction
+ *                      carries through LDS; 0: one line per workgroup
  *   PR_OPT_LANES       slice lanes per line in the fine sweeps (lines per wave =
  *                      64 / lanes): 0 = per-instance default (the smallest power
  *                      of two >= N, in [8, 64]), or a cap of 8, 16, 32, 64
@@ -207,13 +214,15 @@ pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_m
  *                      group running all s fine steps before the next (a
  *                      smaller working set between consecutive sweeps)
  * Results do not depend on the options beyond rounding. */
-enum { PR_OPT_GRAPH = 1, PR_OPT_FINE_CHUNK = 2, PR_OPT_LANES = 3, PR_OPT_BLOCKS_PER_PASS = 4 };
+enum { PR_OPT_GRAPH = 1, PR_OPT_FINE_CHUNK = 2, PR_OPT_LANES = 3, PR_OPT_BLOCKS_PER_PASS = 4,
+       PR_OPT_TWISTED = 5, PR_OPT_GROUPED = 6 };
 pr_status pr_set_option(pr_problem p, int option, int value);
 pr_status pr_get_option(pr_problem p, int option, int* value);
 
 /* Autotuner: times pr_fine_propagate on the handle's own shapes for every
- * (lanes, chunk) choice, keeps the fastest and reports it (host pointers,
- * each may be NULL; best_ms = its time). Overwrites the library's internal
+ * (lanes, chunk, twisted) choice, keeps the fastest and reports it (host
+ * pointers, each may be NULL; best_ms = its time; the twisted choice is read
+ * with pr_get_option). Overwrites the library's internal
  * parareal buffers (not the caller's). Synchronous. */
 pr_status pr_autotune(pr_problem p, void* hip_stream, int* lanes, int* chunk, float* best_ms);
 

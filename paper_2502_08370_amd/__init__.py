@@ -57,7 +57,8 @@ def _check_coef(dim, nx, ny, mode, cx, cy, device):
 
 
 _OPTS = {"graph": B.PR_OPT_GRAPH, "fine_chunk": B.PR_OPT_FINE_CHUNK, "lanes": B.PR_OPT_LANES,
-         "blocks_per_pass": B.PR_OPT_BLOCKS_PER_PASS}
+         "blocks_per_pass": B.PR_OPT_BLOCKS_PER_PASS, "twisted": B.PR_OPT_TWISTED,
+         "grouped": B.PR_OPT_GROUPED}
 
 
 def _ptr(t):
@@ -243,8 +244,10 @@ class Problem:
         B.check(B.lib().pr_sequential_fine(self._h, _ptr(u0), _ptr(U), _stream(stream)))
 
     def set_option(self, name, value):
-        """name: 'graph' (0/1), 'fine_chunk' (16/32), 'lanes' (0/8/16/32/64),
-        'blocks_per_pass' (0 = all slice blocks per launch, k > 0 = k at a time)."""
+        """name: 'graph' (0/1), 'fine_chunk' (16/24/32), 'lanes' (0/8/16/32/64),
+        'blocks_per_pass' (0 = all slice blocks per launch, k > 0 = k at a time),
+        'twisted' (1: two waves per fine line, one from each end; 0: one wave),
+        'grouped' (1: four lines per workgroup share their carry loads; 0: one line)."""
         B.check(B.lib().pr_set_option(self._h, _OPTS[name], int(value)))
 
     def get_option(self, name):
@@ -267,14 +270,15 @@ class Problem:
             with open(cache) as f:
                 table = json.load(f)
             if key in table:
-                lanes, chunk = table[key]["lanes"], table[key]["fine_chunk"]
-                self.set_option("lanes", lanes)
-                self.set_option("fine_chunk", chunk)
+                self.set_option("lanes", table[key]["lanes"])
+                self.set_option("fine_chunk", table[key]["fine_chunk"])
+                self.set_option("twisted", table[key].get("twisted", 1))
                 return dict(table[key], cached=True)
         lanes, chunk, ms = C.c_int(), C.c_int(), C.c_float()
         B.check(B.lib().pr_autotune(self._h, _stream(stream), C.byref(lanes), C.byref(chunk),
                                     C.byref(ms)))
-        res = dict(lanes=lanes.value, fine_chunk=chunk.value, fine_ms=ms.value)
+        res = dict(lanes=lanes.value, fine_chunk=chunk.value, twisted=self.get_option("twisted"),
+                   fine_ms=ms.value)
         if cache:
             table = {}
             if os.path.exists(cache):

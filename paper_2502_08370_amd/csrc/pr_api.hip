@@ -192,7 +192,9 @@ struct pr_problem_s {
   std::vector<Rec> recs;
   pr_profile acc{};
   size_t tot_u0 = 0, tot_slices = 0, tot_states = 0;
-  int M = 32;  // fine-sweep chunk length (PR_OPT_FINE_CHUNK)
+  int M = 20;  // fine-sweep chunk length (PR_OPT_FINE_CHUNK)
+  bool twisted = true;  // two-wave twisted fine sweeps (PR_OPT_TWISTED)
+  bool grouped = true;  // several lines per workgroup sharing their carry loads (PR_OPT_GROUPED)
   DimInst* d_inst = nullptr;  // device descriptors, one per instance
   // grouped work lists per lane width L (index log2 L) and direction
   struct Group {
@@ -200,6 +202,7 @@ struct pr_problem_s {
     int dr = 0;                // Douglas-Rachford instances (the sweeps add / subtract S)
     int ft = 0;                // instances with a source term (the x sweep adds it)
     int M = 32;                // chunk length of the group's sweeps
+    bool grouped = false;      // workgroups of grouped_lines() lines sharing the carry loads
     std::vector<int> members;  // instances of the group
     WorkItem* d_work[2] = {nullptr, nullptr};
     int n_work[2] = {0, 0};
@@ -341,6 +344,47 @@ pr_status setup_forcing(Instance& I, const pr_problem_desc& d, hipStream_t s) {
   return PR_OK;
 }
 
+// Split chunk of the twisted fine sweeps: the bottom part of a line starts at
+// chunk (P + 1) / 2 (lines of one chunk are not twisted).
+void set_twist(DimInst& h, bool twisted) {
+  h.twx = (twisted && h.Px >= 2) ? (h.Px + 1) / 2 : h.Px;
+  h.twy = (twisted && h.Py >= 2) ? (h.Py + 1) / 2 : h.Py;
+}
+
+// Factorisation job of the fine line systems of one direction (tau = dt).
+FactorJob fine_job(Instance& I, int dir) {
+  const pr_problem_desc& d = I.d;
+  const int nx = d.nx, ny = d.ny;
+  const double h = dir == 0 ? 1.0 / (nx + 1) : 1.0 / (ny + 1);
+  FactorJob j{};
+  j.face = dir == 0 ? I.ax.p : I.ay.p;
+  j.n_lines = dir == 0 ? ny : nx;
+  j.n_pos = dir == 0 ? nx : ny;
+  j.face_line_stride = dir == 0 ? nx + 1 : 1;
+  j.face_pos_stride = dir == 0 ? 1 : nx;
+  j.tau_over_h2 = I.dt / (h * h);
+  j.react = I.dt * (d.c / d.dim);
+  j.E = nullptr;
+  j.R = dir == 0 ? I.fxR.p : I.fyR.p;
+  j.G = dir == 0 ? I.fxG.p : I.fyG.p;
+  j.pos_major = 0;
+  return j;
+}
+
+// Fine factors of the sweeps (twisted at chunk twx / twy, plain LU when the
+// split chunk is the line's last) and their chunk products phi.
+pr_status fine_factors(Instance& I, hipStream_t s) {
+  const DimInst& h = I.h;
+  HIPOK(launch_factorize_twisted(fine_job(I, 0), h.twx * h.M, s));
+  HIPOK(launch_chunk_phi_twisted(I.fxG.p, I.d.ny, I.d.nx, h.M, h.twx, I.fxPhiC.p, I.fxPhiS.p, s));
+  if (I.d.dim == 2) {
+    HIPOK(launch_factorize_twisted(fine_job(I, 1), h.twy * h.M, s));
+    HIPOK(launch_chunk_phi_twisted(I.fyG.p, I.d.nx, I.d.ny, h.M, h.twy, I.fyPhiC.p, I.fyPhiS.p,
+                                   s));
+  }
+  return PR_OK;
+}
+
 pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   const pr_problem_desc& d = I.d;
   const int nx = d.nx, ny = d.ny, N = d.n_slices;
@@ -379,6 +423,7 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   const int Mc = d.fine == PR_DR ? kDRChunk : P->M;
   h.nx = nx; h.ny = ny; h.N = N; h.L = L; h.B = B; h.M = Mc;
   h.Px = (nx + Mc - 1) / Mc; h.Py = (ny + Mc - 1) / Mc;
+  set_twist(h, P->twisted);
   h.steps = d.fine_steps;
   h.slab = (long)npts * L;
   HIPOK(I.Z.alloc((size_t)B * npts * L));
@@ -451,9 +496,10 @@ pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
       HIPOK(launch_block_factors(jy.G, nx, ny, coarse ? I.cyGb.p : I.fyGb.p, s));
     }
   }
-  HIPOK(launch_chunk_phi(I.fxG.p, ny, nx, M, I.fxPhiC.p, I.fxPhiS.p, s));
-  if (d.dim == 2) HIPOK(launch_chunk_phi(I.fyG.p, nx, ny, M, I.fyPhiC.p, I.fyPhiS.p, s));
-  return PR_OK;
+  (void)M;
+  // the fine sweeps' factors: twisted at the instance's split chunk (the lane-
+  // blocked copies above keep the plain LU)
+  return fine_factors(I, s);
 }
 
 enum { PH_FINE = 0, PH_TRANSPOSE = 1, PH_COARSE_X = 2, PH_COARSE_Y = 3, PH_OTHER = 4 };
@@ -1156,14 +1202,14 @@ pr_status dd2_fine(pr_problem_s* P, Instance& I, const double* U, double* out, h
 // dealt to the 8 XCDs round-robin by id).
 std::vector<WorkItem> build_work(const std::vector<int>& members,
                                  const std::vector<std::unique_ptr<Instance>>& inst, int dir,
-                                 int M, int b_lo = 0, int b_hi = 1 << 30) {
+                                 int M, int b_lo = 0, int b_hi = 1 << 30, int per_item = 1) {
   const int kXcd = 8;
   std::vector<std::vector<WorkItem>> per(kXcd);
   for (int m : members) {
     const DimInst& h = inst[m]->h;
     if (dir == 1 && inst[m]->d.dim == 1) continue;
     const int n_lines = dir == 0 ? h.ny : h.nx;
-    const int G = 64 / h.L;
+    const int G = 64 / h.L * per_item;  // lines per work item
     const int n_groups = (n_lines + G - 1) / G;
     const int groups_per_chunk = std::max(1, M / G);
     for (int b = std::max(0, b_lo); b < std::min(h.B, b_hi); b++)
@@ -1238,7 +1284,7 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
           PhaseTimer pt(P, PH_FINE, s);
           HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir] + off, cnt, g.L, g.M, dir,
                                   dir == 1 || t > 0, t, s, g.dr ? (dir == 0 ? 1 : -1) : 0,
-                                  dir == 0 && g.ft));
+                                  dir == 0 && g.ft, P->twisted, g.grouped));
         }
       }
     }
@@ -1415,12 +1461,14 @@ pr_status build_schedules(pr_problem_s* P) {
       g.dr = dr;
       g.ft = ft;
       g.M = dr ? kDRChunk : P->M;
+      g.grouped = L == 64 && !dr && P->twisted && P->grouped && (g.M == 20 || g.M == 24);
       g.members = members;
       for (int dir = 0; dir < 2; dir++) {
         std::vector<WorkItem> all;
         g.pass_off[dir].assign(1, 0);
         for (int q = 0; q < P->n_passes; q++) {
-          std::vector<WorkItem> part = build_work(members, P->inst, dir, g.M, q * bpp, (q + 1) * bpp);
+          std::vector<WorkItem> part = build_work(members, P->inst, dir, g.M, q * bpp, (q + 1) * bpp,
+                                                  g.grouped ? grouped_lines() : 1);
           all.insert(all.end(), part.begin(), part.end());
           g.pass_off[dir].push_back((int)all.size());
         }
@@ -1469,7 +1517,7 @@ pr_status build_schedules(pr_problem_s* P) {
 // Lane width (lines per wave = 64 / L) and chunk length of the fine sweeps.
 // lanes_cap = 0 keeps every instance's default L; otherwise L = min(cap, default).
 // Workspaces were sized for the default L and M = 16, which bound every choice.
-pr_status apply_layout(pr_problem_s* P, int lanes_cap, int M) {
+pr_status apply_layout(pr_problem_s* P, int lanes_cap, int M, bool twisted) {
   HIPOK(hipDeviceSynchronize());
   for (auto& Ip : P->inst) {
     Instance& I = *Ip;
@@ -1481,16 +1529,18 @@ pr_status apply_layout(pr_problem_s* P, int lanes_cap, int M) {
     h.B = (N + L - 1) / L;
     h.slab = (long)nx * ny * L;
     const int Mi = I.d.fine == PR_DR ? kDRChunk : M;
-    if (Mi != h.M) {
-      h.M = Mi;
-      h.Px = (nx + Mi - 1) / Mi;
-      h.Py = (ny + Mi - 1) / Mi;
-      HIPOK(launch_chunk_phi(I.fxG.p, ny, nx, Mi, I.fxPhiC.p, I.fxPhiS.p, nullptr));
-      if (I.d.dim == 2)
-        HIPOK(launch_chunk_phi(I.fyG.p, nx, ny, Mi, I.fyPhiC.p, I.fyPhiS.p, nullptr));
+    const int Mprev = h.M, twx = h.twx, twy = h.twy;
+    h.M = Mi;
+    h.Px = (nx + Mi - 1) / Mi;
+    h.Py = (ny + Mi - 1) / Mi;
+    set_twist(h, twisted);
+    if (h.M != Mprev || h.twx != twx || h.twy != twy) {
+      pr_status st = fine_factors(I, nullptr);
+      if (st != PR_OK) return st;
     }
   }
   P->M = M;
+  P->twisted = twisted;
   P->lanes_cap = lanes_cap;
   HIPOK(hipDeviceSynchronize());
   if (P->gexec) {
@@ -1914,16 +1964,24 @@ pr_status pr_set_option(pr_problem p, int option, int value) {
         p->use_graph = value == 1;
         return PR_OK;
       case PR_OPT_FINE_CHUNK:
-        if (value != 16 && value != 32) return fail(PR_EINVAL, "fine chunk must be 16 or 32");
-        return apply_layout(p, p->lanes_cap, value);
+        if (value != 16 && value != 20 && value != 24 && value != 32)
+          return fail(PR_EINVAL, "fine chunk must be 16, 20, 24 or 32");
+        return apply_layout(p, p->lanes_cap, value, p->twisted);
+      case PR_OPT_TWISTED:
+        if (value != 0 && value != 1) return fail(PR_EINVAL, "twisted option must be 0 or 1");
+        return apply_layout(p, p->lanes_cap, p->M, value == 1);
+      case PR_OPT_GROUPED:
+        if (value != 0 && value != 1) return fail(PR_EINVAL, "grouped option must be 0 or 1");
+        p->grouped = value == 1;
+        return apply_layout(p, p->lanes_cap, p->M, p->twisted);
       case PR_OPT_LANES:
         if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
           return fail(PR_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
-        return apply_layout(p, value, p->M);
+        return apply_layout(p, value, p->M, p->twisted);
       case PR_OPT_BLOCKS_PER_PASS:
         if (value < 0) return fail(PR_EINVAL, "blocks per pass must be >= 0");
         p->blocks_per_pass = value;
-        return apply_layout(p, p->lanes_cap, p->M);
+        return apply_layout(p, p->lanes_cap, p->M, p->twisted);
       default:
         return fail(PR_EINVAL, "unknown option %d", option);
     }
@@ -1936,6 +1994,8 @@ pr_status pr_get_option(pr_problem p, int option, int* value) {
     switch (option) {
       case PR_OPT_GRAPH: *value = p->use_graph ? 1 : 0; return PR_OK;
       case PR_OPT_FINE_CHUNK: *value = p->M; return PR_OK;
+      case PR_OPT_TWISTED: *value = p->twisted ? 1 : 0; return PR_OK;
+      case PR_OPT_GROUPED: *value = p->grouped ? 1 : 0; return PR_OK;
       case PR_OPT_LANES: *value = p->lanes_cap; return PR_OK;
       case PR_OPT_BLOCKS_PER_PASS: *value = p->blocks_per_pass; return PR_OK;
       default: return fail(PR_EINVAL, "unknown option %d", option);
@@ -1955,12 +2015,14 @@ pr_status pr_autotune(pr_problem p, void* hip_stream, int* lanes, int* chunk, fl
     HIPOK(hipEventCreate(&e1));
     float best = -1.f;
     int bl = p->lanes_cap, bm = p->M;
+    bool btw = p->twisted;
     const bool prof = p->prof;
     p->prof = false;
     pr_status st = PR_OK;
     for (int L = 8; L <= Lmax && st == PR_OK; L <<= 1)
-      for (int M : {16, 32}) {
-        st = apply_layout(p, L == Lmax ? 0 : L, M);
+      for (int tw = 0; tw < 2 && st == PR_OK; tw++)
+      for (int M : {16, 20, 24, 32}) {
+        st = apply_layout(p, L == Lmax ? 0 : L, M, tw == 1);
         if (st != PR_OK) break;
         float ms_min = -1.f;
         for (int rep = 0; rep < 3 && st == PR_OK; rep++) {
@@ -1979,13 +2041,14 @@ pr_status pr_autotune(pr_problem p, void* hip_stream, int* lanes, int* chunk, fl
           best = ms_min;
           bl = L == Lmax ? 0 : L;
           bm = M;
+          btw = tw == 1;
         }
       }
     p->prof = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != PR_OK) return st;
-    st = apply_layout(p, bl, bm);
+    st = apply_layout(p, bl, bm, btw);
     if (st != PR_OK) return st;
     if (lanes) *lanes = bl;
     if (chunk) *chunk = bm;
@@ -2234,9 +2297,9 @@ pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lamb
     for (int t = 0; t < S; t++) {
       PhaseTimer pt(p, PH_FINE, s);
       HIPOK(launch_fine_sweep(Dd + 1 + 2 * t, g.d_work[0], g.n_work[0], g.L, g.M, 0, t > 0, t, s, 0,
-                              g.ft != 0));
+                              g.ft != 0, p->twisted, g.grouped));
       HIPOK(launch_fine_sweep(Dd + 2 + 2 * t, g.d_work[1], g.n_work[1], g.L, g.M, 1, 1, t, s, 0,
-                              false));
+                              false, p->twisted, g.grouped));
     }
     // 6. reverse steps of every slice from lambda_{n+1}: y solve, face gradients
     //    with V_t, x solve, face gradients with W_t
@@ -2251,12 +2314,14 @@ pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lamb
     for (int t = S - 1; t >= 0; t--) {
       {
         PhaseTimer pt(p, PH_FINE, s);
-        HIPOK(launch_fine_sweep(Da, g.d_work[1], g.n_work[1], g.L, g.M, 1, t < S - 1, t, s, 0, false));
+        HIPOK(launch_fine_sweep(Da, g.d_work[1], g.n_work[1], g.L, g.M, 1, t < S - 1, t, s, 0, false,
+                                p->twisted, g.grouped));
       }
       HIPOK(launch_grad_faces(1, Da, Dd + 2 * S + 2 + 2 * t, h, cy, I.adjGay.p, s));
       {
         PhaseTimer pt(p, PH_FINE, s);
-        HIPOK(launch_fine_sweep(Da, g.d_work[0], g.n_work[0], g.L, g.M, 0, 1, t, s, 0, false));
+        HIPOK(launch_fine_sweep(Da, g.d_work[0], g.n_work[0], g.L, g.M, 0, 1, t, s, 0, false,
+                                p->twisted, g.grouped));
       }
       HIPOK(launch_grad_faces(0, Da, Dd + 2 * S + 1 + 2 * t, h, cx, I.adjGax.p, s));
     }

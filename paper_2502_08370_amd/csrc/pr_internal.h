@@ -36,6 +36,11 @@ struct DimInst {
   int L, B;          // lanes per slice block, number of slice blocks
   int M;             // chunk length of the fine sweeps
   int Px, Py;        // chunks per x-line (ceil(nx/M)), per y-line (ceil(ny/M))
+  // Twisted fine factorisation: x-line positions from chunk twx on (y-lines: twy)
+  // hold the UL factors of the line's bottom part (r_p = 1 / v_p, g_p = w_p / v_p,
+  // v the pivots eliminated from the line end), the positions before them the
+  // LU factors of the top part; twx = Px (twy = Py) when the lines are not twisted.
+  int twx, twy;
   int steps;         // fine steps per slice; grouped sweeps skip instances past it
   long slab;         // doubles per slice block of Z: ny*nx*L
   double* Z;         // [B][ny][nx][L]
@@ -375,6 +380,13 @@ int positions_per_lane(int n);
 // lane-blocked copy [line][c][lane] of line-major factors [line][pos]
 hipError_t launch_block_factors(const double* src, int n_lines, int n_pos, double* dst,
                                 hipStream_t s);
+// Fine factors of one direction with the lines twisted at position mid (mid >=
+// n_pos: the plain LU), and the chunk products phi of that factorisation: top
+// chunks from the position to the chunk end, bottom chunks from the chunk start
+// to the position (phiS: the product over the whole chunk).
+hipError_t launch_factorize_twisted(const FactorJob& job, int mid, hipStream_t s);
+hipError_t launch_chunk_phi_twisted(const double* G, int n_lines, int n_pos, int M, int kmid,
+                                    double* phiC, double* phiS, hipStream_t s);
 hipError_t launch_chunk_phi(const double* G, int n_lines, int n_pos, int M, double* phiC,
                             double* phiS, hipStream_t s);
 hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const double* U_in,
@@ -384,9 +396,14 @@ hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, doub
                                    bool with_corr, hipStream_t s);
 // sgn = +1 / -1: add / subtract the instance's DR array on load (0: FIE);
 // forced: the x sweep adds the step's source term (dir 0 only).
+// twisted: two-wave workgroups, the bottom chunks [twx / twy, P) of every line
+// eliminated from the line end with the UL factors (see k_fine_sweep).
+// grouped (twisted, L = 64, FIE only): workgroups of grouped_lines() lines whose
+// work items count line groups of that many lines (k_fine_sweep_g).
 hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
                              int M, int dir, int has_prev, int step, hipStream_t s, int sgn = 0,
-                             bool forced = false);
+                             bool forced = false, bool twisted = false, bool grouped = false);
+int grouped_lines();
 // S = dt A_y U on the slice-interleaved workspace (U with the pending y-sweep
 // correction when has_prev) of one instance, slice blocks [b_lo, b_hi), before
 // fine step `step` (nothing once the instance has finished its steps).

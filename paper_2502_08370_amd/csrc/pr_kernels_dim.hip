@@ -140,6 +140,77 @@ __global__ void k_chunk_phi(const double* __restrict__ G, int n_lines, int n_pos
   }
 }
 
+// Twisted factorisation of I - tau A along each line (one thread per line):
+// positions p < mid keep the LU factors of k_factorize (the top part does not
+// depend on the rest of the line); positions p >= mid get the UL factors of
+// the bottom part, eliminated from the line end: v_{n-1} = diag, v_p = diag_p -
+// w_{p+1}^2 / v_{p+1}, r_p = 1 / v_p, g_p = w_p r_p (coupling to p - 1, so the
+// upward multiplier e_p = w_{p+1} / v_{p+1} is g_{p+1} exactly).
+__global__ void k_factorize_twisted(FactorJob job, int mid) {
+  int line = blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= job.n_lines) return;
+  const double* face = job.face + line * job.face_line_stride;
+  const int n = job.n_pos;
+  const int m = min(mid, n);
+  double r_prev = 0.0;
+  double wl = job.tau_over_h2 * face[0];
+  for (int p = 0; p < m; p++) {
+    double wr = job.tau_over_h2 * face[(long)(p + 1) * job.face_pos_stride];
+    double diag = 1.0 + wl + wr + job.react;
+    double e = (p == 0) ? 0.0 : wl * r_prev;
+    double u = diag - wl * e;
+    double r = 1.0 / u;
+    double g = (p + 1 < n) ? wr * r : 0.0;
+    long idx = (long)line * n + p;
+    job.R[idx] = r;
+    job.G[idx] = g;
+    r_prev = r;
+    wl = wr;
+  }
+  double r_next = 0.0;
+  double wr = job.tau_over_h2 * face[(long)n * job.face_pos_stride];
+  for (int p = n - 1; p >= m; p--) {
+    double wlp = job.tau_over_h2 * face[(long)p * job.face_pos_stride];
+    double diag = 1.0 + wlp + wr + job.react;
+    double e = (p == n - 1) ? 0.0 : wr * r_next;
+    double v = diag - wr * e;
+    double r = 1.0 / v;
+    double g = (p > 0) ? wlp * r : 0.0;
+    long idx = (long)line * n + p;
+    job.R[idx] = r;
+    job.G[idx] = g;
+    r_next = r;
+    wr = wlp;
+  }
+}
+
+// phi of the twisted factorisation: chunks k < kmid as k_chunk_phi (product of g
+// from the position to the chunk end), chunks k >= kmid from the chunk start to
+// the position; phiS[line][k] = the product over the whole chunk.
+__global__ void k_chunk_phi_twisted(const double* __restrict__ G, int n_lines, int n_pos, int M,
+                                    int kmid, double* __restrict__ phiC,
+                                    double* __restrict__ phiS) {
+  int line = blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= n_lines) return;
+  const int P = (n_pos + M - 1) / M;
+  for (int k = 0; k < P; k++) {
+    int p0 = k * M, p1 = min(n_pos, p0 + M);
+    double phi = 1.0;
+    if (k < kmid) {
+      for (int p = p1 - 1; p >= p0; p--) {
+        phi = G[(long)line * n_pos + p] * phi;
+        phiC[(long)p * n_lines + line] = phi;
+      }
+    } else {
+      for (int p = p0; p < p1; p++) {
+        phi = G[(long)line * n_pos + p] * phi;
+        phiC[(long)p * n_lines + line] = phi;
+      }
+    }
+    phiS[(long)line * P + k] = phi;
+  }
+}
+
 // ------------------------------------------------- interleave transposes ---
 
 // Natural U[slice][j][i] <-> Z[b][j][i][l] through a 64 x 64 LDS tile; one
@@ -226,40 +297,63 @@ __global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
 // wave walks its lines in chunks of M positions, holding one chunk in
 // registers while the next one is being loaded. With HP, the pending chunk
 // correction of the previous (other-direction) sweep is added on load.
-// A partial last chunk is computed in full on clamped loads: the line's last
-// back-substitution factor is 0, so the padded positions cannot leak into the
-// real ones, and only real positions are stored. The workspace values are
+// A partial last chunk is computed in full on clamped loads: the multiplier
+// that couples the line's last position to the next one is 0 (stored so for
+// the top part, forced for the bottom part), so the padded positions cannot
+// leak into the real ones, and only real positions are stored. The workspace values are
 // written with nontemporal stores (each is read once, by the next sweep), which
 // keeps the reused carries and factors in the caches.
-template <int L, int M, int DIR, bool HP, int SGN = 0, bool FT = false>
-__global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict__ insts,
-                                                      const WorkItem* __restrict__ work,
-                                                      int step) {
+//
+// TW (twisted factorisation): a workgroup of two waves per line group, which
+// doubles the waves in flight without adding registers per wave. The first
+// wave takes the chunks [0, kmid) with the LU factors of the line's top part
+// (forward y_p = d_p + g_{p-1} y_{p-1}; chunk-local back substitution
+// z_p = r_p y_p + g_p z_{p+1}, zero past the chunk end); the second wave the
+// chunks [kmid, P) from the bottom with the UL factors stored at those
+// positions (upward y_p = d_p + g_{p+1} y_{p+1}; chunk-local substitution
+// z_p = r_p y_p + g_p z_{p-1}, zero before the chunk start). At mid = kmid*M
+// the true values follow from the two innermost chunk-local values:
+// x_{mid-1} = z_{mid-1} + g_{mid-1} x_mid and x_mid = z_mid + g_mid x_{mid-1}.
+// Each wave then resolves its chunks' carries outwards. The consumer's
+// correction keeps its form x_p = z_p + phi_p sigma_k: for a bottom chunk phi
+// is the product of its g from the chunk start to p and sigma the true value
+// just before the chunk.
+template <int L, int M, int DIR, bool HP, int SGN = 0, bool FT = false, bool TW = false>
+__global__ __launch_bounds__(TW ? 2 * kWave : kWave) void k_fine_sweep(
+    const DimInst* __restrict__ insts, const WorkItem* __restrict__ work, int step) {
   constexpr int G = kWave / L;  // lines per wave
   constexpr bool kUni = (L == kWave);
   constexpr int NQ = kUni ? 1 : (G * M + kWave - 1) / kWave;
   // per-position rows: e, r, g, phi of the pending correction, and with a
   // source the spatial factors S_0, S_1
   constexpr int NF = FT ? 4 + kMaxForcing : 4;
+  constexpr int NW = TW ? 2 : 1;  // waves per workgroup
   static_assert(M <= kWave, "chunk longer than a wave");
   static_assert(!FT || DIR == 0, "the source enters the first (x) stage");
-  // factor staging when a wave holds several lines: [NF][G][M+1]
-  __shared__ double sF[kUni ? 1 : NF][kUni ? 1 : G][M + 1];
-  // first value of every chunk of the wave's lines, resolved into carries at the end
+  // factor staging when a wave holds several lines: [wave][NF][G][M+1]
+  __shared__ double sF[NW][kUni ? 1 : NF][kUni ? 1 : G][M + 1];
+  // outer chunk-local value of every chunk of the group's lines (the first of a
+  // top chunk, the last of a bottom chunk), resolved into carries at the end
   constexpr int kMaxChunks = (kMaxCoarseLine + M - 1) / M;
-  __shared__ double zfirst[kMaxChunks][kWave];
+  __shared__ double zouter[kMaxChunks][kWave];
+  __shared__ double zmid[NW][kWave];  // innermost chunk-local values of the two waves
 
   const WorkItem w = work[blockIdx.x];
   const DimInst& I = insts[w.inst];
   if (step >= I.steps) return;  // this instance has finished its fine steps
   if (I.active && !I.active[I.idx]) return;  // converged instance
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = TW ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
   const int gsub = lane / L;
   const int sl = lane - gsub * L;
 
   const int n_lines = DIR == 0 ? I.ny : I.nx;
   const int n_pos = DIR == 0 ? I.nx : I.ny;
   const int P = DIR == 0 ? I.Px : I.Py;
+  // chunks [kbeg, kend) of this wave; the bottom part starts at chunk kmid
+  const int kmid = TW ? min(DIR == 0 ? I.twx : I.twy, P) : P;
+  const bool bottom = TW && wv == 1;
+  const int kbeg = bottom ? kmid : 0, kend = bottom ? P : kmid;
   const int nl_prev = n_pos;  // lines of the previous sweep = our positions
   const long pstr = DIR == 0 ? (long)L : (long)I.nx * L;
   const long lstr = DIR == 0 ? (long)I.nx * L : (long)L;
@@ -342,6 +436,8 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
       }
     }
     if constexpr (kUni) {
+      // lanes past the line end load clamped entries (their values are not used
+      // for the real positions; see process_up for the one multiplier that is)
       const long idx = frow + p0 + (lane < cnt ? lane : 0);
       f[1][0] = R[idx];
       f[2][0] = Gf[idx];
@@ -358,7 +454,11 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
         const int ln = line0 + g, p = p0 + t;
         const bool ok = q < G * M && ln < n_lines && p < n_pos;
         const long idx = ok ? (long)ln * n_pos + p : 0;
-        f[0][qq] = (ok && p > 0) ? Gf[idx - 1] : 0.0;  // e_p = g_{p-1}
+        // e_p: g_{p-1} eliminating downwards (top), g_{p+1} upwards (bottom)
+        if (bottom)
+          f[0][qq] = (ok && p + 1 < n_pos) ? Gf[idx + 1] : 0.0;
+        else
+          f[0][qq] = (ok && p > 0) ? Gf[idx - 1] : 0.0;
         f[1][qq] = R[idx];
         f[2][qq] = Gf[idx];
         if constexpr (HP) f[3][qq] = phiPrev[idx];
@@ -371,11 +471,11 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
   };
 
   double ycarry = 0.0;
-  double gcarry = 0.0;  // g at the last position of the previous chunk (kUni path)
-  auto process = [&](double (&v)[M], double (&sv)[MS], double (&sg)[M], double (&f)[NF][NQ],
-                     int k) {
-    const int p0 = k * M;
-    const int cnt = min(M, n_pos - p0);
+  double gcarry = 0.0;  // kUni: e of the chunk's first processed position, from the previous chunk
+  double zin = 0.0;     // chunk-local value at this wave's innermost position
+  // Staging of a chunk's factor rows in LDS (several lines per wave) and the
+  // per-position load corrections (pending carry, DR term, source).
+  auto stage = [&](double (&f)[NF][NQ]) {
     if constexpr (!kUni) {
 #pragma unroll
       for (int qq = 0; qq < NQ; qq++) {
@@ -384,48 +484,32 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
           const int g = q / M, t = q - g * M;
 #pragma unroll
           for (int c = 0; c < NF; c++)
-            if (HP || c != 3) sF[c][g][t] = f[c][qq];
+            if (HP || c != 3) sF[wv][c][g][t] = f[c][qq];
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
-    auto fac = [&](int c, int t) -> double {
-      if constexpr (kUni) {
-        if (c == 0)  // e_p = g_{p-1}: the previous lane's g, or the last g of the previous chunk
-          return t == 0 ? gcarry : lane_value(f[2][0], t - 1);
-        return lane_value(f[c][0], t);
-      } else {
-        return sF[c][gsub][t];
-      }
-    };
-    double y = ycarry;
-#pragma unroll
-    for (int t = 0; t < M; t++) {
-      double d = v[t];
-      if constexpr (HP) d = fma(fac(3, t), sg[t], d);
-      if constexpr (SGN > 0) {
-        // x stage of DR: U + S; S carries the same pending correction as U
-        if constexpr (HP) sv[t] = fma(fac(3, t), sg[t], sv[t]);
-        d = d + sv[t];
-      } else if constexpr (SGN < 0) {
-        d = d - sv[t];  // y stage: W - S
-        sv[t] = d;      // kept: the next step's S is U' - (W - S)
-      }
-      if constexpr (FT) {
-#pragma unroll
-        for (int m = 0; m < kMaxForcing; m++) d = fma(gl[m], fac(4 + m, t), d);
-      }
-      y = fma(fac(0, t), y, d);
-      v[t] = y;
+  };
+  auto rhs = [&](double (&v)[M], double (&sv)[MS], double (&sg)[M], auto fac, int t) -> double {
+    double d = v[t];
+    if constexpr (HP) d = fma(fac(3, t), sg[t], d);
+    if constexpr (SGN > 0) {
+      // x stage of DR: U + S; S carries the same pending correction as U
+      if constexpr (HP) sv[t] = fma(fac(3, t), sg[t], sv[t]);
+      d = d + sv[t];
+    } else if constexpr (SGN < 0) {
+      d = d - sv[t];  // y stage: W - S
+      sv[t] = d;      // kept: the next step's S is U' - (W - S)
     }
-    ycarry = y;
-    if constexpr (kUni) gcarry = lane_value(f[2][0], M - 1);
-    double z = 0.0;
+    if constexpr (FT) {
 #pragma unroll
-    for (int t = M - 1; t >= 0; t--) {
-      z = fma(fac(2, t), z, fac(1, t) * v[t]);
-      v[t] = z;
+      for (int m = 0; m < kMaxForcing; m++) d = fma(gl[m], fac(4 + m, t), d);
     }
+    return d;
+  };
+  auto store = [&](double (&v)[M], double (&sv)[MS], int k) {
+    const int p0 = k * M;
+    const int cnt = min(M, n_pos - p0);
     if constexpr (SGN < 0) {
 #pragma unroll
       for (int t = 0; t < M; t++) sv[t] = v[t] - sv[t];  // S' = U' - Y (same pending correction)
@@ -463,44 +547,415 @@ __global__ __launch_bounds__(kWave) void k_fine_sweep(const DimInst* __restrict_
           }
       }
     }
-    zfirst[k][lane] = v[0];  // resolved into the chunk's carry below
+  };
+
+  // top part: eliminate downwards, substitute upwards inside the chunk
+  auto process_down = [&](double (&v)[M], double (&sv)[MS], double (&sg)[M],
+                          double (&f)[NF][NQ], int k) {
+    stage(f);
+    auto fac = [&](int c, int t) -> double {
+      if constexpr (kUni) {
+        if (c == 0)  // e_p = g_{p-1}: the previous lane's g, or the last g of the previous chunk
+          return t == 0 ? gcarry : lane_value(f[2][0], t - 1);
+        return lane_value(f[c][0], t);
+      } else {
+        return sF[wv][c][gsub][t];
+      }
+    };
+    double y = ycarry;
+#pragma unroll
+    for (int t = 0; t < M; t++) {
+      const double d = rhs(v, sv, sg, fac, t);
+      y = fma(fac(0, t), y, d);
+      v[t] = y;
+    }
+    ycarry = y;
+    if constexpr (kUni) gcarry = lane_value(f[2][0], M - 1);
+    double z = 0.0;
+#pragma unroll
+    for (int t = M - 1; t >= 0; t--) {
+      z = fma(fac(2, t), z, fac(1, t) * v[t]);
+      v[t] = z;
+    }
+    zin = v[M - 1];
+    store(v, sv, k);
+    zouter[k][lane] = v[0];  // resolved into the previous chunk's carry below
+    if constexpr (!kUni) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  };
+  // bottom part (TW): eliminate upwards, substitute downwards inside the chunk
+  auto process_up = [&](double (&v)[M], double (&sv)[MS], double (&sg)[M],
+                        double (&f)[NF][NQ], int k) {
+    stage(f);
+    const int cnt = min(M, n_pos - k * M);
+    auto fac = [&](int c, int t) -> double {
+      if constexpr (kUni) {
+        // e_p = g_{p+1}: the next lane's g, or the first g of the previous chunk;
+        // 0 at the line's last position (the lanes past it hold clamped loads)
+        if (c == 0)
+          return t == M - 1 ? gcarry : (t + 1 < cnt ? lane_value(f[2][0], t + 1) : 0.0);
+        return lane_value(f[c][0], t);
+      } else {
+        return sF[wv][c][gsub][t];
+      }
+    };
+    double y = ycarry;
+#pragma unroll
+    for (int t = M - 1; t >= 0; t--) {
+      const double d = rhs(v, sv, sg, fac, t);
+      y = fma(fac(0, t), y, d);
+      v[t] = y;
+    }
+    ycarry = y;
+    if constexpr (kUni) gcarry = lane_value(f[2][0], 0);
+    double z = 0.0;
+#pragma unroll
+    for (int t = 0; t < M; t++) {
+      z = fma(fac(2, t), z, fac(1, t) * v[t]);
+      v[t] = z;
+    }
+    zin = v[0];
+    store(v, sv, k);
+    zouter[k][lane] = v[M - 1];  // resolved into the next chunk's carry below
     if constexpr (!kUni) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   };
 
   double vA[M], sA[M], vB[M], sB[M];
   double svA[MS], svB[MS];
   double fA[NF][NQ], fB[NF][NQ];
-  issue(vA, svA, sA, fA, 0);
-  for (int k = 0; k < P; k += 2) {
-    if (k + 1 < P) issue(vB, svB, sB, fB, k + 1);
-    process(vA, svA, sA, fA, k);
-    if (k + 1 < P) {
-      if (k + 2 < P) issue(vA, svA, sA, fA, k + 2);
-      process(vB, svB, sB, fB, k + 1);
+  if (!bottom) {
+    if (kend > kbeg) {
+      issue(vA, svA, sA, fA, kbeg);
+      for (int k = kbeg; k < kend; k += 2) {
+        if (k + 1 < kend) issue(vB, svB, sB, fB, k + 1);
+        process_down(vA, svA, sA, fA, k);
+        if (k + 1 < kend) {
+          if (k + 2 < kend) issue(vA, svA, sA, fA, k + 2);
+          process_down(vB, svB, sB, fB, k + 1);
+        }
+      }
+    }
+  } else {
+    if (kend > kbeg) {
+      issue(vA, svA, sA, fA, kend - 1);
+      for (int k = kend - 1; k >= kbeg; k -= 2) {
+        if (k - 1 >= kbeg) issue(vB, svB, sB, fB, k - 1);
+        process_up(vA, svA, sA, fA, k);
+        if (k - 1 >= kbeg) {
+          if (k - 2 >= kbeg) issue(vA, svA, sA, fA, k - 2);
+          process_up(vB, svB, sB, fB, k - 1);
+        }
+      }
     }
   }
-  // chunk carries: sigma_{P-1} = 0, sigma_k = zfirst_{k+1} + phi_{(k+1) start} sigma_{k+1}
+  // true value just past this wave's innermost chunk (0 at the line end)
+  double xin = 0.0;
+  if constexpr (TW) {
+    zmid[wv][lane] = zin;
+    __syncthreads();
+    if (kmid < P) {
+      const int mid = kmid * M;
+      const double zt = zmid[0][lane], zb = zmid[1][lane];
+      const double gt = Gf[(long)lc * n_pos + mid - 1];  // couples mid-1 to mid (top)
+      const double gb = Gf[(long)lc * n_pos + mid];      // couples mid to mid-1 (bottom)
+      const double xm1 = (zt + gt * zb) / (1.0 - gt * gb);
+      xin = bottom ? xm1 : fma(gb, xm1, zb);
+    }
+  }
+  // chunk carries, from the innermost chunk outwards:
+  //   top:    sigma_k = zfirst_{k+1} + phi_{(k+1) start} sigma_{k+1}
+  //   bottom: sigma_k = zlast_{k-1} + phi_{(k-1) end} sigma_{k-1}
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  if (active) {
+  if (active && kend > kbeg) {
     gdouble* so = sigOut + (long)line * L + sl;
     const long kstr = (long)n_lines * L;
     const gdouble* ps = phiS + (long)line * P;
-    double sigma = 0.0;
-    so[(long)(P - 1) * kstr] = 0.0;
+    double sigma = xin;
     constexpr int kB = 8;
-    for (int k0 = P - 2; k0 >= 0; k0 -= kB) {
-      double ph[kB];
+    if (!bottom) {
+      so[(long)(kend - 1) * kstr] = sigma;
+      for (int k0 = kend - 2; k0 >= kbeg; k0 -= kB) {
+        double ph[kB];
 #pragma unroll
-      for (int u = 0; u < kB; u++) {
-        const int k = k0 - u;
-        ph[u] = k >= 0 ? ps[k + 1] : 0.0;
+        for (int u = 0; u < kB; u++) {
+          const int k = k0 - u;
+          ph[u] = k >= kbeg ? ps[k + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kB; u++) {
+          const int k = k0 - u;
+          if (k >= kbeg) {
+            sigma = fma(ph[u], sigma, zouter[k + 1][lane]);
+            so[(long)k * kstr] = sigma;
+          }
+        }
       }
+    } else {
+      so[(long)kbeg * kstr] = sigma;
+      for (int k0 = kbeg + 1; k0 < kend; k0 += kB) {
+        double ph[kB];
 #pragma unroll
-      for (int u = 0; u < kB; u++) {
-        const int k = k0 - u;
-        if (k >= 0) {
-          sigma = fma(ph[u], sigma, zfirst[k + 1][lane]);
-          so[(long)k * kstr] = sigma;
+        for (int u = 0; u < kB; u++) {
+          const int k = k0 + u;
+          ph[u] = k < kend ? ps[k - 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kB; u++) {
+          const int k = k0 + u;
+          if (k < kend) {
+            sigma = fma(ph[u], sigma, zouter[k - 1][lane]);
+            so[(long)k * kstr] = sigma;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Fine sweep of kGL consecutive lines per workgroup, one slice block of 64
+// slices per line, two waves per line (the twisted form of k_fine_sweep, see
+// there): 2 * kGL waves. The lines of a workgroup lie in one chunk of the
+// previous sweep (M is a multiple of kGL and groups start at multiples of
+// kGL), so their pending-correction carries sigma_prev[k][p][slice] are the
+// same rows: each wave of a half loads M / kGL of the chunk's rows, stages
+// them in LDS, and after a barrier every wave of the half reads the chunk's
+// carries from there. That cuts the carry loads per wave by kGL, which leaves
+// a wave's limited number of outstanding memory operations to the values
+// themselves. The two halves run the same number of rounds (one chunk each
+// per round, the shorter half idle in its last one) so that every wave
+// reaches every barrier.
+constexpr int kGL = 4;  // lines per workgroup of the grouped sweep
+
+template <int M, int DIR, bool HP, bool FT>
+__global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
+    const DimInst* __restrict__ insts, const WorkItem* __restrict__ work, int step) {
+  constexpr int L = kWave;
+  constexpr int NF = FT ? 4 + kMaxForcing : 4;
+  constexpr int Q = M / kGL;  // carry rows loaded by each wave per chunk
+  static_assert(M % kGL == 0, "the chunk's carry rows are split over the group's waves");
+  static_assert(!FT || DIR == 0, "the source enters the first (x) stage");
+  constexpr int kMaxChunks = (kMaxCoarseLine + M - 1) / M;
+  __shared__ double ssig[HP ? 2 : 1][HP ? 2 : 1][HP ? M : 1][kWave];  // [half][buffer][row][slice]
+  __shared__ double zouter[kGL][kMaxChunks][kWave];
+  __shared__ double zmid[2][kGL][kWave];
+
+  const WorkItem w = work[blockIdx.x];
+  const DimInst& I = insts[w.inst];
+  if (step >= I.steps) return;  // this instance has finished its fine steps
+  if (I.active && !I.active[I.idx]) return;  // converged instance
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int half = wid / kGL;  // 0: top part of the line, 1: bottom part
+  const int q = wid - half * kGL;  // line of the group
+  const bool bottom = half == 1;
+
+  const int n_lines = DIR == 0 ? I.ny : I.nx;
+  const int n_pos = DIR == 0 ? I.nx : I.ny;
+  const int P = DIR == 0 ? I.Px : I.Py;
+  const int kmid = min(DIR == 0 ? I.twx : I.twy, P);
+  const int kbeg = bottom ? kmid : 0, kend = bottom ? P : kmid;
+  const int nmine = kend - kbeg;
+  const int nrounds = max(kmid, P - kmid);
+  const int nl_prev = n_pos;
+  const long pstr = DIR == 0 ? (long)L : (long)I.nx * L;
+  const long lstr = DIR == 0 ? (long)I.nx * L : (long)L;
+  const gdouble* R = gp(DIR == 0 ? I.fxR : I.fyR);
+  const gdouble* Gf = gp(DIR == 0 ? I.fxG : I.fyG);
+  const gdouble* phiS = gp(DIR == 0 ? I.fxPhiS : I.fyPhiS);
+  const gdouble* phiPrev = gp(DIR == 0 ? I.fyPhiC : I.fxPhiC);
+  const gdouble* sigPrev = DIR == 0 ? gp(I.sigY) + (long)w.b * I.Py * I.nx * L
+                                    : gp(I.sigX) + (long)w.b * I.Px * I.ny * L;
+  gdouble* sigOut = DIR == 0 ? gp(I.sigX) + (long)w.b * I.Px * I.ny * L
+                             : gp(I.sigY) + (long)w.b * I.Py * I.nx * L;
+
+  const int line0 = w.group * kGL;
+  const int line = line0 + q;
+  const bool active = line < n_lines;  // wave-uniform
+  const int lc = active ? line : n_lines - 1;  // clamped for in-bounds loads
+  const gdouble* zrow_u = gp(I.Z) + w.b * I.slab + (long)lc * lstr;
+  // carry rows of the group's chunk of the previous sweep
+  const gdouble* sgrow_u = sigPrev + ((long)(line0 / M) * nl_prev) * L;
+  const long frow = (long)lc * n_pos;
+  const unsigned usl = (unsigned)lane;
+  const long zo = I.zout;
+  double gl[kMaxForcing] = {};
+  const gdouble* fS = FT ? gp(I.fS) : nullptr;
+  if constexpr (FT) {
+    const int slice = w.b * L + lane;
+    const long nst = (long)I.N * I.steps;
+    const long gi = (long)(slice < I.N ? slice : 0) * I.steps + step;
+#pragma unroll
+    for (int m = 0; m < kMaxForcing; m++) {
+      const double g = gp(I.fgf)[m * nst + gi];
+      gl[m] = slice < I.N ? g : 0.0;
+    }
+  }
+  // chunk processed by this wave in round r
+  auto chunk_of = [&](int r) { return bottom ? P - 1 - r : r; };
+  auto issue = [&](double (&v)[M], double (&sq)[Q], double (&f)[NF], int r) {
+    const int k = chunk_of(r);
+    const int p0 = k * M;
+    const int cnt = min(M, n_pos - p0);
+    const gdouble* zc = zrow_u + (long)p0 * pstr;
+#pragma unroll
+    for (int t = 0; t < M; t++) {
+      const int tt = (cnt == M || t < cnt) ? t : 0;
+      v[t] = (zc + (long)tt * pstr)[usl];
+    }
+    if constexpr (HP) {
+      const gdouble* sc = sgrow_u + (long)p0 * L;
+#pragma unroll
+      for (int t = 0; t < Q; t++) {
+        const int tr = q * Q + t;
+        const int tt = tr < cnt ? tr : 0;
+        sq[t] = (sc + (long)tt * L)[usl];
+      }
+    }
+    const long idx = frow + p0 + (lane < cnt ? lane : 0);
+    f[1] = R[idx];
+    f[2] = Gf[idx];
+    if constexpr (HP) f[3] = phiPrev[idx];
+    if constexpr (FT) {
+#pragma unroll
+      for (int m = 0; m < kMaxForcing; m++) f[4 + m] = fS[m * I.npts + idx];
+    }
+  };
+
+  double ycarry = 0.0, gcarry = 0.0, zin = 0.0;
+  auto round = [&](double (&v)[M], double (&sq)[Q], double (&f)[NF], int r) {
+    const bool mine = r < nmine;  // wave-uniform
+    const int buf = r & 1;
+    if constexpr (HP) {
+      if (mine) {
+#pragma unroll
+        for (int t = 0; t < Q; t++) ssig[half][buf][q * Q + t][lane] = sq[t];
+      }
+      __syncthreads();
+    }
+    if (!mine) return;
+    const int k = chunk_of(r);
+    const int p0 = k * M;
+    const int cnt = min(M, n_pos - p0);
+    auto rhs = [&](int t) -> double {
+      double d = v[t];
+      if constexpr (HP) d = fma(lane_value(f[3], t), ssig[half][buf][t][lane], d);
+      if constexpr (FT) {
+#pragma unroll
+        for (int m = 0; m < kMaxForcing; m++) d = fma(gl[m], lane_value(f[4 + m], t), d);
+      }
+      return d;
+    };
+    double y = ycarry;
+    if (!bottom) {
+#pragma unroll
+      for (int t = 0; t < M; t++) {
+        const double e = t == 0 ? gcarry : lane_value(f[2], t - 1);
+        y = fma(e, y, rhs(t));
+        v[t] = y;
+      }
+      gcarry = lane_value(f[2], M - 1);
+      double z = 0.0;
+#pragma unroll
+      for (int t = M - 1; t >= 0; t--) {
+        z = fma(lane_value(f[2], t), z, lane_value(f[1], t) * v[t]);
+        v[t] = z;
+      }
+      zin = v[M - 1];
+      zouter[q][k][lane] = v[0];
+    } else {
+#pragma unroll
+      for (int t = M - 1; t >= 0; t--) {
+        const double e = t == M - 1 ? gcarry : (t + 1 < cnt ? lane_value(f[2], t + 1) : 0.0);
+        y = fma(e, y, rhs(t));
+        v[t] = y;
+      }
+      gcarry = lane_value(f[2], 0);
+      double z = 0.0;
+#pragma unroll
+      for (int t = 0; t < M; t++) {
+        z = fma(lane_value(f[2], t), z, lane_value(f[1], t) * v[t]);
+        v[t] = z;
+      }
+      zin = v[0];
+      zouter[q][k][lane] = v[M - 1];
+    }
+    ycarry = y;
+    if (active) {
+      gdouble* zc = (gdouble*)zrow_u + (long)p0 * pstr;
+      if (cnt == M) {
+#pragma unroll
+        for (int t = 0; t < M; t++) __builtin_nontemporal_store(v[t], &(zc + zo + (long)t * pstr)[usl]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < M; t++)
+          if (t < cnt) __builtin_nontemporal_store(v[t], &(zc + zo + (long)t * pstr)[usl]);
+      }
+    }
+  };
+
+  double vA[M], vB[M], qA[Q], qB[Q], fA[NF], fB[NF];
+  if (nrounds > 0) {
+    if (nmine > 0) issue(vA, qA, fA, 0);
+    for (int r = 0; r < nrounds; r += 2) {
+      if (r + 1 < nmine) issue(vB, qB, fB, r + 1);
+      round(vA, qA, fA, r);
+      if (r + 1 < nrounds) {
+        if (r + 2 < nmine) issue(vA, qA, fA, r + 2);
+        round(vB, qB, fB, r + 1);
+      }
+    }
+  }
+  // interface of the two parts (see k_fine_sweep)
+  zmid[half][q][lane] = zin;
+  __syncthreads();
+  double xin = 0.0;
+  if (kmid < P) {
+    const int mid = kmid * M;
+    const double zt = zmid[0][q][lane], zb = zmid[1][q][lane];
+    const double gt = Gf[frow + mid - 1];
+    const double gb = Gf[frow + mid];
+    const double xm1 = (zt + gt * zb) / (1.0 - gt * gb);
+    xin = bottom ? xm1 : fma(gb, xm1, zb);
+  }
+  if (active && nmine > 0) {
+    gdouble* so = sigOut + (long)line * L + lane;
+    const long kstr = (long)n_lines * L;
+    const gdouble* ps = phiS + (long)line * P;
+    double sigma = xin;
+    constexpr int kB = 8;
+    if (!bottom) {
+      so[(long)(kend - 1) * kstr] = sigma;
+      for (int k0 = kend - 2; k0 >= kbeg; k0 -= kB) {
+        double ph[kB];
+#pragma unroll
+        for (int u = 0; u < kB; u++) {
+          const int k = k0 - u;
+          ph[u] = k >= kbeg ? ps[k + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kB; u++) {
+          const int k = k0 - u;
+          if (k >= kbeg) {
+            sigma = fma(ph[u], sigma, zouter[q][k + 1][lane]);
+            so[(long)k * kstr] = sigma;
+          }
+        }
+      }
+    } else {
+      so[(long)kbeg * kstr] = sigma;
+      for (int k0 = kbeg + 1; k0 < kend; k0 += kB) {
+        double ph[kB];
+#pragma unroll
+        for (int u = 0; u < kB; u++) {
+          const int k = k0 + u;
+          ph[u] = k < kend ? ps[k - 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kB; u++) {
+          const int k = k0 + u;
+          if (k < kend) {
+            sigma = fma(ph[u], sigma, zouter[q][k - 1][lane]);
+            so[(long)k * kstr] = sigma;
+          }
         }
       }
     }
@@ -1021,6 +1476,19 @@ hipError_t launch_factorize(const FactorJob& job, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_factorize_twisted(const FactorJob& job, int mid, hipStream_t s) {
+  hipLaunchKernelGGL(k_factorize_twisted, dim3((job.n_lines + 127) / 128), dim3(128), 0, s, job,
+                     mid);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_phi_twisted(const double* G, int n_lines, int n_pos, int M, int kmid,
+                                    double* phiC, double* phiS, hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk_phi_twisted, dim3((n_lines + 127) / 128), dim3(128), 0, s, G, n_lines,
+                     n_pos, M, kmid, phiC, phiS);
+  return hipGetLastError();
+}
+
 hipError_t launch_chunk_phi(const double* G, int n_lines, int n_pos, int M, double* phiC,
                             double* phiS, hipStream_t s) {
   int blocks = (n_lines + 63) / 64;
@@ -1043,67 +1511,116 @@ hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, doub
   return hipGetLastError();
 }
 
-template <int L, int M, int DIR, bool HP, int SGN = 0, bool FT = false>
+template <int L, int M, int DIR, bool HP, int SGN, bool FT, bool TW>
 static hipError_t launch_sweep_t(const DimInst* d_insts, const WorkItem* d_work, int n_work,
                                  int step, hipStream_t s) {
-  hipLaunchKernelGGL((k_fine_sweep<L, M, DIR, HP, SGN, FT>), dim3(n_work), dim3(kWave), 0, s,
-                     d_insts, d_work, step);
+  hipLaunchKernelGGL((k_fine_sweep<L, M, DIR, HP, SGN, FT, TW>), dim3(n_work),
+                     dim3(TW ? 2 * kWave : kWave), 0, s, d_insts, d_work, step);
   return hipGetLastError();
 }
 
 // x sweep: pending correction (hp), DR array added (SGN), source (FT)
-template <int L, int M, int SGN>
+template <int L, int M, int SGN, bool TW>
 static hipError_t launch_sweep_x(const DimInst* d_insts, const WorkItem* d_work, int n_work,
                                  int has_prev, int step, hipStream_t s, bool forced) {
   if (forced)
-    return has_prev ? launch_sweep_t<L, M, 0, true, SGN, true>(d_insts, d_work, n_work, step, s)
-                    : launch_sweep_t<L, M, 0, false, SGN, true>(d_insts, d_work, n_work, step, s);
-  return has_prev ? launch_sweep_t<L, M, 0, true, SGN>(d_insts, d_work, n_work, step, s)
-                  : launch_sweep_t<L, M, 0, false, SGN>(d_insts, d_work, n_work, step, s);
+    return has_prev ? launch_sweep_t<L, M, 0, true, SGN, true, TW>(d_insts, d_work, n_work, step, s)
+                    : launch_sweep_t<L, M, 0, false, SGN, true, TW>(d_insts, d_work, n_work, step, s);
+  return has_prev ? launch_sweep_t<L, M, 0, true, SGN, false, TW>(d_insts, d_work, n_work, step, s)
+                  : launch_sweep_t<L, M, 0, false, SGN, false, TW>(d_insts, d_work, n_work, step, s);
 }
 
-template <int L, int M>
+template <int L, int M, bool TW>
 static hipError_t launch_sweep_lm(const DimInst* d_insts, const WorkItem* d_work, int n_work,
                                   int dir, int has_prev, int step, hipStream_t s, int sgn,
                                   bool forced) {
   if (sgn != 0) {  // Douglas-Rachford (short chunks only): x adds S, y subtracts it
     if constexpr (M == kDRChunk) {
       if (dir == 0)
-        return launch_sweep_x<L, M, 1>(d_insts, d_work, n_work, has_prev, step, s, forced);
-      return launch_sweep_t<L, M, 1, true, -1>(d_insts, d_work, n_work, step, s);
+        return launch_sweep_x<L, M, 1, TW>(d_insts, d_work, n_work, has_prev, step, s, forced);
+      return launch_sweep_t<L, M, 1, true, -1, false, TW>(d_insts, d_work, n_work, step, s);
     } else {
       return hipErrorInvalidValue;
     }
   }
-  if (dir == 0) return launch_sweep_x<L, M, 0>(d_insts, d_work, n_work, has_prev, step, s, forced);
-  return has_prev ? launch_sweep_t<L, M, 1, true>(d_insts, d_work, n_work, step, s)
-                  : launch_sweep_t<L, M, 1, false>(d_insts, d_work, n_work, step, s);
+  if (dir == 0)
+    return launch_sweep_x<L, M, 0, TW>(d_insts, d_work, n_work, has_prev, step, s, forced);
+  return has_prev ? launch_sweep_t<L, M, 1, true, 0, false, TW>(d_insts, d_work, n_work, step, s)
+                  : launch_sweep_t<L, M, 1, false, 0, false, TW>(d_insts, d_work, n_work, step, s);
 }
 
-template <int M>
+template <int M, bool TW>
 static hipError_t launch_sweep_m(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
                                  int dir, int has_prev, int step, hipStream_t s, int sgn,
                                  bool f) {
   switch (L) {
-    case 8: return launch_sweep_lm<8, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
-    case 16: return launch_sweep_lm<16, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
-    case 32: return launch_sweep_lm<32, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
-    case 64: return launch_sweep_lm<64, M>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
+    case 8: return launch_sweep_lm<8, M, TW>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
+    case 16: return launch_sweep_lm<16, M, TW>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
+    case 32: return launch_sweep_lm<32, M, TW>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
+    case 64: return launch_sweep_lm<64, M, TW>(d_insts, d_work, n_work, dir, has_prev, step, s, sgn, f);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
-                             int M, int dir, int has_prev, int step, hipStream_t s, int sgn,
-                             bool forced) {
-  if (forced && dir != 0) return hipErrorInvalidValue;
+template <bool TW>
+static hipError_t launch_sweep_tw(const DimInst* d_insts, const WorkItem* d_work, int n_work,
+                                  int L, int M, int dir, int has_prev, int step, hipStream_t s,
+                                  int sgn, bool forced) {
   switch (M) {
     case 16:
-      return launch_sweep_m<16>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn, forced);
+      return launch_sweep_m<16, TW>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn, forced);
+    case 20:
+      return launch_sweep_m<20, TW>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn, forced);
+    case 24:
+      return launch_sweep_m<24, TW>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn, forced);
     case 32:
-      return launch_sweep_m<32>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn, forced);
+      return launch_sweep_m<32, TW>(d_insts, d_work, n_work, L, dir, has_prev, step, s, sgn, forced);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int M>
+static hipError_t launch_sweep_g(const DimInst* d_insts, const WorkItem* d_work, int n_work,
+                                 int dir, int has_prev, int step, hipStream_t s, bool forced) {
+  const dim3 grid(n_work), block(2 * kGL * kWave);
+  if (dir == 1) {
+    if (has_prev)
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 1, true, false>), grid, block, 0, s, d_insts, d_work, step);
+    else
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 1, false, false>), grid, block, 0, s, d_insts, d_work, step);
+  } else if (forced) {
+    if (has_prev)
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, true, true>), grid, block, 0, s, d_insts, d_work, step);
+    else
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, false, true>), grid, block, 0, s, d_insts, d_work, step);
+  } else {
+    if (has_prev)
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, true, false>), grid, block, 0, s, d_insts, d_work, step);
+    else
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, false, false>), grid, block, 0, s, d_insts, d_work, step);
+  }
+  return hipGetLastError();
+}
+
+int grouped_lines() { return kGL; }
+
+hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
+                             int M, int dir, int has_prev, int step, hipStream_t s, int sgn,
+                             bool forced, bool twisted, bool grouped) {
+  if (forced && dir != 0) return hipErrorInvalidValue;
+  if (grouped) {
+    if (L != kWave || sgn != 0 || !twisted) return hipErrorInvalidValue;
+    switch (M) {
+      case 20: return launch_sweep_g<20>(d_insts, d_work, n_work, dir, has_prev, step, s, forced);
+      case 24: return launch_sweep_g<24>(d_insts, d_work, n_work, dir, has_prev, step, s, forced);
+      case 32: return launch_sweep_g<32>(d_insts, d_work, n_work, dir, has_prev, step, s, forced);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return twisted ? launch_sweep_tw<true>(d_insts, d_work, n_work, L, M, dir, has_prev, step, s,
+                                         sgn, forced)
+                 : launch_sweep_tw<false>(d_insts, d_work, n_work, L, M, dir, has_prev, step, s,
+                                          sgn, forced);
 }
 
 int positions_per_lane(int n) {

@@ -50,6 +50,41 @@ def test_fine_propagate(nx, ny, N, s, var):
     assert relerr(F.cpu().numpy().reshape(ref.shape), ref) <= TOL
 
 
+SWEEP_SHAPES = [
+    # nx, ny, N: ragged groups of four lines (ny % 4 != 0), one- and two-chunk lines,
+    # an odd number of chunks (uneven top and bottom parts), 64-slice and padded blocks
+    (70, 45, 64),
+    (19, 130, 64),
+    (41, 23, 40),
+    (100, 37, 3),
+]
+
+
+@pytest.mark.parametrize("twisted,grouped,chunk", [(1, 1, 20), (1, 1, 24), (1, 0, 16), (1, 0, 24),
+                                                   (1, 0, 32), (0, 0, 20), (0, 0, 32)])
+def test_fine_sweep_variants(twisted, grouped, chunk):
+    """Every fine-sweep form (one wave per line; two waves per line from the two ends;
+    four lines per workgroup sharing their carry loads) and chunk length against the
+    oracle, with and without a source term."""
+    for k, (nx, ny, N) in enumerate(SWEEP_SHAPES):
+        w = W.small_dim2(nx, ny, n_slices=N, fine_steps=3, seed=50 + k)
+        if k == 1:
+            src = W.manufactured2d(nx, N, 3)
+            w.forcing = src.forcing
+            S = np.random.default_rng(k).standard_normal((1, ny, nx))
+            w.forcing = (S, src.forcing[1], src.forcing[2])
+        P, O = gpu_problem(w), oracle_problem(w)
+        P.set_option("twisted", twisted)
+        P.set_option("grouped", grouped)
+        P.set_option("fine_chunk", chunk)
+        Uin = slice_inputs(w, seed=k)
+        F = P.new_slices()
+        P.fine_propagate(dev(Uin), F)
+        torch.cuda.synchronize()
+        ref = O.fine_batch(Uin)
+        assert relerr(F.cpu().numpy().reshape(ref.shape), ref) <= TOL, (nx, ny, N)
+
+
 def test_varcoef2d_full_size_sampled():
     """The 1023^2, N = 64, s = 64 workload at its real shape, in the benchmark's
     launch configuration: all 64 slices propagated on the GPU, slices 0, 37 and 63
