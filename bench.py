@@ -116,6 +116,15 @@ def measured_traffic(kernel_src, summary):
     return fig["traffic_bytes_per_launch"] if fig.get("source_sha256_16") == h else None
 
 
+def sweep_label(prob):
+    """Name and form of the fine sweep kernel the handle launches."""
+    tw, gr, m = (prob.get_option(k) for k in ("twisted", "grouped", "fine_chunk"))
+    lanes = max(8, min(64, 1 << (max(ins["n_slices"] for ins in prob.instances) - 1).bit_length()))
+    if tw and gr and lanes == 64 and m in (20, 24):
+        return f"k_fine_sweep_g (four lines per workgroup, two waves per line, chunk {m})"
+    return f"k_fine_sweep ({'two waves' if tw else 'one wave'} per line, chunk {m})"
+
+
 def cpu_baseline(w, budget_s):
     """Oracle (serial FP64 C, one thread) on a bounded sample of the same workload:
     the fine propagator on one slice for as many fine steps as fit the budget."""
@@ -461,7 +470,7 @@ def main():
         "roofline": {"bound": "hbm",
                      "kernel": ("dd2 substep (k_dd2_solve phases + k_dd2_tri0s + k_dd2_kup0)" if dd2 else
                                 "dd substep (k_dd_local + k_dd_runmaps + k_dd_runscan + "
-                                "k_dd_segcarries)" if w.split == "dd" else "k_fine_sweep"),
+                                "k_dd_segcarries)" if w.split == "dd" else sweep_label(prob)),
                      "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic["gbs"] if traffic else None,
