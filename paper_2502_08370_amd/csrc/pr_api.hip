@@ -180,6 +180,10 @@ struct Instance {
 
 }  // namespace
 
+// Fewer one-wave-per-line sweep waves than this (two per SIMD of the 256 CUs):
+// twisted sweeps by default.
+constexpr long kTwistBelowWaves = 2 * 4 * 256;
+
 struct pr_problem_s {
   std::vector<std::unique_ptr<Instance>> inst;
   // phase timers (pr_profile_control / pr_profile_read)
@@ -231,6 +235,7 @@ struct pr_problem_s {
   hipGraphExec_t gexec = nullptr;
   double graph_tol = -1.0;
   const double* graph_U = nullptr;
+  std::vector<char> graph_active;  // host mask of the domain-decomposition instances baked into the graph
   int lanes_cap = 0;  // 0: each instance uses its default lane width
   pr_problem_s* adjT = nullptr;  // transposed problem of the parallel adjoint
   hipStream_t astream = nullptr;  // its stream (runs beside the forward checkpoints)
@@ -1251,11 +1256,15 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // Fine propagation of every slice of every instance: in_base + per-instance
 // offset (slices or states layout) -> out_base + slices offset.
 pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout, double* out_base,
-                   hipStream_t s) {
+                   hipStream_t s, const std::vector<char>* host_active = nullptr) {
   const int n = (int)P->inst.size();
+  // domain-decomposition instances that have converged are skipped on the host
+  // (the dimensional kernels read the device mask themselves)
+  auto skip = [&](int i) { return P->inst[i]->dd && host_active && !(*host_active)[i]; };
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
     const double* U = in_base + (in_states_layout ? I.off_states : I.off_slices);
+    if (skip(i)) continue;
     if (I.dd2) {
       pr_status st = dd2_fine(P, I, U, out_base + I.off_slices, s);
       if (st != PR_OK) return st;
@@ -1291,7 +1300,7 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   }
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
-    if (!I.dd || I.dd2) continue;
+    if (!I.dd || I.dd2 || skip(i)) continue;
     for (int t = 0; t < I.d.fine_steps; t++) {
       if (I.h.nforce) {
         PhaseTimer pt(P, PH_FINE, s);
@@ -1303,7 +1312,7 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   }
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
-    if (I.dd2) continue;
+    if (I.dd2 || skip(i)) continue;
     PhaseTimer pt(P, PH_TRANSPOSE, s);
     if (I.dd)
       HIPOK(launch_dd_from_interleaved(I.d_dd, I.hdd, I.ffine.view(), out_base + I.off_slices, s));
@@ -1725,6 +1734,22 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
     }
     std::unique_ptr<pr_problem_s> P(new (std::nothrow) pr_problem_s());
     if (!P) return fail(PR_ENOMEM, "host allocation failed");
+    // Default fine-sweep form: one wave per (line group, slice block) gives
+    // `waves` waves per sweep; below two per SIMD of the chip the lines are
+    // twisted (two waves each, short chunks, grouped carries), otherwise one
+    // wave per line with long chunks keeps the per-wave overheads lowest.
+    {
+      long waves = 0;
+      for (int i = 0; i < n_instances; i++) {
+        const pr_problem_desc& d = descs[i];
+        if (d.split != PR_SPLIT_DIM) continue;
+        const int L = std::min(64, std::max(8, pow2_at_least(d.n_slices)));
+        const long B = (d.n_slices + L - 1) / L, G = 64 / L;
+        waves += B * std::max((d.ny + G - 1) / G, (d.nx + G - 1) / G);
+      }
+      P->twisted = waves < kTwistBelowWaves;
+      P->M = P->twisted ? 20 : 32;
+    }
     size_t ou = 0, osl = 0, ost = 0;
     for (int i = 0; i < n_instances; i++) {
       auto I = std::make_unique<Instance>();
@@ -1895,7 +1920,7 @@ pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_m
     // one parareal correction: F on all active slices, coarse sweep with the
     // correction and increment, device mask update, increment to the host
     auto correction = [&]() -> pr_status {
-      pr_status r = fine_all(p, U, true, p->F.p, s);
+      pr_status r = fine_all(p, U, true, p->F.p, s, &active);
       if (r != PR_OK) return r;
       r = coarse_sweep_impl(p, p->F.p, p->Gold.p, U, p->d_inc, s, &active);
       if (r != PR_OK) return r;
@@ -1903,8 +1928,11 @@ pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_m
       HIPOK(hipMemcpyAsync(p->h_inc, p->d_inc, n * sizeof(double), hipMemcpyDeviceToHost, s));
       return PR_OK;
     };
-    const bool graph = p->use_graph && !p->any_dd && !p->prof && k_max > 0;
-    if (graph && (!p->gexec || p->graph_tol != tol || p->graph_U != U)) {
+    // The captured correction bakes in which domain-decomposition instances are
+    // still active (their kernels are skipped on the host); it is captured again
+    // when that set changes, i.e. when such an instance converges.
+    const bool graph = p->use_graph && !p->prof && k_max > 0;
+    auto capture = [&]() -> pr_status {
       if (p->gexec) {
         (void)hipGraphExecDestroy(p->gexec);
         p->gexec = nullptr;
@@ -1926,10 +1954,27 @@ pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_m
       HIPOK(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
       p->graph_tol = tol;
       p->graph_U = U;
+      p->graph_active = active;
+      return PR_OK;
+    };
+    auto dd_mask_changed = [&]() {
+      if (!p->any_dd) return false;
+      for (int i = 0; i < n; i++)
+        if (p->inst[i]->dd && active[i] != p->graph_active[i]) return true;
+      return false;
+    };
+    if (graph && (!p->gexec || p->graph_tol != tol || p->graph_U != U ||
+                  p->graph_active.size() != active.size() || dd_mask_changed())) {
+      st = capture();
+      if (st != PR_OK) return st;
     }
     pr_status result = PR_OK;
     for (int k = 0; k < k_max && n_active > 0; k++) {
       if (graph) {
+        if (dd_mask_changed()) {
+          st = capture();
+          if (st != PR_OK) return st;
+        }
         HIPOK(hipGraphLaunch(p->gexec, s));
       } else {
         st = correction();

@@ -93,3 +93,34 @@ def test_autotune_keeps_results(tmp_path):
     for i, w in enumerate(ws):
         Uo, _, _ = oracle_problem(w).parareal(w.u0, 2)
         assert relerr(P.view(U, i, "states").cpu().numpy(), Uo) <= TOL
+
+
+def test_graph_with_domain_decomposition_instances():
+    """Handles holding 1D and 2D domain-decomposition instances beside a dimensional one
+    are captured too: the graph bakes in which of them are still active and is captured
+    again when one converges. Replays match direct launches bit for bit, and the run to
+    a tolerance matches the oracle instance by instance."""
+    ws = [W.small_dim2(37, 29, 6, 3, seed=1),
+          W.small_dd1(300, 4, 2, 8, 6, 2, seed=2),
+          W.small_dd2(40, 33, 2, 0.1, 6, 2, seed=3)]
+    Pg, Pe = gpu_problem(ws), gpu_problem(ws)
+    Pe.set_option("graph", 0)
+    u0 = Pg.pack_u0([w.u0 for w in ws])
+    hists = [oracle_problem(w).parareal(w.u0, 6)[2] for w in ws]
+    # a tolerance between the third increments of the 1D DD and the dimensional
+    # instance: the domain-decomposition instances stop first
+    tol = float(np.sqrt(hists[1][2] * hists[0][2]))
+    for K, t in ((1, 0.0), (4, 0.0), (6, tol)):
+        Ug, Ue = Pg.new_states(), Pe.new_states()
+        kg, ig = Pg.parareal_iterate(u0, Ug, k_max=K, tol=t)
+        scratch = torch.randn(1 << 16, device="cuda", dtype=torch.float64).sum().item()
+        ke, ie = Pe.parareal_iterate(u0, Ue, k_max=K, tol=t)
+        torch.cuda.synchronize()
+        assert kg == ke and ig == ie, (K, kg, ke)
+        assert torch.equal(Ug, Ue), K
+        assert np.isfinite(scratch)
+        for i, w in enumerate(ws):
+            Uo, ko, _ = oracle_problem(w).parareal(w.u0, K, t)
+            assert kg[i] == ko, (K, i, kg[i], ko)
+            assert relerr(Pg.view(Ug, i, "states").cpu().numpy(), Uo) <= TOL
+    assert kg[1] < kg[0]  # a domain-decomposition instance converged first
