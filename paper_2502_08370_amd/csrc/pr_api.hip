@@ -119,6 +119,7 @@ struct Instance {
   DimInst h{};       // host mirror of the device descriptor
   DBuf ax, ay, theta;
   DBuf fxR, fxG, fyR, fyG, fxPhiC, fyPhiC, fxPhiS, fyPhiS;
+  DBuf fxRG, fyRG;  // (r, g) pairs of the fine factors (grouped sweeps)
   DBuf cxR, cxG, cyR, cyG;
   DBuf cxRb, cxGb, cyRb, cyGb, fxRb, fxGb, fyRb, fyGb;  // lane-blocked copies
   DBuf Z, sigX, sigY, tmp;
@@ -380,12 +381,15 @@ FactorJob fine_job(Instance& I, int dir) {
 // split chunk is the line's last) and their chunk products phi.
 pr_status fine_factors(Instance& I, hipStream_t s) {
   const DimInst& h = I.h;
+  const long npts = (long)I.d.nx * I.d.ny;
   HIPOK(launch_factorize_twisted(fine_job(I, 0), h.twx * h.M, s));
   HIPOK(launch_chunk_phi_twisted(I.fxG.p, I.d.ny, I.d.nx, h.M, h.twx, I.fxPhiC.p, I.fxPhiS.p, s));
+  HIPOK(launch_interleave_pairs(I.fxR.p, I.fxG.p, npts, I.fxRG.p, s));
   if (I.d.dim == 2) {
     HIPOK(launch_factorize_twisted(fine_job(I, 1), h.twy * h.M, s));
     HIPOK(launch_chunk_phi_twisted(I.fyG.p, I.d.nx, I.d.ny, h.M, h.twy, I.fyPhiC.p, I.fyPhiS.p,
                                    s));
+    HIPOK(launch_interleave_pairs(I.fyR.p, I.fyG.p, npts, I.fyRG.p, s));
   }
   return PR_OK;
 }
@@ -404,7 +408,7 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   pr_status st = PR_OK;
   (void)st;
   const int Px = (nx + M - 1) / M, Py = (ny + M - 1) / M;
-  HIPOK(I.fxR.alloc(npts)); HIPOK(I.fxG.alloc(npts));
+  HIPOK(I.fxR.alloc(npts)); HIPOK(I.fxG.alloc(npts)); HIPOK(I.fxRG.alloc(2 * npts));
   HIPOK(I.cxR.alloc(npts)); HIPOK(I.cxG.alloc(npts));
   HIPOK(I.fxPhiC.alloc(npts)); HIPOK(I.fxPhiS.alloc((size_t)ny * Px));
   const int Kx = positions_per_lane(nx), Ky = positions_per_lane(ny);
@@ -412,7 +416,7 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   HIPOK(I.cxRb.alloc(nbx)); HIPOK(I.cxGb.alloc(nbx));
   HIPOK(I.fxRb.alloc(nbx)); HIPOK(I.fxGb.alloc(nbx));
   if (d.dim == 2) {
-    HIPOK(I.fyR.alloc(npts)); HIPOK(I.fyG.alloc(npts));
+    HIPOK(I.fyR.alloc(npts)); HIPOK(I.fyG.alloc(npts)); HIPOK(I.fyRG.alloc(2 * npts));
     HIPOK(I.cyR.alloc(npts)); HIPOK(I.cyG.alloc(npts));
     HIPOK(I.fyPhiC.alloc(npts)); HIPOK(I.fyPhiS.alloc((size_t)nx * Py));
     HIPOK(I.cyRb.alloc(nby)); HIPOK(I.cyGb.alloc(nby));
@@ -449,6 +453,7 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   }
   h.fxR = I.fxR.p; h.fxG = I.fxG.p;
   h.fyR = I.fyR.p; h.fyG = I.fyG.p;
+  h.fxRG = I.fxRG.p; h.fyRG = I.fyRG.p;
   h.fxPhiC = I.fxPhiC.p; h.fyPhiC = I.fyPhiC.p; h.fxPhiS = I.fxPhiS.p; h.fyPhiS = I.fyPhiS.p;
   h.Kx = Kx; h.Ky = Ky;
   h.cxRb = I.cxRb.p; h.cxGb = I.cxGb.p; h.cyRb = I.cyRb.p; h.cyGb = I.cyGb.p;

@@ -50,6 +50,8 @@ struct DimInst {
   // fine factorisations, line-major: x-line j entry (j*nx + i), y-line i entry (i*ny + j)
   const double* fxR; const double* fxG;
   const double* fyR; const double* fyG;
+  // the same as (r, g) pairs, [line][pos][2], for one 16-byte load per position
+  const double* fxRG; const double* fyRG;
   // phi of the fine sweeps, stored where their consumer reads them:
   //   fxPhiC[i*ny + j]: x-line j, position i (read by y-lines)
   //   fyPhiC[j*nx + i]: y-line i, position j (read by x-lines and the final transpose)
@@ -385,6 +387,9 @@ hipError_t launch_block_factors(const double* src, int n_lines, int n_pos, doubl
 // chunks from the position to the chunk end, bottom chunks from the chunk start
 // to the position (phiS: the product over the whole chunk).
 hipError_t launch_factorize_twisted(const FactorJob& job, int mid, hipStream_t s);
+// out[2 p] = a[p], out[2 p + 1] = b[p] for p < n.
+hipError_t launch_interleave_pairs(const double* a, const double* b, long n, double* out,
+                                   hipStream_t s);
 hipError_t launch_chunk_phi_twisted(const double* G, int n_lines, int n_pos, int M, int kmid,
                                     double* phiC, double* phiS, hipStream_t s);
 hipError_t launch_chunk_phi(const double* G, int n_lines, int n_pos, int M, double* phiC,

@@ -16,6 +16,8 @@ constexpr int kWave = 64;
 
 #define GLOBAL __attribute__((address_space(1)))
 typedef GLOBAL double gdouble;
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef GLOBAL dv2 gdv2;
 
 // Pointers read from descriptor tables are generic; these casts let the
 // compiler emit global (not flat) memory instructions for them.
@@ -208,6 +210,15 @@ __global__ void k_chunk_phi_twisted(const double* __restrict__ G, int n_lines, i
       }
     }
     phiS[(long)line * P + k] = phi;
+  }
+}
+
+__global__ void k_interleave_pairs(const double* __restrict__ a, const double* __restrict__ b, long n,
+                                   double* __restrict__ out) {
+  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (p < n) {
+    out[2 * p] = a[p];
+    out[2 * p + 1] = b[p];
   }
 }
 
@@ -730,11 +741,12 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
     const DimInst* __restrict__ insts, const WorkItem* __restrict__ work, int step) {
   constexpr int L = kWave;
   constexpr int NF = FT ? 4 + kMaxForcing : 4;
-  constexpr int Q = M / kGL;  // carry rows loaded by each wave per chunk
+  constexpr int Q = M / kGL;  // carry rows staged by each wave per chunk
+  constexpr int QO = (Q + 1) / 2;  // 16-byte loads for them: two rows per load
   static_assert(M % kGL == 0, "the chunk's carry rows are split over the group's waves");
   static_assert(!FT || DIR == 0, "the source enters the first (x) stage");
   constexpr int kMaxChunks = (kMaxCoarseLine + M - 1) / M;
-  __shared__ double ssig[HP ? 2 : 1][HP ? 2 : 1][HP ? M : 1][kWave];  // [half][buffer][row][slice]
+  __shared__ __attribute__((aligned(16))) double ssig[HP ? 2 : 1][HP ? 2 : 1][HP ? M : 1][kWave];  // [half][buffer][row][slice]
   __shared__ double zouter[kGL][kMaxChunks][kWave];
   __shared__ double zmid[2][kGL][kWave];
 
@@ -758,7 +770,7 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
   const int nl_prev = n_pos;
   const long pstr = DIR == 0 ? (long)L : (long)I.nx * L;
   const long lstr = DIR == 0 ? (long)I.nx * L : (long)L;
-  const gdouble* R = gp(DIR == 0 ? I.fxR : I.fyR);
+  const gdv2* RG = (const gdv2*)gp(DIR == 0 ? I.fxRG : I.fyRG);
   const gdouble* Gf = gp(DIR == 0 ? I.fxG : I.fyG);
   const gdouble* phiS = gp(DIR == 0 ? I.fxPhiS : I.fyPhiS);
   const gdouble* phiPrev = gp(DIR == 0 ? I.fyPhiC : I.fxPhiC);
@@ -791,7 +803,10 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
   }
   // chunk processed by this wave in round r
   auto chunk_of = [&](int r) { return bottom ? P - 1 - r : r; };
-  auto issue = [&](double (&v)[M], double (&sq)[Q], double (&f)[NF], int r) {
+  // carry staging: load o of this wave covers rows q Q + 2 o (lanes 0-31) and
+  // q Q + 2 o + 1 (lanes 32-63) of the chunk, two slices per lane
+  const int srow = lane >> 5, sslc = 2 * (lane & 31);
+  auto issue = [&](double (&v)[M], dv2 (&sq)[QO], double (&f)[NF], int r) {
     const int k = chunk_of(r);
     const int p0 = k * M;
     const int cnt = min(M, n_pos - p0);
@@ -802,17 +817,18 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
       v[t] = (zc + (long)tt * pstr)[usl];
     }
     if constexpr (HP) {
-      const gdouble* sc = sgrow_u + (long)p0 * L;
+      const gdouble* sc = sgrow_u + (long)p0 * L + sslc;
 #pragma unroll
-      for (int t = 0; t < Q; t++) {
-        const int tr = q * Q + t;
+      for (int o = 0; o < QO; o++) {
+        const int tr = q * Q + 2 * o + srow;
         const int tt = tr < cnt ? tr : 0;
-        sq[t] = (sc + (long)tt * L)[usl];
+        sq[o] = *(const gdv2*)(sc + (long)tt * L);
       }
     }
     const long idx = frow + p0 + (lane < cnt ? lane : 0);
-    f[1] = R[idx];
-    f[2] = Gf[idx];
+    const dv2 rg = RG[idx];
+    f[1] = rg.x;
+    f[2] = rg.y;
     if constexpr (HP) f[3] = phiPrev[idx];
     if constexpr (FT) {
 #pragma unroll
@@ -821,13 +837,16 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
   };
 
   double ycarry = 0.0, gcarry = 0.0, zin = 0.0;
-  auto round = [&](double (&v)[M], double (&sq)[Q], double (&f)[NF], int r) {
+  auto round = [&](double (&v)[M], dv2 (&sq)[QO], double (&f)[NF], int r) {
     const bool mine = r < nmine;  // wave-uniform
     const int buf = r & 1;
     if constexpr (HP) {
       if (mine) {
 #pragma unroll
-        for (int t = 0; t < Q; t++) ssig[half][buf][q * Q + t][lane] = sq[t];
+        for (int o = 0; o < QO; o++) {
+          const int row = 2 * o + srow;
+          if (row < Q) *(dv2*)&ssig[half][buf][q * Q + row][sslc] = sq[o];
+        }
       }
       __syncthreads();
     }
@@ -892,7 +911,8 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
     }
   };
 
-  double vA[M], vB[M], qA[Q], qB[Q], fA[NF], fB[NF];
+  double vA[M], vB[M], fA[NF], fB[NF];
+  dv2 qA[QO], qB[QO];
   if (nrounds > 0) {
     if (nmine > 0) issue(vA, qA, fA, 0);
     for (int r = 0; r < nrounds; r += 2) {
@@ -1479,6 +1499,13 @@ hipError_t launch_factorize(const FactorJob& job, hipStream_t s) {
 hipError_t launch_factorize_twisted(const FactorJob& job, int mid, hipStream_t s) {
   hipLaunchKernelGGL(k_factorize_twisted, dim3((job.n_lines + 127) / 128), dim3(128), 0, s, job,
                      mid);
+  return hipGetLastError();
+}
+
+hipError_t launch_interleave_pairs(const double* a, const double* b, long n, double* out,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_interleave_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n,
+                     out);
   return hipGetLastError();
 }
 
