@@ -119,7 +119,10 @@ def measured_traffic(kernel_src, summary):
 def sweep_label(prob):
     """Name and form of the fine sweep kernel the handle launches."""
     tw, gr, m = (prob.get_option(k) for k in ("twisted", "grouped", "fine_chunk"))
-    lanes = max(8, min(64, 1 << (max(ins["n_slices"] for ins in prob.instances) - 1).bit_length()))
+    ins = prob.instances[0]
+    lanes = max(8, min(64, 1 << (ins["n_slices"] - 1).bit_length()))
+    if ins["fine"] == 1:  # Douglas-Rachford sweeps use the short chunk
+        return f"k_fine_sweep ({'two waves' if tw else 'one wave'} per line, chunk 16, DR)"
     if tw and gr and lanes == 64 and m in (20, 24):
         return f"k_fine_sweep_g (four lines per workgroup, two waves per line, chunk {m})"
     return f"k_fine_sweep ({'two waves' if tw else 'one wave'} per line, chunk {m})"
@@ -445,6 +448,9 @@ def main():
     elif w.split == "dd":
         # one colour substep reads and writes each node of that colour's components once
         bytes_per_sweep = 16.0 * float(np.mean(covered_nodes(w))) * N
+    elif w.fine == "dr":
+        # a Douglas-Rachford substep reads and writes the value and the term S = dt A_y U
+        bytes_per_sweep = 32.0 * npts * N
     else:
         bytes_per_sweep = 16.0 * npts * N  # one substep: read + write one FP64 per point per slice
     achieved = bytes_per_sweep / (sweep_avg_ms * 1e-3) / 1e9

@@ -201,9 +201,10 @@ pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_m
  *   PR_OPT_FINE_CHUNK  chunk length of the fine line sweeps: 16, 20, 24, 32
  *   PR_OPT_TWISTED     1: each fine line is solved by two waves, one
  *                      eliminating from either end (twisted factorisation);
- *                      0: one wave per line. Default: 1 with chunk 20 when one
- *                      wave per line would give fewer than 2048 waves per sweep
- *                      over the handle's instances, else 0 with chunk 32
+ *                      0: one wave per line. Default: 1 when one wave per line
+ *                      would give fewer than 2048 waves per sweep over the
+ *                      handle's instances, else 0; the default chunk is 20 when
+ *                      the twisted lines include grouped ones (below), else 32
  *   PR_OPT_GROUPED     1 (default): with twisted sweeps, 64-slice blocks, the FIE
  *                      fine propagator and a chunk of 20 or 24, four lines per
  *                      workgroup share the loads of their pending-correction

@@ -1743,17 +1743,21 @@ pr_status pr_create_problem(const pr_problem_desc* descs, int n_instances, void*
     // `waves` waves per sweep; below two per SIMD of the chip the lines are
     // twisted (two waves each, short chunks, grouped carries), otherwise one
     // wave per line with long chunks keeps the per-wave overheads lowest.
+    // Twisted 64-slice FIE lines run grouped, whose loads are balanced at chunk
+    // 20; the other forms keep the long chunk.
     {
       long waves = 0;
+      bool any_grouped = false;
       for (int i = 0; i < n_instances; i++) {
         const pr_problem_desc& d = descs[i];
         if (d.split != PR_SPLIT_DIM) continue;
         const int L = std::min(64, std::max(8, pow2_at_least(d.n_slices)));
         const long B = (d.n_slices + L - 1) / L, G = 64 / L;
         waves += B * std::max((d.ny + G - 1) / G, (d.nx + G - 1) / G);
+        any_grouped = any_grouped || (L == 64 && d.fine == PR_FIE);
       }
       P->twisted = waves < kTwistBelowWaves;
-      P->M = P->twisted ? 20 : 32;
+      P->M = P->twisted && any_grouped ? 20 : 32;
     }
     size_t ou = 0, osl = 0, ost = 0;
     for (int i = 0; i < n_instances; i++) {

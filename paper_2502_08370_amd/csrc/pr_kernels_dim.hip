@@ -413,39 +413,8 @@ __global__ __launch_bounds__(TW ? 2 * kWave : kWave) void k_fine_sweep(
                    int k) {
     const int p0 = k * M;
     const int cnt = min(M, n_pos - p0);
-    if constexpr (kUni) {
-      const gdouble* zc = zrow_u + (long)p0 * pstr;
-      const gdouble* sc = sgrow_u + (long)p0 * L;
-#pragma unroll
-      for (int t = 0; t < M; t++) {
-        const int tt = (cnt == M || t < cnt) ? t : 0;
-        v[t] = (zc + (long)tt * pstr)[usl];
-        if constexpr (SGN != 0) sv[t] = (zc + drOff + (long)tt * pstr)[usl];
-        if constexpr (HP) sg[t] = (sc + (long)tt * L)[usl];
-      }
-    } else {
-      const gdouble* zc = zbase + (long)p0 * pstr;
-      const gdouble* sc = sgRow + (long)p0 * L;
-      if (cnt == M) {
-#pragma unroll
-        for (int t = 0; t < M; t++) {
-          v[t] = zc[t * pstr];
-          if constexpr (SGN != 0) sv[t] = zc[drOff + t * pstr];
-        }
-        if constexpr (HP) {
-#pragma unroll
-          for (int t = 0; t < M; t++) sg[t] = sc[t * L];
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < M; t++) {
-          const int tt = t < cnt ? t : 0;
-          v[t] = zc[tt * pstr];
-          if constexpr (SGN != 0) sv[t] = zc[drOff + tt * pstr];
-          if constexpr (HP) sg[t] = sc[tt * L];
-        }
-      }
-    }
+    // factors first: a wait for an older load is a wait for everything issued
+    // before it, and the factor registers are the first to be reused
     if constexpr (kUni) {
       // lanes past the line end load clamped entries (their values are not used
       // for the real positions; see process_up for the one multiplier that is)
@@ -476,6 +445,39 @@ __global__ __launch_bounds__(TW ? 2 * kWave : kWave) void k_fine_sweep(
         if constexpr (FT) {
 #pragma unroll
           for (int m = 0; m < kMaxForcing; m++) f[4 + m][qq] = fS[m * I.npts + idx];
+        }
+      }
+    }
+    if constexpr (kUni) {
+      const gdouble* zc = zrow_u + (long)p0 * pstr;
+      const gdouble* sc = sgrow_u + (long)p0 * L;
+#pragma unroll
+      for (int t = 0; t < M; t++) {
+        const int tt = (cnt == M || t < cnt) ? t : 0;
+        v[t] = (zc + (long)tt * pstr)[usl];
+        if constexpr (SGN != 0) sv[t] = (zc + drOff + (long)tt * pstr)[usl];
+        if constexpr (HP) sg[t] = (sc + (long)tt * L)[usl];
+      }
+    } else {
+      const gdouble* zc = zbase + (long)p0 * pstr;
+      const gdouble* sc = sgRow + (long)p0 * L;
+      if (cnt == M) {
+#pragma unroll
+        for (int t = 0; t < M; t++) {
+          v[t] = zc[t * pstr];
+          if constexpr (SGN != 0) sv[t] = zc[drOff + t * pstr];
+        }
+        if constexpr (HP) {
+#pragma unroll
+          for (int t = 0; t < M; t++) sg[t] = sc[t * L];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < M; t++) {
+          const int tt = t < cnt ? t : 0;
+          v[t] = zc[tt * pstr];
+          if constexpr (SGN != 0) sv[t] = zc[drOff + tt * pstr];
+          if constexpr (HP) sg[t] = sc[tt * L];
         }
       }
     }
@@ -810,11 +812,17 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
     const int k = chunk_of(r);
     const int p0 = k * M;
     const int cnt = min(M, n_pos - p0);
-    const gdouble* zc = zrow_u + (long)p0 * pstr;
+    // issue order: factors, carry rows, values. A wait for an older load is a wait
+    // for everything issued before it, so the loads whose registers are freed (or
+    // staged) first come first.
+    const long idx = frow + p0 + (lane < cnt ? lane : 0);
+    const dv2 rg = RG[idx];
+    double fphi = 0.0;
+    if constexpr (HP) fphi = phiPrev[idx];
+    double fsrc[kMaxForcing] = {};
+    if constexpr (FT) {
 #pragma unroll
-    for (int t = 0; t < M; t++) {
-      const int tt = (cnt == M || t < cnt) ? t : 0;
-      v[t] = (zc + (long)tt * pstr)[usl];
+      for (int m = 0; m < kMaxForcing; m++) fsrc[m] = fS[m * I.npts + idx];
     }
     if constexpr (HP) {
       const gdouble* sc = sgrow_u + (long)p0 * L + sslc;
@@ -825,14 +833,18 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
         sq[o] = *(const gdv2*)(sc + (long)tt * L);
       }
     }
-    const long idx = frow + p0 + (lane < cnt ? lane : 0);
-    const dv2 rg = RG[idx];
+    const gdouble* zc = zrow_u + (long)p0 * pstr;
+#pragma unroll
+    for (int t = 0; t < M; t++) {
+      const int tt = (cnt == M || t < cnt) ? t : 0;
+      v[t] = (zc + (long)tt * pstr)[usl];
+    }
     f[1] = rg.x;
     f[2] = rg.y;
-    if constexpr (HP) f[3] = phiPrev[idx];
+    if constexpr (HP) f[3] = fphi;
     if constexpr (FT) {
 #pragma unroll
-      for (int m = 0; m < kMaxForcing; m++) f[4 + m] = fS[m * I.npts + idx];
+      for (int m = 0; m < kMaxForcing; m++) f[4 + m] = fsrc[m];
     }
   };
 
@@ -913,14 +925,21 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
 
   double vA[M], vB[M], fA[NF], fB[NF];
   dv2 qA[QO], qB[QO];
+  // the scheduling barriers keep each chunk's loads issued before the previous
+  // chunk is processed (the compiler would otherwise sink them past the barrier
+  // wait of the carry staging)
   if (nrounds > 0) {
     if (nmine > 0) issue(vA, qA, fA, 0);
     for (int r = 0; r < nrounds; r += 2) {
       if (r + 1 < nmine) issue(vB, qB, fB, r + 1);
+      __builtin_amdgcn_sched_barrier(0);
       round(vA, qA, fA, r);
+      __builtin_amdgcn_sched_barrier(0);
       if (r + 1 < nrounds) {
         if (r + 2 < nmine) issue(vA, qA, fA, r + 2);
+        __builtin_amdgcn_sched_barrier(0);
         round(vB, qB, fB, r + 1);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
