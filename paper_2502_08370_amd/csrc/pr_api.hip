@@ -294,9 +294,6 @@ pr_status validate(const pr_problem_desc& d, int idx) {
   if (d.split == PR_SPLIT_DIM && d.dim == 1)
     return fail(PR_EUNSUPPORTED, "instance %d: 1D problems use the DD split (one colour, rho = 1)",
                 idx);
-  if (d.split == PR_SPLIT_DIM && (d.nx > kMaxCoarseLine || d.ny > kMaxCoarseLine))
-    return fail(PR_EUNSUPPORTED, "instance %d: dimensional splitting supports nx, ny <= %d", idx,
-                kMaxCoarseLine);
   if (d.split == PR_SPLIT_DD) {
     if (d.dim == 1 && d.c != 0.0)
       return fail(PR_EUNSUPPORTED, "instance %d: 1D DD splitting needs c = 0", idx);
@@ -412,7 +409,8 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   HIPOK(I.cxR.alloc(npts)); HIPOK(I.cxG.alloc(npts));
   HIPOK(I.fxPhiC.alloc(npts)); HIPOK(I.fxPhiS.alloc((size_t)ny * Px));
   const int Kx = positions_per_lane(nx), Ky = positions_per_lane(ny);
-  const size_t nbx = (size_t)ny * 64 * Kx, nby = (size_t)nx * 64 * Ky;
+  const int Sx = line_segments(nx), Sy = line_segments(ny);
+  const size_t nbx = (size_t)ny * 64 * Kx * Sx, nby = (size_t)nx * 64 * Ky * Sy;
   HIPOK(I.cxRb.alloc(nbx)); HIPOK(I.cxGb.alloc(nbx));
   HIPOK(I.fxRb.alloc(nbx)); HIPOK(I.fxGb.alloc(nbx));
   if (d.dim == 2) {
@@ -455,7 +453,7 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   h.fyR = I.fyR.p; h.fyG = I.fyG.p;
   h.fxRG = I.fxRG.p; h.fyRG = I.fyRG.p;
   h.fxPhiC = I.fxPhiC.p; h.fyPhiC = I.fyPhiC.p; h.fxPhiS = I.fxPhiS.p; h.fyPhiS = I.fyPhiS.p;
-  h.Kx = Kx; h.Ky = Ky;
+  h.Kx = Kx; h.Ky = Ky; h.Sx = Sx; h.Sy = Sy;
   h.cxRb = I.cxRb.p; h.cxGb = I.cxGb.p; h.cyRb = I.cyRb.p; h.cyGb = I.cyGb.p;
   h.fxRb = I.fxRb.p; h.fxGb = I.fxGb.p; h.fyRb = I.fyRb.p; h.fyGb = I.fyGb.p;
   h.tmp = I.tmp.p;
@@ -948,7 +946,9 @@ pr_status setup_dd2_instance(Instance& I, const double* rho_host, hipStream_t s)
       Instance::Strip2 S;
       S.colour = k; S.col0 = i; S.w = j - i; S.W = (S.w + 15) / 16 * 16; S.bc0 = 0;
       if (S.W > kDD2MaxW)
-        return fail(PR_EUNSUPPORTED, "2D DD strip of %d columns (at most %d)", S.w, kDD2MaxW);
+        return fail(PR_EUNSUPPORTED,
+                    "2D DD strip of %d columns (at most %d; use more strips per subdomain)", S.w,
+                    kDD2MaxW);
       I.strips2.push_back(S);
       i = j;
     }

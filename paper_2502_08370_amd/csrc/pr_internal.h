@@ -59,9 +59,10 @@ struct DimInst {
   const double* fxPhiC; const double* fyPhiC;
   const double* fxPhiS; const double* fyPhiS;
   // Lane-blocked factor copies for the one-wave-per-line solvers (coarse
-  // propagator, sequential fine solve, adjoint): line l, position p = lane*K + c
-  // at [l][c][lane], zero past the line end; K = Kx for x-lines, Ky for y-lines.
-  int Kx, Ky;
+  // propagator, sequential fine solve, adjoint): line l, segment s, position
+  // p = s*64*K + lane*K + c at [l][s][c][lane], zero past the line end; K = Kx,
+  // Sx segments for x-lines, Ky, Sy for y-lines (S > 1 only when K = 16).
+  int Kx, Ky, Sx, Sy;
   const double* cxRb; const double* cxGb; const double* cyRb; const double* cyGb;
   const double* fxRb; const double* fxGb; const double* fyRb; const double* fyGb;
   double* tmp;       // one-state scratch of the coarse sweep
@@ -377,9 +378,12 @@ hipError_t launch_faces_from_theta_2d(const double* theta, int nx, int ny, doubl
                                       hipStream_t s);
 hipError_t launch_faces_from_theta_1d(const double* theta, int nx, double* ax, hipStream_t s);
 hipError_t launch_factorize(const FactorJob& job, hipStream_t s);
-// positions per lane K of a line of n points (smallest power of two, 64 K >= n)
+// positions per lane K of a line of n points (smallest power of two with
+// 64 K >= n, at most kLineSeg / 64)
 int positions_per_lane(int n);
-// lane-blocked copy [line][c][lane] of line-major factors [line][pos]
+// Segments of a line of n positions for the one-wave-per-line solvers.
+int line_segments(int n);
+// lane-blocked copy [line][s][c][lane] of line-major factors [line][pos]
 hipError_t launch_block_factors(const double* src, int n_lines, int n_pos, double* dst,
                                 hipStream_t s);
 // Fine factors of one direction with the lines twisted at position mid (mid >=
@@ -418,15 +422,19 @@ hipError_t launch_dr_stencil(const DimInst* d_inst, const DimInst& h, int has_pr
 // out = out - S (mode 1).
 hipError_t launch_dr_stencil_nat(const DimInst* d_inst, const DimInst& h, const double* U,
                                  double* out, int mode, hipStream_t s);
-// Exact line solves of one state, one wave per line (lines <= kMaxCoarseLine).
+// Exact line solves of one state, one wave per line (lines longer than
+// kLineSeg in segments of kLineSeg positions).
 // fine = false uses the coarse factorisation, fine = true the fine one. With
 // gtab != NULL the x solve's right-hand side also receives sum_m
 // gtab[m * gstride + gidx] S_m (a source table premultiplied by the step).
 hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
                            bool fine, hipStream_t s, const double* gtab = nullptr, long gidx = 0,
                            long gstride = 0);
-// Largest grid extent the coarse sweeps handle (whole line per wave, 64-point chunks).
-constexpr int kMaxCoarseLine = 1024;
+// Positions a wave of the one-wave-per-line solvers holds at once (64 lanes x
+// 16): longer lines are solved in segments of this length. The fine sweeps keep
+// the chunk outer values of lines up to this length in LDS, of longer lines in
+// the carry array.
+constexpr int kLineSeg = 1024;
 constexpr int kCoarseRowsPerBlock = 4;    // x lines per block of the coarse x kernels
 constexpr int kCoarseColsPerBlock = 4;    // y lines per block of the coarse y kernels
 // Batched coarse sweep: one launch covers every instance's slice n (items of

@@ -344,8 +344,9 @@ __global__ __launch_bounds__(TW ? 2 * kWave : kWave) void k_fine_sweep(
   // factor staging when a wave holds several lines: [wave][NF][G][M+1]
   __shared__ double sF[NW][kUni ? 1 : NF][kUni ? 1 : G][M + 1];
   // outer chunk-local value of every chunk of the group's lines (the first of a
-  // top chunk, the last of a bottom chunk), resolved into carries at the end
-  constexpr int kMaxChunks = (kMaxCoarseLine + M - 1) / M;
+  // top chunk, the last of a bottom chunk), resolved into carries at the end;
+  // lines of more chunks park them in the carry slots they resolve into
+  constexpr int kMaxChunks = (kLineSeg + M - 1) / M;
   __shared__ double zouter[kMaxChunks][kWave];
   __shared__ double zmid[NW][kWave];  // innermost chunk-local values of the two waves
 
@@ -381,6 +382,12 @@ __global__ __launch_bounds__(TW ? 2 * kWave : kWave) void k_fine_sweep(
   const int line = line0 + gsub;
   const bool active = line < n_lines;
   const int lc = active ? line : n_lines - 1;  // clamped for in-bounds loads
+  // chunk outer values in LDS, or (longer lines) in this lane's carry slots:
+  // a top chunk's in the slot of the chunk above it, a bottom chunk's in the
+  // slot of the chunk below it, which the resolution reads before overwriting
+  const bool zlds = P <= kMaxChunks;  // wave-uniform
+  gdouble* zslot = sigOut + (long)lc * L + sl;
+  const long kstr = (long)n_lines * L;
   // row of the previous sweep's carries for the chunk that holds this line
   const gdouble* sgRow = sigPrev + ((long)(lc / M) * nl_prev) * L + sl;
   gdouble* zbase = gp(I.Z) + w.b * I.slab + (long)lc * lstr + sl;
@@ -592,7 +599,9 @@ __global__ __launch_bounds__(TW ? 2 * kWave : kWave) void k_fine_sweep(
     }
     zin = v[M - 1];
     store(v, sv, k);
-    zouter[k][lane] = v[0];  // resolved into the previous chunk's carry below
+    // resolved into the previous chunk's carry below
+    if (zlds) zouter[k][lane] = v[0];
+    else if (active && k > kbeg) zslot[(long)(k - 1) * kstr] = v[0];
     if constexpr (!kUni) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   };
   // bottom part (TW): eliminate upwards, substitute downwards inside the chunk
@@ -628,7 +637,9 @@ __global__ __launch_bounds__(TW ? 2 * kWave : kWave) void k_fine_sweep(
     }
     zin = v[0];
     store(v, sv, k);
-    zouter[k][lane] = v[M - 1];  // resolved into the next chunk's carry below
+    // resolved into the next chunk's carry below
+    if (zlds) zouter[k][lane] = v[M - 1];
+    else if (active && k + 1 < kend) zslot[(long)(k + 1) * kstr] = v[M - 1];
     if constexpr (!kUni) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   };
 
@@ -679,25 +690,25 @@ __global__ __launch_bounds__(TW ? 2 * kWave : kWave) void k_fine_sweep(
   //   bottom: sigma_k = zlast_{k-1} + phi_{(k-1) end} sigma_{k-1}
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   if (active && kend > kbeg) {
-    gdouble* so = sigOut + (long)line * L + sl;
-    const long kstr = (long)n_lines * L;
+    gdouble* so = zslot;
     const gdouble* ps = phiS + (long)line * P;
     double sigma = xin;
     constexpr int kB = 8;
     if (!bottom) {
       so[(long)(kend - 1) * kstr] = sigma;
       for (int k0 = kend - 2; k0 >= kbeg; k0 -= kB) {
-        double ph[kB];
+        double ph[kB], zq[kB];
 #pragma unroll
         for (int u = 0; u < kB; u++) {
           const int k = k0 - u;
           ph[u] = k >= kbeg ? ps[k + 1] : 0.0;
+          zq[u] = k >= kbeg ? (zlds ? zouter[k + 1][lane] : so[(long)k * kstr]) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kB; u++) {
           const int k = k0 - u;
           if (k >= kbeg) {
-            sigma = fma(ph[u], sigma, zouter[k + 1][lane]);
+            sigma = fma(ph[u], sigma, zq[u]);
             so[(long)k * kstr] = sigma;
           }
         }
@@ -705,17 +716,18 @@ __global__ __launch_bounds__(TW ? 2 * kWave : kWave) void k_fine_sweep(
     } else {
       so[(long)kbeg * kstr] = sigma;
       for (int k0 = kbeg + 1; k0 < kend; k0 += kB) {
-        double ph[kB];
+        double ph[kB], zq[kB];
 #pragma unroll
         for (int u = 0; u < kB; u++) {
           const int k = k0 + u;
           ph[u] = k < kend ? ps[k - 1] : 0.0;
+          zq[u] = k < kend ? (zlds ? zouter[k - 1][lane] : so[(long)k * kstr]) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kB; u++) {
           const int k = k0 + u;
           if (k < kend) {
-            sigma = fma(ph[u], sigma, zouter[k - 1][lane]);
+            sigma = fma(ph[u], sigma, zq[u]);
             so[(long)k * kstr] = sigma;
           }
         }
@@ -747,7 +759,7 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
   constexpr int QO = (Q + 1) / 2;  // 16-byte loads for them: two rows per load
   static_assert(M % kGL == 0, "the chunk's carry rows are split over the group's waves");
   static_assert(!FT || DIR == 0, "the source enters the first (x) stage");
-  constexpr int kMaxChunks = (kMaxCoarseLine + M - 1) / M;
+  constexpr int kMaxChunks = (kLineSeg + M - 1) / M;
   __shared__ __attribute__((aligned(16))) double ssig[HP ? 2 : 1][HP ? 2 : 1][HP ? M : 1][kWave];  // [half][buffer][row][slice]
   __shared__ double zouter[kGL][kMaxChunks][kWave];
   __shared__ double zmid[2][kGL][kWave];
@@ -785,6 +797,11 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
   const int line = line0 + q;
   const bool active = line < n_lines;  // wave-uniform
   const int lc = active ? line : n_lines - 1;  // clamped for in-bounds loads
+  // chunk outer values in LDS, or (longer lines) in the carry slots they
+  // resolve into (see k_fine_sweep)
+  const bool zlds = P <= kMaxChunks;  // workgroup-uniform
+  gdouble* zslot = sigOut + (long)lc * L + lane;
+  const long kstr = (long)n_lines * L;
   const gdouble* zrow_u = gp(I.Z) + w.b * I.slab + (long)lc * lstr;
   // carry rows of the group's chunk of the previous sweep
   const gdouble* sgrow_u = sigPrev + ((long)(line0 / M) * nl_prev) * L;
@@ -891,7 +908,8 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
         v[t] = z;
       }
       zin = v[M - 1];
-      zouter[q][k][lane] = v[0];
+      if (zlds) zouter[q][k][lane] = v[0];
+      else if (active && k > kbeg) zslot[(long)(k - 1) * kstr] = v[0];
     } else {
 #pragma unroll
       for (int t = M - 1; t >= 0; t--) {
@@ -907,7 +925,8 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
         v[t] = z;
       }
       zin = v[0];
-      zouter[q][k][lane] = v[M - 1];
+      if (zlds) zouter[q][k][lane] = v[M - 1];
+      else if (active && k + 1 < kend) zslot[(long)(k + 1) * kstr] = v[M - 1];
     }
     ycarry = y;
     if (active) {
@@ -956,25 +975,25 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
     xin = bottom ? xm1 : fma(gb, xm1, zb);
   }
   if (active && nmine > 0) {
-    gdouble* so = sigOut + (long)line * L + lane;
-    const long kstr = (long)n_lines * L;
+    gdouble* so = zslot;
     const gdouble* ps = phiS + (long)line * P;
     double sigma = xin;
     constexpr int kB = 8;
     if (!bottom) {
       so[(long)(kend - 1) * kstr] = sigma;
       for (int k0 = kend - 2; k0 >= kbeg; k0 -= kB) {
-        double ph[kB];
+        double ph[kB], zq[kB];
 #pragma unroll
         for (int u = 0; u < kB; u++) {
           const int k = k0 - u;
           ph[u] = k >= kbeg ? ps[k + 1] : 0.0;
+          zq[u] = k >= kbeg ? (zlds ? zouter[q][k + 1][lane] : so[(long)k * kstr]) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kB; u++) {
           const int k = k0 - u;
           if (k >= kbeg) {
-            sigma = fma(ph[u], sigma, zouter[q][k + 1][lane]);
+            sigma = fma(ph[u], sigma, zq[u]);
             so[(long)k * kstr] = sigma;
           }
         }
@@ -982,17 +1001,18 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
     } else {
       so[(long)kbeg * kstr] = sigma;
       for (int k0 = kbeg + 1; k0 < kend; k0 += kB) {
-        double ph[kB];
+        double ph[kB], zq[kB];
 #pragma unroll
         for (int u = 0; u < kB; u++) {
           const int k = k0 + u;
           ph[u] = k < kend ? ps[k - 1] : 0.0;
+          zq[u] = k < kend ? (zlds ? zouter[q][k - 1][lane] : so[(long)k * kstr]) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kB; u++) {
           const int k = k0 + u;
           if (k < kend) {
-            sigma = fma(ph[u], sigma, zouter[q][k - 1][lane]);
+            sigma = fma(ph[u], sigma, zq[u]);
             so[(long)k * kstr] = sigma;
           }
         }
@@ -1003,27 +1023,24 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
 
 // -------------------------------------------------------- coarse sweeps ---
 // One state (natural layout). Each line is solved exactly by one wave: lane l
-// owns the K consecutive positions lK .. lK+K-1 (64 K >= line length). The
-// forward elimination y_p = e_p y_{p-1} + d_p and the back substitution
+// owns the K consecutive positions lK .. lK+K-1 of a segment of 64 K positions
+// (the whole line when it has at most kLineSeg positions). The forward
+// elimination y_p = e_p y_{p-1} + d_p and the back substitution
 // x_p = g_p x_{p+1} + r_p y_p are affine recurrences: each lane composes its K
 // maps, one inclusive scan of the 64 lane maps across the wave gives every lane
-// its incoming value, and each lane re-runs its K steps from it. The line stays
-// in registers between the two passes.
+// its incoming value, and each lane re-runs its K steps from it. A line of one
+// segment stays in registers between the two passes; a longer one is
+// eliminated segment by segment downwards with the last y (and the last g, the
+// next segment's first multiplier) carried across, the y of every segment but
+// the last parked in the destination, and then substituted segment by segment
+// upwards with the first x carried across.
 //
-// The factors are read in the lane-blocked layout [line][c][lane] (position
-// lane*K + c; one contiguous 512-byte segment per load). The state moves between
-// its natural layout and the lanes through an LDS line buffer with one pad slot
-// per 16 entries, which keeps both the position-ordered accesses of the global
-// loads and stores and the lane-blocked accesses of the solve free of bank
-// conflicts.
-
-// positions per lane: the smallest power of two with 64 K >= n
-__device__ __forceinline__ int chunks_pow2_dev(int n) {
-  const int c = (n + kWave - 1) / kWave;
-  int p = 1;
-  while (p < c) p <<= 1;
-  return p;
-}
+// The factors are read in the lane-blocked layout [line][segment][c][lane]
+// (position lane*K + c of the segment; one contiguous 512-byte segment per
+// load). The state moves between its natural layout and the lanes through an
+// LDS line buffer with one pad slot per 16 entries, which keeps both the
+// position-ordered accesses of the global loads and stores and the lane-blocked
+// accesses of the solve free of bank conflicts.
 
 __device__ __forceinline__ int lds_pad(int q) { return q + (q >> 4); }
 
@@ -1031,7 +1048,7 @@ __device__ __forceinline__ int lds_pad(int q) { return q + (q >> 4); }
 // buffers start on different banks)
 __host__ __device__ constexpr int line_buf_len(int K) { return 68 * K + 1; }
 
-constexpr int kKMax = kMaxCoarseLine / kWave;  // positions per lane of the longest line
+constexpr int kKMax = kLineSeg / kWave;  // positions per lane of a segment
 
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1042,7 +1059,7 @@ __device__ __forceinline__ void wave_lds_fence() {
 // r = 0, value 0), so there is no branch on K between a load and its use and the
 // loads stay in flight together.
 
-// Loads the line's blocked factors (Rb, Gb at the line) into registers.
+// Loads a segment's blocked factors (Rb, Gb at the segment) into registers.
 __device__ __forceinline__ void load_line_factors(double (&gq)[kKMax], double (&rq)[kKMax], int K,
                                                   const gdouble* Rb, const gdouble* Gb,
                                                   int lane) {
@@ -1054,26 +1071,22 @@ __device__ __forceinline__ void load_line_factors(double (&gq)[kKMax], double (&
   }
 }
 
-// Solves the line whose right-hand side is v (lane-blocked, zero past the line
-// end and for t >= K) in place, with the line's factors from load_line_factors.
-__device__ __forceinline__ void line_solve_lanes(double (&v)[kKMax], int K,
-                                                 const double (&gq)[kKMax],
-                                                 const double (&rq)[kKMax], int lane) {
-  // e_p = g_{p-1}: the lane's previous entry, or the last entry of the lane below
+// Forward elimination y_p = e_p y_{p-1} + v_p, in place, of one lane-blocked
+// segment (v zero past the line end and for t >= K; e_p = g_{p-1}, past the line
+// end g = 0, so those positions stay 0). yin is y just before the segment and
+// ein the multiplier of its first position (the g of the position before it),
+// both 0 for a line's first segment; on return they hold the same two values
+// for the next segment.
+__device__ __forceinline__ void seg_forward(double (&v)[kKMax], int K, const double (&gq)[kKMax],
+                                            double& yin, double& ein, int lane) {
   double glast = 0.0;
 #pragma unroll
   for (int t = 0; t < kKMax; t++) glast = t == K - 1 ? gq[t] : glast;
   double e0 = __shfl_up(glast, 1, kWave);
-  if (lane == 0) e0 = 0.0;
-  double eq[kKMax], gg[kKMax], rr[kKMax];
+  if (lane == 0) e0 = ein;
+  double eq[kKMax];
 #pragma unroll
-  for (int t = 0; t < kKMax; t++) {
-    const bool in = t < K;
-    eq[t] = in ? (t == 0 ? e0 : gq[t - 1]) : 1.0;
-    gg[t] = in ? gq[t] : 1.0;
-    rr[t] = in ? rq[t] : 0.0;
-  }
-  // forward elimination (past the line end g = 0, so those positions stay 0)
+  for (int t = 0; t < kKMax; t++) eq[t] = t < K ? (t == 0 ? e0 : gq[t - 1]) : 1.0;
   double A = 1.0, B = 0.0;
 #pragma unroll
   for (int t = 0; t < kKMax; t++) {
@@ -1081,168 +1094,261 @@ __device__ __forceinline__ void line_solve_lanes(double (&v)[kKMax], int K,
     A = eq[t] * A;
   }
   affine_scan_up(A, B, lane);
-  double y = __shfl_up(B, 1, kWave);  // value just before the lane's first position
-  if (lane == 0) y = 0.0;
+  const double ap = __shfl_up(A, 1, kWave), bp = __shfl_up(B, 1, kWave);
+  double y = lane == 0 ? yin : fma(ap, yin, bp);  // y just before the lane's first position
 #pragma unroll
   for (int t = 0; t < kKMax; t++) {
     y = fma(eq[t], y, v[t]);
     v[t] = y;
   }
-  // back substitution
-  A = 1.0;
-  B = 0.0;
+  yin = lane_value(fma(A, yin, B), kWave - 1);
+  ein = lane_value(glast, kWave - 1);
+}
+
+// Back substitution x_p = g_p x_{p+1} + r_p y_p, in place (v holds y), of one
+// lane-blocked segment. xin is x just past the segment (0 for a line's last
+// segment); on return it holds the segment's first x.
+__device__ __forceinline__ void seg_backward(double (&v)[kKMax], int K, const double (&gq)[kKMax],
+                                             const double (&rq)[kKMax], double& xin, int lane) {
+  double gg[kKMax], rr[kKMax];
+#pragma unroll
+  for (int t = 0; t < kKMax; t++) {
+    gg[t] = t < K ? gq[t] : 1.0;
+    rr[t] = t < K ? rq[t] : 0.0;
+  }
+  double A = 1.0, B = 0.0;
 #pragma unroll
   for (int t = kKMax - 1; t >= 0; t--) {
     B = fma(gg[t], B, rr[t] * v[t]);
     A = gg[t] * A;
   }
   affine_scan_down(A, B, lane);
-  double x = __shfl_down(B, 1, kWave);  // value just after the lane's last position
-  if (lane == kWave - 1) x = 0.0;
+  const double an = __shfl_down(A, 1, kWave), bn = __shfl_down(B, 1, kWave);
+  double x = lane == kWave - 1 ? xin : fma(an, xin, bn);  // x just after the lane's last position
 #pragma unroll
   for (int t = kKMax - 1; t >= 0; t--) {
     x = fma(gg[t], x, rr[t] * v[t]);
     v[t] = x;
   }
+  xin = lane_value(fma(A, xin, B), 0);
 }
 
-// LDS line buffers are sized for the longest line, so every buffer access
-// below stays inside its own buffer for any K.
+// LDS line buffers hold one segment, so every buffer access below stays inside
+// its own buffer for any K.
 constexpr int kLineBuf = line_buf_len(kKMax);
 
-// One row (contiguous, n values): src -> dst (may alias); buf is the wave's
-// LDS line buffer. With S != NULL the right-hand side also receives
-// g0 S_0 + g1 S_1 (S_m at the row, S_1 = S_0 + spts).
+// One row (contiguous, n values, S segments of 64 K): src -> dst (may alias);
+// buf is the wave's LDS line buffer. With Sf != NULL the right-hand side also
+// receives g0 S_0 + g1 S_1 (S_m at the row, S_1 = S_0 + spts).
 __device__ __forceinline__ void solve_row(const gdouble* src, gdouble* dst, const gdouble* Rb,
-                                          const gdouble* Gb, int n, int K, double* buf, int lane,
-                                          const gdouble* S = nullptr, long spts = 0,
+                                          const gdouble* Gb, int n, int K, int S, double* buf,
+                                          int lane, const gdouble* Sf = nullptr, long spts = 0,
                                           double g0 = 0.0, double g1 = 0.0) {
+  const int SL = kWave * K;
   double v[kKMax], gq[kKMax], rq[kKMax];
+  // v (position order) -> lane-blocked v, through the LDS buffer
+  auto to_lanes = [&]() {
 #pragma unroll
-  for (int t = 0; t < kKMax; t++) {
-    const int p = t * kWave + lane;
-    const double x = src[p < n ? p : 0];
-    v[t] = p < n ? x : 0.0;  // p >= n for every t >= K
-  }
-  if (S) {  // wave-uniform
+    for (int t = 0; t < kKMax; t++) buf[lds_pad(t * kWave + lane)] = v[t];
+    wave_lds_fence();
+#pragma unroll
+    for (int t = 0; t < kKMax; t++) {
+      const double x = buf[lds_pad(lane * K + (t < K ? t : 0))];
+      v[t] = t < K ? x : 0.0;
+    }
+    wave_lds_fence();
+  };
+  // lane-blocked v -> dst[p0 + p], p < ns
+  auto from_lanes = [&](int p0, int ns) {
+#pragma unroll
+    for (int t = 0; t < kKMax; t++)
+      if (t < K) buf[lds_pad(lane * K + t)] = v[t];
+    wave_lds_fence();
 #pragma unroll
     for (int t = 0; t < kKMax; t++) {
       const int p = t * kWave + lane;
-      const int pc = p < n ? p : 0;
-      const double s0 = S[pc], s1 = S[spts + pc];
-      v[t] = p < n ? fma(g1, s1, fma(g0, s0, v[t])) : 0.0;
+      if (p < ns) dst[p0 + p] = buf[lds_pad(p)];
     }
+    wave_lds_fence();
+  };
+  auto load_seg = [&](const gdouble* a, int p0, int ns) {
+#pragma unroll
+    for (int t = 0; t < kKMax; t++) {
+      const int p = t * kWave + lane;
+      const double x = a[p0 + (p < ns ? p : 0)];
+      v[t] = p < ns ? x : 0.0;  // p >= ns for every t >= K
+    }
+  };
+  double yc = 0.0, ec = 0.0;
+  for (int sg = 0; sg < S; sg++) {
+    const int p0 = sg * SL, ns = min(n - p0, SL);
+    load_seg(src, p0, ns);
+    if (Sf) {  // wave-uniform
+#pragma unroll
+      for (int t = 0; t < kKMax; t++) {
+        const int p = t * kWave + lane;
+        const int pc = p0 + (p < ns ? p : 0);
+        const double s0 = Sf[pc], s1 = Sf[spts + pc];
+        v[t] = p < ns ? fma(g1, s1, fma(g0, s0, v[t])) : 0.0;
+      }
+    }
+    load_line_factors(gq, rq, K, Rb + (long)sg * SL, Gb + (long)sg * SL, lane);
+    to_lanes();
+    seg_forward(v, K, gq, yc, ec, lane);
+    if (sg + 1 < S) from_lanes(p0, ns);  // y parked in dst (read back by the same lanes)
   }
-  load_line_factors(gq, rq, K, Rb, Gb, lane);
-#pragma unroll
-  for (int t = 0; t < kKMax; t++) buf[lds_pad(t * kWave + lane)] = v[t];
-  wave_lds_fence();
-#pragma unroll
-  for (int t = 0; t < kKMax; t++) {
-    const double x = buf[lds_pad(lane * K + (t < K ? t : 0))];
-    v[t] = t < K ? x : 0.0;
-  }
-  line_solve_lanes(v, K, gq, rq, lane);
-  wave_lds_fence();
-#pragma unroll
-  for (int t = 0; t < kKMax; t++)
-    if (t < K) buf[lds_pad(lane * K + t)] = v[t];
-  wave_lds_fence();
-#pragma unroll
-  for (int t = 0; t < kKMax; t++) {
-    const int p = t * kWave + lane;
-    if (p < n) dst[p] = buf[lds_pad(p)];
+  double xc = 0.0;
+  for (int sg = S - 1; sg >= 0; sg--) {
+    const int p0 = sg * SL, ns = min(n - p0, SL);
+    if (sg + 1 < S) {
+      load_seg(dst, p0, ns);
+      load_line_factors(gq, rq, K, Rb + (long)sg * SL, Gb + (long)sg * SL, lane);
+      to_lanes();
+    }
+    seg_backward(v, K, gq, rq, xc, lane);
+    from_lanes(p0, ns);
   }
 }
 
 constexpr int kRowsPerBlock = kCoarseRowsPerBlock;
 constexpr int kColsPerBlock = kCoarseColsPerBlock;
 constexpr int kColThreads = kWave * kColsPerBlock;
-// staged elements per thread: a column block of the longest line
-constexpr int kStageIt = (kMaxCoarseLine * kColsPerBlock + kColThreads - 1) / kColThreads;
+// staged elements per thread: a segment of the block's columns
+constexpr int kStageIt = (kLineSeg * kColsPerBlock + kColThreads - 1) / kColThreads;
 
-// Columns i0 .. i0 + kColsPerBlock - 1 of a state, one column per wave, result
-// into dst (mode 0), or combined with the parareal correction (mode 1:
-// U_next = F + (g - G_old), G_old = g, increment) or the initial guess (mode 2:
-// U_next = G_old = g). The columns are staged into one LDS line buffer each
-// through row segments. Every global load of the block (state, factors and the
-// correction operands) is issued before the first LDS store. Returns the
-// thread's largest |change| bit pattern (mode 1).
+// Columns i0 .. i0 + kColsPerBlock - 1 of a state (S segments of 64 K rows),
+// one column per wave, result into dst (mode 0), or combined with the parareal
+// correction (mode 1: U_next = F + (g - G_old), G_old = g, increment) or the
+// initial guess (mode 2: U_next = G_old = g). The columns are staged into one
+// LDS line buffer each through row segments. Every global load of a segment
+// (state, factors and the correction operands) is issued before its first LDS
+// store. Columns of several segments park the y of all but the last segment in
+// dst (which may alias src). Returns the thread's largest |change| bit pattern
+// (mode 1).
 __device__ __forceinline__ unsigned long long solve_cols(
-    const gdouble* src, int nx, int ny, int i0, int K, const gdouble* Rb, const gdouble* Gb,
+    const gdouble* src, int nx, int ny, int i0, int K, int S, const gdouble* Rb, const gdouble* Gb,
     int mode, gdouble* dst, const gdouble* F, gdouble* Gold, gdouble* Unext, double* T,
     int tid) {
   const int lane = tid & (kWave - 1), wv = tid / kWave;
-  const int total = ny * kColsPerBlock;
   const int col = i0 + wv;
   const int colc = col < nx ? col : nx - 1;  // clamped for the factor loads
-  double st[kStageIt], gq[kKMax], rq[kKMax];
+  const int SL = kWave * K;
+  const gdouble* Rl = Rb + (long)colc * SL * S;
+  const gdouble* Gl = Gb + (long)colc * SL * S;
+  double* buf = T + wv * kLineBuf;
+  double st[kStageIt], gq[kKMax], rq[kKMax], v[kKMax];
   double fv[kStageIt], gv[kStageIt], uv[kStageIt];
-#pragma unroll
-  for (int u = 0; u < kStageIt; u++) {
-    const int q = tid + u * kColThreads;
-    const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
-    const int i = i0 + c;
-    const bool ok = q < total && i < nx;
-    const double x = src[ok ? (long)j * nx + i : 0];
-    st[u] = ok ? x : 0.0;
-  }
-  load_line_factors(gq, rq, K, Rb + (long)colc * kWave * K, Gb + (long)colc * kWave * K, lane);
-  if (mode == 1) {
+  // rows [p0, p0 + ns) of the block's columns: thread entry u is row p0 + j,
+  // column i0 + c with q = tid + u * kColThreads = j * kColsPerBlock + c
+  auto stage_load = [&](const gdouble* a, int p0, int ns) {
 #pragma unroll
     for (int u = 0; u < kStageIt; u++) {
       const int q = tid + u * kColThreads;
       const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
       const int i = i0 + c;
-      const bool ok = q < total && i < nx;
-      const long idx = ok ? (long)j * nx + i : 0;
+      const bool ok = q < ns * kColsPerBlock && i < nx;
+      const double x = a[ok ? (long)(p0 + j) * nx + i : 0];
+      st[u] = ok ? x : 0.0;
+    }
+  };
+  auto corr_load = [&](int p0, int ns) {
+    if (mode != 1) return;
+#pragma unroll
+    for (int u = 0; u < kStageIt; u++) {
+      const int q = tid + u * kColThreads;
+      const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+      const int i = i0 + c;
+      const bool ok = q < ns * kColsPerBlock && i < nx;
+      const long idx = ok ? (long)(p0 + j) * nx + i : 0;
       fv[u] = F[idx];
       gv[u] = Gold[idx];
       uv[u] = Unext[idx];
     }
-  }
+  };
+  auto stage_store = [&](int ns) {
 #pragma unroll
-  for (int u = 0; u < kStageIt; u++) {
-    const int q = tid + u * kColThreads;
-    const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
-    if (q < total) T[c * kLineBuf + lds_pad(j)] = st[u];
-  }
-  __syncthreads();
-  if (col < nx) {  // wave-uniform
-    double* buf = T + wv * kLineBuf;
-    double v[kKMax];
+    for (int u = 0; u < kStageIt; u++) {
+      const int q = tid + u * kColThreads;
+      const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+      if (q < ns * kColsPerBlock) T[c * kLineBuf + lds_pad(j)] = st[u];
+    }
+  };
+  auto lanes_in = [&](int ns) {
 #pragma unroll
     for (int t = 0; t < kKMax; t++) {
       const int p = lane * K + (t < K ? t : 0);
       const double x = buf[lds_pad(p)];
-      v[t] = (t < K && p < ny) ? x : 0.0;
+      v[t] = (t < K && p < ns) ? x : 0.0;
     }
-    line_solve_lanes(v, K, gq, rq, lane);
+  };
+  auto lanes_out = [&]() {
 #pragma unroll
     for (int t = 0; t < kKMax; t++)
       if (t < K) buf[lds_pad(lane * K + t)] = v[t];
-  }
-  __syncthreads();
-  unsigned long long mx = 0;
+  };
+  double yc = 0.0, ec = 0.0;
+  for (int sg = 0; sg < S; sg++) {
+    const int p0 = sg * SL, ns = min(ny - p0, SL);
+    stage_load(src, p0, ns);
+    load_line_factors(gq, rq, K, Rl + (long)sg * SL, Gl + (long)sg * SL, lane);
+    if (sg + 1 == S) corr_load(p0, ns);  // the last segment is the first to finish
+    if (sg > 0) __syncthreads();  // the previous segment's LDS reads are done
+    stage_store(ns);
+    __syncthreads();
+    if (col < nx) {  // wave-uniform
+      lanes_in(ns);
+      seg_forward(v, K, gq, yc, ec, lane);
+      if (sg + 1 < S) lanes_out();
+    }
+    if (sg + 1 < S) {
+      __syncthreads();
 #pragma unroll
-  for (int u = 0; u < kStageIt; u++) {
-    const int q = tid + u * kColThreads;
-    const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
-    const int i = i0 + c;
-    if (q < total && i < nx) {
-      const long idx = (long)j * nx + i;
-      const double g = T[c * kLineBuf + lds_pad(j)];
-      if (mode == 0) {
-        dst[idx] = g;
-      } else if (mode == 2) {
-        Unext[idx] = g;
-        Gold[idx] = g;
-      } else {
-        const double un = fv[u] + (g - gv[u]);
-        const unsigned long long bits = abs_bits(un - uv[u]);
-        mx = bits > mx ? bits : mx;
-        Unext[idx] = un;
-        Gold[idx] = g;
+      for (int u = 0; u < kStageIt; u++) {
+        const int q = tid + u * kColThreads;
+        const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+        const int i = i0 + c;
+        if (q < ns * kColsPerBlock && i < nx) dst[(long)(p0 + j) * nx + i] = T[c * kLineBuf + lds_pad(j)];
+      }
+    }
+  }
+  unsigned long long mx = 0;
+  double xc = 0.0;
+  for (int sg = S - 1; sg >= 0; sg--) {
+    const int p0 = sg * SL, ns = min(ny - p0, SL);
+    if (sg + 1 < S) {
+      stage_load(dst, p0, ns);  // the parked y, read back by the threads that stored it
+      load_line_factors(gq, rq, K, Rl + (long)sg * SL, Gl + (long)sg * SL, lane);
+      corr_load(p0, ns);
+      __syncthreads();  // the previous segment's output phase is done with T
+      stage_store(ns);
+      __syncthreads();
+      if (col < nx) lanes_in(ns);
+    }
+    if (col < nx) {
+      seg_backward(v, K, gq, rq, xc, lane);
+      lanes_out();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kStageIt; u++) {
+      const int q = tid + u * kColThreads;
+      const int j = q / kColsPerBlock, c = q - j * kColsPerBlock;
+      const int i = i0 + c;
+      if (q < ns * kColsPerBlock && i < nx) {
+        const long idx = (long)(p0 + j) * nx + i;
+        const double g = T[c * kLineBuf + lds_pad(j)];
+        if (mode == 0) {
+          dst[idx] = g;
+        } else if (mode == 2) {
+          Unext[idx] = g;
+          Gold[idx] = g;
+        } else {
+          const double un = fv[u] + (g - gv[u]);
+          const unsigned long long bits = abs_bits(un - uv[u]);
+          mx = bits > mx ? bits : mx;
+          Unext[idx] = un;
+          Gold[idx] = g;
+        }
       }
     }
   }
@@ -1266,15 +1372,16 @@ __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_x(
     long gidx, long gstride) {
   __shared__ double T[kRowsPerBlock * kLineBuf];
   const DimInst& I = insts[0];
-  const int nx = I.nx, ny = I.ny, K = I.Kx;
+  const int nx = I.nx, ny = I.ny, K = I.Kx, Sg = I.Sx;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int row = xcd_block(blockIdx.x, gridDim.x) * kRowsPerBlock + wv;
   if (row >= ny) return;  // whole wave; no block-level barrier follows
   const long base = (long)row * nx;
+  const long fb = (long)row * kWave * K * Sg;
   const gdouble* S = gtab ? gp(I.fS) + base : nullptr;
   const double g0 = gtab ? gtab[gidx] : 0.0, g1 = gtab ? gtab[gstride + gidx] : 0.0;
-  solve_row(gp(src) + base, gp(dst) + base, gp(Rb) + (long)row * kWave * K,
-            gp(Gb) + (long)row * kWave * K, nx, K, T + wv * kLineBuf, lane, S, I.npts, g0, g1);
+  solve_row(gp(src) + base, gp(dst) + base, gp(Rb) + fb, gp(Gb) + fb, nx, K, Sg,
+            T + wv * kLineBuf, lane, S, I.npts, g0, g1);
 }
 
 // y-lines (columns) of one state, kColsPerBlock columns per block: dst = result.
@@ -1286,8 +1393,8 @@ __global__ __launch_bounds__(kColThreads) void k_coarse_y(const DimInst* __restr
   __shared__ double T[kColsPerBlock * kLineBuf];
   const DimInst& I = insts[0];
   const int i0 = xcd_block(blockIdx.x, gridDim.x) * kColsPerBlock;
-  solve_cols(gp(src), I.nx, I.ny, i0, I.Ky, gp(Rb), gp(Gb), 0, gp(dst), nullptr, nullptr, nullptr,
-             T, threadIdx.x);
+  solve_cols(gp(src), I.nx, I.ny, i0, I.Ky, I.Sy, gp(Rb), gp(Gb), 0, gp(dst), nullptr, nullptr,
+             nullptr, T, threadIdx.x);
 }
 
 // ----------------------------------------------- batched coarse sweeps ---
@@ -1302,7 +1409,7 @@ __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_xb(
   const DimInst& I = insts[it.inst];
   if (I.active && !I.active[I.idx]) return;
   if (n >= I.N || c >= I.cs) return;
-  const int nx = I.nx, ny = I.ny, K = I.Kx;
+  const int nx = I.nx, ny = I.ny, K = I.Kx, Sg = I.Sx;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int row = it.block * kRowsPerBlock + wv;
   if (row >= ny) return;  // whole wave
@@ -1312,8 +1419,9 @@ __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_xb(
   const gdouble* S = I.nforce ? gp(I.fS) + base : nullptr;
   const long nc = (long)I.N * I.cs, gi = (long)n * I.cs + c;
   const double g0 = I.nforce ? I.fgc[gi] : 0.0, g1 = I.nforce ? I.fgc[nc + gi] : 0.0;
-  solve_row(src + base, gp(I.tmp) + base, gp(I.cxRb) + (long)row * kWave * K,
-            gp(I.cxGb) + (long)row * kWave * K, nx, K, T + wv * kLineBuf, lane, S, I.npts, g0, g1);
+  const long fb = (long)row * kWave * K * Sg;
+  solve_row(src + base, gp(I.tmp) + base, gp(I.cxRb) + fb, gp(I.cxGb) + fb, nx, K, Sg,
+            T + wv * kLineBuf, lane, S, I.npts, g0, g1);
 }
 
 // The increment of the correction (mode 1) goes to the instance's per-column-
@@ -1331,7 +1439,7 @@ __global__ __launch_bounds__(kColThreads) void k_coarse_yb(
   const int tid = threadIdx.x;
   const int md = (c + 1 == I.cs) ? mode : 0;
   unsigned long long mx = solve_cols(
-      gp(I.tmp), I.nx, I.ny, it.block * kColsPerBlock, I.Ky, gp(I.cyRb), gp(I.cyGb), md,
+      gp(I.tmp), I.nx, I.ny, it.block * kColsPerBlock, I.Ky, I.Sy, gp(I.cyRb), gp(I.cyGb), md,
       gp(I.tmp), gp(F_base) + I.off_slices + (long)n * I.npts,
       gp(G_base) + I.off_slices + (long)n * I.npts,
       gp(U_base) + I.off_states + (long)(n + 1) * I.npts, T, tid);
@@ -1370,17 +1478,21 @@ __global__ __launch_bounds__(256) void k_inc_reduce(const DimInst* __restrict__ 
   }
 }
 
-// Lane-blocked copy of line-major factors: dst[l][c][lane] = src[l][lane*K + c]
-// (0 past the line end). One thread per destination entry.
+// Lane-blocked copy of line-major factors: dst[l][s][c][lane] =
+// src[l][s*64*K + lane*K + c] (0 past the line end), S segments per line. One
+// thread per destination entry.
 __global__ void k_block_factors(const double* __restrict__ src, int n_lines, int n_pos, int K,
-                                double* __restrict__ dst) {
+                                int S, double* __restrict__ dst) {
   const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long per = (long)kWave * K;
+  const long seg = (long)kWave * K;
+  const long per = seg * S;
   if (t >= (long)n_lines * per) return;
   const long l = t / per;
-  const int r = (int)(t - l * per);
-  const int c = r / kWave, lane = r - c * kWave;
-  const int p = lane * K + c;
+  const long r = t - l * per;
+  const long sg = r / seg;
+  const int rs = (int)(r - sg * seg);
+  const int c = rs / kWave, lane = rs - c * kWave;
+  const long p = sg * seg + (long)lane * K + c;
   dst[t] = p < n_pos ? src[l * n_pos + p] : 0.0;
 }
 
@@ -1671,15 +1783,21 @@ hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int
 
 int positions_per_lane(int n) {
   int p = 1;
-  while (p * kWave < n) p <<= 1;
+  while (p * kWave < n && p * kWave < kLineSeg) p <<= 1;
   return p;
+}
+
+int line_segments(int n) {
+  const int seg = kWave * positions_per_lane(n);
+  return (n + seg - 1) / seg;
 }
 
 hipError_t launch_block_factors(const double* src, int n_lines, int n_pos, double* dst,
                                 hipStream_t s) {
-  const long total = (long)n_lines * kWave * positions_per_lane(n_pos);
+  const int K = positions_per_lane(n_pos), S = line_segments(n_pos);
+  const long total = (long)n_lines * kWave * K * S;
   hipLaunchKernelGGL(k_block_factors, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src,
-                     n_lines, n_pos, positions_per_lane(n_pos), dst);
+                     n_lines, n_pos, K, S, dst);
   return hipGetLastError();
 }
 
