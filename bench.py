@@ -486,8 +486,8 @@ def main():
                            "with correction and increment"},
         "roofline": {"bound": "hbm",
                      "kernel": ("dd2 substep (k_dd2_solve phases + k_dd2_tri0s + k_dd2_kup0)" if dd2 else
-                                "dd substep (k_dd_local + k_dd_runmaps + k_dd_runscan + "
-                                "k_dd_segcarries)" if w.split == "dd" else sweep_label(prob)),
+                                "dd substep (k_dd_local_run + k_dd_runscan)" if w.split == "dd"
+                                else sweep_label(prob)),
                      "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic["gbs"] if traffic else None,

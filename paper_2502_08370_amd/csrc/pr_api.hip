@@ -102,9 +102,10 @@ struct DArr {
 struct DDFactorSet {
   DBuf R, G, CHI, PHI, PSIE, CHIA, PHIA;
   DBuf PC0, PP0, PC1, PP1, FC, FP;  // deferred corrections (fine set only)
+  DBuf SA, SC, SD;                  // per segment, from its run's factors
   DDFactors view() const {
     return DDFactors{R.p, G.p, CHI.p, PHI.p, PSIE.p, CHIA.p, PHIA.p,
-                     PC0.p, PP0.p, PC1.p, PP1.p, FC.p, FP.p};
+                     PC0.p, PP0.p, PC1.p, PP1.p, FC.p, FP.p, SA.p, SC.p, SD.p};
   }
 };
 
@@ -133,13 +134,15 @@ struct Instance {
   DArr<DDRun> runs;
   DArr<int> comp_run_first, comp_run_count;
   DArr<int> seg_src0, seg_src1, fin_seg;  // pending-correction sources (deferred substeps)
+  DArr<int> seg_run;                      // the run of each segment
+  DArr<DDRunRec> run_recs;
   DBuf RP, RQ, RU, RV, RW, RY, RX;        // fine (interleaved) run maps and carries
   DBuf RP1, RQ1, RU1, RV1, RW1, RY1, RX1;  // single-state run maps and carries
   DBuf rho, W;
   DArr<DDSeg> segs;
   DArr<int> seg_colour, comp_lo, comp_hi, comp_colour, comp_first, comp_count;
   DDFactorSet ffine, fcoarse;
-  DBuf Yb, Za, Yin, Xin;      // fine (interleaved) carries
+  DBuf Yp, Xp, Yin, Xin;      // fine (interleaved): slice parts of the carries, final carries
   DBuf Yb1, Za1, Yin1, Xin1;  // single-state carries
   DDInst hdd{}, hdd1{};       // interleaved fine workspace / single state (tmp)
   DDInst* d_dd = nullptr;     // device copies [hdd, hdd1]
@@ -659,6 +662,27 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
     I.run_off.push_back((int)runs.size());
   }
   const int n_runs = (int)runs.size();
+  std::vector<int> srun(std::max(n_segs, 1), 0);  // the run of each segment
+  for (int r = 0; r < n_runs; r++)
+    for (int t = 0; t < runs[r].len; t++) srun[runs[r].seg0 + t] = r;
+  HIPOK(I.seg_run.upload(srun));
+  std::vector<DDRunRec> recs(std::max(n_runs, 1));
+  for (int r = 0; r < n_runs; r++) {
+    DDRunRec& q = recs[r];
+    q = DDRunRec{};
+    q.seg0 = runs[r].seg0;
+    q.len = runs[r].len;
+    for (int t = 0; t < kDDRun; t++) {
+      const int si = q.seg0 + std::min(t, q.len - 1);  // clamped past the run's end
+      q.lo[t] = segs[si].lo;
+      q.cnt[t] = t < q.len ? segs[si].len : 0;
+      q.src[0][t] = sfresh[si];
+      q.src[1][t] = src1[si];
+      q.srun[0][t] = sfresh[si] >= 0 ? srun[sfresh[si]] : 0;
+      q.srun[1][t] = src1[si] >= 0 ? srun[src1[si]] : 0;
+    }
+  }
+  HIPOK(I.run_recs.upload(recs));
   HIPOK(I.runs.upload(runs));
   HIPOK(I.comp_run_first.upload(crfirst));
   HIPOK(I.comp_run_count.upload(crcount));
@@ -675,7 +699,8 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
       HIPOK(b->alloc((size_t)K * n));
       HIPOK(launch_fill_zero(b->p, b->n, s));
     }
-    for (DBuf* b : {&fs->PSIE, &fs->CHIA, &fs->PHIA}) HIPOK(b->alloc(std::max(n_segs, 1)));
+    for (DBuf* b : {&fs->PSIE, &fs->CHIA, &fs->PHIA, &fs->SA, &fs->SC, &fs->SD})
+      HIPOK(b->alloc(std::max(n_segs, 1)));
   }
   for (DBuf* b : {&I.ffine.PC0, &I.ffine.PP0, &I.ffine.PC1, &I.ffine.PP1}) {
     HIPOK(b->alloc((size_t)K * n));
@@ -686,7 +711,8 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
   const int B = (N + L - 1) / L;
   HIPOK(I.Z.alloc((size_t)B * n * L));
   HIPOK(I.tmp.alloc(n));
-  for (DBuf* b : {&I.Yb, &I.Za, &I.Yin, &I.Xin}) HIPOK(b->alloc((size_t)B * std::max(n_segs, 1) * L));
+  for (DBuf* b : {&I.Yp, &I.Xp, &I.Yin, &I.Xin})
+    HIPOK(b->alloc((size_t)B * std::max(n_segs, 1) * L));
   for (DBuf* b : {&I.Yb1, &I.Za1, &I.Yin1, &I.Xin1}) HIPOK(b->alloc(std::max(n_segs, 1)));
   for (DBuf* b : {&I.RP, &I.RQ, &I.RU, &I.RV, &I.RW, &I.RY, &I.RX})
     HIPOK(b->alloc((size_t)B * std::max(n_runs, 1) * L));
@@ -695,15 +721,20 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
   DDInst& h = I.hdd;
   h.n = n; h.N = N; h.L = L; h.B = B; h.n_colors = K; h.n_segs = n_segs;
   h.slab = (long)n * L; h.Z = I.Z.p; h.segs = I.segs.p;
-  h.Yb = I.Yb.p; h.Za = I.Za.p; h.Yin = I.Yin.p; h.Xin = I.Xin.p;
+  h.Yb = h.Za = nullptr;
+  h.Yin = I.Yin.p; h.Xin = I.Xin.p;
+  h.Yp = I.Yp.p; h.Xp = I.Xp.p;
   h.n_runs = n_runs; h.runs = I.runs.p;
   h.seg_src0 = I.seg_src0.p; h.seg_src1 = I.seg_src1.p; h.fin_seg = I.fin_seg.p;
+  h.seg_run = I.seg_run.p; h.run_recs = I.run_recs.p;
   h.RP = I.RP.p; h.RQ = I.RQ.p; h.RU = I.RU.p; h.RV = I.RV.p; h.RW = I.RW.p;
   h.RY = I.RY.p; h.RX = I.RX.p;
   DDInst& h1 = I.hdd1;
   h1 = h;
   h1.N = 1; h1.L = 1; h1.B = 1; h1.slab = n; h1.Z = I.tmp.p;
   h1.Yb = I.Yb1.p; h1.Za = I.Za1.p; h1.Yin = I.Yin1.p; h1.Xin = I.Xin1.p;
+  h1.Yp = h1.Xp = nullptr;
+  h1.seg_run = nullptr;
   h1.RP = I.RP1.p; h1.RQ = I.RQ1.p; h1.RU = I.RU1.p; h1.RV = I.RV1.p; h1.RW = I.RW1.p;
   h1.RY = I.RY1.p; h1.RX = I.RX1.p;
   HIPOK(hipMalloc(reinterpret_cast<void**>(&I.d_dd), 2 * sizeof(DDInst)));
@@ -734,6 +765,7 @@ pr_status factorize_dd_instance(Instance& I, const double* coef_x, hipStream_t s
                               tau / (h * h), fs.R.p, fs.G.p, s));
     HIPOK(launch_dd_segfactors(I.segs.p, I.seg_colour.p, n_segs, n, fs.R.p, fs.G.p,
                                fs.CHI.p, fs.PHI.p, fs.PSIE.p, fs.CHIA.p, fs.PHIA.p, s));
+    HIPOK(launch_dd_runfactors(I.d_dd, I.hdd, fs.view(), fs.SA.p, fs.SC.p, fs.SD.p, s));
   }
   DDFactorSet& ff = I.ffine;
   HIPOK(launch_dd_pending(I.d_dd, I.hdd, ff.view(), ff.PC0.p, ff.PP0.p, ff.PC1.p, ff.PP1.p,
@@ -758,7 +790,7 @@ pr_status dd_fie_step(pr_problem_s* P, Instance& I, bool coarse, int which, int 
     const int cb = I.comp_off[k], cc = I.comp_off[k + 1] - cb;
     const int rb = I.run_off[k], rc = I.run_off[k + 1] - rb;
     PhaseTimer pt(P, which ? PH_COARSE_X : PH_FINE, s);
-    HIPOK(launch_dd_local(dI, h, f, k, sb, sc, defer, step > 0, s));
+    HIPOK(launch_dd_local(dI, h, f, k, sb, sc, rb, rc, step > 0, s));
     HIPOK(launch_dd_carries(dI, h, f, rb, rc, I.comp_run_first.p + cb, I.comp_run_count.p + cb, cc,
                             s));
     if (!defer) HIPOK(launch_dd_correct(dI, h, f, k, sb, sc, s));

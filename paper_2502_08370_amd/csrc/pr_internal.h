@@ -150,6 +150,10 @@ struct DDFactors {
   // the correction it carries after the last substep (FC, FP: [node]).
   const double* PC0; const double* PP0; const double* PC1; const double* PP1;
   const double* FC; const double* FP;
+  // Per segment t of its run (slice-independent parts of the carries, see
+  // DDInst): SA = product of PSIE over the run's segments before t; the X after
+  // segment t is SC RX + SD RY + (its slice part).
+  const double* SA; const double* SC; const double* SD;
 };
 
 // The carries are resolved over runs of kDDRun consecutive segments of one
@@ -163,14 +167,31 @@ struct DDRun {
   int seg0, len;  // first segment (index into segs), segment count (<= kDDRun)
 };
 
+// Everything the slice-interleaved segment solves of one run look up, in one
+// record (one level of loads before the values): per segment t of the run its
+// node range and the pending-correction source (first step, later steps; -1:
+// none) with that source's run.
+struct DDRunRec {
+  int seg0, len;
+  int lo[kDDRun], cnt[kDDRun];
+  int src[2][kDDRun], srun[2][kDDRun];
+};
+
 struct DDInst {
   int n, N, L, B;       // nodes, slices, lanes per slice block, slice blocks
   int n_colors, n_segs;  // colours, segments of all colours
   long slab;            // doubles per slice block of Z: n*L
   double* Z;            // [B][n][L] (fine) or the state itself (L = 1)
   const DDSeg* segs;    // [n_segs], colour-major
-  // per (segment, slice): [B][n_segs][L]
+  // per (segment, slice): [B][n_segs][L]; Yb, Za single state (L = 1) only,
+  // Yin, Xin of the slice-interleaved workspace only after its last substep
   double* Yb; double* Za; double* Yin; double* Xin;
+  // Slice-interleaved workspace: the carries of segment t of run r are formed
+  // where they are used, Yin = SA_t RY_r + Yp_t and Xin = SC_t RX_r + SD_t RY_r
+  // + Xp_t, from the run's carries and the slice parts Yp, Xp ([B][n_segs][L])
+  // that the segment solves leave behind.
+  double* Yp; double* Xp;
+  const int* seg_run;   // [n_segs]: the run that holds the segment
   int n_runs;           // runs of all colours
   const DDRun* runs;    // [n_runs], colour-major, runs of a component contiguous
   // per (run, slice): [B][n_runs][L]. Run maps: Y_last = P Y_before + Q,
@@ -184,24 +205,36 @@ struct DDInst {
   // colour covering it); per node: the segment whose correction it carries
   // after the last substep (fin_seg).
   const int* seg_src0; const int* seg_src1; const int* fin_seg;
+  const DDRunRec* run_recs;  // [n_runs]
 };
 
-// Phase 1. defer: apply the pending correction of the previous substeps on
-// load (stale_ok: the previous step's corrections exist) and leave this one
-// pending; otherwise the input carries no correction.
+// Phase 1. Single state (L = 1): segments [seg_begin, seg_begin + seg_count)
+// with zero carries, the input carrying no correction. Slice-interleaved
+// workspace (L >= 8): one workgroup per run [run_begin, run_begin + run_count)
+// of the colour, which also chains the run's segments (the slice parts Yp, Xp
+// and the run maps of phase 2); the pending correction of the previous
+// substeps is applied on load (stale_ok: the previous step's corrections
+// exist) and this one is left pending.
 hipError_t launch_dd_local(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
-                           int seg_begin, int seg_count, bool defer, bool stale_ok, hipStream_t s);
+                           int seg_begin, int seg_count, int run_begin, int run_count,
+                           bool stale_ok, hipStream_t s);
 // Interleaved Z with the pending corrections of the last substeps -> natural
 // F[slice][node].
 hipError_t launch_dd_from_interleaved(const DDInst* d, const DDInst& h, const DDFactors& f,
                                       double* F, hipStream_t s);
 // Runs [run_begin, run_begin + run_count) of one colour; comp_run_first /
-// comp_run_count (device, n_comps entries) list each component's runs.
+// comp_run_count (device, n_comps entries) list each component's runs. The
+// slice-interleaved workspace only needs the scan over runs (its run maps come
+// from launch_dd_local).
 hipError_t launch_dd_carries(const DDInst* d, const DDInst& h, const DDFactors& f, int run_begin,
                              int run_count, const int* comp_run_first, const int* comp_run_count,
                              int n_comps, hipStream_t s);
+// Phase 3 of the single state (L = 1).
 hipError_t launch_dd_correct(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
                              int seg_begin, int seg_count, hipStream_t s);
+// SA, SC, SD of every run's segments (written through the given pointers).
+hipError_t launch_dd_runfactors(const DDInst* d, const DDInst& h, const DDFactors& f, double* SA,
+                                double* SC, double* SD, hipStream_t s);
 // Set-up: component LU (one thread per component) and segment factors.
 hipError_t launch_dd_faces(const double* rho, const double* a, int n, int n_colors, double* w,
                            hipStream_t s);

@@ -159,98 +159,184 @@ __global__ void k_dd_segfactors(const DDSeg* __restrict__ segs, const int* __res
 }
 
 // ------------------------------------------------------------- phase 1 ---
-// Segment solves with zero carries: forward elimination (tilde y) and back
-// substitution (tilde z) of each segment, in place; records tilde y at the
-// segment's last node (Yb) and tilde z at its first node (Za). With DEFER the
+// Slice-interleaved workspace, one workgroup per (run, slice block) with
+// kDDRun * L lanes. Every wave solves G segments of the run with zero carries:
+// forward elimination (tilde y) and back substitution (tilde z) in place. The
 // loaded values first receive the pending correction chi Yin + phi Xin of the
 // segment's source (see DDInst), and the segment's own correction is left
-// pending in turn.
-template <int L, bool DEFER>
-__global__ __launch_bounds__(kWave) void k_dd_local(const DDInst* __restrict__ insts, DDFactors f,
-                                                    int colour, int seg_begin, int seg_count,
-                                                    int stale_ok) {
-  constexpr int G = kWave / L;
+// pending in turn. Then one lane per slice chains the run's segments (tilde y
+// at each segment's last node and tilde z at its first node are staged in
+// LDS): Y before segment t = A_t RY + B_t (A_t = SA_t, the product of PSIE
+// before t), X after segment t = C_t RX + D_t RY + E_t with
+//   X after t-1 = PHIA_t (X after t) + CHIA_t (Y before t) + tilde z_first,t,
+// which leaves B_t, E_t in Yp, Xp and the run's maps (Y after the run =
+// RP RY + RQ, X at its first node = RU RX + RV RY + RW) for the scan over the
+// component's runs. C_t and D_t are the slice-independent SC_t, SD_t.
+template <int L>
+__global__ __launch_bounds__(kDDRun* L) void k_dd_local_run(const DDInst* __restrict__ insts,
+                                                            DDFactors f, int colour,
+                                                            int run_begin, int stale_ok) {
+  constexpr int G = kWave / L;  // segments per wave
   constexpr int M = kDDSeg;
+  constexpr int NW = kDDRun / G;  // waves per workgroup
   constexpr int NQ = (G * M + kWave - 1) / kWave;
-  constexpr int NS = DEFER ? G : 1;
-  __shared__ double sE[G][M + 1], sR[G][M + 1], sG[G][M + 1];
-  __shared__ double sC[NS][M + 1], sP[NS][M + 1];
+  static_assert(kDDRun % G == 0, "a run is a whole number of waves");
+  __shared__ double sE[NW][G][M + 1], sR[NW][G][M + 1], sG[NW][G][M + 1];
+  __shared__ double sC[NW][G][M + 1], sP[NW][G][M + 1];
+  __shared__ double sYb[kDDRun][L], sZa[kDDRun][L];
+  __shared__ double sF[4][kDDRun];  // the run's PSIE, CHIA, PHIA, SA
   const DDInst& I = insts[0];
-  const int lane = threadIdx.x, gsub = lane / L, sl = lane - gsub * L;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int gsub = lane / L, sl = lane - gsub * L;
   const int b = blockIdx.y;
-  const int s0 = blockIdx.x * G;
+  const int ri = run_begin + blockIdx.x;
+  const DDRunRec* rec = I.run_recs + ri;
+  const int rlen = rec->len, seg0 = rec->seg0;  // workgroup-uniform
+  const int t0 = wv * G;        // the wave's first segment in the run
+  const int tr = t0 + gsub;     // the lane's segment in the run
+  const bool active = tr < rlen;
+  // the lane's segment, its source and the source's run, from the run record
+  const int slo = rec->lo[tr], scnt = rec->cnt[tr];
+  const int src = rec->src[stale_ok][tr], sr = rec->srun[stale_ok][tr];
   const long cb = (long)colour * I.n;
-  // the lane's segment values first (the longest-latency loads)
-  const int sidx = s0 + gsub;
-  const bool active = sidx < seg_count;
-  const int sg_i = seg_begin + (active ? sidx : seg_count - 1);
-  const DDSeg sg = I.segs[sg_i];
-  gdouble* zb = gp(I.Z) + b * I.slab + (long)sg.lo * L + sl;
+  // the lane's segment values (the longest-latency loads)
+  gdouble* zb = gp(I.Z) + b * I.slab + (long)slo * L + sl;
   double v[M];
 #pragma unroll
   for (int t = 0; t < M; t++) {
-    const double x = zb[(long)(t < sg.len ? t : 0) * L];
-    v[t] = t < sg.len ? x : 0.0;
+    const double x = zb[(long)(t < scnt ? t : 0) * L];
+    v[t] = t < scnt ? x : 0.0;
+  }
+  // carries of the source segment, from its run's carries and its slice parts
+  // (read before this workgroup overwrites the slice parts of its own run: a
+  // segment's source in its own colour is the segment itself)
+  const int sc = src >= 0 ? src : 0;
+  const long si = ((long)b * I.n_segs + sc) * L + sl;
+  const long sri = ((long)b * I.n_runs + sr) * L + sl;
+  const double yp = gp(I.Yp)[si], xp = gp(I.Xp)[si];
+  const double ry = gp(I.RY)[sri], rx = gp(I.RX)[sri];
+  const double fa = gp(f.SA)[sc], fc = gp(f.SC)[sc], fd = gp(f.SD)[sc];
+  if (threadIdx.x < 4 * kDDRun) {  // the run's factors for the chaining below
+    const int k = threadIdx.x / kDDRun, t = threadIdx.x - k * kDDRun;
+    const int s = seg0 + (t < rlen ? t : 0);
+    const gdouble* src_f = gp(k == 0 ? f.PSIE : (k == 1 ? f.CHIA : (k == 2 ? f.PHIA : f.SA)));
+    sF[k][t] = src_f[s];
   }
   // factors of the wave's segments; padded positions act as identity and
   // carry no pending correction
   const gdouble* R = gp(f.R) + cb;
   const gdouble* Gf = gp(f.G) + cb;
-  const gdouble* PC = DEFER ? gp(stale_ok ? f.PC1 : f.PC0) + cb : nullptr;
-  const gdouble* PP = DEFER ? gp(stale_ok ? f.PP1 : f.PP0) + cb : nullptr;
+  const gdouble* PC = gp(stale_ok ? f.PC1 : f.PC0) + cb;
+  const gdouble* PP = gp(stale_ok ? f.PP1 : f.PP0) + cb;
 #pragma unroll
   for (int qq = 0; qq < NQ; qq++) {
     const int q = lane + qq * kWave;
     if (q < G * M) {
       const int g = q / M, t = q - g * M;
-      const int gidx = s0 + g;
-      const DDSeg gs = I.segs[seg_begin + min(gidx, seg_count - 1)];
-      const bool ok = gidx < seg_count && t < gs.len;
-      const long node = gs.lo + (ok ? t : 0);
+      const int tg = t0 + g;
+      const int glo = rec->lo[tg], gcnt = rec->cnt[tg];  // cnt = 0 past the run's end
+      const bool ok = t < gcnt;
+      const long node = glo + (ok ? t : 0);
       // e = g of the previous node (same cache lines as g)
       const double e = Gf[node > 0 ? node - 1 : 0], r = R[node], gg = Gf[node];
-      sE[g][t] = ok ? (node > 0 ? e : 0.0) : 1.0;
-      sR[g][t] = ok ? r : 0.0;
-      sG[g][t] = ok ? gg : 0.0;
-      if constexpr (DEFER) {
-        const double c = PC[node], p = PP[node];
-        sC[g][t] = ok ? c : 0.0;
-        sP[g][t] = ok ? p : 0.0;
-      }
+      const double c = PC[node], p = PP[node];
+      sE[wv][g][t] = ok ? (node > 0 ? e : 0.0) : 1.0;
+      sR[wv][g][t] = ok ? r : 0.0;
+      sG[wv][g][t] = ok ? gg : 0.0;
+      sC[wv][g][t] = ok ? c : 0.0;
+      sP[wv][g][t] = ok ? p : 0.0;
     }
   }
-  double ys = 0.0, xs = 0.0;
-  if constexpr (DEFER) {
-    const int src = (stale_ok ? I.seg_src1 : I.seg_src0)[sg_i];
-    const long si = ((long)b * I.n_segs + (src >= 0 ? src : 0)) * L + sl;
-    const double yv = gp(I.Yin)[si], xv = gp(I.Xin)[si];
-    ys = src >= 0 ? yv : 0.0;
-    xs = src >= 0 ? xv : 0.0;
-  }
-  __syncthreads();
-  if constexpr (DEFER) {
+  const double ys = src >= 0 ? fma(fa, ry, yp) : 0.0;
+  const double xs = src >= 0 ? fma(fc, rx, fma(fd, ry, xp)) : 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the wave's factor staging
 #pragma unroll
-    for (int t = 0; t < M; t++) v[t] = fma(sP[gsub][t], xs, fma(sC[gsub][t], ys, v[t]));
-  }
+  for (int t = 0; t < M; t++) v[t] = fma(sP[wv][gsub][t], xs, fma(sC[wv][gsub][t], ys, v[t]));
   double y = 0.0;
 #pragma unroll
   for (int t = 0; t < M; t++) {
-    y = fma(sE[gsub][t], y, v[t]);
+    y = fma(sE[wv][gsub][t], y, v[t]);
     v[t] = y;
   }
   double z = 0.0;
 #pragma unroll
   for (int t = M - 1; t >= 0; t--) {
-    z = fma(sG[gsub][t], z, sR[gsub][t] * v[t]);
+    z = fma(sG[wv][gsub][t], z, sR[wv][gsub][t] * v[t]);
     v[t] = z;
   }
   if (active) {  // streaming stores: each value is read once, by a later substep
 #pragma unroll
     for (int t = 0; t < M; t++)
-      if (t < sg.len) __builtin_nontemporal_store(v[t], &zb[(long)t * L]);
-    const long bi = ((long)b * I.n_segs + sg_i) * L + sl;
-    gp(I.Yb)[bi] = y;
-    gp(I.Za)[bi] = v[0];
+      if (t < scnt) __builtin_nontemporal_store(v[t], &zb[(long)t * L]);
+  }
+  sYb[tr][sl] = y;
+  sZa[tr][sl] = v[0];
+  __syncthreads();
+  if (threadIdx.x < L) {  // one lane per slice; the run's factors are uniform
+    const int l = threadIdx.x;
+    double A = 1.0, Bq = 0.0;
+    const long base = (long)b * I.n_segs * L + l;
+    for (int t = 0; t < rlen; t++) {  // B_t replaces tilde y in LDS
+      const double yb = sYb[t][l];
+      sYb[t][l] = Bq;
+      gp(I.Yp)[base + (long)(seg0 + t) * L] = Bq;
+      Bq = fma(sF[0][t], Bq, yb);
+      A = sF[0][t] * A;
+    }
+    double C = 1.0, D = 0.0, E = 0.0;
+    for (int t = rlen - 1; t >= 0; t--) {
+      const double pa = sF[2][t], ca = sF[1][t];
+      gp(I.Xp)[base + (long)(seg0 + t) * L] = E;
+      E = fma(pa, E, fma(ca, sYb[t][l], sZa[t][l]));
+      D = fma(pa, D, ca * sF[3][t]);
+      C = pa * C;
+    }
+    const long ridx = ((long)b * I.n_runs + ri) * L + l;
+    gp(I.RP)[ridx] = A;
+    gp(I.RQ)[ridx] = Bq;
+    gp(I.RU)[ridx] = C;
+    gp(I.RV)[ridx] = D;
+    gp(I.RW)[ridx] = E;
+  }
+}
+
+// Carries of every segment (and slice) after the last substep, from its run's
+// carries and its slice parts, for the final transpose: one thread per entry.
+__global__ void k_dd_final_carries(const DDInst* __restrict__ insts, DDFactors f) {
+  const DDInst& I = insts[0];
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long per = (long)I.n_segs * I.L;
+  if (t >= (long)I.B * per) return;
+  const int b = (int)(t / per);
+  const long r = t - b * per;
+  const int s = (int)(r / I.L), l = (int)(r - (long)s * I.L);
+  const long ri = ((long)b * I.n_runs + I.seg_run[s]) * I.L + l;
+  const double ry = gp(I.RY)[ri], rx = gp(I.RX)[ri];
+  gp(I.Yin)[t] = fma(gp(f.SA)[s], ry, gp(I.Yp)[t]);
+  gp(I.Xin)[t] = fma(gp(f.SC)[s], rx, fma(gp(f.SD)[s], ry, gp(I.Xp)[t]));
+}
+
+// SA, SC, SD of every run's segments (one thread per run): the same products
+// as k_dd_local_run forms, in the same order.
+__global__ void k_dd_runfactors(const DDInst* __restrict__ insts, DDFactors f,
+                                double* __restrict__ SA, double* __restrict__ SC,
+                                double* __restrict__ SD) {
+  const DDInst& I = insts[0];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= I.n_runs) return;
+  const DDRun rn = I.runs[r];
+  double A = 1.0;
+  for (int t = 0; t < rn.len; t++) {
+    SA[rn.seg0 + t] = A;
+    A = f.PSIE[rn.seg0 + t] * A;
+  }
+  double C = 1.0, D = 0.0;
+  for (int t = rn.len - 1; t >= 0; t--) {
+    const int s = rn.seg0 + t;
+    SC[s] = C;
+    SD[s] = D;
+    D = fma(f.PHIA[s], D, f.CHIA[s] * SA[s]);
+    C = f.PHIA[s] * C;
   }
 }
 
@@ -283,8 +369,8 @@ __global__ void k_dd_pending(const DDInst* __restrict__ insts, DDFactors f,
 }
 
 // Final transpose of the deferred fine substeps: F[slice][node] = Z[b][node][l]
-// + chi Yin + phi Xin of the node's last segment; one block of 4 waves per
-// (64-node tile, slice block).
+// + chi Yin + phi Xin of the node's last segment (the carries formed by
+// k_dd_final_carries); one block of 4 waves per (64-node tile, slice block).
 __global__ __launch_bounds__(4 * kWave) void k_dd_from_interleaved(
     const DDInst* __restrict__ insts, DDFactors f, double* __restrict__ F) {
   __shared__ double tile[64][65];
@@ -328,8 +414,11 @@ __global__ __launch_bounds__(4 * kWave) void k_dd_from_interleaved(
 // ------------------------------------------------------------- phase 2 ---
 // Carry resolution per (component, slice): Y_s = Yb_s + psi_s Y_{s-1} over the
 // component's segments, then X_s = Za_s + chi_s Y_{s-1} + phi_s X_{s+1}
-// backwards; stores Yin_s = Y_{s-1} and Xin_s = X_{s+1}. Three launches over
-// runs of kDDRun segments (see pr_internal.h); lanes are (run, slice).
+// backwards; stores Yin_s = Y_{s-1} and Xin_s = X_{s+1}. For the single state
+// three launches over runs of kDDRun segments (see pr_internal.h; lanes are
+// runs): run maps, the scan over each component's runs, and the carries of
+// every segment from its run's. The slice-interleaved workspace forms its run
+// maps in k_dd_local_run and needs only the scan (lanes are slices).
 
 // Loads the carry inputs of a run's segments (identity maps past its end).
 template <int L>
@@ -528,51 +617,8 @@ __global__ __launch_bounds__(kWave) void k_dd_segcarries(const DDInst* __restric
 }
 
 // ------------------------------------------------------------- phase 3 ---
-// x = z + chi Yin + phi Xin over each segment; chi and phi of the wave's
-// segments are staged in LDS, and every value load is issued before the first
-// store.
-template <int L>
-__global__ __launch_bounds__(kWave) void k_dd_correct(const DDInst* __restrict__ insts,
-                                                      DDFactors f, int colour, int seg_begin,
-                                                      int seg_count) {
-  constexpr int G = kWave / L;
-  constexpr int M = kDDSeg;
-  constexpr int NQ = (G * M + kWave - 1) / kWave;
-  __shared__ double sC[G][M + 1], sP[G][M + 1];
-  const DDInst& I = insts[0];
-  const int lane = threadIdx.x, gsub = lane / L, sl = lane - gsub * L;
-  const int b = blockIdx.y;
-  const int s0 = blockIdx.x * G;
-  const long cb = (long)colour * I.n;
-#pragma unroll
-  for (int qq = 0; qq < NQ; qq++) {
-    const int q = lane + qq * kWave;
-    if (q < G * M) {
-      const int g = q / M, t = q - g * M;
-      const int sidx = s0 + g;
-      const DDSeg sg = I.segs[seg_begin + min(sidx, seg_count - 1)];
-      const long node = cb + sg.lo + (t < sg.len ? t : 0);
-      sC[g][t] = gp(f.CHI)[node];
-      sP[g][t] = gp(f.PHI)[node];
-    }
-  }
-  const int sidx = s0 + gsub;
-  const bool active = sidx < seg_count;
-  const int sg_i = seg_begin + (active ? sidx : seg_count - 1);
-  const DDSeg sg = I.segs[sg_i];
-  const long bi = ((long)b * I.n_segs + sg_i) * L + sl;
-  const double yin = gp(I.Yin)[bi], xin = gp(I.Xin)[bi];
-  gdouble* zb = gp(I.Z) + b * I.slab + (long)sg.lo * L + sl;
-  double v[M];
-#pragma unroll
-  for (int t = 0; t < M; t++) v[t] = zb[(long)(t < sg.len ? t : 0) * L];
-  __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int t = 0; t < M; t++)
-      if (t < sg.len) zb[(long)t * L] = fma(sP[gsub][t], xin, fma(sC[gsub][t], yin, v[t]));
-  }
-}
+// (single state, below; the slice-interleaved workspace defers the correction
+// to the next load of each node)
 
 // Single state (L = 1): kDDSeg lanes per segment, lane = node. The zero-carry
 // segment solve is one forward and one backward affine scan across those lanes.
@@ -694,40 +740,40 @@ hipError_t launch_dd_segfactors(const DDSeg* segs, const int* seg_colour, int n_
   return hipGetLastError();
 }
 
-template <int L, bool DEFER>
-static hipError_t dd_local_t(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
-                             int seg_begin, int seg_count, bool stale_ok, hipStream_t s) {
-  constexpr int G = kWave / L;
-  dim3 grid((seg_count + G - 1) / G, h.B);
-  hipLaunchKernelGGL((k_dd_local<L, DEFER>), grid, dim3(kWave), 0, s, d, f, colour, seg_begin,
-                     seg_count, (int)stale_ok);
+template <int L>
+static hipError_t dd_local_run_t(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
+                                 int run_begin, int run_count, bool stale_ok, hipStream_t s) {
+  dim3 grid(run_count, h.B);
+  hipLaunchKernelGGL((k_dd_local_run<L>), grid, dim3(kDDRun * L), 0, s, d, f, colour, run_begin,
+                     (int)stale_ok);
   return hipGetLastError();
 }
 
-template <int L>
-static hipError_t dd_local_l(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
-                             int seg_begin, int seg_count, bool defer, bool stale_ok,
-                             hipStream_t s) {
-  return defer ? dd_local_t<L, true>(d, h, f, colour, seg_begin, seg_count, stale_ok, s)
-               : dd_local_t<L, false>(d, h, f, colour, seg_begin, seg_count, stale_ok, s);
-}
-
 hipError_t launch_dd_local(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
-                           int seg_begin, int seg_count, bool defer, bool stale_ok,
-                           hipStream_t s) {
-  if (seg_count <= 0) return hipSuccess;
+                           int seg_begin, int seg_count, int run_begin, int run_count,
+                           bool stale_ok, hipStream_t s) {
+  if (h.L == 1) {
+    if (seg_count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dd_local1, dim3((seg_count + 4 * kSegsPerWave - 1) / (4 * kSegsPerWave)),
+                       dim3(4 * kWave), 0, s, d, f, colour, seg_begin, seg_count);
+    return hipGetLastError();
+  }
+  if (run_count <= 0) return hipSuccess;
   switch (h.L) {
-    case 1:
-      if (defer) return hipErrorInvalidValue;  // single states are corrected in place
-      hipLaunchKernelGGL(k_dd_local1, dim3((seg_count + 4 * kSegsPerWave - 1) / (4 * kSegsPerWave)),
-                         dim3(4 * kWave), 0, s, d, f, colour, seg_begin, seg_count);
-      return hipGetLastError();
-    case 8: return dd_local_l<8>(d, h, f, colour, seg_begin, seg_count, defer, stale_ok, s);
-    case 16: return dd_local_l<16>(d, h, f, colour, seg_begin, seg_count, defer, stale_ok, s);
-    case 32: return dd_local_l<32>(d, h, f, colour, seg_begin, seg_count, defer, stale_ok, s);
-    case 64: return dd_local_l<64>(d, h, f, colour, seg_begin, seg_count, defer, stale_ok, s);
+    case 8: return dd_local_run_t<8>(d, h, f, colour, run_begin, run_count, stale_ok, s);
+    case 16: return dd_local_run_t<16>(d, h, f, colour, run_begin, run_count, stale_ok, s);
+    case 32: return dd_local_run_t<32>(d, h, f, colour, run_begin, run_count, stale_ok, s);
+    case 64: return dd_local_run_t<64>(d, h, f, colour, run_begin, run_count, stale_ok, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_dd_runfactors(const DDInst* d, const DDInst& h, const DDFactors& f, double* SA,
+                                double* SC, double* SD, hipStream_t s) {
+  if (h.n_runs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dd_runfactors, dim3((h.n_runs + 127) / 128), dim3(128), 0, s, d, f, SA, SC,
+                     SD);
+  return hipGetLastError();
 }
 
 hipError_t launch_dd_pending(const DDInst* d, const DDInst& h, const DDFactors& f, double* PC0,
@@ -741,21 +787,12 @@ hipError_t launch_dd_pending(const DDInst* d, const DDInst& h, const DDFactors& 
 
 hipError_t launch_dd_from_interleaved(const DDInst* d, const DDInst& h, const DDFactors& f,
                                       double* F, hipStream_t s) {
+  const long total = (long)h.B * h.n_segs * h.L;
+  if (total > 0)
+    hipLaunchKernelGGL(k_dd_final_carries, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       d, f);
   hipLaunchKernelGGL(k_dd_from_interleaved, dim3((h.n + 63) / 64, h.B), dim3(4 * kWave), 0, s, d,
                      f, F);
-  return hipGetLastError();
-}
-
-template <int L>
-static hipError_t dd_carries_t(const DDInst* d, const DDInst& h, const DDFactors& f,
-                               int run_begin, int run_count, const int* comp_run_first,
-                               const int* comp_run_count, int n_comps, hipStream_t s) {
-  constexpr int G = kWave / L;
-  const dim3 grid((run_count + G - 1) / G, h.B);
-  hipLaunchKernelGGL((k_dd_runmaps<L>), grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
-  hipLaunchKernelGGL(k_dd_runscan, dim3(n_comps, h.B * h.L), dim3(kWave), 0, s, d, comp_run_first,
-                     comp_run_count);
-  hipLaunchKernelGGL((k_dd_segcarries<L>), grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
   return hipGetLastError();
 }
 
@@ -763,46 +800,26 @@ hipError_t launch_dd_carries(const DDInst* d, const DDInst& h, const DDFactors& 
                              int run_count, const int* comp_run_first, const int* comp_run_count,
                              int n_comps, hipStream_t s) {
   if (n_comps <= 0 || run_count <= 0) return hipSuccess;
-  switch (h.L) {
-    case 1: return dd_carries_t<1>(d, h, f, run_begin, run_count, comp_run_first, comp_run_count,
-                                   n_comps, s);
-    case 8: return dd_carries_t<8>(d, h, f, run_begin, run_count, comp_run_first, comp_run_count,
-                                   n_comps, s);
-    case 16: return dd_carries_t<16>(d, h, f, run_begin, run_count, comp_run_first,
-                                     comp_run_count, n_comps, s);
-    case 32: return dd_carries_t<32>(d, h, f, run_begin, run_count, comp_run_first,
-                                     comp_run_count, n_comps, s);
-    case 64: return dd_carries_t<64>(d, h, f, run_begin, run_count, comp_run_first,
-                                     comp_run_count, n_comps, s);
-    default: return hipErrorInvalidValue;
+  if (h.L == 1) {
+    const dim3 grid((run_count + kWave - 1) / kWave, 1);
+    hipLaunchKernelGGL((k_dd_runmaps<1>), grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
+    hipLaunchKernelGGL(k_dd_runscan, dim3(n_comps, 1), dim3(kWave), 0, s, d, comp_run_first,
+                       comp_run_count);
+    hipLaunchKernelGGL((k_dd_segcarries<1>), grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
+    return hipGetLastError();
   }
-}
-
-template <int L>
-static hipError_t dd_correct_t(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
-                               int seg_begin, int seg_count, hipStream_t s) {
-  constexpr int G = kWave / L;
-  dim3 grid((seg_count + G - 1) / G, h.B);
-  hipLaunchKernelGGL((k_dd_correct<L>), grid, dim3(kWave), 0, s, d, f, colour, seg_begin,
-                     seg_count);
+  hipLaunchKernelGGL(k_dd_runscan, dim3(n_comps, h.B * h.L), dim3(kWave), 0, s, d, comp_run_first,
+                     comp_run_count);
   return hipGetLastError();
 }
 
 hipError_t launch_dd_correct(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
                              int seg_begin, int seg_count, hipStream_t s) {
   if (seg_count <= 0) return hipSuccess;
-  switch (h.L) {
-    case 1:
-      hipLaunchKernelGGL(k_dd_correct1,
-                         dim3((seg_count + 4 * kSegsPerWave - 1) / (4 * kSegsPerWave)),
-                         dim3(4 * kWave), 0, s, d, f, colour, seg_begin, seg_count);
-      return hipGetLastError();
-    case 8: return dd_correct_t<8>(d, h, f, colour, seg_begin, seg_count, s);
-    case 16: return dd_correct_t<16>(d, h, f, colour, seg_begin, seg_count, s);
-    case 32: return dd_correct_t<32>(d, h, f, colour, seg_begin, seg_count, s);
-    case 64: return dd_correct_t<64>(d, h, f, colour, seg_begin, seg_count, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (h.L != 1) return hipErrorInvalidValue;  // the interleaved workspace defers it
+  hipLaunchKernelGGL(k_dd_correct1, dim3((seg_count + 4 * kSegsPerWave - 1) / (4 * kSegsPerWave)),
+                     dim3(4 * kWave), 0, s, d, f, colour, seg_begin, seg_count);
+  return hipGetLastError();
 }
 
 int update_blocks(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 2048); }
