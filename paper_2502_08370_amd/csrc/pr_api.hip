@@ -211,6 +211,7 @@ struct pr_problem_s {
     int ft = 0;                // instances with a source term (the x sweep adds it)
     int M = 32;                // chunk length of the group's sweeps
     bool grouped = false;      // workgroups of grouped_lines() lines sharing the carry loads
+    bool long_lines = false;   // a member has lines of more than lds_chunk_lines(M) chunks
     std::vector<int> members;  // instances of the group
     WorkItem* d_work[2] = {nullptr, nullptr};
     int n_work[2] = {0, 0};
@@ -1330,7 +1331,7 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
           PhaseTimer pt(P, PH_FINE, s);
           HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir] + off, cnt, g.L, g.M, dir,
                                   dir == 1 || t > 0, t, s, g.dr ? (dir == 0 ? 1 : -1) : 0,
-                                  dir == 0 && g.ft, P->twisted, g.grouped));
+                                  dir == 0 && g.ft, P->twisted, g.grouped, g.long_lines));
         }
       }
     }
@@ -1509,6 +1510,10 @@ pr_status build_schedules(pr_problem_s* P) {
       g.M = dr ? kDRChunk : P->M;
       g.grouped = L == 64 && !dr && P->twisted && P->grouped && (g.M == 20 || g.M == 24);
       g.members = members;
+      for (int i : members) {
+        const DimInst& hi = P->inst[i]->h;
+        if (std::max(hi.Px, hi.Py) > lds_chunk_lines(g.M)) g.long_lines = true;
+      }
       for (int dir = 0; dir < 2; dir++) {
         std::vector<WorkItem> all;
         g.pass_off[dir].assign(1, 0);
@@ -2383,9 +2388,9 @@ pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lamb
     for (int t = 0; t < S; t++) {
       PhaseTimer pt(p, PH_FINE, s);
       HIPOK(launch_fine_sweep(Dd + 1 + 2 * t, g.d_work[0], g.n_work[0], g.L, g.M, 0, t > 0, t, s, 0,
-                              g.ft != 0, p->twisted, g.grouped));
+                              g.ft != 0, p->twisted, g.grouped, g.long_lines));
       HIPOK(launch_fine_sweep(Dd + 2 + 2 * t, g.d_work[1], g.n_work[1], g.L, g.M, 1, 1, t, s, 0,
-                              false, p->twisted, g.grouped));
+                              false, p->twisted, g.grouped, g.long_lines));
     }
     // 6. reverse steps of every slice from lambda_{n+1}: y solve, face gradients
     //    with V_t, x solve, face gradients with W_t
@@ -2401,13 +2406,13 @@ pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lamb
       {
         PhaseTimer pt(p, PH_FINE, s);
         HIPOK(launch_fine_sweep(Da, g.d_work[1], g.n_work[1], g.L, g.M, 1, t < S - 1, t, s, 0, false,
-                                p->twisted, g.grouped));
+                                p->twisted, g.grouped, g.long_lines));
       }
       HIPOK(launch_grad_faces(1, Da, Dd + 2 * S + 2 + 2 * t, h, cy, I.adjGay.p, s));
       {
         PhaseTimer pt(p, PH_FINE, s);
         HIPOK(launch_fine_sweep(Da, g.d_work[0], g.n_work[0], g.L, g.M, 0, 1, t, s, 0, false,
-                                p->twisted, g.grouped));
+                                p->twisted, g.grouped, g.long_lines));
       }
       HIPOK(launch_grad_faces(0, Da, Dd + 2 * S + 1 + 2 * t, h, cx, I.adjGax.p, s));
     }

@@ -441,11 +441,16 @@ hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, doub
 // twisted: two-wave workgroups, the bottom chunks [twx / twy, P) of every line
 // eliminated from the line end with the UL factors (see k_fine_sweep).
 // grouped (twisted, L = 64, FIE only): workgroups of grouped_lines() lines whose
-// work items count line groups of that many lines (k_fine_sweep_g).
+// work items count line groups of that many lines (k_fine_sweep_g); long_lines:
+// some instance of the launch has lines of more than lds_chunk_lines(M) chunks
+// (the grouped form then keeps every chunk outer value in the carry slots).
 hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
                              int M, int dir, int has_prev, int step, hipStream_t s, int sgn = 0,
-                             bool forced = false, bool twisted = false, bool grouped = false);
+                             bool forced = false, bool twisted = false, bool grouped = false,
+                             bool long_lines = false);
 int grouped_lines();
+// Chunks of M positions whose outer values the fine sweeps keep in LDS.
+int lds_chunk_lines(int M);
 // S = dt A_y U on the slice-interleaved workspace (U with the pending y-sweep
 // correction when has_prev) of one instance, slice blocks [b_lo, b_hi), before
 // fine step `step` (nothing once the instance has finished its steps).

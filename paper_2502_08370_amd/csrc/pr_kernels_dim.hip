@@ -750,7 +750,7 @@ __global__ __launch_bounds__(TW ? 2 * kWave : kWave) void k_fine_sweep(
 // reaches every barrier.
 constexpr int kGL = 4;  // lines per workgroup of the grouped sweep
 
-template <int M, int DIR, bool HP, bool FT>
+template <int M, int DIR, bool HP, bool FT, bool ZG>
 __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
     const DimInst* __restrict__ insts, const WorkItem* __restrict__ work, int step) {
   constexpr int L = kWave;
@@ -797,9 +797,9 @@ __global__ __launch_bounds__(2 * kGL * kWave) void k_fine_sweep_g(
   const int line = line0 + q;
   const bool active = line < n_lines;  // wave-uniform
   const int lc = active ? line : n_lines - 1;  // clamped for in-bounds loads
-  // chunk outer values in LDS, or (longer lines) in the carry slots they
-  // resolve into (see k_fine_sweep)
-  const bool zlds = P <= kMaxChunks;  // workgroup-uniform
+  // chunk outer values in LDS, or (ZG: launches with lines longer than the
+  // LDS store holds) in the carry slots they resolve into (see k_fine_sweep)
+  constexpr bool zlds = !ZG;
   gdouble* zslot = sigOut + (long)lc * L + lane;
   const long kstr = (long)n_lines * L;
   const gdouble* zrow_u = gp(I.Z) + w.b * I.slab + (long)lc * lstr;
@@ -1737,41 +1737,52 @@ static hipError_t launch_sweep_tw(const DimInst* d_insts, const WorkItem* d_work
   }
 }
 
-template <int M>
-static hipError_t launch_sweep_g(const DimInst* d_insts, const WorkItem* d_work, int n_work,
-                                 int dir, int has_prev, int step, hipStream_t s, bool forced) {
+template <int M, bool ZG>
+static hipError_t launch_sweep_gz(const DimInst* d_insts, const WorkItem* d_work, int n_work,
+                                  int dir, int has_prev, int step, hipStream_t s, bool forced) {
   const dim3 grid(n_work), block(2 * kGL * kWave);
   if (dir == 1) {
     if (has_prev)
-      hipLaunchKernelGGL((k_fine_sweep_g<M, 1, true, false>), grid, block, 0, s, d_insts, d_work, step);
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 1, true, false, ZG>), grid, block, 0, s, d_insts, d_work, step);
     else
-      hipLaunchKernelGGL((k_fine_sweep_g<M, 1, false, false>), grid, block, 0, s, d_insts, d_work, step);
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 1, false, false, ZG>), grid, block, 0, s, d_insts, d_work, step);
   } else if (forced) {
     if (has_prev)
-      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, true, true>), grid, block, 0, s, d_insts, d_work, step);
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, true, true, ZG>), grid, block, 0, s, d_insts, d_work, step);
     else
-      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, false, true>), grid, block, 0, s, d_insts, d_work, step);
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, false, true, ZG>), grid, block, 0, s, d_insts, d_work, step);
   } else {
     if (has_prev)
-      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, true, false>), grid, block, 0, s, d_insts, d_work, step);
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, true, false, ZG>), grid, block, 0, s, d_insts, d_work, step);
     else
-      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, false, false>), grid, block, 0, s, d_insts, d_work, step);
+      hipLaunchKernelGGL((k_fine_sweep_g<M, 0, false, false, ZG>), grid, block, 0, s, d_insts, d_work, step);
   }
   return hipGetLastError();
 }
+
+template <int M>
+static hipError_t launch_sweep_g(const DimInst* d_insts, const WorkItem* d_work, int n_work,
+                                 int dir, int has_prev, int step, hipStream_t s, bool forced,
+                                 bool long_lines) {
+  return long_lines
+             ? launch_sweep_gz<M, true>(d_insts, d_work, n_work, dir, has_prev, step, s, forced)
+             : launch_sweep_gz<M, false>(d_insts, d_work, n_work, dir, has_prev, step, s, forced);
+}
+
+int lds_chunk_lines(int M) { return (kLineSeg + M - 1) / M; }
 
 int grouped_lines() { return kGL; }
 
 hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int L,
                              int M, int dir, int has_prev, int step, hipStream_t s, int sgn,
-                             bool forced, bool twisted, bool grouped) {
+                             bool forced, bool twisted, bool grouped, bool long_lines) {
   if (forced && dir != 0) return hipErrorInvalidValue;
   if (grouped) {
     if (L != kWave || sgn != 0 || !twisted) return hipErrorInvalidValue;
     switch (M) {
-      case 20: return launch_sweep_g<20>(d_insts, d_work, n_work, dir, has_prev, step, s, forced);
-      case 24: return launch_sweep_g<24>(d_insts, d_work, n_work, dir, has_prev, step, s, forced);
-      case 32: return launch_sweep_g<32>(d_insts, d_work, n_work, dir, has_prev, step, s, forced);
+      case 20: return launch_sweep_g<20>(d_insts, d_work, n_work, dir, has_prev, step, s, forced, long_lines);
+      case 24: return launch_sweep_g<24>(d_insts, d_work, n_work, dir, has_prev, step, s, forced, long_lines);
+      case 32: return launch_sweep_g<32>(d_insts, d_work, n_work, dir, has_prev, step, s, forced, long_lines);
       default: return hipErrorInvalidValue;
     }
   }
