@@ -1407,6 +1407,12 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
       if (st != PR_OK) return st;
     }
   }
+  bool segx = false, segy = false;
+  for (auto& I : P->inst)
+    if (!I->dd) {
+      segx = segx || I->h.Sx > 1;
+      segy = segy || I->h.Sy > 1;
+    }
   for (int k = 0; k < P->Nmax; k++) {
     const int xb = P->xoff[k], xn = P->xoff[k + 1] - xb;
     const int yb = P->yoff[k], yn = P->yoff[k + 1] - yb;
@@ -1414,10 +1420,11 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
     for (int c = 0; c < P->csmax; c++) {
       {
         PhaseTimer pt(P, PH_COARSE_X, s);
-        HIPOK(launch_coarse_xb(P->d_inst, P->xitems.p + xb, xn, k, c, U, s));
+        HIPOK(launch_coarse_xb(P->d_inst, P->xitems.p + xb, xn, k, c, U, s, segx));
       }
       PhaseTimer pt(P, PH_COARSE_Y, s);
-      HIPOK(launch_coarse_yb(P->d_inst, P->yitems.p + yb, yn, k, c, F ? 1 : 2, F, Gold, U, s));
+      HIPOK(launch_coarse_yb(P->d_inst, P->yitems.p + yb, yn, k, c, F ? 1 : 2, F, Gold, U, s,
+                             segy));
     }
   }
   HIPOK(launch_inc_reduce(P->d_inst, n, inc, s));

@@ -482,12 +482,14 @@ constexpr int kCoarseColsPerBlock = 4;    // y lines per block of the coarse y k
 // initial guess) to U[n+1] / G_old[n] / F[n], the others write tmp.
 // The mode-1 increment of each instance goes to its partial maxima (incp,
 // zeroed by the caller before the sweep); launch_inc_reduce folds them into
-// inc_bits[instance] after the sweep's last launch.
+// inc_bits[instance] after the sweep's last launch. seg: some instance of the
+// launch has lines of more than one segment (the segmented solve, which holds
+// more registers, is then used for the whole launch).
 hipError_t launch_coarse_xb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
-                            int c, const double* U_base, hipStream_t s);
+                            int c, const double* U_base, hipStream_t s, bool seg);
 hipError_t launch_coarse_yb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
                             int c, int mode, const double* F_base, double* G_base, double* U_base,
-                            hipStream_t s);
+                            hipStream_t s, bool seg);
 hipError_t launch_inc_reduce(const DimInst* d_insts, int n_inst, unsigned long long* inc_bits,
                              hipStream_t s);
 // Parareal bookkeeping on the device: inc = 0 for active instances (start of

@@ -1140,10 +1140,12 @@ constexpr int kLineBuf = line_buf_len(kKMax);
 // One row (contiguous, n values, S segments of 64 K): src -> dst (may alias);
 // buf is the wave's LDS line buffer. With Sf != NULL the right-hand side also
 // receives g0 S_0 + g1 S_1 (S_m at the row, S_1 = S_0 + spts).
+template <bool SEG>
 __device__ __forceinline__ void solve_row(const gdouble* src, gdouble* dst, const gdouble* Rb,
-                                          const gdouble* Gb, int n, int K, int S, double* buf,
+                                          const gdouble* Gb, int n, int K, int S_, double* buf,
                                           int lane, const gdouble* Sf = nullptr, long spts = 0,
                                           double g0 = 0.0, double g1 = 0.0) {
+  const int S = SEG ? S_ : 1;  // one segment: a single pass (fewer live registers)
   const int SL = kWave * K;
   double v[kKMax], gq[kKMax], rq[kKMax];
   // v (position order) -> lane-blocked v, through the LDS buffer
@@ -1225,10 +1227,12 @@ constexpr int kStageIt = (kLineSeg * kColsPerBlock + kColThreads - 1) / kColThre
 // store. Columns of several segments park the y of all but the last segment in
 // dst (which may alias src). Returns the thread's largest |change| bit pattern
 // (mode 1).
+template <bool SEG>
 __device__ __forceinline__ unsigned long long solve_cols(
-    const gdouble* src, int nx, int ny, int i0, int K, int S, const gdouble* Rb, const gdouble* Gb,
+    const gdouble* src, int nx, int ny, int i0, int K, int S_, const gdouble* Rb, const gdouble* Gb,
     int mode, gdouble* dst, const gdouble* F, gdouble* Gold, gdouble* Unext, double* T,
     int tid) {
+  const int S = SEG ? S_ : 1;  // one segment: a single pass (fewer live registers)
   const int lane = tid & (kWave - 1), wv = tid / kWave;
   const int col = i0 + wv;
   const int colc = col < nx ? col : nx - 1;  // clamped for the factor loads
@@ -1366,6 +1370,7 @@ __device__ __forceinline__ int xcd_block(int bid, int nb) {
 
 // x-lines (rows) of one state, one wave per row; with gtab the source
 // sum_m gtab[m * gstride + gidx] S_m joins the right-hand side.
+template <bool SEG>
 __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_x(
     const DimInst* __restrict__ insts, const double* __restrict__ src, double* __restrict__ dst,
     const double* __restrict__ Rb, const double* __restrict__ Gb, const double* __restrict__ gtab,
@@ -1380,11 +1385,12 @@ __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_x(
   const long fb = (long)row * kWave * K * Sg;
   const gdouble* S = gtab ? gp(I.fS) + base : nullptr;
   const double g0 = gtab ? gtab[gidx] : 0.0, g1 = gtab ? gtab[gstride + gidx] : 0.0;
-  solve_row(gp(src) + base, gp(dst) + base, gp(Rb) + fb, gp(Gb) + fb, nx, K, Sg,
-            T + wv * kLineBuf, lane, S, I.npts, g0, g1);
+  solve_row<SEG>(gp(src) + base, gp(dst) + base, gp(Rb) + fb, gp(Gb) + fb, nx, K, Sg,
+                 T + wv * kLineBuf, lane, S, I.npts, g0, g1);
 }
 
 // y-lines (columns) of one state, kColsPerBlock columns per block: dst = result.
+template <bool SEG>
 __global__ __launch_bounds__(kColThreads) void k_coarse_y(const DimInst* __restrict__ insts,
                                                           const double* __restrict__ src,
                                                           double* __restrict__ dst,
@@ -1393,14 +1399,15 @@ __global__ __launch_bounds__(kColThreads) void k_coarse_y(const DimInst* __restr
   __shared__ double T[kColsPerBlock * kLineBuf];
   const DimInst& I = insts[0];
   const int i0 = xcd_block(blockIdx.x, gridDim.x) * kColsPerBlock;
-  solve_cols(gp(src), I.nx, I.ny, i0, I.Ky, I.Sy, gp(Rb), gp(Gb), 0, gp(dst), nullptr, nullptr,
-             nullptr, T, threadIdx.x);
+  solve_cols<SEG>(gp(src), I.nx, I.ny, i0, I.Ky, I.Sy, gp(Rb), gp(Gb), 0, gp(dst), nullptr,
+                  nullptr, nullptr, T, threadIdx.x);
 }
 
 // ----------------------------------------------- batched coarse sweeps ---
 // Same line solves, one launch per slice index n over the line blocks of every
 // instance that has that slice (items ordered on the host per XCD).
 
+template <bool SEG>
 __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_xb(
     const DimInst* __restrict__ insts, const LineItem* __restrict__ items, int n, int c,
     const double* __restrict__ U_base) {
@@ -1420,13 +1427,14 @@ __global__ __launch_bounds__(kWave* kRowsPerBlock) void k_coarse_xb(
   const long nc = (long)I.N * I.cs, gi = (long)n * I.cs + c;
   const double g0 = I.nforce ? I.fgc[gi] : 0.0, g1 = I.nforce ? I.fgc[nc + gi] : 0.0;
   const long fb = (long)row * kWave * K * Sg;
-  solve_row(src + base, gp(I.tmp) + base, gp(I.cxRb) + fb, gp(I.cxGb) + fb, nx, K, Sg,
-            T + wv * kLineBuf, lane, S, I.npts, g0, g1);
+  solve_row<SEG>(src + base, gp(I.tmp) + base, gp(I.cxRb) + fb, gp(I.cxGb) + fb, nx, K, Sg,
+                 T + wv * kLineBuf, lane, S, I.npts, g0, g1);
 }
 
 // The increment of the correction (mode 1) goes to the instance's per-column-
 // block partial maxima (plain read-modify-write: one block per entry per
 // launch, launches in stream order); k_inc_reduce folds them afterwards.
+template <bool SEG>
 __global__ __launch_bounds__(kColThreads) void k_coarse_yb(
     const DimInst* __restrict__ insts, const LineItem* __restrict__ items, int n, int c, int mode,
     const double* __restrict__ F_base, double* __restrict__ G_base, double* __restrict__ U_base) {
@@ -1438,7 +1446,7 @@ __global__ __launch_bounds__(kColThreads) void k_coarse_yb(
   if (n >= I.N || c >= I.cs) return;
   const int tid = threadIdx.x;
   const int md = (c + 1 == I.cs) ? mode : 0;
-  unsigned long long mx = solve_cols(
+  unsigned long long mx = solve_cols<SEG>(
       gp(I.tmp), I.nx, I.ny, it.block * kColsPerBlock, I.Ky, I.Sy, gp(I.cyRb), gp(I.cyGb), md,
       gp(I.tmp), gp(F_base) + I.off_slices + (long)n * I.npts,
       gp(G_base) + I.off_slices + (long)n * I.npts,
@@ -1814,17 +1822,25 @@ hipError_t launch_block_factors(const double* src, int n_lines, int n_pos, doubl
 
 hipError_t launch_coarse_x(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
                            bool fine, hipStream_t s, const double* gtab, long gidx, long gstride) {
-  hipLaunchKernelGGL(k_coarse_x, dim3((h.ny + kRowsPerBlock - 1) / kRowsPerBlock),
-                     dim3(kWave * kRowsPerBlock), 0, s, d_inst, src, dst, fine ? h.fxRb : h.cxRb,
-                     fine ? h.fxGb : h.cxGb, gtab, gidx, gstride);
+  const dim3 grid((h.ny + kRowsPerBlock - 1) / kRowsPerBlock), block(kWave * kRowsPerBlock);
+  if (h.Sx > 1)
+    hipLaunchKernelGGL(k_coarse_x<true>, grid, block, 0, s, d_inst, src, dst,
+                       fine ? h.fxRb : h.cxRb, fine ? h.fxGb : h.cxGb, gtab, gidx, gstride);
+  else
+    hipLaunchKernelGGL(k_coarse_x<false>, grid, block, 0, s, d_inst, src, dst,
+                       fine ? h.fxRb : h.cxRb, fine ? h.fxGb : h.cxGb, gtab, gidx, gstride);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_y(const DimInst* d_inst, const DimInst& h, const double* src, double* dst,
                            bool fine, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarse_y, dim3((h.nx + kColsPerBlock - 1) / kColsPerBlock),
-                     dim3(kColThreads), 0, s, d_inst, src, dst, fine ? h.fyRb : h.cyRb,
-                     fine ? h.fyGb : h.cyGb);
+  const dim3 grid((h.nx + kColsPerBlock - 1) / kColsPerBlock), block(kColThreads);
+  if (h.Sy > 1)
+    hipLaunchKernelGGL(k_coarse_y<true>, grid, block, 0, s, d_inst, src, dst,
+                       fine ? h.fyRb : h.cyRb, fine ? h.fyGb : h.cyGb);
+  else
+    hipLaunchKernelGGL(k_coarse_y<false>, grid, block, 0, s, d_inst, src, dst,
+                       fine ? h.fyRb : h.cyRb, fine ? h.fyGb : h.cyGb);
   return hipGetLastError();
 }
 
@@ -1858,19 +1874,27 @@ hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t s) 
 }
 
 hipError_t launch_coarse_xb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
-                            int c, const double* U_base, hipStream_t s) {
+                            int c, const double* U_base, hipStream_t s, bool seg) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coarse_xb, dim3(n_items), dim3(kWave * kRowsPerBlock), 0, s, d_insts,
-                     items, n, c, U_base);
+  if (seg)
+    hipLaunchKernelGGL(k_coarse_xb<true>, dim3(n_items), dim3(kWave * kRowsPerBlock), 0, s,
+                       d_insts, items, n, c, U_base);
+  else
+    hipLaunchKernelGGL(k_coarse_xb<false>, dim3(n_items), dim3(kWave * kRowsPerBlock), 0, s,
+                       d_insts, items, n, c, U_base);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_yb(const DimInst* d_insts, const LineItem* items, int n_items, int n,
                             int c, int mode, const double* F_base, double* G_base, double* U_base,
-                            hipStream_t s) {
+                            hipStream_t s, bool seg) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coarse_yb, dim3(n_items), dim3(kColThreads), 0, s, d_insts, items, n, c,
-                     mode, F_base, G_base, U_base);
+  if (seg)
+    hipLaunchKernelGGL(k_coarse_yb<true>, dim3(n_items), dim3(kColThreads), 0, s, d_insts, items,
+                       n, c, mode, F_base, G_base, U_base);
+  else
+    hipLaunchKernelGGL(k_coarse_yb<false>, dim3(n_items), dim3(kColThreads), 0, s, d_insts, items,
+                       n, c, mode, F_base, G_base, U_base);
   return hipGetLastError();
 }
 
