@@ -11,7 +11,9 @@ coarse sweep fused with the correction and the increment (pr_coarse_sweep).
 value = fine point-updates per second over the whole step, in Gpts/s.
 
 Also reported: the fine sweep kernel's roofline (algorithmic bytes per launch
-over its mean launch time from hipEvents on the work stream), the oracle timed
+over its mean launch time from hipEvents on the work stream, one event pair
+around each step's loop of sweeps, so the mean includes the gaps between
+launches), the oracle timed
 on a bounded sample on the host, and the parareal wall time to tolerance
 against the sequential fine solve on the same GPU.
 """
@@ -423,7 +425,9 @@ def main():
         step()
     torch.cuda.synchronize()
     prob.profile(2)
-    prob.profile(1)
+    # span mode: one event pair around each loop of fine sweeps and each coarse
+    # sweep (per-launch events would add their own queue time to the step)
+    prob.profile(3)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_host = time.perf_counter()
     e0.record()
@@ -470,7 +474,8 @@ def main():
         traffic = {"gbs": round(tb / (sweep_avg_ms * 1e-3) / 1e9, 1), "bytes_per_launch": tb,
                    "over_algorithmic": round(tb / bytes_per_sweep, 4)}
     fine_ms = (phases["fine_sweep"][0] + phases.get("fine_transpose", (0, 0))[0]) / args.steps
-    coarse_ms = (phases.get("coarse_x", (0, 0))[0] + phases.get("coarse_y", (0, 0))[0]) / args.steps
+    coarse_ms = (phases.get("coarse_sweep", (0, 0))[0] + phases.get("coarse_x", (0, 0))[0]
+                 + phases.get("coarse_y", (0, 0))[0]) / args.steps
 
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gpts/s", "n_gpus": 1,

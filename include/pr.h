@@ -286,11 +286,18 @@ pr_status pr_adjoint_parallel(pr_problem p, const double* u0, const double* lamb
 /* Phase timers. When enabled, the library records a pair of hipEvents on the
  * work stream around every launch and accumulates their elapsed times per
  * phase (no extra synchronisation is added while recording). Phases:
- *   0 fine sweeps (one FIE substep of every line of every slice)
+ *   0 fine sweeps (one FIE substep of every line of every slice; a domain-
+ *     decomposition colour substep counts as one)
  *   1 fine layout transposes (slice-interleaved workspace in/out)
  *   2 coarse x sweeps      3 coarse y sweeps (fused with the parareal update)
  *   4 other (copies, fills)
- * pr_profile_control(p, 1) enables, 0 disables, 2 clears the totals.
+ *   5 whole coarse sweeps (span mode only)
+ * pr_profile_control(p, 1) enables, 0 disables, 2 clears the totals, 3 enables
+ * span mode: one event pair around each loop of fine sweeps (phase 0, counting
+ * its launches) and each coarse sweep (phase 5, counting its slice steps)
+ * instead of one per launch. Each event record costs a few microseconds of
+ * queue time, so span mode is the one to use while timing whole iterations;
+ * its per-launch means include the gaps between launches.
  * pr_profile_read waits for the recorded events and returns the totals. */
 #define PR_PROFILE_PHASES 8
 typedef struct {

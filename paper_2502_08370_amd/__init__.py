@@ -290,7 +290,9 @@ class Problem:
         return dict(res, cached=False)
 
     def profile(self, mode):
-        """1: start recording phase timers, 0: stop, 2: clear."""
+        """1: start recording phase timers (one event pair per launch), 3: start them in
+        span mode (one pair per loop of fine sweeps and per coarse sweep), 0: stop,
+        2: clear."""
         B.check(B.lib().pr_profile_control(self._h, int(mode)))
 
     def profile_read(self):

@@ -48,7 +48,8 @@ class PrInstanceLayout(C.Structure):
 
 
 PROFILE_PHASES = 8
-PHASE_NAMES = ["fine_sweep", "fine_transpose", "coarse_x", "coarse_y", "other", "p5", "p6", "p7"]
+PHASE_NAMES = ["fine_sweep", "fine_transpose", "coarse_x", "coarse_y", "other", "coarse_sweep", "p6",
+               "p7"]
 
 
 class PrProfile(C.Structure):

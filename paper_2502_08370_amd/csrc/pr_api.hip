@@ -192,9 +192,12 @@ struct pr_problem_s {
   std::vector<std::unique_ptr<Instance>> inst;
   // phase timers (pr_profile_control / pr_profile_read)
   bool prof = false;
+  bool prof_span = false;  // span mode: one event pair around each loop of launches
+  int span_depth = 0;      // open spans (their launches record no events of their own)
   struct Rec {
     int phase;
     hipEvent_t a, b;
+    int n;  // launches the interval covers
   };
   std::vector<hipEvent_t> ev_free;
   std::vector<Rec> recs;
@@ -514,7 +517,8 @@ pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
   return fine_factors(I, s);
 }
 
-enum { PH_FINE = 0, PH_TRANSPOSE = 1, PH_COARSE_X = 2, PH_COARSE_Y = 3, PH_OTHER = 4 };
+enum { PH_FINE = 0, PH_TRANSPOSE = 1, PH_COARSE_X = 2, PH_COARSE_Y = 3, PH_OTHER = 4,
+       PH_COARSE = 5 };
 
 hipEvent_t take_event(pr_problem_s* P) {
   if (!P->ev_free.empty()) {
@@ -535,7 +539,7 @@ struct PhaseTimer {
   hipStream_t s;
   hipEvent_t a = nullptr;
   PhaseTimer(pr_problem_s* P_, int ph, hipStream_t s_) : P(P_), phase(ph), s(s_) {
-    if (!P->prof) return;
+    if (!P->prof || P->span_depth > 0) return;
     a = take_event(P);
     if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
   }
@@ -547,7 +551,38 @@ struct PhaseTimer {
       if (b) P->ev_free.push_back(b);
       return;
     }
-    P->recs.push_back({phase, a, b});
+    P->recs.push_back({phase, a, b, 1});
+  }
+};
+
+// Span-mode timer: one event pair around a loop of launches, which count
+// themselves with add(); the per-launch timers inside it record nothing. The
+// interval includes the gaps between the launches, so its mean per launch is an
+// upper bound of a launch's duration, at a cost of two events per loop instead
+// of two per launch.
+struct PhaseSpan {
+  pr_problem_s* P;
+  int phase;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  int n = 0;
+  PhaseSpan(pr_problem_s* P_, int ph, hipStream_t s_) : P(P_), phase(ph), s(s_) {
+    if (!P->prof || !P->prof_span) return;
+    a = take_event(P);
+    if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+    if (a) P->span_depth++;
+  }
+  void add(int k = 1) { n += k; }
+  ~PhaseSpan() {
+    if (!a) return;
+    P->span_depth--;
+    hipEvent_t b = take_event(P);
+    if (!b || hipEventRecord(b, s) != hipSuccess || n == 0) {
+      P->ev_free.push_back(a);
+      if (b) P->ev_free.push_back(b);
+      return;
+    }
+    P->recs.push_back({phase, a, b, n});
   }
 };
 
@@ -1316,22 +1351,27 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   // its steps before the next one starts, keeping its working set cached)
   int smax = 0;
   for (auto& I : P->inst) smax = std::max(smax, I->d.fine_steps);
-  for (int q = 0; q < P->n_passes; q++) {
-    for (int t = 0; t < smax; t++) {
-      for (auto& g : P->groups) {
-        if (g.dr && t == 0) {  // S = dt A_y U of the input; later steps' S come from the y sweep
-          PhaseTimer pt(P, PH_FINE, s);
-          for (int i : g.members)
-            HIPOK(launch_dr_stencil(P->d_inst + i, P->inst[i]->h, 0, t, q * P->pass_blocks,
-                                    (q + 1) * P->pass_blocks, s));
-        }
-        for (int dir = 0; dir < 2; dir++) {
-          const int off = g.pass_off[dir][q], cnt = g.pass_off[dir][q + 1] - off;
-          if (!cnt) continue;
-          PhaseTimer pt(P, PH_FINE, s);
-          HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir] + off, cnt, g.L, g.M, dir,
-                                  dir == 1 || t > 0, t, s, g.dr ? (dir == 0 ? 1 : -1) : 0,
-                                  dir == 0 && g.ft, P->twisted, g.grouped, g.long_lines));
+  {
+    PhaseSpan sp(P, PH_FINE, s);
+    for (int q = 0; q < P->n_passes; q++) {
+      for (int t = 0; t < smax; t++) {
+        for (auto& g : P->groups) {
+          if (g.dr && t == 0) {  // S = dt A_y U of the input; later steps' S come from the y sweep
+            PhaseTimer pt(P, PH_FINE, s);
+            for (int i : g.members)
+              HIPOK(launch_dr_stencil(P->d_inst + i, P->inst[i]->h, 0, t, q * P->pass_blocks,
+                                      (q + 1) * P->pass_blocks, s));
+            sp.add();
+          }
+          for (int dir = 0; dir < 2; dir++) {
+            const int off = g.pass_off[dir][q], cnt = g.pass_off[dir][q + 1] - off;
+            if (!cnt) continue;
+            PhaseTimer pt(P, PH_FINE, s);
+            HIPOK(launch_fine_sweep(P->d_inst, g.d_work[dir] + off, cnt, g.L, g.M, dir,
+                                    dir == 1 || t > 0, t, s, g.dr ? (dir == 0 ? 1 : -1) : 0,
+                                    dir == 0 && g.ft, P->twisted, g.grouped, g.long_lines));
+            sp.add();
+          }
         }
       }
     }
@@ -1339,13 +1379,16 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
     if (!I.dd || I.dd2 || skip(i)) continue;
+    PhaseSpan sp(P, PH_FINE, s);
     for (int t = 0; t < I.d.fine_steps; t++) {
       if (I.h.nforce) {
         PhaseTimer pt(P, PH_FINE, s);
         HIPOK(launch_force_interleaved(P->d_inst + i, I.h, t, s));
+        sp.add();
       }
       pr_status st = dd_fie_step(P, I, false, 0, t, s);
       if (st != PR_OK) return st;
+      sp.add(I.n_colors);  // one colour substep per colour
     }
   }
   for (int i = 0; i < n; i++) {
@@ -1398,6 +1441,7 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
   for (int i = 0; i < n; i++) {
     Instance& I = *P->inst[i];
     if (!I.dd || (host_active && !(*host_active)[i])) continue;
+    PhaseSpan sp(P, PH_COARSE, s);
     for (int k = 0; k < I.d.n_slices; k++) {
       const double* Un = U + I.off_states + (size_t)k * I.npts;
       double* Unext = U + I.off_states + (size_t)(k + 1) * I.npts;
@@ -1405,6 +1449,7 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
       const double* Fk = F ? F + I.off_slices + (size_t)k * I.npts : nullptr;
       pr_status st = coarse_apply_dd(P, i, k, Un, F ? 1 : 2, Fk, Gk, Unext, s);
       if (st != PR_OK) return st;
+      sp.add();  // one coarse step of one slice
     }
   }
   bool segx = false, segy = false;
@@ -1413,6 +1458,7 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
       segx = segx || I->h.Sx > 1;
       segy = segy || I->h.Sy > 1;
     }
+  PhaseSpan sp(P, PH_COARSE, s);
   for (int k = 0; k < P->Nmax; k++) {
     const int xb = P->xoff[k], xn = P->xoff[k + 1] - xb;
     const int yb = P->yoff[k], yn = P->yoff[k + 1] - yb;
@@ -1425,6 +1471,7 @@ pr_status coarse_sweep_impl(pr_problem_s* P, const double* F, double* Gold, doub
       PhaseTimer pt(P, PH_COARSE_Y, s);
       HIPOK(launch_coarse_yb(P->d_inst, P->yitems.p + yb, yn, k, c, F ? 1 : 2, F, Gold, U, s,
                              segy));
+      sp.add(2);
     }
   }
   HIPOK(launch_inc_reduce(P->d_inst, n, inc, s));
@@ -1729,8 +1776,9 @@ const char* pr_last_error(void) { return g_err; }
 pr_status pr_profile_control(pr_problem p, int mode) {
   return guarded([&]() -> pr_status {
     if (!p) return fail(PR_EINVAL, "NULL handle");
-    if (mode == 0 || mode == 1) {
-      p->prof = mode == 1;
+    if (mode == 0 || mode == 1 || mode == 3) {
+      p->prof = mode != 0;
+      p->prof_span = mode == 3;
     } else if (mode == 2) {
       pr_profile z{};
       p->acc = z;
@@ -1741,7 +1789,7 @@ pr_status pr_profile_control(pr_problem p, int mode) {
       }
       p->recs.clear();
     } else {
-      return fail(PR_EINVAL, "mode must be 0, 1 or 2");
+      return fail(PR_EINVAL, "mode must be 0, 1, 2 or 3");
     }
     return PR_OK;
   });
@@ -1755,7 +1803,7 @@ pr_status pr_profile_read(pr_problem p, pr_profile* out) {
       float ms = 0.f;
       HIPOK(hipEventElapsedTime(&ms, r.a, r.b));
       p->acc.ms[r.phase] += ms;
-      p->acc.count[r.phase] += 1;
+      p->acc.count[r.phase] += r.n;
       p->ev_free.push_back(r.a);
       p->ev_free.push_back(r.b);
     }

@@ -241,3 +241,31 @@ def test_invalid_arguments_rejected():
     d["n_slices"] = 0
     with pytest.raises(pr.PrError):
         pr.Problem([d])
+
+
+def test_profile_span_mode_counts():
+    """Span-mode phase timers: one event pair per loop, the launch counts of the
+    per-launch mode, and results unchanged by either mode."""
+    w = W.small_dim2(40, 33, n_slices=6, fine_steps=3, seed=9)
+    P = gpu_problem(w)
+    Uin = dev(slice_inputs(w, seed=2))
+    counts = {}
+    outs = []
+    for mode in (1, 3):
+        P.profile(2)
+        P.profile(mode)
+        F = P.new_slices()
+        P.fine_propagate(Uin, F)
+        U = P.new_states()
+        U[: w.nx * w.ny].copy_(dev(w.u0))
+        G = P.new_slices()
+        inc = torch.zeros(1, dtype=torch.float64, device="cuda")
+        P.coarse_sweep(F, G, U, inc)
+        torch.cuda.synchronize()
+        P.profile(0)
+        counts[mode] = {k: v[1] for k, v in P.profile_read().items()}
+        outs.append((F.clone(), U.clone()))
+    assert counts[1]["fine_sweep"] == counts[3]["fine_sweep"] == 2 * w.fine_steps
+    assert counts[1]["coarse_x"] == counts[1]["coarse_y"] == w.n_slices
+    assert counts[3]["coarse_sweep"] == 2 * w.n_slices and "coarse_x" not in counts[3]
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
