@@ -107,10 +107,13 @@ def test_douglas_rachford_long_lines():
     assert relerr(F.cpu().numpy().reshape(ref.shape), ref) <= TOL
 
 
-@pytest.mark.parametrize("parallel", [False, True])
-def test_adjoint_long_lines(parallel):
+@pytest.mark.parametrize("parallel,N", [(False, 3), (True, 3), (True, 64)])
+def test_adjoint_long_lines(parallel, N):
+    """Serial and parallel-in-time adjoints on 1100-point x lines; with 64 slices the
+    parallel adjoint's recomputed forward steps take the grouped sweeps' long-line
+    variant."""
     nx, ny = 1100, 21
-    w = W.small_dim2(nx, ny, n_slices=3, fine_steps=2, seed=4)
+    w = W.small_dim2(nx, ny, n_slices=N, fine_steps=2, seed=4)
     theta = w.theta
     P, O = gpu_problem(w), oracle_problem(w)
     lam = np.random.default_rng(4).standard_normal((ny, nx))
