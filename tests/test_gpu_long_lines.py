@@ -29,6 +29,9 @@ LONG_SHAPES = [
     (29, 2100, 3),
     (9, 2048, 64),
     (1025, 9, 5),
+    # degenerate: one long line and lines of one point
+    (3000, 1, 5),
+    (1, 2049, 64),
 ]
 
 
@@ -48,11 +51,16 @@ def test_fine_propagate_long_lines(twisted, grouped, chunk):
         assert relerr(F.cpu().numpy().reshape(ref.shape), ref) <= TOL, (nx, ny, N)
 
 
-@pytest.mark.parametrize("nx,ny,N,cs", [(1100, 40, 3, 2), (40, 2100, 2, 1), (1030, 1025, 2, 1)])
-def test_coarse_sweep_long_lines(nx, ny, N, cs):
+@pytest.mark.parametrize("nx,ny,N,cs,T", [(1100, 40, 3, 2, 0.05), (40, 2100, 2, 1, 0.05),
+                                           (1030, 1025, 2, 1, 0.05), (3000, 1, 2, 1, 1e-4),
+                                           (1, 3000, 2, 2, 1e-4)])
+def test_coarse_sweep_long_lines(nx, ny, N, cs, T):
     """Initial guess (mode 2) and correction with increment (mode 1) with the
-    coarse y solve of the last coarse step fused, on segmented rows and columns."""
-    w = W.small_dim2(nx, ny, n_slices=N, fine_steps=2, seed=nx + ny)
+    coarse y solve of the last coarse step fused, on segmented rows and columns.
+    The one-point-wide grids take a moderate step (tau / h^2 about 225): at
+    T = 0.05 the 3000-point lines' coarse step has tau / h^2 = 1.1e5, where two
+    exact eliminations of one line agree only to about 2e-12."""
+    w = W.small_dim2(nx, ny, n_slices=N, fine_steps=2, seed=nx + ny, T=T)
     w.coarse_steps = cs
     P, O = gpu_problem(w), oracle_problem(w)
     U0 = np.zeros((N + 1, ny, nx))
