@@ -420,18 +420,17 @@ __global__ __launch_bounds__(4 * kWave) void k_dd_from_interleaved(
 // every segment from its run's. The slice-interleaved workspace forms its run
 // maps in k_dd_local_run and needs only the scan (lanes are slices).
 
-// Loads the carry inputs of a run's segments (identity maps past its end).
-template <int L>
-__device__ __forceinline__ void load_run(const DDInst& I, const DDFactors& f, const DDRun& rn,
-                                         int b, int sl, double (&yb)[kDDRun],
-                                         double (&za)[kDDRun], double (&ps)[kDDRun],
-                                         double (&ca)[kDDRun], double (&pa)[kDDRun]) {
+// Loads the carry inputs of a run's segments (identity maps past its end); the
+// single state, one lane per run.
+__device__ __forceinline__ void load_run1(const DDInst& I, const DDFactors& f, const DDRun& rn,
+                                          double (&yb)[kDDRun], double (&za)[kDDRun],
+                                          double (&ps)[kDDRun], double (&ca)[kDDRun],
+                                          double (&pa)[kDDRun]) {
 #pragma unroll
   for (int t = 0; t < kDDRun; t++) {
     const bool ok = t < rn.len;
     const int sidx = rn.seg0 + (ok ? t : 0);
-    const long bi = ((long)b * I.n_segs + sidx) * L + sl;
-    const double y = gp(I.Yb)[bi], z = gp(I.Za)[bi];
+    const double y = gp(I.Yb)[sidx], z = gp(I.Za)[sidx];
     const double p = gp(f.PSIE)[sidx], c = gp(f.CHIA)[sidx], h = gp(f.PHIA)[sidx];
     yb[t] = ok ? y : 0.0;
     za[t] = ok ? z : 0.0;
@@ -441,20 +440,16 @@ __device__ __forceinline__ void load_run(const DDInst& I, const DDFactors& f, co
   }
 }
 
-// 2a: run maps.
-template <int L>
-__global__ __launch_bounds__(kWave) void k_dd_runmaps(const DDInst* __restrict__ insts,
-                                                      DDFactors f, int run_begin, int run_count) {
-  constexpr int G = kWave / L;
+// 2a: run maps (single state, one lane per run).
+__global__ __launch_bounds__(kWave) void k_dd_runmaps1(const DDInst* __restrict__ insts,
+                                                       DDFactors f, int run_begin, int run_count) {
   const DDInst& I = insts[0];
-  const int lane = threadIdx.x, g = lane / L, sl = lane - g * L;
-  const int b = blockIdx.y;
-  const int rix = blockIdx.x * G + g;
+  const int rix = blockIdx.x * kWave + threadIdx.x;
   const bool active = rix < run_count;
   const int ri = run_begin + (active ? rix : run_count - 1);
   const DDRun rn = I.runs[ri];
   double yb[kDDRun], za[kDDRun], ps[kDDRun], ca[kDDRun], pa[kDDRun];
-  load_run<L>(I, f, rn, b, sl, yb, za, ps, ca, pa);
+  load_run1(I, f, rn, yb, za, ps, ca, pa);
   // forward: Y before segment t = pp[t] Y_before + qq[t]
   double p = 1.0, q = 0.0, pp[kDDRun], qq[kDDRun];
 #pragma unroll
@@ -473,7 +468,7 @@ __global__ __launch_bounds__(kWave) void k_dd_runmaps(const DDInst* __restrict__
     u = pa[t] * u;
   }
   if (active) {
-    const long ridx = ((long)b * I.n_runs + ri) * L + sl;
+    const long ridx = ri;
     gp(I.RP)[ridx] = p;
     gp(I.RQ)[ridx] = q;
     gp(I.RU)[ridx] = u;
@@ -576,22 +571,18 @@ __global__ __launch_bounds__(kWave) void k_dd_runscan(const DDInst* __restrict__
   }
 }
 
-// 2c: carries of every segment from its run's carries.
-template <int L>
-__global__ __launch_bounds__(kWave) void k_dd_segcarries(const DDInst* __restrict__ insts,
-                                                         DDFactors f, int run_begin,
-                                                         int run_count) {
-  constexpr int G = kWave / L;
+// 2c: carries of every segment from its run's carries (single state).
+__global__ __launch_bounds__(kWave) void k_dd_segcarries1(const DDInst* __restrict__ insts,
+                                                          DDFactors f, int run_begin,
+                                                          int run_count) {
   const DDInst& I = insts[0];
-  const int lane = threadIdx.x, g = lane / L, sl = lane - g * L;
-  const int b = blockIdx.y;
-  const int rix = blockIdx.x * G + g;
+  const int rix = blockIdx.x * kWave + threadIdx.x;
   const bool active = rix < run_count;
   const int ri = run_begin + (active ? rix : run_count - 1);
   const DDRun rn = I.runs[ri];
   double yb[kDDRun], za[kDDRun], ps[kDDRun], ca[kDDRun], pa[kDDRun];
-  load_run<L>(I, f, rn, b, sl, yb, za, ps, ca, pa);
-  const long ridx = ((long)b * I.n_runs + ri) * L + sl;
+  load_run1(I, f, rn, yb, za, ps, ca, pa);
+  const long ridx = ri;
   double Y = gp(I.RY)[ridx];
   double X = gp(I.RX)[ridx];
   double yin[kDDRun], xin[kDDRun];
@@ -609,9 +600,8 @@ __global__ __launch_bounds__(kWave) void k_dd_segcarries(const DDInst* __restric
 #pragma unroll
     for (int t = 0; t < kDDRun; t++)
       if (t < rn.len) {
-        const long bi = ((long)b * I.n_segs + rn.seg0 + t) * L + sl;
-        gp(I.Yin)[bi] = yin[t];
-        gp(I.Xin)[bi] = xin[t];
+        gp(I.Yin)[rn.seg0 + t] = yin[t];
+        gp(I.Xin)[rn.seg0 + t] = xin[t];
       }
   }
 }
@@ -802,10 +792,10 @@ hipError_t launch_dd_carries(const DDInst* d, const DDInst& h, const DDFactors& 
   if (n_comps <= 0 || run_count <= 0) return hipSuccess;
   if (h.L == 1) {
     const dim3 grid((run_count + kWave - 1) / kWave, 1);
-    hipLaunchKernelGGL((k_dd_runmaps<1>), grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
+    hipLaunchKernelGGL(k_dd_runmaps1, grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
     hipLaunchKernelGGL(k_dd_runscan, dim3(n_comps, 1), dim3(kWave), 0, s, d, comp_run_first,
                        comp_run_count);
-    hipLaunchKernelGGL((k_dd_segcarries<1>), grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
+    hipLaunchKernelGGL(k_dd_segcarries1, grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_dd_runscan, dim3(n_comps, h.B * h.L), dim3(kWave), 0, s, d, comp_run_first,
