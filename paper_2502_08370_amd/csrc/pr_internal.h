@@ -183,13 +183,13 @@ struct DDInst {
   long slab;            // doubles per slice block of Z: n*L
   double* Z;            // [B][n][L] (fine) or the state itself (L = 1)
   const DDSeg* segs;    // [n_segs], colour-major
-  // per (segment, slice): [B][n_segs][L]; Yb, Za single state (L = 1) only,
-  // Yin, Xin of the slice-interleaved workspace only after its last substep
+  // per (segment, slice): [B][n_segs][L]; Yb, Za (zero-carry values at the
+  // segment's ends) single state (L = 1) only, Yin, Xin of the slice-interleaved
+  // workspace only after its last substep
   double* Yb; double* Za; double* Yin; double* Xin;
-  // Slice-interleaved workspace: the carries of segment t of run r are formed
-  // where they are used, Yin = SA_t RY_r + Yp_t and Xin = SC_t RX_r + SD_t RY_r
-  // + Xp_t, from the run's carries and the slice parts Yp, Xp ([B][n_segs][L])
-  // that the segment solves leave behind.
+  // The carries of segment t of run r are formed where they are used,
+  // Yin = SA_t RY_r + Yp_t and Xin = SC_t RX_r + SD_t RY_r + Xp_t, from the run's
+  // carries and the slice parts Yp, Xp ([B][n_segs][L]) that the run maps leave.
   double* Yp; double* Xp;
   const int* seg_run;   // [n_segs]: the run that holds the segment
   int n_runs;           // runs of all colours

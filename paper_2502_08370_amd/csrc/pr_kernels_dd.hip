@@ -414,11 +414,12 @@ __global__ __launch_bounds__(4 * kWave) void k_dd_from_interleaved(
 // ------------------------------------------------------------- phase 2 ---
 // Carry resolution per (component, slice): Y_s = Yb_s + psi_s Y_{s-1} over the
 // component's segments, then X_s = Za_s + chi_s Y_{s-1} + phi_s X_{s+1}
-// backwards; stores Yin_s = Y_{s-1} and Xin_s = X_{s+1}. For the single state
-// three launches over runs of kDDRun segments (see pr_internal.h; lanes are
-// runs): run maps, the scan over each component's runs, and the carries of
-// every segment from its run's. The slice-interleaved workspace forms its run
-// maps in k_dd_local_run and needs only the scan (lanes are slices).
+// backwards, over runs of kDDRun segments (see pr_internal.h): each run's maps
+// and the slice parts of its segments' carries, then the scan over each
+// component's runs; a segment's carries are formed where they are used. The
+// single state takes two launches (run maps with one lane per run, the scan);
+// the slice-interleaved workspace forms its run maps in k_dd_local_run and
+// needs only the scan (lanes are slices).
 
 // Loads the carry inputs of a run's segments (identity maps past its end); the
 // single state, one lane per run.
@@ -440,7 +441,8 @@ __device__ __forceinline__ void load_run1(const DDInst& I, const DDFactors& f, c
   }
 }
 
-// 2a: run maps (single state, one lane per run).
+// 2a: run maps (single state, one lane per run), and the slice parts of the
+// carries of the run's segments (Yp, Xp; see DDInst).
 __global__ __launch_bounds__(kWave) void k_dd_runmaps1(const DDInst* __restrict__ insts,
                                                        DDFactors f, int run_begin, int run_count) {
   const DDInst& I = insts[0];
@@ -459,15 +461,23 @@ __global__ __launch_bounds__(kWave) void k_dd_runmaps1(const DDInst* __restrict_
     q = fma(ps[t], q, yb[t]);
     p = ps[t] * p;
   }
-  // backward: X at segment t = u X_after + v Y_before + w
-  double u = 1.0, v = 0.0, w = 0.0;
+  // backward: X at segment t = u X_after + v Y_before + w; the w before segment
+  // t's update is the slice part of the X after it (see k_dd_local_run)
+  double u = 1.0, v = 0.0, w = 0.0, xp[kDDRun];
 #pragma unroll
   for (int t = kDDRun - 1; t >= 0; t--) {
+    xp[t] = w;
     w = fma(pa[t], w, fma(ca[t], qq[t], za[t]));
     v = fma(pa[t], v, ca[t] * pp[t]);
     u = pa[t] * u;
   }
   if (active) {
+#pragma unroll
+    for (int t = 0; t < kDDRun; t++)
+      if (t < rn.len) {
+        gp(I.Yp)[rn.seg0 + t] = qq[t];
+        gp(I.Xp)[rn.seg0 + t] = xp[t];
+      }
     const long ridx = ri;
     gp(I.RP)[ridx] = p;
     gp(I.RQ)[ridx] = q;
@@ -571,44 +581,9 @@ __global__ __launch_bounds__(kWave) void k_dd_runscan(const DDInst* __restrict__
   }
 }
 
-// 2c: carries of every segment from its run's carries (single state).
-__global__ __launch_bounds__(kWave) void k_dd_segcarries1(const DDInst* __restrict__ insts,
-                                                          DDFactors f, int run_begin,
-                                                          int run_count) {
-  const DDInst& I = insts[0];
-  const int rix = blockIdx.x * kWave + threadIdx.x;
-  const bool active = rix < run_count;
-  const int ri = run_begin + (active ? rix : run_count - 1);
-  const DDRun rn = I.runs[ri];
-  double yb[kDDRun], za[kDDRun], ps[kDDRun], ca[kDDRun], pa[kDDRun];
-  load_run1(I, f, rn, yb, za, ps, ca, pa);
-  const long ridx = ri;
-  double Y = gp(I.RY)[ridx];
-  double X = gp(I.RX)[ridx];
-  double yin[kDDRun], xin[kDDRun];
-#pragma unroll
-  for (int t = 0; t < kDDRun; t++) {
-    yin[t] = Y;
-    Y = fma(ps[t], Y, yb[t]);
-  }
-#pragma unroll
-  for (int t = kDDRun - 1; t >= 0; t--) {
-    xin[t] = X;
-    X = fma(pa[t], X, fma(ca[t], yin[t], za[t]));
-  }
-  if (active) {
-#pragma unroll
-    for (int t = 0; t < kDDRun; t++)
-      if (t < rn.len) {
-        gp(I.Yin)[rn.seg0 + t] = yin[t];
-        gp(I.Xin)[rn.seg0 + t] = xin[t];
-      }
-  }
-}
-
 // ------------------------------------------------------------- phase 3 ---
-// (single state, below; the slice-interleaved workspace defers the correction
-// to the next load of each node)
+// (single state, below: x = z + chi Yin + phi Xin in place; the slice-
+// interleaved workspace defers the correction to the next load of each node)
 
 // Single state (L = 1): kDDSeg lanes per segment, lane = node. The zero-carry
 // segment solve is one forward and one backward affine scan across those lanes.
@@ -660,7 +635,11 @@ __global__ __launch_bounds__(4 * kWave) void k_dd_correct1(const DDInst* __restr
   if (gl >= sg.len) return;
   const long node = sg.lo + gl;
   const long cb = (long)colour * I.n;
-  const double yin = gp(I.Yin)[si], xin = gp(I.Xin)[si];
+  // the segment's carries from its run's carries and its slice parts
+  const int r = I.seg_run[si];
+  const double ry = gp(I.RY)[r], rx = gp(I.RX)[r];
+  const double yin = fma(gp(f.SA)[si], ry, gp(I.Yp)[si]);
+  const double xin = fma(gp(f.SC)[si], rx, fma(gp(f.SD)[si], ry, gp(I.Xp)[si]));
   gp(I.Z)[node] =
       fma(gp(f.PHI)[cb + node], xin, fma(gp(f.CHI)[cb + node], yin, gp(I.Z)[node]));
 }
@@ -795,7 +774,6 @@ hipError_t launch_dd_carries(const DDInst* d, const DDInst& h, const DDFactors& 
     hipLaunchKernelGGL(k_dd_runmaps1, grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
     hipLaunchKernelGGL(k_dd_runscan, dim3(n_comps, 1), dim3(kWave), 0, s, d, comp_run_first,
                        comp_run_count);
-    hipLaunchKernelGGL(k_dd_segcarries1, grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_dd_runscan, dim3(n_comps, h.B * h.L), dim3(kWave), 0, s, d, comp_run_first,
