@@ -143,7 +143,7 @@ struct Instance {
   DArr<int> seg_colour, comp_lo, comp_hi, comp_colour, comp_first, comp_count;
   DDFactorSet ffine, fcoarse;
   DBuf Yp, Xp, Yin, Xin;      // fine (interleaved): slice parts of the carries, final carries
-  DBuf Yb1, Za1, Yp1, Xp1;    // single-state segment ends and carry parts
+  DBuf Yp1, Xp1;              // single state: slice parts of the carries
   DDInst hdd{}, hdd1{};       // interleaved fine workspace / single state (tmp)
   DDInst* d_dd = nullptr;     // device copies [hdd, hdd1]
   // domain decomposition (2D, vertical strips; dd is also set)
@@ -749,7 +749,7 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
   HIPOK(I.tmp.alloc(n));
   for (DBuf* b : {&I.Yp, &I.Xp, &I.Yin, &I.Xin})
     HIPOK(b->alloc((size_t)B * std::max(n_segs, 1) * L));
-  for (DBuf* b : {&I.Yb1, &I.Za1, &I.Yp1, &I.Xp1}) HIPOK(b->alloc(std::max(n_segs, 1)));
+  for (DBuf* b : {&I.Yp1, &I.Xp1}) HIPOK(b->alloc(std::max(n_segs, 1)));
   for (DBuf* b : {&I.RP, &I.RQ, &I.RU, &I.RV, &I.RW, &I.RY, &I.RX})
     HIPOK(b->alloc((size_t)B * std::max(n_runs, 1) * L));
   for (DBuf* b : {&I.RP1, &I.RQ1, &I.RU1, &I.RV1, &I.RW1, &I.RY1, &I.RX1})
@@ -757,7 +757,6 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
   DDInst& h = I.hdd;
   h.n = n; h.N = N; h.L = L; h.B = B; h.n_colors = K; h.n_segs = n_segs;
   h.slab = (long)n * L; h.Z = I.Z.p; h.segs = I.segs.p;
-  h.Yb = h.Za = nullptr;
   h.Yin = I.Yin.p; h.Xin = I.Xin.p;
   h.Yp = I.Yp.p; h.Xp = I.Xp.p;
   h.n_runs = n_runs; h.runs = I.runs.p;
@@ -768,7 +767,7 @@ pr_status setup_dd_instance(pr_problem_s* P, Instance& I, const double* rho_host
   DDInst& h1 = I.hdd1;
   h1 = h;
   h1.N = 1; h1.L = 1; h1.B = 1; h1.slab = n; h1.Z = I.tmp.p;
-  h1.Yb = I.Yb1.p; h1.Za = I.Za1.p; h1.Yin = h1.Xin = nullptr;
+  h1.Yin = h1.Xin = nullptr;
   h1.Yp = I.Yp1.p; h1.Xp = I.Xp1.p;
   h1.RP = I.RP1.p; h1.RQ = I.RQ1.p; h1.RU = I.RU1.p; h1.RV = I.RV1.p; h1.RW = I.RW1.p;
   h1.RY = I.RY1.p; h1.RX = I.RX1.p;

@@ -183,10 +183,9 @@ struct DDInst {
   long slab;            // doubles per slice block of Z: n*L
   double* Z;            // [B][n][L] (fine) or the state itself (L = 1)
   const DDSeg* segs;    // [n_segs], colour-major
-  // per (segment, slice): [B][n_segs][L]; Yb, Za (zero-carry values at the
-  // segment's ends) single state (L = 1) only, Yin, Xin of the slice-interleaved
-  // workspace only after its last substep
-  double* Yb; double* Za; double* Yin; double* Xin;
+  // per (segment, slice): [B][n_segs][L]; the carries of the slice-interleaved
+  // workspace after its last substep (k_dd_final_carries)
+  double* Yin; double* Xin;
   // The carries of segment t of run r are formed where they are used,
   // Yin = SA_t RY_r + Yp_t and Xin = SC_t RX_r + SD_t RY_r + Xp_t, from the run's
   // carries and the slice parts Yp, Xp ([B][n_segs][L]) that the run maps leave.
@@ -208,13 +207,14 @@ struct DDInst {
   const DDRunRec* run_recs;  // [n_runs]
 };
 
-// Phase 1. Single state (L = 1): segments [seg_begin, seg_begin + seg_count)
-// with zero carries, the input carrying no correction. Slice-interleaved
-// workspace (L >= 8): one workgroup per run [run_begin, run_begin + run_count)
-// of the colour, which also chains the run's segments (the slice parts Yp, Xp
-// and the run maps of phase 2); the pending correction of the previous
+// Phase 1, one workgroup per run [run_begin, run_begin + run_count) of the
+// colour, which also chains the run's segments (the slice parts Yp, Xp and the
+// run maps of phase 2). Single state (L = 1): zero-carry segment solves of an
+// input that carries no correction (phase 3 corrects in place). Slice-
+// interleaved workspace (L >= 8): the pending correction of the previous
 // substeps is applied on load (stale_ok: the previous step's corrections
-// exist) and this one is left pending.
+// exist) and this one is left pending. seg_begin, seg_count: the colour's
+// segments (unused by the kernels; kept for the caller's bookkeeping).
 hipError_t launch_dd_local(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
                            int seg_begin, int seg_count, int run_begin, int run_count,
                            bool stale_ok, hipStream_t s);

@@ -415,77 +415,9 @@ __global__ __launch_bounds__(4 * kWave) void k_dd_from_interleaved(
 // Carry resolution per (component, slice): Y_s = Yb_s + psi_s Y_{s-1} over the
 // component's segments, then X_s = Za_s + chi_s Y_{s-1} + phi_s X_{s+1}
 // backwards, over runs of kDDRun segments (see pr_internal.h): each run's maps
-// and the slice parts of its segments' carries, then the scan over each
-// component's runs; a segment's carries are formed where they are used. The
-// single state takes two launches (run maps with one lane per run, the scan);
-// the slice-interleaved workspace forms its run maps in k_dd_local_run and
-// needs only the scan (lanes are slices).
-
-// Loads the carry inputs of a run's segments (identity maps past its end); the
-// single state, one lane per run.
-__device__ __forceinline__ void load_run1(const DDInst& I, const DDFactors& f, const DDRun& rn,
-                                          double (&yb)[kDDRun], double (&za)[kDDRun],
-                                          double (&ps)[kDDRun], double (&ca)[kDDRun],
-                                          double (&pa)[kDDRun]) {
-#pragma unroll
-  for (int t = 0; t < kDDRun; t++) {
-    const bool ok = t < rn.len;
-    const int sidx = rn.seg0 + (ok ? t : 0);
-    const double y = gp(I.Yb)[sidx], z = gp(I.Za)[sidx];
-    const double p = gp(f.PSIE)[sidx], c = gp(f.CHIA)[sidx], h = gp(f.PHIA)[sidx];
-    yb[t] = ok ? y : 0.0;
-    za[t] = ok ? z : 0.0;
-    ps[t] = ok ? p : 1.0;
-    ca[t] = ok ? c : 0.0;
-    pa[t] = ok ? h : 1.0;
-  }
-}
-
-// 2a: run maps (single state, one lane per run), and the slice parts of the
-// carries of the run's segments (Yp, Xp; see DDInst).
-__global__ __launch_bounds__(kWave) void k_dd_runmaps1(const DDInst* __restrict__ insts,
-                                                       DDFactors f, int run_begin, int run_count) {
-  const DDInst& I = insts[0];
-  const int rix = blockIdx.x * kWave + threadIdx.x;
-  const bool active = rix < run_count;
-  const int ri = run_begin + (active ? rix : run_count - 1);
-  const DDRun rn = I.runs[ri];
-  double yb[kDDRun], za[kDDRun], ps[kDDRun], ca[kDDRun], pa[kDDRun];
-  load_run1(I, f, rn, yb, za, ps, ca, pa);
-  // forward: Y before segment t = pp[t] Y_before + qq[t]
-  double p = 1.0, q = 0.0, pp[kDDRun], qq[kDDRun];
-#pragma unroll
-  for (int t = 0; t < kDDRun; t++) {
-    pp[t] = p;
-    qq[t] = q;
-    q = fma(ps[t], q, yb[t]);
-    p = ps[t] * p;
-  }
-  // backward: X at segment t = u X_after + v Y_before + w; the w before segment
-  // t's update is the slice part of the X after it (see k_dd_local_run)
-  double u = 1.0, v = 0.0, w = 0.0, xp[kDDRun];
-#pragma unroll
-  for (int t = kDDRun - 1; t >= 0; t--) {
-    xp[t] = w;
-    w = fma(pa[t], w, fma(ca[t], qq[t], za[t]));
-    v = fma(pa[t], v, ca[t] * pp[t]);
-    u = pa[t] * u;
-  }
-  if (active) {
-#pragma unroll
-    for (int t = 0; t < kDDRun; t++)
-      if (t < rn.len) {
-        gp(I.Yp)[rn.seg0 + t] = qq[t];
-        gp(I.Xp)[rn.seg0 + t] = xp[t];
-      }
-    const long ridx = ri;
-    gp(I.RP)[ridx] = p;
-    gp(I.RQ)[ridx] = q;
-    gp(I.RU)[ridx] = u;
-    gp(I.RV)[ridx] = v;
-    gp(I.RW)[ridx] = w;
-  }
-}
+// and the slice parts of its segments' carries (formed by the segment solves'
+// workgroups, k_dd_local_run and k_dd_local_run1), then the scan over each
+// component's runs (below); a segment's carries are formed where they are used.
 
 // 2b: chains the runs of one component for one slice, 64 runs per wave step.
 // Components of up to kScanChunks * 64 runs (2^17-node components in 32-node
@@ -585,25 +517,39 @@ __global__ __launch_bounds__(kWave) void k_dd_runscan(const DDInst* __restrict__
 // (single state, below: x = z + chi Yin + phi Xin in place; the slice-
 // interleaved workspace defers the correction to the next load of each node)
 
-// Single state (L = 1): kDDSeg lanes per segment, lane = node. The zero-carry
-// segment solve is one forward and one backward affine scan across those lanes.
-__global__ __launch_bounds__(4 * kWave) void k_dd_local1(const DDInst* __restrict__ insts,
-                                                         DDFactors f, int colour, int seg_begin,
-                                                         int seg_count) {
+// Single state (L = 1): one workgroup per run, kDDSeg lanes per segment, lane =
+// node. The zero-carry segment solve is one forward and one backward affine
+// scan across those lanes; then one lane chains the run's segments (run maps and
+// the slice parts of the segments' carries, as k_dd_local_run does per slice).
+constexpr int kRun1Threads = kDDRun / kSegsPerWave * kWave;
+static_assert(kDDRun % kSegsPerWave == 0, "a run is a whole number of waves");
+
+__global__ __launch_bounds__(kRun1Threads) void k_dd_local_run1(const DDInst* __restrict__ insts,
+                                                                DDFactors f, int colour,
+                                                                int run_begin) {
+  __shared__ double sYb[kDDRun], sZa[kDDRun];
+  __shared__ double sF[4][kDDRun];  // the run's PSIE, CHIA, PHIA, SA
   const DDInst& I = insts[0];
-  const int lane = threadIdx.x & (kWave - 1);
+  const int ri = run_begin + blockIdx.x;
+  const DDRunRec* rec = I.run_recs + ri;
+  const int rlen = rec->len, seg0 = rec->seg0;  // workgroup-uniform
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int gl = lane % kDDSeg;  // node within the segment
-  const int w = (int)(blockIdx.x * 4 + threadIdx.x / kWave) * kSegsPerWave + lane / kDDSeg;
-  if (w >= seg_count) return;  // whole lane group; no block-level barrier follows
-  const int si = seg_begin + w;
-  const DDSeg sg = I.segs[si];
-  const bool ok = gl < sg.len;
-  const long node = sg.lo + (ok ? gl : 0);
+  const int t = wv * kSegsPerWave + lane / kDDSeg;  // segment within the run
+  const int slo = rec->lo[t], scnt = rec->cnt[t];  // cnt = 0 past the run's end
+  const bool ok = gl < scnt;
+  const long node = slo + (ok ? gl : 0);
   const long cb = (long)colour * I.n;
   const double em = gp(f.G)[cb + (node > 0 ? node - 1 : 0)];
   const double e = node > 0 ? em : 0.0;  // e = g of the previous node
   const double r = gp(f.R)[cb + node], g = gp(f.G)[cb + node];
   const double z0 = gp(I.Z)[node];
+  if (threadIdx.x < 4 * kDDRun) {
+    const int k = threadIdx.x / kDDRun, q = threadIdx.x - k * kDDRun;
+    const int sq = seg0 + (q < rlen ? q : 0);
+    const gdouble* src = gp(k == 0 ? f.PSIE : (k == 1 ? f.CHIA : (k == 2 ? f.PHIA : f.SA)));
+    sF[k][q] = src[sq];
+  }
   // forward: y_t = e_t y_{t-1} + d_t from y = 0 before the segment (e = 1,
   // d = 0 past its end)
   double a = ok ? e : 1.0, bb = ok ? z0 : 0.0;
@@ -615,10 +561,37 @@ __global__ __launch_bounds__(4 * kWave) void k_dd_local1(const DDInst* __restric
   group_scan_down<kDDSeg>(a, bb, gl);
   const double z = bb;
   if (ok) gp(I.Z)[node] = z;
-  const double ylast = __shfl(y, sg.len - 1, kDDSeg), zfirst = __shfl(z, 0, kDDSeg);
+  const double ylast = __shfl(y, (scnt > 0 ? scnt : 1) - 1, kDDSeg);
+  const double zfirst = __shfl(z, 0, kDDSeg);
   if (gl == 0) {
-    gp(I.Yb)[si] = ylast;
-    gp(I.Za)[si] = zfirst;
+    sYb[t] = ylast;
+    sZa[t] = zfirst;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // forward: Y before segment q = A_q Y_before + B_q; backward: X after it =
+    // C_q X_after + D_q Y_before + E_q (B, E are the slice parts)
+    double A = 1.0, Bq = 0.0;
+    for (int q = 0; q < rlen; q++) {
+      const double yb = sYb[q];
+      sYb[q] = Bq;
+      gp(I.Yp)[seg0 + q] = Bq;
+      Bq = fma(sF[0][q], Bq, yb);
+      A = sF[0][q] * A;
+    }
+    double C = 1.0, D = 0.0, E = 0.0;
+    for (int q = rlen - 1; q >= 0; q--) {
+      const double pa = sF[2][q], ca = sF[1][q];
+      gp(I.Xp)[seg0 + q] = E;
+      E = fma(pa, E, fma(ca, sYb[q], sZa[q]));
+      D = fma(pa, D, ca * sF[3][q]);
+      C = pa * C;
+    }
+    gp(I.RP)[ri] = A;
+    gp(I.RQ)[ri] = Bq;
+    gp(I.RU)[ri] = C;
+    gp(I.RV)[ri] = D;
+    gp(I.RW)[ri] = E;
   }
 }
 
@@ -721,13 +694,12 @@ static hipError_t dd_local_run_t(const DDInst* d, const DDInst& h, const DDFacto
 hipError_t launch_dd_local(const DDInst* d, const DDInst& h, const DDFactors& f, int colour,
                            int seg_begin, int seg_count, int run_begin, int run_count,
                            bool stale_ok, hipStream_t s) {
+  if (run_count <= 0) return hipSuccess;
   if (h.L == 1) {
-    if (seg_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dd_local1, dim3((seg_count + 4 * kSegsPerWave - 1) / (4 * kSegsPerWave)),
-                       dim3(4 * kWave), 0, s, d, f, colour, seg_begin, seg_count);
+    hipLaunchKernelGGL(k_dd_local_run1, dim3(run_count), dim3(kRun1Threads), 0, s, d, f, colour,
+                       run_begin);
     return hipGetLastError();
   }
-  if (run_count <= 0) return hipSuccess;
   switch (h.L) {
     case 8: return dd_local_run_t<8>(d, h, f, colour, run_begin, run_count, stale_ok, s);
     case 16: return dd_local_run_t<16>(d, h, f, colour, run_begin, run_count, stale_ok, s);
@@ -769,13 +741,6 @@ hipError_t launch_dd_carries(const DDInst* d, const DDInst& h, const DDFactors& 
                              int run_count, const int* comp_run_first, const int* comp_run_count,
                              int n_comps, hipStream_t s) {
   if (n_comps <= 0 || run_count <= 0) return hipSuccess;
-  if (h.L == 1) {
-    const dim3 grid((run_count + kWave - 1) / kWave, 1);
-    hipLaunchKernelGGL(k_dd_runmaps1, grid, dim3(kWave), 0, s, d, f, run_begin, run_count);
-    hipLaunchKernelGGL(k_dd_runscan, dim3(n_comps, 1), dim3(kWave), 0, s, d, comp_run_first,
-                       comp_run_count);
-    return hipGetLastError();
-  }
   hipLaunchKernelGGL(k_dd_runscan, dim3(n_comps, h.B * h.L), dim3(kWave), 0, s, d, comp_run_first,
                      comp_run_count);
   return hipGetLastError();
