@@ -151,3 +151,28 @@ def test_long_and_short_instances_in_one_handle():
         Uo, ko, _ = oracle_problem(w).parareal(w.u0, 2)
         assert k[i] == ko
         assert relerr(P.view(U, i, "states").cpu().numpy(), Uo) <= TOL
+
+
+@pytest.mark.parametrize("fine,nx,ny,N", [("fie", 1100, 37, 64), ("fie", 29, 2100, 3),
+                                          ("dr", 1100, 37, 4), ("dr", 33, 1500, 5)])
+def test_source_term_long_lines(fine, nx, ny, N):
+    """A source term (random spatial factor, the manufactured problem's time factors)
+    on lines longer than one segment: the fine propagation of every slice and two
+    parareal corrections against the oracle."""
+    w = W.small_dim2(nx, ny, n_slices=N, fine_steps=2, seed=nx + ny + N)
+    w.fine = fine
+    src = W.manufactured2d(8, N, 2)
+    S = np.random.default_rng(N).standard_normal((1, ny, nx))
+    w.forcing = (S, src.forcing[1], src.forcing[2])
+    P, O = gpu_problem(w), oracle_problem(w)
+    Uin = slice_inputs(w, seed=1)
+    F = P.new_slices()
+    P.fine_propagate(dev(Uin), F)
+    U = P.new_states()
+    k, inc = P.parareal_iterate(dev(w.u0), U, k_max=2, tol=0.0)
+    torch.cuda.synchronize()
+    ref = O.fine_batch(Uin)
+    assert relerr(F.cpu().numpy().reshape(ref.shape), ref) <= TOL
+    Uo, ko, _ = O.parareal(w.u0, 2)
+    assert k[0] == ko
+    assert relerr(U.cpu().numpy().reshape(Uo.shape), Uo) <= TOL
