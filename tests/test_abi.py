@@ -37,3 +37,14 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(B, "_lib", None)
     with pytest.raises(ImportError):
         B.lib()
+
+
+def test_null_handle_is_rejected_without_a_gpu():
+    """Entry points validate their handle before any device call: a NULL handle gives
+    PR_EINVAL and a message (host-only, so it runs here)."""
+    from paper_2502_08370_amd import _binding as B
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libpr.so is not built (run __graft_entry__.build())")
+    lib = B.lib()
+    assert lib.pr_profile_control(None, 3) == 1
+    assert b"NULL" in lib.pr_last_error()

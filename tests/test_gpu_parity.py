@@ -269,3 +269,6 @@ def test_profile_span_mode_counts():
     assert counts[1]["coarse_x"] == counts[1]["coarse_y"] == w.n_slices
     assert counts[3]["coarse_sweep"] == 2 * w.n_slices and "coarse_x" not in counts[3]
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    import paper_2502_08370_amd as pr
+    with pytest.raises(pr.PrError):
+        P.profile(4)
