@@ -121,6 +121,8 @@ def measured_traffic(kernel_src, summary):
 def sweep_label(prob):
     """Name and form of the fine sweep kernel the handle launches."""
     tw, gr, m = (prob.get_option(k) for k in ("twisted", "grouped", "fine_chunk"))
+    if prob.get_option("partitioned_used") > 0:
+        return "k_part_sweep (one workgroup per line, parts of up to 24 positions per lane)"
     ins = prob.instances[0]
     lanes = max(8, min(64, 1 << (ins["n_slices"] - 1).bit_length()))
     if ins["fine"] == 1:  # Douglas-Rachford sweeps use the short chunk
@@ -349,6 +351,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=512,
                     help="size of a plain device-to-device copy timed in the same run (0: skip)")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--partitioned", type=int, choices=[0, 1, 2], default=1,
+                    help="partitioned fine sweeps: 1 few slices (default), 2 wherever a line fits "
+                         "one workgroup, 0 chunked sweeps only")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1023)
@@ -406,6 +411,7 @@ def main():
         inst["forcing"] = w.forcing
     t_setup = time.perf_counter()
     prob = pr.Problem([inst])
+    prob.set_option("partitioned", args.partitioned)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     log(f"problem set-up (factorisations) {t_setup:.3f} s")

@@ -216,9 +216,22 @@ pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_m
  *                      blocks; k > 0: blocks are processed k at a time, each
  *                      group running all s fine steps before the next (a
  *                      smaller working set between consecutive sweeps)
+ *   PR_OPT_PARTITIONED 1 (default): the fine sweeps of 2D FIE instances with
+ *                      at most 24 slices whose lines fit one workgroup (at
+ *                      most 1024 positions, and at most 8 * (64 / Lp) * 24
+ *                      positions with slice blocks of Lp slices: few slices)
+ *                      hold each line whole, cut into parts solved side by
+ *                      side and joined exactly, and write exact values; the
+ *                      options above then only affect the other instances (with
+ *                      more slices the chunked sweeps were measured faster);
+ *                      2: every instance whose lines fit; 0: chunked sweeps
+ *   PR_OPT_PARTITIONED_USED  read only (pr_set_option returns PR_EINVAL): the
+ *                      number of the handle's instances whose fine sweeps are
+ *                      partitioned under the current options
  * Results do not depend on the options beyond rounding. */
 enum { PR_OPT_GRAPH = 1, PR_OPT_FINE_CHUNK = 2, PR_OPT_LANES = 3, PR_OPT_BLOCKS_PER_PASS = 4,
-       PR_OPT_TWISTED = 5, PR_OPT_GROUPED = 6 };
+       PR_OPT_TWISTED = 5, PR_OPT_GROUPED = 6, PR_OPT_PARTITIONED = 7,
+       PR_OPT_PARTITIONED_USED = 8 };
 pr_status pr_set_option(pr_problem p, int option, int value);
 pr_status pr_get_option(pr_problem p, int option, int* value);
 

@@ -58,7 +58,8 @@ def _check_coef(dim, nx, ny, mode, cx, cy, device):
 
 _OPTS = {"graph": B.PR_OPT_GRAPH, "fine_chunk": B.PR_OPT_FINE_CHUNK, "lanes": B.PR_OPT_LANES,
          "blocks_per_pass": B.PR_OPT_BLOCKS_PER_PASS, "twisted": B.PR_OPT_TWISTED,
-         "grouped": B.PR_OPT_GROUPED}
+         "grouped": B.PR_OPT_GROUPED, "partitioned": B.PR_OPT_PARTITIONED,
+         "partitioned_used": B.PR_OPT_PARTITIONED_USED}
 
 
 def _ptr(t):

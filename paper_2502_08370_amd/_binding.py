@@ -16,8 +16,8 @@ PR_OK, PR_EINVAL, PR_ENOMEM, PR_EDEVICE, PR_ENUMERIC, PR_EUNSUPPORTED = range(6)
 PR_SPLIT_DIM, PR_SPLIT_DD = 0, 1
 PR_FIE, PR_DR = 0, 1
 PR_COEF_FACES, PR_COEF_NODAL_LOG = 0, 1
-PR_OPT_GRAPH, PR_OPT_FINE_CHUNK, PR_OPT_LANES, PR_OPT_BLOCKS_PER_PASS, PR_OPT_TWISTED, PR_OPT_GROUPED = (
-    1, 2, 3, 4, 5, 6)
+(PR_OPT_GRAPH, PR_OPT_FINE_CHUNK, PR_OPT_LANES, PR_OPT_BLOCKS_PER_PASS, PR_OPT_TWISTED, PR_OPT_GROUPED,
+ PR_OPT_PARTITIONED, PR_OPT_PARTITIONED_USED) = (1, 2, 3, 4, 5, 6, 7, 8)
 
 STATUS_NAMES = {0: "PR_OK", 1: "PR_EINVAL", 2: "PR_ENOMEM", 3: "PR_EDEVICE", 4: "PR_ENUMERIC",
                 5: "PR_EUNSUPPORTED"}

@@ -121,6 +121,9 @@ struct Instance {
   DBuf ax, ay, theta;
   DBuf fxR, fxG, fyR, fyG, fxPhiC, fyPhiC, fxPhiS, fyPhiS;
   DBuf fxRG, fyRG;  // (r, g) pairs of the fine factors (grouped sweeps)
+  DBuf pxRG, pyRG;  // (r, g) pairs of the plain fine LU (partitioned sweeps)
+  bool part = false;  // its fine sweeps are partitioned (their output carries no correction)
+  int plx0 = 0, ply0 = 0;  // positions per part when they can be (0: the lines do not fit)
   DBuf cxR, cxG, cyR, cyG;
   DBuf cxRb, cxGb, cyRb, cyGb, fxRb, fxGb, fyRb, fyGb;  // lane-blocked copies
   DBuf Z, sigX, sigY, tmp;
@@ -206,6 +209,7 @@ struct pr_problem_s {
   int M = 20;  // fine-sweep chunk length (PR_OPT_FINE_CHUNK)
   bool twisted = true;  // two-wave twisted fine sweeps (PR_OPT_TWISTED)
   bool grouped = true;  // several lines per workgroup sharing their carry loads (PR_OPT_GROUPED)
+  int part_sweeps = 1;  // partitioned sweeps: 0 never, 1 few slices, 2 wherever lines fit (PR_OPT_PARTITIONED)
   DimInst* d_inst = nullptr;  // device descriptors, one per instance
   // grouped work lists per lane width L (index log2 L) and direction
   struct Group {
@@ -219,6 +223,12 @@ struct pr_problem_s {
     WorkItem* d_work[2] = {nullptr, nullptr};
     int n_work[2] = {0, 0};
     std::vector<int> pass_off[2];  // items of pass q: [pass_off[q], pass_off[q+1])
+    // partitioned sweeps (every member's lines fit a workgroup): items (inst,
+    // b, line), waves per workgroup and register positions per lane
+    bool part = false;
+    WorkItem* d_pwork[2] = {nullptr, nullptr};
+    int n_pwork[2] = {0, 0};
+    int pwaves[2] = {0, 0}, ppl[2] = {0, 0};
   };
   int blocks_per_pass = 0;  // 0: every slice block in every launch
   int n_passes = 1;
@@ -258,9 +268,12 @@ struct pr_problem_s {
     if (gstream) (void)hipStreamDestroy(gstream);
     if (d_active) (void)hipFree(d_active);
     if (d_inst) (void)hipFree(d_inst);
-    for (auto& g : groups)
+    for (auto& g : groups) {
       for (auto* w : g.d_work)
         if (w) (void)hipFree(w);
+      for (auto* w : g.d_pwork)
+        if (w) (void)hipFree(w);
+    }
     if (d_inc) (void)hipFree(d_inc);
     if (d_incp) (void)hipFree(d_incp);
     if (h_inc) (void)hipHostFree(h_inc);
@@ -413,6 +426,7 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   (void)st;
   const int Px = (nx + M - 1) / M, Py = (ny + M - 1) / M;
   HIPOK(I.fxR.alloc(npts)); HIPOK(I.fxG.alloc(npts)); HIPOK(I.fxRG.alloc(2 * npts));
+  HIPOK(I.pxRG.alloc(2 * npts));
   HIPOK(I.cxR.alloc(npts)); HIPOK(I.cxG.alloc(npts));
   HIPOK(I.fxPhiC.alloc(npts)); HIPOK(I.fxPhiS.alloc((size_t)ny * Px));
   const int Kx = positions_per_lane(nx), Ky = positions_per_lane(ny);
@@ -422,6 +436,7 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   HIPOK(I.fxRb.alloc(nbx)); HIPOK(I.fxGb.alloc(nbx));
   if (d.dim == 2) {
     HIPOK(I.fyR.alloc(npts)); HIPOK(I.fyG.alloc(npts)); HIPOK(I.fyRG.alloc(2 * npts));
+    HIPOK(I.pyRG.alloc(2 * npts));
     HIPOK(I.cyR.alloc(npts)); HIPOK(I.cyG.alloc(npts));
     HIPOK(I.fyPhiC.alloc(npts)); HIPOK(I.fyPhiS.alloc((size_t)nx * Py));
     HIPOK(I.cyRb.alloc(nby)); HIPOK(I.cyGb.alloc(nby));
@@ -440,7 +455,14 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   set_twist(h, P->twisted);
   h.steps = d.fine_steps;
   h.slab = (long)npts * L;
-  HIPOK(I.Z.alloc((size_t)B * npts * L));
+  // slice blocks of the partitioned sweeps (2D FIE only; the workspace holds
+  // either layout)
+  h.Lp = h.Bp = 0;
+  h.slabp = 0;
+  if (d.dim == 2 && d.fine == PR_FIE &&
+      part_layout(nx, ny, N, &h.Lp, &h.Bp, &I.plx0, &I.ply0))
+    h.slabp = (long)npts * h.Lp;
+  HIPOK(I.Z.alloc((size_t)std::max(B * L, h.Bp * h.Lp) * npts));
   HIPOK(I.sigX.alloc((size_t)B * ny * Px * L));
   if (d.dim == 2) HIPOK(I.sigY.alloc((size_t)B * nx * Py * L));
   HIPOK(I.tmp.alloc(npts));
@@ -459,6 +481,8 @@ pr_status setup_dim_instance(pr_problem_s* P, Instance& I, hipStream_t s) {
   h.fxR = I.fxR.p; h.fxG = I.fxG.p;
   h.fyR = I.fyR.p; h.fyG = I.fyG.p;
   h.fxRG = I.fxRG.p; h.fyRG = I.fyRG.p;
+  h.pxRG = I.pxRG.p; h.pyRG = I.pyRG.p;
+  h.plx = h.ply = 0;
   h.fxPhiC = I.fxPhiC.p; h.fyPhiC = I.fyPhiC.p; h.fxPhiS = I.fxPhiS.p; h.fyPhiS = I.fyPhiS.p;
   h.Kx = Kx; h.Ky = Ky; h.Sx = Sx; h.Sy = Sy;
   h.cxRb = I.cxRb.p; h.cxGb = I.cxGb.p; h.cyRb = I.cyRb.p; h.cyGb = I.cyGb.p;
@@ -497,6 +521,7 @@ pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
     jx.E = nullptr; jx.R = coarse ? I.cxR.p : I.fxR.p;
     jx.G = coarse ? I.cxG.p : I.fxG.p; jx.pos_major = 0;
     HIPOK(launch_factorize(jx, s));
+    if (!coarse) HIPOK(launch_interleave_pairs(jx.R, jx.G, (long)nx * ny, I.pxRG.p, s));
     HIPOK(launch_block_factors(jx.R, ny, nx, coarse ? I.cxRb.p : I.fxRb.p, s));
     HIPOK(launch_block_factors(jx.G, ny, nx, coarse ? I.cxGb.p : I.fxGb.p, s));
     if (d.dim == 2) {
@@ -507,6 +532,7 @@ pr_status factorize_instance(pr_problem_s* P, Instance& I, const double* coef_x,
       jy.E = nullptr; jy.R = coarse ? I.cyR.p : I.fyR.p;
       jy.G = coarse ? I.cyG.p : I.fyG.p; jy.pos_major = 0;
       HIPOK(launch_factorize(jy, s));
+      if (!coarse) HIPOK(launch_interleave_pairs(jy.R, jy.G, (long)nx * ny, I.pyRG.p, s));
       HIPOK(launch_block_factors(jy.R, nx, ny, coarse ? I.cyRb.p : I.fyRb.p, s));
       HIPOK(launch_block_factors(jy.G, nx, ny, coarse ? I.cyGb.p : I.fyGb.p, s));
     }
@@ -1306,7 +1332,8 @@ std::vector<WorkItem> build_work(const std::vector<int>& members,
 // Appends `items` to `out` in launch order such that, with workgroups dealt to
 // the 8 XCDs round-robin, each XCD receives a contiguous range of the list
 // (neighbouring line blocks share cache lines).
-void append_xcd_ordered(const std::vector<LineItem>& items, std::vector<LineItem>& out) {
+template <typename Item>
+void append_xcd_ordered(const std::vector<Item>& items, std::vector<Item>& out) {
   const int nb = (int)items.size(), per = nb / 8, rem = nb % 8;
   for (int bid = 0; bid < nb; bid++) {
     const int x = bid % 8, r = bid / 8;
@@ -1342,7 +1369,7 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
       continue;
     }
     PhaseTimer pt(P, PH_TRANSPOSE, s);
-    HIPOK(launch_to_interleaved(P->d_inst + i, I.h, U, s));
+    HIPOK(launch_to_interleaved(P->d_inst + i, I.h, U, s, I.part));
   }
   // all instances advance step by step; one grouped launch per lane width and
   // direction (per pass of slice blocks when passes are enabled: a pass runs all
@@ -1360,6 +1387,16 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
               HIPOK(launch_dr_stencil(P->d_inst + i, P->inst[i]->h, 0, t, q * P->pass_blocks,
                                       (q + 1) * P->pass_blocks, s));
             sp.add();
+          }
+          if (g.part) {  // all slice blocks in the first pass
+            if (q > 0) continue;
+            for (int dir = 0; dir < 2; dir++) {
+              PhaseTimer pt(P, PH_FINE, s);
+              HIPOK(launch_part_sweep(P->d_inst, g.d_pwork[dir], g.n_pwork[dir], dir, t,
+                                      g.pwaves[dir], g.ppl[dir], dir == 0 && g.ft, s));
+              sp.add();
+            }
+            continue;
           }
           for (int dir = 0; dir < 2; dir++) {
             const int off = g.pass_off[dir][q], cnt = g.pass_off[dir][q + 1] - off;
@@ -1396,7 +1433,8 @@ pr_status fine_all(pr_problem_s* P, const double* in_base, bool in_states_layout
     if (I.dd)
       HIPOK(launch_dd_from_interleaved(I.d_dd, I.hdd, I.ffine.view(), out_base + I.off_slices, s));
     else
-      HIPOK(launch_from_interleaved(P->d_inst + i, I.h, out_base + I.off_slices, true, s));
+      HIPOK(launch_from_interleaved(P->d_inst + i, I.h, out_base + I.off_slices, !I.part, s,
+                                    I.part));
   }
   return PR_OK;
 }
@@ -1529,15 +1567,33 @@ pr_status set_all_active(pr_problem_s* P, hipStream_t s) {
 // per-slice-index item lists of the batched coarse sweeps.
 pr_status build_schedules(pr_problem_s* P) {
   const int n = (int)P->inst.size();
+  // partitioned sweeps: 2D FIE instances whose lines fit one workgroup in both
+  // directions with the instance's fullest slice block
+  for (auto& Ip : P->inst) {
+    Instance& I = *Ip;
+    I.part = false;
+    if (I.dd) continue;
+    DimInst& h = I.h;
+    const bool on = I.plx0 > 0 && I.ply0 > 0 &&
+                    (P->part_sweeps == 2 || (P->part_sweeps == 1 && h.N <= kPartMaxSlices));
+    h.plx = on ? I.plx0 : 0;
+    h.ply = on ? I.ply0 : 0;
+  }
   std::vector<DimInst> hd(n);
   for (int i = 0; i < n; i++) hd[i] = P->inst[i]->h;
   HIPOK(hipMemcpy(P->d_inst, hd.data(), hd.size() * sizeof(DimInst), hipMemcpyHostToDevice));
-  for (auto& g : P->groups)
+  for (auto& g : P->groups) {
     for (auto*& w : g.d_work)
       if (w) {
         (void)hipFree(w);
         w = nullptr;
       }
+    for (auto*& w : g.d_pwork)
+      if (w) {
+        (void)hipFree(w);
+        w = nullptr;
+      }
+  }
   P->groups.clear();
   int Bmax = 1;
   for (auto& I : P->inst)
@@ -1546,12 +1602,13 @@ pr_status build_schedules(pr_problem_s* P) {
   P->n_passes = (Bmax + bpp - 1) / bpp;
   P->pass_blocks = bpp;
   for (int L = 1; L <= 64; L <<= 1)
-    for (int key = 0; key < 4; key++) {
-      const int dr = key & 1, ft = key >> 1;
+    for (int key = 0; key < 8; key++) {
+      const int dr = key & 1, ft = (key >> 1) & 1, pt = key >> 2;
       std::vector<int> members;
       for (int i = 0; i < n; i++) {
         const DimInst& hi = P->inst[i]->h;
-        if (!P->inst[i]->dd && hi.L == L && hi.dr == dr && (hi.nforce > 0) == (ft == 1))
+        if (!P->inst[i]->dd && hi.L == L && hi.dr == dr && (hi.nforce > 0) == (ft == 1) &&
+            (hi.plx > 0 && hi.ply > 0) == (pt == 1))
           members.push_back(i);
       }
       if (members.empty()) continue;
@@ -1576,6 +1633,27 @@ pr_status build_schedules(pr_problem_s* P) {
           g.pass_off[dir].push_back((int)all.size());
         }
         HIPOK(upload_work(all, &g.d_work[dir], &g.n_work[dir]));
+      }
+      g.part = pt == 1;  // every member's lines fit a workgroup
+      if (g.part) {
+        for (int dir = 0; dir < 2; dir++) {
+          std::vector<WorkItem> items;
+          for (int i : members) {
+            const DimInst& hi = P->inst[i]->h;
+            const int n_lines = dir == 0 ? hi.ny : hi.nx, n_pos = dir == 0 ? hi.nx : hi.ny;
+            const int Pl = dir == 0 ? hi.plx : hi.ply;
+            g.pwaves[dir] = std::max(g.pwaves[dir], part_waves(n_pos, Pl, hi.Lp));
+            g.ppl[dir] = std::max(g.ppl[dir], Pl);
+            // the blocks of a line share its factor rows, neighbouring y-lines
+            // the cache lines of their nodes
+            for (int ln = 0; ln < n_lines; ln++)
+              for (int b = 0; b < hi.Bp; b++) items.push_back(WorkItem{i, b, ln, 0});
+          }
+          std::vector<WorkItem> ordered;
+          append_xcd_ordered(items, ordered);
+          HIPOK(upload_work(ordered, &g.d_pwork[dir], &g.n_pwork[dir]));
+        }
+        for (int i : members) P->inst[i]->part = true;
       }
       P->groups.push_back(g);
     }
@@ -2122,6 +2200,12 @@ pr_status pr_set_option(pr_problem p, int option, int value) {
         if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
           return fail(PR_EINVAL, "lanes must be 0, 8, 16, 32 or 64");
         return apply_layout(p, value, p->M, p->twisted);
+      case PR_OPT_PARTITIONED:
+        if (value < 0 || value > 2) return fail(PR_EINVAL, "partitioned option must be 0, 1 or 2");
+        p->part_sweeps = value;
+        return apply_layout(p, p->lanes_cap, p->M, p->twisted);
+      case PR_OPT_PARTITIONED_USED:
+        return fail(PR_EINVAL, "option %d is read only", option);
       case PR_OPT_BLOCKS_PER_PASS:
         if (value < 0) return fail(PR_EINVAL, "blocks per pass must be >= 0");
         p->blocks_per_pass = value;
@@ -2142,6 +2226,13 @@ pr_status pr_get_option(pr_problem p, int option, int* value) {
       case PR_OPT_GROUPED: *value = p->grouped ? 1 : 0; return PR_OK;
       case PR_OPT_LANES: *value = p->lanes_cap; return PR_OK;
       case PR_OPT_BLOCKS_PER_PASS: *value = p->blocks_per_pass; return PR_OK;
+      case PR_OPT_PARTITIONED: *value = p->part_sweeps; return PR_OK;
+      case PR_OPT_PARTITIONED_USED: {
+        int c = 0;
+        for (auto& I : p->inst) c += I->part ? 1 : 0;
+        *value = c;
+        return PR_OK;
+      }
       default: return fail(PR_EINVAL, "unknown option %d", option);
     }
   });

@@ -58,6 +58,16 @@ struct DimInst {
   //   fxPhiS[j*Px + k], fyPhiS[i*Py + k]: phi at the first position of chunk k
   const double* fxPhiC; const double* fyPhiC;
   const double* fxPhiS; const double* fyPhiS;
+  // Partitioned fine sweeps (few slices, see launch_part_sweep): positions per
+  // part of an x-line / y-line (0: not used); their own slice blocks of Lp
+  // slices (Bp blocks, the last one possibly shorter; no padding) laid out as
+  // Z[b][j][i][l] with slabp = nx*ny*Lp doubles per block; and the plain LU of
+  // the fine line systems as (r, g) pairs, [line][pos][2], whatever form the
+  // other sweeps use
+  int plx, ply;
+  int Lp, Bp;
+  long slabp;
+  const double* pxRG; const double* pyRG;
   // Lane-blocked factor copies for the one-wave-per-line solvers (coarse
   // propagator, sequential fine solve, adjoint): line l, segment s, position
   // p = s*64*K + lane*K + c at [l][s][c][lane], zero past the line end; K = Kx,
@@ -431,11 +441,12 @@ hipError_t launch_chunk_phi_twisted(const double* G, int n_lines, int n_pos, int
                                     double* phiC, double* phiS, hipStream_t s);
 hipError_t launch_chunk_phi(const double* G, int n_lines, int n_pos, int M, double* phiC,
                             double* phiS, hipStream_t s);
+// part: the partitioned sweeps' slice blocks (Lp, Bp, slabp) instead of (L, B, slab).
 hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const double* U_in,
-                                 hipStream_t s);
+                                 hipStream_t s, bool part = false);
 // with_corr = false: plain transpose (no pending chunk correction).
 hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, double* F_out,
-                                   bool with_corr, hipStream_t s);
+                                   bool with_corr, hipStream_t s, bool part = false);
 // sgn = +1 / -1: add / subtract the instance's DR array on load (0: FIE);
 // forced: the x sweep adds the step's source term (dir 0 only).
 // twisted: two-wave workgroups, the bottom chunks [twx / twy, P) of every line
@@ -451,6 +462,31 @@ hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int
 int grouped_lines();
 // Chunks of M positions whose outer values the fine sweeps keep in LDS.
 int lds_chunk_lines(int M);
+// Partitioned fine sweeps (k_part_sweep): one workgroup of at most kPartWaves
+// waves per (instance, slice block, line) holds the whole line, cut into parts
+// of at most kPartMaxPL positions per lane, and writes exact values (no pending
+// correction: the next sweep and the final transpose read them as they are).
+// Workgroups of 8 waves within 128 registers let two share a compute unit.
+constexpr int kPartWaves = 8;
+constexpr int kPartMaxPL = 24;  // more positions per lane spill registers
+// Positions per part for lines of n positions and slice blocks of at most nb
+// slices (0: such a line does not fit one workgroup), and the waves it takes.
+int part_positions(int n, int nb);
+int part_waves(int n, int Pl, int nb);
+// By default the partitioned sweeps serve instances of at most kPartMaxSlices
+// slices: with more, the chunked sweeps hold enough line recurrences in flight
+// and were measured faster (999^2: partitioned 0.47 against 0.39 of 8 TB/s at
+// N = 20, 0.42 against 0.47 at N = 32, 0.43 against 0.54 at 1023^2, N = 64).
+constexpr int kPartMaxSlices = 24;
+// Slice blocks of the partitioned sweeps for an nx x ny grid and N slices: the
+// fewest blocks Bp (of Lp = ceil(N / Bp) slices) with which the lines of both
+// directions fit one workgroup, and their positions per part; false if none.
+bool part_layout(int nx, int ny, int N, int* Lp, int* Bp, int* plx, int* ply);
+// One partitioned sweep of direction dir over the work items (inst, b, line):
+// workgroups of `waves` waves, register arrays for pl positions per lane (pl at
+// least every item's part length); forced: the x sweep adds the step's source.
+hipError_t launch_part_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int dir,
+                             int step, int waves, int pl, bool forced, hipStream_t s);
 // S = dt A_y U on the slice-interleaved workspace (U with the pending y-sweep
 // correction when has_prev) of one instance, slice blocks [b_lo, b_hi), before
 // fine step `step` (nothing once the instance has finished its steps).

@@ -232,13 +232,16 @@ constexpr int kTrThreads = kTrWaves * kWave;
 constexpr int kTrIt = kWave * kWave / kTrThreads;  // tile entries per thread
 
 __global__ __launch_bounds__(kTrThreads) void k_to_interleaved(const DimInst* __restrict__ insts,
-                                                               const double* __restrict__ U) {
+                                                               const double* __restrict__ U,
+                                                               int part) {
   __shared__ double tile[64][65];
   const DimInst& I = insts[0];
   if (I.active && !I.active[I.idx]) return;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int i0 = blockIdx.x * 64, j = blockIdx.y, b = blockIdx.z;
-  const int L = I.L, nx = I.nx, lg = 31 - __clz(L);
+  // blocks of the partitioned sweeps need not be a power of two wide
+  const int L = part ? I.Lp : I.L, nx = I.nx, lg = 31 - __clz(L);
+  const long slab = part ? I.slabp : I.slab;
   const long npts = (long)nx * I.ny;
   const int i = i0 + lane;
   double v[kTrIt];
@@ -253,26 +256,26 @@ __global__ __launch_bounds__(kTrThreads) void k_to_interleaved(const DimInst* __
     if (sl < L) tile[sl][lane] = v[u];
   }
   __syncthreads();
-  gdouble* Zb = gp(I.Z) + b * I.slab + ((long)j * nx + i0) * L;
+  gdouble* Zb = gp(I.Z) + b * slab + ((long)j * nx + i0) * L;
   const int n = min(64, nx - i0) * L;
 #pragma unroll
   for (int u = 0; u < kTrIt; u++) {
     const int q = tid + kTrThreads * u;
-    if (q < n) Zb[q] = tile[q & (L - 1)][q >> lg];
+    if (q < n) Zb[q] = part ? tile[q % L][q / L] : tile[q & (L - 1)][q >> lg];
   }
 }
 
 // Z (+ the pending chunk correction of the last y sweep) -> natural F[slice][j][i].
 __global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
-    const DimInst* __restrict__ insts, double* __restrict__ F, int with_corr) {
+    const DimInst* __restrict__ insts, double* __restrict__ F, int with_corr, int part) {
   __shared__ double tile[64][65];
   const DimInst& I = insts[0];
   if (I.active && !I.active[I.idx]) return;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int i0 = blockIdx.x * 64, j = blockIdx.y, b = blockIdx.z;
-  const int L = I.L, nx = I.nx, M = I.M, Py = I.Py, lg = 31 - __clz(L);
+  const int L = part ? I.Lp : I.L, nx = I.nx, M = I.M, Py = I.Py, lg = 31 - __clz(L);
   const long npts = (long)nx * I.ny;
-  const gdouble* Zb = gp(I.Z) + b * I.slab + ((long)j * nx + i0) * L;
+  const gdouble* Zb = gp(I.Z) + b * (part ? I.slabp : I.slab) + ((long)j * nx + i0) * L;
   const gdouble* sig = with_corr ? gp(I.sigY) + ((long)b * Py + j / M) * nx * L : nullptr;
   const gdouble* phiC = with_corr ? gp(I.fyPhiC) + (long)j * nx : nullptr;
   const int n = min(64, nx - i0) * L;
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
   for (int u = 0; u < kTrIt; u++) {
     const int q = tid + kTrThreads * u;
     const bool ok = q < n;
-    const int t = q >> lg, sl = q & (L - 1);
+    const int t = part ? q / L : q >> lg, sl = part ? q % L : q & (L - 1);
     z[u] = ok ? Zb[q] : 0.0;
     ph[u] = (ok && with_corr) ? phiC[i0 + t] : 0.0;
     sg[u] = (ok && with_corr) ? sig[(long)(i0 + t) * L + sl] : 0.0;
@@ -289,7 +292,8 @@ __global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
 #pragma unroll
   for (int u = 0; u < kTrIt; u++) {
     const int q = tid + kTrThreads * u;
-    if (q < n) tile[q & (L - 1)][q >> lg] = fma(ph[u], sg[u], z[u]);
+    if (q < n)
+      tile[part ? q % L : q & (L - 1)][part ? q / L : q >> lg] = fma(ph[u], sg[u], z[u]);
   }
   __syncthreads();
   const int cnt = min(64, nx - i0);
@@ -1611,6 +1615,217 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, siz
   for (; i < n; i += stride) b[i] = a[i];
 }
 
+// ------------------------------------------------ partitioned fine sweeps ---
+
+// One substep of the fine FIE step for the lines of direction DIR when a whole
+// line of a slice block fits in one workgroup's registers (few slices), one
+// workgroup per (instance, slice block, line). The line is cut into parts of Pl
+// consecutive positions; a lane holds one (part, slice) pair, a wave 64 / nb
+// parts of the block's nb slices, and each lane loads all of its part's values
+// at once, so every load of the sweep is in flight together. With the line's
+// plain LU (forward y_p = d_p + e_p y_{p-1}, e_p = g_{p-1}; back x_p = r_p y_p +
+// g_p x_{p+1}; section 2.2, eq. FIE_method: each substep is an exact solve):
+// started from y_{s-1} = 0, a part [s, e) gives y0, and the true y_p = y0_p +
+// (e_s ... e_p) Yin with Yin the true y_{s-1}, so the parts' incoming values
+// follow from a fold over the earlier parts of the maps Yin -> (e_s ... e_{e-1})
+// Yin + y0_{e-1}. With the true y, the part's back substitution from x_e = 0
+// gives x0_s, and x_s = x0_s + (g_s ... g_{e-1}) Xout with Xout = x_e the first
+// value of the next part: a fold over the later parts gives each part's Xout,
+// and a last back substitution from it gives the exact values. Every value is
+// read and written once, and the output carries no pending correction.
+template <int DIR, bool FT, int PL>
+__global__ __launch_bounds__(kPartWaves* kWave, 4) void k_part_sweep(
+    const DimInst* __restrict__ insts, const WorkItem* __restrict__ work, int step) {
+  static_assert(!FT || DIR == 0, "the source enters the first (x) stage");
+  __shared__ dv2 sRG[kLineSeg];  // (r_p, g_p) of the line
+  __shared__ double sSrc[FT ? kMaxForcing : 1][FT ? kLineSeg : 1];
+  // per lane: the part's forward map (A: product of e, B: y0 at its end), then
+  // its backward map (C: product of g, D: x0 at its start)
+  __shared__ double sA[kPartWaves * kWave], sB[kPartWaves * kWave];
+  __shared__ double sC[kPartWaves * kWave], sD[kPartWaves * kWave];
+
+  const WorkItem w = work[blockIdx.x];
+  const DimInst& I = insts[w.inst];
+  if (step >= I.steps) return;  // this instance has finished its fine steps
+  if (I.active && !I.active[I.idx]) return;  // converged instance
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
+  const int L = I.Lp;                    // the partitioned sweeps' slice blocks
+  const int nb = min(L, I.N - w.b * L);  // slices of this block
+  const int G = kWave / nb;              // parts per wave
+  const int gq = lane / nb, sl = lane - gq * nb;
+  const int q = wv * G + gq;             // this lane's part
+  const int n_pos = DIR == 0 ? I.nx : I.ny;
+  const int Pl = DIR == 0 ? I.plx : I.ply;
+  const int Pn = (n_pos + Pl - 1) / Pl;
+  const bool act = gq < G && q < Pn;
+  const int s0 = act ? q * Pl : 0;
+  const int cnt = act ? min(Pl, n_pos - s0) : 0;
+  const int line = w.group;
+  const long pstr = DIR == 0 ? (long)L : (long)I.nx * L;
+  const long lstr = DIR == 0 ? (long)I.nx * L : (long)L;
+  const long base = w.b * I.slabp + (long)line * lstr + (long)s0 * pstr + (act ? sl : 0);
+  const gdouble* zin = gp(I.Z) + base;
+  gdouble* zst = gp(I.Z) + I.zout + base;
+
+  // the part's values (positions past its end reload its first one)
+  double v[PL];
+#pragma unroll
+  for (int t = 0; t < PL; t++) v[t] = t < Pl ? zin[(long)(t < cnt ? t : 0) * pstr] : 0.0;
+  // the line's factors and source rows, staged for every lane (registers first,
+  // so that one wait covers them)
+  const gdv2* RG = (const gdv2*)(DIR == 0 ? I.pxRG : I.pyRG) + (long)line * n_pos;
+  const int nthr = blockDim.x;
+  constexpr int KS = 4;
+  dv2 rg_st[KS];
+  double src_st[FT ? KS : 1][FT ? kMaxForcing : 1];
+#pragma unroll
+  for (int k = 0; k < KS; k++) {
+    const int p = tid + k * nthr;
+    if (p < n_pos) {
+      rg_st[k] = RG[p];
+      if constexpr (FT) {
+#pragma unroll
+        for (int m = 0; m < kMaxForcing; m++)
+          src_st[k][m] = gp(I.fS)[m * I.npts + (long)line * I.nx + p];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KS; k++) {
+    const int p = tid + k * nthr;
+    if (p < n_pos) {
+      sRG[p] = rg_st[k];
+      if constexpr (FT) {
+#pragma unroll
+        for (int m = 0; m < kMaxForcing; m++) sSrc[m][p] = src_st[k][m];
+      }
+    }
+  }
+  for (int p = tid + KS * nthr; p < n_pos; p += nthr) {  // workgroups of fewer than 4 waves
+    sRG[p] = RG[p];
+    if constexpr (FT) {
+#pragma unroll
+      for (int m = 0; m < kMaxForcing; m++) sSrc[m][p] = gp(I.fS)[m * I.npts + (long)line * I.nx + p];
+    }
+  }
+  // source: dt * g_m of this lane's slice at this step
+  double gl[kMaxForcing] = {};
+  if constexpr (FT) {
+    const int slice = w.b * L + sl;
+    const long nst = (long)I.N * I.steps;
+#pragma unroll
+    for (int m = 0; m < kMaxForcing; m++)
+      gl[m] = (act && slice < I.N) ? gp(I.fgf)[m * nst + (long)slice * I.steps + step] : 0.0;
+  }
+  __syncthreads();
+
+  // The recurrences run over all PL positions with clamped factor reads and
+  // keep only the part's own steps (no branches, so the LDS reads can be issued
+  // ahead); values past the part's end are never stored.
+  const int last = n_pos - 1;
+  // forward elimination of the part from y_{s-1} = 0
+  double y = 0.0, psi = 1.0;
+#pragma unroll
+  for (int t = 0; t < PL; t++) {
+    const int p = min(s0 + t, last);
+    const bool ok = t < cnt;
+    const double ep = sRG[p > 0 ? p - 1 : 0].y;
+    const double e = p > 0 ? ep : 0.0;
+    double d = v[t];
+    if constexpr (FT) {
+#pragma unroll
+      for (int m = 0; m < kMaxForcing; m++) d = fma(gl[m], sSrc[m][p], d);
+    }
+    const double yn = fma(e, y, d);
+    v[t] = yn;
+    y = ok ? yn : y;
+    psi = ok ? psi * e : psi;
+  }
+  sA[tid] = psi;
+  sB[tid] = y;
+  __syncthreads();
+  // Yin: the forward maps of the earlier parts, in order
+  // (four entries read before they are folded, so the chain waits on the
+  // multiply-adds rather than on every read). Part k sits in lane (k % G) * nb +
+  // sl of wave k / G; the folds step (k / G, k % G) instead of dividing.
+  constexpr int KF = 4;
+  double Y = 0.0;
+  const int qa = act ? q : 0;  // lanes without a part fold nothing
+  {
+    int kw = 0, kr = 0;
+    for (int k0 = 0; k0 < qa; k0 += KF) {
+      double a[KF], b[KF];
+#pragma unroll
+      for (int j = 0; j < KF; j++) {
+        const bool ok = k0 + j < qa;
+        const int t2 = ok ? kw * kWave + kr * nb + sl : 0;
+        a[j] = ok ? sA[t2] : 1.0;
+        b[j] = ok ? sB[t2] : 0.0;
+        if (++kr == G) {
+          kr = 0;
+          ++kw;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < KF; j++) Y = fma(a[j], Y, b[j]);
+    }
+  }
+  // true y of the part, and its back substitution from x_e = 0
+  double dy = Y;
+#pragma unroll
+  for (int t = 0; t < PL; t++) {
+    const int p = min(s0 + t, last);
+    const double ep = sRG[p > 0 ? p - 1 : 0].y;
+    dy *= p > 0 ? ep : 0.0;
+    v[t] += dy;
+  }
+  double x = 0.0, phi = 1.0;
+#pragma unroll
+  for (int t = PL - 1; t >= 0; t--) {
+    const bool ok = t < cnt;
+    const dv2 rg = sRG[min(s0 + t, last)];
+    const double xn = fma(rg.x, v[t], rg.y * x);
+    x = ok ? xn : x;
+    phi = ok ? phi * rg.y : phi;
+  }
+  sC[tid] = phi;
+  sD[tid] = x;
+  __syncthreads();
+  // Xout: the backward maps of the later parts, from the line end
+  double X = 0.0;
+  const int qb = act ? q : Pn - 1;  // parts (qb, Pn) are folded, last first
+  {
+    int kw = (Pn - 1) / G, kr = (Pn - 1) - kw * G;
+    for (int k0 = Pn - 1; k0 > qb; k0 -= KF) {
+      double c[KF], dd[KF];
+#pragma unroll
+      for (int j = 0; j < KF; j++) {
+        const bool ok = k0 - j > qb;
+        const int t2 = ok ? kw * kWave + kr * nb + sl : 0;
+        c[j] = ok ? sC[t2] : 1.0;
+        dd[j] = ok ? sD[t2] : 0.0;
+        if (kr-- == 0) {
+          kr = G - 1;
+          --kw;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < KF; j++) X = fma(c[j], X, dd[j]);
+    }
+  }
+  // plain stores: a node's slices of one block seldom fill whole cache lines,
+  // and the cache merges the pieces (nontemporal stores of them were slower)
+  x = X;
+#pragma unroll
+  for (int t = PL - 1; t >= 0; t--) {
+    const bool ok = t < cnt;
+    const dv2 rg = sRG[min(s0 + t, last)];
+    const double xn = fma(rg.x, v[t], rg.y * x);
+    x = ok ? xn : x;
+    if (ok) zst[(long)t * pstr] = xn;
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launchers ---
@@ -1663,17 +1878,18 @@ hipError_t launch_chunk_phi(const double* G, int n_lines, int n_pos, int M, doub
 }
 
 hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const double* U_in,
-                                 hipStream_t s) {
-  dim3 grid((h.nx + 63) / 64, h.ny, h.B);
-  hipLaunchKernelGGL(k_to_interleaved, grid, dim3(kTrThreads), 0, s, d_inst, U_in);
+                                 hipStream_t s, bool part) {
+  dim3 grid((h.nx + 63) / 64, h.ny, part ? h.Bp : h.B);
+  hipLaunchKernelGGL(k_to_interleaved, grid, dim3(kTrThreads), 0, s, d_inst, U_in, (int)part);
   return hipGetLastError();
 }
 
 hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, double* F_out,
-                                   bool with_corr, hipStream_t s) {
-  dim3 grid((h.nx + 63) / 64, h.ny, h.B);
+                                   bool with_corr, hipStream_t s, bool part) {
+  if (part && with_corr) return hipErrorInvalidValue;  // partitioned output is exact
+  dim3 grid((h.nx + 63) / 64, h.ny, part ? h.Bp : h.B);
   hipLaunchKernelGGL(k_from_interleaved, grid, dim3(kTrThreads), 0, s, d_inst, F_out,
-                     (int)with_corr);
+                     (int)with_corr, (int)part);
   return hipGetLastError();
 }
 
@@ -1798,6 +2014,57 @@ hipError_t launch_fine_sweep(const DimInst* d_insts, const WorkItem* d_work, int
                                          sgn, forced)
                  : launch_sweep_tw<false>(d_insts, d_work, n_work, L, M, dir, has_prev, step, s,
                                           sgn, forced);
+}
+
+int part_positions(int n, int nb) {
+  if (n < 1 || n > kLineSeg || nb < 1 || nb > kWave) return 0;
+  const int parts = kPartWaves * (kWave / nb);
+  const int Pl = (n + parts - 1) / parts;
+  return Pl <= kPartMaxPL ? Pl : 0;
+}
+
+int part_waves(int n, int Pl, int nb) {
+  const int Pn = (n + Pl - 1) / Pl, G = kWave / nb;
+  return (Pn + G - 1) / G;
+}
+
+bool part_layout(int nx, int ny, int N, int* Lp, int* Bp, int* plx, int* ply) {
+  for (int B = (N + kWave - 1) / kWave; B <= N; B++) {
+    const int L = (N + B - 1) / B;
+    if ((N + L - 1) / L != B) continue;  // the same blocks as fewer of them
+    const int px = part_positions(nx, L), py = part_positions(ny, L);
+    if (px > 0 && py > 0) {
+      *Lp = L;
+      *Bp = B;
+      *plx = px;
+      *ply = py;
+      return true;
+    }
+  }
+  return false;
+}
+
+template <int DIR, bool FT>
+static hipError_t launch_part_t(const DimInst* d_insts, const WorkItem* d_work, int n_work,
+                                int step, int waves, int pl, hipStream_t s) {
+  const dim3 grid(n_work), block(waves * kWave);
+  static_assert(kPartMaxPL == 24, "register arrays of 16 and 24 positions");
+  if (pl <= 16)
+    hipLaunchKernelGGL((k_part_sweep<DIR, FT, 16>), grid, block, 0, s, d_insts, d_work, step);
+  else
+    hipLaunchKernelGGL((k_part_sweep<DIR, FT, 24>), grid, block, 0, s, d_insts, d_work, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_part_sweep(const DimInst* d_insts, const WorkItem* d_work, int n_work, int dir,
+                             int step, int waves, int pl, bool forced, hipStream_t s) {
+  if ((forced && dir != 0) || waves < 1 || waves > kPartWaves || pl < 1 || pl > kPartMaxPL)
+    return hipErrorInvalidValue;
+  if (n_work == 0) return hipSuccess;
+  if (dir == 0)
+    return forced ? launch_part_t<0, true>(d_insts, d_work, n_work, step, waves, pl, s)
+                  : launch_part_t<0, false>(d_insts, d_work, n_work, step, waves, pl, s);
+  return launch_part_t<1, false>(d_insts, d_work, n_work, step, waves, pl, s);
 }
 
 int positions_per_lane(int n) {

@@ -63,10 +63,12 @@ def test_batch_tolerance_masking_matches_oracle():
     assert len(ks) > 1  # the masking was exercised
 
 
+@pytest.mark.parametrize("part", [2, 0])
 @pytest.mark.parametrize("lanes,chunk", [(8, 16), (16, 32), (32, 16), (0, 32)])
-def test_layout_options(lanes, chunk):
+def test_layout_options(lanes, chunk, part):
     ws = [W.small_dim2(70, 45, 64, 3, seed=5), W.small_dim2(33, 50, 16, 3, seed=6)]
     P = gpu_problem(ws)
+    P.set_option("partitioned", part)
     P.set_option("lanes", lanes)
     P.set_option("fine_chunk", chunk)
     u0 = P.pack_u0([w.u0 for w in ws])

@@ -51,10 +51,12 @@ def test_forced_fine_propagate(nx, ny, N, s, m, fine):
     assert relerr(F.cpu().numpy().reshape(ref.shape), ref) <= TOL
 
 
+@pytest.mark.parametrize("part", [2, 0])
 @pytest.mark.parametrize("lanes,chunk", [(8, 16), (16, 32), (32, 16), (64, 32)])
-def test_forced_layouts(lanes, chunk):
+def test_forced_layouts(lanes, chunk, part):
     w = forced(75, 66, 64, 2, fine="fie", seed=3, c=0.5)
     P, O = gpu_problem(w), oracle_problem(w)
+    P.set_option("partitioned", part)
     P.set_option("lanes", lanes)
     P.set_option("fine_chunk", chunk)
     Uin = slice_inputs(w, seed=2)

@@ -38,10 +38,12 @@ FINE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("part", [2, 0])
 @pytest.mark.parametrize("nx,ny,N,s,var", FINE_CASES)
-def test_fine_propagate(nx, ny, N, s, var):
+def test_fine_propagate(nx, ny, N, s, var, part):
     w = W.small_dim2(nx, ny, n_slices=N, fine_steps=s, seed=nx + 7 * ny + N, variable=var)
     P, O = gpu_problem(w), oracle_problem(w)
+    P.set_option("partitioned", part)
     Uin = slice_inputs(w, seed=N)
     F = P.new_slices()
     P.fine_propagate(dev(Uin), F)
@@ -63,7 +65,7 @@ SWEEP_SHAPES = [
 @pytest.mark.parametrize("twisted,grouped,chunk", [(1, 1, 20), (1, 1, 24), (1, 0, 16), (1, 0, 24),
                                                    (1, 0, 32), (0, 0, 20), (0, 0, 32)])
 def test_fine_sweep_variants(twisted, grouped, chunk):
-    """Every fine-sweep form (one wave per line; two waves per line from the two ends;
+    """Every chunked fine-sweep form (one wave per line; two waves per line from the two ends;
     four lines per workgroup sharing their carry loads) and chunk length against the
     oracle, with and without a source term."""
     for k, (nx, ny, N) in enumerate(SWEEP_SHAPES):
@@ -74,6 +76,7 @@ def test_fine_sweep_variants(twisted, grouped, chunk):
             S = np.random.default_rng(k).standard_normal((1, ny, nx))
             w.forcing = (S, src.forcing[1], src.forcing[2])
         P, O = gpu_problem(w), oracle_problem(w)
+        P.set_option("partitioned", 0)
         P.set_option("twisted", twisted)
         P.set_option("grouped", grouped)
         P.set_option("fine_chunk", chunk)
