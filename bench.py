@@ -201,8 +201,10 @@ def bench_batch(args):
 
     t0 = time.perf_counter()
     P = pr.Problem([inst(w) for w in ws])
+    P.set_option("partitioned", args.partitioned)
     torch.cuda.synchronize()
-    log(f"batch handle: {len(ws)} instances, created in {time.perf_counter() - t0:.2f} s")
+    log(f"batch handle: {len(ws)} instances, created in {time.perf_counter() - t0:.2f} s, "
+        f"{P.get_option('partitioned_used')} with partitioned sweeps")
     tune = P.autotune() if args.autotune else None
     if tune:
         log(f"autotune: {tune}")
@@ -230,6 +232,7 @@ def bench_batch(args):
         t_loop = 0.0
         for i, w in enumerate(ws):
             Pi = pr.Problem([inst(w)])
+            Pi.set_option("partitioned", args.partitioned)
             Pi.set_option("graph", use_graph)
             ui = torch.as_tensor(w.u0, device=dev).reshape(-1).contiguous()
             Ui = Pi.new_states()
@@ -470,6 +473,10 @@ def main():
     if w.split != "dd" and (w.nx, w.n_slices, w.fine_steps) == (1023, 64, 64):
         tb = measured_traffic(os.path.join(csrc, "pr_kernels_dim.hip"),
                               os.path.join(ROOT, "profiles", "pmc_fine_sweep_varcoef2d_1023_N64_s64.json"))
+    elif (w.split != "dd" and w.fine == "fie" and (w.nx, w.n_slices, w.fine_steps) == (999, 20, 20)
+          and prob.get_option("partitioned_used") > 0):
+        tb = measured_traffic(os.path.join(csrc, "pr_kernels_dim.hip"),
+                              os.path.join(ROOT, "profiles", "pmc_fine_sweep_manufactured2d_999_N20_s20.json"))
     elif dd2 and (w.nx, w.n_slices, w.fine_steps) == (999, 20, 20):
         tb = measured_traffic(os.path.join(csrc, "pr_kernels_dd2.hip"),
                               os.path.join(ROOT, "profiles", "pmc_dd2_substep_dd2d_999_M2_q2_N20_s20.json"))
