@@ -1639,8 +1639,11 @@ __global__ __launch_bounds__(kPartWaves* kWave, 4) void k_part_sweep(
   static_assert(!FT || DIR == 0, "the source enters the first (x) stage");
   __shared__ dv2 sRG[kLineSeg];  // (r_p, g_p) of the line
   __shared__ double sSrc[FT ? kMaxForcing : 1][FT ? kLineSeg : 1];
-  // per lane: the part's forward map (A: product of e, B: y0 at its end), then
-  // its backward map (C: product of g, D: x0 at its start)
+  // per lane: its scan within the wave (exchanged through LDS: the wave's lanes
+  // run in lockstep, so each step's reads precede its writes without a
+  // barrier); per wave and slice: the composed forward maps of its parts (A, B)
+  // and the composed maps of their first values (C, D)
+  __shared__ double sP[2][kPartWaves * kWave];
   __shared__ double sA[kPartWaves * kWave], sB[kPartWaves * kWave];
   __shared__ double sC[kPartWaves * kWave], sD[kPartWaves * kWave];
 
@@ -1741,35 +1744,39 @@ __global__ __launch_bounds__(kPartWaves* kWave, 4) void k_part_sweep(
     y = ok ? yn : y;
     psi = ok ? psi * e : psi;
   }
-  sA[tid] = psi;
-  sB[tid] = y;
-  __syncthreads();
-  // Yin: the forward maps of the earlier parts, in order
-  // (four entries read before they are folded, so the chain waits on the
-  // multiply-adds rather than on every read). Part k sits in lane (k % G) * nb +
-  // sl of wave k / G; the folds step (k / G, k % G) instead of dividing.
-  constexpr int KF = 4;
-  double Y = 0.0;
-  const int qa = act ? q : 0;  // lanes without a part fold nothing
+  // Yin of each part: the composition of the earlier parts' forward maps
+  // y -> a y + b (a = psi at the part's end, b = y0 there) applied to 0; lanes
+  // without a part carry the identity. An inclusive scan over this wave's parts
+  // (lanes nb apart, same slice), each wave's total map through LDS folded over
+  // the earlier waves, then the scan of the part before this one.
+  const int nw = blockDim.x / kWave;
   {
-    int kw = 0, kr = 0;
-    for (int k0 = 0; k0 < qa; k0 += KF) {
-      double a[KF], b[KF];
-#pragma unroll
-      for (int j = 0; j < KF; j++) {
-        const bool ok = k0 + j < qa;
-        const int t2 = ok ? kw * kWave + kr * nb + sl : 0;
-        a[j] = ok ? sA[t2] : 1.0;
-        b[j] = ok ? sB[t2] : 0.0;
-        if (++kr == G) {
-          kr = 0;
-          ++kw;
-        }
+    double fa = act ? psi : 1.0, fb = act ? y : 0.0;
+    sP[0][tid] = fa;
+    sP[1][tid] = fb;
+#pragma unroll 1
+    for (int k = 1; k < G; k <<= 1) {
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      const int src = gq >= k ? tid - k * nb : tid;
+      const double pa = sP[0][src], pb = sP[1][src];
+      if (gq >= k) {
+        fb = fma(fa, pb, fb);
+        fa *= pa;
       }
-#pragma unroll
-      for (int j = 0; j < KF; j++) Y = fma(a[j], Y, b[j]);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      sP[0][tid] = fa;
+      sP[1][tid] = fb;
+    }
+    if (gq == G - 1) {
+      sA[wv * kWave + sl] = fa;
+      sB[wv * kWave + sl] = fb;
     }
   }
+  __syncthreads();
+  double Y = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < wv; k++) Y = fma(sA[k * kWave + sl], Y, sB[k * kWave + sl]);
+  if (gq >= 1) Y = fma(sP[0][tid - nb], Y, sP[1][tid - nb]);
   // true y of the part, and its back substitution from x_e = 0
   double dy = Y;
 #pragma unroll
@@ -1788,33 +1795,37 @@ __global__ __launch_bounds__(kPartWaves* kWave, 4) void k_part_sweep(
     x = ok ? xn : x;
     phi = ok ? phi * rg.y : phi;
   }
-  sC[tid] = phi;
-  sD[tid] = x;
-  __syncthreads();
-  // Xout: the backward maps of the later parts, from the line end
-  double X = 0.0;
-  const int qb = act ? q : Pn - 1;  // parts (qb, Pn) are folded, last first
+  // Xout of each part: its first value x_s = C Xout + D (C = the product of g
+  // over the part, D = x0_s) composed over the later parts from the line end
+  // (Xout = 0 after the last part), the same way in the other direction.
+  __syncthreads();  // every lane has read its scan entries
   {
-    int kw = (Pn - 1) / G, kr = (Pn - 1) - kw * G;
-    for (int k0 = Pn - 1; k0 > qb; k0 -= KF) {
-      double c[KF], dd[KF];
-#pragma unroll
-      for (int j = 0; j < KF; j++) {
-        const bool ok = k0 - j > qb;
-        const int t2 = ok ? kw * kWave + kr * nb + sl : 0;
-        c[j] = ok ? sC[t2] : 1.0;
-        dd[j] = ok ? sD[t2] : 0.0;
-        if (kr-- == 0) {
-          kr = G - 1;
-          --kw;
-        }
+    double cc = act ? phi : 1.0, cd = act ? x : 0.0;
+    sP[0][tid] = cc;
+    sP[1][tid] = cd;
+#pragma unroll 1
+    for (int k = 1; k < G; k <<= 1) {
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      const int src = gq + k < G ? tid + k * nb : tid;
+      const double na = sP[0][src], nd = sP[1][src];
+      if (gq + k < G) {
+        cd = fma(cc, nd, cd);
+        cc *= na;
       }
-#pragma unroll
-      for (int j = 0; j < KF; j++) X = fma(c[j], X, dd[j]);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      sP[0][tid] = cc;
+      sP[1][tid] = cd;
+    }
+    if (gq == 0) {
+      sC[wv * kWave + sl] = cc;
+      sD[wv * kWave + sl] = cd;
     }
   }
-  // plain stores: a node's slices of one block seldom fill whole cache lines,
-  // and the cache merges the pieces (nontemporal stores of them were slower)
+  __syncthreads();
+  double X = 0.0;
+#pragma unroll 1
+  for (int k = nw - 1; k > wv; k--) X = fma(sC[k * kWave + sl], X, sD[k * kWave + sl]);
+  if (gq + 1 < G) X = fma(sP[0][tid + nb], X, sP[1][tid + nb]);
   x = X;
 #pragma unroll
   for (int t = PL - 1; t >= 0; t--) {
