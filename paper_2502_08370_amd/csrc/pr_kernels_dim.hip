@@ -232,16 +232,14 @@ constexpr int kTrThreads = kTrWaves * kWave;
 constexpr int kTrIt = kWave * kWave / kTrThreads;  // tile entries per thread
 
 __global__ __launch_bounds__(kTrThreads) void k_to_interleaved(const DimInst* __restrict__ insts,
-                                                               const double* __restrict__ U,
-                                                               int part) {
+                                                               const double* __restrict__ U) {
   __shared__ double tile[64][65];
   const DimInst& I = insts[0];
   if (I.active && !I.active[I.idx]) return;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int i0 = blockIdx.x * 64, j = blockIdx.y, b = blockIdx.z;
-  // blocks of the partitioned sweeps need not be a power of two wide
-  const int L = part ? I.Lp : I.L, nx = I.nx, lg = 31 - __clz(L);
-  const long slab = part ? I.slabp : I.slab;
+  const int L = I.L, nx = I.nx, lg = 31 - __clz(L);
+  const long slab = I.slab;
   const long npts = (long)nx * I.ny;
   const int i = i0 + lane;
   double v[kTrIt];
@@ -261,21 +259,21 @@ __global__ __launch_bounds__(kTrThreads) void k_to_interleaved(const DimInst* __
 #pragma unroll
   for (int u = 0; u < kTrIt; u++) {
     const int q = tid + kTrThreads * u;
-    if (q < n) Zb[q] = part ? tile[q % L][q / L] : tile[q & (L - 1)][q >> lg];
+    if (q < n) Zb[q] = tile[q & (L - 1)][q >> lg];
   }
 }
 
 // Z (+ the pending chunk correction of the last y sweep) -> natural F[slice][j][i].
 __global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
-    const DimInst* __restrict__ insts, double* __restrict__ F, int with_corr, int part) {
+    const DimInst* __restrict__ insts, double* __restrict__ F, int with_corr) {
   __shared__ double tile[64][65];
   const DimInst& I = insts[0];
   if (I.active && !I.active[I.idx]) return;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int i0 = blockIdx.x * 64, j = blockIdx.y, b = blockIdx.z;
-  const int L = part ? I.Lp : I.L, nx = I.nx, M = I.M, Py = I.Py, lg = 31 - __clz(L);
+  const int L = I.L, nx = I.nx, M = I.M, Py = I.Py, lg = 31 - __clz(L);
   const long npts = (long)nx * I.ny;
-  const gdouble* Zb = gp(I.Z) + b * (part ? I.slabp : I.slab) + ((long)j * nx + i0) * L;
+  const gdouble* Zb = gp(I.Z) + b * I.slab + ((long)j * nx + i0) * L;
   const gdouble* sig = with_corr ? gp(I.sigY) + ((long)b * Py + j / M) * nx * L : nullptr;
   const gdouble* phiC = with_corr ? gp(I.fyPhiC) + (long)j * nx : nullptr;
   const int n = min(64, nx - i0) * L;
@@ -284,7 +282,7 @@ __global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
   for (int u = 0; u < kTrIt; u++) {
     const int q = tid + kTrThreads * u;
     const bool ok = q < n;
-    const int t = part ? q / L : q >> lg, sl = part ? q % L : q & (L - 1);
+    const int t = q >> lg, sl = q & (L - 1);
     z[u] = ok ? Zb[q] : 0.0;
     ph[u] = (ok && with_corr) ? phiC[i0 + t] : 0.0;
     sg[u] = (ok && with_corr) ? sig[(long)(i0 + t) * L + sl] : 0.0;
@@ -292,8 +290,7 @@ __global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
 #pragma unroll
   for (int u = 0; u < kTrIt; u++) {
     const int q = tid + kTrThreads * u;
-    if (q < n)
-      tile[part ? q % L : q & (L - 1)][part ? q / L : q >> lg] = fma(ph[u], sg[u], z[u]);
+    if (q < n) tile[q & (L - 1)][q >> lg] = fma(ph[u], sg[u], z[u]);
   }
   __syncthreads();
   const int cnt = min(64, nx - i0);
@@ -302,6 +299,60 @@ __global__ __launch_bounds__(kTrThreads) void k_from_interleaved(
     const int sl = w + kTrWaves * u, slice = b * L + sl;
     if (sl < L && slice < I.N && lane < cnt)
       F[slice * npts + (long)j * nx + i0 + lane] = tile[sl][lane];
+  }
+}
+
+// Natural U[slice][node] <-> the partitioned sweeps' blocks Z[b][node][l] (Lp
+// slices per block, not a power of two). Into the blocks: a workgroup stages 64
+// nodes of the block's slices in LDS, reading each slice's 64 nodes as one run
+// and writing the 64 * Lp doubles of the block as one run. Back: one thread per
+// (node, block) reads its node's run and writes the node in each slice, 64
+// consecutive nodes per wave.
+constexpr int kPartTrNodes = 64;
+__global__ __launch_bounds__(256) void k_to_part(const DimInst* __restrict__ insts,
+                                                 const double* __restrict__ U) {
+  __shared__ double tile[kPartTrNodes * kWave];
+  const DimInst& I = insts[0];
+  if (I.active && !I.active[I.idx]) return;
+  const long npts = (long)I.nx * I.ny;
+  const long n0 = (long)blockIdx.x * kPartTrNodes;
+  const int b = blockIdx.y, L = I.Lp, nb = min(L, I.N - b * L);
+  const int cnt = (int)min((long)kPartTrNodes, npts - n0);
+  const gdouble* u = gp(U) + (long)b * L * npts + n0;
+  constexpr int kIt = kPartTrNodes * kWave / 256;  // entries per thread at most
+  double v[kIt];
+#pragma unroll
+  for (int k = 0; k < kIt; k++) {  // every load issued before the first LDS store
+    const int e = threadIdx.x + 256 * k, l = e / kPartTrNodes, nd = e - l * kPartTrNodes;
+    v[k] = (l < nb && nd < cnt) ? u[(long)l * npts + nd] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < kIt; k++) {
+    const int e = threadIdx.x + 256 * k, l = e / kPartTrNodes, nd = e - l * kPartTrNodes;
+    if (l < L) tile[nd * L + l] = v[k];
+  }
+  __syncthreads();
+  gdouble* z = gp(I.Z) + b * I.slabp + n0 * L;
+  for (int e = threadIdx.x; e < cnt * L; e += blockDim.x) z[e] = tile[e];
+}
+
+__global__ __launch_bounds__(256) void k_from_part(const DimInst* __restrict__ insts,
+                                                   double* __restrict__ F) {
+  const DimInst& I = insts[0];
+  if (I.active && !I.active[I.idx]) return;
+  const long npts = (long)I.nx * I.ny;
+  const long node = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const int b = blockIdx.y, L = I.Lp, nb = min(L, I.N - b * L);
+  if (node >= npts) return;
+  const gdouble* z = gp(I.Z) + b * I.slabp + node * L;
+  gdouble* f = gp(F) + (long)b * L * npts + node;
+  for (int l0 = 0; l0 < nb; l0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) v[k] = l0 + k < nb ? z[l0 + k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+      if (l0 + k < nb) f[(long)(l0 + k) * npts] = v[k];
   }
 }
 
@@ -1890,17 +1941,29 @@ hipError_t launch_chunk_phi(const double* G, int n_lines, int n_pos, int M, doub
 
 hipError_t launch_to_interleaved(const DimInst* d_inst, const DimInst& h, const double* U_in,
                                  hipStream_t s, bool part) {
-  dim3 grid((h.nx + 63) / 64, h.ny, part ? h.Bp : h.B);
-  hipLaunchKernelGGL(k_to_interleaved, grid, dim3(kTrThreads), 0, s, d_inst, U_in, (int)part);
+  if (part) {
+    const long npts = (long)h.nx * h.ny;
+    hipLaunchKernelGGL(k_to_part, dim3((unsigned)((npts + kPartTrNodes - 1) / kPartTrNodes), h.Bp),
+                       dim3(256), 0, s, d_inst, U_in);
+    return hipGetLastError();
+  }
+  dim3 grid((h.nx + 63) / 64, h.ny, h.B);
+  hipLaunchKernelGGL(k_to_interleaved, grid, dim3(kTrThreads), 0, s, d_inst, U_in);
   return hipGetLastError();
 }
 
 hipError_t launch_from_interleaved(const DimInst* d_inst, const DimInst& h, double* F_out,
                                    bool with_corr, hipStream_t s, bool part) {
-  if (part && with_corr) return hipErrorInvalidValue;  // partitioned output is exact
-  dim3 grid((h.nx + 63) / 64, h.ny, part ? h.Bp : h.B);
+  if (part) {
+    if (with_corr) return hipErrorInvalidValue;  // partitioned output is exact
+    const long npts = (long)h.nx * h.ny;
+    hipLaunchKernelGGL(k_from_part, dim3((unsigned)((npts + 255) / 256), h.Bp), dim3(256), 0, s,
+                       d_inst, F_out);
+    return hipGetLastError();
+  }
+  dim3 grid((h.nx + 63) / 64, h.ny, h.B);
   hipLaunchKernelGGL(k_from_interleaved, grid, dim3(kTrThreads), 0, s, d_inst, F_out,
-                     (int)with_corr, (int)part);
+                     (int)with_corr);
   return hipGetLastError();
 }
 
