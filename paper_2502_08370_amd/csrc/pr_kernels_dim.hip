@@ -1729,6 +1729,7 @@ __global__ __launch_bounds__(kPartWaves* kWave, 4) void k_part_sweep(
   // so that one wait covers them)
   const gdv2* RG = (const gdv2*)(DIR == 0 ? I.pxRG : I.pyRG) + (long)line * n_pos;
   const int nthr = blockDim.x;
+  const int nf = FT ? I.nforce : 0;  // source terms in use (the other rows are zero)
   constexpr int KS = 4;
   dv2 rg_st[KS];
   double src_st[FT ? KS : 1][FT ? kMaxForcing : 1];
@@ -1740,7 +1741,7 @@ __global__ __launch_bounds__(kPartWaves* kWave, 4) void k_part_sweep(
       if constexpr (FT) {
 #pragma unroll
         for (int m = 0; m < kMaxForcing; m++)
-          src_st[k][m] = gp(I.fS)[m * I.npts + (long)line * I.nx + p];
+          src_st[k][m] = m < nf ? gp(I.fS)[m * I.npts + (long)line * I.nx + p] : 0.0;
       }
     }
   }
@@ -1759,7 +1760,8 @@ __global__ __launch_bounds__(kPartWaves* kWave, 4) void k_part_sweep(
     sRG[p] = RG[p];
     if constexpr (FT) {
 #pragma unroll
-      for (int m = 0; m < kMaxForcing; m++) sSrc[m][p] = gp(I.fS)[m * I.npts + (long)line * I.nx + p];
+      for (int m = 0; m < kMaxForcing; m++)
+        sSrc[m][p] = m < nf ? gp(I.fS)[m * I.npts + (long)line * I.nx + p] : 0.0;
     }
   }
   // source: dt * g_m of this lane's slice at this step
