@@ -221,9 +221,10 @@ pr_status pr_parareal_iterate(pr_problem p, const double* u0, double* U, int k_m
  *                      most 1024 positions, and at most 8 * (64 / Lp) * 24
  *                      positions with slice blocks of Lp slices: few slices)
  *                      hold each line whole, cut into parts solved side by
- *                      side and joined exactly, and write exact values; the
- *                      options above then only affect the other instances (with
- *                      more slices the chunked sweeps were measured faster);
+ *                      side and joined exactly, and write exact values; for
+ *                      those instances the options above then affect only the
+ *                      adjoints' recomputed steps, which keep the chunked sweeps
+ *                      (with more slices the chunked sweeps were measured faster);
  *                      2: every instance whose lines fit; 0: chunked sweeps
  *   PR_OPT_PARTITIONED_USED  read only (pr_set_option returns PR_EINVAL): the
  *                      number of the handle's instances whose fine sweeps are
