@@ -475,8 +475,9 @@ int part_positions(int n, int nb);
 int part_waves(int n, int Pl, int nb);
 // By default the partitioned sweeps serve instances of at most kPartMaxSlices
 // slices: with more, the chunked sweeps hold enough line recurrences in flight
-// and were measured faster (999^2: partitioned 0.47 against 0.39 of 8 TB/s at
-// N = 20, 0.42 against 0.47 at N = 32, 0.43 against 0.54 at 1023^2, N = 64).
+// and were measured faster (999^2: partitioned 0.53 against 0.41 of 8 TB/s at
+// N = 20, 0.49 against 0.51 at N = 32, 0.44 against 0.48 at N = 48; 1023^2,
+// N = 64: 0.43 against 0.53).
 constexpr int kPartMaxSlices = 24;
 // Slice blocks of the partitioned sweeps for an nx x ny grid and N slices: the
 // fewest blocks Bp (of Lp = ceil(N / Bp) slices) with which the lines of both
